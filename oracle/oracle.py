@@ -1,0 +1,305 @@
+"""FP64 CPU oracle for the likelihood-matrix hot path -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+use this module.  It is the plain definition of what the hot path computes,
+written from the paper (arXiv:2507.16022) without any of the GPU path's
+rearrangements: every (waveform i, extrinsic sample e, phase o) triple gets
+its own detector waveform, its inner products are direct sums over all
+frequency bins, distance is integrated with 2000-node Gauss-Legendre and
+the evidence is a log-sum-exp over all pairs.  It shares no code with the
+GPU library and does not import it.
+
+Readings of the paper (where it is silent, ambiguous or garbled):
+  * the distance-marginalised likelihood of eq. (lnl_dist_marginalized) is
+    the integral itself (the "ln" on its left-hand side is a typo);
+  * the (h|h) inner product of eq. (hh_ieo) is per detector with that
+    detector's noise weights;
+  * modes are (l, m) channels; the orbital-phase factor uses m of the
+    channel, applied as exp(-i m phi) to the waveform (sign immaterial on
+    a regular phase grid, which maps o -> N-o);
+  * arrival time t_k = t_geo - r_k . n / c with n pointing to the source;
+  * inner products are sums over the given frequency bins with weights
+    w_kb = 4 df_b / S_k(f_b) (relative-binning summaries with
+    W^{dh} = w d and W^{hh} = w on those bins);
+  * non-precessing waveforms: the inclination dependence factorises into
+    K_{c,p}(iota), so the bank stores one complex amplitude per (l, m) and
+    the inclination travels with the extrinsic sample;
+  * phase grid phi_o = 2 pi o / N_phi, w_o = 1 (Sec. III B);
+  * distance prior proportional to D^2 on (0, D_max].
+"""
+from __future__ import annotations
+
+import functools
+import math
+
+import numpy as np
+
+C_SI = 299792458.0
+
+
+def _lse(x, axis=-1):
+    """log(sum(exp(x))) along an axis, stable; -inf for all -inf input."""
+    x = np.asarray(x, dtype=np.float64)
+    m = np.max(x, axis=axis, keepdims=True)
+    m_safe = np.where(np.isfinite(m), m, 0.0)
+    s = np.sum(np.exp(x - m_safe), axis=axis, keepdims=True)
+    out = np.log(s) + m_safe
+    return np.squeeze(out, axis=axis)
+
+
+# --------------------------------------------------------------------------
+# O1: geometry -- eq. (thetaext), (response_plus/cross), (t_at_detector)
+# --------------------------------------------------------------------------
+def sky_direction(lat, lon):
+    """Unit vector towards the source in the Earth-fixed frame, [N, 3]."""
+    lat = np.asarray(lat, dtype=np.float64)
+    lon = np.asarray(lon, dtype=np.float64)
+    return np.stack([np.cos(lat) * np.cos(lon), np.cos(lat) * np.sin(lon), np.sin(lat)], -1)
+
+
+def polarization_tensors(lat, lon, psi):
+    """e_+ and e_x [N, 3, 3] for waves from (lat, lon) at polarisation psi.
+
+    Transverse basis: X = cos(psi) e_lon + sin(psi) e_lat and
+    Y = -sin(psi) e_lon + cos(psi) e_lat, with e_lon, e_lat the unit
+    vectors of increasing longitude and latitude at the source direction.
+    """
+    lat, lon, psi = (np.asarray(a, dtype=np.float64) for a in (lat, lon, psi))
+    e_lon = np.stack([-np.sin(lon), np.cos(lon), np.zeros_like(lon)], -1)
+    e_lat = np.stack([-np.sin(lat) * np.cos(lon), -np.sin(lat) * np.sin(lon), np.cos(lat)], -1)
+    X = np.cos(psi)[:, None] * e_lon + np.sin(psi)[:, None] * e_lat
+    Y = -np.sin(psi)[:, None] * e_lon + np.cos(psi)[:, None] * e_lat
+    ep = X[:, :, None] * X[:, None, :] - Y[:, :, None] * Y[:, None, :]
+    ex = X[:, :, None] * Y[:, None, :] + Y[:, :, None] * X[:, None, :]
+    return ep, ex
+
+
+def antenna_patterns(det_D, lat, lon, psi):
+    """F_{ekp}: [N_e, K, 2] real (p = +, x), the contraction D_k : e_p."""
+    ep, ex = polarization_tensors(lat, lon, psi)
+    fp = np.einsum("kab,eab->ek", det_D, ep)
+    fx = np.einsum("kab,eab->ek", det_D, ex)
+    return np.stack([fp, fx], -1)
+
+
+def arrival_times(det_r, lat, lon, t_geo):
+    """t_{ek} = t_geo - r_k . n / c  [N_e, K] (reading of eq. t_at_detector)."""
+    n = sky_direction(lat, lon)
+    return np.asarray(t_geo, dtype=np.float64)[:, None] - (n @ np.asarray(det_r).T) / C_SI
+
+
+# --------------------------------------------------------------------------
+# O2/O3: mode factors and complex response
+# --------------------------------------------------------------------------
+def swsh_m2(l, m, cos_t):
+    """Spin-weight -2 spherical harmonic at azimuth 0, from the Wigner small-d
+    matrix: -2Y_lm(theta, 0) = sqrt((2l+1)/(4 pi)) d^l_{m,2}(theta)."""
+    cos_t = np.asarray(cos_t, dtype=np.float64)
+    th = np.arccos(np.clip(cos_t, -1.0, 1.0))
+    cb, sb = np.cos(th / 2), np.sin(th / 2)
+    j, mp, mm = l, m, 2          # d^j_{m' m}: m' = m (mode), m = 2 (spin)
+    fac = math.factorial
+    out = np.zeros_like(cos_t)
+    for k in range(0, 2 * j + 1):
+        a, b, c, d = j + mm - k, k, j - k - mp, k - mm + mp
+        if min(a, b, c, d) < 0:
+            continue
+        coef = (-1.0) ** (k - mm + mp) * math.sqrt(fac(j + mm) * fac(j - mm) * fac(j + mp) * fac(j - mp)) \
+            / (fac(a) * fac(b) * fac(c) * fac(d))
+        out = out + coef * cb ** (2 * j - 2 * k + mm - mp) * sb ** (2 * k - mm + mp)
+    return math.sqrt((2 * l + 1) / (4 * math.pi)) * out
+
+
+def mode_factors(modes, cos_iota):
+    """K_{c,p}(iota): [N_e, N_c, 2] complex.  For a non-precessing source the
+    positive-frequency + and x polarisations of channel (l, m) are
+    K_+ = (Y_{l,-m} + (-1)^l Y_{lm})/2 and K_x = i (Y_{l,-m} - (-1)^l Y_{lm})/2
+    times the stored mode amplitude."""
+    out = np.zeros((len(cos_iota), len(modes), 2), dtype=np.complex128)
+    for c, (l, m) in enumerate(modes):
+        yn = swsh_m2(l, -m, cos_iota)
+        yp = swsh_m2(l, m, cos_iota)
+        out[:, c, 0] = 0.5 * (yn + (-1) ** l * yp)
+        out[:, c, 1] = 0.5j * (yn - (-1) ** l * yp)
+    return out
+
+
+def response(wl_det_D, modes, ext):
+    """R_{ekc} = sum_p F_{ekp} K_{cp}(iota_e): [N_e, K, N_c] complex."""
+    F = antenna_patterns(wl_det_D, ext["lat"], ext["lon"], ext["psi"])
+    Kf = mode_factors(modes, ext["cos_iota"])
+    return np.einsum("ekp,ecp->ekc", F.astype(np.complex128), Kf)
+
+
+# --------------------------------------------------------------------------
+# O4/O5: detector waveforms and inner products, per triple, direct sums
+# --------------------------------------------------------------------------
+def phase_grid(n_phi):
+    return 2.0 * np.pi * np.arange(n_phi) / n_phi
+
+
+def triple_inner_products(h_i, R, t, f, mode_m, phis, d, w):
+    """dh, hh for one waveform against a block of extrinsic samples.
+
+    h_i [N_c, N_b]; R [E, K, N_c]; t [E, K]; returns dh, hh [E, N_phi].
+    h_{eokb} = sum_c h_{cb} R_{ekc} exp(-2 pi i f_b t_{ek}) exp(-i m_c phi_o)
+    (eq. h_k at d0), dh = Re sum_kb w d conj(h), hh = sum_kb w |h|^2
+    (eq. inner_product).
+    """
+    T = np.exp(-2j * np.pi * f[None, None, :] * t[:, :, None])          # [E,K,B]
+    Phi = np.exp(-1j * np.outer(phis, mode_m))                          # [O,C]
+    hk = np.einsum("cb,ekc,oc->eokb", h_i, R, Phi) * T[:, None, :, :]  # [E,O,K,B]
+    dh = np.real(np.einsum("kb,eokb->eo", w * d, np.conj(hk)))
+    hh = np.einsum("kb,eokb->eo", w, np.abs(hk) ** 2)
+    return dh, hh
+
+
+def data_inner(d, w):
+    """(d|d) = sum_kb w |d|^2."""
+    return float(np.sum(w * np.abs(d) ** 2))
+
+
+# --------------------------------------------------------------------------
+# O6/O7: maximum likelihood over distance, distance marginalisation
+# --------------------------------------------------------------------------
+def lnl_at_distance(dh, hh, dist, d0=1.0):
+    """eq. (lnlike_ieo_arb_dL)."""
+    x = dist / d0
+    return dh / x - 0.5 * hh / x ** 2
+
+
+def lnl_ml(dh, hh):
+    """eq. (bestfit_lnl): dh^2/(2 hh) if dh > 0 else 0."""
+    dh = np.asarray(dh, dtype=np.float64)
+    hh = np.asarray(hh, dtype=np.float64)
+    pos = dh > 0
+    out = np.zeros(np.broadcast(dh, hh).shape)
+    np.divide(dh * dh, 2.0 * hh, out=out, where=pos & (hh > 0))
+    return out
+
+
+@functools.lru_cache(maxsize=8)
+def _gl(n_nodes):
+    return np.polynomial.legendre.leggauss(n_nodes)
+
+
+def distance_nodes(d_max, n_nodes=2000):
+    """Gauss-Legendre nodes D_j on (0, D_max] and normalised weights q_j for
+    the prior proportional to D^2 (q_j proportional to GL weight x D_j^2,
+    summing to one)."""
+    x, wq = _gl(int(n_nodes))
+    D = 0.5 * d_max * (x + 1.0)
+    q = wq * D * D
+    return D, q / np.sum(q)
+
+
+def ln_dist_marg(dh, hh, d_max, d0=1.0, n_nodes=2000, chunk=4096):
+    """ln of eq. (lnl_dist_marginalized): ln sum_j q_j exp(dh u_j - hh u_j^2/2),
+    2000-node Gauss-Legendre in D over (0, D_max] (the integrand vanishes
+    smoothly at D -> 0 and is cut hard at D_max, where a Gauss rule keeps
+    its accuracy), 
+    u_j = d0/D_j, evaluated in log space.  dh, hh: arrays of equal shape."""
+    dh = np.asarray(dh, dtype=np.float64)
+    hh = np.asarray(hh, dtype=np.float64)
+    shape = np.broadcast(dh, hh).shape
+    dh = np.broadcast_to(dh, shape).ravel()
+    hh = np.broadcast_to(hh, shape).ravel()
+    D, q = distance_nodes(d_max, n_nodes)
+    u = d0 / D
+    lq = np.log(q)
+    out = np.empty(dh.shape)
+    for s in range(0, dh.size, chunk):
+        a = dh[s:s + chunk, None]
+        b = hh[s:s + chunk, None]
+        out[s:s + chunk] = _lse(lq[None, :] + a * u[None, :] - 0.5 * b * (u * u)[None, :], axis=1)
+    return out.reshape(shape)
+
+
+# --------------------------------------------------------------------------
+# O8-O10: per-pair likelihood, evidence, top-K
+# --------------------------------------------------------------------------
+def eval_pairs_block(wl, rows, ext_idx=None, n_nodes=2000, return_triples=False):
+    """ln Lbar_ie for bank rows `rows` x extrinsic samples `ext_idx`.
+
+    Returns dict with lnl [len(rows), E] and max lnL^ML [len(rows), E];
+    with return_triples also dh, hh [len(rows), E, N_phi].
+    """
+    ext_idx = np.arange(wl.n_ext) if ext_idx is None else np.asarray(ext_idx)
+    ext = {k: np.asarray(v)[ext_idx] for k, v in wl.ext.items()}
+    R = response(wl.det_D, wl.modes, ext)
+    t = arrival_times(wl.det_r, ext["lat"], ext["lon"], ext["t_geo"])
+    phis = phase_grid(wl.n_phi)
+    mode_m = np.array([m for _, m in wl.modes], dtype=np.float64)
+    E = len(ext_idx)
+    lnl = np.empty((len(rows), E))
+    mlmax = np.empty((len(rows), E))
+    dhs = np.empty((len(rows), E, wl.n_phi)) if return_triples else None
+    hhs = np.empty((len(rows), E, wl.n_phi)) if return_triples else None
+    eb = max(1, min(E, 262144 // max(1, wl.n_phi * wl.d.shape[0] * len(wl.f))))
+    for a, i in enumerate(rows):
+        for s in range(0, E, eb):
+            sl = slice(s, s + eb)
+            dh, hh = triple_inner_products(wl.h[i], R[sl], t[sl], wl.f, mode_m, phis, wl.d, wl.w)
+            lnl_o = ln_dist_marg(dh, hh, wl.d_max, wl.d0, n_nodes)
+            lnl[a, sl] = _lse(lnl_o, axis=1) - math.log(wl.n_phi)
+            mlmax[a, sl] = np.max(lnl_ml(dh, hh), axis=1)
+            if return_triples:
+                dhs[a, sl] = dh
+                hhs[a, sl] = hh
+    out = dict(lnl=lnl, ml_max=mlmax)
+    if return_triples:
+        out.update(dh=dhs, hh=hhs)
+    return out
+
+
+def _worker(args):
+    wl, rows, n_nodes = args
+    return eval_pairs_block(wl, rows, None, n_nodes)
+
+
+def eval_lnl(wl, n_nodes=2000, processes=1):
+    """ln Lbar_ie for every bank row and extrinsic sample of the workload."""
+    rows = np.arange(wl.n_int)
+    if processes <= 1:
+        return eval_pairs_block(wl, rows, None, n_nodes)
+    import multiprocessing as mp
+    chunks = [c for c in np.array_split(rows, processes * 4) if len(c)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(processes) as pool:
+        parts = pool.map(_worker, [(wl, c, n_nodes) for c in chunks])
+    return dict(lnl=np.concatenate([p["lnl"] for p in parts]),
+                ml_max=np.concatenate([p["ml_max"] for p in parts]))
+
+
+def evidence_from_lnl(lnl, ln_w_int, ln_w_ext, n_norm=0.0):
+    """eq. (Z_sum) with w_o = 1: ln Z = LSE_ie(ln w_i + ln w_e + ln Lbar_ie)
+    - ln N_norm - ln N_ext.  Also ln sum p, ln sum p^2 (eq. n_effective)."""
+    lnp = np.asarray(ln_w_int)[:, None] + np.asarray(ln_w_ext)[None, :] + lnl
+    n_norm = float(n_norm) if n_norm and n_norm > 0 else float(lnl.shape[0])
+    ln_sum_p = float(_lse(lnp.ravel()))
+    ln_sum_p2 = float(_lse(2.0 * lnp.ravel()))
+    ln_z = ln_sum_p - math.log(n_norm) - math.log(lnl.shape[1])
+    return dict(ln_z=ln_z, ln_sum_p=ln_sum_p, ln_sum_p2=ln_sum_p2,
+                n_eff=math.exp(2 * ln_sum_p - ln_sum_p2), lnp=lnp)
+
+
+def top_k(lnp, k):
+    """Top-k (i, e) pairs by ln p descending, ties by i then e ascending."""
+    n_i, n_e = lnp.shape
+    flat = lnp.ravel()
+    order = np.lexsort((np.arange(flat.size), -flat))   # stable: index order
+    sel = order[:k]
+    return np.stack([sel // n_e, sel % n_e], -1), flat[sel]
+
+
+def evidence(wl, n_nodes=2000, processes=1, k=0):
+    """Full oracle: ln Z, N_eff ingredients, max lnL^ML, (d|d), top-k."""
+    r = eval_lnl(wl, n_nodes, processes)
+    ev = evidence_from_lnl(r["lnl"], wl.ln_w_int, wl.ln_w_ext, wl.n_norm)
+    out = dict(ln_z=ev["ln_z"], ln_sum_p=ev["ln_sum_p"], ln_sum_p2=ev["ln_sum_p2"],
+               n_eff=ev["n_eff"], max_lnl_ml=float(np.max(r["ml_max"])),
+               dd=data_inner(wl.d, wl.w), lnl=r["lnl"], lnp=ev["lnp"])
+    if k:
+        idx, vals = top_k(ev["lnp"], k)
+        out.update(topk_idx=idx, topk_lnp=vals)
+    return out
