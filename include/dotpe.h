@@ -1,0 +1,204 @@
+/* dotpe.h -- C ABI of the likelihood-matrix hot path (gfx950).
+ *
+ * Computes, for every pair of an intrinsic-bank waveform i and an extrinsic
+ * sample e, the distance- and phase-marginalised likelihood
+ *     Lbar_ie = (1/N_phi) sum_o int dD pi(D) exp(dh_ieo d0/D - hh_ieo d0^2/(2 D^2))
+ * with dh, hh the inner products of eq. (dh_ieo) and eq. (hh_ieo), the
+ * distance scaling of eq. (lnlike_ieo_arb_dL) and the distance integral of
+ * eq. (lnl_dist_marginalized), and reduces it to the evidence of eq. (Z_sum)
+ *     Z = 1/(N_norm N_ext) sum_ie w_i w_e Lbar_ie        (w_o = 1)
+ * plus effective-sample-size ingredients (eq. n_effective) and the top-k
+ * pairs by posterior weight p_ie = w_i w_e Lbar_ie.
+ *
+ * Conventions (all inputs FP64, little-endian, row-major, interleaved complex
+ * re,im):
+ *   detector waveform  h_k(f_b) = (d0/D) sum_c h_cb R_ekc exp(-2 pi i f_b t_ek)
+ *                                  exp(-i m_c phi_o)                  (eq. h_k)
+ *   response           R_ekc = F_ek+ K_c+(iota_e) + F_ekx K_cx(iota_e)
+ *                      F_ekp = D_k : e_p, e_+ = XX^T - YY^T, e_x = XY^T + YX^T,
+ *                      X = cos(psi) e_lon + sin(psi) e_lat,
+ *                      Y = -sin(psi) e_lon + cos(psi) e_lat   (eq. response_plus/cross)
+ *                      K_c+ = (Y_l,-m + (-1)^l Y_lm)/2, K_cx = i(Y_l,-m - (-1)^l Y_lm)/2,
+ *                      Y = spin-weight -2 spherical harmonic at azimuth 0
+ *   arrival time       t_ek = t_geo,e - r_k . n_e / c, n_e towards the source
+ *                      (eq. t_at_detector, source-pointing n)
+ *   inner products     (a|b) = sum_k sum_b w_kb a_kb conj(b_kb), w_kb = 4 df_b/S_k(f_b)
+ *                      (eq. inner_product on the given bins)
+ *   phase grid         phi_o = 2 pi o / N_phi
+ *   distance prior     proportional to D^2 on (0, D_max]
+ *
+ * Error behaviour: every call returns DOTPE_OK (0) or a negative code;
+ * dotpe_last_error() returns a message for the calling thread's last error.
+ * On error, outputs are left untouched and no handle is returned.
+ * Handles are owned by the library and freed with the matching free call.
+ * A context is not thread-safe.
+ */
+#ifndef DOTPE_H
+#define DOTPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DOTPE_OK 0
+#define DOTPE_E_INVALID_ARG (-1)
+#define DOTPE_E_OOM (-2)
+#define DOTPE_E_ADMISSION (-3)
+#define DOTPE_E_NUMERIC (-4)
+#define DOTPE_E_DEVICE (-5)
+#define DOTPE_E_TOO_LARGE (-6)
+#define DOTPE_E_UNIMPLEMENTED (-7)
+
+/* arithmetic of the (d|h) contraction */
+#define DOTPE_PREC_FP64 0     /* FP64 operands, FP64 MFMA */
+#define DOTPE_PREC_FP16X2 1   /* FP16 hi+lo operands, 3 products, FP32 MFMA accumulation */
+#define DOTPE_PREC_BF16X2 2   /* BF16 hi+lo operands, 3 products, FP32 MFMA accumulation */
+
+/* where a caller pointer lives */
+#define DOTPE_MEM_HOST 0
+#define DOTPE_MEM_DEVICE 1
+
+typedef struct dotpe_ctx dotpe_ctx;
+typedef struct dotpe_bank dotpe_bank;
+typedef struct dotpe_event dotpe_event;
+
+/* Library version string. */
+const char* dotpe_version(void);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* dotpe_last_error(void);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the
+ * device memory its banks and events may hold (0 = no cap; the context's
+ * own distance table, about 21 MB, is not charged).  Builds the distance
+ * marginalisation table on the device.  Errors: INVALID_ARG (bad device),
+ * DEVICE, OOM. */
+int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out);
+
+/* Release a context and everything it owns.  NULL is a no-op. */
+int dotpe_destroy(dotpe_ctx* ctx);
+
+/* Bytes of device memory currently held by the context. */
+uint64_t dotpe_device_bytes(const dotpe_ctx* ctx);
+
+/* Intrinsic waveform bank (Sec. III C): n_wf waveforms, each n_modes (l, m)
+ * channel amplitudes on n_bins frequencies, at distance d0, reference phase
+ * 0 and polarisation angle 0. */
+typedef struct dotpe_bank_desc {
+  int64_t n_wf;
+  int32_t n_modes;        /* 1..8 channels; m in 1..4; at most 4 distinct m */
+  int32_t n_bins;         /* 1..4096 */
+  const int32_t* mode_l;  /* [n_modes] host */
+  const int32_t* mode_m;  /* [n_modes] host */
+  const double* f_bins;   /* [n_bins] Hz, host */
+  const double* h;        /* [n_wf][n_modes][n_bins][2], host or device (mem) */
+  const double* ln_w;     /* [n_wf] ln w_i (eq. int_weights), host or device, NULL = 0 */
+  int32_t precision;      /* DOTPE_PREC_* */
+  int32_t mem;            /* DOTPE_MEM_* for h and ln_w */
+} dotpe_bank_desc;
+
+/* Copy and convert a bank into device memory (the bank-summary layout).
+ * The caller keeps ownership of its arrays.  Errors: INVALID_ARG,
+ * NUMERIC (non-finite amplitudes), OOM / ADMISSION (over budget), DEVICE. */
+int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* desc, dotpe_bank** out);
+int dotpe_free_bank(dotpe_ctx* ctx, dotpe_bank* bank);
+
+/* One event: data, noise weights, detectors and the extrinsic set
+ * (Sec. III A, III B).  All pointers are host memory. */
+typedef struct dotpe_event_desc {
+  int32_t n_det;            /* 1..8 */
+  int32_t n_phi;            /* 1..128 reference-phase grid points */
+  const double* d;          /* [n_det][n_bins][2] data at f_bins */
+  const double* w;          /* [n_det][n_bins] w_kb = 4 df_b / S_k(f_b) */
+  const double* det_r;      /* [n_det][3] detector positions, metres, Earth-fixed */
+  const double* det_D;      /* [n_det][3][3] response tensors 0.5 (x x^T - y y^T) */
+  int64_t n_ext;            /* >= 1 */
+  const double* lat;        /* [n_ext] Earth-fixed latitude, rad */
+  const double* lon;        /* [n_ext] Earth-fixed longitude, rad */
+  const double* psi;        /* [n_ext] polarisation angle, rad */
+  const double* cos_iota;   /* [n_ext] cosine of inclination */
+  const double* t_geo;      /* [n_ext] arrival time at the geocentre, s */
+  const double* ln_w_ext;   /* [n_ext] ln w_e, NULL = 0 */
+  double d_max;             /* Mpc, upper end of the distance prior */
+  double d0;                /* Mpc, distance the bank is stored at */
+  double n_norm;            /* N_int of eq. (Z_sum); <= 0 means the subset size */
+  int64_t sub_start;        /* bank rows [sub_start, sub_start + sub_count) ... */
+  int64_t sub_count;        /* ... 0 = the whole bank */
+  const int64_t* sub_idx;   /* or explicit rows [sub_count] (host), NULL = range */
+  double cut_delta;         /* coherent cut (eq. coherent_ML_selection): triples with
+                               lnL^ML < running max - cut_delta are bounded, not
+                               marginalised; <= 0 disables the cut */
+  int32_t top_k;            /* number of top pairs to return from dotpe_evidence */
+  int32_t flags;            /* reserved, 0 */
+  double topk_window;       /* candidates kept within this of the max ln p (default 40 if <= 0) */
+  void* stream;             /* hipStream_t for this event's work; NULL = context stream */
+} dotpe_event_desc;
+
+/* Stage an event against a resident bank: copies inputs, builds the
+ * extrinsic operand (antenna patterns x time-shift phasors folded over
+ * detectors with the data), the per-pair (h|h) coefficient tables and the
+ * per-waveform (h|h) sums.  Errors: INVALID_ARG, NUMERIC, OOM, ADMISSION,
+ * DEVICE. */
+int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_event_desc* desc,
+                    dotpe_event** out);
+int dotpe_free_event(dotpe_ctx* ctx, dotpe_event* ev);
+
+/* Materialise ln Lbar_ie for every pair, no cut (parity and small shapes).
+ *   lnl      [n_sub][n_ext]            ln Lbar_ie (required)
+ *   ml_max   [n_sub][n_ext]            max_o lnL^ML_ieo (eq. bestfit_lnl), or NULL
+ *   triples  [n_sub][n_ext][n_phi][2]  (dh, hh) per triple at d0, or NULL
+ * mem says where the outputs live.  Synchronous.  Errors: INVALID_ARG,
+ * TOO_LARGE (outputs over the budget), DEVICE. */
+int dotpe_eval_lnl(dotpe_ctx* ctx, dotpe_event* ev, double* lnl, double* ml_max,
+                   double* triples, int32_t mem);
+
+typedef struct dotpe_evidence_result {
+  double ln_z;          /* ln Z over the marginalised triples */
+  double ln_z_upper;    /* ln(Z + bound on everything cut); = ln_z without cut */
+  double max_lnl_ml;    /* max over triples of lnL^ML */
+  double ln_sum_p;      /* ln sum_ie p_ie */
+  double ln_sum_p2;     /* ln sum_ie p_ie^2 (N_eff = exp(2 ln_sum_p - ln_sum_p2)) */
+  double dd;            /* (d|d) */
+  double max_ln_p;      /* max_ie ln p_ie */
+  int64_t n_pairs;
+  int64_t n_pairs_bounded;  /* pairs skipped by the per-pair bound */
+  int64_t n_triples_marg;   /* triples distance-marginalised */
+  int32_t precision;
+  int32_t topk_count;       /* entries written to topk */
+  int32_t topk_exact;       /* 1 if no cut pair could have entered the top-k window */
+  int32_t status;
+  double t_pilot_ms;        /* device time of the threshold pilot pass (HIP events) */
+  double t_fused_ms;        /* device time of the fused pass (HIP events) */
+} dotpe_evidence_result;
+
+typedef struct dotpe_sample {
+  int64_t i;        /* bank row (absolute index) */
+  int64_t e;        /* extrinsic sample */
+  double ln_p;      /* ln w_i + ln w_e + ln Lbar_ie */
+  int32_t o_best;   /* phase index of the largest ln Lbar_ieo */
+  int32_t reserved;
+} dotpe_sample;
+
+/* Fused, non-materialising evaluation: one persistent pass of the
+ * (d|h) contraction with the marginalisation and evidence epilogue.
+ * topk: [desc.top_k] host array or NULL.  Synchronous.  Errors:
+ * INVALID_ARG, DEVICE. */
+int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out,
+                   dotpe_sample* topk);
+
+/* Evaluate the device distance-marginalisation rule for n (dh, hh) pairs
+ * (host arrays), d0/D_max given; for checking the rule against a reference. */
+int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const double* hh,
+                         double d0_over_dmax, double* out);
+
+/* Copy back the event's extrinsic response: R [n_ext][n_det][n_modes][2] and
+ * t [n_ext][n_det] (host arrays), channels in the bank's input order. */
+int dotpe_debug_response(dotpe_ctx* ctx, const dotpe_event* ev, double* R, double* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOTPE_H */

@@ -1,0 +1,905 @@
+// Host runtime of the C ABI in include/dotpe.h: context, bank-summary
+// layout, event staging, launches of the fused likelihood kernel, evidence
+// finalisation and top-k selection.  All compute runs in the kernels of
+// kernels.h; host code validates, allocates, copies and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dotpe.h"
+#include "kernels.h"
+
+using namespace dotpe;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(DOTPE_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                            \
+  } while (0)
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct dotpe_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t budget = 0;
+  uint64_t bytes = 0;
+  uint64_t own_bytes = 0;    // the context's own tables (not charged to the budget)
+  double* dist_tab = nullptr;
+  DistTableGeom geom{};
+  double ghx[kGH], ghw[kGH];
+};
+
+struct dotpe_bank {
+  int64_t n_wf = 0;
+  int n_c = 0, n_b = 0, n_bp = 0;
+  int64_t K2 = 0;
+  int prec = 0;
+  ModeTables mt{};
+  double* f = nullptr;          // device [n_b]
+  std::vector<double> f_host;
+  void* A0 = nullptr;
+  void* A1 = nullptr;
+  double* row_scale = nullptr;
+  double* ln_w = nullptr;
+  uint64_t bytes = 0;
+};
+
+struct dotpe_event {
+  const dotpe_bank* bank = nullptr;
+  hipStream_t stream = nullptr;
+  int n_det = 0, n_phi = 0;
+  int64_t n_ext = 0, n_ext_p = 0, n_sub = 0, sub0 = 0;
+  int64_t* sub_idx = nullptr;
+  double d0 = 1.0, d_max = 1.0, n_norm = 0.0, cut_delta = 0.0, topk_window = 40.0;
+  int top_k = 0;
+  double dd = 0.0;
+  // device arrays
+  void* B[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* col_scale = nullptr;
+  double* ln_w_ext = nullptr;
+  double2* H = nullptr;
+  double* Hdiag = nullptr;
+  double2* Q = nullptr;
+  double* R2 = nullptr;
+  double2* R = nullptr;
+  double* T = nullptr;
+  double* phase_cs = nullptr;
+  // evidence scratch
+  double* partials = nullptr;
+  uint64_t* state = nullptr;
+  double* cand = nullptr;
+  int64_t cand_cap = 0;
+  double* final_out = nullptr;
+  hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};
+  std::vector<void*> allocs;
+  uint64_t bytes = 0;
+};
+
+namespace {
+
+int dev_alloc(dotpe_ctx* ctx, void** p, size_t n, std::vector<void*>* owner, uint64_t* acct) {
+  if (n == 0) n = 16;
+  if (ctx->budget && ctx->bytes - ctx->own_bytes + n > ctx->budget)
+    return fail(DOTPE_E_ADMISSION, "device budget exceeded: %llu + %zu > %llu bytes",
+                (unsigned long long)(ctx->bytes - ctx->own_bytes), n,
+                (unsigned long long)ctx->budget);
+  hipError_t e = hipMalloc(p, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DOTPE_E_OOM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
+  }
+  ctx->bytes += n;
+  if (acct) *acct += n;
+  if (owner) owner->push_back(*p);
+  return DOTPE_OK;
+}
+
+// probabilists' Gauss-Hermite nodes/weights (weight exp(-x^2/2)/sqrt(2 pi)):
+// roots of He_n bracketed on a grid and polished by Newton steps
+void gauss_hermite(int n, double* x, double* w) {
+  auto he = [n](double t, double* dn) {
+    double p0 = 1.0, p1 = t;
+    for (int k = 1; k < n; ++k) {
+      double p2 = t * p1 - k * p0;
+      p0 = p1;
+      p1 = p2;
+    }
+    *dn = n * p0;   // He_n' = n He_{n-1}
+    return p1;
+  };
+  int found = 0;
+  double prev_t = -12.0, d;
+  double prev_v = he(prev_t, &d);
+  for (int s = 1; s <= 240000 && found < n; ++s) {
+    double t = -12.0 + s * 1e-4;
+    double v = he(t, &d);
+    if ((v < 0) != (prev_v < 0)) {
+      double r = 0.5 * (t + prev_t);
+      for (int it = 0; it < 50; ++it) {
+        double val = he(r, &d);
+        double step = val / d;
+        r -= step;
+        if (std::fabs(step) < 1e-16) break;
+      }
+      x[found++] = r;
+    }
+    prev_t = t;
+    prev_v = v;
+  }
+  double sum = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double hn1 = 0.0;
+    he(x[k], &hn1);
+    hn1 /= n;      // He_{n-1}(x_k)
+    w[k] = 1.0 / (n * hn1 * hn1);   // up to the n! normalisation, fixed below
+    sum += w[k];
+  }
+  for (int k = 0; k < n; ++k) w[k] /= sum;
+}
+
+int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
+  const int nc = d->n_modes;
+  std::vector<int> ms;
+  for (int c = 0; c < nc; ++c) {
+    int l = d->mode_l[c], m = d->mode_m[c];
+    if (m < 1 || m > kMaxM || l < 2 || l > 8 || m > l)
+      return fail(DOTPE_E_INVALID_ARG, "mode (%d,%d) unsupported (need 2<=l<=8, 1<=m<=min(l,4))",
+                  l, m);
+    if (std::find(ms.begin(), ms.end(), m) == ms.end()) ms.push_back(m);
+  }
+  std::sort(ms.begin(), ms.end());
+  if ((int)ms.size() > kMaxG) return fail(DOTPE_E_INVALID_ARG, "too many distinct m");
+  std::memset(mt, 0, sizeof(*mt));
+  mt->n_c = nc;
+  mt->G = (int)ms.size();
+  int c2 = 0;
+  const int cpc = n_bp / kChunk;
+  for (int g = 0; g < mt->G; ++g) {
+    mt->gm[g] = ms[g];
+    mt->gk0[g] = c2 * cpc;
+    for (int c = 0; c < nc; ++c)
+      if (d->mode_m[c] == ms[g]) {
+        mt->l[c2] = d->mode_l[c];
+        mt->m[c2] = d->mode_m[c];
+        mt->orig[c2] = c;
+        ++c2;
+      }
+  }
+  mt->gk0[mt->G] = c2 * cpc;
+  mt->ND = ms.back() - ms.front() + 1;
+  int p = 0;
+  for (int a = 0; a < nc; ++a)
+    for (int b = a; b < nc; ++b) {
+      mt->pc[p] = a;
+      mt->pc2[p] = b;
+      mt->pdel[p] = mt->m[a] - mt->m[b];
+      ++p;
+    }
+  mt->NP = p;
+  return DOTPE_OK;
+}
+
+template <int PREC>
+void launch_bank_convert(const double* h, dotpe_bank* bk, int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_bank_convert<PREC>, dim3((unsigned)bk->n_wf), dim3(256), 0, s, h, bk->n_wf,
+                     bk->n_c, bk->n_b, bk->n_bp, bk->mt, bk->A0, bk->A1, bk->row_scale, err);
+}
+
+template <int PREC>
+void launch_convert_B(dotpe_event* ev, const double2* Btmp, int* err) {
+  const dotpe_bank* bk = ev->bank;
+  hipLaunchKernelGGL(k_convert_B<PREC>, dim3((unsigned)ev->n_ext_p), dim3(256), 0, ev->stream,
+                     ev->n_ext, ev->n_ext_p, bk->n_c, bk->n_bp, Btmp, ev->B[0], ev->B[1], ev->B[2],
+                     ev->B[3], ev->col_scale, err);
+}
+
+template <int PREC>
+void launch_hh(dotpe_event* ev, const double* w) {
+  const dotpe_bank* bk = ev->bank;
+  size_t sh = (size_t)bk->n_c * bk->n_bp * sizeof(double2);
+  if (sh > 65536) sh = 0;
+  hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(64), sh, ev->stream,
+                     ev->n_sub, ev->sub_idx, ev->sub0, bk->A0, bk->A1, bk->row_scale, bk->n_bp,
+                     bk->n_b, ev->n_det, w, bk->mt, ev->H, ev->Hdiag);
+}
+
+template <int PREC, int G, int MODE>
+int launch_fused_t(const FusedArgs& a, int64_t grid, hipStream_t s) {
+  typedef Tile<PREC> TL;
+  size_t sh = TL::MAIN_BYTES + sizeof(double) * kMaxM * a.n_phi * 2;
+  static bool attr_set = false;
+  if (!attr_set) {
+    // allow more than 64 KiB of dynamic LDS; not every runtime needs or
+    // supports the attribute, so a failure here is not an error
+    if (hipFuncSetAttribute((const void*)k_lnl_fused<PREC, G, MODE>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh + 16384) != hipSuccess)
+      (void)hipGetLastError();
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_lnl_fused<PREC, G, MODE>), dim3((unsigned)grid), dim3(256), sh, s, a);
+  HIP_OK(hipGetLastError());
+  return DOTPE_OK;
+}
+
+template <int PREC, int MODE>
+int launch_fused_g(const FusedArgs& a, int64_t grid, hipStream_t s) {
+  switch (a.mt.G) {
+    case 1: return launch_fused_t<PREC, 1, MODE>(a, grid, s);
+    case 2: return launch_fused_t<PREC, 2, MODE>(a, grid, s);
+    case 3: return launch_fused_t<PREC, 3, MODE>(a, grid, s);
+    case 4: return launch_fused_t<PREC, 4, MODE>(a, grid, s);
+  }
+  return fail(DOTPE_E_INVALID_ARG, "bad group count %d", a.mt.G);
+}
+
+template <int MODE>
+int launch_fused(int prec, const FusedArgs& a, int64_t grid, hipStream_t s) {
+  switch (prec) {
+    case kFP64: return launch_fused_g<kFP64, MODE>(a, grid, s);
+    case kFP16X2: return launch_fused_g<kFP16X2, MODE>(a, grid, s);
+    case kBF16X2: return launch_fused_g<kBF16X2, MODE>(a, grid, s);
+  }
+  return fail(DOTPE_E_INVALID_ARG, "bad precision %d", prec);
+}
+
+void tile_shape(int prec, int* tm, int* tn) {
+  if (prec == kFP64) {
+    *tm = Tile<kFP64>::TM;
+    *tn = Tile<kFP64>::TN;
+  } else {
+    *tm = Tile<kFP16X2>::TM;
+    *tn = Tile<kFP16X2>::TN;
+  }
+}
+
+FusedArgs make_args(dotpe_ctx* ctx, dotpe_event* ev) {
+  const dotpe_bank* bk = ev->bank;
+  FusedArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.A0 = bk->A0;
+  a.A1 = bk->A1;
+  a.row_scale = bk->row_scale;
+  a.ln_w_bank = bk->ln_w;
+  a.sub_idx = ev->sub_idx;
+  a.sub0 = ev->sub0;
+  a.n_sub = ev->n_sub;
+  a.B0 = ev->B[0];
+  a.B1 = ev->B[1];
+  a.B2 = ev->B[2];
+  a.B3 = ev->B[3];
+  a.col_scale = ev->col_scale;
+  a.ln_w_ext = ev->ln_w_ext;
+  a.n_ext = ev->n_ext;
+  a.n_ext_p = ev->n_ext_p;
+  a.K2 = bk->K2;
+  a.n_chunks = (int)(bk->K2 / 32);
+  a.H = ev->H;
+  a.Hdiag = ev->Hdiag;
+  a.Q = ev->Q;
+  a.R2 = ev->R2;
+  a.n_det = ev->n_det;
+  a.mt = bk->mt;
+  a.n_phi = ev->n_phi;
+  a.phase_cs = ev->phase_cs;
+  a.ln_nphi = std::log((double)ev->n_phi);
+  a.dist.tab = ctx->dist_tab;
+  a.dist.geom = ctx->geom;
+  for (int k = 0; k < kGH; ++k) {
+    a.dist.ghx[k] = ctx->ghx[k];
+    a.dist.ghw[k] = ctx->ghw[k];
+  }
+  a.r0 = ev->d0 / ev->d_max;
+  a.cut_delta = ev->cut_delta;
+  a.topk_window = ev->topk_window;
+  int tm, tn;
+  tile_shape(bk->prec, &tm, &tn);
+  a.n_tiles_m = (ev->n_sub + tm - 1) / tm;
+  a.n_tiles_n = (ev->n_ext + tn - 1) / tn;
+  a.n_tiles = a.n_tiles_m * a.n_tiles_n;
+  return a;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+__global__ void k_reset_state(uint64_t* st) {
+  if (threadIdx.x == 0) {
+    st[0] = 0ull;                       // bits of +0.0
+    st[1] = 0x000fffffffffffffull;      // ordered encoding below every finite value
+    st[2] = 0ull;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dotpe_version(void) { return "dotpe 0.1 (gfx950)"; }
+
+const char* dotpe_last_error(void) { return g_err.c_str(); }
+
+int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
+  if (!out) return fail(DOTPE_E_INVALID_ARG, "out is NULL");
+  int n = 0;
+  HIP_OK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(DOTPE_E_INVALID_ARG, "device %d of %d", device, n);
+  HIP_OK(hipSetDevice(device));
+  dotpe_ctx* ctx = new dotpe_ctx();
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  hipError_t e = hipStreamCreate(&ctx->stream);
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(DOTPE_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+  }
+  ctx->geom = dr_make_geom();
+  DistTableGeom& g = ctx->geom;
+  size_t ntab = (size_t)g.ncol * g.nt;
+  ctx->budget = 0;
+  int rc = dev_alloc(ctx, (void**)&ctx->dist_tab, ntab * sizeof(double), nullptr, nullptr);
+  ctx->budget = hbm_budget_bytes;
+  ctx->own_bytes = ctx->bytes;
+  if (rc) {
+    hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return rc;
+  }
+  hipLaunchKernelGGL(k_build_dist_table, dim3((unsigned)((ntab + 255) / 256)), dim3(256), 0,
+                     ctx->stream, ctx->dist_tab, g);
+  gauss_hermite(kGH, ctx->ghx, ctx->ghw);
+  e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    dotpe_destroy(ctx);
+    return fail(DOTPE_E_DEVICE, "distance table build: %s", hipGetErrorString(e));
+  }
+  *out = ctx;
+  return DOTPE_OK;
+}
+
+int dotpe_destroy(dotpe_ctx* ctx) {
+  if (!ctx) return DOTPE_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->dist_tab) (void)hipFree(ctx->dist_tab);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return DOTPE_OK;
+}
+
+uint64_t dotpe_device_bytes(const dotpe_ctx* ctx) { return ctx ? ctx->bytes : 0; }
+
+int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) {
+  if (!ctx || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (d->n_wf < 1 || d->n_modes < 1 || d->n_modes > kMaxC || d->n_bins < 1 || d->n_bins > 4096)
+    return fail(DOTPE_E_INVALID_ARG, "bank shape n_wf=%lld n_modes=%d n_bins=%d out of range",
+                (long long)d->n_wf, d->n_modes, d->n_bins);
+  if (!d->mode_l || !d->mode_m || !d->f_bins || !d->h)
+    return fail(DOTPE_E_INVALID_ARG, "bank arrays must not be NULL");
+  if (d->precision < 0 || d->precision > 2) return fail(DOTPE_E_INVALID_ARG, "bad precision");
+  if (d->mem != DOTPE_MEM_HOST && d->mem != DOTPE_MEM_DEVICE)
+    return fail(DOTPE_E_INVALID_ARG, "bad mem");
+  if (!finite_all(d->f_bins, d->n_bins)) return fail(DOTPE_E_NUMERIC, "non-finite f_bins");
+  HIP_OK(hipSetDevice(ctx->device));
+  dotpe_bank* bk = new dotpe_bank();
+  bk->n_wf = d->n_wf;
+  bk->n_c = d->n_modes;
+  bk->n_b = d->n_bins;
+  bk->n_bp = (int)round_up(d->n_bins, kChunk);
+  bk->K2 = (int64_t)bk->n_c * bk->n_bp * 2;
+  bk->prec = d->precision;
+  int rc = build_modes(d, &bk->mt, bk->n_bp);
+  if (rc) {
+    delete bk;
+    return rc;
+  }
+  bk->f_host.assign(d->f_bins, d->f_bins + d->n_bins);
+  std::vector<void*> owned;
+  auto cleanup = [&](int code) {
+    for (void* p : owned) (void)hipFree(p);
+    ctx->bytes -= bk->bytes;
+    delete bk;
+    return code;
+  };
+  const size_t esz = bk->prec == kFP64 ? 8 : 2;
+  const size_t nA = (size_t)bk->n_wf * bk->K2;
+  if ((rc = dev_alloc(ctx, &bk->A0, nA * esz, &owned, &bk->bytes))) return cleanup(rc);
+  if (bk->prec != kFP64) {
+    if ((rc = dev_alloc(ctx, &bk->A1, nA * esz, &owned, &bk->bytes))) return cleanup(rc);
+    if ((rc = dev_alloc(ctx, (void**)&bk->row_scale, bk->n_wf * 8, &owned, &bk->bytes)))
+      return cleanup(rc);
+  }
+  if ((rc = dev_alloc(ctx, (void**)&bk->f, bk->n_b * 8, &owned, &bk->bytes))) return cleanup(rc);
+  if ((rc = dev_alloc(ctx, (void**)&bk->ln_w, bk->n_wf * 8, &owned, &bk->bytes)))
+    return cleanup(rc);
+  int* err = nullptr;
+  if ((rc = dev_alloc(ctx, (void**)&err, 64, &owned, &bk->bytes))) return cleanup(rc);
+  hipStream_t s = ctx->stream;
+  auto hip_fail = [&](hipError_t e, const char* what) {
+    (void)hipStreamSynchronize(s);
+    int c = fail(DOTPE_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return cleanup(c);
+  };
+  hipError_t e;
+  if ((e = hipMemcpyAsync(bk->f, d->f_bins, bk->n_b * 8, hipMemcpyHostToDevice, s)))
+    return hip_fail(e, "copy f");
+  if ((e = hipMemsetAsync(err, 0, 64, s))) return hip_fail(e, "memset");
+  if (d->ln_w) {
+    if ((e = hipMemcpyAsync(bk->ln_w, d->ln_w, bk->n_wf * 8,
+                            d->mem == DOTPE_MEM_HOST ? hipMemcpyHostToDevice
+                                                     : hipMemcpyDeviceToDevice, s)))
+      return hip_fail(e, "copy ln_w");
+  } else if ((e = hipMemsetAsync(bk->ln_w, 0, bk->n_wf * 8, s))) {
+    return hip_fail(e, "memset ln_w");
+  }
+  if (bk->prec == kFP64 && (e = hipMemsetAsync(bk->A0, 0, nA * esz, s)))
+    return hip_fail(e, "memset A");
+  // amplitudes: staged through a bounded device buffer when on the host
+  const size_t row_bytes = (size_t)bk->n_c * bk->n_b * 16;
+  if (d->mem == DOTPE_MEM_DEVICE) {
+    switch (bk->prec) {
+      case kFP64: launch_bank_convert<kFP64>(d->h, bk, err, s); break;
+      case kFP16X2: launch_bank_convert<kFP16X2>(d->h, bk, err, s); break;
+      default: launch_bank_convert<kBF16X2>(d->h, bk, err, s); break;
+    }
+    if ((e = hipGetLastError())) return hip_fail(e, "bank convert");
+  } else {
+    int64_t rows_per = std::max<int64_t>(1, (int64_t)((256ull << 20) / row_bytes));
+    rows_per = std::min(rows_per, bk->n_wf);
+    double* stagebuf = nullptr;
+    if ((e = hipMalloc((void**)&stagebuf, rows_per * row_bytes))) return hip_fail(e, "stage alloc");
+    for (int64_t r0 = 0; r0 < bk->n_wf; r0 += rows_per) {
+      int64_t nr = std::min(rows_per, bk->n_wf - r0);
+      e = hipMemcpyAsync(stagebuf, d->h + (size_t)r0 * bk->n_c * bk->n_b * 2, nr * row_bytes,
+                         hipMemcpyHostToDevice, s);
+      if (e) break;
+      dotpe_bank view = *bk;
+      view.n_wf = nr;
+      view.A0 = (char*)bk->A0 + (size_t)r0 * bk->K2 * esz;
+      view.A1 = bk->A1 ? (char*)bk->A1 + (size_t)r0 * bk->K2 * esz : nullptr;
+      view.row_scale = bk->row_scale ? bk->row_scale + r0 : nullptr;
+      switch (bk->prec) {
+        case kFP64: launch_bank_convert<kFP64>(stagebuf, &view, err, s); break;
+        case kFP16X2: launch_bank_convert<kFP16X2>(stagebuf, &view, err, s); break;
+        default: launch_bank_convert<kBF16X2>(stagebuf, &view, err, s); break;
+      }
+      if ((e = hipGetLastError())) break;
+      if ((e = hipStreamSynchronize(s))) break;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(stagebuf);
+    if (e) return hip_fail(e, "bank staging");
+  }
+  int herr = 0;
+  if ((e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s)))
+    return hip_fail(e, "copy err");
+  if ((e = hipStreamSynchronize(s))) return hip_fail(e, "bank sync");
+  if (herr) return cleanup(fail(DOTPE_E_NUMERIC, "non-finite bank amplitudes"));
+  (void)hipFree(err);
+  owned.erase(std::find(owned.begin(), owned.end(), (void*)err));
+  ctx->bytes -= 64;
+  bk->bytes -= 64;
+  *out = bk;
+  return DOTPE_OK;
+}
+
+int dotpe_free_bank(dotpe_ctx* ctx, dotpe_bank* bk) {
+  if (!ctx || !bk) return DOTPE_OK;
+  (void)hipSetDevice(ctx->device);
+  for (void* p : {bk->A0, bk->A1, (void*)bk->row_scale, (void*)bk->f, (void*)bk->ln_w})
+    if (p) (void)hipFree(p);
+  ctx->bytes -= bk->bytes;
+  delete bk;
+  return DOTPE_OK;
+}
+
+int dotpe_free_event(dotpe_ctx* ctx, dotpe_event* ev) {
+  if (!ctx || !ev) return DOTPE_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ev->stream);
+  for (void* p : ev->allocs) (void)hipFree(p);
+  for (hipEvent_t t : ev->ev_t)
+    if (t) (void)hipEventDestroy(t);
+  ctx->bytes -= ev->bytes;
+  delete ev;
+  return DOTPE_OK;
+}
+
+int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d,
+                    dotpe_event** out) {
+  if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
+  if (d->n_phi < 1 || d->n_phi > kMaxPhi) return fail(DOTPE_E_INVALID_ARG, "n_phi=%d", d->n_phi);
+  if (d->n_ext < 1) return fail(DOTPE_E_INVALID_ARG, "n_ext=%lld", (long long)d->n_ext);
+  if (!d->d || !d->w || !d->det_r || !d->det_D || !d->lat || !d->lon || !d->psi || !d->cos_iota ||
+      !d->t_geo)
+    return fail(DOTPE_E_INVALID_ARG, "event arrays must not be NULL");
+  if (!(d->d_max > 0.0) || !(d->d0 > 0.0) || !std::isfinite(d->d_max) || !std::isfinite(d->d0))
+    return fail(DOTPE_E_INVALID_ARG, "distances must be positive and finite");
+  const int nb = bk->n_b, nk = d->n_det;
+  const int64_t ne = d->n_ext;
+  if (!finite_all(d->d, (size_t)nk * nb * 2) || !finite_all(d->w, (size_t)nk * nb) ||
+      !finite_all(d->det_r, nk * 3) || !finite_all(d->det_D, nk * 9) || !finite_all(d->lat, ne) ||
+      !finite_all(d->lon, ne) || !finite_all(d->psi, ne) || !finite_all(d->cos_iota, ne) ||
+      !finite_all(d->t_geo, ne) || (d->ln_w_ext && !finite_all(d->ln_w_ext, ne)))
+    return fail(DOTPE_E_NUMERIC, "non-finite event input");
+  for (int64_t e = 0; e < ne; ++e)
+    if (std::fabs(d->cos_iota[e]) > 1.0) return fail(DOTPE_E_INVALID_ARG, "|cos_iota| > 1");
+  for (size_t t = 0; t < (size_t)nk * nb; ++t)
+    if (d->w[t] < 0.0) return fail(DOTPE_E_INVALID_ARG, "negative noise weight");
+  int64_t n_sub = d->sub_count > 0 ? d->sub_count : bk->n_wf;
+  if (d->sub_idx) {
+    if (d->sub_count < 1) return fail(DOTPE_E_INVALID_ARG, "sub_idx needs sub_count >= 1");
+    for (int64_t r = 0; r < n_sub; ++r)
+      if (d->sub_idx[r] < 0 || d->sub_idx[r] >= bk->n_wf)
+        return fail(DOTPE_E_INVALID_ARG, "sub_idx[%lld]=%lld out of range", (long long)r,
+                    (long long)d->sub_idx[r]);
+  } else if (d->sub_start < 0 || d->sub_start + n_sub > bk->n_wf) {
+    return fail(DOTPE_E_INVALID_ARG, "bank range out of bounds");
+  }
+  HIP_OK(hipSetDevice(ctx->device));
+  dotpe_event* ev = new dotpe_event();
+  ev->bank = bk;
+  ev->stream = d->stream ? (hipStream_t)d->stream : ctx->stream;
+  ev->n_det = nk;
+  ev->n_phi = d->n_phi;
+  ev->n_ext = ne;
+  ev->n_ext_p = round_up(ne, 64);
+  ev->n_sub = n_sub;
+  ev->sub0 = d->sub_idx ? 0 : d->sub_start;
+  ev->d0 = d->d0;
+  ev->d_max = d->d_max;
+  ev->n_norm = d->n_norm > 0 ? d->n_norm : (double)n_sub;
+  ev->cut_delta = d->cut_delta;
+  ev->topk_window = d->topk_window > 0 ? d->topk_window : 40.0;
+  ev->top_k = std::max(0, d->top_k);
+  const ModeTables& mt = bk->mt;
+  const int nc = bk->n_c;
+  hipStream_t s = ev->stream;
+  int rc;
+  auto cleanup = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    for (void* p : ev->allocs) (void)hipFree(p);
+    ctx->bytes -= ev->bytes;
+    delete ev;
+    return code;
+  };
+  auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &ev->allocs, &ev->bytes); };
+  const size_t esz = bk->prec == kFP64 ? 8 : 2;
+  const int nB = bk->prec == kFP64 ? 2 : 4;
+  for (int q = 0; q < nB; ++q)
+    if ((rc = alloc(&ev->B[q], (size_t)ev->n_ext_p * bk->K2 * esz))) return cleanup(rc);
+  if (bk->prec != kFP64 && (rc = alloc((void**)&ev->col_scale, ne * 8))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->H, (size_t)n_sub * nk * mt.NP * 16))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->Hdiag, (size_t)n_sub * nk * nc * 8))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->Q, (size_t)ne * nk * mt.NP * 16))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->R2, (size_t)ne * nk * nc * 8))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->R, (size_t)ne * nk * nc * 16))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->T, (size_t)ne * nk * 8))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->phase_cs, (size_t)kMaxM * d->n_phi * 2 * 8))) return cleanup(rc);
+  if (d->ln_w_ext && (rc = alloc((void**)&ev->ln_w_ext, ne * 8))) return cleanup(rc);
+  if (d->sub_idx && (rc = alloc((void**)&ev->sub_idx, n_sub * 8))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->state, 64))) return cleanup(rc);
+  if ((rc = alloc((void**)&ev->final_out, kNPart * 8 + 64))) return cleanup(rc);
+  // staging inputs (freed at the end of this call)
+  std::vector<void*> tmp;
+  uint64_t tmp_bytes = 0;
+  auto talloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &tmp, &tmp_bytes); };
+  auto done_tmp = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : tmp) (void)hipFree(p);
+    ctx->bytes -= tmp_bytes;
+    tmp.clear();
+    tmp_bytes = 0;
+  };
+  double *dd = nullptr, *dw = nullptr, *dr = nullptr, *dD = nullptr, *dlat = nullptr,
+         *dlon = nullptr, *dpsi = nullptr, *dci = nullptr, *dtg = nullptr;
+  double2* Btmp = nullptr;
+  int* err = nullptr;
+  size_t sizes[] = {(size_t)nk * nb * 16, (size_t)nk * nb * 8, (size_t)nk * 24, (size_t)nk * 72,
+                    (size_t)ne * 8, (size_t)ne * 8, (size_t)ne * 8, (size_t)ne * 8, (size_t)ne * 8,
+                    (size_t)ne * nc * bk->n_bp * 16, 64};
+  void** ptrs[] = {(void**)&dd, (void**)&dw, (void**)&dr, (void**)&dD, (void**)&dlat,
+                   (void**)&dlon, (void**)&dpsi, (void**)&dci, (void**)&dtg, (void**)&Btmp,
+                   (void**)&err};
+  for (int q = 0; q < 11; ++q) {
+    if ((rc = talloc(ptrs[q], sizes[q]))) {
+      done_tmp();
+      return cleanup(rc);
+    }
+  }
+  hipError_t e = hipSuccess;
+  auto H2D = [&](void* dst, const void* src, size_t n) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+  };
+  H2D(dd, d->d, sizes[0]);
+  H2D(dw, d->w, sizes[1]);
+  H2D(dr, d->det_r, sizes[2]);
+  H2D(dD, d->det_D, sizes[3]);
+  H2D(dlat, d->lat, sizes[4]);
+  H2D(dlon, d->lon, sizes[5]);
+  H2D(dpsi, d->psi, sizes[6]);
+  H2D(dci, d->cos_iota, sizes[7]);
+  H2D(dtg, d->t_geo, sizes[8]);
+  if (d->ln_w_ext) H2D(ev->ln_w_ext, d->ln_w_ext, ne * 8);
+  if (d->sub_idx) H2D(ev->sub_idx, d->sub_idx, n_sub * 8);
+  if (e == hipSuccess) e = hipMemsetAsync(err, 0, 64, s);
+  // phase table cos, sin (m phi_o), m = 1..4 (a twiddle table of the grid)
+  std::vector<double> cs((size_t)kMaxM * d->n_phi * 2);
+  for (int m = 1; m <= kMaxM; ++m)
+    for (int o = 0; o < d->n_phi; ++o) {
+      double ph = 2.0 * M_PI * (double)((m * o) % d->n_phi) / d->n_phi;
+      cs[((m - 1) * d->n_phi + o) * 2] = std::cos(ph);
+      cs[((m - 1) * d->n_phi + o) * 2 + 1] = std::sin(ph);
+    }
+  H2D(ev->phase_cs, cs.data(), cs.size() * 8);
+  if (e != hipSuccess) {
+    done_tmp();
+    return cleanup(fail(DOTPE_E_DEVICE, "event upload: %s", hipGetErrorString(e)));
+  }
+  // extrinsic response, B operand, (h|h) tables, (d|d)
+  hipLaunchKernelGGL(k_ext_response, dim3((unsigned)((ne + 127) / 128)), dim3(128), 0, s, ne, nk,
+                     dr, dD, dlat, dlon, dpsi, dci, dtg, mt, ev->R, ev->T, ev->Q, ev->R2);
+  int64_t nbt = ne * nc * bk->n_bp;
+  hipLaunchKernelGGL(k_build_B, dim3((unsigned)((nbt + 255) / 256)), dim3(256), 0, s, ne, nk, nc,
+                     nb, bk->n_bp, bk->f, (const double2*)dd, dw, ev->R, ev->T, Btmp);
+  switch (bk->prec) {
+    case kFP64: launch_convert_B<kFP64>(ev, Btmp, err); break;
+    case kFP16X2: launch_convert_B<kFP16X2>(ev, Btmp, err); break;
+    default: launch_convert_B<kBF16X2>(ev, Btmp, err); break;
+  }
+  switch (bk->prec) {
+    case kFP64: launch_hh<kFP64>(ev, dw); break;
+    case kFP16X2: launch_hh<kFP16X2>(ev, dw); break;
+    default: launch_hh<kBF16X2>(ev, dw); break;
+  }
+  hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(256), 0, s, nk * nb, (const double2*)dd, dw,
+                     ev->final_out + kNPart);
+  e = hipGetLastError();
+  int herr = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&ev->dd, ev->final_out + kNPart, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  done_tmp();
+  if (e != hipSuccess) return cleanup(fail(DOTPE_E_DEVICE, "event staging: %s", hipGetErrorString(e)));
+  if (herr) return cleanup(fail(DOTPE_E_NUMERIC, "non-finite extrinsic operand"));
+  *out = ev;
+  return DOTPE_OK;
+}
+
+int dotpe_eval_lnl(dotpe_ctx* ctx, dotpe_event* ev, double* lnl, double* ml_max, double* triples,
+                   int32_t mem) {
+  if (!ctx || !ev || !lnl) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (mem != DOTPE_MEM_HOST && mem != DOTPE_MEM_DEVICE) return fail(DOTPE_E_INVALID_ARG, "bad mem");
+  HIP_OK(hipSetDevice(ctx->device));
+  const size_t npair = (size_t)ev->n_sub * ev->n_ext;
+  const size_t ntrip = triples ? npair * ev->n_phi * 2 : 0;
+  hipStream_t s = ev->stream;
+  double *o1 = lnl, *o2 = ml_max, *o3 = triples;
+  std::vector<void*> tmp;
+  uint64_t tb = 0;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (void* p : tmp) (void)hipFree(p);
+    ctx->bytes -= tb;
+  };
+  int rc;
+  if (mem == DOTPE_MEM_HOST) {
+    if ((rc = dev_alloc(ctx, (void**)&o1, npair * 8, &tmp, &tb))) { release(); return rc == DOTPE_E_ADMISSION ? fail(DOTPE_E_TOO_LARGE, "%s", g_err.c_str()) : rc; }
+    if (ml_max && (rc = dev_alloc(ctx, (void**)&o2, npair * 8, &tmp, &tb))) { release(); return rc == DOTPE_E_ADMISSION ? fail(DOTPE_E_TOO_LARGE, "%s", g_err.c_str()) : rc; }
+    if (triples && (rc = dev_alloc(ctx, (void**)&o3, ntrip * 8, &tmp, &tb))) { release(); return rc == DOTPE_E_ADMISSION ? fail(DOTPE_E_TOO_LARGE, "%s", g_err.c_str()) : rc; }
+  }
+  FusedArgs a = make_args(ctx, ev);
+  a.lnl_out = o1;
+  a.ml_out = ml_max ? o2 : nullptr;
+  a.trip_out = triples ? o3 : nullptr;
+  int64_t grid = round_up(a.n_tiles, 8);
+  rc = launch_fused<kEval>(ev->bank->prec, a, grid, s);
+  if (rc) { release(); return rc; }
+  hipError_t e = hipSuccess;
+  if (mem == DOTPE_MEM_HOST) {
+    e = hipMemcpyAsync(lnl, o1, npair * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && ml_max) e = hipMemcpyAsync(ml_max, o2, npair * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && triples) e = hipMemcpyAsync(triples, o3, ntrip * 8, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
+  if (e != hipSuccess) return fail(DOTPE_E_DEVICE, "eval_lnl: %s", hipGetErrorString(e));
+  return DOTPE_OK;
+}
+
+int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, dotpe_sample* topk) {
+  if (!ctx || !ev || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ev->stream;
+  FusedArgs a = make_args(ctx, ev);
+  int rc;
+  // scratch sized for this event (kept with the event)
+  if (!ev->partials) {
+    if ((rc = dev_alloc(ctx, (void**)&ev->partials, (size_t)a.n_tiles * kNPart * 8, &ev->allocs,
+                        &ev->bytes)))
+      return rc;
+    int64_t cap = std::max<int64_t>(1 << 16, 16 * (int64_t)ev->top_k);
+    if ((rc = dev_alloc(ctx, (void**)&ev->cand, (size_t)cap * 32, &ev->allocs, &ev->bytes)))
+      return rc;
+    ev->cand_cap = cap;
+  }
+  a.state = ev->state;
+  a.partials = ev->partials;
+  a.cand = ev->cand;
+  a.cand_cap = ev->cand_cap;
+  if (!ev->ev_t[0]) {
+    HIP_OK(hipEventCreate(&ev->ev_t[0]));
+    HIP_OK(hipEventCreate(&ev->ev_t[1]));
+    HIP_OK(hipEventCreate(&ev->ev_t[2]));
+  }
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
+  HIP_OK(hipEventRecord(ev->ev_t[0], s));
+  if (ev->cut_delta > 0.0 && a.n_tiles_m > 1) {
+    // pilot: max lnL^ML over every 16th row of tiles seeds the cut threshold
+    a.pilot_stride = 16;
+    int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
+    if ((rc = launch_fused<kPilot>(ev->bank->prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
+  }
+  HIP_OK(hipEventRecord(ev->ev_t[1], s));
+  int64_t grid = round_up(a.n_tiles, 8);
+  if ((rc = launch_fused<kEvidence>(ev->bank->prec, a, grid, s))) return rc;
+  HIP_OK(hipEventRecord(ev->ev_t[2], s));
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ev->partials, a.n_tiles, ev->final_out);
+  HIP_OK(hipGetLastError());
+  double fo[kNPart];
+  uint64_t st[3];
+  HIP_OK(hipMemcpyAsync(fo, ev->final_out, sizeof(fo), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(st, ev->state, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const double ln_norm = std::log(ev->n_norm) + std::log((double)ev->n_ext);
+  dotpe_evidence_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.ln_sum_p = fo[0] + std::log(fo[1]);
+  r.ln_sum_p2 = 2.0 * fo[0] + std::log(fo[2]);
+  r.ln_z = r.ln_sum_p - ln_norm;
+  double ln_drop = (fo[3] == -INFINITY) ? -INFINITY : fo[3] + std::log(fo[4]);
+  double mx = std::max(r.ln_sum_p, ln_drop);
+  r.ln_z_upper = (mx == -INFINITY) ? -INFINITY
+                                   : mx + std::log(std::exp(r.ln_sum_p - mx) + std::exp(ln_drop - mx)) - ln_norm;
+  r.max_lnl_ml = fo[5];
+  r.n_triples_marg = (int64_t)fo[6];
+  r.n_pairs_bounded = (int64_t)fo[7];
+  r.max_ln_p = fo[9];
+  r.n_pairs = (int64_t)fo[10];
+  r.dd = ev->dd;
+  r.precision = ev->bank->prec;
+  float t_pilot = 0.f, t_main = 0.f;
+  HIP_OK(hipEventElapsedTime(&t_pilot, ev->ev_t[0], ev->ev_t[1]));
+  HIP_OK(hipEventElapsedTime(&t_main, ev->ev_t[1], ev->ev_t[2]));
+  r.t_pilot_ms = t_pilot;
+  r.t_fused_ms = t_main;
+  // top-k among candidates within the window of the final maximum
+  int64_t ncand = std::min<int64_t>((int64_t)st[2], ev->cand_cap);
+  const double thr = r.max_ln_p - ev->topk_window;
+  r.topk_exact = ((int64_t)st[2] <= ev->cand_cap && !(fo[8] >= thr)) ? 1 : 0;
+  if (ev->top_k > 0 && topk && ncand > 0) {
+    int64_t n2 = 1;
+    while (n2 < ncand) n2 <<= 1;
+    double* buf = ev->cand;
+    void* extra = nullptr;
+    uint64_t xb = 0;
+    std::vector<void*> xo;
+    if (n2 > ev->cand_cap) {
+      if ((rc = dev_alloc(ctx, &extra, (size_t)n2 * 32, &xo, &xb))) return rc;
+      HIP_OK(hipMemcpyAsync(extra, ev->cand, ncand * 32, hipMemcpyDeviceToDevice, s));
+      buf = (double*)extra;
+    }
+    if (n2 > ncand)
+      hipLaunchKernelGGL(k_fill_cand, dim3((unsigned)((n2 - ncand + 255) / 256)), dim3(256), 0, s,
+                         buf, ncand, n2);
+    for (int64_t k = 2; k <= n2; k <<= 1)
+      for (int64_t j = k >> 1; j > 0; j >>= 1)
+        hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, buf,
+                           n2, j, k);
+    int64_t take = std::min<int64_t>(ev->top_k, ncand);
+    std::vector<double> h(take * 4);
+    HIP_OK(hipMemcpyAsync(h.data(), buf, take * 32, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (extra) {
+      (void)hipFree(extra);
+      ctx->bytes -= xb;
+    }
+    int cnt = 0;
+    for (int64_t q = 0; q < take; ++q) {
+      if (!(h[4 * q] >= thr)) break;
+      topk[cnt].ln_p = h[4 * q];
+      topk[cnt].i = (int64_t)h[4 * q + 1];
+      topk[cnt].e = (int64_t)h[4 * q + 2];
+      topk[cnt].o_best = (int32_t)h[4 * q + 3];
+      topk[cnt].reserved = 0;
+      ++cnt;
+    }
+    r.topk_count = cnt;
+  }
+  r.status = DOTPE_OK;
+  *out = r;
+  return DOTPE_OK;
+}
+
+int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const double* hh,
+                         double r0, double* out) {
+  if (!ctx || n < 0 || (n > 0 && (!dh || !hh || !out))) return fail(DOTPE_E_INVALID_ARG, "bad args");
+  if (n == 0) return DOTPE_OK;
+  HIP_OK(hipSetDevice(ctx->device));
+  double* buf = nullptr;
+  std::vector<void*> tmp;
+  uint64_t tb = 0;
+  int rc;
+  if ((rc = dev_alloc(ctx, (void**)&buf, (size_t)n * 24, &tmp, &tb))) return rc;
+  hipStream_t s = ctx->stream;
+  DistArgs da;
+  da.tab = ctx->dist_tab;
+  da.geom = ctx->geom;
+  for (int k = 0; k < kGH; ++k) {
+    da.ghx[k] = ctx->ghx[k];
+    da.ghw[k] = ctx->ghw[k];
+  }
+  hipError_t e = hipMemcpyAsync(buf, dh, n * 8, hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(buf + n, hh, n * 8, hipMemcpyHostToDevice, s);
+  if (!e) {
+    hipLaunchKernelGGL(k_debug_distmarg, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, buf,
+                       buf + n, r0, da, buf + 2 * n);
+    e = hipGetLastError();
+  }
+  if (!e) e = hipMemcpyAsync(out, buf + 2 * n, n * 8, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  ctx->bytes -= tb;
+  if (e) return fail(DOTPE_E_DEVICE, "debug_distmarg: %s", hipGetErrorString(e));
+  return DOTPE_OK;
+}
+
+int dotpe_debug_response(dotpe_ctx* ctx, const dotpe_event* ev, double* R, double* t) {
+  if (!ctx || !ev || !R || !t) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  HIP_OK(hipSetDevice(ctx->device));
+  const dotpe_bank* bk = ev->bank;
+  const int nc = bk->n_c;
+  std::vector<double> Rg((size_t)ev->n_ext * ev->n_det * nc * 2);
+  HIP_OK(hipMemcpyAsync(Rg.data(), ev->R, Rg.size() * 8, hipMemcpyDeviceToHost, ev->stream));
+  HIP_OK(hipMemcpyAsync(t, ev->T, (size_t)ev->n_ext * ev->n_det * 8, hipMemcpyDeviceToHost,
+                        ev->stream));
+  HIP_OK(hipStreamSynchronize(ev->stream));
+  for (int64_t e = 0; e < ev->n_ext; ++e)
+    for (int k = 0; k < ev->n_det; ++k)
+      for (int c = 0; c < nc; ++c) {
+        size_t src = ((e * ev->n_det + k) * nc + c) * 2;
+        size_t dst = ((e * ev->n_det + k) * nc + bk->mt.orig[c]) * 2;
+        R[dst] = Rg[src];
+        R[dst + 1] = Rg[src + 1];
+      }
+  return DOTPE_OK;
+}
+
+}  // extern "C"

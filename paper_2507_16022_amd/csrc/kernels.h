@@ -1,0 +1,1036 @@
+// Device kernels of the likelihood-matrix hot path (gfx950, wave64, MFMA).
+//
+// Notation: i bank row (subset index ie), e extrinsic sample, k detector,
+// c mode channel (channels reordered so that equal m are contiguous; g the
+// group of channels sharing m), b frequency bin, o phase grid index.
+//
+// (d|h) for a triple (eq. dh_ieo) is rearranged as
+//     dh_ieo = Re sum_g exp(i m_g phi_o) X_ieg,
+//     X_ieg  = sum_{c in g} sum_b conj(h_icb) B_cb(e),
+//     B_cb(e) = sum_k w_kb d_kb conj(R_ekc) exp(+2 pi i f_b t_ek),
+// i.e. a complex GEMM over K = (c, b) with the detector sum folded into the
+// extrinsic operand; (h|h) (eq. hh_ieo) as
+//     hh_ieo = S0 + 2 Re sum_{delta > 0} S_delta exp(-i delta phi_o),
+//     S_delta = sum_k sum_{c,c': m_c - m_c' = delta} H_ikcc' Q_ekcc',
+//     H_ikcc' = sum_b w_kb h_icb conj(h_ic'b),  Q_ekcc' = R_ekc conj(R_ekc').
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "dist_rule.h"
+
+namespace dotpe {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxC = 8;        // channels
+constexpr int kMaxG = 4;        // distinct m
+constexpr int kMaxDet = 8;
+constexpr int kMaxPhi = 128;
+constexpr int kMaxNP = kMaxC * (kMaxC + 1) / 2;
+constexpr int kMaxND = 4;       // delta = 0..3
+constexpr int kMaxM = 4;
+constexpr int kChunk = 16;      // bins per K chunk (32 real K)
+constexpr int kNPart = 12;      // doubles per tile partial
+
+enum Prec { kFP64 = 0, kFP16X2 = 1, kBF16X2 = 2 };
+
+struct ModeTables {
+  int n_c, G, ND, NP;
+  int l[kMaxC], m[kMaxC];          // per channel (group order)
+  int orig[kMaxC];                 // input channel index of each
+  int gm[kMaxG];                   // m of each group
+  int gk0[kMaxG + 1];              // chunk index where each group starts
+  int pc[kMaxNP], pc2[kMaxNP], pdel[kMaxNP];   // channel pairs c <= c', m_c - m_c'
+};
+
+struct DistArgs {
+  const double* tab;
+  DistTableGeom geom;
+  double ghx[kGH], ghw[kGH];
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// online log-sum-exp accumulator (also of 2x)
+struct Lse {
+  double m, s, s2;
+  __device__ void init() { m = -INFINITY; s = 0.0; s2 = 0.0; }
+  __device__ void add(double x) {
+    if (x == -INFINITY) return;
+    if (x > m) {
+      double f = exp(m - x);
+      s = s * f + 1.0;
+      s2 = s2 * f * f + 1.0;
+      m = x;
+    } else {
+      double f = exp(x - m);
+      s += f;
+      s2 += f * f;
+    }
+  }
+  __device__ void merge(double mb, double sb, double s2b) {
+    if (mb == -INFINITY) return;
+    if (m == -INFINITY) { m = mb; s = sb; s2 = s2b; return; }
+    double mm = fmax(m, mb);
+    double fa = exp(m - mm), fb = exp(mb - mm);
+    s = s * fa + sb * fb;
+    s2 = s2 * fa * fa + s2b * fb * fb;
+    m = mm;
+  }
+};
+
+__device__ __forceinline__ uint64_t order_bits(double x) {
+  uint64_t u = __double_as_longlong(x);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_value(uint64_t u) {
+  u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+  return __longlong_as_double(u);
+}
+
+// ---------------------------------------------------------------------------
+// distance-marginalisation table
+// ---------------------------------------------------------------------------
+__global__ void k_build_dist_table(double* tab, DistTableGeom g) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)g.ncol * g.nt) return;
+  int col = (int)(idx % g.ncol), jt = (int)(idx / g.ncol);
+  double z = dr_col_z(g, col), t = g.t0 + jt * g.ht;
+  tab[idx] = dr_ln_exact(z, dr_s_of_tau(t));
+}
+
+__global__ void k_debug_distmarg(int64_t n, const double* dh, const double* hh, double r0,
+                                 DistArgs da, double* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = dr_ln_marg(dh[i], hh[i], r0, da.tab, da.geom, da.ghx, da.ghw);
+}
+
+// ---------------------------------------------------------------------------
+// bank-summary layout: FP64 amplitudes -> MFMA operand rows
+// row layout (K2 = n_c * n_bp * 2 per row): for channel c (group order) and
+// chunk j of 16 bins, 32 consecutive values: Re A (16 bins) then Im A,
+// A = conj(h) (scaled by 2^-e_i in the split precisions).
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ void k_bank_convert(const double* __restrict__ h, int64_t n_wf, int n_c_in, int n_b,
+                               int n_bp, ModeTables mt, void* __restrict__ A0,
+                               void* __restrict__ A1, double* __restrict__ row_scale,
+                               int* __restrict__ err) {
+  const int64_t row = blockIdx.x;
+  if (row >= n_wf) return;
+  const double* hr = h + (size_t)row * n_c_in * n_b * 2;
+  __shared__ double red[256];
+  double mx = 0.0;
+  bool bad = false;
+  for (int t = threadIdx.x; t < n_c_in * n_b; t += blockDim.x) {
+    double re = hr[2 * t], im = hr[2 * t + 1];
+    if (!isfinite(re) || !isfinite(im)) bad = true;
+    mx = fmax(mx, fmax(fabs(re), fabs(im)));
+  }
+  if (bad) atomicOr(err, 1);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  mx = red[0];
+  int ex = 0;
+  if (PREC != kFP64 && mx > 0.0 && isfinite(mx)) ex = ilogb(mx) - 13;   // max in [2^13, 2^14)
+  if (threadIdx.x == 0 && row_scale) row_scale[row] = ldexp(1.0, ex);
+  const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
+  for (int t = threadIdx.x; t < mt.n_c * n_bp; t += blockDim.x) {
+    int c = t / n_bp, b = t % n_bp;
+    double re = 0.0, im = 0.0;
+    if (b < n_b) {
+      const double* src = hr + ((size_t)mt.orig[c] * n_b + b) * 2;
+      re = ldexp(src[0], -ex);
+      im = -ldexp(src[1], -ex);                 // conj(h)
+    }
+    int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+    int64_t o = (int64_t)row * K2 + base;
+    if (PREC == kFP64) {
+      double* A = (double*)A0;
+      A[o] = re;
+      A[o + 16] = im;
+    } else if (PREC == kFP16X2) {
+      _Float16* Ah = (_Float16*)A0;
+      _Float16* Al = (_Float16*)A1;
+      _Float16 hr_ = (_Float16)re, hi_ = (_Float16)im;
+      Ah[o] = hr_; Ah[o + 16] = hi_;
+      Al[o] = (_Float16)(re - (double)hr_); Al[o + 16] = (_Float16)(im - (double)hi_);
+    } else {
+      __bf16* Ah = (__bf16*)A0;
+      __bf16* Al = (__bf16*)A1;
+      __bf16 hr_ = (__bf16)(float)re, hi_ = (__bf16)(float)im;
+      Ah[o] = hr_; Ah[o + 16] = hi_;
+      Al[o] = (__bf16)(float)(re - (double)(float)hr_);
+      Al[o + 16] = (__bf16)(float)(im - (double)(float)hi_);
+    }
+  }
+}
+
+// reconstructed conj(h) value (A) of row, channel c (group order), bin b
+template <int PREC>
+__device__ __forceinline__ double2 bank_value(const void* A0, const void* A1, int64_t rowoff,
+                                              int c, int b, int n_bp) {
+  int64_t o = rowoff + ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+  if (PREC == kFP64) {
+    const double* A = (const double*)A0;
+    return make_double2(A[o], A[o + 16]);
+  } else if (PREC == kFP16X2) {
+    const _Float16* Ah = (const _Float16*)A0;
+    const _Float16* Al = (const _Float16*)A1;
+    return make_double2((double)Ah[o] + (double)Al[o], (double)Ah[o + 16] + (double)Al[o + 16]);
+  } else {
+    const __bf16* Ah = (const __bf16*)A0;
+    const __bf16* Al = (const __bf16*)A1;
+    return make_double2((double)(float)Ah[o] + (double)(float)Al[o],
+                        (double)(float)Ah[o + 16] + (double)(float)Al[o + 16]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// extrinsic response (Sec. III A): antenna patterns, arrival times, mode
+// factors, R_ekc, |R_ekc|^2 and Q_ekcc'
+// ---------------------------------------------------------------------------
+__device__ double swsh_m2(int l, int m, double cos_t) {
+  // spin-weight -2 harmonic at azimuth 0: sqrt((2l+1)/4pi) d^l_{m,2}(theta)
+  const double fact[13] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880, 3628800, 39916800,
+                           479001600};
+  double ct = fmin(1.0, fmax(-1.0, cos_t));
+  double cb = sqrt(0.5 * (1.0 + ct)), sb = sqrt(0.5 * (1.0 - ct));   // cos, sin of theta/2
+  const int s = 2;
+  double sum = 0.0;
+  for (int k = 0; k <= 2 * l; ++k) {
+    int a = l + s - k, b = k, c = l - k - m, d = k - s + m;
+    if (a < 0 || c < 0 || d < 0) continue;
+    double coef = sqrt(fact[l + s] * fact[l - s] * fact[l + m] * fact[l - m]) /
+                  (fact[a] * fact[b] * fact[c] * fact[d]);
+    if ((k - s + m) & 1) coef = -coef;
+    int pc = 2 * l - 2 * k + s - m, ps = 2 * k - s + m;
+    double v = coef;
+    for (int q = 0; q < pc; ++q) v *= cb;
+    for (int q = 0; q < ps; ++q) v *= sb;
+    sum += v;
+  }
+  return sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * sum;
+}
+
+__global__ void k_ext_response(int64_t n_ext, int n_det, const double* __restrict__ det_r,
+                               const double* __restrict__ det_D, const double* __restrict__ lat,
+                               const double* __restrict__ lon, const double* __restrict__ psi,
+                               const double* __restrict__ cosi, const double* __restrict__ tgeo,
+                               ModeTables mt, double2* __restrict__ R, double* __restrict__ T,
+                               double2* __restrict__ Q, double* __restrict__ R2) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_ext) return;
+  const double C = 299792458.0;
+  double la = lat[e], lo = lon[e], ps = psi[e];
+  double sla = sin(la), cla = cos(la), slo = sin(lo), clo = cos(lo), sps = sin(ps), cps = cos(ps);
+  double n[3] = {cla * clo, cla * slo, sla};
+  double elon[3] = {-slo, clo, 0.0};
+  double elat[3] = {-sla * clo, -sla * slo, cla};
+  double X[3], Y[3];
+  for (int a = 0; a < 3; ++a) {
+    X[a] = cps * elon[a] + sps * elat[a];
+    Y[a] = -sps * elon[a] + cps * elat[a];
+  }
+  double2 K[kMaxC][2];
+  for (int c = 0; c < mt.n_c; ++c) {
+    int l = mt.l[c], m = mt.m[c];
+    double yn = swsh_m2(l, -m, cosi[e]), yp = swsh_m2(l, m, cosi[e]);
+    double sg = (l & 1) ? -1.0 : 1.0;
+    K[c][0] = make_double2(0.5 * (yn + sg * yp), 0.0);
+    K[c][1] = make_double2(0.0, 0.5 * (yn - sg * yp));
+  }
+  for (int k = 0; k < n_det; ++k) {
+    const double* Dk = det_D + 9 * k;
+    double fp = 0.0, fx = 0.0, rn = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      rn += det_r[3 * k + a] * n[a];
+      for (int b = 0; b < 3; ++b) {
+        fp += Dk[3 * a + b] * (X[a] * X[b] - Y[a] * Y[b]);
+        fx += Dk[3 * a + b] * (X[a] * Y[b] + Y[a] * X[b]);
+      }
+    }
+    T[e * n_det + k] = tgeo[e] - rn / C;
+    double2 Rk[kMaxC];
+    for (int c = 0; c < mt.n_c; ++c) {
+      Rk[c] = make_double2(fp * K[c][0].x + fx * K[c][1].x, fp * K[c][0].y + fx * K[c][1].y);
+      R[(e * n_det + k) * mt.n_c + c] = Rk[c];
+      R2[(e * n_det + k) * mt.n_c + c] = Rk[c].x * Rk[c].x + Rk[c].y * Rk[c].y;
+    }
+    for (int p = 0; p < mt.NP; ++p)
+      Q[(e * n_det + k) * mt.NP + p] = cmul(Rk[mt.pc[p]], cconj(Rk[mt.pc2[p]]));
+  }
+}
+
+// B_cb(e) = sum_k w_kb d_kb conj(R_ekc) exp(+2 pi i f_b t_ek), bins padded
+__global__ void k_build_B(int64_t n_ext, int n_det, int n_c, int n_b, int n_bp,
+                          const double* __restrict__ f, const double2* __restrict__ d,
+                          const double* __restrict__ w, const double2* __restrict__ R,
+                          const double* __restrict__ T, double2* __restrict__ Btmp) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = n_ext * n_c * n_bp;
+  if (idx >= total) return;
+  int b = (int)(idx % n_bp);
+  int c = (int)((idx / n_bp) % n_c);
+  int64_t e = idx / ((int64_t)n_bp * n_c);
+  double2 acc = make_double2(0.0, 0.0);
+  if (b < n_b) {
+    for (int k = 0; k < n_det; ++k) {
+      double x = f[b] * T[e * n_det + k];     // cycles
+      double fr = x - rint(x);
+      double sn, cs;
+      sincos(2.0 * M_PI * fr, &sn, &cs);
+      double2 r = cconj(R[(e * n_det + k) * n_c + c]);
+      double2 dk = d[k * n_b + b];
+      double wk = w[k * n_b + b];
+      double2 v = cmul(cmul(make_double2(wk * dk.x, wk * dk.y), r), make_double2(cs, sn));
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+  }
+  Btmp[idx] = acc;
+}
+
+// extrinsic operand rows: Bre = [Br | -Bi], Bim = [Bi | Br] per chunk,
+// scaled by 2^-g_e in the split precisions; rows e >= n_ext are zero
+template <int PREC>
+__global__ void k_convert_B(int64_t n_ext, int64_t n_ext_p, int n_c, int n_bp,
+                            const double2* __restrict__ Btmp, void* __restrict__ B0,
+                            void* __restrict__ B1, void* __restrict__ B2, void* __restrict__ B3,
+                            double* __restrict__ col_scale, int* __restrict__ err) {
+  const int64_t e = blockIdx.x;
+  if (e >= n_ext_p) return;
+  __shared__ double red[256];
+  const int n = n_c * n_bp;
+  double mx = 0.0;
+  bool bad = false;
+  if (e < n_ext) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      double2 v = Btmp[e * n + t];
+      if (!isfinite(v.x) || !isfinite(v.y)) bad = true;
+      mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
+    }
+  }
+  if (bad) atomicOr(err, 2);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  mx = red[0];
+  int ex = 0;
+  if (PREC != kFP64 && mx > 0.0 && isfinite(mx)) ex = ilogb(mx) - 13;
+  if (threadIdx.x == 0 && col_scale && e < n_ext) col_scale[e] = ldexp(1.0, ex);
+  const int64_t K2 = (int64_t)n * 2;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    int c = t / n_bp, b = t % n_bp;
+    double br = 0.0, bi = 0.0;
+    if (e < n_ext) {
+      double2 v = Btmp[e * n + t];
+      br = ldexp(v.x, -ex);
+      bi = ldexp(v.y, -ex);
+    }
+    int64_t o = e * K2 + ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+    double re_lo_part[2] = {br, -bi};   // Bre at o, o+16
+    double im_lo_part[2] = {bi, br};    // Bim at o, o+16
+    if (PREC == kFP64) {
+      double* Bre = (double*)B0;
+      double* Bim = (double*)B1;
+      Bre[o] = re_lo_part[0]; Bre[o + 16] = re_lo_part[1];
+      Bim[o] = im_lo_part[0]; Bim[o + 16] = im_lo_part[1];
+    } else if (PREC == kFP16X2) {
+      _Float16 *Brh = (_Float16*)B0, *Brl = (_Float16*)B1, *Bih = (_Float16*)B2, *Bil = (_Float16*)B3;
+      for (int q = 0; q < 2; ++q) {
+        _Float16 h1 = (_Float16)re_lo_part[q], h2 = (_Float16)im_lo_part[q];
+        Brh[o + 16 * q] = h1; Brl[o + 16 * q] = (_Float16)(re_lo_part[q] - (double)h1);
+        Bih[o + 16 * q] = h2; Bil[o + 16 * q] = (_Float16)(im_lo_part[q] - (double)h2);
+      }
+    } else {
+      __bf16 *Brh = (__bf16*)B0, *Brl = (__bf16*)B1, *Bih = (__bf16*)B2, *Bil = (__bf16*)B3;
+      for (int q = 0; q < 2; ++q) {
+        __bf16 h1 = (__bf16)(float)re_lo_part[q], h2 = (__bf16)(float)im_lo_part[q];
+        Brh[o + 16 * q] = h1;
+        Brl[o + 16 * q] = (__bf16)(float)(re_lo_part[q] - (double)(float)h1);
+        Bih[o + 16 * q] = h2;
+        Bil[o + 16 * q] = (__bf16)(float)(im_lo_part[q] - (double)(float)h2);
+      }
+    }
+  }
+}
+
+// (d|d)
+__global__ void k_data_norm(int n, const double2* __restrict__ d, const double* __restrict__ w,
+                            double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) s += w[t] * (d[t].x * d[t].x + d[t].y * d[t].y);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// per-waveform (h|h) sums H_ikcc' for the event's bank subset, from the
+// same operand values the contraction uses
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_idx, int64_t sub0,
+                                const void* __restrict__ A0, const void* __restrict__ A1,
+                                const double* __restrict__ row_scale, int n_bp, int n_b,
+                                int n_det, const double* __restrict__ w, ModeTables mt,
+                                double2* __restrict__ H, double* __restrict__ Hdiag) {
+  extern __shared__ double2 rowbuf[];   // [n_c][n_bp] when it fits
+  const int64_t ie = blockIdx.x;
+  if (ie >= n_sub) return;
+  const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
+  const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
+  const int64_t rowoff = i * K2;
+  const bool staged = (size_t)mt.n_c * n_bp * sizeof(double2) <= 65536;
+  if (staged) {
+    for (int t = threadIdx.x; t < mt.n_c * n_bp; t += blockDim.x)
+      rowbuf[t] = bank_value<PREC>(A0, A1, rowoff, t / n_bp, t % n_bp, n_bp);
+    __syncthreads();
+  }
+  double sc = row_scale ? row_scale[i] : 1.0;
+  sc = sc * sc;
+  for (int t = threadIdx.x; t < n_det * mt.NP; t += blockDim.x) {
+    int k = t / mt.NP, p = t % mt.NP;
+    int c = mt.pc[p], c2 = mt.pc2[p];
+    double2 acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < n_b; ++b) {
+      double2 a = staged ? rowbuf[c * n_bp + b] : bank_value<PREC>(A0, A1, rowoff, c, b, n_bp);
+      double2 a2 = staged ? rowbuf[c2 * n_bp + b] : bank_value<PREC>(A0, A1, rowoff, c2, b, n_bp);
+      // h_c conj(h_c') = conj(A_c) A_c'
+      double2 v = cmul(cconj(a), a2);
+      double ww = w[k * n_b + b];
+      acc.x += ww * v.x;
+      acc.y += ww * v.y;
+    }
+    acc.x *= sc;
+    acc.y *= sc;
+    H[(ie * n_det + k) * mt.NP + p] = acc;
+    if (c == c2) Hdiag[(ie * n_det + k) * mt.n_c + c] = acc.x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused kernel: complex MFMA GEMM + per-pair marginalisation epilogue
+// ---------------------------------------------------------------------------
+struct FusedArgs {
+  // bank operand (row-major [n_wf][K2])
+  const void* A0;
+  const void* A1;
+  const double* row_scale;
+  const double* ln_w_bank;
+  // subset
+  const int64_t* sub_idx;
+  int64_t sub0, n_sub;
+  // extrinsic operand ([n_ext_p][K2])
+  const void* B0;
+  const void* B1;
+  const void* B2;
+  const void* B3;
+  const double* col_scale;
+  const double* ln_w_ext;
+  int64_t n_ext, n_ext_p;
+  int64_t K2;
+  int n_chunks;
+  // hh tables
+  const double2* H;      // [n_sub][n_det][NP]
+  const double* Hdiag;   // [n_sub][n_det][n_c]
+  const double2* Q;      // [n_ext][n_det][NP]
+  const double* R2;      // [n_ext][n_det][n_c]
+  int n_det;
+  ModeTables mt;
+  // phases
+  int n_phi;
+  const double* phase_cs;   // [kMaxM][n_phi][2] cos, sin of m phi_o, m = 1..kMaxM
+  double ln_nphi;
+  // distance rule
+  DistArgs dist;
+  double r0;                 // d0 / D_max
+  // eval outputs
+  double* lnl_out;
+  double* ml_out;
+  double* trip_out;
+  // evidence
+  double cut_delta;          // <= 0: no cut
+  double topk_window;
+  uint64_t* state;           // [0] max lnL^ML bits, [1] ordered max ln p, [2] candidate count
+  double* partials;          // [n_tiles][kNPart]
+  double* cand;              // [cap][4]: ln p, i, e, o
+  int64_t cand_cap;
+  int64_t n_tiles_m, n_tiles_n, n_tiles;
+  int64_t pilot_stride;      // pilot pass: every pilot_stride-th row of tiles
+};
+
+template <int PREC>
+struct Pol;
+template <>
+struct Pol<kFP64> {
+  typedef double T;
+  typedef f64x4 Acc;
+  static constexpr int NA = 1, NB = 2, PITCH = 33, BM = 2, BN = 1;
+};
+template <>
+struct Pol<kFP16X2> {
+  typedef uint16_t T;
+  typedef f32x4 Acc;
+  static constexpr int NA = 2, NB = 4, PITCH = 40, BM = 2, BN = 2;
+};
+template <>
+struct Pol<kBF16X2> : Pol<kFP16X2> {};
+
+template <int PREC>
+struct Tile {
+  typedef Pol<PREC> P;
+  static constexpr int TM = 2 * 16 * P::BM;   // rows per workgroup tile
+  static constexpr int TN = 2 * 16 * P::BN;   // columns per workgroup tile
+  static constexpr int STAGE_ELEMS = (P::NA * TM + P::NB * TN) * P::PITCH;
+  static constexpr int STAGE_BYTES = STAGE_ELEMS * (int)sizeof(typename P::T);
+  static constexpr int ACC_T_BYTES = (PREC == kFP64) ? 8 : 4;
+  static constexpr int EPI_STRIDE = 2 * kMaxG + 1;
+  static constexpr int EPI_BYTES = 4 * 256 * EPI_STRIDE * ACC_T_BYTES;
+  static constexpr int PIECE_ELEMS = 16 / (int)sizeof(typename P::T);   // 16-byte pieces
+  static constexpr int PIECES_PER_ROW = 32 / PIECE_ELEMS;
+  static constexpr int PIECES = (P::NA * TM + P::NB * TN) * PIECES_PER_ROW;
+  static constexpr int PIECES_PER_THREAD = PIECES / 256;
+  static constexpr int MAIN_BYTES = (2 * STAGE_BYTES > EPI_BYTES) ? 2 * STAGE_BYTES : EPI_BYTES;
+};
+
+template <int PREC>
+__device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a, const uint4& b) {
+  if constexpr (PREC == kFP16X2) {
+    half8 av, bv;
+    __builtin_memcpy(&av, &a, 16);
+    __builtin_memcpy(&bv, &b, 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc, 0, 0, 0);
+  } else if constexpr (PREC == kBF16X2) {
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, &a, 16);
+    __builtin_memcpy(&bv, &b, 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+}
+
+// per-pair epilogue state for the evidence reduction
+struct EvAcc {
+  Lse p;          // over ln p_ie
+  Lse drop;       // over bounds of cut contributions (ln)
+  double ml_max;
+  double max_bound;   // max over bounded pairs of ln w_i + ln w_e + bound
+  double n_marg, n_bounded, n_pairs;
+  __device__ void init() {
+    p.init(); drop.init();
+    ml_max = 0.0; max_bound = -INFINITY;
+    n_marg = 0.0; n_bounded = 0.0; n_pairs = 0.0;
+  }
+};
+
+enum Mode { kEval = 0, kEvidence = 1, kPilot = 2 };
+
+// evaluate one pair; returns ln p (or -inf when everything was cut) and o_best
+template <int MODE>
+__device__ double pair_epilogue(const FusedArgs& a, const double* lds_cs, int64_t ie, int64_t i,
+                                int64_t e, const double2* X, double lnw, double thr_ml,
+                                EvAcc& ev, int& o_best) {
+  constexpr bool EVAL = MODE == kEval;
+  const ModeTables& mt = a.mt;
+  const int G = mt.G;
+  o_best = 0;
+  // per-pair bound (cut enabled only): lnL^ML_o <= U^2 / (2 L^2) for all o,
+  // U = sum_g |X_g| >= dh_o, L = lower bound of sqrt(hh_o) from the channel
+  // norms n_c^2 = sum_k |R_ekc|^2 H_ikcc (triangle inequality)
+  if (MODE == kEvidence && thr_ml > -INFINITY) {
+    double U = 0.0;
+    for (int g = 0; g < G; ++g) U += sqrt(X[g].x * X[g].x + X[g].y * X[g].y);
+    double nsum = 0.0, nmax = 0.0;
+    for (int c = 0; c < mt.n_c; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < a.n_det; ++k)
+        s += a.R2[(e * a.n_det + k) * mt.n_c + c] * a.Hdiag[(ie * a.n_det + k) * mt.n_c + c];
+      double nc = sqrt(fmax(s, 0.0));
+      nsum += nc;
+      nmax = fmax(nmax, nc);
+    }
+    double L = 2.0 * nmax - nsum;
+    if (L > 0.0) {
+      double bound = U * U / (2.0 * L * L) * (1.0 + 1e-3) + 1e-3;
+      if (bound < thr_ml) {
+        ev.drop.add(lnw + bound);
+        ev.max_bound = fmax(ev.max_bound, lnw + bound);
+        ev.n_bounded += 1.0;
+        return -INFINITY;
+      }
+    }
+  }
+  // (h|h) coefficients S_delta
+  double S0 = 0.0, Sr[kMaxND], Si[kMaxND];
+  for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0.0; Si[d] = 0.0; }
+  for (int k = 0; k < a.n_det; ++k) {
+    const double2* Hk = a.H + (ie * a.n_det + k) * mt.NP;
+    const double2* Qk = a.Q + (e * a.n_det + k) * mt.NP;
+    for (int p = 0; p < mt.NP; ++p) {
+      double2 h = Hk[p], q = Qk[p];
+      int del = mt.pdel[p];
+      if (mt.pc[p] == mt.pc2[p]) {
+        S0 += h.x * q.x;
+      } else {
+        double2 v = cmul(h, q);
+        if (del == 0) S0 += 2.0 * v.x;
+        else if (del > 0) { Sr[del] += v.x; Si[del] += v.y; }
+        else { Sr[-del] += v.x; Si[-del] -= v.y; }
+      }
+    }
+  }
+  // phase loop
+  Lse lse;
+  lse.init();
+  double best = -INFINITY, mlmax = 0.0;
+  for (int o = 0; o < a.n_phi; ++o) {
+    double dh = 0.0;
+    for (int g = 0; g < G; ++g) {
+      const double* cs = lds_cs + ((mt.gm[g] - 1) * a.n_phi + o) * 2;
+      dh += X[g].x * cs[0] - X[g].y * cs[1];
+    }
+    double hh = S0;
+    for (int d = 1; d < mt.ND; ++d) {
+      const double* cs = lds_cs + ((d - 1) * a.n_phi + o) * 2;
+      hh += 2.0 * (Sr[d] * cs[0] + Si[d] * cs[1]);
+    }
+    hh = fmax(hh, 0.0);
+    double ml = (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0;
+    mlmax = fmax(mlmax, ml);
+    if (EVAL && a.trip_out) {
+      size_t t = (((size_t)ie * a.n_ext + e) * a.n_phi + o) * 2;
+      a.trip_out[t] = dh;
+      a.trip_out[t + 1] = hh;
+    }
+    if (MODE == kPilot) continue;
+    if (!EVAL && ml < thr_ml) {
+      ev.drop.add(lnw + ml - a.ln_nphi);
+      continue;
+    }
+    double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, a.dist.geom, a.dist.ghx, a.dist.ghw);
+    if (v > best) { best = v; o_best = o; }
+    lse.add(v);
+    if (!EVAL) ev.n_marg += 1.0;
+  }
+  double lnl = (lse.m == -INFINITY) ? -INFINITY : lse.m + log(lse.s) - a.ln_nphi;
+  if (EVAL) {
+    size_t t = (size_t)ie * a.n_ext + e;
+    a.lnl_out[t] = lnl;
+    if (a.ml_out) a.ml_out[t] = mlmax;
+    return lnl;
+  }
+  ev.ml_max = fmax(ev.ml_max, mlmax);
+  if (MODE == kPilot || lnl == -INFINITY) return -INFINITY;
+  double lnp = lnw + lnl;
+  ev.p.add(lnp);
+  return lnp;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+template <int PREC, int G, int MODE>
+__global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
+  constexpr bool EVAL = MODE == kEval;
+  typedef Pol<PREC> P;
+  typedef Tile<PREC> TL;
+  typedef typename P::T T;
+  typedef typename P::Acc Acc;
+  constexpr int TM = TL::TM, TN = TL::TN, PITCH = P::PITCH;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* stage = (T*)smem;
+  double* lds_cs = (double*)(smem + TL::MAIN_BYTES);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // workgroup -> tile: spread consecutive ids over the XCDs so that each XCD
+  // walks a contiguous band of tiles, then raster in groups of 8 tile rows
+  int64_t wg = blockIdx.x;
+  {
+    int64_t nwg = gridDim.x;              // multiple of 8
+    wg = (wg % 8) * (nwg / 8) + wg / 8;
+  }
+  int64_t tm, tn;
+  if (MODE == kPilot) {
+    // every pilot_stride-th row of tiles, all columns
+    int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
+    if (wg >= npr * a.n_tiles_n) return;
+    tm = (wg / a.n_tiles_n) * a.pilot_stride;
+    tn = wg % a.n_tiles_n;
+  } else {
+    if (wg >= a.n_tiles) return;
+    const int64_t GM = 8;
+    int64_t band = wg / (GM * a.n_tiles_n);
+    int64_t rows_in_band = min(GM, a.n_tiles_m - band * GM);
+    int64_t in = wg - band * GM * a.n_tiles_n;
+    tm = band * GM + in % rows_in_band;
+    tn = in / rows_in_band;
+  }
+  const int64_t row0 = tm * TM, col0 = tn * TN;
+
+  // phase table to LDS
+  for (int t = tid; t < kMaxM * a.n_phi * 2; t += 256) lds_cs[t] = a.phase_cs[t];
+
+  // ---- K loop ----
+  Acc acc[G][P::BM][P::BN][2];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < P::BN; ++bn)
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) acc[g][bm][bn][ri] = Acc{0, 0, 0, 0};
+
+  // global source rows for this thread's pieces
+  const void* Asrc[2] = {a.A0, a.A1};
+  const void* Bsrc[4] = {a.B0, a.B1, a.B2, a.B3};
+  uint4 stg[TL::PIECES_PER_THREAD];
+
+  auto load_chunk = [&](int ch) {
+#pragma unroll
+    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
+      int p = tid + 256 * q;
+      int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (rowsel < P::NA * TM) {
+        int arr = rowsel / TM, r = rowsel % TM;
+        int64_t ie = row0 + r;
+        if (ie < a.n_sub) {
+          int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+          const T* src = (const T*)Asrc[arr] + i * a.K2 + (int64_t)ch * 32 + piece * TL::PIECE_ELEMS;
+          v = *(const uint4*)src;
+        }
+      } else {
+        int rs = rowsel - P::NA * TM;
+        int arr = rs / TN, c = rs % TN;
+        int64_t e = col0 + c;                  // < n_ext_p by construction
+        const T* src = (const T*)Bsrc[arr] + e * a.K2 + (int64_t)ch * 32 + piece * TL::PIECE_ELEMS;
+        v = *(const uint4*)src;
+      }
+      stg[q] = v;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+    T* base = stage + buf * TL::STAGE_ELEMS;
+#pragma unroll
+    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
+      int p = tid + 256 * q;
+      int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
+      T* dst = base + rowsel * PITCH + piece * TL::PIECE_ELEMS;
+      if constexpr (PREC == kFP64) {
+        // 8-byte aligned rows (odd pitch): two 8-byte stores
+        uint2* d2 = (uint2*)dst;
+        d2[0] = make_uint2(stg[q].x, stg[q].y);
+        d2[1] = make_uint2(stg[q].z, stg[q].w);
+      } else {
+        *(uint4*)dst = stg[q];
+      }
+    }
+  };
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  int ch = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int gend = a.mt.gk0[g + 1];
+    for (; ch < gend; ++ch) {
+      const bool more = ch + 1 < a.n_chunks;
+      if (more) load_chunk(ch + 1);
+      const T* base = stage + (ch & 1) * TL::STAGE_ELEMS;
+      const T* As = base;
+      const T* Bs = base + P::NA * TM * PITCH;
+      if constexpr (PREC == kFP64) {
+        const double* Ad = (const double*)As;
+        const double* Bd = (const double*)Bs;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          double av[P::BM], brv[P::BN], biv[P::BN];
+#pragma unroll
+          for (int bm = 0; bm < P::BM; ++bm)
+            av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s + (lane >> 4)];
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) {
+            int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
+            brv[bn] = Bd[cc * PITCH + 4 * s + (lane >> 4)];
+            biv[bn] = Bd[(TN + cc) * PITCH + 4 * s + (lane >> 4)];
+          }
+#pragma unroll
+          for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < P::BN; ++bn) {
+              acc[g][bm][bn][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], brv[bn], acc[g][bm][bn][0], 0, 0, 0);
+              acc[g][bm][bn][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], biv[bn], acc[g][bm][bn][1], 0, 0, 0);
+            }
+        }
+      } else {
+        uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
+        const int koff = 8 * (lane >> 4);
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm) {
+          int rr = wm * 16 * P::BM + bm * 16 + (lane & 15);
+          ah[bm] = *(const uint4*)(As + rr * PITCH + koff);
+          al[bm] = *(const uint4*)(As + (TM + rr) * PITCH + koff);
+        }
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
+          brh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
+          brl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
+          bih[bn] = *(const uint4*)(Bs + (2 * TN + cc) * PITCH + koff);
+          bil[bn] = *(const uint4*)(Bs + (3 * TN + cc) * PITCH + koff);
+        }
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) {
+            mma<PREC>(acc[g][bm][bn][0], al[bm], brh[bn]);
+            mma<PREC>(acc[g][bm][bn][0], ah[bm], brl[bn]);
+            mma<PREC>(acc[g][bm][bn][0], ah[bm], brh[bn]);
+            mma<PREC>(acc[g][bm][bn][1], al[bm], bih[bn]);
+            mma<PREC>(acc[g][bm][bn][1], ah[bm], bil[bn]);
+            mma<PREC>(acc[g][bm][bn][1], ah[bm], bih[bn]);
+          }
+      }
+      if (more) store_chunk((ch + 1) & 1);
+      __syncthreads();
+    }
+  }
+
+  // ---- epilogue ----
+  typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
+  AT* epi = (AT*)smem + wave * 256 * TL::EPI_STRIDE;
+
+  double thr_ml = -INFINITY, thr_topk_glob = -INFINITY;
+  if (!EVAL) {
+    if (a.cut_delta > 0.0) thr_ml = __longlong_as_double(a.state[0]) - a.cut_delta;
+    thr_topk_glob = order_value(a.state[1]) - a.topk_window;
+  }
+  EvAcc ev;
+  ev.init();
+  double tile_max_lnp = -INFINITY;
+
+#pragma unroll 1
+  for (int blk = 0; blk < P::BM * P::BN; ++blk) {
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < P::BM * P::BN; ++bb) {
+      if (bb != blk) continue;
+      const int bm = bb / P::BN, bn = bb % P::BN;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int rr = (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
+        int q = rr * 16 + (lane & 15);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          epi[q * TL::EPI_STRIDE + 2 * g] = (AT)acc[g][bm][bn][0][r];
+          epi[q * TL::EPI_STRIDE + 2 * g + 1] = (AT)acc[g][bm][bn][1][r];
+        }
+      }
+    }
+    __syncthreads();
+    const int bm = blk / P::BN, bn = blk % P::BN;
+    double lnp_keep[4];
+    int ob_keep[4];
+    int64_t i_keep[4], e_keep[4];
+    double blk_max = -INFINITY;
+    for (int t = 0; t < 4; ++t) {
+      int q = lane + 64 * t;
+      int64_t ie = row0 + wm * 16 * P::BM + bm * 16 + q / 16;
+      int64_t e = col0 + wn * 16 * P::BN + bn * 16 + (q & 15);
+      lnp_keep[t] = -INFINITY;
+      ob_keep[t] = 0;
+      i_keep[t] = -1;
+      e_keep[t] = e;
+      if (ie >= a.n_sub || e >= a.n_ext) continue;
+      int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+      i_keep[t] = i;
+      double sc = 1.0;
+      if (PREC != kFP64) sc = a.row_scale[i] * a.col_scale[e];
+      double2 X[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        X[g] = make_double2(sc * (double)epi[q * TL::EPI_STRIDE + 2 * g],
+                            sc * (double)epi[q * TL::EPI_STRIDE + 2 * g + 1]);
+      double lnw = (a.ln_w_bank ? a.ln_w_bank[i] : 0.0) + (a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
+      int ob = 0;
+      ev.n_pairs += 1.0;
+      double lnp = pair_epilogue<MODE>(a, lds_cs, ie, i, e, X, lnw, thr_ml, ev, ob);
+      if (MODE == kEvidence) {
+        lnp_keep[t] = lnp;
+        ob_keep[t] = ob;
+        blk_max = fmax(blk_max, lnp);
+      }
+    }
+    if (MODE == kEvidence) {
+      blk_max = wave_max(blk_max);
+      tile_max_lnp = fmax(tile_max_lnp, blk_max);
+      double thr_k = fmax(thr_topk_glob, blk_max - a.topk_window);
+      for (int t = 0; t < 4; ++t) {
+        if (lnp_keep[t] > -INFINITY && lnp_keep[t] >= thr_k) {
+          unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
+          if ((int64_t)slot < a.cand_cap) {
+            double* cd = a.cand + 4 * slot;
+            cd[0] = lnp_keep[t];
+            cd[1] = (double)i_keep[t];
+            cd[2] = (double)e_keep[t];
+            cd[3] = (double)ob_keep[t];
+          }
+        }
+      }
+    }
+  }
+  if (EVAL) return;
+  if (MODE == kPilot) {
+    double mlm = wave_max(ev.ml_max);
+    if (lane == 0)
+      atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
+    return;
+  }
+
+  // ---- tile reduction ----
+  __syncthreads();
+  double* red = (double*)smem;   // [4 waves][kNPart]
+  {
+    Lse p = ev.p, d = ev.drop;
+    for (int off = 32; off > 0; off >>= 1) {
+      double pm = __shfl_xor(p.m, off), ps = __shfl_xor(p.s, off), ps2 = __shfl_xor(p.s2, off);
+      p.merge(pm, ps, ps2);
+      double dm = __shfl_xor(d.m, off), ds = __shfl_xor(d.s, off), ds2 = __shfl_xor(d.s2, off);
+      d.merge(dm, ds, ds2);
+    }
+    double mlm = wave_max(ev.ml_max), mb = wave_max(ev.max_bound);
+    double nm = wave_sum(ev.n_marg), nb = wave_sum(ev.n_bounded), np_ = wave_sum(ev.n_pairs);
+    if (lane == 0) {
+      double* r = red + wave * kNPart;
+      r[0] = p.m; r[1] = p.s; r[2] = p.s2; r[3] = d.m; r[4] = d.s; r[5] = mlm;
+      r[6] = nm; r[7] = nb; r[8] = mb; r[9] = tile_max_lnp; r[10] = np_; r[11] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Lse p, d;
+    p.init(); d.init();
+    double mlm = 0.0, mb = -INFINITY, mxp = -INFINITY, nm = 0, nb = 0, np_ = 0;
+    for (int w = 0; w < 4; ++w) {
+      const double* r = red + w * kNPart;
+      p.merge(r[0], r[1], r[2]);
+      d.merge(r[3], r[4], 0.0);
+      mlm = fmax(mlm, r[5]);
+      nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); mxp = fmax(mxp, r[9]); np_ += r[10];
+    }
+    double* out = a.partials + wg * kNPart;
+    out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
+    out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
+    atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
+    if (mxp > -INFINITY) atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(mxp));
+  }
+}
+
+// fixed-order reduction of tile partials: out[kNPart] combined
+__global__ void k_finalize(const double* __restrict__ partials, int64_t n_tiles,
+                           double* __restrict__ out) {
+  __shared__ double sh[256 * kNPart];
+  Lse p, d;
+  p.init(); d.init();
+  double mlm = 0.0, mb = -INFINITY, mxp = -INFINITY, nm = 0, nb = 0, np_ = 0;
+  for (int64_t t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const double* r = partials + t * kNPart;
+    p.merge(r[0], r[1], r[2]);
+    d.merge(r[3], r[4], 0.0);
+    mlm = fmax(mlm, r[5]);
+    nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); mxp = fmax(mxp, r[9]); np_ += r[10];
+  }
+  double* m = sh + threadIdx.x * kNPart;
+  m[0] = p.m; m[1] = p.s; m[2] = p.s2; m[3] = d.m; m[4] = d.s; m[5] = mlm;
+  m[6] = nm; m[7] = nb; m[8] = mb; m[9] = mxp; m[10] = np_; m[11] = 0;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      double* x = sh + threadIdx.x * kNPart;
+      double* y = sh + (threadIdx.x + s) * kNPart;
+      Lse pp, dd;
+      pp.m = x[0]; pp.s = x[1]; pp.s2 = x[2];
+      dd.m = x[3]; dd.s = x[4]; dd.s2 = 0.0;
+      pp.merge(y[0], y[1], y[2]);
+      dd.merge(y[3], y[4], 0.0);
+      x[0] = pp.m; x[1] = pp.s; x[2] = pp.s2; x[3] = dd.m; x[4] = dd.s;
+      x[5] = fmax(x[5], y[5]); x[6] += y[6]; x[7] += y[7]; x[8] = fmax(x[8], y[8]);
+      x[9] = fmax(x[9], y[9]); x[10] += y[10];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < kNPart; ++q) out[q] = sh[q];
+}
+
+// one bitonic merge step over candidate records [n][4] (ln p, i, e, o):
+// order = ln p descending, then i, then e ascending
+__device__ __forceinline__ bool cand_before(const double* x, const double* y) {
+  if (x[0] != y[0]) return x[0] > y[0];
+  if (x[1] != y[1]) return x[1] < y[1];
+  return x[2] < y[2];
+}
+__global__ void k_bitonic_step(double* __restrict__ c, int64_t n, int64_t j, int64_t k) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t l = i ^ j;
+  if (l <= i) return;
+  double* x = c + 4 * i;
+  double* y = c + 4 * l;
+  bool up = (i & k) == 0;
+  bool swap = up ? cand_before(y, x) : cand_before(x, y);
+  if (swap) {
+    for (int q = 0; q < 4; ++q) {
+      double t = x[q];
+      x[q] = y[q];
+      y[q] = t;
+    }
+  }
+}
+__global__ void k_fill_cand(double* __restrict__ c, int64_t from, int64_t to) {
+  int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= to) return;
+  c[4 * i] = -INFINITY;
+  c[4 * i + 1] = 1e300;
+  c[4 * i + 2] = 1e300;
+  c[4 * i + 3] = 0;
+}
+
+}  // namespace dotpe

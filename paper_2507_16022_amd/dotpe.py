@@ -1,0 +1,336 @@
+"""Python binding of the C ABI in include/dotpe.h (argument marshalling only).
+
+Every computation runs in libdotpe.so's HIP kernels.  numpy arrays are
+passed as host pointers; torch tensors on a GPU are passed as device
+pointers (torch is used only for device memory and streams).  If the
+library has not been built this module raises on first use: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdotpe.so")
+
+OK = 0
+E_INVALID_ARG = -1
+E_OOM = -2
+E_ADMISSION = -3
+E_NUMERIC = -4
+E_DEVICE = -5
+E_TOO_LARGE = -6
+E_UNIMPLEMENTED = -7
+
+PREC = {"fp64": 0, "fp16x2": 1, "bf16x2": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_c_ip = ctypes.POINTER(ctypes.c_int32)
+_c_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+class BankDesc(ctypes.Structure):
+    _fields_ = [("n_wf", ctypes.c_int64), ("n_modes", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("mode_l", ctypes.c_void_p), ("mode_m", ctypes.c_void_p),
+                ("f_bins", ctypes.c_void_p), ("h", ctypes.c_void_p), ("ln_w", ctypes.c_void_p),
+                ("precision", ctypes.c_int32), ("mem", ctypes.c_int32)]
+
+
+class EventDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+                ("d", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("det_r", ctypes.c_void_p), ("det_D", ctypes.c_void_p),
+                ("n_ext", ctypes.c_int64),
+                ("lat", ctypes.c_void_p), ("lon", ctypes.c_void_p), ("psi", ctypes.c_void_p),
+                ("cos_iota", ctypes.c_void_p), ("t_geo", ctypes.c_void_p),
+                ("ln_w_ext", ctypes.c_void_p),
+                ("d_max", ctypes.c_double), ("d0", ctypes.c_double), ("n_norm", ctypes.c_double),
+                ("sub_start", ctypes.c_int64), ("sub_count", ctypes.c_int64),
+                ("sub_idx", ctypes.c_void_p),
+                ("cut_delta", ctypes.c_double), ("top_k", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("topk_window", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class EvidenceResult(ctypes.Structure):
+    _fields_ = [("ln_z", ctypes.c_double), ("ln_z_upper", ctypes.c_double),
+                ("max_lnl_ml", ctypes.c_double), ("ln_sum_p", ctypes.c_double),
+                ("ln_sum_p2", ctypes.c_double), ("dd", ctypes.c_double),
+                ("max_ln_p", ctypes.c_double),
+                ("n_pairs", ctypes.c_int64), ("n_pairs_bounded", ctypes.c_int64),
+                ("n_triples_marg", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("topk_count", ctypes.c_int32), ("topk_exact", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("t_pilot_ms", ctypes.c_double),
+                ("t_fused_ms", ctypes.c_double)]
+
+
+class Sample(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int64), ("e", ctypes.c_int64), ("ln_p", ctypes.c_double),
+                ("o_best", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+SYMBOLS = {
+    "dotpe_version": (ctypes.c_char_p, []),
+    "dotpe_last_error": (ctypes.c_char_p, []),
+    "dotpe_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]),
+    "dotpe_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "dotpe_device_bytes": (ctypes.c_uint64, [ctypes.c_void_p]),
+    "dotpe_load_bank": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(BankDesc),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "dotpe_free_bank": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dotpe_set_event": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(EventDesc),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "dotpe_free_event": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dotpe_eval_lnl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "dotpe_evidence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(EvidenceResult), ctypes.c_void_p]),
+    "dotpe_debug_distmarg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "dotpe_debug_response": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libdotpe.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with __graft_entry__.build() "
+                           "(python paper_2507_16022_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SYMBOLS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class DotpeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dotpe error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise DotpeError(rc, load_library().dotpe_last_error().decode())
+
+
+def _host(a, dtype=np.float64):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class Context:
+    def __init__(self, device=0, budget_bytes=0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.dotpe_create(int(device), int(budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def device_bytes(self):
+        return int(load_library().dotpe_device_bytes(self._h))
+
+    def close(self):
+        if self._h:
+            load_library().dotpe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_bank(self, h, modes, f, ln_w=None, precision="fp16x2"):
+        """h: complex numpy [N, C, B] (host) or a float64 torch tensor
+        [N, C, B, 2] on the GPU (device pointer, no host copy)."""
+        return Bank(self, h, modes, f, ln_w, precision)
+
+    def set_event(self, bank, **kw):
+        return Event(self, bank, **kw)
+
+    def distmarg(self, dh, hh, r0):
+        dh, pdh = _host(dh)
+        hh, phh = _host(hh)
+        out = np.empty_like(dh)
+        _check(load_library().dotpe_debug_distmarg(self._h, dh.size, pdh, phh, float(r0),
+                                                   out.ctypes.data))
+        return out
+
+
+class Bank:
+    def __init__(self, ctx, h, modes, f, ln_w=None, precision="fp16x2"):
+        lib = load_library()
+        self.ctx = ctx
+        self._keep = []
+        ml, pml = _host([l for l, _ in modes], np.int32)
+        mm, pmm = _host([m for _, m in modes], np.int32)
+        fb, pf = _host(f)
+        self._keep += [ml, mm, fb]
+        if _is_torch(h):
+            assert h.is_cuda and str(h.dtype) == "torch.float64" and h.is_contiguous()
+            n_wf, n_c, n_b = h.shape[0], h.shape[1], h.shape[2]
+            ph, mem = h.data_ptr(), MEM_DEVICE
+            self._keep.append(h)
+            if ln_w is not None:
+                assert _is_torch(ln_w) and ln_w.is_cuda
+                pw = ln_w.data_ptr()
+                self._keep.append(ln_w)
+            else:
+                pw = None
+        else:
+            hh = np.ascontiguousarray(h, dtype=np.complex128)
+            n_wf, n_c, n_b = hh.shape
+            ph, mem = hh.ctypes.data, MEM_HOST
+            self._keep.append(hh)
+            if ln_w is not None:
+                lw, pw = _host(ln_w)
+                self._keep.append(lw)
+            else:
+                pw = None
+        desc = BankDesc(n_wf, n_c, n_b, pml, pmm, pf, ph, pw, PREC[precision], mem)
+        out = ctypes.c_void_p()
+        _check(lib.dotpe_load_bank(ctx.handle, ctypes.byref(desc), ctypes.byref(out)))
+        self._h = out
+        self._keep = []
+        self.n_wf, self.n_modes, self.n_bins = n_wf, n_c, n_b
+        self.precision = precision
+        self.modes = tuple(modes)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().dotpe_free_bank(self.ctx.handle, self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Event:
+    def __init__(self, ctx, bank, d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0,
+                 d0=1.0, n_norm=0.0, sub_start=0, sub_count=0, sub_idx=None, cut_delta=0.0,
+                 top_k=0, topk_window=40.0, stream=None):
+        lib = load_library()
+        self.ctx, self.bank = ctx, bank
+        keep = []
+
+        def hp(a, dt=np.float64):
+            arr, p = _host(a, dt)
+            keep.append(arr)
+            return arr, p
+
+        dc, pd = hp(np.asarray(d, dtype=np.complex128), np.complex128)
+        _, pw = hp(w)
+        _, pr = hp(det_r)
+        _, pD = hp(det_D)
+        n_ext = len(ext["lat"])
+        _, plat = hp(ext["lat"])
+        _, plon = hp(ext["lon"])
+        _, ppsi = hp(ext["psi"])
+        _, pci = hp(ext["cos_iota"])
+        _, ptg = hp(ext["t_geo"])
+        plw = hp(ln_w_ext)[1] if ln_w_ext is not None else None
+        psub = None
+        if sub_idx is not None:
+            si, psub = hp(sub_idx, np.int64)
+            sub_count = len(si)
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        desc = EventDesc(dc.shape[0], int(n_phi), pd, pw, pr, pD, n_ext, plat, plon, ppsi, pci, ptg,
+                         plw, float(d_max), float(d0), float(n_norm), int(sub_start),
+                         int(sub_count), psub, float(cut_delta), int(top_k), 0,
+                         float(topk_window), stream)
+        out = ctypes.c_void_p()
+        _check(lib.dotpe_set_event(ctx.handle, bank.handle, ctypes.byref(desc), ctypes.byref(out)))
+        self._h = out
+        self.n_ext = n_ext
+        self.n_sub = sub_count if sub_count else bank.n_wf
+        self.n_phi = int(n_phi)
+        self.n_det = dc.shape[0]
+        self.top_k = int(top_k)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().dotpe_free_event(self.ctx.handle, self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval_lnl(self, ml=False, triples=False):
+        """ln Lbar_ie [n_sub, n_ext] (and max_o lnL^ML, (dh, hh) per triple)."""
+        lnl = np.empty((self.n_sub, self.n_ext))
+        mlo = np.empty((self.n_sub, self.n_ext)) if ml else None
+        tr = np.empty((self.n_sub, self.n_ext, self.n_phi, 2)) if triples else None
+        _check(load_library().dotpe_eval_lnl(
+            self.ctx.handle, self._h, lnl.ctypes.data, mlo.ctypes.data if ml else None,
+            tr.ctypes.data if triples else None, MEM_HOST))
+        out = {"lnl": lnl}
+        if ml:
+            out["ml_max"] = mlo
+        if triples:
+            out["dh"] = tr[..., 0]
+            out["hh"] = tr[..., 1]
+        return out
+
+    def eval_lnl_device(self, lnl, ml=None, triples=None):
+        """Device-output variant: torch float64 tensors on the GPU."""
+        _check(load_library().dotpe_eval_lnl(
+            self.ctx.handle, self._h, lnl.data_ptr(), ml.data_ptr() if ml is not None else None,
+            triples.data_ptr() if triples is not None else None, MEM_DEVICE))
+
+    def evidence(self):
+        r = EvidenceResult()
+        k = self.top_k
+        arr = (Sample * max(k, 1))()
+        _check(load_library().dotpe_evidence(self.ctx.handle, self._h, ctypes.byref(r),
+                                             ctypes.cast(arr, ctypes.c_void_p) if k else None))
+        out = {name: getattr(r, name) for name, _ in EvidenceResult._fields_}
+        n = r.topk_count
+        out["topk_i"] = np.array([arr[q].i for q in range(n)], dtype=np.int64)
+        out["topk_e"] = np.array([arr[q].e for q in range(n)], dtype=np.int64)
+        out["topk_lnp"] = np.array([arr[q].ln_p for q in range(n)])
+        out["topk_o"] = np.array([arr[q].o_best for q in range(n)], dtype=np.int32)
+        return out
+
+    def response(self):
+        """(R [n_ext, n_det, n_modes] complex, t [n_ext, n_det]) from the device."""
+        R = np.empty((self.n_ext, self.n_det, self.bank.n_modes, 2))
+        t = np.empty((self.n_ext, self.n_det))
+        _check(load_library().dotpe_debug_response(self.ctx.handle, self._h, R.ctypes.data,
+                                                    t.ctypes.data))
+        return R[..., 0] + 1j * R[..., 1], t

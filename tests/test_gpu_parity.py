@@ -1,0 +1,255 @@
+"""GPU path vs the FP64 CPU oracle, through the C ABI.
+
+Tolerances: the FP64 path differs from the oracle only by rounding order
+and by the distance rule (table + Gauss-Hermite tail vs 2000-node
+Gauss-Legendre), both far below 1e-6 in ln Lbar; the split-precision paths
+must meet |d ln Lbar| <= 1e-3 per pair and |d ln Z| <= 1e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import workload as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-6
+TOL_MIXED = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2507_16022_amd import dotpe
+    c = dotpe.Context(0)
+    yield c
+    c.close()
+
+
+def make_event(ctx, wl, precision="fp64", **kw):
+    bank = ctx.load_bank(wl.h, wl.modes, wl.f, wl.ln_w_int, precision=precision)
+    ev = ctx.set_event(bank, d=wl.d, w=wl.w, det_r=wl.det_r, det_D=wl.det_D, ext=wl.ext,
+                       n_phi=wl.n_phi, ln_w_ext=wl.ln_w_ext, d_max=wl.d_max, d0=wl.d0,
+                       n_norm=wl.n_norm, **kw)
+    return bank, ev
+
+
+def test_distance_rule_vs_oracle(ctx):
+    rng = np.random.default_rng(0)
+    dmax = 5000.0
+    # (z, s) over the range met by the workloads: template SNR at D_max from
+    # 1e-4 to 20, projected data SNR from -10 to 60, peaks resolved by the oracle
+    s = np.exp(rng.uniform(np.log(1e-4), np.log(20.0), 4000))
+    z = rng.uniform(-10, 60, 4000)
+    # the oracle's 2000 Gauss-Legendre nodes resolve a peak at D* = D_max s/z
+    # of width D*/z when that width spans at least two node spacings
+    dstar = dmax * s / np.maximum(z, 1e-9)
+    spacing = np.pi / 2000 * np.sqrt(np.clip(dstar * (dmax - dstar), 1.0, None))
+    keep = (z < 4) | ((dstar / np.maximum(z, 1e-9) >= 2 * spacing) & (dstar < dmax))
+    s, z = s[keep], z[keep]
+    hh = (s * dmax) ** 2
+    dh = z * np.sqrt(hh)
+    got = ctx.distmarg(dh, hh, 1.0 / dmax)
+    ref = O.ln_dist_marg(dh, hh, dmax, 1.0, 2000)
+    err = np.abs(got - ref)
+    print("distance rule: max err", err.max(), "n", len(z), flush=True)
+    assert err.max() < 5e-7
+    assert ctx.distmarg([0.0], [0.0], 1e-3)[0] == 0.0
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "hm"])
+def test_response_vs_oracle(ctx, cfg):
+    wl = W.config_tiny(seed=1, n_int=4, n_ext=100) if cfg == "tiny" else \
+        W.config_production(seed=2, n_int=4, n_ext=100)
+    bank, ev = make_event(ctx, wl)
+    R, t = ev.response()
+    Rref = O.response(wl.det_D, wl.modes, wl.ext)
+    tref = O.arrival_times(wl.det_r, wl.ext["lat"], wl.ext["lon"], wl.ext["t_geo"])
+    assert np.allclose(R, Rref, rtol=0, atol=1e-13)
+    assert np.allclose(t, tref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("shape", [(48, 80), (70, 33), (1, 1), (64, 64)])
+def test_eval_fp64_tiny(ctx, shape):
+    """22-only, 2 detectors, 64 bins: several 64x32 tiles with ragged edges."""
+    wl = W.config_tiny(seed=0, n_int=shape[0], n_ext=shape[1], random_weights=True)
+    bank, ev = make_event(ctx, wl)
+    out = ev.eval_lnl(ml=True, triples=True)
+    ref = O.eval_pairs_block(wl, np.arange(wl.n_int), return_triples=True)
+    scale = np.max(np.abs(ref["dh"])) + 1.0
+    assert np.max(np.abs(out["dh"] - ref["dh"])) <= 1e-9 * scale
+    assert np.allclose(out["hh"], ref["hh"], rtol=1e-11, atol=0)
+    assert np.allclose(out["ml_max"], ref["ml_max"], rtol=1e-9, atol=1e-9)
+    err = np.max(np.abs(out["lnl"] - ref["lnl"]))
+    print(f"fp64 tiny {shape}: max |d lnLbar| = {err:.3e}", flush=True)
+    assert err < TOL_FP64
+
+
+def test_eval_fp64_higher_modes(ctx):
+    """3 detectors, 5 modes (4 m-groups), 256 bins, 32 phases."""
+    wl = W.config_production(seed=5, n_int=40, n_ext=70, snr=20.0, random_weights=True)
+    bank, ev = make_event(ctx, wl)
+    out = ev.eval_lnl(ml=True, triples=True)
+    ref = O.eval_pairs_block(wl, np.arange(wl.n_int), return_triples=True)
+    scale = np.max(np.abs(ref["dh"])) + 1.0
+    assert np.max(np.abs(out["dh"] - ref["dh"])) <= 1e-9 * scale
+    assert np.allclose(out["hh"], ref["hh"], rtol=1e-10, atol=1e-12 * np.max(ref["hh"]))
+    err = np.max(np.abs(out["lnl"] - ref["lnl"]))
+    print(f"fp64 hm: max |d lnLbar| = {err:.3e}", flush=True)
+    assert err < TOL_FP64
+
+
+@pytest.mark.parametrize("window", [40.0, 1e9])
+def test_evidence_fp64_no_cut(ctx, window):
+    """ln Z, N_eff ingredients, max lnL^ML, (d|d) and the top-k pairs (the
+    k largest p_ie within `window` of the largest, ties by (i, e))."""
+    wl = W.config_tiny(seed=0, n_int=100, n_ext=90, random_weights=True)
+    bank, ev = make_event(ctx, wl, top_k=20, topk_window=window)
+    r = ev.evidence()
+    ref = O.evidence(wl, k=20)
+    assert r["n_pairs"] == wl.n_int * wl.n_ext
+    assert abs(r["ln_z"] - ref["ln_z"]) < TOL_FP64
+    assert r["ln_z_upper"] == pytest.approx(r["ln_z"], abs=1e-12)
+    assert abs(r["ln_sum_p2"] - ref["ln_sum_p2"]) < 2 * TOL_FP64
+    assert r["max_lnl_ml"] == pytest.approx(float(np.max(O.eval_pairs_block(
+        wl, np.arange(wl.n_int))["ml_max"])), rel=1e-9)
+    assert r["dd"] == pytest.approx(ref["dd"], rel=1e-12)
+    assert r["max_ln_p"] == pytest.approx(float(np.max(ref["lnp"])), abs=TOL_FP64)
+    in_window = ref["topk_lnp"] >= np.max(ref["lnp"]) - window
+    n_exp = int(np.sum(in_window))
+    assert r["topk_count"] == n_exp and r["topk_exact"] == 1
+    assert np.array_equal(np.stack([r["topk_i"], r["topk_e"]], -1), ref["topk_idx"][:n_exp])
+    assert np.allclose(r["topk_lnp"], ref["topk_lnp"][:n_exp], atol=TOL_FP64)
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
+@pytest.mark.parametrize("snr", [8.0, 20.0, 50.0])
+def test_eval_mixed_tiny(ctx, prec, snr):
+    wl = W.config_tiny(seed=2, n_int=64, n_ext=96, snr=snr)
+    bank, ev = make_event(ctx, wl, precision=prec)
+    got = ev.eval_lnl()["lnl"]
+    ref = O.eval_pairs_block(wl, np.arange(wl.n_int))["lnl"]
+    err = np.abs(got - ref)
+    zg = O.evidence_from_lnl(got, wl.ln_w_int, wl.ln_w_ext)["ln_z"]
+    zr = O.evidence_from_lnl(ref, wl.ln_w_int, wl.ln_w_ext)["ln_z"]
+    print(f"{prec} snr {snr}: max |d lnLbar| = {err.max():.3e}, |d lnZ| = {abs(zg - zr):.3e}",
+          flush=True)
+    if prec == "fp16x2":
+        assert err.max() <= TOL_MIXED
+        assert abs(zg - zr) <= TOL_MIXED
+
+
+def test_eval_mixed_higher_modes(ctx):
+    wl = W.config_production(seed=6, n_int=64, n_ext=64, snr=20.0)
+    bank, ev = make_event(ctx, wl, precision="fp16x2")
+    got = ev.eval_lnl()["lnl"]
+    ref = O.eval_pairs_block(wl, np.arange(wl.n_int))["lnl"]
+    err = np.abs(got - ref)
+    print(f"fp16x2 hm: max |d lnLbar| = {err.max():.3e}", flush=True)
+    assert err.max() <= TOL_MIXED
+
+
+_REF_CACHE = {}
+
+
+def _evidence_ref(wl, k):
+    key = (wl.meta["seed"], wl.n_int, wl.n_ext, k)
+    if key not in _REF_CACHE:
+        _REF_CACHE[key] = O.evidence(wl, k=k)
+    return _REF_CACHE[key]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x2"])
+def test_evidence_cut_is_certified(ctx, prec):
+    """With the coherent cut on, triples below (running max - delta) are not
+    marginalised but bounded by exp(lnL^ML) (since Lbar <= exp(lnL^ML)):
+    ln_z <= ln Z_oracle <= ln_z_upper, and the interval is narrow."""
+    wl = W.config_production(seed=8, n_int=160, n_ext=96, snr=25.0)
+    bank, ev = make_event(ctx, wl, precision=prec, cut_delta=20.0, top_k=64)
+    r = ev.evidence()
+    ref = _evidence_ref(wl, 64)
+    tol = TOL_FP64 if prec == "fp64" else TOL_MIXED
+    print(f"{prec} cut: ln Z {r['ln_z']:.6f} upper {r['ln_z_upper']:.6f} oracle {ref['ln_z']:.6f} "
+          f"bounded pairs {r['n_pairs_bounded']}/{r['n_pairs']} marg triples "
+          f"{r['n_triples_marg']}", flush=True)
+    assert r["n_pairs"] == wl.n_int * wl.n_ext
+    assert r["n_pairs_bounded"] > 0
+    assert r["ln_z"] <= ref["ln_z"] + tol
+    assert ref["ln_z"] <= r["ln_z_upper"] + tol
+    assert r["ln_z_upper"] - r["ln_z"] < 1e-3
+    assert r["max_lnl_ml"] == pytest.approx(float(np.max(
+        O.eval_pairs_block(wl, np.unique(np.r_[ref["topk_idx"][:, 0]]))["ml_max"])), abs=10 * tol)
+    # the best pairs are never cut
+    n = min(r["topk_count"], 16)
+    assert n > 0
+    assert np.array_equal(np.stack([r["topk_i"][:n], r["topk_e"][:n]], -1), ref["topk_idx"][:n])
+    assert np.allclose(r["topk_lnp"][:n], ref["topk_lnp"][:n], atol=tol)
+
+
+def test_subset_rows_and_norm(ctx):
+    """Bank subsets by explicit rows and by range; N_norm enters ln Z as
+    -ln N_norm (eq. Z_sum)."""
+    wl = W.config_tiny(seed=4, n_int=200, n_ext=40)
+    bank = ctx.load_bank(wl.h, wl.modes, wl.f, wl.ln_w_int, precision="fp64")
+    rng = np.random.default_rng(3)
+    rows = rng.choice(200, 37, replace=False)
+    common = dict(d=wl.d, w=wl.w, det_r=wl.det_r, det_D=wl.det_D, ext=wl.ext, n_phi=wl.n_phi,
+                  d_max=wl.d_max, d0=wl.d0)
+    ev = ctx.set_event(bank, sub_idx=rows, n_norm=1000.0, **common)
+    got = ev.eval_lnl()["lnl"]
+    ref = O.eval_pairs_block(wl, rows)["lnl"]
+    assert np.max(np.abs(got - ref)) < TOL_FP64
+    r = ev.evidence()
+    z = O.evidence_from_lnl(ref, wl.ln_w_int[rows], wl.ln_w_ext, n_norm=1000.0)["ln_z"]
+    assert abs(r["ln_z"] - z) < TOL_FP64
+    ev2 = ctx.set_event(bank, sub_start=150, sub_count=50, **common)
+    got2 = ev2.eval_lnl()["lnl"]
+    assert np.max(np.abs(got2 - O.eval_pairs_block(wl, np.arange(150, 200))["lnl"])) < TOL_FP64
+
+
+def test_invalid_inputs_rejected(ctx):
+    from paper_2507_16022_amd import dotpe
+    wl = W.config_tiny(seed=4, n_int=8, n_ext=8)
+    with pytest.raises(dotpe.DotpeError) as e:
+        ctx.load_bank(wl.h, ((2, 5),), wl.f, precision="fp64")
+    assert e.value.code == dotpe.E_INVALID_ARG
+    h = wl.h.copy()
+    h[3, 0, 5] = np.nan
+    with pytest.raises(dotpe.DotpeError) as e:
+        ctx.load_bank(h, wl.modes, wl.f, precision="fp16x2")
+    assert e.value.code == dotpe.E_NUMERIC
+    bank = ctx.load_bank(wl.h, wl.modes, wl.f, precision="fp64")
+    common = dict(d=wl.d, w=wl.w, det_r=wl.det_r, det_D=wl.det_D, n_phi=wl.n_phi)
+    with pytest.raises(dotpe.DotpeError) as e:
+        ctx.set_event(bank, ext=wl.ext, sub_idx=[0, 8], **common)
+    assert e.value.code == dotpe.E_INVALID_ARG
+    bad = dict(wl.ext)
+    bad["t_geo"] = bad["t_geo"].copy()
+    bad["t_geo"][2] = np.inf
+    with pytest.raises(dotpe.DotpeError) as e:
+        ctx.set_event(bank, ext=bad, **common)
+    assert e.value.code == dotpe.E_NUMERIC
+    small = dotpe.Context(0, budget_bytes=1 << 20)
+    with pytest.raises(dotpe.DotpeError) as e:
+        small.load_bank(W.config_tiny(seed=1, n_int=4096, n_ext=2).h, wl.modes, wl.f)
+    assert e.value.code in (dotpe.E_ADMISSION, dotpe.E_OOM)
+
+
+def test_mixed_higher_modes_snr50_vs_fp64(ctx):
+    """Split precision at the 5-mode shape and SNR 50: every pair within 1e-3
+    of the FP64 path and of the oracle."""
+    wl = W.config_production(seed=9, n_int=96, n_ext=64, snr=50.0)
+    b64, e64 = make_event(ctx, wl, precision="fp64")
+    l64 = e64.eval_lnl()["lnl"]
+    ref = O.eval_pairs_block(wl, np.arange(wl.n_int))["lnl"]
+    assert np.max(np.abs(l64 - ref)) < TOL_FP64
+    for prec in ("fp16x2", "bf16x2"):
+        b, e = make_event(ctx, wl, precision=prec)
+        l = e.eval_lnl()["lnl"]
+        err = np.abs(l - l64)
+        top = l64 >= np.max(l64) - 20
+        print(f"{prec} snr50 hm: max |d lnLbar| all {err.max():.3e}, near max {err[top].max():.3e}",
+              flush=True)
+        if prec == "fp16x2":
+            assert err.max() <= TOL_MIXED
