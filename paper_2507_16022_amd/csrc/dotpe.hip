@@ -192,14 +192,24 @@ int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
   }
   mt->gk0[mt->G] = c2 * cpc;
   mt->ND = ms.back() - ms.front() + 1;
+  // channel pairs c <= c', sorted by |m_c - m_c'|
   int p = 0;
-  for (int a = 0; a < nc; ++a)
-    for (int b = a; b < nc; ++b) {
-      mt->pc[p] = a;
-      mt->pc2[p] = b;
-      mt->pdel[p] = mt->m[a] - mt->m[b];
-      ++p;
-    }
+  for (int d = 0; d <= mt->ND - 1 && d < kMaxND; ++d) {
+    mt->pstart[d] = p;
+    for (int a = 0; a < nc; ++a)
+      for (int b = a; b < nc; ++b) {
+        int del = mt->m[a] - mt->m[b];
+        if (std::abs(del) != d) continue;
+        mt->pc[p] = a;
+        mt->pc2[p] = b;
+        mt->pdel[p] = del;
+        mt->pf[p] = (d == 0) ? (a == b ? 1.0f : 2.0f) : 1.0f;
+        mt->ps[p] = del < 0 ? -1.0f : 1.0f;
+        if (a == b) mt->pdiag[a] = p;
+        ++p;
+      }
+  }
+  for (int d = std::min(mt->ND, kMaxND); d <= kMaxND; ++d) mt->pstart[d] = p;
   mt->NP = p;
   return DOTPE_OK;
 }
@@ -542,6 +552,9 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
     return fail(DOTPE_E_INVALID_ARG, "event arrays must not be NULL");
   if (!(d->d_max > 0.0) || !(d->d0 > 0.0) || !std::isfinite(d->d_max) || !std::isfinite(d->d0))
     return fail(DOTPE_E_INVALID_ARG, "distances must be positive and finite");
+  if (d->n_det * bk->mt.NP > kMaxKP)
+    return fail(DOTPE_E_INVALID_ARG, "n_det * n_modes (n_modes + 1) / 2 = %d exceeds %d",
+                d->n_det * bk->mt.NP, kMaxKP);
   const int nb = bk->n_b, nk = d->n_det;
   const int64_t ne = d->n_ext;
   if (!finite_all(d->d, (size_t)nk * nb * 2) || !finite_all(d->w, (size_t)nk * nb) ||

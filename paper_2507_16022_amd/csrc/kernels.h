@@ -47,7 +47,13 @@ struct ModeTables {
   int orig[kMaxC];                 // input channel index of each
   int gm[kMaxG];                   // m of each group
   int gk0[kMaxG + 1];              // chunk index where each group starts
-  int pc[kMaxNP], pc2[kMaxNP], pdel[kMaxNP];   // channel pairs c <= c', m_c - m_c'
+  // channel pairs (c, c') with c <= c', sorted by |m_c - m_c'|: pairs with
+  // |delta| = d occupy [pstart[d], pstart[d + 1])
+  int pc[kMaxNP], pc2[kMaxNP], pdel[kMaxNP];   // m_c - m_c' (signed)
+  int pstart[kMaxND + 1];
+  float pf[kMaxNP];                // delta = 0: 1 (c = c') or 2 (c != c')
+  float ps[kMaxNP];                // sign of the imaginary part (conjugate when delta < 0)
+  int pdiag[kMaxC];                // pair index of (c, c)
 };
 
 struct DistArgs {
@@ -504,6 +510,8 @@ struct Pol<kFP16X2> {
 template <>
 struct Pol<kBF16X2> : Pol<kFP16X2> {};
 
+constexpr int kMaxKP = 48;      // n_det * channel pairs staged per row / column
+
 template <int PREC>
 struct Tile {
   typedef Pol<PREC> P;
@@ -514,11 +522,19 @@ struct Tile {
   static constexpr int ACC_T_BYTES = (PREC == kFP64) ? 8 : 4;
   static constexpr int EPI_STRIDE = 2 * kMaxG + 1;
   static constexpr int EPI_BYTES = 4 * 256 * EPI_STRIDE * ACC_T_BYTES;
+  // epilogue tables after the accumulator blocks
+  static constexpr int HROW_OFF = EPI_BYTES;                       // float2 [kMaxKP][TM]
+  static constexpr int QCOL_OFF = HROW_OFF + TM * kMaxKP * 8;      // float2 [kMaxKP][TN]
+  static constexpr int ROWD_OFF = QCOL_OFF + TN * kMaxKP * 8;      // double [TM][3]
+  static constexpr int COLD_OFF = ROWD_OFF + TM * 3 * 8;           // double [TN][2]
+  static constexpr int LIST_OFF = COLD_OFF + TN * 2 * 8;           // uint16 [1024]
+  static constexpr int CNT_OFF = LIST_OFF + 1024 * 2;              // int counter, u64 max
+  static constexpr int EPI_TOTAL = CNT_OFF + 16;
   static constexpr int PIECE_ELEMS = 16 / (int)sizeof(typename P::T);   // 16-byte pieces
   static constexpr int PIECES_PER_ROW = 32 / PIECE_ELEMS;
   static constexpr int PIECES = (P::NA * TM + P::NB * TN) * PIECES_PER_ROW;
   static constexpr int PIECES_PER_THREAD = PIECES / 256;
-  static constexpr int MAIN_BYTES = (2 * STAGE_BYTES > EPI_BYTES) ? 2 * STAGE_BYTES : EPI_BYTES;
+  static constexpr int MAIN_BYTES = (2 * STAGE_BYTES > EPI_TOTAL) ? 2 * STAGE_BYTES : EPI_TOTAL;
 };
 
 template <int PREC>
@@ -536,12 +552,33 @@ __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a
   }
 }
 
-// per-pair epilogue state for the evidence reduction
+enum Mode { kEval = 0, kEvidence = 1, kPilot = 2 };
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// float online log-sum-exp (for upper bounds of cut contributions)
+struct LseF {
+  float m, s;
+  __device__ void init() { m = -INFINITY; s = 0.f; }
+  __device__ void add(float x) {
+    if (x > m) { s = s * __expf(m - x) + 1.f; m = x; }
+    else s += __expf(x - m);
+  }
+};
+
+// per-thread accumulators of the evidence reduction
 struct EvAcc {
-  Lse p;          // over ln p_ie
-  Lse drop;       // over bounds of cut contributions (ln)
-  double ml_max;
-  double max_bound;   // max over bounded pairs of ln w_i + ln w_e + bound
+  Lse p;              // ln p_ie of evaluated pairs
+  LseF drop;          // upper bounds of everything cut (ln)
+  double ml_max;      // max lnL^ML over evaluated triples
+  float max_bound;    // max over bounded pairs of ln w + bound
   double n_marg, n_bounded, n_pairs;
   __device__ void init() {
     p.init(); drop.init();
@@ -550,66 +587,50 @@ struct EvAcc {
   }
 };
 
-enum Mode { kEval = 0, kEvidence = 1, kPilot = 2 };
+// full evaluation of one pair: (h|h) coefficients, phase loop, cut,
+// distance marginalisation; returns ln p (-inf when nothing was kept)
+// (h|h) phase coefficients S_delta of one pair from per-row H and
+// per-column Q, element (k, p) at H[(k NP + p) * hs], Q[(k NP + p) * qs]
+template <typename T2, typename R>
+__device__ __forceinline__ void hh_coeffs(const ModeTables& mt, int n_det, const T2* H, int hs,
+                                          const T2* Q, int qs, R& S0, R* Sr, R* Si) {
+  S0 = 0;
+#pragma unroll
+  for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0; Si[d] = 0; }
+  for (int k = 0; k < n_det; ++k) {
+    const int base = k * mt.NP;
+    for (int p = mt.pstart[0]; p < mt.pstart[1]; ++p) {
+      T2 h = H[(base + p) * hs], q = Q[(base + p) * qs];
+      S0 += (R)mt.pf[p] * ((R)h.x * (R)q.x - (R)h.y * (R)q.y);
+    }
+#pragma unroll
+    for (int d = 1; d < kMaxND; ++d) {
+      R ar = 0, ai = 0;
+      for (int p = mt.pstart[d]; p < mt.pstart[d + 1]; ++p) {
+        T2 h = H[(base + p) * hs], q = Q[(base + p) * qs];
+        ar += (R)h.x * (R)q.x - (R)h.y * (R)q.y;
+        ai += (R)mt.ps[p] * ((R)h.x * (R)q.y + (R)h.y * (R)q.x);
+      }
+      Sr[d] += ar;
+      Si[d] += ai;
+    }
+  }
+}
 
-// evaluate one pair; returns ln p (or -inf when everything was cut) and o_best
+// full evaluation of one pair given X_g and the (h|h) coefficients: phase
+// loop, cut, distance marginalisation; returns ln p (-inf when nothing kept)
 template <int MODE>
-__device__ double pair_epilogue(const FusedArgs& a, const double* lds_cs, int64_t ie, int64_t i,
-                                int64_t e, const double2* X, double lnw, double thr_ml,
-                                EvAcc& ev, int& o_best) {
+__device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie, int64_t e,
+                            const double2* X, double S0, const double* Sr, const double* Si,
+                            double lnw, double thr_ml, EvAcc& ev, int& o_best) {
   constexpr bool EVAL = MODE == kEval;
   const ModeTables& mt = a.mt;
   const int G = mt.G;
   o_best = 0;
-  // per-pair bound (cut enabled only): lnL^ML_o <= U^2 / (2 L^2) for all o,
-  // U = sum_g |X_g| >= dh_o, L = lower bound of sqrt(hh_o) from the channel
-  // norms n_c^2 = sum_k |R_ekc|^2 H_ikcc (triangle inequality)
-  if (MODE == kEvidence && thr_ml > -INFINITY) {
-    double U = 0.0;
-    for (int g = 0; g < G; ++g) U += sqrt(X[g].x * X[g].x + X[g].y * X[g].y);
-    double nsum = 0.0, nmax = 0.0;
-    for (int c = 0; c < mt.n_c; ++c) {
-      double s = 0.0;
-      for (int k = 0; k < a.n_det; ++k)
-        s += a.R2[(e * a.n_det + k) * mt.n_c + c] * a.Hdiag[(ie * a.n_det + k) * mt.n_c + c];
-      double nc = sqrt(fmax(s, 0.0));
-      nsum += nc;
-      nmax = fmax(nmax, nc);
-    }
-    double L = 2.0 * nmax - nsum;
-    if (L > 0.0) {
-      double bound = U * U / (2.0 * L * L) * (1.0 + 1e-3) + 1e-3;
-      if (bound < thr_ml) {
-        ev.drop.add(lnw + bound);
-        ev.max_bound = fmax(ev.max_bound, lnw + bound);
-        ev.n_bounded += 1.0;
-        return -INFINITY;
-      }
-    }
-  }
-  // (h|h) coefficients S_delta
-  double S0 = 0.0, Sr[kMaxND], Si[kMaxND];
-  for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0.0; Si[d] = 0.0; }
-  for (int k = 0; k < a.n_det; ++k) {
-    const double2* Hk = a.H + (ie * a.n_det + k) * mt.NP;
-    const double2* Qk = a.Q + (e * a.n_det + k) * mt.NP;
-    for (int p = 0; p < mt.NP; ++p) {
-      double2 h = Hk[p], q = Qk[p];
-      int del = mt.pdel[p];
-      if (mt.pc[p] == mt.pc2[p]) {
-        S0 += h.x * q.x;
-      } else {
-        double2 v = cmul(h, q);
-        if (del == 0) S0 += 2.0 * v.x;
-        else if (del > 0) { Sr[del] += v.x; Si[del] += v.y; }
-        else { Sr[-del] += v.x; Si[-del] -= v.y; }
-      }
-    }
-  }
-  // phase loop
   Lse lse;
   lse.init();
   double best = -INFINITY, mlmax = 0.0;
+  const double thr2 = 2.0 * thr_ml;
   for (int o = 0; o < a.n_phi; ++o) {
     double dh = 0.0;
     for (int g = 0; g < G; ++g) {
@@ -622,17 +643,24 @@ __device__ double pair_epilogue(const FusedArgs& a, const double* lds_cs, int64_
       hh += 2.0 * (Sr[d] * cs[0] + Si[d] * cs[1]);
     }
     hh = fmax(hh, 0.0);
-    double ml = (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0;
-    mlmax = fmax(mlmax, ml);
     if (EVAL && a.trip_out) {
       size_t t = (((size_t)ie * a.n_ext + e) * a.n_phi + o) * 2;
       a.trip_out[t] = dh;
       a.trip_out[t + 1] = hh;
     }
-    if (MODE == kPilot) continue;
-    if (!EVAL && ml < thr_ml) {
-      ev.drop.add(lnw + ml - a.ln_nphi);
-      continue;
+    // lnL^ML >= thr  <=>  dh > 0 and dh^2 >= 2 thr hh (no division)
+    const bool keep = EVAL || thr_ml <= 0.0 || (dh > 0.0 && dh * dh >= thr2 * hh);
+    if (MODE == kPilot || !keep || EVAL) {
+      double ml = (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0;
+      mlmax = fmax(mlmax, ml);
+      if (MODE == kPilot) continue;
+      if (!keep) {
+        float x = (float)(lnw + ml - a.ln_nphi);
+        ev.drop.add(x + fabsf(x) * 1e-6f + 1e-5f);   // rounding margin keeps it a bound
+        continue;
+      }
+    } else {
+      mlmax = fmax(mlmax, (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0);
     }
     double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, a.dist.geom, a.dist.ghx, a.dist.ghw);
     if (v > best) { best = v; o_best = o; }
@@ -651,15 +679,6 @@ __device__ double pair_epilogue(const FusedArgs& a, const double* lds_cs, int64_
   double lnp = lnw + lnl;
   ev.p.add(lnp);
   return lnp;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
 }
 
 template <int PREC, int G, int MODE>
@@ -721,29 +740,31 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   const void* Bsrc[4] = {a.B0, a.B1, a.B2, a.B3};
   uint4 stg[TL::PIECES_PER_THREAD];
 
+  // per-thread source pointers of its 16-byte pieces (chunk 0); a piece of
+  // a bank row past the subset reads nothing
+  const T* srcp[TL::PIECES_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
+    int p = tid + 256 * q;
+    int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
+    srcp[q] = nullptr;
+    if (rowsel < P::NA * TM) {
+      int arr = rowsel / TM, r = rowsel % TM;
+      int64_t ie = row0 + r;
+      if (ie < a.n_sub) {
+        int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+        srcp[q] = (const T*)Asrc[arr] + i * a.K2 + piece * TL::PIECE_ELEMS;
+      }
+    } else {
+      int rs = rowsel - P::NA * TM;
+      int arr = rs / TN, c = rs % TN;
+      srcp[q] = (const T*)Bsrc[arr] + (col0 + c) * a.K2 + piece * TL::PIECE_ELEMS;
+    }
+  }
   auto load_chunk = [&](int ch) {
 #pragma unroll
-    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
-      int p = tid + 256 * q;
-      int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (rowsel < P::NA * TM) {
-        int arr = rowsel / TM, r = rowsel % TM;
-        int64_t ie = row0 + r;
-        if (ie < a.n_sub) {
-          int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-          const T* src = (const T*)Asrc[arr] + i * a.K2 + (int64_t)ch * 32 + piece * TL::PIECE_ELEMS;
-          v = *(const uint4*)src;
-        }
-      } else {
-        int rs = rowsel - P::NA * TM;
-        int arr = rs / TN, c = rs % TN;
-        int64_t e = col0 + c;                  // < n_ext_p by construction
-        const T* src = (const T*)Bsrc[arr] + e * a.K2 + (int64_t)ch * 32 + piece * TL::PIECE_ELEMS;
-        v = *(const uint4*)src;
-      }
-      stg[q] = v;
-    }
+    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q)
+      stg[q] = srcp[q] ? *(const uint4*)(srcp[q] + (int64_t)ch * 32) : make_uint4(0, 0, 0, 0);
   };
   auto store_chunk = [&](int buf) {
     T* base = stage + buf * TL::STAGE_ELEMS;
@@ -834,17 +855,63 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   }
 
   // ---- epilogue ----
+  // E0: per-row / per-column tables of the tile to LDS
   typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
-  AT* epi = (AT*)smem + wave * 256 * TL::EPI_STRIDE;
+  float2* hrow = (float2*)(smem + TL::HROW_OFF);
+  float2* qcol = (float2*)(smem + TL::QCOL_OFF);
+  double* rowd = (double*)(smem + TL::ROWD_OFF);
+  double* cold = (double*)(smem + TL::COLD_OFF);
+  uint16_t* list = (uint16_t*)(smem + TL::LIST_OFF);
+  int* list_n = (int*)(smem + TL::CNT_OFF);
+  unsigned long long* tile_lnp_max = (unsigned long long*)(smem + TL::CNT_OFF + 8);
+  const int KP = a.n_det * a.mt.NP;
+  for (int t = tid; t < TM; t += 256) {
+    int64_t ie = row0 + t;
+    double lw = 0.0, sc = 1.0, ii = -1.0;
+    if (ie < a.n_sub) {
+      int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+      lw = a.ln_w_bank ? a.ln_w_bank[i] : 0.0;
+      sc = PREC == kFP64 ? 1.0 : a.row_scale[i];
+      ii = (double)i;
+    }
+    rowd[t * 3] = lw; rowd[t * 3 + 1] = sc; rowd[t * 3 + 2] = ii;
+  }
+  for (int t = tid; t < TN; t += 256) {
+    int64_t e = col0 + t;
+    double lw = 0.0, sc = 1.0;
+    if (e < a.n_ext) {
+      lw = a.ln_w_ext ? a.ln_w_ext[e] : 0.0;
+      sc = PREC == kFP64 ? 1.0 : a.col_scale[e];
+    }
+    cold[t * 2] = lw; cold[t * 2 + 1] = sc;
+  }
+  for (int r = wave; r < TM; r += 4) {
+    int64_t ie = row0 + r;
+    for (int q = lane; q < KP; q += 64) {
+      double2 v = ie < a.n_sub ? a.H[ie * KP + q] : make_double2(0.0, 0.0);
+      hrow[q * TM + r] = make_float2((float)v.x, (float)v.y);
+    }
+  }
+  for (int c = wave; c < TN; c += 4) {
+    int64_t e = col0 + c;
+    for (int q = lane; q < KP; q += 64) {
+      double2 v = e < a.n_ext ? a.Q[e * KP + q] : make_double2(0.0, 0.0);
+      qcol[q * TN + c] = make_float2((float)v.x, (float)v.y);
+    }
+  }
+  if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
 
   double thr_ml = -INFINITY, thr_topk_glob = -INFINITY;
-  if (!EVAL) {
+  if (MODE == kEvidence) {
     if (a.cut_delta > 0.0) thr_ml = __longlong_as_double(a.state[0]) - a.cut_delta;
     thr_topk_glob = order_value(a.state[1]) - a.topk_window;
   }
+  const bool use_bound = MODE == kEvidence && thr_ml > 0.0;
+  const float thr_f = (float)thr_ml;
   EvAcc ev;
   ev.init();
-  double tile_max_lnp = -INFINITY;
+  AT* epi_all = (AT*)smem;
+  AT* epi = epi_all + wave * 256 * TL::EPI_STRIDE;
 
 #pragma unroll 1
   for (int blk = 0; blk < P::BM * P::BN; ++blk) {
@@ -866,55 +933,100 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
     }
     __syncthreads();
     const int bm = blk / P::BN, bn = blk % P::BN;
-    double lnp_keep[4];
-    int ob_keep[4];
-    int64_t i_keep[4], e_keep[4];
-    double blk_max = -INFINITY;
+    // E1: per-pair bound, survivors to the list
     for (int t = 0; t < 4; ++t) {
       int q = lane + 64 * t;
-      int64_t ie = row0 + wm * 16 * P::BM + bm * 16 + q / 16;
-      int64_t e = col0 + wn * 16 * P::BN + bn * 16 + (q & 15);
-      lnp_keep[t] = -INFINITY;
-      ob_keep[t] = 0;
-      i_keep[t] = -1;
-      e_keep[t] = e;
-      if (ie >= a.n_sub || e >= a.n_ext) continue;
-      int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-      i_keep[t] = i;
-      double sc = 1.0;
-      if (PREC != kFP64) sc = a.row_scale[i] * a.col_scale[e];
-      double2 X[G];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-        X[g] = make_double2(sc * (double)epi[q * TL::EPI_STRIDE + 2 * g],
-                            sc * (double)epi[q * TL::EPI_STRIDE + 2 * g + 1]);
-      double lnw = (a.ln_w_bank ? a.ln_w_bank[i] : 0.0) + (a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
-      int ob = 0;
+      int tr = wm * 16 * P::BM + bm * 16 + q / 16;
+      int tc = wn * 16 * P::BN + bn * 16 + (q & 15);
+      if (row0 + tr >= a.n_sub || col0 + tc >= a.n_ext) continue;
       ev.n_pairs += 1.0;
-      double lnp = pair_epilogue<MODE>(a, lds_cs, ie, i, e, X, lnw, thr_ml, ev, ob);
-      if (MODE == kEvidence) {
-        lnp_keep[t] = lnp;
-        ob_keep[t] = ob;
-        blk_max = fmax(blk_max, lnp);
+      bool survive = true;
+      if (use_bound) {
+        float sc = (float)(rowd[tr * 3 + 1] * cold[tc * 2 + 1]);
+        float U = 0.f;
+        for (int g = 0; g < G; ++g) {
+          float xr = (float)epi[q * TL::EPI_STRIDE + 2 * g], xi = (float)epi[q * TL::EPI_STRIDE + 2 * g + 1];
+          U += sqrtf(xr * xr + xi * xi);
+        }
+        U *= fabsf(sc);
+        // two lower bounds of hh_o valid for every phase: S0 - 2 sum |S_delta|
+        // and (2 max_c n_c - sum_c n_c)^2 with n_c^2 = sum_k H_kcc Q_kcc
+        float S0f, Srf[kMaxND], Sif[kMaxND];
+        hh_coeffs<float2, float>(a.mt, a.n_det, hrow + tr, TM, qcol + tc, TN, S0f, Srf, Sif);
+        float lo1 = S0f;
+        for (int d = 1; d < a.mt.ND; ++d) lo1 -= 2.f * sqrtf(Srf[d] * Srf[d] + Sif[d] * Sif[d]);
+        float nsum = 0.f, nmax = 0.f;
+        for (int c = 0; c < a.mt.n_c; ++c) {
+          float s2 = 0.f;
+          for (int k = 0; k < a.n_det; ++k) {
+            int pq = k * a.mt.NP + a.mt.pdiag[c];
+            s2 += hrow[pq * TM + tr].x * qcol[pq * TN + tc].x;
+          }
+          float nc = sqrtf(fmaxf(s2, 0.f));
+          nsum += nc;
+          nmax = fmaxf(nmax, nc);
+        }
+        float lo2 = 2.f * nmax - nsum;
+        lo2 = lo2 > 0.f ? lo2 * lo2 : 0.f;
+        float hlo = fmaxf(lo1, lo2) * 0.999f;     // margin for FP32 rounding
+        // lnL^ML_o <= U^2 / (2 hlo) for every phase
+        if (hlo > 0.f) {
+          float bound = U * U / (2.f * hlo) * 1.001f + 1e-3f;
+          if (bound < thr_f) {
+            survive = false;
+            float lw = (float)(rowd[tr * 3] + cold[tc * 2]);
+            ev.drop.add(lw + bound);
+            ev.max_bound = fmaxf(ev.max_bound, lw + bound);
+            ev.n_bounded += 1.0;
+          }
+        }
+      }
+      if (survive) {
+        int slot = atomicAdd(list_n, 1);
+        list[slot] = (uint16_t)((wave << 8) | q);
       }
     }
-    if (MODE == kEvidence) {
-      blk_max = wave_max(blk_max);
-      tile_max_lnp = fmax(tile_max_lnp, blk_max);
-      double thr_k = fmax(thr_topk_glob, blk_max - a.topk_window);
-      for (int t = 0; t < 4; ++t) {
-        if (lnp_keep[t] > -INFINITY && lnp_keep[t] >= thr_k) {
+    __syncthreads();
+    // E2: survivors, load-balanced over the workgroup
+    const int nsurv = *list_n;
+    for (int j = tid; j < nsurv; j += 256) {
+      int w = list[j] >> 8, q = list[j] & 255;
+      int wm_ = w >> 1, wn_ = w & 1;
+      int tr = wm_ * 16 * P::BM + bm * 16 + q / 16;
+      int tc = wn_ * 16 * P::BN + bn * 16 + (q & 15);
+      int64_t ie = row0 + tr, e = col0 + tc;
+      const AT* xq = epi_all + (w * 256 + q) * TL::EPI_STRIDE;
+      double sc = rowd[tr * 3 + 1] * cold[tc * 2 + 1];
+      double2 X[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) X[g] = make_double2(sc * (double)xq[2 * g], sc * (double)xq[2 * g + 1]);
+      double lnw = rowd[tr * 3] + cold[tc * 2];
+      double S0, Sr[kMaxND], Si[kMaxND];
+      if (PREC == kFP64)
+        hh_coeffs<double2, double>(a.mt, a.n_det, a.H + ie * KP, 1, a.Q + e * KP, 1, S0, Sr, Si);
+      else
+        hh_coeffs<float2, double>(a.mt, a.n_det, hrow + tr, TM, qcol + tc, TN, S0, Sr, Si);
+      int ob = 0;
+      double lnp = pair_full<MODE>(a, lds_cs, ie, e, X, S0, Sr, Si, lnw, thr_ml, ev, ob);
+      if (MODE == kEvidence && lnp > -INFINITY) {
+        unsigned long long ob_bits = order_bits(lnp);
+        unsigned long long prev = atomicMax(tile_lnp_max, ob_bits);
+        double tmax = order_value(prev > ob_bits ? prev : ob_bits);
+        double thr_k = fmax(thr_topk_glob, tmax - a.topk_window);
+        if (lnp >= thr_k) {
           unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
           if ((int64_t)slot < a.cand_cap) {
             double* cd = a.cand + 4 * slot;
-            cd[0] = lnp_keep[t];
-            cd[1] = (double)i_keep[t];
-            cd[2] = (double)e_keep[t];
-            cd[3] = (double)ob_keep[t];
+            cd[0] = lnp;
+            cd[1] = rowd[tr * 3 + 2];
+            cd[2] = (double)e;
+            cd[3] = (double)ob;
           }
         }
       }
     }
+    __syncthreads();
+    if (tid == 0) *list_n = 0;
   }
   if (EVAL) return;
   if (MODE == kPilot) {
@@ -926,16 +1038,22 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
 
   // ---- tile reduction ----
   __syncthreads();
+  const double tile_max_lnp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
+  __syncthreads();
   double* red = (double*)smem;   // [4 waves][kNPart]
   {
-    Lse p = ev.p, d = ev.drop;
+    Lse p = ev.p;
+    Lse d;
+    d.m = ev.drop.m == -INFINITY ? -INFINITY : (double)ev.drop.m;
+    d.s = ev.drop.s;
+    d.s2 = 0.0;
     for (int off = 32; off > 0; off >>= 1) {
       double pm = __shfl_xor(p.m, off), ps = __shfl_xor(p.s, off), ps2 = __shfl_xor(p.s2, off);
       p.merge(pm, ps, ps2);
-      double dm = __shfl_xor(d.m, off), ds = __shfl_xor(d.s, off), ds2 = __shfl_xor(d.s2, off);
-      d.merge(dm, ds, ds2);
+      double dm = __shfl_xor(d.m, off), ds = __shfl_xor(d.s, off);
+      d.merge(dm, ds, 0.0);
     }
-    double mlm = wave_max(ev.ml_max), mb = wave_max(ev.max_bound);
+    double mlm = wave_max(ev.ml_max), mb = wave_max((double)ev.max_bound);
     double nm = wave_sum(ev.n_marg), nb = wave_sum(ev.n_bounded), np_ = wave_sum(ev.n_pairs);
     if (lane == 0) {
       double* r = red + wave * kNPart;
