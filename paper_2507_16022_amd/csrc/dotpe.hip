@@ -82,8 +82,12 @@ struct dotpe_event {
   void* B[4] = {nullptr, nullptr, nullptr, nullptr};
   double* col_scale = nullptr;
   double* ln_w_ext = nullptr;
-  double2* H = nullptr;
-  double* Hdiag = nullptr;
+  int* hh_terms = nullptr;     // (h|h) term codes [KH]
+  int KH = 0;                  // (h|h) operand row length
+  void* Ah[2] = {nullptr, nullptr};   // row-side (h|h) operand [n_sub][KH]
+  double* ah_scale = nullptr;
+  void* Bh[2] = {nullptr, nullptr};   // column-side (h|h) operand [n_ext_p][KH]
+  double* bh_scale = nullptr;
   double2* Q = nullptr;
   double* R2 = nullptr;
   double2* R = nullptr;
@@ -214,6 +218,51 @@ int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
   return DOTPE_OK;
 }
 
+// (h|h) term codes: output r < NR owns K block r (32 slots); see kernels.h
+int build_hh_terms(const ModeTables& mt, int n_det, std::vector<int>* terms, int* KH) {
+  const int nhb = mt.G == 1 ? 2 : kMaxNR + 1;
+  *KH = nhb * 32;
+  terms->assign(*KH, 0);
+  const int NR = 2 * mt.ND - 1;
+  auto code = [](int k, int p, int apart, int bpart, int coef_idx) {
+    return (k & 15) | ((p & 63) << 4) | (apart << 10) | (bpart << 11) | (coef_idx << 12) | 0x8000;
+  };
+  for (int r = 0; r < NR; ++r) {
+    std::vector<int> t;
+    for (int k = 0; k < n_det; ++k) {
+      if (r == 0) {
+        for (int p = mt.pstart[0]; p < mt.pstart[1]; ++p) {
+          if (mt.pc[p] == mt.pc2[p]) {
+            t.push_back(code(k, p, 0, 0, 1));
+          } else {
+            t.push_back(code(k, p, 0, 0, 3));     // 2 Re(H Q) = 2 (Hr Qr - Hi Qi)
+            t.push_back(code(k, p, 1, 1, 4));
+          }
+        }
+      } else {
+        const int d = (r + 1) / 2;
+        const bool im = (r % 2) == 0;
+        for (int p = mt.pstart[d]; p < mt.pstart[d + 1]; ++p) {
+          if (!im) {                               // Re(H Q) = Hr Qr - Hi Qi
+            t.push_back(code(k, p, 0, 0, 1));
+            t.push_back(code(k, p, 1, 1, 2));
+          } else {                                 // ps Im(H Q) = ps (Hr Qi + Hi Qr)
+            int ci = mt.ps[p] > 0 ? 1 : 2;
+            t.push_back(code(k, p, 0, 1, ci));
+            t.push_back(code(k, p, 1, 0, ci));
+          }
+        }
+      }
+    }
+    if (t.size() > 32)
+      return fail(DOTPE_E_INVALID_ARG,
+                  "(h|h) output %d needs %zu terms (> 32): too many modes x detectors", r,
+                  t.size());
+    for (size_t j = 0; j < t.size(); ++j) (*terms)[r * 32 + j] = t[j];
+  }
+  return DOTPE_OK;
+}
+
 template <int PREC>
 void launch_bank_convert(const double* h, dotpe_bank* bk, int* err, hipStream_t s) {
   hipLaunchKernelGGL(k_bank_convert<PREC>, dim3((unsigned)bk->n_wf), dim3(256), 0, s, h, bk->n_wf,
@@ -235,7 +284,11 @@ void launch_hh(dotpe_event* ev, const double* w) {
   if (sh > 65536) sh = 0;
   hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(64), sh, ev->stream,
                      ev->n_sub, ev->sub_idx, ev->sub0, bk->A0, bk->A1, bk->row_scale, bk->n_bp,
-                     bk->n_b, ev->n_det, w, bk->mt, ev->H, ev->Hdiag);
+                     bk->n_b, ev->n_det, w, bk->mt, ev->hh_terms, ev->KH, ev->Ah[0], ev->Ah[1],
+                     ev->ah_scale);
+  hipLaunchKernelGGL(k_build_Bhh<PREC>, dim3((unsigned)ev->n_ext_p), dim3(64), 0, ev->stream,
+                     ev->n_ext, ev->n_ext_p, ev->n_det, ev->Q, bk->mt, ev->hh_terms, ev->KH,
+                     ev->Bh[0], ev->Bh[1], ev->bh_scale);
 }
 
 template <int PREC, int G, int MODE>
@@ -308,10 +361,13 @@ FusedArgs make_args(dotpe_ctx* ctx, dotpe_event* ev) {
   a.n_ext_p = ev->n_ext_p;
   a.K2 = bk->K2;
   a.n_chunks = (int)(bk->K2 / 32);
-  a.H = ev->H;
-  a.Hdiag = ev->Hdiag;
-  a.Q = ev->Q;
-  a.R2 = ev->R2;
+  a.Ah0 = ev->Ah[0];
+  a.Ah1 = ev->Ah[1];
+  a.ah_scale = ev->ah_scale;
+  a.Bh0 = ev->Bh[0];
+  a.Bh1 = ev->Bh[1];
+  a.bh_scale = ev->bh_scale;
+  a.KH = ev->KH;
   a.n_det = ev->n_det;
   a.mt = bk->mt;
   a.n_phi = ev->n_phi;
@@ -421,7 +477,7 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
   bk->n_wf = d->n_wf;
   bk->n_c = d->n_modes;
   bk->n_b = d->n_bins;
-  bk->n_bp = (int)round_up(d->n_bins, kChunk);
+  bk->n_bp = (int)round_up(d->n_bins, 2 * kChunk);   // even chunk count per channel
   bk->K2 = (int64_t)bk->n_c * bk->n_bp * 2;
   bk->prec = d->precision;
   int rc = build_modes(d, &bk->mt, bk->n_bp);
@@ -552,9 +608,12 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
     return fail(DOTPE_E_INVALID_ARG, "event arrays must not be NULL");
   if (!(d->d_max > 0.0) || !(d->d0 > 0.0) || !std::isfinite(d->d_max) || !std::isfinite(d->d0))
     return fail(DOTPE_E_INVALID_ARG, "distances must be positive and finite");
-  if (d->n_det * bk->mt.NP > kMaxKP)
-    return fail(DOTPE_E_INVALID_ARG, "n_det * n_modes (n_modes + 1) / 2 = %d exceeds %d",
-                d->n_det * bk->mt.NP, kMaxKP);
+  std::vector<int> terms;
+  int KH = 0;
+  {
+    int rc0 = build_hh_terms(bk->mt, d->n_det, &terms, &KH);
+    if (rc0) return rc0;
+  }
   const int nb = bk->n_b, nk = d->n_det;
   const int64_t ne = d->n_ext;
   if (!finite_all(d->d, (size_t)nk * nb * 2) || !finite_all(d->w, (size_t)nk * nb) ||
@@ -609,8 +668,16 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
   for (int q = 0; q < nB; ++q)
     if ((rc = alloc(&ev->B[q], (size_t)ev->n_ext_p * bk->K2 * esz))) return cleanup(rc);
   if (bk->prec != kFP64 && (rc = alloc((void**)&ev->col_scale, ne * 8))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->H, (size_t)n_sub * nk * mt.NP * 16))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->Hdiag, (size_t)n_sub * nk * nc * 8))) return cleanup(rc);
+  ev->KH = KH;
+  if ((rc = alloc((void**)&ev->hh_terms, (size_t)KH * sizeof(int)))) return cleanup(rc);
+  for (int q = 0; q < (bk->prec == kFP64 ? 1 : 2); ++q) {
+    if ((rc = alloc(&ev->Ah[q], (size_t)n_sub * KH * esz))) return cleanup(rc);
+    if ((rc = alloc(&ev->Bh[q], (size_t)ev->n_ext_p * KH * esz))) return cleanup(rc);
+  }
+  if (bk->prec != kFP64) {
+    if ((rc = alloc((void**)&ev->ah_scale, (size_t)n_sub * 8))) return cleanup(rc);
+    if ((rc = alloc((void**)&ev->bh_scale, (size_t)ne * 8))) return cleanup(rc);
+  }
   if ((rc = alloc((void**)&ev->Q, (size_t)ne * nk * mt.NP * 16))) return cleanup(rc);
   if ((rc = alloc((void**)&ev->R2, (size_t)ne * nk * nc * 8))) return cleanup(rc);
   if ((rc = alloc((void**)&ev->R, (size_t)ne * nk * nc * 16))) return cleanup(rc);
@@ -662,6 +729,7 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
   H2D(dtg, d->t_geo, sizes[8]);
   if (d->ln_w_ext) H2D(ev->ln_w_ext, d->ln_w_ext, ne * 8);
   if (d->sub_idx) H2D(ev->sub_idx, d->sub_idx, n_sub * 8);
+  H2D(ev->hh_terms, terms.data(), terms.size() * sizeof(int));
   if (e == hipSuccess) e = hipMemsetAsync(err, 0, 64, s);
   // phase table cos, sin (m phi_o), m = 1..4 (a twiddle table of the grid)
   std::vector<double> cs((size_t)kMaxM * d->n_phi * 2);
@@ -775,8 +843,8 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
   HIP_OK(hipEventRecord(ev->ev_t[0], s));
   if (ev->cut_delta > 0.0 && a.n_tiles_m > 1) {
-    // pilot: max lnL^ML over every 16th row of tiles seeds the cut threshold
-    a.pilot_stride = 16;
+    // pilot: max lnL^ML over every 64th row of tiles seeds the cut threshold
+    a.pilot_stride = 64;
     int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
     if ((rc = launch_fused<kPilot>(ev->bank->prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
   }

@@ -70,6 +70,20 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for_impl(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for_impl<I + 1, N>(f);
+  }
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<0, N>(f);
+}
+
+
 // online log-sum-exp accumulator (also of 2x)
 struct Lse {
   double m, s, s2;
@@ -399,16 +413,59 @@ __global__ void k_data_norm(int n, const double2* __restrict__ d, const double* 
 }
 
 // ---------------------------------------------------------------------------
-// per-waveform (h|h) sums H_ikcc' for the event's bank subset, from the
-// same operand values the contraction uses
+// (h|h) operands.  For one pair, the phase coefficients of (h|h)
+//     S0 (real), Re S_d, Im S_d (d = 1 .. ND-1)      -- NR = 2 ND - 1 outputs
+// are each a dot product of at most 32 terms a * b with a taken from the
+// waveform's H_ikcc' and b from the sample's Q_ekcc'; they are computed by
+// the same matrix cores as (d|h), as extra K blocks of 32.  A term (output r,
+// slot j) is encoded in 16 bits: k (0-3), p (4-9), a from Im H (10), b from
+// Im Q (11), coefficient index (12-14: 0, 1, -1, 2, -2), valid (15).
 // ---------------------------------------------------------------------------
+constexpr int kMaxNR = 2 * kMaxND - 1;
+
+__device__ __forceinline__ double term_value(int code, const double2* X, int NP, bool row_side) {
+  if (!(code & 0x8000)) return 0.0;
+  int k = code & 15, p = (code >> 4) & 63;
+  int part = row_side ? (code >> 10) & 1 : (code >> 11) & 1;
+  double2 v = X[k * NP + p];
+  double x = part ? v.y : v.x;
+  if (row_side) {
+    int ci = (code >> 12) & 7;
+    x *= ci == 1 ? 1.0 : ci == 2 ? -1.0 : ci == 3 ? 2.0 : ci == 4 ? -2.0 : 0.0;
+  }
+  return x;
+}
+
+template <int PREC>
+__device__ __forceinline__ void store_split(void* A0, void* A1, int64_t o, double v) {
+  if (PREC == kFP64) {
+    ((double*)A0)[o] = v;
+  } else if (PREC == kFP16X2) {
+    _Float16 h = (_Float16)v;
+    ((_Float16*)A0)[o] = h;
+    ((_Float16*)A1)[o] = (_Float16)(v - (double)h);
+  } else {
+    __bf16 h = (__bf16)(float)v;
+    ((__bf16*)A0)[o] = h;
+    ((__bf16*)A1)[o] = (__bf16)(float)(v - (double)(float)h);
+  }
+}
+
+// per-waveform (h|h) sums H_ikcc' = sum_b w_kb h_icb conj(h_ic'b) for the
+// event's bank subset, from the same operand values the contraction uses,
+// written as the row-side (h|h) operand [n_sub][KH] with a power-of-two
+// row scale in the split precisions
 template <int PREC>
 __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_idx, int64_t sub0,
                                 const void* __restrict__ A0, const void* __restrict__ A1,
                                 const double* __restrict__ row_scale, int n_bp, int n_b,
                                 int n_det, const double* __restrict__ w, ModeTables mt,
-                                double2* __restrict__ H, double* __restrict__ Hdiag) {
+                                const int* __restrict__ terms, int KH, void* __restrict__ H0,
+                                void* __restrict__ H1, double* __restrict__ hscale) {
   extern __shared__ double2 rowbuf[];   // [n_c][n_bp] when it fits
+  __shared__ double2 Hs[kMaxDet * kMaxNP];
+  __shared__ double vals[256];
+  __shared__ double red[64];
   const int64_t ie = blockIdx.x;
   if (ie >= n_sub) return;
   const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
@@ -429,21 +486,65 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
     for (int b = 0; b < n_b; ++b) {
       double2 a = staged ? rowbuf[c * n_bp + b] : bank_value<PREC>(A0, A1, rowoff, c, b, n_bp);
       double2 a2 = staged ? rowbuf[c2 * n_bp + b] : bank_value<PREC>(A0, A1, rowoff, c2, b, n_bp);
-      // h_c conj(h_c') = conj(A_c) A_c'
-      double2 v = cmul(cconj(a), a2);
+      double2 v = cmul(cconj(a), a2);      // h_c conj(h_c') = conj(A_c) A_c'
       double ww = w[k * n_b + b];
       acc.x += ww * v.x;
       acc.y += ww * v.y;
     }
-    acc.x *= sc;
-    acc.y *= sc;
-    H[(ie * n_det + k) * mt.NP + p] = acc;
-    if (c == c2) Hdiag[(ie * n_det + k) * mt.n_c + c] = acc.x;
+    Hs[k * mt.NP + p] = make_double2(acc.x * sc, acc.y * sc);
   }
+  __syncthreads();
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < KH; j += blockDim.x) {
+    double v = term_value(terms[j], Hs, mt.NP, true);
+    vals[j] = v;
+    mx = fmax(mx, fabs(v));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  int ex = 0;
+  if (PREC != kFP64 && red[0] > 0.0 && isfinite(red[0])) ex = ilogb(red[0]) - 13;
+  if (threadIdx.x == 0 && hscale) hscale[ie] = ldexp(1.0, ex);
+  for (int j = threadIdx.x; j < KH; j += blockDim.x)
+    store_split<PREC>(H0, H1, ie * KH + j, ldexp(vals[j], -ex));
+}
+
+// column-side (h|h) operand [n_ext_p][KH] from Q_ekcc' = R_ekc conj(R_ekc')
+template <int PREC>
+__global__ void k_build_Bhh(int64_t n_ext, int64_t n_ext_p, int n_det, const double2* __restrict__ Q,
+                            ModeTables mt, const int* __restrict__ terms, int KH,
+                            void* __restrict__ B0, void* __restrict__ B1,
+                            double* __restrict__ bscale) {
+  __shared__ double vals[256];
+  __shared__ double red[64];
+  const int64_t e = blockIdx.x;
+  if (e >= n_ext_p) return;
+  double mx = 0.0;
+  for (int j = threadIdx.x; j < KH; j += blockDim.x) {
+    double v = e < n_ext ? term_value(terms[j], Q + e * n_det * mt.NP, mt.NP, false) : 0.0;
+    vals[j] = v;
+    mx = fmax(mx, fabs(v));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  int ex = 0;
+  if (PREC != kFP64 && red[0] > 0.0 && isfinite(red[0])) ex = ilogb(red[0]) - 13;
+  if (threadIdx.x == 0 && bscale && e < n_ext) bscale[e] = ldexp(1.0, ex);
+  for (int j = threadIdx.x; j < KH; j += blockDim.x)
+    store_split<PREC>(B0, B1, e * KH + j, ldexp(vals[j], -ex));
 }
 
 // ---------------------------------------------------------------------------
-// fused kernel: complex MFMA GEMM + per-pair marginalisation epilogue
+// fused kernel: complex MFMA contraction (d|h) + (h|h) phase coefficients,
+// then the per-pair marginalisation epilogue
 // ---------------------------------------------------------------------------
 struct FusedArgs {
   // bank operand (row-major [n_wf][K2])
@@ -464,11 +565,14 @@ struct FusedArgs {
   int64_t n_ext, n_ext_p;
   int64_t K2;
   int n_chunks;
-  // hh tables
-  const double2* H;      // [n_sub][n_det][NP]
-  const double* Hdiag;   // [n_sub][n_det][n_c]
-  const double2* Q;      // [n_ext][n_det][NP]
-  const double* R2;      // [n_ext][n_det][n_c]
+  // (h|h) operands ([n_sub][KH] and [n_ext_p][KH])
+  const void* Ah0;
+  const void* Ah1;
+  const double* ah_scale;
+  const void* Bh0;
+  const void* Bh1;
+  const double* bh_scale;
+  int KH;
   int n_det;
   ModeTables mt;
   // phases
@@ -510,8 +614,6 @@ struct Pol<kFP16X2> {
 template <>
 struct Pol<kBF16X2> : Pol<kFP16X2> {};
 
-constexpr int kMaxKP = 48;      // n_det * channel pairs staged per row / column
-
 template <int PREC>
 struct Tile {
   typedef Pol<PREC> P;
@@ -520,21 +622,18 @@ struct Tile {
   static constexpr int STAGE_ELEMS = (P::NA * TM + P::NB * TN) * P::PITCH;
   static constexpr int STAGE_BYTES = STAGE_ELEMS * (int)sizeof(typename P::T);
   static constexpr int ACC_T_BYTES = (PREC == kFP64) ? 8 : 4;
-  static constexpr int EPI_STRIDE = 2 * kMaxG + 1;
+  static constexpr int EPI_STRIDE = 2 * kMaxG + kMaxNR + 2;   // 17 (odd: spreads banks)
   static constexpr int EPI_BYTES = 4 * 256 * EPI_STRIDE * ACC_T_BYTES;
-  // epilogue tables after the accumulator blocks
-  static constexpr int HROW_OFF = EPI_BYTES;                       // float2 [kMaxKP][TM]
-  static constexpr int QCOL_OFF = HROW_OFF + TM * kMaxKP * 8;      // float2 [kMaxKP][TN]
-  static constexpr int ROWD_OFF = QCOL_OFF + TN * kMaxKP * 8;      // double [TM][3]
-  static constexpr int COLD_OFF = ROWD_OFF + TM * 3 * 8;           // double [TN][2]
-  static constexpr int LIST_OFF = COLD_OFF + TN * 2 * 8;           // uint16 [1024]
+  static constexpr int UNION_BYTES = (2 * STAGE_BYTES > EPI_BYTES) ? 2 * STAGE_BYTES : EPI_BYTES;
+  static constexpr int ROWD_OFF = (UNION_BYTES + 15) / 16 * 16;    // double [TM][4]
+  static constexpr int COLD_OFF = ROWD_OFF + TM * 4 * 8;           // double [TN][3]
+  static constexpr int LIST_OFF = COLD_OFF + TN * 3 * 8;           // uint16 [1024]
   static constexpr int CNT_OFF = LIST_OFF + 1024 * 2;              // int counter, u64 max
-  static constexpr int EPI_TOTAL = CNT_OFF + 16;
+  static constexpr int MAIN_BYTES = CNT_OFF + 16;
   static constexpr int PIECE_ELEMS = 16 / (int)sizeof(typename P::T);   // 16-byte pieces
   static constexpr int PIECES_PER_ROW = 32 / PIECE_ELEMS;
   static constexpr int PIECES = (P::NA * TM + P::NB * TN) * PIECES_PER_ROW;
   static constexpr int PIECES_PER_THREAD = PIECES / 256;
-  static constexpr int MAIN_BYTES = (2 * STAGE_BYTES > EPI_TOTAL) ? 2 * STAGE_BYTES : EPI_TOTAL;
 };
 
 template <int PREC>
@@ -587,36 +686,6 @@ struct EvAcc {
   }
 };
 
-// full evaluation of one pair: (h|h) coefficients, phase loop, cut,
-// distance marginalisation; returns ln p (-inf when nothing was kept)
-// (h|h) phase coefficients S_delta of one pair from per-row H and
-// per-column Q, element (k, p) at H[(k NP + p) * hs], Q[(k NP + p) * qs]
-template <typename T2, typename R>
-__device__ __forceinline__ void hh_coeffs(const ModeTables& mt, int n_det, const T2* H, int hs,
-                                          const T2* Q, int qs, R& S0, R* Sr, R* Si) {
-  S0 = 0;
-#pragma unroll
-  for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0; Si[d] = 0; }
-  for (int k = 0; k < n_det; ++k) {
-    const int base = k * mt.NP;
-    for (int p = mt.pstart[0]; p < mt.pstart[1]; ++p) {
-      T2 h = H[(base + p) * hs], q = Q[(base + p) * qs];
-      S0 += (R)mt.pf[p] * ((R)h.x * (R)q.x - (R)h.y * (R)q.y);
-    }
-#pragma unroll
-    for (int d = 1; d < kMaxND; ++d) {
-      R ar = 0, ai = 0;
-      for (int p = mt.pstart[d]; p < mt.pstart[d + 1]; ++p) {
-        T2 h = H[(base + p) * hs], q = Q[(base + p) * qs];
-        ar += (R)h.x * (R)q.x - (R)h.y * (R)q.y;
-        ai += (R)mt.ps[p] * ((R)h.x * (R)q.y + (R)h.y * (R)q.x);
-      }
-      Sr[d] += ar;
-      Si[d] += ai;
-    }
-  }
-}
-
 // full evaluation of one pair given X_g and the (h|h) coefficients: phase
 // loop, cut, distance marginalisation; returns ln p (-inf when nothing kept)
 template <int MODE>
@@ -650,17 +719,13 @@ __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie
     }
     // lnL^ML >= thr  <=>  dh > 0 and dh^2 >= 2 thr hh (no division)
     const bool keep = EVAL || thr_ml <= 0.0 || (dh > 0.0 && dh * dh >= thr2 * hh);
-    if (MODE == kPilot || !keep || EVAL) {
-      double ml = (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0;
-      mlmax = fmax(mlmax, ml);
-      if (MODE == kPilot) continue;
-      if (!keep) {
-        float x = (float)(lnw + ml - a.ln_nphi);
-        ev.drop.add(x + fabsf(x) * 1e-6f + 1e-5f);   // rounding margin keeps it a bound
-        continue;
-      }
-    } else {
-      mlmax = fmax(mlmax, (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0);
+    double ml = (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0;
+    mlmax = fmax(mlmax, ml);
+    if (MODE == kPilot) continue;
+    if (!keep) {
+      float x = (float)(lnw + ml - a.ln_nphi);
+      ev.drop.add(x + fabsf(x) * 1e-6f + 1e-5f);   // rounding margin keeps it a bound
+      continue;
     }
     double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, a.dist.geom, a.dist.ghx, a.dist.ghw);
     if (v > best) { best = v; o_best = o; }
@@ -684,6 +749,10 @@ __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie
 template <int PREC, int G, int MODE>
 __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   constexpr bool EVAL = MODE == kEval;
+  // (h|h) outputs: a single m group has S0 only; otherwise up to 7, padded
+  // to an even number of K blocks
+  constexpr int NRT = (G == 1) ? 1 : kMaxNR;
+  constexpr int NHB = (G == 1) ? 2 : kMaxNR + 1;
   typedef Pol<PREC> P;
   typedef Tile<PREC> TL;
   typedef typename P::T T;
@@ -724,8 +793,35 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   // phase table to LDS
   for (int t = tid; t < kMaxM * a.n_phi * 2; t += 256) lds_cs[t] = a.phase_cs[t];
 
+  // per-row / per-column scalars: issued first, stored after the first
+  // chunk's loads are in flight
+  double* rowd = (double*)(smem + TL::ROWD_OFF);
+  double* cold = (double*)(smem + TL::COLD_OFF);
+  uint16_t* list = (uint16_t*)(smem + TL::LIST_OFF);
+  int* list_n = (int*)(smem + TL::CNT_OFF);
+  unsigned long long* tile_lnp_max = (unsigned long long*)(smem + TL::CNT_OFF + 8);
+  double rv0 = 0.0, rv1 = 1.0, rv2 = 1.0, rv3 = -1.0;
+  if (tid < TM) {
+    int64_t ie = row0 + tid;
+    if (ie < a.n_sub) {
+      int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+      rv0 = a.ln_w_bank ? a.ln_w_bank[i] : 0.0;
+      rv1 = PREC == kFP64 ? 1.0 : a.row_scale[i];
+      rv2 = PREC == kFP64 ? 1.0 : a.ah_scale[ie];
+      rv3 = (double)i;
+    }
+  } else if (tid < TM + TN) {
+    int64_t e = col0 + (tid - TM);
+    if (e < a.n_ext) {
+      rv0 = a.ln_w_ext ? a.ln_w_ext[e] : 0.0;
+      rv1 = PREC == kFP64 ? 1.0 : a.col_scale[e];
+      rv2 = PREC == kFP64 ? 1.0 : a.bh_scale[e];
+    }
+  }
+
   // ---- K loop ----
-  Acc acc[G][P::BM][P::BN][2];
+  Acc acc[G][P::BM][P::BN][2];     // (d|h): per m group, re and im
+  Acc acch[NRT][P::BM][P::BN];     // (h|h) phase coefficients
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -734,39 +830,65 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       for (int bn = 0; bn < P::BN; ++bn)
 #pragma unroll
         for (int ri = 0; ri < 2; ++ri) acc[g][bm][bn][ri] = Acc{0, 0, 0, 0};
-
-  // global source rows for this thread's pieces
-  const void* Asrc[2] = {a.A0, a.A1};
-  const void* Bsrc[4] = {a.B0, a.B1, a.B2, a.B3};
-  uint4 stg[TL::PIECES_PER_THREAD];
-
-  // per-thread source pointers of its 16-byte pieces (chunk 0); a piece of
-  // a bank row past the subset reads nothing
-  const T* srcp[TL::PIECES_PER_THREAD];
 #pragma unroll
-  for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
-    int p = tid + 256 * q;
-    int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
-    srcp[q] = nullptr;
-    if (rowsel < P::NA * TM) {
-      int arr = rowsel / TM, r = rowsel % TM;
-      int64_t ie = row0 + r;
-      if (ie < a.n_sub) {
-        int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-        srcp[q] = (const T*)Asrc[arr] + i * a.K2 + piece * TL::PIECE_ELEMS;
+  for (int r = 0; r < NRT; ++r)
+#pragma unroll
+    for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < P::BN; ++bn) acch[r][bm][bn] = Acc{0, 0, 0, 0};
+
+  // per-thread source pointers of its 16-byte pieces for chunk 0 of the
+  // (d|h) operands (srcp) and block 0 of the (h|h) operands (srch); a piece
+  // past the subset, or of an operand array the (h|h) blocks do not use,
+  // reads nothing
+  const T* srcp[TL::PIECES_PER_THREAD];
+  const T* srch[TL::PIECES_PER_THREAD];
+  {
+    const void* Asrc[2] = {a.A0, a.A1};
+    const void* Bsrc[4] = {a.B0, a.B1, a.B2, a.B3};
+    const void* Ahs[2] = {a.Ah0, a.Ah1};
+    const void* Bhs[2] = {a.Bh0, a.Bh1};
+#pragma unroll
+    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
+      int p = tid + 256 * q;
+      int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
+      srcp[q] = nullptr;
+      srch[q] = nullptr;
+      if (rowsel < P::NA * TM) {
+        int arr = rowsel / TM, r = rowsel % TM;
+        int64_t ie = row0 + r;
+        if (ie < a.n_sub) {
+          int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+          srcp[q] = (const T*)Asrc[arr] + i * a.K2 + piece * TL::PIECE_ELEMS;
+          srch[q] = (const T*)Ahs[arr] + ie * a.KH + piece * TL::PIECE_ELEMS;
+        }
+      } else {
+        int rs = rowsel - P::NA * TM;
+        int arr = rs / TN, c = rs % TN;
+        srcp[q] = (const T*)Bsrc[arr] + (col0 + c) * a.K2 + piece * TL::PIECE_ELEMS;
+        if (arr < (PREC == kFP64 ? 1 : 2))
+          srch[q] = (const T*)Bhs[arr] + (col0 + c) * a.KH + piece * TL::PIECE_ELEMS;
       }
-    } else {
-      int rs = rowsel - P::NA * TM;
-      int arr = rs / TN, c = rs % TN;
-      srcp[q] = (const T*)Bsrc[arr] + (col0 + c) * a.K2 + piece * TL::PIECE_ELEMS;
     }
   }
-  auto load_chunk = [&](int ch) {
+  const int ndh = a.n_chunks;        // (d|h) chunks (even)
+  const int nch = ndh + NHB;         // then the (h|h) blocks
+  // two register stage sets: chunks ch+1 and ch+2 are in flight while ch is
+  // multiplied out of LDS
+  uint4 stA[TL::PIECES_PER_THREAD], stB[TL::PIECES_PER_THREAD];
+  auto load_into = [&](uint4* st, int ch) {
+    if (ch < ndh) {
 #pragma unroll
-    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q)
-      stg[q] = srcp[q] ? *(const uint4*)(srcp[q] + (int64_t)ch * 32) : make_uint4(0, 0, 0, 0);
+      for (int q = 0; q < TL::PIECES_PER_THREAD; ++q)
+        st[q] = srcp[q] ? *(const uint4*)(srcp[q] + (int64_t)ch * 32) : make_uint4(0, 0, 0, 0);
+    } else {
+      const int hb = ch - ndh;
+#pragma unroll
+      for (int q = 0; q < TL::PIECES_PER_THREAD; ++q)
+        st[q] = srch[q] ? *(const uint4*)(srch[q] + hb * 32) : make_uint4(0, 0, 0, 0);
+    }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_from = [&](const uint4* st, int buf) {
     T* base = stage + buf * TL::STAGE_ELEMS;
 #pragma unroll
     for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
@@ -774,54 +896,100 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
       T* dst = base + rowsel * PITCH + piece * TL::PIECE_ELEMS;
       if constexpr (PREC == kFP64) {
-        // 8-byte aligned rows (odd pitch): two 8-byte stores
         uint2* d2 = (uint2*)dst;
-        d2[0] = make_uint2(stg[q].x, stg[q].y);
-        d2[1] = make_uint2(stg[q].z, stg[q].w);
+        d2[0] = make_uint2(st[q].x, st[q].y);
+        d2[1] = make_uint2(st[q].z, st[q].w);
       } else {
-        *(uint4*)dst = stg[q];
+        *(uint4*)dst = st[q];
       }
     }
   };
-
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
-  int ch = 0;
+  // (d|h) chunk: complex product, 3 split products per real product
+  auto compute_dh = [&](int buf, auto gi) {
+    constexpr int g = decltype(gi)::value;
+    const T* base = stage + buf * TL::STAGE_ELEMS;
+    const T* As = base;
+    const T* Bs = base + P::NA * TM * PITCH;
+    if constexpr (PREC == kFP64) {
+      const double* Ad = (const double*)As;
+      const double* Bd = (const double*)Bs;
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int gend = a.mt.gk0[g + 1];
-    for (; ch < gend; ++ch) {
-      const bool more = ch + 1 < a.n_chunks;
-      if (more) load_chunk(ch + 1);
-      const T* base = stage + (ch & 1) * TL::STAGE_ELEMS;
+      for (int s8 = 0; s8 < 8; ++s8) {
+        double av[P::BM], brv[P::BN], biv[P::BN];
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+          av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
+          brv[bn] = Bd[cc * PITCH + 4 * s8 + (lane >> 4)];
+          biv[bn] = Bd[(TN + cc) * PITCH + 4 * s8 + (lane >> 4)];
+        }
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) {
+            acc[g][bm][bn][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], brv[bn], acc[g][bm][bn][0], 0, 0, 0);
+            acc[g][bm][bn][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], biv[bn], acc[g][bm][bn][1], 0, 0, 0);
+          }
+      }
+    } else {
+      uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
+      const int koff = 8 * (lane >> 4);
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm) {
+        int rr = wm * 16 * P::BM + bm * 16 + (lane & 15);
+        ah[bm] = *(const uint4*)(As + rr * PITCH + koff);
+        al[bm] = *(const uint4*)(As + (TM + rr) * PITCH + koff);
+      }
+#pragma unroll
+      for (int bn = 0; bn < P::BN; ++bn) {
+        int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
+        brh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
+        brl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
+        bih[bn] = *(const uint4*)(Bs + (2 * TN + cc) * PITCH + koff);
+        bil[bn] = *(const uint4*)(Bs + (3 * TN + cc) * PITCH + koff);
+      }
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          mma<PREC>(acc[g][bm][bn][0], al[bm], brh[bn]);
+          mma<PREC>(acc[g][bm][bn][0], ah[bm], brl[bn]);
+          mma<PREC>(acc[g][bm][bn][0], ah[bm], brh[bn]);
+          mma<PREC>(acc[g][bm][bn][1], al[bm], bih[bn]);
+          mma<PREC>(acc[g][bm][bn][1], ah[bm], bil[bn]);
+          mma<PREC>(acc[g][bm][bn][1], ah[bm], bih[bn]);
+        }
+    }
+  };
+  // (h|h) block r: real product of the row and column (h|h) operands
+  auto compute_hh = [&](int buf, auto ri) {
+    constexpr int r = decltype(ri)::value;
+    if constexpr (r < NRT) {
+      const T* base = stage + buf * TL::STAGE_ELEMS;
       const T* As = base;
       const T* Bs = base + P::NA * TM * PITCH;
       if constexpr (PREC == kFP64) {
         const double* Ad = (const double*)As;
         const double* Bd = (const double*)Bs;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          double av[P::BM], brv[P::BN], biv[P::BN];
+        for (int s8 = 0; s8 < 8; ++s8) {
+          double av[P::BM], bv[P::BN];
 #pragma unroll
           for (int bm = 0; bm < P::BM; ++bm)
-            av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s + (lane >> 4)];
+            av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
 #pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) {
-            int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-            brv[bn] = Bd[cc * PITCH + 4 * s + (lane >> 4)];
-            biv[bn] = Bd[(TN + cc) * PITCH + 4 * s + (lane >> 4)];
-          }
+          for (int bn = 0; bn < P::BN; ++bn)
+            bv[bn] = Bd[(wn * 16 * P::BN + bn * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
 #pragma unroll
           for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
-            for (int bn = 0; bn < P::BN; ++bn) {
-              acc[g][bm][bn][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], brv[bn], acc[g][bm][bn][0], 0, 0, 0);
-              acc[g][bm][bn][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], biv[bn], acc[g][bm][bn][1], 0, 0, 0);
-            }
+            for (int bn = 0; bn < P::BN; ++bn)
+              acch[r][bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], bv[bn], acch[r][bm][bn], 0, 0, 0);
         }
       } else {
-        uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
+        uint4 ah[P::BM], al[P::BM], bh[P::BN], bl[P::BN];
         const int koff = 8 * (lane >> 4);
 #pragma unroll
         for (int bm = 0; bm < P::BM; ++bm) {
@@ -832,75 +1000,64 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
 #pragma unroll
         for (int bn = 0; bn < P::BN; ++bn) {
           int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-          brh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
-          brl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
-          bih[bn] = *(const uint4*)(Bs + (2 * TN + cc) * PITCH + koff);
-          bil[bn] = *(const uint4*)(Bs + (3 * TN + cc) * PITCH + koff);
+          bh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
+          bl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
         }
 #pragma unroll
         for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
           for (int bn = 0; bn < P::BN; ++bn) {
-            mma<PREC>(acc[g][bm][bn][0], al[bm], brh[bn]);
-            mma<PREC>(acc[g][bm][bn][0], ah[bm], brl[bn]);
-            mma<PREC>(acc[g][bm][bn][0], ah[bm], brh[bn]);
-            mma<PREC>(acc[g][bm][bn][1], al[bm], bih[bn]);
-            mma<PREC>(acc[g][bm][bn][1], ah[bm], bil[bn]);
-            mma<PREC>(acc[g][bm][bn][1], ah[bm], bih[bn]);
+            mma<PREC>(acch[r][bm][bn], al[bm], bh[bn]);
+            mma<PREC>(acch[r][bm][bn], ah[bm], bl[bn]);
+            mma<PREC>(acch[r][bm][bn], ah[bm], bh[bn]);
           }
       }
-      if (more) store_chunk((ch + 1) & 1);
-      __syncthreads();
     }
-  }
+  };
 
-  // ---- epilogue ----
-  // E0: per-row / per-column tables of the tile to LDS
-  typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
-  float2* hrow = (float2*)(smem + TL::HROW_OFF);
-  float2* qcol = (float2*)(smem + TL::QCOL_OFF);
-  double* rowd = (double*)(smem + TL::ROWD_OFF);
-  double* cold = (double*)(smem + TL::COLD_OFF);
-  uint16_t* list = (uint16_t*)(smem + TL::LIST_OFF);
-  int* list_n = (int*)(smem + TL::CNT_OFF);
-  unsigned long long* tile_lnp_max = (unsigned long long*)(smem + TL::CNT_OFF + 8);
-  const int KP = a.n_det * a.mt.NP;
-  for (int t = tid; t < TM; t += 256) {
-    int64_t ie = row0 + t;
-    double lw = 0.0, sc = 1.0, ii = -1.0;
-    if (ie < a.n_sub) {
-      int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-      lw = a.ln_w_bank ? a.ln_w_bank[i] : 0.0;
-      sc = PREC == kFP64 ? 1.0 : a.row_scale[i];
-      ii = (double)i;
-    }
-    rowd[t * 3] = lw; rowd[t * 3 + 1] = sc; rowd[t * 3 + 2] = ii;
-  }
-  for (int t = tid; t < TN; t += 256) {
-    int64_t e = col0 + t;
-    double lw = 0.0, sc = 1.0;
-    if (e < a.n_ext) {
-      lw = a.ln_w_ext ? a.ln_w_ext[e] : 0.0;
-      sc = PREC == kFP64 ? 1.0 : a.col_scale[e];
-    }
-    cold[t * 2] = lw; cold[t * 2 + 1] = sc;
-  }
-  for (int r = wave; r < TM; r += 4) {
-    int64_t ie = row0 + r;
-    for (int q = lane; q < KP; q += 64) {
-      double2 v = ie < a.n_sub ? a.H[ie * KP + q] : make_double2(0.0, 0.0);
-      hrow[q * TM + r] = make_float2((float)v.x, (float)v.y);
-    }
-  }
-  for (int c = wave; c < TN; c += 4) {
-    int64_t e = col0 + c;
-    for (int q = lane; q < KP; q += 64) {
-      double2 v = e < a.n_ext ? a.Q[e * KP + q] : make_double2(0.0, 0.0);
-      qcol[q * TN + c] = make_float2((float)v.x, (float)v.y);
-    }
+  load_into(stA, 0);
+  load_into(stB, 1);
+  if (tid < TM) {
+    rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
+  } else if (tid < TM + TN) {
+    cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
   }
   if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
+  store_from(stA, 0);
+  __syncthreads();
+  // every group spans an even number of chunks (bins padded to 32), so the
+  // two-step pipeline never straddles a group and each step's accumulator
+  // set is static; the (h|h) blocks follow in the same pipeline
+  int ch = 0;
+  static_for<G>([&](auto gi) {
+    constexpr int g = decltype(gi)::value;
+    const int gend = a.mt.gk0[g + 1];
+    for (; ch < gend; ch += 2) {
+      if (ch + 2 < nch) load_into(stA, ch + 2);
+      compute_dh(0, gi);
+      store_from(stB, 1);
+      __syncthreads();
+      if (ch + 3 < nch) load_into(stB, ch + 3);
+      compute_dh(1, gi);
+      store_from(stA, 0);
+      __syncthreads();
+    }
+  });
+  static_for<NHB / 2>([&](auto hi) {
+    constexpr int r = 2 * decltype(hi)::value;
+    const int c0 = ndh + r;
+    if (c0 + 2 < nch) load_into(stA, c0 + 2);
+    compute_hh(0, std::integral_constant<int, r>{});
+    store_from(stB, 1);
+    __syncthreads();
+    if (c0 + 3 < nch) load_into(stB, c0 + 3);
+    compute_hh(1, std::integral_constant<int, r + 1>{});
+    if (c0 + 2 < nch) store_from(stA, 0);
+    __syncthreads();
+  });
 
+  // ---- epilogue ----
+  typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
   double thr_ml = -INFINITY, thr_topk_glob = -INFINITY;
   if (MODE == kEvidence) {
     if (a.cut_delta > 0.0) thr_ml = __longlong_as_double(a.state[0]) - a.cut_delta;
@@ -908,10 +1065,12 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   }
   const bool use_bound = MODE == kEvidence && thr_ml > 0.0;
   const float thr_f = (float)thr_ml;
+  const int ND = a.mt.ND;
   EvAcc ev;
   ev.init();
   AT* epi_all = (AT*)smem;
   AT* epi = epi_all + wave * 256 * TL::EPI_STRIDE;
+  constexpr int XO = 0, SO = 2 * G;   // offsets of X and S in a pair's record
 
 #pragma unroll 1
   for (int blk = 0; blk < P::BM * P::BN; ++blk) {
@@ -926,9 +1085,11 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
         int q = rr * 16 + (lane & 15);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          epi[q * TL::EPI_STRIDE + 2 * g] = (AT)acc[g][bm][bn][0][r];
-          epi[q * TL::EPI_STRIDE + 2 * g + 1] = (AT)acc[g][bm][bn][1][r];
+          epi[q * TL::EPI_STRIDE + XO + 2 * g] = (AT)acc[g][bm][bn][0][r];
+          epi[q * TL::EPI_STRIDE + XO + 2 * g + 1] = (AT)acc[g][bm][bn][1][r];
         }
+#pragma unroll
+        for (int s = 0; s < NRT; ++s) epi[q * TL::EPI_STRIDE + SO + s] = (AT)acch[s][bm][bn][r];
       }
     }
     __syncthreads();
@@ -942,39 +1103,31 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       ev.n_pairs += 1.0;
       bool survive = true;
       if (use_bound) {
-        float sc = (float)(rowd[tr * 3 + 1] * cold[tc * 2 + 1]);
+        const AT* x = epi + q * TL::EPI_STRIDE;
+        float sx = (float)(rowd[tr * 4 + 1] * cold[tc * 3 + 1]);
+        float sh = (float)(rowd[tr * 4 + 2] * cold[tc * 3 + 2]);
         float U = 0.f;
+#pragma unroll
         for (int g = 0; g < G; ++g) {
-          float xr = (float)epi[q * TL::EPI_STRIDE + 2 * g], xi = (float)epi[q * TL::EPI_STRIDE + 2 * g + 1];
+          float xr = (float)x[XO + 2 * g], xi = (float)x[XO + 2 * g + 1];
           U += sqrtf(xr * xr + xi * xi);
         }
-        U *= fabsf(sc);
-        // two lower bounds of hh_o valid for every phase: S0 - 2 sum |S_delta|
-        // and (2 max_c n_c - sum_c n_c)^2 with n_c^2 = sum_k H_kcc Q_kcc
-        float S0f, Srf[kMaxND], Sif[kMaxND];
-        hh_coeffs<float2, float>(a.mt, a.n_det, hrow + tr, TM, qcol + tc, TN, S0f, Srf, Sif);
-        float lo1 = S0f;
-        for (int d = 1; d < a.mt.ND; ++d) lo1 -= 2.f * sqrtf(Srf[d] * Srf[d] + Sif[d] * Sif[d]);
-        float nsum = 0.f, nmax = 0.f;
-        for (int c = 0; c < a.mt.n_c; ++c) {
-          float s2 = 0.f;
-          for (int k = 0; k < a.n_det; ++k) {
-            int pq = k * a.mt.NP + a.mt.pdiag[c];
-            s2 += hrow[pq * TM + tr].x * qcol[pq * TN + tc].x;
-          }
-          float nc = sqrtf(fmaxf(s2, 0.f));
-          nsum += nc;
-          nmax = fmaxf(nmax, nc);
+        U *= fabsf(sx);
+        // hh_o >= S0 - 2 sum_d |S_d| for every phase
+        float lo = (float)x[SO];
+#pragma unroll
+        for (int d = 1; d < (NRT + 1) / 2; ++d) {
+          if (d >= ND) break;
+          float sr = (float)x[SO + 2 * d - 1], si = (float)x[SO + 2 * d];
+          lo -= 2.f * sqrtf(sr * sr + si * si);
         }
-        float lo2 = 2.f * nmax - nsum;
-        lo2 = lo2 > 0.f ? lo2 * lo2 : 0.f;
-        float hlo = fmaxf(lo1, lo2) * 0.999f;     // margin for FP32 rounding
-        // lnL^ML_o <= U^2 / (2 hlo) for every phase
-        if (hlo > 0.f) {
-          float bound = U * U / (2.f * hlo) * 1.001f + 1e-3f;
+        lo *= sh * 0.999f;                         // margin for rounding
+        // lnL^ML_o <= U^2 / (2 lo) for every phase
+        if (lo > 0.f) {
+          float bound = U * U / (2.f * lo) * 1.001f + 1e-3f;
           if (bound < thr_f) {
             survive = false;
-            float lw = (float)(rowd[tr * 3] + cold[tc * 2]);
+            float lw = (float)(rowd[tr * 4] + cold[tc * 3]);
             ev.drop.add(lw + bound);
             ev.max_bound = fmaxf(ev.max_bound, lw + bound);
             ev.n_bounded += 1.0;
@@ -996,16 +1149,21 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       int tc = wn_ * 16 * P::BN + bn * 16 + (q & 15);
       int64_t ie = row0 + tr, e = col0 + tc;
       const AT* xq = epi_all + (w * 256 + q) * TL::EPI_STRIDE;
-      double sc = rowd[tr * 3 + 1] * cold[tc * 2 + 1];
+      double sx = rowd[tr * 4 + 1] * cold[tc * 3 + 1];
+      double sh = rowd[tr * 4 + 2] * cold[tc * 3 + 2];
       double2 X[G];
 #pragma unroll
-      for (int g = 0; g < G; ++g) X[g] = make_double2(sc * (double)xq[2 * g], sc * (double)xq[2 * g + 1]);
-      double lnw = rowd[tr * 3] + cold[tc * 2];
-      double S0, Sr[kMaxND], Si[kMaxND];
-      if (PREC == kFP64)
-        hh_coeffs<double2, double>(a.mt, a.n_det, a.H + ie * KP, 1, a.Q + e * KP, 1, S0, Sr, Si);
-      else
-        hh_coeffs<float2, double>(a.mt, a.n_det, hrow + tr, TM, qcol + tc, TN, S0, Sr, Si);
+      for (int g = 0; g < G; ++g)
+        X[g] = make_double2(sx * (double)xq[XO + 2 * g], sx * (double)xq[XO + 2 * g + 1]);
+      double S0 = sh * (double)xq[SO], Sr[kMaxND], Si[kMaxND];
+#pragma unroll
+      for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0.0; Si[d] = 0.0; }
+#pragma unroll
+      for (int d = 1; d < (NRT + 1) / 2; ++d) {
+        Sr[d] = sh * (double)xq[SO + 2 * d - 1];
+        Si[d] = sh * (double)xq[SO + 2 * d];
+      }
+      double lnw = rowd[tr * 4] + cold[tc * 3];
       int ob = 0;
       double lnp = pair_full<MODE>(a, lds_cs, ie, e, X, S0, Sr, Si, lnw, thr_ml, ev, ob);
       if (MODE == kEvidence && lnp > -INFINITY) {
@@ -1018,7 +1176,7 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
           if ((int64_t)slot < a.cand_cap) {
             double* cd = a.cand + 4 * slot;
             cd[0] = lnp;
-            cd[1] = rowd[tr * 3 + 2];
+            cd[1] = rowd[tr * 4 + 3];
             cd[2] = (double)e;
             cd[3] = (double)ob;
           }
