@@ -99,6 +99,7 @@ struct dotpe_event {
   double* cand = nullptr;
   int64_t cand_cap = 0;
   double* final_out = nullptr;
+  double* final_blk = nullptr;
   hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};
   std::vector<void*> allocs;
   uint64_t bytes = 0;
@@ -220,7 +221,7 @@ int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
 
 // (h|h) term codes: output r < NR owns K block r (32 slots); see kernels.h
 int build_hh_terms(const ModeTables& mt, int n_det, std::vector<int>* terms, int* KH) {
-  const int nhb = mt.G == 1 ? 2 : kMaxNR + 1;
+  const int nhb = mt.G == 1 ? 4 : kMaxNR + 1;
   *KH = nhb * 32;
   terms->assign(*KH, 0);
   const int NR = 2 * mt.ND - 1;
@@ -477,7 +478,7 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
   bk->n_wf = d->n_wf;
   bk->n_c = d->n_modes;
   bk->n_b = d->n_bins;
-  bk->n_bp = (int)round_up(d->n_bins, 2 * kChunk);   // even chunk count per channel
+  bk->n_bp = (int)round_up(d->n_bins, 4 * kChunk);   // chunk count per channel divisible by 4
   bk->K2 = (int64_t)bk->n_c * bk->n_bp * 2;
   bk->prec = d->precision;
   int rc = build_modes(d, &bk->mt, bk->n_bp);
@@ -664,7 +665,7 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
   };
   auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &ev->allocs, &ev->bytes); };
   const size_t esz = bk->prec == kFP64 ? 8 : 2;
-  const int nB = bk->prec == kFP64 ? 2 : 4;
+  const int nB = 2;   // FP64: B_re, B_im; split precisions: B_re hi, lo
   for (int q = 0; q < nB; ++q)
     if ((rc = alloc(&ev->B[q], (size_t)ev->n_ext_p * bk->K2 * esz))) return cleanup(rc);
   if (bk->prec != kFP64 && (rc = alloc((void**)&ev->col_scale, ne * 8))) return cleanup(rc);
@@ -826,7 +827,10 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
     if ((rc = dev_alloc(ctx, (void**)&ev->partials, (size_t)a.n_tiles * kNPart * 8, &ev->allocs,
                         &ev->bytes)))
       return rc;
-    int64_t cap = std::max<int64_t>(1 << 16, 16 * (int64_t)ev->top_k);
+    if ((rc = dev_alloc(ctx, (void**)&ev->final_blk,
+                        (size_t)((a.n_tiles + 4095) / 4096) * kNPart * 8, &ev->allocs, &ev->bytes)))
+      return rc;
+    int64_t cap = std::max<int64_t>(1 << 20, 16 * (int64_t)ev->top_k);
     if ((rc = dev_alloc(ctx, (void**)&ev->cand, (size_t)cap * 32, &ev->allocs, &ev->bytes)))
       return rc;
     ev->cand_cap = cap;
@@ -844,6 +848,7 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   HIP_OK(hipEventRecord(ev->ev_t[0], s));
   if (ev->cut_delta > 0.0 && a.n_tiles_m > 1) {
     // pilot: max lnL^ML over every 64th row of tiles seeds the cut threshold
+    // (the main pass raises it further as tiles complete)
     a.pilot_stride = 64;
     int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
     if ((rc = launch_fused<kPilot>(ev->bank->prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
@@ -852,7 +857,15 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   int64_t grid = round_up(a.n_tiles, 8);
   if ((rc = launch_fused<kEvidence>(ev->bank->prec, a, grid, s))) return rc;
   HIP_OK(hipEventRecord(ev->ev_t[2], s));
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ev->partials, a.n_tiles, ev->final_out);
+  {
+    // fixed-order two-level reduction of the tile partials
+    const int64_t per = 4096;
+    const int64_t nblk = (a.n_tiles + per - 1) / per;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)nblk), dim3(256), 0, s, ev->partials, a.n_tiles,
+                       per, ev->final_blk);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ev->final_blk, nblk, nblk,
+                       ev->final_out);
+  }
   HIP_OK(hipGetLastError());
   double fo[kNPart];
   uint64_t st[3];

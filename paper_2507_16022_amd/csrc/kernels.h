@@ -329,6 +329,21 @@ __global__ void k_build_B(int64_t n_ext, int n_det, int n_c, int n_b, int n_bp,
   Btmp[idx] = acc;
 }
 
+template <int PREC>
+__device__ __forceinline__ void store_split(void* A0, void* A1, int64_t o, double v) {
+  if (PREC == kFP64) {
+    ((double*)A0)[o] = v;
+  } else if (PREC == kFP16X2) {
+    _Float16 h = (_Float16)v;
+    ((_Float16*)A0)[o] = h;
+    ((_Float16*)A1)[o] = (_Float16)(v - (double)h);
+  } else {
+    __bf16 h = (__bf16)(float)v;
+    ((__bf16*)A0)[o] = h;
+    ((__bf16*)A1)[o] = (__bf16)(float)(v - (double)(float)h);
+  }
+}
+
 // extrinsic operand rows: Bre = [Br | -Bi], Bim = [Bi | Br] per chunk,
 // scaled by 2^-g_e in the split precisions; rows e >= n_ext are zero
 template <int PREC>
@@ -377,22 +392,9 @@ __global__ void k_convert_B(int64_t n_ext, int64_t n_ext_p, int n_c, int n_bp,
       double* Bim = (double*)B1;
       Bre[o] = re_lo_part[0]; Bre[o + 16] = re_lo_part[1];
       Bim[o] = im_lo_part[0]; Bim[o + 16] = im_lo_part[1];
-    } else if (PREC == kFP16X2) {
-      _Float16 *Brh = (_Float16*)B0, *Brl = (_Float16*)B1, *Bih = (_Float16*)B2, *Bil = (_Float16*)B3;
-      for (int q = 0; q < 2; ++q) {
-        _Float16 h1 = (_Float16)re_lo_part[q], h2 = (_Float16)im_lo_part[q];
-        Brh[o + 16 * q] = h1; Brl[o + 16 * q] = (_Float16)(re_lo_part[q] - (double)h1);
-        Bih[o + 16 * q] = h2; Bil[o + 16 * q] = (_Float16)(im_lo_part[q] - (double)h2);
-      }
     } else {
-      __bf16 *Brh = (__bf16*)B0, *Brl = (__bf16*)B1, *Bih = (__bf16*)B2, *Bil = (__bf16*)B3;
-      for (int q = 0; q < 2; ++q) {
-        __bf16 h1 = (__bf16)(float)re_lo_part[q], h2 = (__bf16)(float)im_lo_part[q];
-        Brh[o + 16 * q] = h1;
-        Brl[o + 16 * q] = (__bf16)(float)(re_lo_part[q] - (double)(float)h1);
-        Bih[o + 16 * q] = h2;
-        Bil[o + 16 * q] = (__bf16)(float)(im_lo_part[q] - (double)(float)h2);
-      }
+      // split precisions: B_re only (B_im is formed in registers)
+      for (int q = 0; q < 2; ++q) store_split<PREC>(B0, B1, o + 16 * q, re_lo_part[q]);
     }
   }
 }
@@ -434,21 +436,6 @@ __device__ __forceinline__ double term_value(int code, const double2* X, int NP,
     x *= ci == 1 ? 1.0 : ci == 2 ? -1.0 : ci == 3 ? 2.0 : ci == 4 ? -2.0 : 0.0;
   }
   return x;
-}
-
-template <int PREC>
-__device__ __forceinline__ void store_split(void* A0, void* A1, int64_t o, double v) {
-  if (PREC == kFP64) {
-    ((double*)A0)[o] = v;
-  } else if (PREC == kFP16X2) {
-    _Float16 h = (_Float16)v;
-    ((_Float16*)A0)[o] = h;
-    ((_Float16*)A1)[o] = (_Float16)(v - (double)h);
-  } else {
-    __bf16 h = (__bf16)(float)v;
-    ((__bf16*)A0)[o] = h;
-    ((__bf16*)A1)[o] = (__bf16)(float)(v - (double)(float)h);
-  }
 }
 
 // per-waveform (h|h) sums H_ikcc' = sum_b w_kb h_icb conj(h_ic'b) for the
@@ -609,7 +596,8 @@ template <>
 struct Pol<kFP16X2> {
   typedef uint16_t T;
   typedef f32x4 Acc;
-  static constexpr int NA = 2, NB = 4, PITCH = 40, BM = 2, BN = 2;
+  // B_im = [Bi | Br] is formed in registers from B_re = [Br | -Bi]
+  static constexpr int NA = 2, NB = 2, PITCH = 40, BM = 2, BN = 2;
 };
 template <>
 struct Pol<kBF16X2> : Pol<kFP16X2> {};
@@ -635,6 +623,22 @@ struct Tile {
   static constexpr int PIECES = (P::NA * TM + P::NB * TN) * PIECES_PER_ROW;
   static constexpr int PIECES_PER_THREAD = PIECES / 256;
 };
+
+// B_im fragment from the B_re fragment of a 16x16x32 operand: lanes 0-31
+// hold K 0-15 (Br), lanes 32-63 hold K 16-31 (-Bi); the result holds Bi in
+// lanes 0-31 and Br in lanes 32-63 (swap halves, negate the new lower half)
+__device__ __forceinline__ uint4 bim_from_bre(const uint4& x, int lane) {
+  const bool lo = lane < 32;
+  uint4 y;
+  unsigned in[4] = {x.x, x.y, x.z, x.w}, out[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    auto r = __builtin_amdgcn_permlane32_swap(in[k], in[k], false, false);
+    out[k] = lo ? (r[1] ^ 0x80008000u) : r[0];
+  }
+  y.x = out[0]; y.y = out[1]; y.z = out[2]; y.w = out[3];
+  return y;
+}
 
 template <int PREC>
 __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a, const uint4& b) {
@@ -752,7 +756,10 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   // (h|h) outputs: a single m group has S0 only; otherwise up to 7, padded
   // to an even number of K blocks
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;
-  constexpr int NHB = (G == 1) ? 2 : kMaxNR + 1;
+  constexpr int NHB = (G == 1) ? 4 : kMaxNR + 1;
+  // register stage sets: loads run R chunks ahead (FP64 pieces are twice as
+  // many per thread, so it keeps two sets to stay within the register file)
+  constexpr int R = (PREC == kFP64) ? 2 : 4;
   typedef Pol<PREC> P;
   typedef Tile<PREC> TL;
   typedef typename P::T T;
@@ -830,65 +837,65 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       for (int bn = 0; bn < P::BN; ++bn)
 #pragma unroll
         for (int ri = 0; ri < 2; ++ri) acc[g][bm][bn][ri] = Acc{0, 0, 0, 0};
-#pragma unroll
-  for (int r = 0; r < NRT; ++r)
-#pragma unroll
-    for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < P::BN; ++bn) acch[r][bm][bn] = Acc{0, 0, 0, 0};
 
-  // per-thread source pointers of its 16-byte pieces for chunk 0 of the
-  // (d|h) operands (srcp) and block 0 of the (h|h) operands (srch); a piece
-  // past the subset, or of an operand array the (h|h) blocks do not use,
-  // reads nothing
-  const T* srcp[TL::PIECES_PER_THREAD];
-  const T* srch[TL::PIECES_PER_THREAD];
+  // per-thread source addresses of its 16-byte pieces for chunk 0 of the
+  // (d|h) operands (srcp) and block 0 of the (h|h) operands (srch), in the
+  // global address space so that the loads wait on the vector-memory counter
+  // only.  Rows past the subset re-read the last row (their pairs are never
+  // used) and the FP64 B_im slot of an (h|h) block re-reads B_re (the block
+  // does not use it), so no load is predicated.
+  typedef __attribute__((address_space(1))) const unsigned char gbyte;
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(1))) const u32x4 gu4;
+  gbyte* srcp[TL::PIECES_PER_THREAD];
+  gbyte* srch[TL::PIECES_PER_THREAD];
   {
-    const void* Asrc[2] = {a.A0, a.A1};
-    const void* Bsrc[4] = {a.B0, a.B1, a.B2, a.B3};
-    const void* Ahs[2] = {a.Ah0, a.Ah1};
-    const void* Bhs[2] = {a.Bh0, a.Bh1};
+    constexpr int ES = (int)sizeof(T);
 #pragma unroll
     for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
       int p = tid + 256 * q;
       int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
-      srcp[q] = nullptr;
-      srch[q] = nullptr;
       if (rowsel < P::NA * TM) {
         int arr = rowsel / TM, r = rowsel % TM;
-        int64_t ie = row0 + r;
-        if (ie < a.n_sub) {
-          int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-          srcp[q] = (const T*)Asrc[arr] + i * a.K2 + piece * TL::PIECE_ELEMS;
-          srch[q] = (const T*)Ahs[arr] + ie * a.KH + piece * TL::PIECE_ELEMS;
-        }
+        int64_t ie = min(row0 + r, a.n_sub - 1);
+        int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+        srcp[q] = (gbyte*)(arr == 0 ? a.A0 : a.A1) + (i * a.K2 + piece * TL::PIECE_ELEMS) * ES;
+        srch[q] = (gbyte*)(arr == 0 ? a.Ah0 : a.Ah1) + (ie * a.KH + piece * TL::PIECE_ELEMS) * ES;
       } else {
         int rs = rowsel - P::NA * TM;
         int arr = rs / TN, c = rs % TN;
-        srcp[q] = (const T*)Bsrc[arr] + (col0 + c) * a.K2 + piece * TL::PIECE_ELEMS;
-        if (arr < (PREC == kFP64 ? 1 : 2))
-          srch[q] = (const T*)Bhs[arr] + (col0 + c) * a.KH + piece * TL::PIECE_ELEMS;
+        srcp[q] = (gbyte*)(arr == 0 ? a.B0 : a.B1) + ((col0 + c) * a.K2 + piece * TL::PIECE_ELEMS) * ES;
+        const bool h1 = PREC != kFP64 && arr == 1;
+        srch[q] = (gbyte*)(h1 ? a.Bh1 : a.Bh0) + ((col0 + c) * a.KH + piece * TL::PIECE_ELEMS) * ES;
       }
     }
   }
   const int ndh = a.n_chunks;        // (d|h) chunks (even)
   const int nch = ndh + NHB;         // then the (h|h) blocks
-  // two register stage sets: chunks ch+1 and ch+2 are in flight while ch is
-  // multiplied out of LDS
-  uint4 stA[TL::PIECES_PER_THREAD], stB[TL::PIECES_PER_THREAD];
-  auto load_into = [&](uint4* st, int ch) {
-    if (ch < ndh) {
-#pragma unroll
-      for (int q = 0; q < TL::PIECES_PER_THREAD; ++q)
-        st[q] = srcp[q] ? *(const uint4*)(srcp[q] + (int64_t)ch * 32) : make_uint4(0, 0, 0, 0);
-    } else {
-      const int hb = ch - ndh;
-#pragma unroll
-      for (int q = 0; q < TL::PIECES_PER_THREAD; ++q)
-        st[q] = srch[q] ? *(const uint4*)(srch[q] + hb * 32) : make_uint4(0, 0, 0, 0);
-    }
+  // R register stage sets: while chunk j is multiplied out of LDS, chunks
+  // j+1 .. j+R are in flight (set j mod R holds chunk j).  Separate arrays
+  // picked at compile time, and load sites that are each statically a (d|h)
+  // or an (h|h) load, keep the sets and the address arrays in registers.
+  u32x4 st0[TL::PIECES_PER_THREAD], st1[TL::PIECES_PER_THREAD];
+  u32x4 st2[TL::PIECES_PER_THREAD], st3[TL::PIECES_PER_THREAD];
+  auto set = [&](auto slot) -> u32x4* {
+    constexpr int k = decltype(slot)::value % R;
+    if constexpr (k == 0) return st0;
+    else if constexpr (k == 1) return st1;
+    else if constexpr (k == 2) return st2;
+    else return st3;
   };
-  auto store_from = [&](const uint4* st, int buf) {
+  auto load_dh = [&](u32x4* stq, int ch) {
+    const int64_t off = (int64_t)ch * 32 * sizeof(T);
+#pragma unroll
+    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) stq[q] = *(gu4*)(srcp[q] + off);
+  };
+  auto load_hh = [&](u32x4* stq, int hb) {
+    const int off = hb * 32 * (int)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) stq[q] = *(gu4*)(srch[q] + off);
+  };
+  auto store_from = [&](const u32x4* st, int buf) {
     T* base = stage + buf * TL::STAGE_ELEMS;
 #pragma unroll
     for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
@@ -896,11 +903,12 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
       T* dst = base + rowsel * PITCH + piece * TL::PIECE_ELEMS;
       if constexpr (PREC == kFP64) {
-        uint2* d2 = (uint2*)dst;
-        d2[0] = make_uint2(st[q].x, st[q].y);
-        d2[1] = make_uint2(st[q].z, st[q].w);
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        u32x2* d2 = (u32x2*)dst;
+        d2[0] = st[q].xy;
+        d2[1] = st[q].zw;
       } else {
-        *(uint4*)dst = st[q];
+        *(u32x4*)dst = st[q];
       }
     }
   };
@@ -947,18 +955,30 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
         int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
         brh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
         brl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
-        bih[bn] = *(const uint4*)(Bs + (2 * TN + cc) * PITCH + koff);
-        bil[bn] = *(const uint4*)(Bs + (3 * TN + cc) * PITCH + koff);
+        bih[bn] = bim_from_bre(brh[bn], lane);
+        bil[bn] = bim_from_bre(brl[bn], lane);
       }
+      // issue order: the three split products of one accumulator are
+      // separated by the products of the 2 x BM x BN independent ones
 #pragma unroll
       for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < P::BN; ++bn) {
           mma<PREC>(acc[g][bm][bn][0], al[bm], brh[bn]);
-          mma<PREC>(acc[g][bm][bn][0], ah[bm], brl[bn]);
-          mma<PREC>(acc[g][bm][bn][0], ah[bm], brh[bn]);
           mma<PREC>(acc[g][bm][bn][1], al[bm], bih[bn]);
+        }
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          mma<PREC>(acc[g][bm][bn][0], ah[bm], brl[bn]);
           mma<PREC>(acc[g][bm][bn][1], ah[bm], bil[bn]);
+        }
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          mma<PREC>(acc[g][bm][bn][0], ah[bm], brh[bn]);
           mma<PREC>(acc[g][bm][bn][1], ah[bm], bih[bn]);
         }
     }
@@ -1006,54 +1026,76 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
 #pragma unroll
         for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) {
-            mma<PREC>(acch[r][bm][bn], al[bm], bh[bn]);
-            mma<PREC>(acch[r][bm][bn], ah[bm], bl[bn]);
-            mma<PREC>(acch[r][bm][bn], ah[bm], bh[bn]);
-          }
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], al[bm], bh[bn]);
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], ah[bm], bl[bn]);
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], ah[bm], bh[bn]);
       }
     }
   };
 
-  load_into(stA, 0);
-  load_into(stB, 1);
+  // prologue: chunks 0 .. R-1 (every group spans at least R chunks)
+  static_for<R>([&](auto q) { load_dh(set(q), decltype(q)::value); });
   if (tid < TM) {
     rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
   } else if (tid < TM + TN) {
     cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
   }
   if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
-  store_from(stA, 0);
+  store_from(st0, 0);
   __syncthreads();
-  // every group spans an even number of chunks (bins padded to 32), so the
-  // two-step pipeline never straddles a group and each step's accumulator
-  // set is static; the (h|h) blocks follow in the same pipeline
+  // one step: refill the set that held chunk j with chunk j + R (PF: 0 a
+  // (d|h) chunk, 1 an (h|h) block, 2 nothing), multiply chunk j out of LDS
+  // buffer j % 2, move chunk j + 1 into the other buffer.  Every group spans
+  // a multiple of R chunks (bins padded to 64) and R is even, so the set and
+  // the buffer of each step are static.
+  auto step = [&](int j, auto slot, auto pf, bool more, auto&& compute_fn) {
+    constexpr int sl = decltype(slot)::value;
+    constexpr int PF = decltype(pf)::value;
+    if constexpr (PF == 0) load_dh(set(slot), j + R);
+    if constexpr (PF == 1) load_hh(set(slot), j + R - ndh);
+    compute_fn(sl & 1);
+    if (more) store_from(set(std::integral_constant<int, sl + 1>{}), (sl + 1) & 1);
+    __syncthreads();
+  };
+  using PF_DH = std::integral_constant<int, 0>;
+  using PF_HH = std::integral_constant<int, 1>;
+  using PF_NONE = std::integral_constant<int, 2>;
   int ch = 0;
   static_for<G>([&](auto gi) {
     constexpr int g = decltype(gi)::value;
-    const int gend = a.mt.gk0[g + 1];
-    for (; ch < gend; ch += 2) {
-      if (ch + 2 < nch) load_into(stA, ch + 2);
-      compute_dh(0, gi);
-      store_from(stB, 1);
-      __syncthreads();
-      if (ch + 3 < nch) load_into(stB, ch + 3);
-      compute_dh(1, gi);
-      store_from(stA, 0);
-      __syncthreads();
+    // the last group's last R chunks prefetch the (h|h) blocks
+    const int gend = a.mt.gk0[g + 1] - (g == G - 1 ? R : 0);
+    for (; ch < gend; ch += R) {
+      static_for<R>([&](auto slot) {
+        step(ch + decltype(slot)::value, slot, PF_DH{}, true,
+             [&](int buf) { compute_dh(buf, gi); });
+      });
+    }
+    if constexpr (g == G - 1) {
+      static_for<R>([&](auto slot) {
+        step(ch + decltype(slot)::value, slot, PF_HH{}, true,
+             [&](int buf) { compute_dh(buf, gi); });
+      });
     }
   });
-  static_for<NHB / 2>([&](auto hi) {
-    constexpr int r = 2 * decltype(hi)::value;
-    const int c0 = ndh + r;
-    if (c0 + 2 < nch) load_into(stA, c0 + 2);
-    compute_hh(0, std::integral_constant<int, r>{});
-    store_from(stB, 1);
-    __syncthreads();
-    if (c0 + 3 < nch) load_into(stB, c0 + 3);
-    compute_hh(1, std::integral_constant<int, r + 1>{});
-    if (c0 + 2 < nch) store_from(stA, 0);
-    __syncthreads();
+  // the (h|h) accumulators only live from here on
+#pragma unroll
+  for (int r = 0; r < NRT; ++r)
+#pragma unroll
+    for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < P::BN; ++bn) acch[r][bm][bn] = Acc{0, 0, 0, 0};
+  static_for<NHB>([&](auto ri) {
+    constexpr int r = decltype(ri)::value;
+    using PFr = typename std::conditional<(r + R < NHB), PF_HH, PF_NONE>::type;
+    step(ndh + r, std::integral_constant<int, r % R>{}, PFr{}, r + 1 < NHB,
+         [&](int buf) { compute_hh(buf, ri); });
   });
 
   // ---- epilogue ----
@@ -1063,7 +1105,9 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
     if (a.cut_delta > 0.0) thr_ml = __longlong_as_double(a.state[0]) - a.cut_delta;
     thr_topk_glob = order_value(a.state[1]) - a.topk_window;
   }
-  const bool use_bound = MODE == kEvidence && thr_ml > 0.0;
+  // the pilot only needs pairs that can raise the running maximum
+  if (MODE == kPilot) thr_ml = __longlong_as_double(a.state[0]);
+  const bool use_bound = MODE != kEval && thr_ml > 0.0;
   const float thr_f = (float)thr_ml;
   const int ND = a.mt.ND;
   EvAcc ev;
@@ -1127,10 +1171,12 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
           float bound = U * U / (2.f * lo) * 1.001f + 1e-3f;
           if (bound < thr_f) {
             survive = false;
-            float lw = (float)(rowd[tr * 4] + cold[tc * 3]);
-            ev.drop.add(lw + bound);
-            ev.max_bound = fmaxf(ev.max_bound, lw + bound);
-            ev.n_bounded += 1.0;
+            if (MODE == kEvidence) {
+              float lw = (float)(rowd[tr * 4] + cold[tc * 3]);
+              ev.drop.add(lw + bound);
+              ev.max_bound = fmaxf(ev.max_bound, lw + bound);
+              ev.n_bounded += 1.0;
+            }
           }
         }
       }
@@ -1239,14 +1285,17 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   }
 }
 
-// fixed-order reduction of tile partials: out[kNPart] combined
-__global__ void k_finalize(const double* __restrict__ partials, int64_t n_tiles,
+// fixed-order reduction of tile partials: block b combines tiles
+// [b * per, (b + 1) * per) into out[b][kNPart]; a second launch with one
+// block combines the block results
+__global__ void k_finalize(const double* __restrict__ partials, int64_t n_tiles, int64_t per,
                            double* __restrict__ out) {
   __shared__ double sh[256 * kNPart];
+  const int64_t t0 = blockIdx.x * per, t1 = min(n_tiles, t0 + per);
   Lse p, d;
   p.init(); d.init();
   double mlm = 0.0, mb = -INFINITY, mxp = -INFINITY, nm = 0, nb = 0, np_ = 0;
-  for (int64_t t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
     const double* r = partials + t * kNPart;
     p.merge(r[0], r[1], r[2]);
     d.merge(r[3], r[4], 0.0);
@@ -1273,7 +1322,7 @@ __global__ void k_finalize(const double* __restrict__ partials, int64_t n_tiles,
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int q = 0; q < kNPart; ++q) out[q] = sh[q];
+    for (int q = 0; q < kNPart; ++q) out[blockIdx.x * kNPart + q] = sh[q];
 }
 
 // one bitonic merge step over candidate records [n][4] (ln p, i, e, o):
