@@ -31,8 +31,45 @@ WORKLOADS = {
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lnl_fused_large_hbm_traffic.txt")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha256():
+    """Hash of the HIP sources with comments and white space removed; a stored counter
+    figure is valid only for the same code."""
+    import glob
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2507_16022_amd", "csrc", "*"))):
+        with open(f) as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(os.path.basename(f).encode())
+        h.update(" ".join(code.split()).encode())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3 summary, or None
+    when the summary is missing or was taken on other kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel source sha256") != kernel_source_sha256():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def device_bank(torch, mc, q, chi, f, modes, chunk=32768):
@@ -72,6 +109,37 @@ def cpu_baseline(wl_meta, rows, cols, f, modes, wl_event, budget_s=20.0):
     return done / dt, done, lnl
 
 
+def fp64_comparison(torch, dotpe, W, ctx, args, reps=2):
+    """Fused-pass time of the plain FP64 path against the split-precision path on the
+    same production-shape event (65536 x 4096 pairs, same cut), and their ln Z."""
+    n_int, n_ext, seed, snr = WORKLOADS["production"]
+    modes = W.MODES_HM
+    wl = W.make_workload(seed, n_int=n_int, n_ext=n_ext, n_bins=256, modes=modes, dets="HLV",
+                         n_phi=32, snr=snr, mc_range=(5.0, 80.0), q_range=(0.1, 1.0),
+                         chi_range=(-0.9, 0.9), with_bank=False)
+    hdev = device_bank(torch, wl.meta["mc"], wl.meta["q"], wl.meta["chi"], wl.f, modes)
+    out = {"workload": f"production: {n_int} x {n_ext} pairs, cut {args.cut}"}
+    for prec in ("fp64", args.precision):
+        bank = ctx.load_bank(hdev, modes, wl.f, precision=prec)
+        ts = []
+        for _ in range(reps):
+            ev = ctx.set_event(bank, d=wl.d, w=wl.w, det_r=wl.det_r, det_D=wl.det_D, ext=wl.ext,
+                               n_phi=wl.n_phi, ln_w_ext=wl.ln_w_ext, d_max=wl.d_max, d0=wl.d0,
+                               cut_delta=args.cut, top_k=16, topk_window=args.topk_window)
+            r = ev.evidence()
+            ev.close()
+            ts.append(r["t_pilot_ms"] + r["t_fused_ms"])
+        bank.close()
+        out[f"{prec}_ms"] = min(ts)
+        out[f"{prec}_ln_z"] = r["ln_z"]
+    out["speedup"] = out["fp64_ms"] / out[f"{args.precision}_ms"]
+    log(f"FP64 path {out['fp64_ms']:.1f} ms vs {args.precision} {out[args.precision + '_ms']:.1f} ms "
+        f"(x{out['speedup']:.1f}); ln Z {out['fp64_ln_z']:.6f} vs {out[args.precision + '_ln_z']:.6f}")
+    del hdev
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +151,8 @@ def main():
     ap.add_argument("--topk-window", type=float, default=20.0)
     ap.add_argument("--top-k", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64-path comparison at the production shape")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (calibrates HBM counters)")
@@ -174,6 +244,8 @@ def main():
                          "sums + 2000-node distance quadrature, single process"}
         log(f"oracle {rate:.1f} pairs/s on {done} pairs; sampled max |d lnLbar| = {parity}")
 
+    fp64_cmp = None if args.no_fp64 else fp64_comparison(torch, dotpe, W, ctx, args)
+    traffic = stored_traffic()
     out = {
         "metric": "lnL pairs/s at |dlnL|<=1e-3 (mixed vs FP64)",
         "value": n_pairs / dt,
@@ -192,7 +264,9 @@ def main():
                                f"cut {args.cut}, top-{args.top_k}",
                    "n_int": n_int, "n_ext": n_ext, "pairs": n_pairs},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": traffic if (args.workload == "large" and args.precision == "fp16x2")
+                     else None,
                      "kernel": "k_lnl_fused (evidence pass)", "kernel_ms": fused_ms},
         "cpu_baseline": cpu,
         "ln_z": r["ln_z"], "ln_z_upper": r["ln_z_upper"], "max_lnl_ml": r["max_lnl_ml"],
@@ -202,6 +276,7 @@ def main():
         "pilot_ms": pilot_ms,
         "sampled_max_abs_dlnl_vs_oracle": parity,
         "topk_count": r["topk_count"], "topk_exact": r["topk_exact"],
+        "fp64_path": fp64_cmp,
     }
     print(json.dumps(out), flush=True)
 

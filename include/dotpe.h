@@ -83,7 +83,7 @@ int dotpe_destroy(dotpe_ctx* ctx);
 /* Bytes of device memory currently held by the context. */
 uint64_t dotpe_device_bytes(const dotpe_ctx* ctx);
 
-/* Intrinsic waveform bank (Sec. III C): n_wf waveforms, each n_modes (l, m)
+/* Intrinsic waveform bank (Sec. IV C): n_wf waveforms, each n_modes (l, m)
  * channel amplitudes on n_bins frequencies, at distance d0, reference phase
  * 0 and polarisation angle 0. */
 typedef struct dotpe_bank_desc {
@@ -106,7 +106,7 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* desc, dotpe_bank** ou
 int dotpe_free_bank(dotpe_ctx* ctx, dotpe_bank* bank);
 
 /* One event: data, noise weights, detectors and the extrinsic set
- * (Sec. III A, III B).  All pointers are host memory. */
+ * (Sec. IV A, IV B).  All pointers are host memory. */
 typedef struct dotpe_event_desc {
   int32_t n_det;            /* 1..8 */
   int32_t n_phi;            /* 1..128 reference-phase grid points */

@@ -24,7 +24,7 @@ Readings of the paper (where it is silent, ambiguous or garbled):
   * non-precessing waveforms: the inclination dependence factorises into
     K_{c,p}(iota), so the bank stores one complex amplitude per (l, m) and
     the inclination travels with the extrinsic sample;
-  * phase grid phi_o = 2 pi o / N_phi, w_o = 1 (Sec. III B);
+  * phase grid phi_o = 2 pi o / N_phi, w_o = 1 (Sec. IV B);
   * distance prior proportional to D^2 on (0, D_max].
 """
 from __future__ import annotations

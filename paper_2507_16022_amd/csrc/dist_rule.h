@@ -1,5 +1,5 @@
 // Distance marginalisation of the per-triple likelihood (eq. lnl_dist_marginalized
-// with a prior proportional to D^2 on (0, D_max], Sec. III B).
+// with a prior proportional to D^2 on (0, D_max], Sec. IV B).
 //
 // In the variables z = dh / sqrt(hh) (data projected on the unit template)
 // and s = sqrt(hh) d0 / D_max (template SNR at the largest distance), with

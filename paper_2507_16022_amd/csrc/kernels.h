@@ -225,7 +225,7 @@ __device__ __forceinline__ double2 bank_value(const void* A0, const void* A1, in
 }
 
 // ---------------------------------------------------------------------------
-// extrinsic response (Sec. III A): antenna patterns, arrival times, mode
+// extrinsic response (Sec. IV A): antenna patterns, arrival times, mode
 // factors, R_ekc, |R_ekc|^2 and Q_ekcc'
 // ---------------------------------------------------------------------------
 __device__ double swsh_m2(int l, int m, double cos_t) {

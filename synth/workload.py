@@ -20,7 +20,7 @@ GWTC-calibrated banks -- are not available):
 
 Units: frequencies in Hz, times in s, distances in Mpc, detector positions
 in metres.  Waveforms are stored at the reference distance d0 (1 Mpc,
-Sec. III B) with reference phase 0 and polarisation angle 0 (Sec. III A).
+Sec. IV B) with reference phase 0 and polarisation angle 0 (Sec. IV A).
 """
 from __future__ import annotations
 
@@ -99,7 +99,7 @@ def bin_widths(f):
 
 def psd_weights(f, net: Network):
     """w_kb = 4 df_b / S_k(f_b): the per-bin weights of the noise-weighted
-    inner product (Sec. II B, summed over the bins)."""
+    inner product (Sec. III A, summed over the bins)."""
     df = bin_widths(f)
     return np.stack([4.0 * df / psd(f, a) for a in net.noise_amp])
 

@@ -138,6 +138,11 @@ def test_eval_mixed_tiny(ctx, prec, snr):
     if prec == "fp16x2":
         assert err.max() <= TOL_MIXED
         assert abs(zg - zr) <= TOL_MIXED
+    else:
+        # BF16 hi+lo keeps ~16 significant bits per operand: the coherent worst case of the
+        # representation error is ~2^-16 rho^2 in lnL, so 1e-3 is out of reach at high SNR;
+        # hold it to twice that bound
+        assert err.max() <= 2.0 ** -15 * snr ** 2
 
 
 def test_eval_mixed_higher_modes(ctx):

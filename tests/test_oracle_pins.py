@@ -43,7 +43,7 @@ def test_zero_noise_injection_rho2_over_2(modes, dets, snr):
 
 # ---------------------------------------------------------------- P2 ------
 def test_cauchy_schwarz(tiny):
-    """(d|h)^2 <= (d|d)(h|h) for every triple (inner product of Sec. II B)."""
+    """(d|h)^2 <= (d|d)(h|h) for every triple (inner product of Sec. III A)."""
     wl = tiny.subset(rows=np.arange(8), cols=np.arange(32))
     r = O.eval_pairs_block(wl, np.arange(8), return_triples=True)
     dd = O.data_inner(wl.d, wl.w)
@@ -92,7 +92,7 @@ def test_phase_grid_bessel_identity():
 
 # ---------------------------------------------------------------- P5 ------
 def test_distance_quadrature_converged(tiny):
-    """The 2000-node rule agrees with 4000 nodes (Sec. III B distance
+    """The 2000-node rule agrees with 4000 nodes (Sec. IV B distance
     marginalisation computed to well below the 1e-3 target)."""
     wl = tiny.subset(rows=np.arange(4), cols=np.arange(16))
     r = O.eval_pairs_block(wl, np.arange(4), return_triples=True)
@@ -240,7 +240,7 @@ def test_evidence_invariances(tiny):
 # ---------------------------------------------------------------- P11 -----
 def test_time_shift_covariance(tiny):
     """Shifting the data by exp(-2 pi i f tau) and every t_geo by tau leaves
-    all inner products unchanged (time-shift factor T of Sec. III A)."""
+    all inner products unchanged (time-shift factor T of Sec. IV A)."""
     wl = tiny.subset(rows=np.arange(3), cols=np.arange(8))
     r0 = O.eval_pairs_block(wl, np.arange(3), return_triples=True)
     tau = 0.0123
