@@ -140,6 +140,56 @@ def fp64_comparison(torch, dotpe, W, ctx, args, reps=2):
     return out
 
 
+def serving_leg(dotpe, W, ctx, bank, n_bank, rate_pairs, args):
+    """Events of mixed sizes arriving as a Poisson stream, served against the resident bank.
+
+    Per event: a contiguous bank range of log-uniform size 2048..262144 at a random start,
+    log-uniform 512..8192 extrinsic samples, 2 or 3 detectors, SNR uniform in 8..30.  The
+    arrival rate offers args.serve_load x the measured single-event throughput (pairs/s)."""
+    rng = np.random.default_rng(2024)
+    n = args.serve_events
+    specs, pairs = [], []
+    for q in range(n):
+        n_sub = int(round(math.exp(rng.uniform(math.log(2048), math.log(262144)))))
+        n_ext = int(round(math.exp(rng.uniform(math.log(512), math.log(8192)))))
+        dets = "HLV" if rng.random() < 0.5 else "HL"
+        start = int(rng.integers(0, n_bank - n_sub + 1))
+        ev = W.make_workload(1000 + q, n_int=8, n_ext=n_ext, n_bins=256, modes=W.MODES_HM,
+                             dets=dets, n_phi=32, snr=float(rng.uniform(8.0, 30.0)),
+                             mc_range=(5.0, 80.0), q_range=(0.1, 1.0), chi_range=(-0.9, 0.9),
+                             with_bank=False)
+        specs.append(dict(d=ev.d, w=ev.w, det_r=ev.det_r, det_D=ev.det_D, ext=ev.ext,
+                          n_phi=ev.n_phi, ln_w_ext=ev.ln_w_ext, d_max=ev.d_max, d0=ev.d0,
+                          sub_start=start, sub_count=n_sub, cut_delta=args.cut, top_k=256,
+                          topk_window=args.topk_window))
+        pairs.append(n_sub * n_ext)
+    lam = args.serve_load * rate_pairs / float(np.mean(pairs))     # events per second
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
+    srv = dotpe.Server(ctx, bank, n_slots=args.serve_slots, pool_bytes=args.serve_pool_gib << 30)
+    t0 = time.perf_counter()
+    tickets = []
+    for q in range(n):
+        dt = arrivals[q] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(**specs[q]))
+    infos = []
+    for t in tickets:
+        r, info = srv.wait(t)
+        infos.append(info)
+    srv.close()
+    lat = np.array([i["t_done_ms"] - i["t_submit_ms"] for i in infos])
+    queue = np.array([i["t_start_ms"] - i["t_submit_ms"] for i in infos])
+    span_s = (max(i["t_done_ms"] for i in infos) - min(i["t_submit_ms"] for i in infos)) / 1e3
+    out = {"events": n, "slots": args.serve_slots, "offered_load": args.serve_load,
+           "arrival_rate_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "mean_queue_ms": float(queue.mean()),
+           "pairs_per_s": float(np.sum(pairs)) / span_s, "pairs_total": int(np.sum(pairs))}
+    log(f"serving: {n} events at {lam:.1f}/s: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, "
+        f"{out['pairs_per_s']:.3g} pairs/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +201,11 @@ def main():
     ap.add_argument("--topk-window", type=float, default=20.0)
     ap.add_argument("--top-k", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-events", type=int, default=256,
+                    help="events in the serving leg (0 skips it)")
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-pool-gib", type=int, default=8)
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64-path comparison at the production shape")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -244,6 +299,8 @@ def main():
                          "sums + 2000-node distance quadrature, single process"}
         log(f"oracle {rate:.1f} pairs/s on {done} pairs; sampled max |d lnLbar| = {parity}")
 
+    serving = (serving_leg(dotpe, W, ctx, bank, n_int, n_pairs / dt, args)
+               if args.serve_events > 0 else None)
     fp64_cmp = None if args.no_fp64 else fp64_comparison(torch, dotpe, W, ctx, args)
     traffic = stored_traffic()
     out = {
@@ -277,6 +334,7 @@ def main():
         "sampled_max_abs_dlnl_vs_oracle": parity,
         "topk_count": r["topk_count"], "topk_exact": r["topk_exact"],
         "fp64_path": fp64_cmp,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

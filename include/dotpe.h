@@ -31,7 +31,7 @@
  * dotpe_last_error() returns a message for the calling thread's last error.
  * On error, outputs are left untouched and no handle is returned.
  * Handles are owned by the library and freed with the matching free call.
- * A context is not thread-safe.
+ * A context is not thread-safe; a server's calls may be made from any thread.
  */
 #ifndef DOTPE_H
 #define DOTPE_H
@@ -187,6 +187,72 @@ typedef struct dotpe_sample {
  * INVALID_ARG, DEVICE. */
 int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out,
                    dotpe_sample* topk);
+
+/* Device bytes one event needs: every buffer dotpe_set_event and
+ * dotpe_evidence use for it, packed in one block (the admission footprint of
+ * the serving calls).  Validates the description like dotpe_set_event.
+ * Errors: INVALID_ARG, NUMERIC. */
+int dotpe_event_bytes(const dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_event_desc* desc,
+                      uint64_t* bytes);
+
+/* ---- Serving: continuous admission of events against a resident bank ----
+ *
+ * A server owns one device pool and n_slots streams.  dotpe_submit copies an
+ * event description and returns at once.  Events are admitted first in, first
+ * out: the head of the queue starts when a slot is idle and the pool has a
+ * free block of its footprint (dotpe_event_bytes).  Each admitted event is
+ * staged and evaluated (dotpe_set_event + dotpe_evidence semantics, the
+ * description's stream ignored) on its slot's stream, with every buffer packed
+ * in its pool block, so serving allocates no device memory per event and the
+ * work of events in different slots overlaps on the device.  The block
+ * returns to the pool when the event completes.  Results equal those of
+ * dotpe_evidence on the same event alone, up to the certified cut (which
+ * pairs are bounded depends on when the running maximum rises).
+ * (Sec. IV B: every event is an independent evaluation of the likelihood
+ * matrix; scheduling is outside the paper.) */
+typedef struct dotpe_server dotpe_server;
+
+typedef struct dotpe_server_desc {
+  int32_t n_slots;        /* events in flight at once, 1..16; 0 = 4 */
+  int32_t reserved;       /* 0 */
+  uint64_t pool_bytes;    /* device pool shared by admitted events; 0 = 8 GiB */
+} dotpe_server_desc;
+
+typedef struct dotpe_ticket_info {
+  double t_submit_ms;     /* host steady clock, ms since the server was created */
+  double t_start_ms;      /* admitted: slot and pool block granted */
+  double t_done_ms;       /* results on the host */
+  uint64_t bytes;         /* pool footprint of the event */
+  int32_t slot;           /* slot (stream) that ran it */
+  int32_t status;         /* DOTPE_OK or the event's error code */
+} dotpe_ticket_info;
+
+/* Create a server for `bank` (which must outlive it).  The pool is charged to
+ * the context's budget.  Errors: INVALID_ARG, ADMISSION / OOM (pool), DEVICE. */
+int dotpe_server_create(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_server_desc* desc,
+                        dotpe_server** out);
+
+/* Run every submitted event to completion, then release the server.  Results
+ * not collected with dotpe_wait are dropped.  NULL is a no-op. */
+int dotpe_server_destroy(dotpe_server* srv);
+
+/* Queue one event; the description's arrays are copied before returning and
+ * remain the caller's.  *ticket identifies it for dotpe_poll / dotpe_wait.
+ * Errors: INVALID_ARG, NUMERIC (as dotpe_set_event), ADMISSION (footprint
+ * larger than the whole pool). */
+int dotpe_submit(dotpe_server* srv, const dotpe_event_desc* desc, int64_t* ticket);
+
+/* *done = 1 when the event has completed, else 0.  Errors: INVALID_ARG
+ * (unknown or already collected ticket). */
+int dotpe_poll(dotpe_server* srv, int64_t ticket, int32_t* done);
+
+/* Block until the event completes and collect it (the ticket is then
+ * forgotten).  out, topk ([desc.top_k] host array) and info may be NULL.
+ * Returns the event's own status (its error message via dotpe_last_error);
+ * info is filled in either case.  Errors: INVALID_ARG (unknown ticket), or
+ * the event's error code. */
+int dotpe_wait(dotpe_server* srv, int64_t ticket, dotpe_evidence_result* out, dotpe_sample* topk,
+               dotpe_ticket_info* info);
 
 /* Evaluate the device distance-marginalisation rule for n (dh, hh) pairs
  * (host arrays), d0/D_max given; for checking the rule against a reference. */

@@ -5,15 +5,20 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/dotpe.h"
 #include "kernels.h"
+#include "serving.h"
 
 using namespace dotpe;
 
@@ -47,7 +52,7 @@ struct dotpe_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
-  uint64_t bytes = 0;
+  std::atomic<uint64_t> bytes{0};   // serving slot threads also release through it
   uint64_t own_bytes = 0;    // the context's own tables (not charged to the budget)
   double* dist_tab = nullptr;
   DistTableGeom geom{};
@@ -397,12 +402,20 @@ bool finite_all(const double* p, size_t n) {
   return true;
 }
 
+// state words: [0] running max of lnL^ML (bits of a non-negative double),
+// [1] running max of ln p (ordered encoding), [2] candidate count,
+// [3] cut reference frozen after the pilot pass
 __global__ void k_reset_state(uint64_t* st) {
   if (threadIdx.x == 0) {
     st[0] = 0ull;                       // bits of +0.0
     st[1] = 0x000fffffffffffffull;      // ordered encoding below every finite value
     st[2] = 0ull;
+    st[3] = 0ull;
   }
+}
+
+__global__ void k_freeze_threshold(uint64_t* st) {
+  if (threadIdx.x == 0) st[3] = st[0];
 }
 
 }  // namespace
@@ -460,7 +473,7 @@ int dotpe_destroy(dotpe_ctx* ctx) {
   return DOTPE_OK;
 }
 
-uint64_t dotpe_device_bytes(const dotpe_ctx* ctx) { return ctx ? ctx->bytes : 0; }
+uint64_t dotpe_device_bytes(const dotpe_ctx* ctx) { return ctx ? ctx->bytes.load() : 0; }
 
 int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) {
   if (!ctx || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
@@ -598,9 +611,32 @@ int dotpe_free_event(dotpe_ctx* ctx, dotpe_event* ev) {
   return DOTPE_OK;
 }
 
-int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d,
-                    dotpe_event** out) {
-  if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// validated description of one event and the shapes derived from it
+struct EvDims {
+  int nk = 0, nb = 0, nc = 0, n_bp = 0, n_phi = 0, KH = 0, NP = 0, prec = 0;
+  int64_t ne = 0, ne_p = 0, n_sub = 0, K2 = 0, n_tiles = 0, cand_cap = 0;
+  bool ln_w_ext = false, sub_idx = false;
+};
+
+// input staging buffers of set_event (used only while the event is staged)
+struct EvStage {
+  double *d = nullptr, *w = nullptr, *r = nullptr, *D = nullptr, *lat = nullptr, *lon = nullptr,
+         *psi = nullptr, *ci = nullptr, *tg = nullptr;
+  double2* Btmp = nullptr;
+  int* err = nullptr;
+};
+
+struct EvBuf {
+  void** p;
+  size_t n;
+  bool stage;
+};
+
+int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::vector<int>* terms) {
   if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
   if (d->n_phi < 1 || d->n_phi > kMaxPhi) return fail(DOTPE_E_INVALID_ARG, "n_phi=%d", d->n_phi);
   if (d->n_ext < 1) return fail(DOTPE_E_INVALID_ARG, "n_ext=%lld", (long long)d->n_ext);
@@ -609,10 +645,9 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
     return fail(DOTPE_E_INVALID_ARG, "event arrays must not be NULL");
   if (!(d->d_max > 0.0) || !(d->d0 > 0.0) || !std::isfinite(d->d_max) || !std::isfinite(d->d0))
     return fail(DOTPE_E_INVALID_ARG, "distances must be positive and finite");
-  std::vector<int> terms;
   int KH = 0;
   {
-    int rc0 = build_hh_terms(bk->mt, d->n_det, &terms, &KH);
+    int rc0 = build_hh_terms(bk->mt, d->n_det, terms, &KH);
     if (rc0) return rc0;
   }
   const int nb = bk->n_b, nk = d->n_det;
@@ -636,102 +671,166 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
   } else if (d->sub_start < 0 || d->sub_start + n_sub > bk->n_wf) {
     return fail(DOTPE_E_INVALID_ARG, "bank range out of bounds");
   }
+  D->nk = nk;
+  D->nb = nb;
+  D->nc = bk->n_c;
+  D->n_bp = bk->n_bp;
+  D->n_phi = d->n_phi;
+  D->KH = KH;
+  D->NP = bk->mt.NP;
+  D->prec = bk->prec;
+  D->ne = ne;
+  D->ne_p = round_up(ne, 64);
+  D->n_sub = n_sub;
+  D->K2 = bk->K2;
+  int tm, tn;
+  tile_shape(bk->prec, &tm, &tn);
+  D->n_tiles = ((n_sub + tm - 1) / tm) * ((ne + tn - 1) / tn);
+  // top-k candidate buffer: a power of two (the bitonic sort runs in place),
+  // never more than the number of pairs
+  int64_t want = std::max<int64_t>(int64_t(1) << 20, 16 * (int64_t)std::max(0, d->top_k));
+  want = std::max<int64_t>(1, std::min<int64_t>(want, n_sub * ne));
+  int64_t cap = 1;
+  while (cap < want) cap <<= 1;
+  D->cand_cap = cap;
+  D->ln_w_ext = d->ln_w_ext != nullptr;
+  D->sub_idx = d->sub_idx != nullptr;
+  return DOTPE_OK;
+}
+
+// the event's device buffers in allocation order: what it keeps, then the
+// staging of its inputs
+std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) {
+  std::vector<EvBuf> v;
+  const size_t esz = D.prec == kFP64 ? 8 : 2;
+  // FP64: B_re, B_im; split precisions: B_re hi, lo (B_im is formed in registers)
+  for (int q = 0; q < 2; ++q) v.push_back({&ev->B[q], (size_t)D.ne_p * D.K2 * esz, false});
+  if (D.prec != kFP64) v.push_back({(void**)&ev->col_scale, (size_t)D.ne * 8, false});
+  v.push_back({(void**)&ev->hh_terms, (size_t)D.KH * sizeof(int), false});
+  for (int q = 0; q < (D.prec == kFP64 ? 1 : 2); ++q) {
+    v.push_back({&ev->Ah[q], (size_t)D.n_sub * D.KH * esz, false});
+    v.push_back({&ev->Bh[q], (size_t)D.ne_p * D.KH * esz, false});
+  }
+  if (D.prec != kFP64) {
+    v.push_back({(void**)&ev->ah_scale, (size_t)D.n_sub * 8, false});
+    v.push_back({(void**)&ev->bh_scale, (size_t)D.ne * 8, false});
+  }
+  v.push_back({(void**)&ev->Q, (size_t)D.ne * D.nk * D.NP * 16, false});
+  v.push_back({(void**)&ev->R2, (size_t)D.ne * D.nk * D.nc * 8, false});
+  v.push_back({(void**)&ev->R, (size_t)D.ne * D.nk * D.nc * 16, false});
+  v.push_back({(void**)&ev->T, (size_t)D.ne * D.nk * 8, false});
+  v.push_back({(void**)&ev->phase_cs, (size_t)kMaxM * D.n_phi * 2 * 8, false});
+  if (D.ln_w_ext) v.push_back({(void**)&ev->ln_w_ext, (size_t)D.ne * 8, false});
+  if (D.sub_idx) v.push_back({(void**)&ev->sub_idx, (size_t)D.n_sub * 8, false});
+  v.push_back({(void**)&ev->state, 64, false});
+  v.push_back({(void**)&ev->final_out, kNPart * 8 + 64, false});
+  v.push_back({(void**)&ev->partials, (size_t)D.n_tiles * kNPart * 8, false});
+  v.push_back({(void**)&ev->final_blk, (size_t)((D.n_tiles + 4095) / 4096) * kNPart * 8, false});
+  v.push_back({(void**)&ev->cand, (size_t)D.cand_cap * 32, false});
+  v.push_back({(void**)&st->d, (size_t)D.nk * D.nb * 16, true});
+  v.push_back({(void**)&st->w, (size_t)D.nk * D.nb * 8, true});
+  v.push_back({(void**)&st->r, (size_t)D.nk * 24, true});
+  v.push_back({(void**)&st->D, (size_t)D.nk * 72, true});
+  v.push_back({(void**)&st->lat, (size_t)D.ne * 8, true});
+  v.push_back({(void**)&st->lon, (size_t)D.ne * 8, true});
+  v.push_back({(void**)&st->psi, (size_t)D.ne * 8, true});
+  v.push_back({(void**)&st->ci, (size_t)D.ne * 8, true});
+  v.push_back({(void**)&st->tg, (size_t)D.ne * 8, true});
+  v.push_back({(void**)&st->Btmp, (size_t)D.ne * D.nc * D.n_bp * 16, true});
+  v.push_back({(void**)&st->err, 64, true});
+  return v;
+}
+
+constexpr uint64_t kBlockAlign = 256;
+
+// bytes of one block holding every buffer of the list, packed as set_event packs them
+uint64_t block_bytes(const std::vector<EvBuf>& v) {
+  uint64_t off = 0;
+  for (const EvBuf& b : v) off = round_up(off, kBlockAlign) + b.n;
+  return round_up(off, kBlockAlign);
+}
+
+// Stage one event.  With block == nullptr every buffer is its own device
+// allocation (staging buffers are freed before returning); otherwise all of
+// them are packed into the caller's device block of block_len bytes and
+// nothing is allocated.
+int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d, char* block,
+                   uint64_t block_len, hipStream_t s, dotpe_event** out) {
+  EvDims D;
+  std::vector<int> terms;
+  int rc = event_dims(bk, d, &D, &terms);
+  if (rc) return rc;
   HIP_OK(hipSetDevice(ctx->device));
   dotpe_event* ev = new dotpe_event();
   ev->bank = bk;
-  ev->stream = d->stream ? (hipStream_t)d->stream : ctx->stream;
-  ev->n_det = nk;
-  ev->n_phi = d->n_phi;
-  ev->n_ext = ne;
-  ev->n_ext_p = round_up(ne, 64);
-  ev->n_sub = n_sub;
+  ev->stream = s;
+  ev->n_det = D.nk;
+  ev->n_phi = D.n_phi;
+  ev->n_ext = D.ne;
+  ev->n_ext_p = D.ne_p;
+  ev->n_sub = D.n_sub;
   ev->sub0 = d->sub_idx ? 0 : d->sub_start;
   ev->d0 = d->d0;
   ev->d_max = d->d_max;
-  ev->n_norm = d->n_norm > 0 ? d->n_norm : (double)n_sub;
+  ev->n_norm = d->n_norm > 0 ? d->n_norm : (double)D.n_sub;
   ev->cut_delta = d->cut_delta;
   ev->topk_window = d->topk_window > 0 ? d->topk_window : 40.0;
   ev->top_k = std::max(0, d->top_k);
+  ev->KH = D.KH;
+  ev->cand_cap = D.cand_cap;
   const ModeTables& mt = bk->mt;
-  const int nc = bk->n_c;
-  hipStream_t s = ev->stream;
-  int rc;
-  auto cleanup = [&](int code) {
-    (void)hipStreamSynchronize(s);
-    for (void* p : ev->allocs) (void)hipFree(p);
-    ctx->bytes -= ev->bytes;
-    delete ev;
-    return code;
-  };
-  auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &ev->allocs, &ev->bytes); };
-  const size_t esz = bk->prec == kFP64 ? 8 : 2;
-  const int nB = 2;   // FP64: B_re, B_im; split precisions: B_re hi, lo
-  for (int q = 0; q < nB; ++q)
-    if ((rc = alloc(&ev->B[q], (size_t)ev->n_ext_p * bk->K2 * esz))) return cleanup(rc);
-  if (bk->prec != kFP64 && (rc = alloc((void**)&ev->col_scale, ne * 8))) return cleanup(rc);
-  ev->KH = KH;
-  if ((rc = alloc((void**)&ev->hh_terms, (size_t)KH * sizeof(int)))) return cleanup(rc);
-  for (int q = 0; q < (bk->prec == kFP64 ? 1 : 2); ++q) {
-    if ((rc = alloc(&ev->Ah[q], (size_t)n_sub * KH * esz))) return cleanup(rc);
-    if ((rc = alloc(&ev->Bh[q], (size_t)ev->n_ext_p * KH * esz))) return cleanup(rc);
-  }
-  if (bk->prec != kFP64) {
-    if ((rc = alloc((void**)&ev->ah_scale, (size_t)n_sub * 8))) return cleanup(rc);
-    if ((rc = alloc((void**)&ev->bh_scale, (size_t)ne * 8))) return cleanup(rc);
-  }
-  if ((rc = alloc((void**)&ev->Q, (size_t)ne * nk * mt.NP * 16))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->R2, (size_t)ne * nk * nc * 8))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->R, (size_t)ne * nk * nc * 16))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->T, (size_t)ne * nk * 8))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->phase_cs, (size_t)kMaxM * d->n_phi * 2 * 8))) return cleanup(rc);
-  if (d->ln_w_ext && (rc = alloc((void**)&ev->ln_w_ext, ne * 8))) return cleanup(rc);
-  if (d->sub_idx && (rc = alloc((void**)&ev->sub_idx, n_sub * 8))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->state, 64))) return cleanup(rc);
-  if ((rc = alloc((void**)&ev->final_out, kNPart * 8 + 64))) return cleanup(rc);
-  // staging inputs (freed at the end of this call)
+  const int nb = D.nb, nk = D.nk, nc = D.nc;
+  const int64_t ne = D.ne, n_sub = D.n_sub;
+  EvStage st;
+  std::vector<EvBuf> bufs = event_buffers(D, ev, &st);
   std::vector<void*> tmp;
   uint64_t tmp_bytes = 0;
-  auto talloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &tmp, &tmp_bytes); };
-  auto done_tmp = [&]() {
+  auto release_tmp = [&]() {
     (void)hipStreamSynchronize(s);
     for (void* p : tmp) (void)hipFree(p);
     ctx->bytes -= tmp_bytes;
     tmp.clear();
     tmp_bytes = 0;
   };
-  double *dd = nullptr, *dw = nullptr, *dr = nullptr, *dD = nullptr, *dlat = nullptr,
-         *dlon = nullptr, *dpsi = nullptr, *dci = nullptr, *dtg = nullptr;
-  double2* Btmp = nullptr;
-  int* err = nullptr;
-  size_t sizes[] = {(size_t)nk * nb * 16, (size_t)nk * nb * 8, (size_t)nk * 24, (size_t)nk * 72,
-                    (size_t)ne * 8, (size_t)ne * 8, (size_t)ne * 8, (size_t)ne * 8, (size_t)ne * 8,
-                    (size_t)ne * nc * bk->n_bp * 16, 64};
-  void** ptrs[] = {(void**)&dd, (void**)&dw, (void**)&dr, (void**)&dD, (void**)&dlat,
-                   (void**)&dlon, (void**)&dpsi, (void**)&dci, (void**)&dtg, (void**)&Btmp,
-                   (void**)&err};
-  for (int q = 0; q < 11; ++q) {
-    if ((rc = talloc(ptrs[q], sizes[q]))) {
-      done_tmp();
-      return cleanup(rc);
+  auto cleanup = [&](int code) {
+    release_tmp();
+    for (void* p : ev->allocs) (void)hipFree(p);
+    ctx->bytes -= ev->bytes;
+    delete ev;
+    return code;
+  };
+  uint64_t off = 0;
+  for (const EvBuf& b : bufs) {
+    if (block) {
+      off = round_up(off, kBlockAlign);
+      if (off + b.n > block_len)
+        return cleanup(fail(DOTPE_E_ADMISSION, "event does not fit its %llu-byte block",
+                            (unsigned long long)block_len));
+      *b.p = block + off;
+      off += b.n;
+    } else {
+      rc = b.stage ? dev_alloc(ctx, b.p, b.n, &tmp, &tmp_bytes)
+                   : dev_alloc(ctx, b.p, b.n, &ev->allocs, &ev->bytes);
+      if (rc) return cleanup(rc);
     }
   }
   hipError_t e = hipSuccess;
   auto H2D = [&](void* dst, const void* src, size_t n) {
     if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
   };
-  H2D(dd, d->d, sizes[0]);
-  H2D(dw, d->w, sizes[1]);
-  H2D(dr, d->det_r, sizes[2]);
-  H2D(dD, d->det_D, sizes[3]);
-  H2D(dlat, d->lat, sizes[4]);
-  H2D(dlon, d->lon, sizes[5]);
-  H2D(dpsi, d->psi, sizes[6]);
-  H2D(dci, d->cos_iota, sizes[7]);
-  H2D(dtg, d->t_geo, sizes[8]);
+  H2D(st.d, d->d, (size_t)nk * nb * 16);
+  H2D(st.w, d->w, (size_t)nk * nb * 8);
+  H2D(st.r, d->det_r, (size_t)nk * 24);
+  H2D(st.D, d->det_D, (size_t)nk * 72);
+  H2D(st.lat, d->lat, ne * 8);
+  H2D(st.lon, d->lon, ne * 8);
+  H2D(st.psi, d->psi, ne * 8);
+  H2D(st.ci, d->cos_iota, ne * 8);
+  H2D(st.tg, d->t_geo, ne * 8);
   if (d->ln_w_ext) H2D(ev->ln_w_ext, d->ln_w_ext, ne * 8);
   if (d->sub_idx) H2D(ev->sub_idx, d->sub_idx, n_sub * 8);
   H2D(ev->hh_terms, terms.data(), terms.size() * sizeof(int));
-  if (e == hipSuccess) e = hipMemsetAsync(err, 0, 64, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st.err, 0, 64, s);
   // phase table cos, sin (m phi_o), m = 1..4 (a twiddle table of the grid)
   std::vector<double> cs((size_t)kMaxM * d->n_phi * 2);
   for (int m = 1; m <= kMaxM; ++m)
@@ -741,37 +840,61 @@ int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc
       cs[((m - 1) * d->n_phi + o) * 2 + 1] = std::sin(ph);
     }
   H2D(ev->phase_cs, cs.data(), cs.size() * 8);
-  if (e != hipSuccess) {
-    done_tmp();
+  if (e != hipSuccess)
     return cleanup(fail(DOTPE_E_DEVICE, "event upload: %s", hipGetErrorString(e)));
-  }
   // extrinsic response, B operand, (h|h) tables, (d|d)
   hipLaunchKernelGGL(k_ext_response, dim3((unsigned)((ne + 127) / 128)), dim3(128), 0, s, ne, nk,
-                     dr, dD, dlat, dlon, dpsi, dci, dtg, mt, ev->R, ev->T, ev->Q, ev->R2);
+                     st.r, st.D, st.lat, st.lon, st.psi, st.ci, st.tg, mt, ev->R, ev->T, ev->Q,
+                     ev->R2);
   int64_t nbt = ne * nc * bk->n_bp;
   hipLaunchKernelGGL(k_build_B, dim3((unsigned)((nbt + 255) / 256)), dim3(256), 0, s, ne, nk, nc,
-                     nb, bk->n_bp, bk->f, (const double2*)dd, dw, ev->R, ev->T, Btmp);
+                     nb, bk->n_bp, bk->f, (const double2*)st.d, st.w, ev->R, ev->T, st.Btmp);
   switch (bk->prec) {
-    case kFP64: launch_convert_B<kFP64>(ev, Btmp, err); break;
-    case kFP16X2: launch_convert_B<kFP16X2>(ev, Btmp, err); break;
-    default: launch_convert_B<kBF16X2>(ev, Btmp, err); break;
+    case kFP64: launch_convert_B<kFP64>(ev, st.Btmp, st.err); break;
+    case kFP16X2: launch_convert_B<kFP16X2>(ev, st.Btmp, st.err); break;
+    default: launch_convert_B<kBF16X2>(ev, st.Btmp, st.err); break;
   }
   switch (bk->prec) {
-    case kFP64: launch_hh<kFP64>(ev, dw); break;
-    case kFP16X2: launch_hh<kFP16X2>(ev, dw); break;
-    default: launch_hh<kBF16X2>(ev, dw); break;
+    case kFP64: launch_hh<kFP64>(ev, st.w); break;
+    case kFP16X2: launch_hh<kFP16X2>(ev, st.w); break;
+    default: launch_hh<kBF16X2>(ev, st.w); break;
   }
-  hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(256), 0, s, nk * nb, (const double2*)dd, dw,
+  hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(256), 0, s, nk * nb, (const double2*)st.d, st.w,
                      ev->final_out + kNPart);
   e = hipGetLastError();
   int herr = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(&ev->dd, ev->final_out + kNPart, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, st.err, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&ev->dd, ev->final_out + kNPart, 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  done_tmp();
+  release_tmp();
   if (e != hipSuccess) return cleanup(fail(DOTPE_E_DEVICE, "event staging: %s", hipGetErrorString(e)));
   if (herr) return cleanup(fail(DOTPE_E_NUMERIC, "non-finite extrinsic operand"));
   *out = ev;
+  return DOTPE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d,
+                    dotpe_event** out) {
+  if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  return set_event_impl(ctx, bk, d, nullptr, 0,
+                        d->stream ? (hipStream_t)d->stream : ctx->stream, out);
+}
+
+int dotpe_event_bytes(const dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d,
+                      uint64_t* bytes) {
+  if (!ctx || !bk || !d || !bytes) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  EvDims D;
+  std::vector<int> terms;
+  int rc = event_dims(bk, d, &D, &terms);
+  if (rc) return rc;
+  dotpe_event probe;
+  EvStage st;
+  *bytes = block_bytes(event_buffers(D, &probe, &st));
   return DOTPE_OK;
 }
 
@@ -822,19 +945,6 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   hipStream_t s = ev->stream;
   FusedArgs a = make_args(ctx, ev);
   int rc;
-  // scratch sized for this event (kept with the event)
-  if (!ev->partials) {
-    if ((rc = dev_alloc(ctx, (void**)&ev->partials, (size_t)a.n_tiles * kNPart * 8, &ev->allocs,
-                        &ev->bytes)))
-      return rc;
-    if ((rc = dev_alloc(ctx, (void**)&ev->final_blk,
-                        (size_t)((a.n_tiles + 4095) / 4096) * kNPart * 8, &ev->allocs, &ev->bytes)))
-      return rc;
-    int64_t cap = std::max<int64_t>(1 << 20, 16 * (int64_t)ev->top_k);
-    if ((rc = dev_alloc(ctx, (void**)&ev->cand, (size_t)cap * 32, &ev->allocs, &ev->bytes)))
-      return rc;
-    ev->cand_cap = cap;
-  }
   a.state = ev->state;
   a.partials = ev->partials;
   a.cand = ev->cand;
@@ -853,6 +963,7 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
     int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
     if ((rc = launch_fused<kPilot>(ev->bank->prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
   }
+  hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, ev->state);
   HIP_OK(hipEventRecord(ev->ev_t[1], s));
   int64_t grid = round_up(a.n_tiles, 8);
   if ((rc = launch_fused<kEvidence>(ev->bank->prec, a, grid, s))) return rc;
@@ -901,15 +1012,9 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   if (ev->top_k > 0 && topk && ncand > 0) {
     int64_t n2 = 1;
     while (n2 < ncand) n2 <<= 1;
+    // the candidate buffer is a power of two at least as long as ncand
+    if (n2 > ev->cand_cap) return fail(DOTPE_E_DEVICE, "top-k buffer too small");
     double* buf = ev->cand;
-    void* extra = nullptr;
-    uint64_t xb = 0;
-    std::vector<void*> xo;
-    if (n2 > ev->cand_cap) {
-      if ((rc = dev_alloc(ctx, &extra, (size_t)n2 * 32, &xo, &xb))) return rc;
-      HIP_OK(hipMemcpyAsync(extra, ev->cand, ncand * 32, hipMemcpyDeviceToDevice, s));
-      buf = (double*)extra;
-    }
     if (n2 > ncand)
       hipLaunchKernelGGL(k_fill_cand, dim3((unsigned)((n2 - ncand + 255) / 256)), dim3(256), 0, s,
                          buf, ncand, n2);
@@ -921,10 +1026,6 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
     std::vector<double> h(take * 4);
     HIP_OK(hipMemcpyAsync(h.data(), buf, take * 32, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    if (extra) {
-      (void)hipFree(extra);
-      ctx->bytes -= xb;
-    }
     int cnt = 0;
     for (int64_t q = 0; q < take; ++q) {
       if (!(h[4 * q] >= thr)) break;
@@ -993,6 +1094,187 @@ int dotpe_debug_response(dotpe_ctx* ctx, const dotpe_event* ev, double* R, doubl
         R[dst] = Rg[src];
         R[dst + 1] = Rg[src + 1];
       }
+  return DOTPE_OK;
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: events submitted while others run are admitted FIFO as a slot and
+// a block of the device pool free up; each slot runs its event's staging and
+// evidence on its own stream, so the device work of concurrent events overlaps.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ServeJob {
+  dotpe_event_desc desc{};
+  std::vector<double> d, w, r, D, lat, lon, psi, ci, tg, lnwe;
+  std::vector<int64_t> sub_idx;
+  uint64_t bytes = 0;
+  dotpe_evidence_result res{};
+  std::vector<dotpe_sample> topk;
+  std::string err;
+};
+
+template <class T>
+const T* copy_in(std::vector<T>* v, const T* src, size_t n) {
+  if (!src) return nullptr;
+  v->assign(src, src + n);
+  return v->data();
+}
+
+}  // namespace
+
+struct dotpe_server {
+  dotpe_ctx* ctx = nullptr;
+  const dotpe_bank* bank = nullptr;
+  char* pool = nullptr;
+  uint64_t pool_len = 0;
+  std::vector<hipStream_t> streams;
+  std::unique_ptr<Scheduler> sched;
+  std::mutex mu;
+  std::map<int64_t, std::shared_ptr<ServeJob>> jobs;
+};
+
+extern "C" {
+
+int dotpe_server_create(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_server_desc* desc,
+                        dotpe_server** out) {
+  if (!ctx || !bank || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  int n_slots = (desc && desc->n_slots > 0) ? desc->n_slots : 4;
+  uint64_t pool = (desc && desc->pool_bytes) ? desc->pool_bytes : (uint64_t(8) << 30);
+  if (n_slots > 16) return fail(DOTPE_E_INVALID_ARG, "n_slots=%d (at most 16)", n_slots);
+  pool = pool / kBlockAlign * kBlockAlign;
+  if (pool < kBlockAlign) return fail(DOTPE_E_INVALID_ARG, "pool_bytes too small");
+  HIP_OK(hipSetDevice(ctx->device));
+  dotpe_server* srv = new dotpe_server();
+  srv->ctx = ctx;
+  srv->bank = bank;
+  int rc = dev_alloc(ctx, (void**)&srv->pool, pool, nullptr, nullptr);
+  if (rc) {
+    delete srv;
+    return rc;
+  }
+  srv->pool_len = pool;
+  for (int q = 0; q < n_slots; ++q) {
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (hipStream_t t : srv->streams) (void)hipStreamDestroy(t);
+      (void)hipFree(srv->pool);
+      ctx->bytes -= pool;
+      delete srv;
+      return fail(DOTPE_E_DEVICE, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+    }
+    srv->streams.push_back(st);
+  }
+  const int dev = ctx->device;
+  srv->sched.reset(new Scheduler(n_slots, pool, [dev](int) { (void)hipSetDevice(dev); }));
+  *out = srv;
+  return DOTPE_OK;
+}
+
+int dotpe_server_destroy(dotpe_server* srv) {
+  if (!srv) return DOTPE_OK;
+  srv->sched.reset();   // runs every submitted event to completion
+  for (hipStream_t t : srv->streams) (void)hipStreamDestroy(t);
+  if (srv->pool) {
+    (void)hipFree(srv->pool);
+    srv->ctx->bytes -= srv->pool_len;
+  }
+  delete srv;
+  return DOTPE_OK;
+}
+
+int dotpe_submit(dotpe_server* srv, const dotpe_event_desc* d, int64_t* ticket) {
+  if (!srv || !d || !ticket) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  EvDims D;
+  std::vector<int> terms;
+  int rc = event_dims(srv->bank, d, &D, &terms);
+  if (rc) return rc;
+  auto job = std::make_shared<ServeJob>();
+  {
+    dotpe_event probe;
+    EvStage st;
+    job->bytes = block_bytes(event_buffers(D, &probe, &st));
+  }
+  if (!srv->sched->admissible(job->bytes))
+    return fail(DOTPE_E_ADMISSION, "event needs %llu bytes; the serving pool holds %llu",
+                (unsigned long long)job->bytes, (unsigned long long)srv->pool_len);
+  const size_t nk = (size_t)d->n_det, nb = (size_t)srv->bank->n_b, ne = (size_t)d->n_ext;
+  job->desc = *d;
+  job->desc.d = copy_in(&job->d, d->d, nk * nb * 2);
+  job->desc.w = copy_in(&job->w, d->w, nk * nb);
+  job->desc.det_r = copy_in(&job->r, d->det_r, nk * 3);
+  job->desc.det_D = copy_in(&job->D, d->det_D, nk * 9);
+  job->desc.lat = copy_in(&job->lat, d->lat, ne);
+  job->desc.lon = copy_in(&job->lon, d->lon, ne);
+  job->desc.psi = copy_in(&job->psi, d->psi, ne);
+  job->desc.cos_iota = copy_in(&job->ci, d->cos_iota, ne);
+  job->desc.t_geo = copy_in(&job->tg, d->t_geo, ne);
+  job->desc.ln_w_ext = copy_in(&job->lnwe, d->ln_w_ext, ne);
+  job->desc.sub_idx = copy_in(&job->sub_idx, d->sub_idx, d->sub_idx ? (size_t)D.n_sub : 0);
+  job->desc.stream = nullptr;
+  job->topk.resize((size_t)std::max(0, d->top_k));
+  dotpe_server* s = srv;
+  int64_t t = srv->sched->submit(job->bytes, [s, job](int slot, uint64_t off) -> int {
+    dotpe_event* ev = nullptr;
+    int r = set_event_impl(s->ctx, s->bank, &job->desc, s->pool + off, job->bytes,
+                           s->streams[slot], &ev);
+    if (r == DOTPE_OK)
+      r = dotpe_evidence(s->ctx, ev, &job->res, job->topk.empty() ? nullptr : job->topk.data());
+    if (ev) dotpe_free_event(s->ctx, ev);
+    if (r != DOTPE_OK) job->err = g_err;
+    return r;
+  });
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->jobs[t] = job;
+  }
+  *ticket = t;
+  return DOTPE_OK;
+}
+
+int dotpe_poll(dotpe_server* srv, int64_t ticket, int32_t* done) {
+  if (!srv || !done) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  int r = srv->sched->poll(ticket);
+  if (r < 0) return fail(DOTPE_E_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+  *done = r;
+  return DOTPE_OK;
+}
+
+int dotpe_wait(dotpe_server* srv, int64_t ticket, dotpe_evidence_result* out, dotpe_sample* topk,
+               dotpe_ticket_info* info) {
+  if (!srv) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  std::shared_ptr<ServeJob> job;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(ticket);
+    if (it == srv->jobs.end())
+      return fail(DOTPE_E_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+    job = it->second;
+  }
+  JobTimes tm;
+  int rc = srv->sched->wait(ticket, &tm);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->jobs.erase(ticket);
+  }
+  if (rc == Scheduler::kUnknown)
+    return fail(DOTPE_E_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+  if (info) {
+    info->t_submit_ms = tm.t_submit_ms;
+    info->t_start_ms = tm.t_start_ms;
+    info->t_done_ms = tm.t_done_ms;
+    info->bytes = tm.bytes;
+    info->slot = tm.slot;
+    info->status = rc;
+  }
+  if (rc != DOTPE_OK) return fail(rc, "%s", job->err.c_str());
+  if (out) *out = job->res;
+  if (topk)
+    for (int q = 0; q < job->res.topk_count; ++q) topk[q] = job->topk[q];
   return DOTPE_OK;
 }
 

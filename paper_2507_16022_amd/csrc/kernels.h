@@ -1102,7 +1102,9 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
   double thr_ml = -INFINITY, thr_topk_glob = -INFINITY;
   if (MODE == kEvidence) {
-    if (a.cut_delta > 0.0) thr_ml = __longlong_as_double(a.state[0]) - a.cut_delta;
+    // the cut threshold is the one frozen after the pilot pass, so which
+    // triples are cut does not depend on the order in which tiles finish
+    if (a.cut_delta > 0.0) thr_ml = __longlong_as_double(a.state[3]) - a.cut_delta;
     thr_topk_glob = order_value(a.state[1]) - a.topk_window;
   }
   // the pilot only needs pairs that can raise the running maximum

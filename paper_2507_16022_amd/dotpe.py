@@ -68,6 +68,17 @@ class EvidenceResult(ctypes.Structure):
                 ("t_fused_ms", ctypes.c_double)]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_uint64)]
+
+
+class TicketInfo(ctypes.Structure):
+    _fields_ = [("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double), ("bytes", ctypes.c_uint64),
+                ("slot", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 class Sample(ctypes.Structure):
     _fields_ = [("i", ctypes.c_int64), ("e", ctypes.c_int64), ("ln_p", ctypes.c_double),
                 ("o_best", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -89,6 +100,17 @@ SYMBOLS = {
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "dotpe_evidence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(EvidenceResult), ctypes.c_void_p]),
+    "dotpe_event_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(EventDesc),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "dotpe_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ServerDesc),
+                                            ctypes.POINTER(ctypes.c_void_p)]),
+    "dotpe_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "dotpe_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(EventDesc),
+                                     ctypes.POINTER(ctypes.c_int64)]),
+    "dotpe_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
+    "dotpe_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(EvidenceResult),
+                                   ctypes.c_void_p, ctypes.POINTER(TicketInfo)]),
     "dotpe_debug_distmarg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "dotpe_debug_response": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -233,48 +255,64 @@ class Bank:
             pass
 
 
+def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=1.0, n_norm=0.0,
+                sub_start=0, sub_count=0, sub_idx=None, cut_delta=0.0, top_k=0, topk_window=40.0,
+                stream=None):
+    """EventDesc over host copies of the inputs; returns (desc, arrays to keep alive)."""
+    keep = []
+
+    def hp(a, dt=np.float64):
+        arr, p = _host(a, dt)
+        keep.append(arr)
+        return arr, p
+
+    dc, pd = hp(np.asarray(d, dtype=np.complex128), np.complex128)
+    _, pw = hp(w)
+    _, pr = hp(det_r)
+    _, pD = hp(det_D)
+    n_ext = len(ext["lat"])
+    _, plat = hp(ext["lat"])
+    _, plon = hp(ext["lon"])
+    _, ppsi = hp(ext["psi"])
+    _, pci = hp(ext["cos_iota"])
+    _, ptg = hp(ext["t_geo"])
+    plw = hp(ln_w_ext)[1] if ln_w_ext is not None else None
+    psub = None
+    if sub_idx is not None:
+        si, psub = hp(sub_idx, np.int64)
+        sub_count = len(si)
+    if stream is not None and not isinstance(stream, int):
+        stream = stream.cuda_stream
+    desc = EventDesc(dc.shape[0], int(n_phi), pd, pw, pr, pD, n_ext, plat, plon, ppsi, pci, ptg,
+                     plw, float(d_max), float(d0), float(n_norm), int(sub_start),
+                     int(sub_count), psub, float(cut_delta), int(top_k), 0,
+                     float(topk_window), stream)
+    return desc, keep
+
+
+def _result(r, arr):
+    out = {name: getattr(r, name) for name, _ in EvidenceResult._fields_}
+    n = r.topk_count
+    out["topk_i"] = np.array([arr[q].i for q in range(n)], dtype=np.int64)
+    out["topk_e"] = np.array([arr[q].e for q in range(n)], dtype=np.int64)
+    out["topk_lnp"] = np.array([arr[q].ln_p for q in range(n)])
+    out["topk_o"] = np.array([arr[q].o_best for q in range(n)], dtype=np.int32)
+    return out
+
+
 class Event:
-    def __init__(self, ctx, bank, d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0,
-                 d0=1.0, n_norm=0.0, sub_start=0, sub_count=0, sub_idx=None, cut_delta=0.0,
-                 top_k=0, topk_window=40.0, stream=None):
+    def __init__(self, ctx, bank, **kw):
         lib = load_library()
         self.ctx, self.bank = ctx, bank
-        keep = []
-
-        def hp(a, dt=np.float64):
-            arr, p = _host(a, dt)
-            keep.append(arr)
-            return arr, p
-
-        dc, pd = hp(np.asarray(d, dtype=np.complex128), np.complex128)
-        _, pw = hp(w)
-        _, pr = hp(det_r)
-        _, pD = hp(det_D)
-        n_ext = len(ext["lat"])
-        _, plat = hp(ext["lat"])
-        _, plon = hp(ext["lon"])
-        _, ppsi = hp(ext["psi"])
-        _, pci = hp(ext["cos_iota"])
-        _, ptg = hp(ext["t_geo"])
-        plw = hp(ln_w_ext)[1] if ln_w_ext is not None else None
-        psub = None
-        if sub_idx is not None:
-            si, psub = hp(sub_idx, np.int64)
-            sub_count = len(si)
-        if stream is not None and not isinstance(stream, int):
-            stream = stream.cuda_stream
-        desc = EventDesc(dc.shape[0], int(n_phi), pd, pw, pr, pD, n_ext, plat, plon, ppsi, pci, ptg,
-                         plw, float(d_max), float(d0), float(n_norm), int(sub_start),
-                         int(sub_count), psub, float(cut_delta), int(top_k), 0,
-                         float(topk_window), stream)
+        desc, keep = _event_desc(**kw)
         out = ctypes.c_void_p()
         _check(lib.dotpe_set_event(ctx.handle, bank.handle, ctypes.byref(desc), ctypes.byref(out)))
         self._h = out
-        self.n_ext = n_ext
-        self.n_sub = sub_count if sub_count else bank.n_wf
-        self.n_phi = int(n_phi)
-        self.n_det = dc.shape[0]
-        self.top_k = int(top_k)
+        self.n_ext = desc.n_ext
+        self.n_sub = desc.sub_count if desc.sub_count else bank.n_wf
+        self.n_phi = desc.n_phi
+        self.n_det = desc.n_det
+        self.top_k = desc.top_k
 
     @property
     def handle(self):
@@ -319,13 +357,7 @@ class Event:
         arr = (Sample * max(k, 1))()
         _check(load_library().dotpe_evidence(self.ctx.handle, self._h, ctypes.byref(r),
                                              ctypes.cast(arr, ctypes.c_void_p) if k else None))
-        out = {name: getattr(r, name) for name, _ in EvidenceResult._fields_}
-        n = r.topk_count
-        out["topk_i"] = np.array([arr[q].i for q in range(n)], dtype=np.int64)
-        out["topk_e"] = np.array([arr[q].e for q in range(n)], dtype=np.int64)
-        out["topk_lnp"] = np.array([arr[q].ln_p for q in range(n)])
-        out["topk_o"] = np.array([arr[q].o_best for q in range(n)], dtype=np.int32)
-        return out
+        return _result(r, arr)
 
     def response(self):
         """(R [n_ext, n_det, n_modes] complex, t [n_ext, n_det]) from the device."""
@@ -334,3 +366,62 @@ class Event:
         _check(load_library().dotpe_debug_response(self.ctx.handle, self._h, R.ctypes.data,
                                                     t.ctypes.data))
         return R[..., 0] + 1j * R[..., 1], t
+
+
+class Server:
+    """Continuous admission of events against a resident bank (dotpe_submit /
+    dotpe_poll / dotpe_wait); see include/dotpe.h."""
+
+    def __init__(self, ctx, bank, n_slots=4, pool_bytes=0):
+        self.ctx, self.bank = ctx, bank
+        h = ctypes.c_void_p()
+        desc = ServerDesc(int(n_slots), 0, int(pool_bytes))
+        _check(load_library().dotpe_server_create(ctx.handle, bank.handle, ctypes.byref(desc),
+                                                  ctypes.byref(h)))
+        self._h = h
+        self._top_k = {}
+
+    def event_bytes(self, **kw):
+        desc, keep = _event_desc(**kw)
+        n = ctypes.c_uint64()
+        _check(load_library().dotpe_event_bytes(self.ctx.handle, self.bank.handle,
+                                                ctypes.byref(desc), ctypes.byref(n)))
+        return int(n.value)
+
+    def submit(self, **kw):
+        """Queue an event (same keywords as Context.set_event); returns its ticket."""
+        desc, keep = _event_desc(**kw)
+        t = ctypes.c_int64()
+        _check(load_library().dotpe_submit(self._h, ctypes.byref(desc), ctypes.byref(t)))
+        self._top_k[t.value] = desc.top_k
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int32()
+        _check(load_library().dotpe_poll(self._h, int(ticket), ctypes.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket):
+        """(result dict as Event.evidence(), timing dict) of a submitted event."""
+        r = EvidenceResult()
+        info = TicketInfo()
+        k = self._top_k.pop(ticket, 0)
+        arr = (Sample * max(k, 1))()
+        rc = load_library().dotpe_wait(self._h, int(ticket), ctypes.byref(r),
+                                       ctypes.cast(arr, ctypes.c_void_p) if k else None,
+                                       ctypes.byref(info))
+        _check(rc)
+        times = {name: getattr(info, name) for name, _ in TicketInfo._fields_}
+        return _result(r, arr), times
+
+    def close(self):
+        if self._h:
+            load_library().dotpe_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

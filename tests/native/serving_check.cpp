@@ -1,0 +1,99 @@
+// Host-only checks of the serving scheduler (pool map, FIFO admission by
+// memory, slot limit, drain on destruction).  Built with g++ by the tests.
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "serving.h"
+
+#define CHECK(c)                                                   \
+  do {                                                             \
+    if (!(c)) {                                                    \
+      std::fprintf(stderr, "FAIL %s:%d %s\n", __FILE__, __LINE__, #c); \
+      std::exit(1);                                                \
+    }                                                              \
+  } while (0)
+
+using dotpe::PoolMap;
+using dotpe::Scheduler;
+
+static void pool_checks() {
+  PoolMap p(4096 + 100);            // rounded down to whole 256-byte units
+  CHECK(p.size() == 4096);
+  uint64_t a, b, c, d;
+  CHECK(p.alloc(1000, &a) && a == 0);        // 1024 bytes
+  CHECK(p.alloc(256, &b) && b == 1024);
+  CHECK(p.alloc(1, &c) && c == 1280);        // 256 bytes
+  CHECK(p.used_bytes() == 1536);
+  CHECK(!p.alloc(4096, &d));
+  CHECK(p.fits(2560) && !p.fits(2561));
+  p.release(b);                               // hole of 256 between a and c
+  CHECK(p.alloc(200, &d) && d == 1024);       // first fit takes the hole
+  p.release(d);
+  p.release(a);                               // coalesces with the hole: [0, 1280)
+  CHECK(p.fits(1280));
+  CHECK(p.alloc(1280, &d) && d == 0);
+  p.release(d);
+  p.release(c);                               // everything free again, one block
+  CHECK(p.n_free_blocks() == 1 && p.used_bytes() == 0 && p.fits(4096));
+  p.release(12345);                           // unknown offsets are ignored
+  CHECK(p.used_bytes() == 0);
+}
+
+static void sched_checks() {
+  const uint64_t pool = 1 << 20;
+  std::atomic<int> running{0}, max_running{0};
+  std::atomic<uint64_t> bytes_live{0}, max_bytes{0};
+  std::mutex m;
+  std::vector<int64_t> start_order;
+  std::vector<int64_t> tickets;
+  {
+    Scheduler s(3, pool, nullptr);
+    CHECK(s.admissible(pool) && !s.admissible(pool + 1));
+    // sizes: the 4th job needs most of the pool, so it waits until the
+    // first three are done; the small jobs behind it must not overtake it
+    std::vector<uint64_t> sizes = {200000, 200000, 200000, 900000, 10000, 10000, 10000, 500000,
+                                   500000, 1000};
+    for (size_t q = 0; q < sizes.size(); ++q) {
+      const uint64_t n = sizes[q];
+      const int64_t id = (int64_t)q;
+      tickets.push_back(s.submit(n, [&, n, id](int slot, uint64_t off) {
+        CHECK(slot >= 0 && slot < 3);
+        CHECK(off % PoolMap::kPoolAlign == 0 && off + n <= pool);
+        {
+          std::lock_guard<std::mutex> lk(m);
+          start_order.push_back(id);
+        }
+        int r = ++running;
+        int mr = max_running.load();
+        while (r > mr && !max_running.compare_exchange_weak(mr, r)) {}
+        uint64_t b = (bytes_live += PoolMap::round(n));
+        uint64_t mb = max_bytes.load();
+        while (b > mb && !max_bytes.compare_exchange_weak(mb, b)) {}
+        std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        bytes_live -= PoolMap::round(n);
+        --running;
+        return (int)id;
+      }));
+    }
+    // wait returns each job's status; a waited ticket is forgotten
+    dotpe::JobTimes t;
+    CHECK(s.wait(tickets[0], &t) == 0);
+    CHECK(t.t_start_ms >= t.t_submit_ms && t.t_done_ms >= t.t_start_ms + 15.0);
+    CHECK(s.poll(tickets[0]) == -1 && s.wait(tickets[0], nullptr) == Scheduler::kUnknown);
+    CHECK(s.wait(tickets[3], nullptr) == 3);
+    // tickets 4.. are left for the destructor to drain
+  }
+  CHECK(start_order.size() == 10);
+  for (size_t q = 0; q < start_order.size(); ++q) CHECK(start_order[q] == (int64_t)q);   // FIFO
+  CHECK(max_running.load() <= 3 && max_running.load() >= 2);
+  CHECK(max_bytes.load() <= pool);
+}
+
+int main() {
+  pool_checks();
+  sched_checks();
+  std::printf("serving_check OK\n");
+  return 0;
+}

@@ -35,3 +35,42 @@ def test_struct_layouts():
     assert ctypes.sizeof(dotpe.BankDesc) == 8 + 4 + 4 + 5 * 8 + 4 + 4
     assert ctypes.sizeof(dotpe.Sample) == 32
     assert ctypes.sizeof(dotpe.EvidenceResult) == 7 * 8 + 3 * 8 + 4 * 4 + 2 * 8
+
+
+STRUCTS = {
+    "dotpe_bank_desc": dotpe.BankDesc,
+    "dotpe_event_desc": dotpe.EventDesc,
+    "dotpe_evidence_result": dotpe.EvidenceResult,
+    "dotpe_sample": dotpe.Sample,
+    "dotpe_server_desc": dotpe.ServerDesc,
+    "dotpe_ticket_info": dotpe.TicketInfo,
+}
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """Every ctypes mirror has the size and field offsets gcc gives the header's structs."""
+    import shutil
+    import subprocess
+    import pytest
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "dotpe.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n"):
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, py in STRUCTS.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
