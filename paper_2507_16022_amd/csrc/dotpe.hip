@@ -55,6 +55,7 @@ struct dotpe_ctx {
   std::atomic<uint64_t> bytes{0};   // serving slot threads also release through it
   uint64_t own_bytes = 0;    // the context's own tables (not charged to the budget)
   double* dist_tab = nullptr;
+  DistParams* dist_prm = nullptr;   // device copy of geom, ghx, ghw
   DistTableGeom geom{};
   double ghx[kGH], ghw[kGH];
 };
@@ -226,7 +227,7 @@ int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
 
 // (h|h) term codes: output r < NR owns K block r (32 slots); see kernels.h
 int build_hh_terms(const ModeTables& mt, int n_det, std::vector<int>* terms, int* KH) {
-  const int nhb = mt.G == 1 ? 4 : kMaxNR + 1;
+  const int nhb = kMaxNR + 1;
   *KH = nhb * 32;
   terms->assign(*KH, 0);
   const int NR = 2 * mt.ND - 1;
@@ -310,7 +311,7 @@ int launch_fused_t(const FusedArgs& a, int64_t grid, hipStream_t s) {
       (void)hipGetLastError();
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_lnl_fused<PREC, G, MODE>), dim3((unsigned)grid), dim3(256), sh, s, a);
+  hipLaunchKernelGGL((k_lnl_fused<PREC, G, MODE>), dim3((unsigned)grid), dim3(TL::NT), sh, s, a);
   HIP_OK(hipGetLastError());
   return DOTPE_OK;
 }
@@ -380,11 +381,7 @@ FusedArgs make_args(dotpe_ctx* ctx, dotpe_event* ev) {
   a.phase_cs = ev->phase_cs;
   a.ln_nphi = std::log((double)ev->n_phi);
   a.dist.tab = ctx->dist_tab;
-  a.dist.geom = ctx->geom;
-  for (int k = 0; k < kGH; ++k) {
-    a.dist.ghx[k] = ctx->ghx[k];
-    a.dist.ghw[k] = ctx->ghw[k];
-  }
+  a.dist.prm = ctx->dist_prm;
   a.r0 = ev->d0 / ev->d_max;
   a.cut_delta = ev->cut_delta;
   a.topk_window = ev->topk_window;
@@ -444,7 +441,9 @@ int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
   DistTableGeom& g = ctx->geom;
   size_t ntab = (size_t)g.ncol * g.nt;
   ctx->budget = 0;
-  int rc = dev_alloc(ctx, (void**)&ctx->dist_tab, ntab * sizeof(double), nullptr, nullptr);
+  int rc = dev_alloc(ctx, (void**)&ctx->dist_tab, ntab * sizeof(double) + sizeof(DistParams),
+                     nullptr, nullptr);
+  ctx->dist_prm = (DistParams*)(ctx->dist_tab + ntab);
   ctx->budget = hbm_budget_bytes;
   ctx->own_bytes = ctx->bytes;
   if (rc) {
@@ -455,7 +454,14 @@ int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
   hipLaunchKernelGGL(k_build_dist_table, dim3((unsigned)((ntab + 255) / 256)), dim3(256), 0,
                      ctx->stream, ctx->dist_tab, g);
   gauss_hermite(kGH, ctx->ghx, ctx->ghw);
-  e = hipStreamSynchronize(ctx->stream);
+  DistParams prm;
+  prm.geom = g;
+  for (int k = 0; k < kGH; ++k) {
+    prm.ghx[k] = ctx->ghx[k];
+    prm.ghw[k] = ctx->ghw[k];
+  }
+  e = hipMemcpyAsync(ctx->dist_prm, &prm, sizeof(prm), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     dotpe_destroy(ctx);
     return fail(DOTPE_E_DEVICE, "distance table build: %s", hipGetErrorString(e));
@@ -1056,11 +1062,7 @@ int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const doub
   hipStream_t s = ctx->stream;
   DistArgs da;
   da.tab = ctx->dist_tab;
-  da.geom = ctx->geom;
-  for (int k = 0; k < kGH; ++k) {
-    da.ghx[k] = ctx->ghx[k];
-    da.ghw[k] = ctx->ghw[k];
-  }
+  da.prm = ctx->dist_prm;
   hipError_t e = hipMemcpyAsync(buf, dh, n * 8, hipMemcpyHostToDevice, s);
   if (!e) e = hipMemcpyAsync(buf + n, hh, n * 8, hipMemcpyHostToDevice, s);
   if (!e) {

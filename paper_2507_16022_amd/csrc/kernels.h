@@ -56,10 +56,15 @@ struct ModeTables {
   int pdiag[kMaxC];                // pair index of (c, c)
 };
 
-struct DistArgs {
-  const double* tab;
+// distance-rule parameters, kept in device memory next to the table (passed
+// by pointer so that no kernel argument has to be copied to private memory)
+struct DistParams {
   DistTableGeom geom;
   double ghx[kGH], ghw[kGH];
+};
+struct DistArgs {
+  const double* tab;
+  const DistParams* prm;
 };
 
 // ---------------------------------------------------------------------------
@@ -136,7 +141,7 @@ __global__ void k_debug_distmarg(int64_t n, const double* dh, const double* hh, 
                                  DistArgs da, double* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = dr_ln_marg(dh[i], hh[i], r0, da.tab, da.geom, da.ghx, da.ghw);
+  out[i] = dr_ln_marg(dh[i], hh[i], r0, da.tab, da.prm->geom, da.prm->ghx, da.prm->ghw);
 }
 
 // ---------------------------------------------------------------------------
@@ -586,18 +591,22 @@ struct FusedArgs {
 
 template <int PREC>
 struct Pol;
+// FP64: 4 waves (2 x 2), each 32 x 16 pairs; 64 x 32 tile
 template <>
 struct Pol<kFP64> {
   typedef double T;
   typedef f64x4 Acc;
-  static constexpr int NA = 1, NB = 2, PITCH = 33, BM = 2, BN = 1;
+  static constexpr int NA = 1, NB = 2, PITCH = 33, BM = 2, BN = 1, WM = 2, WN = 2;
 };
+// split precisions: 8 waves (2 x 4), each 32 x 16 pairs; 64 x 64 tile.  Two
+// waves per SIMD: the accumulators of a 32 x 16 wave tile (4 m groups x re/im
+// plus 7 (h|h) outputs) leave room for two waves' registers.
 template <>
 struct Pol<kFP16X2> {
   typedef uint16_t T;
   typedef f32x4 Acc;
   // B_im = [Bi | Br] is formed in registers from B_re = [Br | -Bi]
-  static constexpr int NA = 2, NB = 2, PITCH = 40, BM = 2, BN = 2;
+  static constexpr int NA = 2, NB = 2, PITCH = 40, BM = 2, BN = 1, WM = 2, WN = 4;
 };
 template <>
 struct Pol<kBF16X2> : Pol<kFP16X2> {};
@@ -605,23 +614,32 @@ struct Pol<kBF16X2> : Pol<kFP16X2> {};
 template <int PREC>
 struct Tile {
   typedef Pol<PREC> P;
-  static constexpr int TM = 2 * 16 * P::BM;   // rows per workgroup tile
-  static constexpr int TN = 2 * 16 * P::BN;   // columns per workgroup tile
+  static constexpr int NW = P::WM * P::WN;           // waves per workgroup
+  static constexpr int NT = 64 * NW;                 // threads per workgroup
+  static constexpr int TM = P::WM * 16 * P::BM;      // rows per workgroup tile
+  static constexpr int TN = P::WN * 16 * P::BN;      // columns per workgroup tile
   static constexpr int STAGE_ELEMS = (P::NA * TM + P::NB * TN) * P::PITCH;
   static constexpr int STAGE_BYTES = STAGE_ELEMS * (int)sizeof(typename P::T);
   static constexpr int ACC_T_BYTES = (PREC == kFP64) ? 8 : 4;
-  static constexpr int EPI_STRIDE = 2 * kMaxG + kMaxNR + 2;   // 17 (odd: spreads banks)
-  static constexpr int EPI_BYTES = 4 * 256 * EPI_STRIDE * ACC_T_BYTES;
-  static constexpr int UNION_BYTES = (2 * STAGE_BYTES > EPI_BYTES) ? 2 * STAGE_BYTES : EPI_BYTES;
+  // epilogue batches: each lane offers 2 of its pairs at a time, so a batch
+  // holds at most 128 pairs per wave; survivors' records (X_g re/im, the
+  // (h|h) outputs) have an odd stride to spread LDS banks
+  static constexpr int REC = 2 * kMaxG + kMaxNR + 2;   // 17
+  static constexpr int BATCH = 128 * NW;
+  static constexpr int EPI_BYTES = BATCH * REC * ACC_T_BYTES;
+  static constexpr int NSB = 3;     // LDS stage buffers (chunks j, j+1, j+2)
+  static constexpr int UNION_BYTES = (NSB * STAGE_BYTES > EPI_BYTES) ? NSB * STAGE_BYTES : EPI_BYTES;
   static constexpr int ROWD_OFF = (UNION_BYTES + 15) / 16 * 16;    // double [TM][4]
   static constexpr int COLD_OFF = ROWD_OFF + TM * 4 * 8;           // double [TN][3]
-  static constexpr int LIST_OFF = COLD_OFF + TN * 3 * 8;           // uint16 [1024]
-  static constexpr int CNT_OFF = LIST_OFF + 1024 * 2;              // int counter, u64 max
+  static constexpr int LIST_OFF = COLD_OFF + TN * 3 * 8;           // uint16 [BATCH]
+  static constexpr int RED_OFF = (LIST_OFF + BATCH * 2 + 15) / 16 * 16;   // double [NW][kNPart]
+  static constexpr int CNT_OFF = RED_OFF + NW * kNPart * 8;        // int counter, u64 max
   static constexpr int MAIN_BYTES = CNT_OFF + 16;
   static constexpr int PIECE_ELEMS = 16 / (int)sizeof(typename P::T);   // 16-byte pieces
   static constexpr int PIECES_PER_ROW = 32 / PIECE_ELEMS;
   static constexpr int PIECES = (P::NA * TM + P::NB * TN) * PIECES_PER_ROW;
-  static constexpr int PIECES_PER_THREAD = PIECES / 256;
+  static constexpr int PIECES_PER_THREAD = PIECES / NT;
+  static_assert(PIECES % NT == 0, "pieces must split evenly over the threads");
 };
 
 // B_im fragment from the B_re fragment of a 16x16x32 operand: lanes 0-31
@@ -692,13 +710,14 @@ struct EvAcc {
 
 // full evaluation of one pair given X_g and the (h|h) coefficients: phase
 // loop, cut, distance marginalisation; returns ln p (-inf when nothing kept)
-template <int MODE>
+template <int MODE, int G>
 __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie, int64_t e,
-                            const double2* X, double S0, const double* Sr, const double* Si,
-                            double lnw, double thr_ml, EvAcc& ev, int& o_best) {
+                            const double2 (&X)[G], double S0, const double (&Sr)[kMaxND],
+                            const double (&Si)[kMaxND], double lnw, double thr_ml, EvAcc& ev,
+                            int& o_best) {
   constexpr bool EVAL = MODE == kEval;
   const ModeTables& mt = a.mt;
-  const int G = mt.G;
+  const int ND = mt.ND;
   o_best = 0;
   Lse lse;
   lse.init();
@@ -706,14 +725,18 @@ __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie
   const double thr2 = 2.0 * thr_ml;
   for (int o = 0; o < a.n_phi; ++o) {
     double dh = 0.0;
+#pragma unroll
     for (int g = 0; g < G; ++g) {
       const double* cs = lds_cs + ((mt.gm[g] - 1) * a.n_phi + o) * 2;
       dh += X[g].x * cs[0] - X[g].y * cs[1];
     }
     double hh = S0;
-    for (int d = 1; d < mt.ND; ++d) {
-      const double* cs = lds_cs + ((d - 1) * a.n_phi + o) * 2;
-      hh += 2.0 * (Sr[d] * cs[0] + Si[d] * cs[1]);
+#pragma unroll
+    for (int d = 1; d < kMaxND; ++d) {
+      if (d < ND) {
+        const double* cs = lds_cs + ((d - 1) * a.n_phi + o) * 2;
+        hh += 2.0 * (Sr[d] * cs[0] + Si[d] * cs[1]);
+      }
     }
     hh = fmax(hh, 0.0);
     if (EVAL && a.trip_out) {
@@ -731,7 +754,7 @@ __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie
       ev.drop.add(x + fabsf(x) * 1e-6f + 1e-5f);   // rounding margin keeps it a bound
       continue;
     }
-    double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, a.dist.geom, a.dist.ghx, a.dist.ghw);
+    double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, a.dist.prm->geom, a.dist.prm->ghx, a.dist.prm->ghw);
     if (v > best) { best = v; o_best = o; }
     lse.add(v);
     if (!EVAL) ev.n_marg += 1.0;
@@ -751,12 +774,12 @@ __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie
 }
 
 template <int PREC, int G, int MODE>
-__global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
+__global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   constexpr bool EVAL = MODE == kEval;
   // (h|h) outputs: a single m group has S0 only; otherwise up to 7, padded
   // to an even number of K blocks
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;
-  constexpr int NHB = (G == 1) ? 4 : kMaxNR + 1;
+  constexpr int NHB = kMaxNR + 1;   // >= R + 2: every (d|h) step keeps the pipeline full
   // register stage sets: loads run R chunks ahead (FP64 pieces are twice as
   // many per thread, so it keeps two sets to stay within the register file)
   constexpr int R = (PREC == kFP64) ? 2 : 4;
@@ -764,13 +787,13 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   typedef Tile<PREC> TL;
   typedef typename P::T T;
   typedef typename P::Acc Acc;
-  constexpr int TM = TL::TM, TN = TL::TN, PITCH = P::PITCH;
+  constexpr int TM = TL::TM, TN = TL::TN, PITCH = P::PITCH, NT = TL::NT, NW = TL::NW;
   extern __shared__ __align__(16) unsigned char smem[];
   T* stage = (T*)smem;
   double* lds_cs = (double*)(smem + TL::MAIN_BYTES);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / P::WN, wn = wave % P::WN;
 
   // workgroup -> tile: spread consecutive ids over the XCDs so that each XCD
   // walks a contiguous band of tiles, then raster in groups of 8 tile rows
@@ -798,7 +821,7 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   const int64_t row0 = tm * TM, col0 = tn * TN;
 
   // phase table to LDS
-  for (int t = tid; t < kMaxM * a.n_phi * 2; t += 256) lds_cs[t] = a.phase_cs[t];
+  for (int t = tid; t < kMaxM * a.n_phi * 2; t += NT) lds_cs[t] = a.phase_cs[t];
 
   // per-row / per-column scalars: issued first, stored after the first
   // chunk's loads are in flight
@@ -853,7 +876,7 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
     constexpr int ES = (int)sizeof(T);
 #pragma unroll
     for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
-      int p = tid + 256 * q;
+      int p = tid + NT * q;
       int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
       if (rowsel < P::NA * TM) {
         int arr = rowsel / TM, r = rowsel % TM;
@@ -870,12 +893,11 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       }
     }
   }
-  const int ndh = a.n_chunks;        // (d|h) chunks (even)
+  const int ndh = a.n_chunks;        // (d|h) chunks (a multiple of 4)
   const int nch = ndh + NHB;         // then the (h|h) blocks
-  // R register stage sets: while chunk j is multiplied out of LDS, chunks
-  // j+1 .. j+R are in flight (set j mod R holds chunk j).  Separate arrays
-  // picked at compile time, and load sites that are each statically a (d|h)
-  // or an (h|h) load, keep the sets and the address arrays in registers.
+  constexpr int ES = (int)sizeof(T);
+  // R register stage sets (set c mod R holds chunk c).  Separate arrays picked
+  // at compile time keep them in registers.
   u32x4 st0[TL::PIECES_PER_THREAD], st1[TL::PIECES_PER_THREAD];
   u32x4 st2[TL::PIECES_PER_THREAD], st3[TL::PIECES_PER_THREAD];
   auto set = [&](auto slot) -> u32x4* {
@@ -885,21 +907,20 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
     else if constexpr (k == 2) return st2;
     else return st3;
   };
-  auto load_dh = [&](u32x4* stq, int ch) {
-    const int64_t off = (int64_t)ch * 32 * sizeof(T);
-#pragma unroll
-    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) stq[q] = *(gu4*)(srcp[q] + off);
-  };
-  auto load_hh = [&](u32x4* stq, int hb) {
-    const int off = hb * 32 * (int)sizeof(T);
-#pragma unroll
-    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) stq[q] = *(gu4*)(srch[q] + off);
-  };
-  auto store_from = [&](const u32x4* st, int buf) {
-    T* base = stage + buf * TL::STAGE_ELEMS;
+  // chunk c into a stage set: a (d|h) chunk for c < ndh, else (h|h) block c - ndh
+  auto load = [&](u32x4* stq, int c) {
+    const bool hh = c >= ndh;
+    const int64_t od = (int64_t)c * 32 * ES, oh = (int64_t)(c - ndh) * 32 * ES;
 #pragma unroll
     for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
-      int p = tid + 256 * q;
+      gbyte* pq = hh ? srch[q] + oh : srcp[q] + od;
+      stq[q] = *(gu4*)pq;
+    }
+  };
+  auto store_from = [&](const u32x4* st, T* base) {
+#pragma unroll
+    for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
+      int p = tid + NT * q;
       int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
       T* dst = base + rowsel * PITCH + piece * TL::PIECE_ELEMS;
       if constexpr (PREC == kFP64) {
@@ -912,15 +933,44 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       }
     }
   };
+  // fragments of one chunk (split precisions): A hi/lo, B_re hi/lo and the
+  // B_im hi/lo formed from B_re; read one chunk ahead of the MFMAs
+  struct Frag {
+    uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
+  };
+  Frag fr0, fr1;
+  auto frag = [&](auto fi) -> Frag& {
+    if constexpr (decltype(fi)::value % 2 == 0) return fr0;
+    else return fr1;
+  };
+  auto read_frag = [&](Frag& f, const T* base) {
+    if constexpr (PREC != kFP64) {
+      const T* As = base;
+      const T* Bs = base + P::NA * TM * PITCH;
+      const int koff = 8 * (lane >> 4);
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm) {
+        int rr = wm * 16 * P::BM + bm * 16 + (lane & 15);
+        f.ah[bm] = *(const uint4*)(As + rr * PITCH + koff);
+        f.al[bm] = *(const uint4*)(As + (TM + rr) * PITCH + koff);
+      }
+#pragma unroll
+      for (int bn = 0; bn < P::BN; ++bn) {
+        int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
+        f.brh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
+        f.brl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
+        f.bih[bn] = bim_from_bre(f.brh[bn], lane);
+        f.bil[bn] = bim_from_bre(f.brl[bn], lane);
+      }
+    }
+  };
   // (d|h) chunk: complex product, 3 split products per real product
-  auto compute_dh = [&](int buf, auto gi) {
+  // (split precisions: from the fragments; FP64: from the LDS buffer)
+  auto compute_dh = [&](const Frag& f, const T* base, auto gi) {
     constexpr int g = decltype(gi)::value;
-    const T* base = stage + buf * TL::STAGE_ELEMS;
-    const T* As = base;
-    const T* Bs = base + P::NA * TM * PITCH;
     if constexpr (PREC == kFP64) {
-      const double* Ad = (const double*)As;
-      const double* Bd = (const double*)Bs;
+      const double* Ad = (const double*)base;
+      const double* Bd = (const double*)(base + P::NA * TM * PITCH);
 #pragma unroll
       for (int s8 = 0; s8 < 8; ++s8) {
         double av[P::BM], brv[P::BN], biv[P::BN];
@@ -942,57 +992,38 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
           }
       }
     } else {
-      uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
-      const int koff = 8 * (lane >> 4);
-#pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm) {
-        int rr = wm * 16 * P::BM + bm * 16 + (lane & 15);
-        ah[bm] = *(const uint4*)(As + rr * PITCH + koff);
-        al[bm] = *(const uint4*)(As + (TM + rr) * PITCH + koff);
-      }
-#pragma unroll
-      for (int bn = 0; bn < P::BN; ++bn) {
-        int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-        brh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
-        brl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
-        bih[bn] = bim_from_bre(brh[bn], lane);
-        bil[bn] = bim_from_bre(brl[bn], lane);
-      }
       // issue order: the three split products of one accumulator are
       // separated by the products of the 2 x BM x BN independent ones
 #pragma unroll
       for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], al[bm], brh[bn]);
-          mma<PREC>(acc[g][bm][bn][1], al[bm], bih[bn]);
+          mma<PREC>(acc[g][bm][bn][0], f.al[bm], f.brh[bn]);
+          mma<PREC>(acc[g][bm][bn][1], f.al[bm], f.bih[bn]);
         }
 #pragma unroll
       for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], ah[bm], brl[bn]);
-          mma<PREC>(acc[g][bm][bn][1], ah[bm], bil[bn]);
+          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brl[bn]);
+          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bil[bn]);
         }
 #pragma unroll
       for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], ah[bm], brh[bn]);
-          mma<PREC>(acc[g][bm][bn][1], ah[bm], bih[bn]);
+          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brh[bn]);
+          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bih[bn]);
         }
     }
   };
   // (h|h) block r: real product of the row and column (h|h) operands
-  auto compute_hh = [&](int buf, auto ri) {
+  auto compute_hh = [&](const Frag& f, const T* base, auto ri) {
     constexpr int r = decltype(ri)::value;
     if constexpr (r < NRT) {
-      const T* base = stage + buf * TL::STAGE_ELEMS;
-      const T* As = base;
-      const T* Bs = base + P::NA * TM * PITCH;
       if constexpr (PREC == kFP64) {
-        const double* Ad = (const double*)As;
-        const double* Bd = (const double*)Bs;
+        const double* Ad = (const double*)base;
+        const double* Bd = (const double*)(base + P::NA * TM * PITCH);
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8) {
           double av[P::BM], bv[P::BN];
@@ -1009,78 +1040,88 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
               acch[r][bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], bv[bn], acch[r][bm][bn], 0, 0, 0);
         }
       } else {
-        uint4 ah[P::BM], al[P::BM], bh[P::BN], bl[P::BN];
-        const int koff = 8 * (lane >> 4);
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm) {
-          int rr = wm * 16 * P::BM + bm * 16 + (lane & 15);
-          ah[bm] = *(const uint4*)(As + rr * PITCH + koff);
-          al[bm] = *(const uint4*)(As + (TM + rr) * PITCH + koff);
-        }
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) {
-          int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-          bh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
-          bl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
-        }
 #pragma unroll
         for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], al[bm], bh[bn]);
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.al[bm], f.brh[bn]);
 #pragma unroll
         for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], ah[bm], bl[bn]);
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brl[bn]);
 #pragma unroll
         for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], ah[bm], bh[bn]);
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brh[bn]);
       }
     }
   };
 
-  // prologue: chunks 0 .. R-1 (every group spans at least R chunks)
-  static_for<R>([&](auto q) { load_dh(set(q), decltype(q)::value); });
+  // Pipeline over chunks, LDS buffers rotating with the chunk index (chunk c
+  // sits in buffer c mod 3 from step c-2 to step c).  Step j: read the
+  // fragments of chunk j+1 (split precisions), multiply chunk j, write chunk
+  // j+2 from its stage set and refill that set with chunk j+2+R, then one
+  // barrier.  The LDS round trip of chunk j+1 and its B_im lane swaps overlap
+  // the matrix products of chunk j.
+  T* buf_c = stage;                          // chunk j
+  T* buf_r = stage + TL::STAGE_ELEMS;        // chunk j+1
+  T* buf_w = stage + 2 * TL::STAGE_ELEMS;    // chunk j+2
+  static_for<R>([&](auto q) { load(set(q), decltype(q)::value); });
   if (tid < TM) {
     rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
   } else if (tid < TM + TN) {
     cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
   }
   if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
-  store_from(st0, 0);
+  store_from(set(std::integral_constant<int, 0>{}), buf_c);
+  store_from(set(std::integral_constant<int, 1>{}), buf_r);
+  if (R < nch) load(set(std::integral_constant<int, 0>{}), R);
+  if (R + 1 < nch) load(set(std::integral_constant<int, 1>{}), R + 1);
   __syncthreads();
-  // one step: refill the set that held chunk j with chunk j + R (PF: 0 a
-  // (d|h) chunk, 1 an (h|h) block, 2 nothing), multiply chunk j out of LDS
-  // buffer j % 2, move chunk j + 1 into the other buffer.  Every group spans
-  // a multiple of R chunks (bins padded to 64) and R is even, so the set and
-  // the buffer of each step are static.
-  auto step = [&](int j, auto slot, auto pf, bool more, auto&& compute_fn) {
+  read_frag(fr0, buf_c);
+  // flags: 1 read the next fragments, 2 write chunk j+2, 4 refill its stage set
+  auto step = [&](int j, auto slot, auto flags, auto&& compute_fn) {
     constexpr int sl = decltype(slot)::value;
-    constexpr int PF = decltype(pf)::value;
-    if constexpr (PF == 0) load_dh(set(slot), j + R);
-    if constexpr (PF == 1) load_hh(set(slot), j + R - ndh);
-    compute_fn(sl & 1);
-    if (more) store_from(set(std::integral_constant<int, sl + 1>{}), (sl + 1) & 1);
+    constexpr int FL = decltype(flags)::value;
+    if constexpr (FL & 1) read_frag(frag(std::integral_constant<int, sl + 1>{}), buf_r);
+    compute_fn(frag(slot), (const T*)buf_c);
+    if constexpr (FL & 2) {
+      u32x4* sw = set(std::integral_constant<int, sl + 2>{});
+      store_from(sw, buf_w);
+      if constexpr (FL & 4) load(sw, j + 2 + R);
+    }
+    if constexpr (PREC != kFP64) {
+      // interleave: the next chunk's LDS reads first, a few matrix products
+      // to cover their latency, then products alternating with the lane
+      // swaps, then the LDS writes and the global loads
+      constexpr int NRD = 2 * (P::BM + P::BN);          // LDS fragment reads
+      constexpr int NMF = 6 * P::BM * P::BN;            // matrix products ((d|h) step)
+      __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      static_for<NMF - 2>([&](auto) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+      });
+      __builtin_amdgcn_sched_group_barrier(0x200, TL::PIECES_PER_THREAD, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, TL::PIECES_PER_THREAD, 0);
+    }
     __syncthreads();
+    T* t = buf_c;
+    buf_c = buf_r;
+    buf_r = buf_w;
+    buf_w = t;
   };
-  using PF_DH = std::integral_constant<int, 0>;
-  using PF_HH = std::integral_constant<int, 1>;
-  using PF_NONE = std::integral_constant<int, 2>;
+  // every group spans a multiple of 4 chunks (bins padded to 64), so the
+  // fragment set (j mod 2) and stage set (j mod R) of each step are static;
+  // with NHB >= R + 2 (h|h) blocks after them, every (d|h) step reads, writes
+  // and refills
   int ch = 0;
   static_for<G>([&](auto gi) {
     constexpr int g = decltype(gi)::value;
-    // the last group's last R chunks prefetch the (h|h) blocks
-    const int gend = a.mt.gk0[g + 1] - (g == G - 1 ? R : 0);
-    for (; ch < gend; ch += R) {
-      static_for<R>([&](auto slot) {
-        step(ch + decltype(slot)::value, slot, PF_DH{}, true,
-             [&](int buf) { compute_dh(buf, gi); });
-      });
-    }
-    if constexpr (g == G - 1) {
-      static_for<R>([&](auto slot) {
-        step(ch + decltype(slot)::value, slot, PF_HH{}, true,
-             [&](int buf) { compute_dh(buf, gi); });
+    const int gend = a.mt.gk0[g + 1];
+    for (; ch < gend; ch += 4) {
+      static_for<4>([&](auto slot) {
+        step(ch + decltype(slot)::value, slot, std::integral_constant<int, 7>{},
+             [&](const Frag& f, const T* base) { compute_dh(f, base, gi); });
       });
     }
   });
@@ -1093,9 +1134,9 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       for (int bn = 0; bn < P::BN; ++bn) acch[r][bm][bn] = Acc{0, 0, 0, 0};
   static_for<NHB>([&](auto ri) {
     constexpr int r = decltype(ri)::value;
-    using PFr = typename std::conditional<(r + R < NHB), PF_HH, PF_NONE>::type;
-    step(ndh + r, std::integral_constant<int, r % R>{}, PFr{}, r + 1 < NHB,
-         [&](int buf) { compute_hh(buf, ri); });
+    constexpr int fl = (r + 1 < NHB ? 1 : 0) | (r + 2 < NHB ? 2 : 0) | (r + 2 + R < NHB ? 4 : 0);
+    step(ndh + r, std::integral_constant<int, r % 4>{}, std::integral_constant<int, fl>{},
+         [&](const Frag& f, const T* base) { compute_hh(f, base, ri); });
   });
 
   // ---- epilogue ----
@@ -1114,91 +1155,85 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
   const int ND = a.mt.ND;
   EvAcc ev;
   ev.init();
-  AT* epi_all = (AT*)smem;
-  AT* epi = epi_all + wave * 256 * TL::EPI_STRIDE;
-  constexpr int XO = 0, SO = 2 * G;   // offsets of X and S in a pair's record
+  int n_pairs_i = 0, n_bounded_i = 0;
+  AT* recs = (AT*)smem;                  // [BATCH][REC] survivors of one batch
+  constexpr int XO = 0, SO = 2 * G;      // offsets of X and S in a record
+  // output element r of a lane's 16x16 accumulator block sits in row rowmap(r)
+  auto rowmap = [&](int r) { return (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r); };
 
-#pragma unroll 1
-  for (int blk = 0; blk < P::BM * P::BN; ++blk) {
-    __syncthreads();
-#pragma unroll
-    for (int bb = 0; bb < P::BM * P::BN; ++bb) {
-      if (bb != blk) continue;
-      const int bm = bb / P::BN, bn = bb % P::BN;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int rr = (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r);
-        int q = rr * 16 + (lane & 15);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          epi[q * TL::EPI_STRIDE + XO + 2 * g] = (AT)acc[g][bm][bn][0][r];
-          epi[q * TL::EPI_STRIDE + XO + 2 * g + 1] = (AT)acc[g][bm][bn][1][r];
-        }
-#pragma unroll
-        for (int s = 0; s < NRT; ++s) epi[q * TL::EPI_STRIDE + SO + s] = (AT)acch[s][bm][bn][r];
-      }
-    }
-    __syncthreads();
-    const int bm = blk / P::BN, bn = blk % P::BN;
-    // E1: per-pair bound, survivors to the list
-    for (int t = 0; t < 4; ++t) {
-      int q = lane + 64 * t;
-      int tr = wm * 16 * P::BM + bm * 16 + q / 16;
-      int tc = wn * 16 * P::BN + bn * 16 + (q & 15);
-      if (row0 + tr >= a.n_sub || col0 + tc >= a.n_ext) continue;
-      ev.n_pairs += 1.0;
+  static_for<P::BM * P::BN * 2>([&](auto bi) {
+    constexpr int bb = decltype(bi)::value >> 1, rh = decltype(bi)::value & 1;
+    constexpr int bm = bb / P::BN, bn = bb % P::BN;
+    const int tc = wn * 16 * P::BN + bn * 16 + (lane & 15);
+    const bool col_ok = col0 + tc < a.n_ext;
+    const double cs1 = cold[tc * 3 + 1], cs2 = cold[tc * 3 + 2], clw = cold[tc * 3];
+    // E1: every pair of the batch straight from the accumulators: the
+    // certified bound on lnL^ML, bounded pairs into the dropped mass,
+    // survivors' records into LDS
+    static_for<2>([&](auto ri) {
+      constexpr int r = 2 * rh + decltype(ri)::value;
+      const int tr = wm * 16 * P::BM + bm * 16 + rowmap(r);
+      if (!(col_ok && row0 + tr < a.n_sub)) return;
+      ++n_pairs_i;
       bool survive = true;
       if (use_bound) {
-        const AT* x = epi + q * TL::EPI_STRIDE;
-        float sx = (float)(rowd[tr * 4 + 1] * cold[tc * 3 + 1]);
-        float sh = (float)(rowd[tr * 4 + 2] * cold[tc * 3 + 2]);
+        const float sx = (float)(rowd[tr * 4 + 1] * cs1);
+        const float sh = (float)(rowd[tr * 4 + 2] * cs2);
         float U = 0.f;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          float xr = (float)x[XO + 2 * g], xi = (float)x[XO + 2 * g + 1];
-          U += sqrtf(xr * xr + xi * xi);
+          float xr = (float)acc[g][bm][bn][0][r], xi = (float)acc[g][bm][bn][1][r];
+          U += __builtin_amdgcn_sqrtf(xr * xr + xi * xi);
         }
         U *= fabsf(sx);
-        // hh_o >= S0 - 2 sum_d |S_d| for every phase
-        float lo = (float)x[SO];
+        // hh_o >= S0 - 2 sum_d |S_d| for every phase; the margin, relative
+        // to the magnitudes involved, covers FP32 accumulation and sqrt
+        // rounding even when the difference cancels
+        const float s0 = (float)acch[0][bm][bn][r];
+        float sabs = 0.f;
 #pragma unroll
         for (int d = 1; d < (NRT + 1) / 2; ++d) {
           if (d >= ND) break;
-          float sr = (float)x[SO + 2 * d - 1], si = (float)x[SO + 2 * d];
-          lo -= 2.f * sqrtf(sr * sr + si * si);
+          float sr = (float)acch[2 * d - 1][bm][bn][r], si = (float)acch[2 * d][bm][bn][r];
+          sabs += 2.f * __builtin_amdgcn_sqrtf(sr * sr + si * si);
         }
-        lo *= sh * 0.999f;                         // margin for rounding
+        float lo = ((s0 - sabs) - 2e-5f * (fabsf(s0) + sabs)) * sh;
         // lnL^ML_o <= U^2 / (2 lo) for every phase
         if (lo > 0.f) {
           float bound = U * U / (2.f * lo) * 1.001f + 1e-3f;
           if (bound < thr_f) {
             survive = false;
             if (MODE == kEvidence) {
-              float lw = (float)(rowd[tr * 4] + cold[tc * 3]);
+              float lw = (float)(rowd[tr * 4] + clw);
               ev.drop.add(lw + bound);
               ev.max_bound = fmaxf(ev.max_bound, lw + bound);
-              ev.n_bounded += 1.0;
+              ++n_bounded_i;
             }
           }
         }
       }
       if (survive) {
         int slot = atomicAdd(list_n, 1);
-        list[slot] = (uint16_t)((wave << 8) | q);
+        AT* rec = recs + slot * TL::REC;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          rec[XO + 2 * g] = (AT)acc[g][bm][bn][0][r];
+          rec[XO + 2 * g + 1] = (AT)acc[g][bm][bn][1][r];
+        }
+#pragma unroll
+        for (int q = 0; q < NRT; ++q) rec[SO + q] = (AT)acch[q][bm][bn][r];
+        list[slot] = (uint16_t)((tr << 8) | tc);
       }
-    }
+    });
     __syncthreads();
     // E2: survivors, load-balanced over the workgroup
     const int nsurv = *list_n;
-    for (int j = tid; j < nsurv; j += 256) {
-      int w = list[j] >> 8, q = list[j] & 255;
-      int wm_ = w >> 1, wn_ = w & 1;
-      int tr = wm_ * 16 * P::BM + bm * 16 + q / 16;
-      int tc = wn_ * 16 * P::BN + bn * 16 + (q & 15);
-      int64_t ie = row0 + tr, e = col0 + tc;
-      const AT* xq = epi_all + (w * 256 + q) * TL::EPI_STRIDE;
-      double sx = rowd[tr * 4 + 1] * cold[tc * 3 + 1];
-      double sh = rowd[tr * 4 + 2] * cold[tc * 3 + 2];
+    for (int j = tid; j < nsurv; j += NT) {
+      const int tr = list[j] >> 8, tcs = list[j] & 255;
+      const int64_t ie = row0 + tr, e = col0 + tcs;
+      const AT* xq = recs + j * TL::REC;
+      double sx = rowd[tr * 4 + 1] * cold[tcs * 3 + 1];
+      double sh = rowd[tr * 4 + 2] * cold[tcs * 3 + 2];
       double2 X[G];
 #pragma unroll
       for (int g = 0; g < G; ++g)
@@ -1211,9 +1246,9 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
         Sr[d] = sh * (double)xq[SO + 2 * d - 1];
         Si[d] = sh * (double)xq[SO + 2 * d];
       }
-      double lnw = rowd[tr * 4] + cold[tc * 3];
+      double lnw = rowd[tr * 4] + cold[tcs * 3];
       int ob = 0;
-      double lnp = pair_full<MODE>(a, lds_cs, ie, e, X, S0, Sr, Si, lnw, thr_ml, ev, ob);
+      double lnp = pair_full<MODE, G>(a, lds_cs, ie, e, X, S0, Sr, Si, lnw, thr_ml, ev, ob);
       if (MODE == kEvidence && lnp > -INFINITY) {
         unsigned long long ob_bits = order_bits(lnp);
         unsigned long long prev = atomicMax(tile_lnp_max, ob_bits);
@@ -1233,7 +1268,8 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
     }
     __syncthreads();
     if (tid == 0) *list_n = 0;
-  }
+    __syncthreads();
+  });
   if (EVAL) return;
   if (MODE == kPilot) {
     double mlm = wave_max(ev.ml_max);
@@ -1241,12 +1277,12 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
       atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
     return;
   }
+  ev.n_pairs = (double)n_pairs_i;
+  ev.n_bounded = (double)n_bounded_i;
 
   // ---- tile reduction ----
-  __syncthreads();
   const double tile_max_lnp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
-  __syncthreads();
-  double* red = (double*)smem;   // [4 waves][kNPart]
+  double* red = (double*)(smem + TL::RED_OFF);   // [NW][kNPart]
   {
     Lse p = ev.p;
     Lse d;
@@ -1272,7 +1308,7 @@ __global__ __launch_bounds__(256) void k_lnl_fused(FusedArgs a) {
     Lse p, d;
     p.init(); d.init();
     double mlm = 0.0, mb = -INFINITY, mxp = -INFINITY, nm = 0, nb = 0, np_ = 0;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < NW; ++w) {
       const double* r = red + w * kNPart;
       p.merge(r[0], r[1], r[2]);
       d.merge(r[3], r[4], 0.0);
