@@ -56,6 +56,13 @@ extern "C" {
 #define DOTPE_PREC_FP16X2 1   /* FP16 hi+lo operands, 3 products, FP32 MFMA accumulation */
 #define DOTPE_PREC_BF16X2 2   /* BF16 hi+lo operands, 3 products, FP32 MFMA accumulation */
 
+/* event flags.  With a cut, dotpe_evidence bounds every pair of a tile
+ * first and evaluates the tile's survivors afterwards; a tile with more
+ * survivors than its record area holds is evaluated again by a second,
+ * batched pass.  DOTPE_FLAG_RERUN_ALL sends every tile with a survivor
+ * through that second pass (a check that both routes agree; slower). */
+#define DOTPE_FLAG_RERUN_ALL 1
+
 /* where a caller pointer lives */
 #define DOTPE_MEM_HOST 0
 #define DOTPE_MEM_DEVICE 1
@@ -131,7 +138,7 @@ typedef struct dotpe_event_desc {
                                lnL^ML < running max - cut_delta are bounded, not
                                marginalised; <= 0 disables the cut */
   int32_t top_k;            /* number of top pairs to return from dotpe_evidence */
-  int32_t flags;            /* reserved, 0 */
+  int32_t flags;            /* 0, or DOTPE_FLAG_RERUN_ALL */
   double topk_window;       /* candidates kept within this of the max ln p (default 40 if <= 0) */
   void* stream;             /* hipStream_t for this event's work; NULL = context stream */
 } dotpe_event_desc;

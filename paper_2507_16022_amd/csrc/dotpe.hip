@@ -83,6 +83,7 @@ struct dotpe_event {
   int64_t* sub_idx = nullptr;
   double d0 = 1.0, d_max = 1.0, n_norm = 0.0, cut_delta = 0.0, topk_window = 40.0;
   int top_k = 0;
+  int flags = 0;
   double dd = 0.0;
   // device arrays
   void* B[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -106,6 +107,7 @@ struct dotpe_event {
   int64_t cand_cap = 0;
   double* final_out = nullptr;
   double* final_blk = nullptr;
+  int* rerun = nullptr;          // tiles a fast evidence pass leaves to the batched epilogue
   hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};
   std::vector<void*> allocs;
   uint64_t bytes = 0;
@@ -298,41 +300,42 @@ void launch_hh(dotpe_event* ev, const double* w) {
                      ev->Bh[0], ev->Bh[1], ev->bh_scale);
 }
 
-template <int PREC, int G, int MODE>
+template <int PREC, int G, int MODE, bool FAST>
 int launch_fused_t(const FusedArgs& a, int64_t grid, hipStream_t s) {
   typedef Tile<PREC> TL;
   size_t sh = TL::MAIN_BYTES + sizeof(double) * kMaxM * a.n_phi * 2;
-  static bool attr_set = false;
-  if (!attr_set) {
-    // allow more than 64 KiB of dynamic LDS; not every runtime needs or
-    // supports the attribute, so a failure here is not an error
-    if (hipFuncSetAttribute((const void*)k_lnl_fused<PREC, G, MODE>,
+  // allow more than 64 KiB of dynamic LDS (once per kernel; not every
+  // runtime needs or supports the attribute, so a failure is not an error)
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [sh] {
+    if (hipFuncSetAttribute((const void*)k_lnl_fused<PREC, G, MODE, FAST>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh + 16384) != hipSuccess)
       (void)hipGetLastError();
-    attr_set = true;
-  }
-  hipLaunchKernelGGL((k_lnl_fused<PREC, G, MODE>), dim3((unsigned)grid), dim3(TL::NT), sh, s, a);
+  });
+  hipLaunchKernelGGL((k_lnl_fused<PREC, G, MODE, FAST>), dim3((unsigned)grid), dim3(TL::NT), sh, s, a);
   HIP_OK(hipGetLastError());
   return DOTPE_OK;
 }
 
-template <int PREC, int MODE>
+template <int PREC, int MODE, bool FAST>
 int launch_fused_g(const FusedArgs& a, int64_t grid, hipStream_t s) {
   switch (a.mt.G) {
-    case 1: return launch_fused_t<PREC, 1, MODE>(a, grid, s);
-    case 2: return launch_fused_t<PREC, 2, MODE>(a, grid, s);
-    case 3: return launch_fused_t<PREC, 3, MODE>(a, grid, s);
-    case 4: return launch_fused_t<PREC, 4, MODE>(a, grid, s);
+    case 1: return launch_fused_t<PREC, 1, MODE, FAST>(a, grid, s);
+    case 2: return launch_fused_t<PREC, 2, MODE, FAST>(a, grid, s);
+    case 3: return launch_fused_t<PREC, 3, MODE, FAST>(a, grid, s);
+    case 4: return launch_fused_t<PREC, 4, MODE, FAST>(a, grid, s);
   }
   return fail(DOTPE_E_INVALID_ARG, "bad group count %d", a.mt.G);
 }
 
-template <int MODE>
+// FAST (evidence pass only): every pair through the bound first, one full
+// evaluation pass after, tiles with too many survivors listed for a rerun
+template <int MODE, bool FAST = false>
 int launch_fused(int prec, const FusedArgs& a, int64_t grid, hipStream_t s) {
   switch (prec) {
-    case kFP64: return launch_fused_g<kFP64, MODE>(a, grid, s);
-    case kFP16X2: return launch_fused_g<kFP16X2, MODE>(a, grid, s);
-    case kBF16X2: return launch_fused_g<kBF16X2, MODE>(a, grid, s);
+    case kFP64: return launch_fused_g<kFP64, MODE, FAST>(a, grid, s);
+    case kFP16X2: return launch_fused_g<kFP16X2, MODE, FAST>(a, grid, s);
+    case kBF16X2: return launch_fused_g<kBF16X2, MODE, FAST>(a, grid, s);
   }
   return fail(DOTPE_E_INVALID_ARG, "bad precision %d", prec);
 }
@@ -401,13 +404,14 @@ bool finite_all(const double* p, size_t n) {
 
 // state words: [0] running max of lnL^ML (bits of a non-negative double),
 // [1] running max of ln p (ordered encoding), [2] candidate count,
-// [3] cut reference frozen after the pilot pass
+// [3] cut reference frozen after the pilot pass, [4] tiles to rerun
 __global__ void k_reset_state(uint64_t* st) {
   if (threadIdx.x == 0) {
     st[0] = 0ull;                       // bits of +0.0
     st[1] = 0x000fffffffffffffull;      // ordered encoding below every finite value
     st[2] = 0ull;
     st[3] = 0ull;
+    st[4] = 0ull;                       // tiles listed for a rerun
   }
 }
 
@@ -651,6 +655,7 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
     return fail(DOTPE_E_INVALID_ARG, "event arrays must not be NULL");
   if (!(d->d_max > 0.0) || !(d->d0 > 0.0) || !std::isfinite(d->d_max) || !std::isfinite(d->d0))
     return fail(DOTPE_E_INVALID_ARG, "distances must be positive and finite");
+  if (d->flags & ~DOTPE_FLAG_RERUN_ALL) return fail(DOTPE_E_INVALID_ARG, "unknown flags 0x%x", d->flags);
   int KH = 0;
   {
     int rc0 = build_hh_terms(bk->mt, d->n_det, terms, &KH);
@@ -733,6 +738,7 @@ std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) 
   v.push_back({(void**)&ev->partials, (size_t)D.n_tiles * kNPart * 8, false});
   v.push_back({(void**)&ev->final_blk, (size_t)((D.n_tiles + 4095) / 4096) * kNPart * 8, false});
   v.push_back({(void**)&ev->cand, (size_t)D.cand_cap * 32, false});
+  v.push_back({(void**)&ev->rerun, (size_t)D.n_tiles * sizeof(int), false});
   v.push_back({(void**)&st->d, (size_t)D.nk * D.nb * 16, true});
   v.push_back({(void**)&st->w, (size_t)D.nk * D.nb * 8, true});
   v.push_back({(void**)&st->r, (size_t)D.nk * 24, true});
@@ -782,6 +788,7 @@ int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc*
   ev->cut_delta = d->cut_delta;
   ev->topk_window = d->topk_window > 0 ? d->topk_window : 40.0;
   ev->top_k = std::max(0, d->top_k);
+  ev->flags = d->flags;
   ev->KH = D.KH;
   ev->cand_cap = D.cand_cap;
   const ModeTables& mt = bk->mt;
@@ -962,6 +969,7 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   }
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
   HIP_OK(hipEventRecord(ev->ev_t[0], s));
+  int64_t r_rerun = 0;
   if (ev->cut_delta > 0.0 && a.n_tiles_m > 1) {
     // pilot: max lnL^ML over every 64th row of tiles seeds the cut threshold
     // (the main pass raises it further as tiles complete)
@@ -971,8 +979,33 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   }
   hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, ev->state);
   HIP_OK(hipEventRecord(ev->ev_t[1], s));
+  // the fast epilogue pays off when the frozen threshold cuts
+  uint64_t thr_bits = 0;
+  if (ev->cut_delta > 0.0 && a.n_tiles_m > 1) {
+    HIP_OK(hipMemcpyAsync(&thr_bits, ev->state + 3, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  double thr_frozen;
+  std::memcpy(&thr_frozen, &thr_bits, 8);
+  const bool fast = ev->cut_delta > 0.0 && thr_frozen - ev->cut_delta > 0.0;
+  a.rerun = ev->rerun;
+  a.rec_cap = (ev->flags & DOTPE_FLAG_RERUN_ALL) ? 0 : (1 << 30);
   int64_t grid = round_up(a.n_tiles, 8);
-  if ((rc = launch_fused<kEvidence>(ev->bank->prec, a, grid, s))) return rc;
+  if (fast) {
+    if ((rc = launch_fused<kEvidence, true>(ev->bank->prec, a, grid, s))) return rc;
+    uint64_t n_rerun = 0;
+    HIP_OK(hipMemcpyAsync(&n_rerun, ev->state + 4, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (n_rerun > 0) {
+      FusedArgs b = a;
+      b.rerun_list = ev->rerun;
+      if ((rc = launch_fused<kEvidence, false>(ev->bank->prec, b, (int64_t)n_rerun, s))) return rc;
+    }
+    r_rerun = (int64_t)n_rerun;
+    (void)r_rerun;
+  } else {
+    if ((rc = launch_fused<kEvidence, false>(ev->bank->prec, a, grid, s))) return rc;
+  }
   HIP_OK(hipEventRecord(ev->ev_t[2], s));
   {
     // fixed-order two-level reduction of the tile partials

@@ -587,6 +587,9 @@ struct FusedArgs {
   int64_t cand_cap;
   int64_t n_tiles_m, n_tiles_n, n_tiles;
   int64_t pilot_stride;      // pilot pass: every pilot_stride-th row of tiles
+  int* rerun;                // fast evidence pass: tiles left to the batched epilogue
+  const int* rerun_list;     // batched pass over listed tiles only (NULL: all tiles)
+  int rec_cap;               // fast pass: survivors a tile may have (<= the record area)
 };
 
 template <int PREC>
@@ -606,7 +609,10 @@ struct Pol<kFP16X2> {
   typedef uint16_t T;
   typedef f32x4 Acc;
   // B_im = [Bi | Br] is formed in registers from B_re = [Br | -Bi]
-  static constexpr int NA = 2, NB = 2, PITCH = 40, BM = 2, BN = 1, WM = 2, WN = 4;
+  // rows of 32 halfs without padding: the 16-byte pieces of a row are
+  // XOR-swizzled instead (see lds_swz), which keeps the fragment reads
+  // conflict-free and lets the loads write whole rows straight into LDS
+  static constexpr int NA = 2, NB = 2, PITCH = 32, BM = 2, BN = 1, WM = 2, WN = 4;
 };
 template <>
 struct Pol<kBF16X2> : Pol<kFP16X2> {};
@@ -627,7 +633,9 @@ struct Tile {
   static constexpr int REC = 2 * kMaxG + kMaxNR + 2;   // 17
   static constexpr int BATCH = 128 * NW;
   static constexpr int EPI_BYTES = BATCH * REC * ACC_T_BYTES;
-  static constexpr int NSB = 3;     // LDS stage buffers (chunks j, j+1, j+2)
+  // LDS stage buffers: FP64 stages chunks j..j+2 through registers; the
+  // split precisions load chunks j..j+3 straight into LDS
+  static constexpr int NSB = (PREC == kFP64) ? 3 : 4;
   static constexpr int UNION_BYTES = (NSB * STAGE_BYTES > EPI_BYTES) ? NSB * STAGE_BYTES : EPI_BYTES;
   static constexpr int ROWD_OFF = (UNION_BYTES + 15) / 16 * 16;    // double [TM][4]
   static constexpr int COLD_OFF = ROWD_OFF + TM * 4 * 8;           // double [TN][3]
@@ -641,6 +649,33 @@ struct Tile {
   static constexpr int PIECES_PER_THREAD = PIECES / NT;
   static_assert(PIECES % NT == 0, "pieces must split evenly over the threads");
 };
+
+// physical 16-byte piece of logical piece p in row r of a split-precision
+// stage buffer (rows of 64 bytes): p ^ lds_swz(r mod 16).  Within any 16
+// consecutive rows read at one logical piece (a fragment read) the pieces
+// fall on distinct bank groups for 32 and for 64 LDS banks.
+__device__ __forceinline__ int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// wait until at most N vector-memory operations of this wave are in flight
+// (expcnt and lgkmcnt left unconstrained)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0xF << 8));
+}
+
+// workgroup barrier for the LDS-load pipeline: this wave's LDS reads are
+// complete and at most N of its loads into LDS are in flight; the compiler
+// may not move memory operations across it.  (A full __syncthreads() would
+// also wait for every load still streaming into LDS.)
+template <int N>
+__device__ __forceinline__ void pipeline_barrier() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0x0 << 8));
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
 
 // B_im fragment from the B_re fragment of a 16x16x32 operand: lanes 0-31
 // hold K 0-15 (Br), lanes 32-63 hold K 16-31 (-Bi); the result holds Bi in
@@ -691,6 +726,13 @@ struct LseF {
   __device__ void add(float x) {
     if (x > m) { s = s * __expf(m - x) + 1.f; m = x; }
     else s += __expf(x - m);
+  }
+  __device__ void merge(float mb, float sb) {
+    if (mb == -INFINITY) return;
+    if (m == -INFINITY) { m = mb; s = sb; return; }
+    float mm = fmaxf(m, mb);
+    s = s * __expf(m - mm) + sb * __expf(mb - mm);
+    m = mm;
   }
 };
 
@@ -773,7 +815,7 @@ __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie
   return lnp;
 }
 
-template <int PREC, int G, int MODE>
+template <int PREC, int G, int MODE, bool FAST>
 __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   constexpr bool EVAL = MODE == kEval;
   // (h|h) outputs: a single m group has S0 only; otherwise up to 7, padded
@@ -798,7 +840,9 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   // workgroup -> tile: spread consecutive ids over the XCDs so that each XCD
   // walks a contiguous band of tiles, then raster in groups of 8 tile rows
   int64_t wg = blockIdx.x;
-  {
+  if (a.rerun_list) {
+    wg = a.rerun_list[blockIdx.x];        // a tile listed by a fast pass
+  } else {
     int64_t nwg = gridDim.x;              // multiple of 8
     wg = (wg % 8) * (nwg / 8) + wg / 8;
   }
@@ -861,6 +905,188 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
 #pragma unroll
         for (int ri = 0; ri < 2; ++ri) acc[g][bm][bn][ri] = Acc{0, 0, 0, 0};
 
+  if constexpr (PREC != kFP64) {
+    // ---- split precisions: loads straight into LDS, 4 buffers ----
+    // Each wave issues 2 loads of 64 x 16 bytes per chunk; lane l of load q
+    // fills 16-byte unit u = (2 wave + q) 64 + l of the 16 KB buffer, i.e. row
+    // u / 4 (A hi, A lo, B hi, B lo: 64 rows each) and physical piece u mod 4,
+    // which holds logical piece (u mod 4) ^ lds_swz(row).  Rows past the
+    // subset re-read the last row (their pairs are never used).
+    typedef __attribute__((address_space(1))) const unsigned char gbyte;
+    typedef __attribute__((address_space(3))) void lvoid;
+    constexpr int ES = (int)sizeof(T);
+    constexpr int NS = TL::NSB;
+    static_assert(TL::PIECES_PER_THREAD == 2 && TL::STAGE_BYTES == 16384, "split staging layout");
+    gbyte* srcp[2];
+    gbyte* srch[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int u = (wave * 2 + q) * 64 + lane;
+      const int row = u >> 2, lp = (u & 3) ^ lds_swz(row & 15);
+      if (row < P::NA * TM) {
+        const int arr = row / TM, r = row % TM;
+        const int64_t ie = min(row0 + r, a.n_sub - 1);
+        const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+        srcp[q] = (gbyte*)(arr == 0 ? a.A0 : a.A1) + (i * a.K2 + lp * 8) * ES;
+        srch[q] = (gbyte*)(arr == 0 ? a.Ah0 : a.Ah1) + (ie * a.KH + lp * 8) * ES;
+      } else {
+        const int rs = row - P::NA * TM;
+        const int arr = rs / TN, c = rs % TN;
+        srcp[q] = (gbyte*)(arr == 0 ? a.B0 : a.B1) + ((col0 + c) * a.K2 + lp * 8) * ES;
+        srch[q] = (gbyte*)(arr == 0 ? a.Bh0 : a.Bh1) + ((col0 + c) * a.KH + lp * 8) * ES;
+      }
+    }
+    const int ndh = a.n_chunks;        // (d|h) chunks (a multiple of 4)
+    const int nch = ndh + NHB;         // then the (h|h) blocks
+    // chunk c into buffer c mod 4
+    auto issue = [&](int c) {
+      const bool hh = c >= ndh;
+      const int64_t od = (int64_t)c * 32 * ES, oh = (int64_t)(c - ndh) * 32 * ES;
+      unsigned char* buf = smem + (c & (NS - 1)) * TL::STAGE_BYTES + wave * 2048;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        gbyte* pq = hh ? srch[q] + oh : srcp[q] + od;
+        // issued as asm so that the compiler does not treat it as a pending
+        // LDS store that every later LDS read must wait for; the pipeline's
+        // own vmcnt waits order it (the load has no register result)
+        const unsigned lds = (unsigned)(uintptr_t)(lvoid*)(buf + q * 1024);
+        __asm__ __volatile__("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                             :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(pq) : "memory", "m0");
+      }
+    };
+    struct Frag {
+      uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
+    };
+    Frag fr0, fr1;
+    auto frag = [&](auto fi) -> Frag& {
+      if constexpr (decltype(fi)::value % 2 == 0) return fr0;
+      else return fr1;
+    };
+    const int lr = lane & 15;
+    const int swo = ((lane >> 4) ^ lds_swz(lr)) * 16;   // byte offset of this lane's piece
+    auto read_frag = [&](Frag& f, int c) {
+      const unsigned char* base = smem + (c & (NS - 1)) * TL::STAGE_BYTES + swo;
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm) {
+        const int rr = wm * 16 * P::BM + bm * 16 + lr;
+        f.ah[bm] = *(const uint4*)(base + rr * 64);
+        f.al[bm] = *(const uint4*)(base + (TM + rr) * 64);
+      }
+#pragma unroll
+      for (int bn = 0; bn < P::BN; ++bn) {
+        const int cc = wn * 16 * P::BN + bn * 16 + lr;
+        f.brh[bn] = *(const uint4*)(base + (2 * TM + cc) * 64);
+        f.brl[bn] = *(const uint4*)(base + (2 * TM + TN + cc) * 64);
+        f.bih[bn] = bim_from_bre(f.brh[bn], lane);
+        f.bil[bn] = bim_from_bre(f.brl[bn], lane);
+      }
+    };
+    // (d|h) chunk: complex product, 3 split products per real product; the
+    // three products of one accumulator are separated by the independent ones
+    auto compute_dh = [&](const Frag& f, auto gi) {
+      constexpr int g = decltype(gi)::value;
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          mma<PREC>(acc[g][bm][bn][0], f.al[bm], f.brh[bn]);
+          mma<PREC>(acc[g][bm][bn][1], f.al[bm], f.bih[bn]);
+        }
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brl[bn]);
+          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bil[bn]);
+        }
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) {
+          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brh[bn]);
+          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bih[bn]);
+        }
+    };
+    // (h|h) block r: real product of the row and column (h|h) operands
+    auto compute_hh = [&](const Frag& f, auto ri) {
+      constexpr int r = decltype(ri)::value;
+      if constexpr (r < NRT) {
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.al[bm], f.brh[bn]);
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brl[bn]);
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brh[bn]);
+      }
+    };
+    // prologue: chunks 0..3 in flight, wait for 0 and 1
+    static_for<NS>([&](auto q) { issue(decltype(q)::value); });
+    if (tid < TM) {
+      rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
+    } else if (tid < TM + TN) {
+      cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
+    }
+    if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
+    __syncthreads();                          // rowd, cold, counters
+    pipeline_barrier<2 * (NS - 2)>();         // chunks 0 and 1 have landed
+    read_frag(fr0, 0);
+    pipeline_barrier<2 * (NS - 2)>();         // step 0 refills buffer 0: chunk 0 read everywhere
+    // step j: read the fragments of chunk j+1, multiply chunk j, refill the
+    // buffer of chunk j (its fragments were read before the last barrier)
+    // with chunk j+4, wait until chunk j+2 has landed, barrier.  FL: 1 read
+    // the next fragments, 2 issue chunk j+4; W: loads allowed in flight
+    auto step = [&](int j, auto slot, auto fl, auto w, auto&& compute_fn) {
+      constexpr int sl = decltype(slot)::value;
+      constexpr int FL = decltype(fl)::value;
+      if constexpr (FL & 1) read_frag(frag(std::integral_constant<int, sl + 1>{}), j + 1);
+      compute_fn(frag(slot));
+      if constexpr (FL & 2) issue(j + NS);
+      constexpr int NRD = 2 * (P::BM + P::BN);
+      constexpr int NMF = 6 * P::BM * P::BN;
+      __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      static_for<NMF - 2>([&](auto) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+      });
+      __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+      pipeline_barrier<decltype(w)::value>();
+    };
+    // every group spans a multiple of 4 chunks (bins padded to 64), so the
+    // fragment set of each step is static; with NHB = 8 (h|h) blocks after
+    // them every (d|h) step reads ahead, issues and keeps 2 chunks in flight
+    static_assert(NHB >= NS + 2, "pipeline needs NS + 2 trailing blocks");
+    int ch = 0;
+    static_for<G>([&](auto gi) {
+      constexpr int g = decltype(gi)::value;
+      const int gend = a.mt.gk0[g + 1];
+      for (; ch < gend; ch += 4) {
+        static_for<4>([&](auto slot) {
+          step(ch + decltype(slot)::value, slot, std::integral_constant<int, 3>{},
+               std::integral_constant<int, 4>{}, [&](const Frag& f) { compute_dh(f, gi); });
+        });
+      }
+    });
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn) acch[r][bm][bn] = Acc{0, 0, 0, 0};
+    static_for<NHB>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      constexpr int fl = (r + 1 < NHB ? 1 : 0) | (r + NS < NHB ? 2 : 0);
+      constexpr int wc = 2 * ((r + 3 < NHB ? 1 : 0) + (r + 4 < NHB ? 1 : 0));
+      step(ndh + r, std::integral_constant<int, r % 4>{}, std::integral_constant<int, fl>{},
+           std::integral_constant<int, wc>{}, [&](const Frag& f) { compute_hh(f, ri); });
+    });
+  } else {
   // per-thread source addresses of its 16-byte pieces for chunk 0 of the
   // (d|h) operands (srcp) and block 0 of the (h|h) operands (srch), in the
   // global address space so that the loads wait on the vector-memory counter
@@ -1138,6 +1364,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     step(ndh + r, std::integral_constant<int, r % 4>{}, std::integral_constant<int, fl>{},
          [&](const Frag& f, const T* base) { compute_hh(f, base, ri); });
   });
+  }
 
   // ---- epilogue ----
   typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
@@ -1156,64 +1383,61 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   EvAcc ev;
   ev.init();
   int n_pairs_i = 0, n_bounded_i = 0;
-  AT* recs = (AT*)smem;                  // [BATCH][REC] survivors of one batch
+  AT* recs = (AT*)smem;                  // [BATCH][REC] survivors' records
   constexpr int XO = 0, SO = 2 * G;      // offsets of X and S in a record
   // output element r of a lane's 16x16 accumulator block sits in row rowmap(r)
   auto rowmap = [&](int r) { return (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r); };
 
-  static_for<P::BM * P::BN * 2>([&](auto bi) {
-    constexpr int bb = decltype(bi)::value >> 1, rh = decltype(bi)::value & 1;
-    constexpr int bm = bb / P::BN, bn = bb % P::BN;
+  // E1 for the pair in element r of block (bm, bn) of this lane, straight
+  // from the accumulators: the certified bound on lnL^ML, bounded pairs into
+  // the dropped mass, a survivor's record into LDS (slots past BATCH are
+  // counted but not written)
+  auto e1_pair = [&](auto bmi, auto bni, auto ri) {
+    constexpr int bm = decltype(bmi)::value, bn = decltype(bni)::value, r = decltype(ri)::value;
     const int tc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-    const bool col_ok = col0 + tc < a.n_ext;
-    const double cs1 = cold[tc * 3 + 1], cs2 = cold[tc * 3 + 2], clw = cold[tc * 3];
-    // E1: every pair of the batch straight from the accumulators: the
-    // certified bound on lnL^ML, bounded pairs into the dropped mass,
-    // survivors' records into LDS
-    static_for<2>([&](auto ri) {
-      constexpr int r = 2 * rh + decltype(ri)::value;
-      const int tr = wm * 16 * P::BM + bm * 16 + rowmap(r);
-      if (!(col_ok && row0 + tr < a.n_sub)) return;
-      ++n_pairs_i;
-      bool survive = true;
-      if (use_bound) {
-        const float sx = (float)(rowd[tr * 4 + 1] * cs1);
-        const float sh = (float)(rowd[tr * 4 + 2] * cs2);
-        float U = 0.f;
+    const int tr = wm * 16 * P::BM + bm * 16 + rowmap(r);
+    if (!(col0 + tc < a.n_ext && row0 + tr < a.n_sub)) return;
+    ++n_pairs_i;
+    bool survive = true;
+    if (use_bound) {
+      const float sx = (float)(rowd[tr * 4 + 1] * cold[tc * 3 + 1]);
+      const float sh = (float)(rowd[tr * 4 + 2] * cold[tc * 3 + 2]);
+      float U = 0.f;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          float xr = (float)acc[g][bm][bn][0][r], xi = (float)acc[g][bm][bn][1][r];
-          U += __builtin_amdgcn_sqrtf(xr * xr + xi * xi);
-        }
-        U *= fabsf(sx);
-        // hh_o >= S0 - 2 sum_d |S_d| for every phase; the margin, relative
-        // to the magnitudes involved, covers FP32 accumulation and sqrt
-        // rounding even when the difference cancels
-        const float s0 = (float)acch[0][bm][bn][r];
-        float sabs = 0.f;
+      for (int g = 0; g < G; ++g) {
+        float xr = (float)acc[g][bm][bn][0][r], xi = (float)acc[g][bm][bn][1][r];
+        U += __builtin_amdgcn_sqrtf(xr * xr + xi * xi);
+      }
+      U *= fabsf(sx);
+      // hh_o >= S0 - 2 sum_d |S_d| for every phase; the margin, relative to
+      // the magnitudes involved, covers FP32 accumulation and sqrt rounding
+      // even when the difference cancels
+      const float s0 = (float)acch[0][bm][bn][r];
+      float sabs = 0.f;
 #pragma unroll
-        for (int d = 1; d < (NRT + 1) / 2; ++d) {
-          if (d >= ND) break;
-          float sr = (float)acch[2 * d - 1][bm][bn][r], si = (float)acch[2 * d][bm][bn][r];
-          sabs += 2.f * __builtin_amdgcn_sqrtf(sr * sr + si * si);
-        }
-        float lo = ((s0 - sabs) - 2e-5f * (fabsf(s0) + sabs)) * sh;
-        // lnL^ML_o <= U^2 / (2 lo) for every phase
-        if (lo > 0.f) {
-          float bound = U * U / (2.f * lo) * 1.001f + 1e-3f;
-          if (bound < thr_f) {
-            survive = false;
-            if (MODE == kEvidence) {
-              float lw = (float)(rowd[tr * 4] + clw);
-              ev.drop.add(lw + bound);
-              ev.max_bound = fmaxf(ev.max_bound, lw + bound);
-              ++n_bounded_i;
-            }
+      for (int d = 1; d < (NRT + 1) / 2; ++d) {
+        if (d >= ND) break;
+        float sr = (float)acch[2 * d - 1][bm][bn][r], si = (float)acch[2 * d][bm][bn][r];
+        sabs += 2.f * __builtin_amdgcn_sqrtf(sr * sr + si * si);
+      }
+      float lo = ((s0 - sabs) - 2e-5f * (fabsf(s0) + sabs)) * sh;
+      // lnL^ML_o <= U^2 / (2 lo) for every phase
+      if (lo > 0.f) {
+        float bound = U * U / (2.f * lo) * 1.001f + 1e-3f;
+        if (bound < thr_f) {
+          survive = false;
+          if (MODE == kEvidence) {
+            float lw = (float)(rowd[tr * 4] + cold[tc * 3]);
+            ev.drop.add(lw + bound);
+            ev.max_bound = fmaxf(ev.max_bound, lw + bound);
+            ++n_bounded_i;
           }
         }
       }
-      if (survive) {
-        int slot = atomicAdd(list_n, 1);
+    }
+    if (survive) {
+      int slot = atomicAdd(list_n, 1);
+      if (slot < TL::BATCH) {
         AT* rec = recs + slot * TL::REC;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -1224,10 +1448,10 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         for (int q = 0; q < NRT; ++q) rec[SO + q] = (AT)acch[q][bm][bn][r];
         list[slot] = (uint16_t)((tr << 8) | tc);
       }
-    });
-    __syncthreads();
-    // E2: survivors, load-balanced over the workgroup
-    const int nsurv = *list_n;
+    }
+  };
+  // E2: the survivors' full evaluation, load-balanced over the workgroup
+  auto e2_list = [&](int nsurv) {
     for (int j = tid; j < nsurv; j += NT) {
       const int tr = list[j] >> 8, tcs = list[j] & 255;
       const int64_t ie = row0 + tr, e = col0 + tcs;
@@ -1266,10 +1490,43 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         }
       }
     }
+  };
+
+  if constexpr (FAST) {
+    // every pair of the tile through E1 first, then one E2 once the
+    // accumulators are dead.  A tile with more survivors than the record
+    // area holds is left to a second launch of the batched epilogue: it is
+    // listed and contributes nothing here.
+    static_for<P::BM>([&](auto bmi) {
+      static_for<P::BN>([&](auto bni) {
+        static_for<4>([&](auto ri) { e1_pair(bmi, bni, ri); });
+      });
+    });
     __syncthreads();
-    if (tid == 0) *list_n = 0;
-    __syncthreads();
-  });
+    const int nsurv = *list_n;
+    if (nsurv > min(a.rec_cap, TL::BATCH)) {
+      if (tid == 0) {
+        unsigned long long k = atomicAdd((unsigned long long*)&a.state[4], 1ull);
+        a.rerun[k] = (int)wg;
+      }
+      return;
+    }
+    e2_list(nsurv);
+  } else {
+    // batches of 2 pairs per lane (at most BATCH survivors each)
+    static_for<P::BM * P::BN * 2>([&](auto bi) {
+      constexpr int bb = decltype(bi)::value >> 1, rh = decltype(bi)::value & 1;
+      static_for<2>([&](auto ri) {
+        e1_pair(std::integral_constant<int, bb / P::BN>{}, std::integral_constant<int, bb % P::BN>{},
+                std::integral_constant<int, 2 * rh + decltype(ri)::value>{});
+      });
+      __syncthreads();
+      e2_list(*list_n);
+      __syncthreads();
+      if (tid == 0) *list_n = 0;
+      __syncthreads();
+    });
+  }
   if (EVAL) return;
   if (MODE == kPilot) {
     double mlm = wave_max(ev.ml_max);

@@ -255,9 +255,12 @@ class Bank:
             pass
 
 
+FLAG_RERUN_ALL = 1
+
+
 def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=1.0, n_norm=0.0,
                 sub_start=0, sub_count=0, sub_idx=None, cut_delta=0.0, top_k=0, topk_window=40.0,
-                stream=None):
+                stream=None, flags=0):
     """EventDesc over host copies of the inputs; returns (desc, arrays to keep alive)."""
     keep = []
 
@@ -285,7 +288,7 @@ def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=
         stream = stream.cuda_stream
     desc = EventDesc(dc.shape[0], int(n_phi), pd, pw, pr, pD, n_ext, plat, plon, ppsi, pci, ptg,
                      plw, float(d_max), float(d0), float(n_norm), int(sub_start),
-                     int(sub_count), psub, float(cut_delta), int(top_k), 0,
+                     int(sub_count), psub, float(cut_delta), int(top_k), int(flags),
                      float(topk_window), stream)
     return desc, keep
 

@@ -258,3 +258,24 @@ def test_mixed_higher_modes_snr50_vs_fp64(ctx):
               flush=True)
         if prec == "fp16x2":
             assert err.max() <= TOL_MIXED
+
+
+def test_evidence_rerun_route_agrees(ctx):
+    """With a cut, a tile's pairs are all bounded first and its survivors
+    evaluated afterwards; tiles with too many survivors are evaluated again
+    by the batched second pass.  Forcing every tile with a survivor through
+    that second pass must give the same evidence and top-k."""
+    from paper_2507_16022_amd import dotpe
+    wl = W.config_production(seed=8, n_int=160, n_ext=96, snr=25.0)
+    res = []
+    for flags in (0, dotpe.FLAG_RERUN_ALL):
+        bank, ev = make_event(ctx, wl, precision="fp16x2", cut_delta=20.0, top_k=64, flags=flags)
+        res.append(ev.evidence())
+    a, b = res
+    for k in ("ln_z", "ln_z_upper", "max_lnl_ml", "ln_sum_p2", "max_ln_p"):
+        assert a[k] == pytest.approx(b[k], abs=1e-10), k
+    assert a["n_pairs"] == b["n_pairs"] and a["n_pairs_bounded"] == b["n_pairs_bounded"]
+    assert a["n_triples_marg"] == b["n_triples_marg"]
+    n = a["topk_count"]
+    assert n == b["topk_count"] and n > 0
+    assert np.array_equal(a["topk_i"], b["topk_i"]) and np.array_equal(a["topk_e"], b["topk_e"])
