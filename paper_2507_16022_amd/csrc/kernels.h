@@ -855,7 +855,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     tn = wg % a.n_tiles_n;
   } else {
     if (wg >= a.n_tiles) return;
-    const int64_t GM = 8;
+    const int64_t GM = 1;
     int64_t band = wg / (GM * a.n_tiles_n);
     int64_t rows_in_band = min(GM, a.n_tiles_m - band * GM);
     int64_t in = wg - band * GM * a.n_tiles_n;
@@ -1575,8 +1575,16 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     double* out = a.partials + wg * kNPart;
     out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
     out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
-    atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
-    if (mxp > -INFINITY) atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(mxp));
+    // running maxima: read first, update only when this tile raises them
+    // (same-address atomics from every tile would serialise in L2)
+    const unsigned long long mb_bits = (unsigned long long)__double_as_longlong(mlm);
+    if (mb_bits > __atomic_load_n((unsigned long long*)&a.state[0], __ATOMIC_RELAXED))
+      atomicMax((unsigned long long*)&a.state[0], mb_bits);
+    if (mxp > -INFINITY) {
+      const unsigned long long pb = (unsigned long long)order_bits(mxp);
+      if (pb > __atomic_load_n((unsigned long long*)&a.state[1], __ATOMIC_RELAXED))
+        atomicMax((unsigned long long*)&a.state[1], pb);
+    }
   }
 }
 
