@@ -677,22 +677,6 @@ __device__ __forceinline__ void pipeline_barrier() {
   __asm__ __volatile__("" ::: "memory");
 }
 
-// B_im fragment from the B_re fragment of a 16x16x32 operand: lanes 0-31
-// hold K 0-15 (Br), lanes 32-63 hold K 16-31 (-Bi); the result holds Bi in
-// lanes 0-31 and Br in lanes 32-63 (swap halves, negate the new lower half)
-__device__ __forceinline__ uint4 bim_from_bre(const uint4& x, int lane) {
-  const bool lo = lane < 32;
-  uint4 y;
-  unsigned in[4] = {x.x, x.y, x.z, x.w}, out[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    auto r = __builtin_amdgcn_permlane32_swap(in[k], in[k], false, false);
-    out[k] = lo ? (r[1] ^ 0x80008000u) : r[0];
-  }
-  y.x = out[0]; y.y = out[1]; y.z = out[2]; y.w = out[3];
-  return y;
-}
-
 template <int PREC>
 __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a, const uint4& b) {
   if constexpr (PREC == kFP16X2) {
@@ -821,10 +805,9 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   // (h|h) outputs: a single m group has S0 only; otherwise up to 7, padded
   // to an even number of K blocks
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;
-  constexpr int NHB = kMaxNR + 1;   // >= R + 2: every (d|h) step keeps the pipeline full
-  // register stage sets: loads run R chunks ahead (FP64 pieces are twice as
-  // many per thread, so it keeps two sets to stay within the register file)
-  constexpr int R = (PREC == kFP64) ? 2 : 4;
+  // (h|h) blocks after the (d|h) chunks: enough that every (d|h) step of
+  // either K loop keeps its pipeline full
+  constexpr int NHB = kMaxNR + 1;
   typedef Pol<PREC> P;
   typedef Tile<PREC> TL;
   typedef typename P::T T;
@@ -964,6 +947,10 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     };
     const int lr = lane & 15;
     const int swo = ((lane >> 4) ^ lds_swz(lr)) * 16;   // byte offset of this lane's piece
+    // B_im = [Bi | Br] is B_re = [Br | -Bi] with the two halves of the chunk
+    // exchanged (logical piece p ^ 2) and lanes 0-31 negated
+    const int swi = (((lane >> 4) ^ 2) ^ lds_swz(lr)) * 16;
+    const unsigned negm = lane < 32 ? 0x80008000u : 0u;
     auto read_frag = [&](Frag& f, int c) {
       const unsigned char* base = smem + (c & (NS - 1)) * TL::STAGE_BYTES + swo;
 #pragma unroll
@@ -977,8 +964,11 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         const int cc = wn * 16 * P::BN + bn * 16 + lr;
         f.brh[bn] = *(const uint4*)(base + (2 * TM + cc) * 64);
         f.brl[bn] = *(const uint4*)(base + (2 * TM + TN + cc) * 64);
-        f.bih[bn] = bim_from_bre(f.brh[bn], lane);
-        f.bil[bn] = bim_from_bre(f.brl[bn], lane);
+        const unsigned char* bi = smem + (c & (NS - 1)) * TL::STAGE_BYTES + swi;
+        const uint4 x = *(const uint4*)(bi + (2 * TM + cc) * 64);
+        const uint4 y = *(const uint4*)(bi + (2 * TM + TN + cc) * 64);
+        f.bih[bn] = make_uint4(x.x ^ negm, x.y ^ negm, x.z ^ negm, x.w ^ negm);
+        f.bil[bn] = make_uint4(y.x ^ negm, y.y ^ negm, y.z ^ negm, y.w ^ negm);
       }
     };
     // (d|h) chunk: complex product, 3 split products per real product; the
@@ -1047,7 +1037,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       if constexpr (FL & 1) read_frag(frag(std::integral_constant<int, sl + 1>{}), j + 1);
       compute_fn(frag(slot));
       if constexpr (FL & 2) issue(j + NS);
-      constexpr int NRD = 2 * (P::BM + P::BN);
+      constexpr int NRD = 2 * (P::BM + 2 * P::BN);
       constexpr int NMF = 6 * P::BM * P::BN;
       __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
       __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
@@ -1114,24 +1104,21 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         int rs = rowsel - P::NA * TM;
         int arr = rs / TN, c = rs % TN;
         srcp[q] = (gbyte*)(arr == 0 ? a.B0 : a.B1) + ((col0 + c) * a.K2 + piece * TL::PIECE_ELEMS) * ES;
-        const bool h1 = PREC != kFP64 && arr == 1;
-        srch[q] = (gbyte*)(h1 ? a.Bh1 : a.Bh0) + ((col0 + c) * a.KH + piece * TL::PIECE_ELEMS) * ES;
+        srch[q] = (gbyte*)a.Bh0 + ((col0 + c) * a.KH + piece * TL::PIECE_ELEMS) * ES;
       }
     }
   }
   const int ndh = a.n_chunks;        // (d|h) chunks (a multiple of 4)
   const int nch = ndh + NHB;         // then the (h|h) blocks
   constexpr int ES = (int)sizeof(T);
-  // R register stage sets (set c mod R holds chunk c).  Separate arrays picked
-  // at compile time keep them in registers.
+  // R = 2 register stage sets (set c mod 2 holds chunk c): loads run two
+  // chunks ahead, as many as the register file holds at this tile size.
+  // Separate arrays picked at compile time keep them in registers.
+  constexpr int R = 2;
   u32x4 st0[TL::PIECES_PER_THREAD], st1[TL::PIECES_PER_THREAD];
-  u32x4 st2[TL::PIECES_PER_THREAD], st3[TL::PIECES_PER_THREAD];
   auto set = [&](auto slot) -> u32x4* {
-    constexpr int k = decltype(slot)::value % R;
-    if constexpr (k == 0) return st0;
-    else if constexpr (k == 1) return st1;
-    else if constexpr (k == 2) return st2;
-    else return st3;
+    if constexpr (decltype(slot)::value % R == 0) return st0;
+    else return st1;
   };
   // chunk c into a stage set: a (d|h) chunk for c < ndh, else (h|h) block c - ndh
   auto load = [&](u32x4* stq, int c) {
@@ -1148,146 +1135,69 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     for (int q = 0; q < TL::PIECES_PER_THREAD; ++q) {
       int p = tid + NT * q;
       int rowsel = p / TL::PIECES_PER_ROW, piece = p % TL::PIECES_PER_ROW;
-      T* dst = base + rowsel * PITCH + piece * TL::PIECE_ELEMS;
-      if constexpr (PREC == kFP64) {
-        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-        u32x2* d2 = (u32x2*)dst;
-        d2[0] = st[q].xy;
-        d2[1] = st[q].zw;
-      } else {
-        *(u32x4*)dst = st[q];
-      }
+      // the odd pitch keeps doubles 8-byte aligned only
+      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+      u32x2* d2 = (u32x2*)(base + rowsel * PITCH + piece * TL::PIECE_ELEMS);
+      d2[0] = st[q].xy;
+      d2[1] = st[q].zw;
     }
   };
-  // fragments of one chunk (split precisions): A hi/lo, B_re hi/lo and the
-  // B_im hi/lo formed from B_re; read one chunk ahead of the MFMAs
-  struct Frag {
-    uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
-  };
-  Frag fr0, fr1;
-  auto frag = [&](auto fi) -> Frag& {
-    if constexpr (decltype(fi)::value % 2 == 0) return fr0;
-    else return fr1;
-  };
-  auto read_frag = [&](Frag& f, const T* base) {
-    if constexpr (PREC != kFP64) {
-      const T* As = base;
-      const T* Bs = base + P::NA * TM * PITCH;
-      const int koff = 8 * (lane >> 4);
+  // (d|h) chunk: complex product from the LDS buffer, one FP64 product per
+  // real product
+  auto compute_dh = [&](const T* base, auto gi) {
+    constexpr int g = decltype(gi)::value;
+    const double* Ad = (const double*)base;
+    const double* Bd = (const double*)(base + P::NA * TM * PITCH);
 #pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm) {
-        int rr = wm * 16 * P::BM + bm * 16 + (lane & 15);
-        f.ah[bm] = *(const uint4*)(As + rr * PITCH + koff);
-        f.al[bm] = *(const uint4*)(As + (TM + rr) * PITCH + koff);
-      }
+    for (int s8 = 0; s8 < 8; ++s8) {
+      double av[P::BM], brv[P::BN], biv[P::BN];
+#pragma unroll
+      for (int bm = 0; bm < P::BM; ++bm)
+        av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
 #pragma unroll
       for (int bn = 0; bn < P::BN; ++bn) {
         int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-        f.brh[bn] = *(const uint4*)(Bs + (0 * TN + cc) * PITCH + koff);
-        f.brl[bn] = *(const uint4*)(Bs + (1 * TN + cc) * PITCH + koff);
-        f.bih[bn] = bim_from_bre(f.brh[bn], lane);
-        f.bil[bn] = bim_from_bre(f.brl[bn], lane);
+        brv[bn] = Bd[cc * PITCH + 4 * s8 + (lane >> 4)];
+        biv[bn] = Bd[(TN + cc) * PITCH + 4 * s8 + (lane >> 4)];
       }
-    }
-  };
-  // (d|h) chunk: complex product, 3 split products per real product
-  // (split precisions: from the fragments; FP64: from the LDS buffer)
-  auto compute_dh = [&](const Frag& f, const T* base, auto gi) {
-    constexpr int g = decltype(gi)::value;
-    if constexpr (PREC == kFP64) {
-      const double* Ad = (const double*)base;
-      const double* Bd = (const double*)(base + P::NA * TM * PITCH);
-#pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8) {
-        double av[P::BM], brv[P::BN], biv[P::BN];
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-          av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) {
-          int cc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-          brv[bn] = Bd[cc * PITCH + 4 * s8 + (lane >> 4)];
-          biv[bn] = Bd[(TN + cc) * PITCH + 4 * s8 + (lane >> 4)];
-        }
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) {
-            acc[g][bm][bn][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], brv[bn], acc[g][bm][bn][0], 0, 0, 0);
-            acc[g][bm][bn][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], biv[bn], acc[g][bm][bn][1], 0, 0, 0);
-          }
-      }
-    } else {
-      // issue order: the three split products of one accumulator are
-      // separated by the products of the 2 x BM x BN independent ones
 #pragma unroll
       for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], f.al[bm], f.brh[bn]);
-          mma<PREC>(acc[g][bm][bn][1], f.al[bm], f.bih[bn]);
-        }
-#pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brl[bn]);
-          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bil[bn]);
-        }
-#pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brh[bn]);
-          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bih[bn]);
+          acc[g][bm][bn][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], brv[bn], acc[g][bm][bn][0], 0, 0, 0);
+          acc[g][bm][bn][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], biv[bn], acc[g][bm][bn][1], 0, 0, 0);
         }
     }
   };
   // (h|h) block r: real product of the row and column (h|h) operands
-  auto compute_hh = [&](const Frag& f, const T* base, auto ri) {
+  auto compute_hh = [&](const T* base, auto ri) {
     constexpr int r = decltype(ri)::value;
     if constexpr (r < NRT) {
-      if constexpr (PREC == kFP64) {
-        const double* Ad = (const double*)base;
-        const double* Bd = (const double*)(base + P::NA * TM * PITCH);
+      const double* Ad = (const double*)base;
+      const double* Bd = (const double*)(base + P::NA * TM * PITCH);
 #pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) {
-          double av[P::BM], bv[P::BN];
+      for (int s8 = 0; s8 < 8; ++s8) {
+        double av[P::BM], bv[P::BN];
 #pragma unroll
-          for (int bm = 0; bm < P::BM; ++bm)
-            av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
+        for (int bm = 0; bm < P::BM; ++bm)
+          av[bm] = Ad[(wm * 16 * P::BM + bm * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
+#pragma unroll
+        for (int bn = 0; bn < P::BN; ++bn)
+          bv[bn] = Bd[(wn * 16 * P::BN + bn * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
+#pragma unroll
+        for (int bm = 0; bm < P::BM; ++bm)
 #pragma unroll
           for (int bn = 0; bn < P::BN; ++bn)
-            bv[bn] = Bd[(wn * 16 * P::BN + bn * 16 + (lane & 15)) * PITCH + 4 * s8 + (lane >> 4)];
-#pragma unroll
-          for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-            for (int bn = 0; bn < P::BN; ++bn)
-              acch[r][bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], bv[bn], acch[r][bm][bn], 0, 0, 0);
-        }
-      } else {
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.al[bm], f.brh[bn]);
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brl[bn]);
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brh[bn]);
+            acch[r][bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], bv[bn], acch[r][bm][bn], 0, 0, 0);
       }
     }
   };
 
   // Pipeline over chunks, LDS buffers rotating with the chunk index (chunk c
-  // sits in buffer c mod 3 from step c-2 to step c).  Step j: read the
-  // fragments of chunk j+1 (split precisions), multiply chunk j, write chunk
-  // j+2 from its stage set and refill that set with chunk j+2+R, then one
-  // barrier.  The LDS round trip of chunk j+1 and its B_im lane swaps overlap
-  // the matrix products of chunk j.
+  // sits in buffer c mod 3 from step c-2 to step c).  Step j: multiply chunk
+  // j, write chunk j+2 from its stage set and refill that set with chunk
+  // j+2+R, then one barrier.  The global loads of chunk j+2+R are in flight
+  // over the products of R steps.
   T* buf_c = stage;                          // chunk j
   T* buf_r = stage + TL::STAGE_ELEMS;        // chunk j+1
   T* buf_w = stage + 2 * TL::STAGE_ELEMS;    // chunk j+2
@@ -1303,32 +1213,15 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   if (R < nch) load(set(std::integral_constant<int, 0>{}), R);
   if (R + 1 < nch) load(set(std::integral_constant<int, 1>{}), R + 1);
   __syncthreads();
-  read_frag(fr0, buf_c);
-  // flags: 1 read the next fragments, 2 write chunk j+2, 4 refill its stage set
+  // flags: 2 write chunk j+2, 4 refill its stage set
   auto step = [&](int j, auto slot, auto flags, auto&& compute_fn) {
     constexpr int sl = decltype(slot)::value;
     constexpr int FL = decltype(flags)::value;
-    if constexpr (FL & 1) read_frag(frag(std::integral_constant<int, sl + 1>{}), buf_r);
-    compute_fn(frag(slot), (const T*)buf_c);
+    compute_fn((const T*)buf_c);
     if constexpr (FL & 2) {
       u32x4* sw = set(std::integral_constant<int, sl + 2>{});
       store_from(sw, buf_w);
       if constexpr (FL & 4) load(sw, j + 2 + R);
-    }
-    if constexpr (PREC != kFP64) {
-      // interleave: the next chunk's LDS reads first, a few matrix products
-      // to cover their latency, then products alternating with the lane
-      // swaps, then the LDS writes and the global loads
-      constexpr int NRD = 2 * (P::BM + P::BN);          // LDS fragment reads
-      constexpr int NMF = 6 * P::BM * P::BN;            // matrix products ((d|h) step)
-      __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-      static_for<NMF - 2>([&](auto) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
-      });
-      __builtin_amdgcn_sched_group_barrier(0x200, TL::PIECES_PER_THREAD, 0);
-      __builtin_amdgcn_sched_group_barrier(0x020, TL::PIECES_PER_THREAD, 0);
     }
     __syncthreads();
     T* t = buf_c;
@@ -1337,17 +1230,16 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     buf_w = t;
   };
   // every group spans a multiple of 4 chunks (bins padded to 64), so the
-  // fragment set (j mod 2) and stage set (j mod R) of each step are static;
-  // with NHB >= R + 2 (h|h) blocks after them, every (d|h) step reads, writes
-  // and refills
+  // stage set (j mod R) of each step is static; with NHB >= R + 2 (h|h)
+  // blocks after them, every (d|h) step writes and refills
   int ch = 0;
   static_for<G>([&](auto gi) {
     constexpr int g = decltype(gi)::value;
     const int gend = a.mt.gk0[g + 1];
     for (; ch < gend; ch += 4) {
       static_for<4>([&](auto slot) {
-        step(ch + decltype(slot)::value, slot, std::integral_constant<int, 7>{},
-             [&](const Frag& f, const T* base) { compute_dh(f, base, gi); });
+        step(ch + decltype(slot)::value, slot, std::integral_constant<int, 6>{},
+             [&](const T* base) { compute_dh(base, gi); });
       });
     }
   });
@@ -1360,9 +1252,9 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       for (int bn = 0; bn < P::BN; ++bn) acch[r][bm][bn] = Acc{0, 0, 0, 0};
   static_for<NHB>([&](auto ri) {
     constexpr int r = decltype(ri)::value;
-    constexpr int fl = (r + 1 < NHB ? 1 : 0) | (r + 2 < NHB ? 2 : 0) | (r + 2 + R < NHB ? 4 : 0);
+    constexpr int fl = (r + 2 < NHB ? 2 : 0) | (r + 2 + R < NHB ? 4 : 0);
     step(ndh + r, std::integral_constant<int, r % 4>{}, std::integral_constant<int, fl>{},
-         [&](const Frag& f, const T* base) { compute_hh(f, base, ri); });
+         [&](const T* base) { compute_hh(base, ri); });
   });
   }
 
