@@ -518,7 +518,8 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
     return code;
   };
   const size_t esz = bk->prec == kFP64 ? 8 : 2;
-  const size_t nA = (size_t)bk->n_wf * bk->K2;
+  // split precisions: whole 32-row blocks (op_index layout)
+  const size_t nA = (size_t)(bk->prec == kFP64 ? bk->n_wf : round_up(bk->n_wf, 32)) * bk->K2;
   if ((rc = dev_alloc(ctx, &bk->A0, nA * esz, &owned, &bk->bytes))) return cleanup(rc);
   if (bk->prec != kFP64) {
     if ((rc = dev_alloc(ctx, &bk->A1, nA * esz, &owned, &bk->bytes))) return cleanup(rc);
@@ -560,8 +561,9 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
     }
     if ((e = hipGetLastError())) return hip_fail(e, "bank convert");
   } else {
-    int64_t rows_per = std::max<int64_t>(1, (int64_t)((256ull << 20) / row_bytes));
-    rows_per = std::min(rows_per, bk->n_wf);
+    // whole 32-row blocks per stage, so that a stage starts a block
+    int64_t rows_per = std::max<int64_t>(32, (int64_t)((256ull << 20) / row_bytes) / 32 * 32);
+    rows_per = std::min(rows_per, round_up(bk->n_wf, 32));
     double* stagebuf = nullptr;
     if ((e = hipMalloc((void**)&stagebuf, rows_per * row_bytes))) return hip_fail(e, "stage alloc");
     for (int64_t r0 = 0; r0 < bk->n_wf; r0 += rows_per) {
@@ -719,7 +721,9 @@ std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) 
   if (D.prec != kFP64) v.push_back({(void**)&ev->col_scale, (size_t)D.ne * 8, false});
   v.push_back({(void**)&ev->hh_terms, (size_t)D.KH * sizeof(int), false});
   for (int q = 0; q < (D.prec == kFP64 ? 1 : 2); ++q) {
-    v.push_back({&ev->Ah[q], (size_t)D.n_sub * D.KH * esz, false});
+    // split precisions: whole 32-row blocks (op_index layout)
+    const int64_t ah_rows = D.prec == kFP64 ? D.n_sub : round_up(D.n_sub, 32);
+    v.push_back({&ev->Ah[q], (size_t)ah_rows * D.KH * esz, false});
     v.push_back({&ev->Bh[q], (size_t)D.ne_p * D.KH * esz, false});
   }
   if (D.prec != kFP64) {

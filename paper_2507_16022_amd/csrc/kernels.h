@@ -28,6 +28,7 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMaxC = 8;        // channels
 constexpr int kMaxG = 4;        // distinct m
@@ -144,6 +145,21 @@ __global__ void k_debug_distmarg(int64_t n, const double* dh, const double* hh, 
   out[i] = dr_ln_marg(dh[i], hh[i], r0, da.tab, da.prm->geom, da.prm->ghx, da.prm->ghw);
 }
 
+// Element offset of (row i, position k) in an operand with K positions per
+// row (K a multiple of 32).  FP64: row-major.  Split precisions: fragment
+// order -- 32-row blocks; within a block each chunk of 32 positions is 2 KB
+// made of 2 slices (positions 16 s .. 16 s + 15) of 1 KB, and in a slice the
+// 8 positions of piece h (8 h .. 8 h + 7) of row r sit at elements
+// 8 (32 h + r) .. +7.  One 32-row slice is then exactly the 1 KB that a
+// 32x32x16 matrix-core operand read takes (lane 32 h + r holds row r, piece
+// h), so loads and LDS reads are contiguous.
+template <int PREC>
+__host__ __device__ __forceinline__ int64_t op_index(int64_t i, int64_t k, int64_t K) {
+  if (PREC == kFP64) return i * K + k;
+  return ((i >> 5) * (K >> 5) + (k >> 5)) * 1024 + ((k >> 4) & 1) * 512 + ((k >> 3) & 1) * 256 +
+         (i & 31) * 8 + (k & 7);
+}
+
 // ---------------------------------------------------------------------------
 // bank-summary layout: FP64 amplitudes -> MFMA operand rows
 // row layout (K2 = n_c * n_bp * 2 per row): for channel c (group order) and
@@ -186,46 +202,47 @@ __global__ void k_bank_convert(const double* __restrict__ h, int64_t n_wf, int n
       re = ldexp(src[0], -ex);
       im = -ldexp(src[1], -ex);                 // conj(h)
     }
-    int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
-    int64_t o = (int64_t)row * K2 + base;
+    const int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+    const int64_t o = op_index<PREC>(row, base, K2), o16 = op_index<PREC>(row, base + 16, K2);
     if (PREC == kFP64) {
       double* A = (double*)A0;
       A[o] = re;
-      A[o + 16] = im;
+      A[o16] = im;
     } else if (PREC == kFP16X2) {
       _Float16* Ah = (_Float16*)A0;
       _Float16* Al = (_Float16*)A1;
       _Float16 hr_ = (_Float16)re, hi_ = (_Float16)im;
-      Ah[o] = hr_; Ah[o + 16] = hi_;
-      Al[o] = (_Float16)(re - (double)hr_); Al[o + 16] = (_Float16)(im - (double)hi_);
+      Ah[o] = hr_; Ah[o16] = hi_;
+      Al[o] = (_Float16)(re - (double)hr_); Al[o16] = (_Float16)(im - (double)hi_);
     } else {
       __bf16* Ah = (__bf16*)A0;
       __bf16* Al = (__bf16*)A1;
       __bf16 hr_ = (__bf16)(float)re, hi_ = (__bf16)(float)im;
-      Ah[o] = hr_; Ah[o + 16] = hi_;
+      Ah[o] = hr_; Ah[o16] = hi_;
       Al[o] = (__bf16)(float)(re - (double)(float)hr_);
-      Al[o + 16] = (__bf16)(float)(im - (double)(float)hi_);
+      Al[o16] = (__bf16)(float)(im - (double)(float)hi_);
     }
   }
 }
 
-// reconstructed conj(h) value (A) of row, channel c (group order), bin b
+// reconstructed conj(h) value (A) of row i, channel c (group order), bin b
 template <int PREC>
-__device__ __forceinline__ double2 bank_value(const void* A0, const void* A1, int64_t rowoff,
+__device__ __forceinline__ double2 bank_value(const void* A0, const void* A1, int64_t i, int64_t K2,
                                               int c, int b, int n_bp) {
-  int64_t o = rowoff + ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+  const int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+  const int64_t o = op_index<PREC>(i, base, K2), o16 = op_index<PREC>(i, base + 16, K2);
   if (PREC == kFP64) {
     const double* A = (const double*)A0;
-    return make_double2(A[o], A[o + 16]);
+    return make_double2(A[o], A[o16]);
   } else if (PREC == kFP16X2) {
     const _Float16* Ah = (const _Float16*)A0;
     const _Float16* Al = (const _Float16*)A1;
-    return make_double2((double)Ah[o] + (double)Al[o], (double)Ah[o + 16] + (double)Al[o + 16]);
+    return make_double2((double)Ah[o] + (double)Al[o], (double)Ah[o16] + (double)Al[o16]);
   } else {
     const __bf16* Ah = (const __bf16*)A0;
     const __bf16* Al = (const __bf16*)A1;
     return make_double2((double)(float)Ah[o] + (double)(float)Al[o],
-                        (double)(float)Ah[o + 16] + (double)(float)Al[o + 16]);
+                        (double)(float)Ah[o16] + (double)(float)Al[o16]);
   }
 }
 
@@ -389,17 +406,17 @@ __global__ void k_convert_B(int64_t n_ext, int64_t n_ext_p, int n_c, int n_bp,
       br = ldexp(v.x, -ex);
       bi = ldexp(v.y, -ex);
     }
-    int64_t o = e * K2 + ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
-    double re_lo_part[2] = {br, -bi};   // Bre at o, o+16
-    double im_lo_part[2] = {bi, br};    // Bim at o, o+16
+    const int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+    const int64_t o = op_index<PREC>(e, base, K2), o16 = op_index<PREC>(e, base + 16, K2);
     if (PREC == kFP64) {
       double* Bre = (double*)B0;
       double* Bim = (double*)B1;
-      Bre[o] = re_lo_part[0]; Bre[o + 16] = re_lo_part[1];
-      Bim[o] = im_lo_part[0]; Bim[o + 16] = im_lo_part[1];
+      Bre[o] = br; Bre[o16] = -bi;     // B_re = [Br | -Bi]
+      Bim[o] = bi; Bim[o16] = br;      // B_im = [Bi | Br]
     } else {
-      // split precisions: B_re only (B_im is formed in registers)
-      for (int q = 0; q < 2; ++q) store_split<PREC>(B0, B1, o + 16 * q, re_lo_part[q]);
+      // split precisions: B_re only (B_im is the other slice of B_re)
+      store_split<PREC>(B0, B1, o, br);
+      store_split<PREC>(B0, B1, o16, -bi);
     }
   }
 }
@@ -445,7 +462,8 @@ __device__ __forceinline__ double term_value(int code, const double2* X, int NP,
 
 // per-waveform (h|h) sums H_ikcc' = sum_b w_kb h_icb conj(h_ic'b) for the
 // event's bank subset, from the same operand values the contraction uses,
-// written as the row-side (h|h) operand [n_sub][KH] with a power-of-two
+// written as the row-side (h|h) operand (n_sub rows of KH, op_index layout)
+// with a power-of-two
 // row scale in the split precisions
 template <int PREC>
 __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_idx, int64_t sub0,
@@ -462,11 +480,10 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   if (ie >= n_sub) return;
   const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
   const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
-  const int64_t rowoff = i * K2;
   const bool staged = (size_t)mt.n_c * n_bp * sizeof(double2) <= 65536;
   if (staged) {
     for (int t = threadIdx.x; t < mt.n_c * n_bp; t += blockDim.x)
-      rowbuf[t] = bank_value<PREC>(A0, A1, rowoff, t / n_bp, t % n_bp, n_bp);
+      rowbuf[t] = bank_value<PREC>(A0, A1, i, K2, t / n_bp, t % n_bp, n_bp);
     __syncthreads();
   }
   double sc = row_scale ? row_scale[i] : 1.0;
@@ -476,8 +493,8 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
     int c = mt.pc[p], c2 = mt.pc2[p];
     double2 acc = make_double2(0.0, 0.0);
     for (int b = 0; b < n_b; ++b) {
-      double2 a = staged ? rowbuf[c * n_bp + b] : bank_value<PREC>(A0, A1, rowoff, c, b, n_bp);
-      double2 a2 = staged ? rowbuf[c2 * n_bp + b] : bank_value<PREC>(A0, A1, rowoff, c2, b, n_bp);
+      double2 a = staged ? rowbuf[c * n_bp + b] : bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
+      double2 a2 = staged ? rowbuf[c2 * n_bp + b] : bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
       double2 v = cmul(cconj(a), a2);      // h_c conj(h_c') = conj(A_c) A_c'
       double ww = w[k * n_b + b];
       acc.x += ww * v.x;
@@ -502,10 +519,11 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   if (PREC != kFP64 && red[0] > 0.0 && isfinite(red[0])) ex = ilogb(red[0]) - 13;
   if (threadIdx.x == 0 && hscale) hscale[ie] = ldexp(1.0, ex);
   for (int j = threadIdx.x; j < KH; j += blockDim.x)
-    store_split<PREC>(H0, H1, ie * KH + j, ldexp(vals[j], -ex));
+    store_split<PREC>(H0, H1, op_index<PREC>(ie, j, KH), ldexp(vals[j], -ex));
 }
 
-// column-side (h|h) operand [n_ext_p][KH] from Q_ekcc' = R_ekc conj(R_ekc')
+// column-side (h|h) operand (n_ext_p rows of KH, op_index layout) from
+// Q_ekcc' = R_ekc conj(R_ekc')
 template <int PREC>
 __global__ void k_build_Bhh(int64_t n_ext, int64_t n_ext_p, int n_det, const double2* __restrict__ Q,
                             ModeTables mt, const int* __restrict__ terms, int KH,
@@ -531,7 +549,7 @@ __global__ void k_build_Bhh(int64_t n_ext, int64_t n_ext_p, int n_det, const dou
   if (PREC != kFP64 && red[0] > 0.0 && isfinite(red[0])) ex = ilogb(red[0]) - 13;
   if (threadIdx.x == 0 && bscale && e < n_ext) bscale[e] = ldexp(1.0, ex);
   for (int j = threadIdx.x; j < KH; j += blockDim.x)
-    store_split<PREC>(B0, B1, e * KH + j, ldexp(vals[j], -ex));
+    store_split<PREC>(B0, B1, op_index<PREC>(e, j, KH), ldexp(vals[j], -ex));
 }
 
 // ---------------------------------------------------------------------------
@@ -539,7 +557,8 @@ __global__ void k_build_Bhh(int64_t n_ext, int64_t n_ext_p, int n_det, const dou
 // then the per-pair marginalisation epilogue
 // ---------------------------------------------------------------------------
 struct FusedArgs {
-  // bank operand (row-major [n_wf][K2])
+  // operands are laid out by op_index
+  // bank operand (n_wf rows of K2)
   const void* A0;
   const void* A1;
   const double* row_scale;
@@ -547,7 +566,7 @@ struct FusedArgs {
   // subset
   const int64_t* sub_idx;
   int64_t sub0, n_sub;
-  // extrinsic operand ([n_ext_p][K2])
+  // extrinsic operand (n_ext_p rows of K2)
   const void* B0;
   const void* B1;
   const void* B2;
@@ -557,7 +576,7 @@ struct FusedArgs {
   int64_t n_ext, n_ext_p;
   int64_t K2;
   int n_chunks;
-  // (h|h) operands ([n_sub][KH] and [n_ext_p][KH])
+  // (h|h) operands (n_sub and n_ext_p rows of KH)
   const void* Ah0;
   const void* Ah1;
   const double* ah_scale;
@@ -594,25 +613,26 @@ struct FusedArgs {
 
 template <int PREC>
 struct Pol;
-// FP64: 4 waves (2 x 2), each 32 x 16 pairs; 64 x 32 tile
+// BS x BS: the output block of one matrix-core product, NE of whose
+// elements each lane holds.
+// FP64: 4 waves (2 x 2), each 32 x 16 pairs (16x16x4 products); 64 x 32 tile
 template <>
 struct Pol<kFP64> {
   typedef double T;
   typedef f64x4 Acc;
   static constexpr int NA = 1, NB = 2, PITCH = 33, BM = 2, BN = 1, WM = 2, WN = 2;
+  static constexpr int BS = 16, NE = 4;
 };
-// split precisions: 8 waves (2 x 4), each 32 x 16 pairs; 64 x 64 tile.  Two
-// waves per SIMD: the accumulators of a 32 x 16 wave tile (4 m groups x re/im
-// plus 7 (h|h) outputs) leave room for two waves' registers.
+// split precisions: 4 waves (2 x 2), one per SIMD, each 32 x 32 pairs
+// (32x32x16 products); 64 x 64 tile.  A wave's accumulators (4 m groups x
+// re/im plus 7 (h|h) outputs, 240 registers) sit in the accumulation
+// registers; single-wave issue keeps the matrix core at its full rate.
 template <>
 struct Pol<kFP16X2> {
   typedef uint16_t T;
-  typedef f32x4 Acc;
-  // B_im = [Bi | Br] is formed in registers from B_re = [Br | -Bi]
-  // rows of 32 halfs without padding: the 16-byte pieces of a row are
-  // XOR-swizzled instead (see lds_swz), which keeps the fragment reads
-  // conflict-free and lets the loads write whole rows straight into LDS
-  static constexpr int NA = 2, NB = 2, PITCH = 32, BM = 2, BN = 1, WM = 2, WN = 4;
+  typedef f32x16 Acc;
+  static constexpr int NA = 2, NB = 2, PITCH = 32, BM = 1, BN = 1, WM = 2, WN = 2;
+  static constexpr int BS = 32, NE = 16;
 };
 template <>
 struct Pol<kBF16X2> : Pol<kFP16X2> {};
@@ -622,8 +642,8 @@ struct Tile {
   typedef Pol<PREC> P;
   static constexpr int NW = P::WM * P::WN;           // waves per workgroup
   static constexpr int NT = 64 * NW;                 // threads per workgroup
-  static constexpr int TM = P::WM * 16 * P::BM;      // rows per workgroup tile
-  static constexpr int TN = P::WN * 16 * P::BN;      // columns per workgroup tile
+  static constexpr int TM = P::WM * P::BS * P::BM;   // rows per workgroup tile
+  static constexpr int TN = P::WN * P::BS * P::BN;   // columns per workgroup tile
   static constexpr int STAGE_ELEMS = (P::NA * TM + P::NB * TN) * P::PITCH;
   static constexpr int STAGE_BYTES = STAGE_ELEMS * (int)sizeof(typename P::T);
   static constexpr int ACC_T_BYTES = (PREC == kFP64) ? 8 : 4;
@@ -677,18 +697,20 @@ __device__ __forceinline__ void pipeline_barrier() {
   __asm__ __volatile__("" ::: "memory");
 }
 
+// acc += a b over 16 positions (32 x 32 block): lane 32 h + r holds
+// positions 8 h .. 8 h + 7 of row r of a and of column r of b
 template <int PREC>
 __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a, const uint4& b) {
   if constexpr (PREC == kFP16X2) {
     half8 av, bv;
     __builtin_memcpy(&av, &a, 16);
     __builtin_memcpy(&bv, &b, 16);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
   } else if constexpr (PREC == kBF16X2) {
     bf16x8 av, bv;
     __builtin_memcpy(&av, &a, 16);
     __builtin_memcpy(&bv, &b, 16);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
   }
 }
 
@@ -886,48 +908,52 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
 #pragma unroll
       for (int bn = 0; bn < P::BN; ++bn)
 #pragma unroll
-        for (int ri = 0; ri < 2; ++ri) acc[g][bm][bn][ri] = Acc{0, 0, 0, 0};
+        for (int ri = 0; ri < 2; ++ri) acc[g][bm][bn][ri] = Acc{};
 
   if constexpr (PREC != kFP64) {
-    // ---- split precisions: loads straight into LDS, 4 buffers ----
-    // Each wave issues 2 loads of 64 x 16 bytes per chunk; lane l of load q
-    // fills 16-byte unit u = (2 wave + q) 64 + l of the 16 KB buffer, i.e. row
-    // u / 4 (A hi, A lo, B hi, B lo: 64 rows each) and physical piece u mod 4,
-    // which holds logical piece (u mod 4) ^ lds_swz(row).  Rows past the
-    // subset re-read the last row (their pairs are never used).
+    // ---- split precisions: loads straight into LDS, NS buffers ----
+    // A stage buffer (16 KB) holds one chunk of A hi, A lo, B hi, B lo: 4 KB
+    // each, 2 row blocks x 2 slices of 1 KB, each slice copied as it sits in
+    // HBM (op_index order), which is the order a fragment read wants.  Wave w
+    // loads array w: its load q brings row block q / 2, slice q % 2.  Rows
+    // past the subset re-read the last row (their pairs are never used).
     typedef __attribute__((address_space(1))) const unsigned char gbyte;
     typedef __attribute__((address_space(3))) void lvoid;
     constexpr int ES = (int)sizeof(T);
     constexpr int NS = TL::NSB;
-    static_assert(TL::PIECES_PER_THREAD == 2 && TL::STAGE_BYTES == 16384, "split staging layout");
-    gbyte* srcp[2];
-    gbyte* srch[2];
+    constexpr int LPC = 4;               // loads per thread per chunk
+    static_assert(TL::PIECES_PER_THREAD == LPC && TL::STAGE_BYTES == 16384 && NW == 4 &&
+                      P::BM == 1 && P::BN == 1 && TM == 64 && TN == 64,
+                  "split staging layout");
+    gbyte* srcp[LPC];
+    gbyte* srch[LPC];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int u = (wave * 2 + q) * 64 + lane;
-      const int row = u >> 2, lp = (u & 3) ^ lds_swz(row & 15);
-      if (row < P::NA * TM) {
-        const int arr = row / TM, r = row % TM;
+    for (int q = 0; q < LPC; ++q) {
+      // row r of the tile; element offset of its piece lane / 32 in slice q % 2
+      // of chunk 0 (a chunk adds 1024 elements)
+      const int r = 32 * (q >> 1) + (lane & 31);
+      const int64_t in_chunk = (q & 1) * 512 + (lane >> 5) * 256;
+      auto blk = [](int64_t i, int64_t K) { return (i >> 5) * (K >> 5) * 1024 + (i & 31) * 8; };
+      if (wave < 2) {
         const int64_t ie = min(row0 + r, a.n_sub - 1);
         const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-        srcp[q] = (gbyte*)(arr == 0 ? a.A0 : a.A1) + (i * a.K2 + lp * 8) * ES;
-        srch[q] = (gbyte*)(arr == 0 ? a.Ah0 : a.Ah1) + (ie * a.KH + lp * 8) * ES;
+        srcp[q] = (gbyte*)(wave == 0 ? a.A0 : a.A1) + (blk(i, a.K2) + in_chunk) * ES;
+        srch[q] = (gbyte*)(wave == 0 ? a.Ah0 : a.Ah1) + (blk(ie, a.KH) + in_chunk) * ES;
       } else {
-        const int rs = row - P::NA * TM;
-        const int arr = rs / TN, c = rs % TN;
-        srcp[q] = (gbyte*)(arr == 0 ? a.B0 : a.B1) + ((col0 + c) * a.K2 + lp * 8) * ES;
-        srch[q] = (gbyte*)(arr == 0 ? a.Bh0 : a.Bh1) + ((col0 + c) * a.KH + lp * 8) * ES;
+        const int64_t e = col0 + r;
+        srcp[q] = (gbyte*)(wave == 2 ? a.B0 : a.B1) + (blk(e, a.K2) + in_chunk) * ES;
+        srch[q] = (gbyte*)(wave == 2 ? a.Bh0 : a.Bh1) + (blk(e, a.KH) + in_chunk) * ES;
       }
     }
     const int ndh = a.n_chunks;        // (d|h) chunks (a multiple of 4)
-    const int nch = ndh + NHB;         // then the (h|h) blocks
-    // chunk c into buffer c mod 4
+    // chunk c into buffer c mod NS: a (d|h) chunk for c < ndh, else (h|h)
+    // block c - ndh
     auto issue = [&](int c) {
       const bool hh = c >= ndh;
-      const int64_t od = (int64_t)c * 32 * ES, oh = (int64_t)(c - ndh) * 32 * ES;
-      unsigned char* buf = smem + (c & (NS - 1)) * TL::STAGE_BYTES + wave * 2048;
+      const int64_t od = (int64_t)c * 1024 * ES, oh = (int64_t)(c - ndh) * 1024 * ES;
+      unsigned char* buf = smem + (c & (NS - 1)) * TL::STAGE_BYTES + wave * 4096;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < LPC; ++q) {
         gbyte* pq = hh ? srch[q] + oh : srcp[q] + od;
         // issued as asm so that the compiler does not treat it as a pending
         // LDS store that every later LDS read must wait for; the pipeline's
@@ -937,85 +963,58 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
                              :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(pq) : "memory", "m0");
       }
     };
+    // fragments of one chunk: A hi/lo and B_re hi/lo of both slices
     struct Frag {
-      uint4 ah[P::BM], al[P::BM], brh[P::BN], brl[P::BN], bih[P::BN], bil[P::BN];
+      uint4 ah[2], al[2], bh[2], bl[2];
     };
     Frag fr0, fr1;
     auto frag = [&](auto fi) -> Frag& {
       if constexpr (decltype(fi)::value % 2 == 0) return fr0;
       else return fr1;
     };
-    const int lr = lane & 15;
-    const int swo = ((lane >> 4) ^ lds_swz(lr)) * 16;   // byte offset of this lane's piece
-    // B_im = [Bi | Br] is B_re = [Br | -Bi] with the two halves of the chunk
-    // exchanged (logical piece p ^ 2) and lanes 0-31 negated
-    const int swi = (((lane >> 4) ^ 2) ^ lds_swz(lr)) * 16;
-    const unsigned negm = lane < 32 ? 0x80008000u : 0u;
     auto read_frag = [&](Frag& f, int c) {
-      const unsigned char* base = smem + (c & (NS - 1)) * TL::STAGE_BYTES + swo;
+      const unsigned char* buf = smem + (c & (NS - 1)) * TL::STAGE_BYTES + lane * 16;
 #pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm) {
-        const int rr = wm * 16 * P::BM + bm * 16 + lr;
-        f.ah[bm] = *(const uint4*)(base + rr * 64);
-        f.al[bm] = *(const uint4*)(base + (TM + rr) * 64);
-      }
-#pragma unroll
-      for (int bn = 0; bn < P::BN; ++bn) {
-        const int cc = wn * 16 * P::BN + bn * 16 + lr;
-        f.brh[bn] = *(const uint4*)(base + (2 * TM + cc) * 64);
-        f.brl[bn] = *(const uint4*)(base + (2 * TM + TN + cc) * 64);
-        const unsigned char* bi = smem + (c & (NS - 1)) * TL::STAGE_BYTES + swi;
-        const uint4 x = *(const uint4*)(bi + (2 * TM + cc) * 64);
-        const uint4 y = *(const uint4*)(bi + (2 * TM + TN + cc) * 64);
-        f.bih[bn] = make_uint4(x.x ^ negm, x.y ^ negm, x.z ^ negm, x.w ^ negm);
-        f.bil[bn] = make_uint4(y.x ^ negm, y.y ^ negm, y.z ^ negm, y.w ^ negm);
+      for (int sl = 0; sl < 2; ++sl) {
+        f.ah[sl] = *(const uint4*)(buf + 0 * 4096 + (2 * wm + sl) * 1024);
+        f.al[sl] = *(const uint4*)(buf + 1 * 4096 + (2 * wm + sl) * 1024);
+        f.bh[sl] = *(const uint4*)(buf + 2 * 4096 + (2 * wn + sl) * 1024);
+        f.bl[sl] = *(const uint4*)(buf + 3 * 4096 + (2 * wn + sl) * 1024);
       }
     };
-    // (d|h) chunk: complex product, 3 split products per real product; the
-    // three products of one accumulator are separated by the independent ones
+    // (d|h) chunk: with A = [hr | hi] and B_re = [Br | -Bi] by slice,
+    // re += A B_re and im += A B_im, B_im = [Bi | Br] = [-(B_re slice 1) |
+    // B_re slice 0]; 3 split products per real product, the smaller ones
+    // first, re and im alternating
     auto compute_dh = [&](const Frag& f, auto gi) {
       constexpr int g = decltype(gi)::value;
-#pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], f.al[bm], f.brh[bn]);
-          mma<PREC>(acc[g][bm][bn][1], f.al[bm], f.bih[bn]);
-        }
-#pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brl[bn]);
-          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bil[bn]);
-        }
-#pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) {
-          mma<PREC>(acc[g][bm][bn][0], f.ah[bm], f.brh[bn]);
-          mma<PREC>(acc[g][bm][bn][1], f.ah[bm], f.bih[bn]);
-        }
+      const uint4 nbh = make_uint4(f.bh[1].x ^ 0x80008000u, f.bh[1].y ^ 0x80008000u,
+                                   f.bh[1].z ^ 0x80008000u, f.bh[1].w ^ 0x80008000u);
+      const uint4 nbl = make_uint4(f.bl[1].x ^ 0x80008000u, f.bl[1].y ^ 0x80008000u,
+                                   f.bl[1].z ^ 0x80008000u, f.bl[1].w ^ 0x80008000u);
+      Acc& re = acc[g][0][0][0];
+      Acc& im = acc[g][0][0][1];
+      mma<PREC>(re, f.al[0], f.bh[0]); mma<PREC>(im, f.al[0], nbh);
+      mma<PREC>(re, f.ah[0], f.bl[0]); mma<PREC>(im, f.ah[0], nbl);
+      mma<PREC>(re, f.ah[0], f.bh[0]); mma<PREC>(im, f.ah[0], nbh);
+      mma<PREC>(re, f.al[1], f.bh[1]); mma<PREC>(im, f.al[1], f.bh[0]);
+      mma<PREC>(re, f.ah[1], f.bl[1]); mma<PREC>(im, f.ah[1], f.bl[0]);
+      mma<PREC>(re, f.ah[1], f.bh[1]); mma<PREC>(im, f.ah[1], f.bh[0]);
     };
     // (h|h) block r: real product of the row and column (h|h) operands
     auto compute_hh = [&](const Frag& f, auto ri) {
       constexpr int r = decltype(ri)::value;
       if constexpr (r < NRT) {
+        Acc& h = acch[r][0][0];
 #pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.al[bm], f.brh[bn]);
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brl[bn]);
-#pragma unroll
-        for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < P::BN; ++bn) mma<PREC>(acch[r][bm][bn], f.ah[bm], f.brh[bn]);
+        for (int sl = 0; sl < 2; ++sl) {
+          mma<PREC>(h, f.al[sl], f.bh[sl]);
+          mma<PREC>(h, f.ah[sl], f.bl[sl]);
+          mma<PREC>(h, f.ah[sl], f.bh[sl]);
+        }
       }
     };
-    // prologue: chunks 0..3 in flight, wait for 0 and 1
+    // prologue: chunks 0..NS-1 in flight, wait for 0 and 1
     static_for<NS>([&](auto q) { issue(decltype(q)::value); });
     if (tid < TM) {
       rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
@@ -1023,35 +1022,35 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
     }
     if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
-    __syncthreads();                          // rowd, cold, counters
-    pipeline_barrier<2 * (NS - 2)>();         // chunks 0 and 1 have landed
+    __syncthreads();                              // rowd, cold, counters
+    pipeline_barrier<LPC * (NS - 2)>();           // chunks 0 and 1 have landed
     read_frag(fr0, 0);
-    pipeline_barrier<2 * (NS - 2)>();         // step 0 refills buffer 0: chunk 0 read everywhere
+    pipeline_barrier<LPC * (NS - 2)>();           // step 0 refills buffer 0: chunk 0 read everywhere
     // step j: read the fragments of chunk j+1, multiply chunk j, refill the
     // buffer of chunk j (its fragments were read before the last barrier)
-    // with chunk j+4, wait until chunk j+2 has landed, barrier.  FL: 1 read
-    // the next fragments, 2 issue chunk j+4; W: loads allowed in flight
-    auto step = [&](int j, auto slot, auto fl, auto w, auto&& compute_fn) {
+    // with chunk j+NS, wait until chunk j+2 has landed, barrier.  FL: 1 read
+    // the next fragments, 2 issue chunk j+NS; W: loads allowed in flight.
+    // One wave per SIMD issues everything: the LDS reads go between the
+    // matrix products so that they issue while a product runs.
+    auto step = [&](int j, auto slot, auto fl, auto w, auto nmf, auto&& compute_fn) {
       constexpr int sl = decltype(slot)::value;
       constexpr int FL = decltype(fl)::value;
+      constexpr int NMF = decltype(nmf)::value;
       if constexpr (FL & 1) read_frag(frag(std::integral_constant<int, sl + 1>{}), j + 1);
       compute_fn(frag(slot));
       if constexpr (FL & 2) issue(j + NS);
-      constexpr int NRD = 2 * (P::BM + 2 * P::BN);
-      constexpr int NMF = 6 * P::BM * P::BN;
-      __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-      static_for<NMF - 2>([&](auto) {
+      constexpr int NRD = (FL & 1) ? 8 : 0;
+      static_for<NMF>([&](auto k) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+        if constexpr (decltype(k)::value < NRD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       });
-      __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
       pipeline_barrier<decltype(w)::value>();
     };
     // every group spans a multiple of 4 chunks (bins padded to 64), so the
-    // fragment set of each step is static; with NHB = 8 (h|h) blocks after
-    // them every (d|h) step reads ahead, issues and keeps 2 chunks in flight
-    static_assert(NHB >= NS + 2, "pipeline needs NS + 2 trailing blocks");
+    // fragment set of each step is static; with at least NS (h|h) blocks
+    // after them every (d|h) step reads ahead, issues chunk j+NS and keeps
+    // chunks j+3..j+NS in flight
+    static_assert(NHB >= NS, "pipeline needs NS trailing blocks");
     int ch = 0;
     static_for<G>([&](auto gi) {
       constexpr int g = decltype(gi)::value;
@@ -1059,22 +1058,22 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       for (; ch < gend; ch += 4) {
         static_for<4>([&](auto slot) {
           step(ch + decltype(slot)::value, slot, std::integral_constant<int, 3>{},
-               std::integral_constant<int, 4>{}, [&](const Frag& f) { compute_dh(f, gi); });
+               std::integral_constant<int, LPC * (NS - 2)>{}, std::integral_constant<int, 12>{},
+               [&](const Frag& f) { compute_dh(f, gi); });
         });
       }
     });
 #pragma unroll
-    for (int r = 0; r < NRT; ++r)
-#pragma unroll
-      for (int bm = 0; bm < P::BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < P::BN; ++bn) acch[r][bm][bn] = Acc{0, 0, 0, 0};
+    for (int r = 0; r < NRT; ++r) acch[r][0][0] = Acc{};
     static_for<NHB>([&](auto ri) {
       constexpr int r = decltype(ri)::value;
       constexpr int fl = (r + 1 < NHB ? 1 : 0) | (r + NS < NHB ? 2 : 0);
-      constexpr int wc = 2 * ((r + 3 < NHB ? 1 : 0) + (r + 4 < NHB ? 1 : 0));
+      // in flight after this step's issue: blocks r+3 .. min(r+NS, NHB-1)
+      constexpr int last = (r + NS < NHB - 1) ? r + NS : NHB - 1;
+      constexpr int wc = LPC * (last > r + 2 ? last - r - 2 : 0);
       step(ndh + r, std::integral_constant<int, r % 4>{}, std::integral_constant<int, fl>{},
-           std::integral_constant<int, wc>{}, [&](const Frag& f) { compute_hh(f, ri); });
+           std::integral_constant<int, wc>{}, std::integral_constant<int, (r < NRT ? 6 : 0)>{},
+           [&](const Frag& f) { compute_hh(f, ri); });
     });
   } else {
   // per-thread source addresses of its 16-byte pieces for chunk 0 of the
@@ -1277,8 +1276,12 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   int n_pairs_i = 0, n_bounded_i = 0;
   AT* recs = (AT*)smem;                  // [BATCH][REC] survivors' records
   constexpr int XO = 0, SO = 2 * G;      // offsets of X and S in a record
-  // output element r of a lane's 16x16 accumulator block sits in row rowmap(r)
-  auto rowmap = [&](int r) { return (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r); };
+  // output element r of a lane's accumulator block sits in row rowmap(r),
+  // column lane mod BS (16x16x4 FP64 and 32x32x16 split-precision layouts)
+  auto rowmap = [&](int r) {
+    return (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
+  };
+  constexpr int BS = P::BS, NE = P::NE;
 
   // E1 for the pair in element r of block (bm, bn) of this lane, straight
   // from the accumulators: the certified bound on lnL^ML, bounded pairs into
@@ -1286,8 +1289,8 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   // counted but not written)
   auto e1_pair = [&](auto bmi, auto bni, auto ri) {
     constexpr int bm = decltype(bmi)::value, bn = decltype(bni)::value, r = decltype(ri)::value;
-    const int tc = wn * 16 * P::BN + bn * 16 + (lane & 15);
-    const int tr = wm * 16 * P::BM + bm * 16 + rowmap(r);
+    const int tc = wn * BS * P::BN + bn * BS + (lane & (BS - 1));
+    const int tr = wm * BS * P::BM + bm * BS + rowmap(r);
     if (!(col0 + tc < a.n_ext && row0 + tr < a.n_sub)) return;
     ++n_pairs_i;
     bool survive = true;
@@ -1391,7 +1394,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     // listed and contributes nothing here.
     static_for<P::BM>([&](auto bmi) {
       static_for<P::BN>([&](auto bni) {
-        static_for<4>([&](auto ri) { e1_pair(bmi, bni, ri); });
+        static_for<NE>([&](auto ri) { e1_pair(bmi, bni, ri); });
       });
     });
     __syncthreads();
@@ -1406,8 +1409,8 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     e2_list(nsurv);
   } else {
     // batches of 2 pairs per lane (at most BATCH survivors each)
-    static_for<P::BM * P::BN * 2>([&](auto bi) {
-      constexpr int bb = decltype(bi)::value >> 1, rh = decltype(bi)::value & 1;
+    static_for<P::BM * P::BN * (NE / 2)>([&](auto bi) {
+      constexpr int bb = decltype(bi)::value / (NE / 2), rh = decltype(bi)::value % (NE / 2);
       static_for<2>([&](auto ri) {
         e1_pair(std::integral_constant<int, bb / P::BN>{}, std::integral_constant<int, bb % P::BN>{},
                 std::integral_constant<int, 2 * rh + decltype(ri)::value>{});
