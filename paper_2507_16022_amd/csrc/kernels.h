@@ -126,6 +126,13 @@ __device__ __forceinline__ double order_value(uint64_t u) {
   u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
   return __longlong_as_double(u);
 }
+// value of lane src (wave-uniform) of a double
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, src);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // ---------------------------------------------------------------------------
 // distance-marginalisation table
@@ -662,7 +669,8 @@ struct Tile {
   static constexpr int LIST_OFF = COLD_OFF + TN * 3 * 8;           // uint16 [BATCH]
   static constexpr int RED_OFF = (LIST_OFF + BATCH * 2 + 15) / 16 * 16;   // double [NW][kNPart]
   static constexpr int CNT_OFF = RED_OFF + NW * kNPart * 8;        // int counter, u64 max
-  static constexpr int MAIN_BYTES = CNT_OFF + 16;
+  static constexpr int ROWQ_OFF = CNT_OFF + 16;                    // double [TM][2]
+  static constexpr int MAIN_BYTES = ROWQ_OFF + TM * 2 * 8;
   static constexpr int PIECE_ELEMS = 16 / (int)sizeof(typename P::T);   // 16-byte pieces
   static constexpr int PIECES_PER_ROW = 32 / PIECE_ELEMS;
   static constexpr int PIECES = (P::NA * TM + P::NB * TN) * PIECES_PER_ROW;
@@ -678,10 +686,16 @@ __device__ __forceinline__ int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3
 
 // wait until at most N vector-memory operations of this wave are in flight
 // (expcnt and lgkmcnt left unconstrained)
+// s_waitcnt immediate: vmcnt N (6 bits, split over [3:0] and [15:14]),
+// expcnt unconstrained, lgkmcnt L
+template <int N, int L>
+constexpr int waitcnt_imm() {
+  static_assert(N >= 0 && N < 64 && L >= 0 && L < 16, "waitcnt immediate");
+  return (N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (L << 8);
+}
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 16, "vmcnt immediate");
-  __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0xF << 8));
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm<N, 0xF>());
 }
 
 // workgroup barrier for the LDS-load pipeline: this wave's LDS reads are
@@ -690,8 +704,7 @@ __device__ __forceinline__ void wait_vmcnt() {
 // also wait for every load still streaming into LDS.)
 template <int N>
 __device__ __forceinline__ void pipeline_barrier() {
-  static_assert(N >= 0 && N < 16, "vmcnt immediate");
-  __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0x0 << 8));
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm<N, 0>());
   __asm__ __volatile__("" ::: "memory");
   __builtin_amdgcn_s_barrier();
   __asm__ __volatile__("" ::: "memory");
@@ -716,28 +729,64 @@ __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a
 
 enum Mode { kEval = 0, kEvidence = 1, kPilot = 2 };
 
-__device__ __forceinline__ double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
+// Wave-wide reductions through DPP lane moves (no LDS round trips): pairs
+// of lanes, quads, half rows and rows of 16 are combined within rows, then
+// rows 0+1 and 2+3 by the row-15 broadcast and all four by the lane-31
+// broadcast; lane 63 ends with the result, which is then read by every lane.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ unsigned dpp_mov(unsigned ident, unsigned v) {
+  return __builtin_amdgcn_update_dpp(ident, v, CTRL, ROWMASK, 0xF, false);
 }
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_mov(double ident, double v) {
+  const unsigned long long bi = (unsigned long long)__double_as_longlong(ident);
+  const unsigned long long bv = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = dpp_mov<CTRL, ROWMASK>((unsigned)bi, (unsigned)bv);
+  const unsigned hi = dpp_mov<CTRL, ROWMASK>((unsigned)(bi >> 32), (unsigned)(bv >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_mov(float ident, float v) {
+  return __uint_as_float(dpp_mov<CTRL, ROWMASK>(__float_as_uint(ident), __float_as_uint(v)));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_mov(int ident, int v) {
+  return (int)dpp_mov<CTRL, ROWMASK>((unsigned)ident, (unsigned)v);
+}
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, T ident, Op op) {
+  v = op(v, dpp_mov<0xB1, 0xF>(ident, v));    // quad_perm 1,0,3,2
+  v = op(v, dpp_mov<0x4E, 0xF>(ident, v));    // quad_perm 2,3,0,1
+  v = op(v, dpp_mov<0x141, 0xF>(ident, v));   // row_half_mirror
+  v = op(v, dpp_mov<0x140, 0xF>(ident, v));   // row_mirror
+  v = op(v, dpp_mov<0x142, 0xA>(ident, v));   // row_bcast:15
+  v = op(v, dpp_mov<0x143, 0xC>(ident, v));   // row_bcast:31
+  return v;                                   // complete in lane 63
+}
+__device__ __forceinline__ double wave_max(double v) {
+  return read_lane(wave_reduce(v, (double)-INFINITY, [](double x, double y) { return fmax(x, y); }), 63);
 }
 
 // float online log-sum-exp (for upper bounds of cut contributions)
 struct LseF {
   float m, s;
   __device__ void init() { m = -INFINITY; s = 0.f; }
+  // x = -inf leaves it unchanged; branch-free (one exponential)
   __device__ void add(float x) {
-    if (x > m) { s = s * __expf(m - x) + 1.f; m = x; }
-    else s += __expf(x - m);
+    const float d = x - m;
+    const float t = __expf(-fabsf(d));
+    const bool up = d > 0.f;
+    const float ns = up ? fmaf(s, t, 1.f) : s + t;
+    const float nm = up ? x : m;
+    const bool skip = !(x > -INFINITY);
+    s = skip ? s : ns;
+    m = skip ? m : nm;
   }
   __device__ void merge(float mb, float sb) {
-    if (mb == -INFINITY) return;
-    if (m == -INFINITY) { m = mb; s = sb; return; }
-    float mm = fmaxf(m, mb);
-    s = s * __expf(m - mm) + sb * __expf(mb - mm);
+    const float mm = fmaxf(m, mb);
+    const float sa = m == -INFINITY ? 0.f : s * __expf(m - mm);
+    const float sc = mb == -INFINITY ? 0.f : sb * __expf(mb - mm);
+    s = sa + sc;
     m = mm;
   }
 };
@@ -748,30 +797,30 @@ struct EvAcc {
   LseF drop;          // upper bounds of everything cut (ln)
   double ml_max;      // max lnL^ML over evaluated triples
   float max_bound;    // max over bounded pairs of ln w + bound
-  double n_marg, n_bounded, n_pairs;
+  int n_marg;         // kept phases evaluated
+  double n_bounded, n_pairs;
   __device__ void init() {
     p.init(); drop.init();
     ml_max = 0.0; max_bound = -INFINITY;
-    n_marg = 0.0; n_bounded = 0.0; n_pairs = 0.0;
+    n_marg = 0; n_bounded = 0.0; n_pairs = 0.0;
   }
 };
 
-// full evaluation of one pair given X_g and the (h|h) coefficients: phase
-// loop, cut, distance marginalisation; returns ln p (-inf when nothing kept)
+// phases o = o0, o0 + os, ... of one pair given X_g and the (h|h)
+// coefficients: cut, distance marginalisation.  The kept phases' ln L go to
+// lse, the best one to best / o_best (first of equal values), the largest
+// lnL^ML to mlmax; cut phases' upper bounds go to ev.drop.  The caller
+// combines the parts of one pair.
 template <int MODE, int G>
-__device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie, int64_t e,
+__device__ void pair_phases(const FusedArgs& a, const double* lds_cs, int64_t ie, int64_t e,
                             const double2 (&X)[G], double S0, const double (&Sr)[kMaxND],
-                            const double (&Si)[kMaxND], double lnw, double thr_ml, EvAcc& ev,
-                            int& o_best) {
+                            const double (&Si)[kMaxND], double lnw, double thr_ml, int o0, int os,
+                            EvAcc& ev, Lse& lse, double& best, int& o_best, double& mlmax) {
   constexpr bool EVAL = MODE == kEval;
   const ModeTables& mt = a.mt;
   const int ND = mt.ND;
-  o_best = 0;
-  Lse lse;
-  lse.init();
-  double best = -INFINITY, mlmax = 0.0;
   const double thr2 = 2.0 * thr_ml;
-  for (int o = 0; o < a.n_phi; ++o) {
+  for (int o = o0; o < a.n_phi; o += os) {
     double dh = 0.0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -805,20 +854,8 @@ __device__ double pair_full(const FusedArgs& a, const double* lds_cs, int64_t ie
     double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, a.dist.prm->geom, a.dist.prm->ghx, a.dist.prm->ghw);
     if (v > best) { best = v; o_best = o; }
     lse.add(v);
-    if (!EVAL) ev.n_marg += 1.0;
+    if (!EVAL) ev.n_marg += 1;
   }
-  double lnl = (lse.m == -INFINITY) ? -INFINITY : lse.m + log(lse.s) - a.ln_nphi;
-  if (EVAL) {
-    size_t t = (size_t)ie * a.n_ext + e;
-    a.lnl_out[t] = lnl;
-    if (a.ml_out) a.ml_out[t] = mlmax;
-    return lnl;
-  }
-  ev.ml_max = fmax(ev.ml_max, mlmax);
-  if (MODE == kPilot || lnl == -INFINITY) return -INFINITY;
-  double lnp = lnw + lnl;
-  ev.p.add(lnp);
-  return lnp;
 }
 
 template <int PREC, int G, int MODE, bool FAST>
@@ -878,6 +915,9 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   double* cold = (double*)(smem + TL::COLD_OFF);
   uint16_t* list = (uint16_t*)(smem + TL::LIST_OFF);
   int* list_n = (int*)(smem + TL::CNT_OFF);
+
+  // per row for the E1 bound: row_scale^2 / ah_scale and ln w
+  double* rowq = (double*)(smem + TL::ROWQ_OFF);
   unsigned long long* tile_lnp_max = (unsigned long long*)(smem + TL::CNT_OFF + 8);
   double rv0 = 0.0, rv1 = 1.0, rv2 = 1.0, rv3 = -1.0;
   if (tid < TM) {
@@ -1018,6 +1058,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     static_for<NS>([&](auto q) { issue(decltype(q)::value); });
     if (tid < TM) {
       rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
+      rowq[tid * 2] = rv1 * rv1 / rv2; rowq[tid * 2 + 1] = rv0;
     } else if (tid < TM + TN) {
       cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
     }
@@ -1203,6 +1244,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   static_for<R>([&](auto q) { load(set(q), decltype(q)::value); });
   if (tid < TM) {
     rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
+    rowq[tid * 2] = rv1 * rv1 / rv2; rowq[tid * 2 + 1] = rv0;
   } else if (tid < TM + TN) {
     cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
   }
@@ -1282,55 +1324,63 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     return (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
   };
   constexpr int BS = P::BS, NE = P::NE;
+  // per column of this lane for the E1 bound: col_scale^2 / bh_scale and ln w
+  double colq[P::BN], colw[P::BN];
+#pragma unroll
+  for (int bn = 0; bn < P::BN; ++bn) {
+    const int tc = wn * BS * P::BN + bn * BS + (lane & (BS - 1));
+    colq[bn] = cold[tc * 3 + 1] * cold[tc * 3 + 1] / cold[tc * 3 + 2];
+    colw[bn] = cold[tc * 3];
+  }
 
   // E1 for the pair in element r of block (bm, bn) of this lane, straight
   // from the accumulators: the certified bound on lnL^ML, bounded pairs into
-  // the dropped mass, a survivor's record into LDS (slots past BATCH are
-  // counted but not written)
-  auto e1_pair = [&](auto bmi, auto bni, auto ri) {
+  // the dropped mass; true for a survivor (no shared-memory writes, so that
+  // the elements' loads and arithmetic overlap)
+  auto e1_bound = [&](auto bmi, auto bni, auto ri) -> bool {
     constexpr int bm = decltype(bmi)::value, bn = decltype(bni)::value, r = decltype(ri)::value;
     const int tc = wn * BS * P::BN + bn * BS + (lane & (BS - 1));
     const int tr = wm * BS * P::BM + bm * BS + rowmap(r);
-    if (!(col0 + tc < a.n_ext && row0 + tr < a.n_sub)) return;
-    ++n_pairs_i;
-    bool survive = true;
-    if (use_bound) {
-      const float sx = (float)(rowd[tr * 4 + 1] * cold[tc * 3 + 1]);
-      const float sh = (float)(rowd[tr * 4 + 2] * cold[tc * 3 + 2]);
-      float U = 0.f;
+    const bool in = col0 + tc < a.n_ext && row0 + tr < a.n_sub;
+    n_pairs_i += in ? 1 : 0;
+    if (!use_bound) return in;
+    // bound = (sx^2 / sh) U0^2 / (2 lo0) from the raw accumulators:
+    // U0 = sum_g |X_g|, and hh_o >= S0 - 2 sum_d |S_d| for every phase (the
+    // margin, relative to the magnitudes involved, covers FP32 accumulation
+    // and sqrt rounding even when the difference cancels); lnL^ML_o <=
+    // U^2 / (2 lo) for every phase.  sx^2 / sh is a power of two.
+    float U0 = 0.f;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        float xr = (float)acc[g][bm][bn][0][r], xi = (float)acc[g][bm][bn][1][r];
-        U += __builtin_amdgcn_sqrtf(xr * xr + xi * xi);
-      }
-      U *= fabsf(sx);
-      // hh_o >= S0 - 2 sum_d |S_d| for every phase; the margin, relative to
-      // the magnitudes involved, covers FP32 accumulation and sqrt rounding
-      // even when the difference cancels
-      const float s0 = (float)acch[0][bm][bn][r];
-      float sabs = 0.f;
-#pragma unroll
-      for (int d = 1; d < (NRT + 1) / 2; ++d) {
-        if (d >= ND) break;
-        float sr = (float)acch[2 * d - 1][bm][bn][r], si = (float)acch[2 * d][bm][bn][r];
-        sabs += 2.f * __builtin_amdgcn_sqrtf(sr * sr + si * si);
-      }
-      float lo = ((s0 - sabs) - 2e-5f * (fabsf(s0) + sabs)) * sh;
-      // lnL^ML_o <= U^2 / (2 lo) for every phase
-      if (lo > 0.f) {
-        float bound = U * U / (2.f * lo) * 1.001f + 1e-3f;
-        if (bound < thr_f) {
-          survive = false;
-          if (MODE == kEvidence) {
-            float lw = (float)(rowd[tr * 4] + cold[tc * 3]);
-            ev.drop.add(lw + bound);
-            ev.max_bound = fmaxf(ev.max_bound, lw + bound);
-            ++n_bounded_i;
-          }
-        }
-      }
+    for (int g = 0; g < G; ++g) {
+      const float xr = (float)acc[g][bm][bn][0][r], xi = (float)acc[g][bm][bn][1][r];
+      U0 += __builtin_amdgcn_sqrtf(xr * xr + xi * xi);
     }
-    if (survive) {
+    const float s0 = (float)acch[0][bm][bn][r];
+    float sabs = 0.f;
+#pragma unroll
+    for (int d = 1; d < (NRT + 1) / 2; ++d) {   // outputs past ND are zero
+      const float sr = (float)acch[2 * d - 1][bm][bn][r], si = (float)acch[2 * d][bm][bn][r];
+      sabs += 2.f * __builtin_amdgcn_sqrtf(sr * sr + si * si);
+    }
+    const float lo0 = (s0 - sabs) - 2e-5f * (fabsf(s0) + sabs);
+    const float q = (float)(rowq[tr * 2] * colq[bn]);
+    // rcp is within an ulp; the 1.001 factor covers it
+    const float bound = q * (U0 * U0) * __builtin_amdgcn_rcpf(2.f * lo0) * 1.001f + 1e-3f;
+    const bool bounded = in && lo0 > 0.f && bound < thr_f;
+    if (MODE == kEvidence) {
+      const float lw = (float)(rowq[tr * 2 + 1] + colw[bn]);
+      ev.drop.add(bounded ? lw + bound : -INFINITY);
+      ev.max_bound = bounded ? fmaxf(ev.max_bound, lw + bound) : ev.max_bound;
+      n_bounded_i += bounded ? 1 : 0;
+    }
+    return in && !bounded;
+  };
+  // a survivor's record into LDS (slots past BATCH are counted but not written)
+  auto e1_record = [&](auto bmi, auto bni, auto ri) {
+    constexpr int bm = decltype(bmi)::value, bn = decltype(bni)::value, r = decltype(ri)::value;
+    const int tc = wn * BS * P::BN + bn * BS + (lane & (BS - 1));
+    const int tr = wm * BS * P::BM + bm * BS + rowmap(r);
+    {
       int slot = atomicAdd(list_n, 1);
       if (slot < TL::BATCH) {
         AT* rec = recs + slot * TL::REC;
@@ -1345,9 +1395,13 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       }
     }
   };
-  // E2: the survivors' full evaluation, load-balanced over the workgroup
+  // E2: the survivors' full evaluation.  The phases of one survivor are
+  // spread over a group of 32 lanes (phase o on lane o mod 32) and combined
+  // by shuffles within the group; the groups take survivors in turn.
   auto e2_list = [&](int nsurv) {
-    for (int j = tid; j < nsurv; j += NT) {
+    constexpr int NGRP = NT / 32;
+    const int grp = tid >> 5, gl = lane & 31;
+    for (int j = grp; j < nsurv; j += NGRP) {
       const int tr = list[j] >> 8, tcs = list[j] & 255;
       const int64_t ie = row0 + tr, e = col0 + tcs;
       const AT* xq = recs + j * TL::REC;
@@ -1366,9 +1420,34 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         Si[d] = sh * (double)xq[SO + 2 * d];
       }
       double lnw = rowd[tr * 4] + cold[tcs * 3];
+      Lse lse;
+      lse.init();
+      double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
-      double lnp = pair_full<MODE, G>(a, lds_cs, ie, e, X, S0, Sr, Si, lnw, thr_ml, ev, ob);
-      if (MODE == kEvidence && lnp > -INFINITY) {
+      pair_phases<MODE, G>(a, lds_cs, ie, e, X, S0, Sr, Si, lnw, thr_ml, gl, 32, ev, lse, best, ob,
+                           mlmax);
+      for (int off = 16; off > 0; off >>= 1) {
+        const double lm = __shfl_xor(lse.m, off, 32), ls = __shfl_xor(lse.s, off, 32);
+        const double ls2 = __shfl_xor(lse.s2, off, 32);
+        lse.merge(lm, ls, ls2);
+        const double bv = __shfl_xor(best, off, 32);
+        const int bo = __shfl_xor(ob, off, 32);
+        if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }
+        mlmax = fmax(mlmax, __shfl_xor(mlmax, off, 32));
+      }
+      if (gl != 0) continue;
+      const double lnl = (lse.m == -INFINITY) ? -INFINITY : lse.m + log(lse.s) - a.ln_nphi;
+      if (EVAL) {
+        const size_t t = (size_t)ie * a.n_ext + e;
+        a.lnl_out[t] = lnl;
+        if (a.ml_out) a.ml_out[t] = mlmax;
+        continue;
+      }
+      ev.ml_max = fmax(ev.ml_max, mlmax);
+      if (MODE == kPilot || lnl == -INFINITY) continue;
+      const double lnp = lnw + lnl;
+      ev.p.add(lnp);
+      if (MODE == kEvidence) {
         unsigned long long ob_bits = order_bits(lnp);
         unsigned long long prev = atomicMax(tile_lnp_max, ob_bits);
         double tmax = order_value(prev > ob_bits ? prev : ob_bits);
@@ -1392,9 +1471,22 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     // accumulators are dead.  A tile with more survivors than the record
     // area holds is left to a second launch of the batched epilogue: it is
     // listed and contributes nothing here.
+    static_assert(P::BM * P::BN * NE <= 32, "survivor mask");
+    unsigned sm = 0;
     static_for<P::BM>([&](auto bmi) {
       static_for<P::BN>([&](auto bni) {
-        static_for<NE>([&](auto ri) { e1_pair(bmi, bni, ri); });
+        static_for<NE>([&](auto ri) {
+          constexpr int k = (decltype(bmi)::value * P::BN + decltype(bni)::value) * NE + decltype(ri)::value;
+          if (e1_bound(bmi, bni, ri)) sm |= 1u << k;
+        });
+      });
+    });
+    static_for<P::BM>([&](auto bmi) {
+      static_for<P::BN>([&](auto bni) {
+        static_for<NE>([&](auto ri) {
+          constexpr int k = (decltype(bmi)::value * P::BN + decltype(bni)::value) * NE + decltype(ri)::value;
+          if (sm & (1u << k)) e1_record(bmi, bni, ri);
+        });
       });
     });
     __syncthreads();
@@ -1412,8 +1504,10 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     static_for<P::BM * P::BN * (NE / 2)>([&](auto bi) {
       constexpr int bb = decltype(bi)::value / (NE / 2), rh = decltype(bi)::value % (NE / 2);
       static_for<2>([&](auto ri) {
-        e1_pair(std::integral_constant<int, bb / P::BN>{}, std::integral_constant<int, bb % P::BN>{},
-                std::integral_constant<int, 2 * rh + decltype(ri)::value>{});
+        const auto bmi = std::integral_constant<int, bb / P::BN>{};
+        const auto bni = std::integral_constant<int, bb % P::BN>{};
+        const auto rr = std::integral_constant<int, 2 * rh + decltype(ri)::value>{};
+        if (e1_bound(bmi, bni, rr)) e1_record(bmi, bni, rr);
       });
       __syncthreads();
       e2_list(*list_n);
@@ -1436,50 +1530,64 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   const double tile_max_lnp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
   double* red = (double*)(smem + TL::RED_OFF);   // [NW][kNPart]
   {
-    Lse p = ev.p;
-    Lse d;
-    d.m = ev.drop.m == -INFINITY ? -INFINITY : (double)ev.drop.m;
-    d.s = ev.drop.s;
-    d.s2 = 0.0;
-    for (int off = 32; off > 0; off >>= 1) {
-      double pm = __shfl_xor(p.m, off), ps = __shfl_xor(p.s, off), ps2 = __shfl_xor(p.s2, off);
-      p.merge(pm, ps, ps2);
-      double dm = __shfl_xor(d.m, off), ds = __shfl_xor(d.s, off);
-      d.merge(dm, ds, 0.0);
+    // counts and maxima: wave reductions, then one lane per wave
+    auto add_i = [](int x, int y) { return x + y; };
+    const int w_np = wave_reduce(n_pairs_i, 0, add_i);
+    const int w_nb = wave_reduce(n_bounded_i, 0, add_i);
+    const int w_nm = wave_reduce(ev.n_marg, 0, add_i);
+    const double w_ml = wave_reduce(ev.ml_max, 0.0, [](double x, double y) { return fmax(x, y); });
+    const float w_mb = wave_reduce(ev.max_bound, (float)-INFINITY, [](float x, float y) { return fmaxf(x, y); });
+    // dropped mass: (m, s) pairs merged the same way
+    float dm = ev.drop.m, ds = ev.drop.s;
+    auto dmerge = [&](auto ctrl, auto rowmask) {
+      constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
+      LseF t{dm, ds};
+      t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
+      dm = t.m;
+      ds = t.s;
+    };
+    dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+    dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+    // evaluated pairs: a few lanes of the wave at most, merged in lane order
+    Lse p;
+    p.init();
+    unsigned long long pl = __ballot(ev.p.m != -INFINITY);
+    while (pl) {
+      const int src = __ffsll((long long)pl) - 1;
+      p.merge(read_lane(ev.p.m, src), read_lane(ev.p.s, src), read_lane(ev.p.s2, src));
+      pl &= pl - 1;
     }
-    double mlm = wave_max(ev.ml_max), mb = wave_max((double)ev.max_bound);
-    double nm = wave_sum(ev.n_marg), nb = wave_sum(ev.n_bounded), np_ = wave_sum(ev.n_pairs);
-    if (lane == 0) {
+    if (lane == 63) {
       double* r = red + wave * kNPart;
-      r[0] = p.m; r[1] = p.s; r[2] = p.s2; r[3] = d.m; r[4] = d.s; r[5] = mlm;
-      r[6] = nm; r[7] = nb; r[8] = mb; r[9] = tile_max_lnp; r[10] = np_; r[11] = 0.0;
+      r[0] = p.m; r[1] = p.s; r[2] = p.s2;
+      r[3] = dm == -INFINITY ? -INFINITY : (double)dm;
+      r[4] = ds; r[5] = w_ml; r[6] = (double)w_nm; r[7] = (double)w_nb; r[8] = (double)w_mb;
+      r[10] = (double)w_np;
     }
   }
   __syncthreads();
   if (tid == 0) {
     Lse p, d;
     p.init(); d.init();
-    double mlm = 0.0, mb = -INFINITY, mxp = -INFINITY, nm = 0, nb = 0, np_ = 0;
+    double mlm = 0.0, mb = -INFINITY, nm = 0, nb = 0, np_ = 0;
     for (int w = 0; w < NW; ++w) {
       const double* r = red + w * kNPart;
       p.merge(r[0], r[1], r[2]);
       d.merge(r[3], r[4], 0.0);
       mlm = fmax(mlm, r[5]);
-      nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); mxp = fmax(mxp, r[9]); np_ += r[10];
+      nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); np_ += r[10];
     }
+    const double mxp = tile_max_lnp;
     double* out = a.partials + wg * kNPart;
     out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
     out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
-    // running maxima: read first, update only when this tile raises them
-    // (same-address atomics from every tile would serialise in L2)
-    const unsigned long long mb_bits = (unsigned long long)__double_as_longlong(mlm);
-    if (mb_bits > __atomic_load_n((unsigned long long*)&a.state[0], __ATOMIC_RELAXED))
-      atomicMax((unsigned long long*)&a.state[0], mb_bits);
-    if (mxp > -INFINITY) {
-      const unsigned long long pb = (unsigned long long)order_bits(mxp);
-      if (pb > __atomic_load_n((unsigned long long*)&a.state[1], __ATOMIC_RELAXED))
-        atomicMax((unsigned long long*)&a.state[1], pb);
-    }
+    // running maxima (the results are not waited for)
+    if (mlm > 0.0) atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
+    if (mxp > -INFINITY) atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(mxp));
   }
 }
 
