@@ -661,8 +661,8 @@ struct Tile {
   static constexpr int BATCH = 128 * NW;
   static constexpr int EPI_BYTES = BATCH * REC * ACC_T_BYTES;
   // LDS stage buffers: FP64 stages chunks j..j+2 through registers; the
-  // split precisions load chunks j..j+3 straight into LDS
-  static constexpr int NSB = (PREC == kFP64) ? 3 : 4;
+  // split precisions load chunks straight into LDS, up to NS - 1 ahead
+  static constexpr int NSB = (PREC == kFP64) ? 3 : 8;
   static constexpr int UNION_BYTES = (NSB * STAGE_BYTES > EPI_BYTES) ? NSB * STAGE_BYTES : EPI_BYTES;
   static constexpr int ROWD_OFF = (UNION_BYTES + 15) / 16 * 16;    // double [TM][4]
   static constexpr int COLD_OFF = ROWD_OFF + TM * 4 * 8;           // double [TN][3]
@@ -986,22 +986,33 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       }
     }
     const int ndh = a.n_chunks;        // (d|h) chunks (a multiple of 4)
-    // chunk c into buffer c mod NS: a (d|h) chunk for c < ndh, else (h|h)
-    // block c - ndh
-    auto issue = [&](int c) {
-      const bool hh = c >= ndh;
-      const int64_t od = (int64_t)c * 1024 * ES, oh = (int64_t)(c - ndh) * 1024 * ES;
-      unsigned char* buf = smem + (c & (NS - 1)) * TL::STAGE_BYTES + wave * 4096;
+    const int nch = ndh + NHB;         // then the (h|h) blocks
+    // next chunk to load: per-thread source of each of its loads, and the
+    // wave's LDS destination base (wave-uniform); chunk c goes to buffer
+    // c mod NS.  The loads of chunk c follow those of c - 1, so the sources
+    // advance by one chunk (2 KB) at a time and switch to the (h|h) operands
+    // after the last (d|h) chunk.
+    gbyte* gp[LPC];
 #pragma unroll
-      for (int q = 0; q < LPC; ++q) {
-        gbyte* pq = hh ? srch[q] + oh : srcp[q] + od;
-        // issued as asm so that the compiler does not treat it as a pending
-        // LDS store that every later LDS read must wait for; the pipeline's
-        // own vmcnt waits order it (the load has no register result)
-        const unsigned lds = (unsigned)(uintptr_t)(lvoid*)(buf + q * 1024);
-        __asm__ __volatile__("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
-                             :: "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(pq) : "memory", "m0");
-      }
+    for (int q = 0; q < LPC; ++q) gp[q] = (ndh == 0) ? srch[q] : srcp[q];
+    const unsigned lds_wave =
+        __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lvoid*)(smem + wave * 4096));
+    // load q of chunk c (issued as asm so that the compiler does not treat
+    // it as a pending LDS store that every later LDS read must wait for; the
+    // pipeline's own vmcnt waits order it: the load has no register result)
+    auto issue_q = [&](int c, int q) {
+      const unsigned m0v = lds_wave + (unsigned)((c & (NS - 1)) * TL::STAGE_BYTES + q * 1024);
+      __asm__ __volatile__("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                           :: "s"(__builtin_amdgcn_readfirstlane(m0v)), "v"(gp[q]) : "memory", "m0");
+    };
+    auto advance = [&](int c) {       // after chunk c has been issued
+#pragma unroll
+      for (int q = 0; q < LPC; ++q) gp[q] = (c + 1 == ndh) ? srch[q] : gp[q] + 1024 * ES;
+    };
+    auto issue = [&](int c) {
+#pragma unroll
+      for (int q = 0; q < LPC; ++q) issue_q(c, q);
+      advance(c);
     };
     // fragments of one chunk: A hi/lo and B_re hi/lo of both slices
     struct Frag {
@@ -1012,50 +1023,97 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       if constexpr (decltype(fi)::value % 2 == 0) return fr0;
       else return fr1;
     };
-    auto read_frag = [&](Frag& f, int c) {
+    // fragment read k (0..7) of chunk c
+    auto read_k = [&](Frag& f, int c, int k) {
       const unsigned char* buf = smem + (c & (NS - 1)) * TL::STAGE_BYTES + lane * 16;
-#pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        f.ah[sl] = *(const uint4*)(buf + 0 * 4096 + (2 * wm + sl) * 1024);
-        f.al[sl] = *(const uint4*)(buf + 1 * 4096 + (2 * wm + sl) * 1024);
-        f.bh[sl] = *(const uint4*)(buf + 2 * 4096 + (2 * wn + sl) * 1024);
-        f.bl[sl] = *(const uint4*)(buf + 3 * 4096 + (2 * wn + sl) * 1024);
+      const int sl = k & 1;
+      switch (k >> 1) {
+        case 0: f.ah[sl] = *(const uint4*)(buf + 0 * 4096 + (2 * wm + sl) * 1024); break;
+        case 1: f.al[sl] = *(const uint4*)(buf + 1 * 4096 + (2 * wm + sl) * 1024); break;
+        case 2: f.bh[sl] = *(const uint4*)(buf + 2 * 4096 + (2 * wn + sl) * 1024); break;
+        default: f.bl[sl] = *(const uint4*)(buf + 3 * 4096 + (2 * wn + sl) * 1024); break;
       }
     };
-    // (d|h) chunk: with A = [hr | hi] and B_re = [Br | -Bi] by slice,
-    // re += A B_re and im += A B_im, B_im = [Bi | Br] = [-(B_re slice 1) |
-    // B_re slice 0]; 3 split products per real product, the smaller ones
-    // first, re and im alternating
-    auto compute_dh = [&](const Frag& f, auto gi) {
-      constexpr int g = decltype(gi)::value;
-      const uint4 nbh = make_uint4(f.bh[1].x ^ 0x80008000u, f.bh[1].y ^ 0x80008000u,
-                                   f.bh[1].z ^ 0x80008000u, f.bh[1].w ^ 0x80008000u);
-      const uint4 nbl = make_uint4(f.bl[1].x ^ 0x80008000u, f.bl[1].y ^ 0x80008000u,
-                                   f.bl[1].z ^ 0x80008000u, f.bl[1].w ^ 0x80008000u);
+    auto read_frag = [&](Frag& f, int c) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) read_k(f, c, k);
+    };
+    // The matrix products of one chunk in issue order.  (d|h): with A =
+    // [hr | hi] and B_re = [Br | -Bi] by slice, re += A B_re and im += A B_im,
+    // B_im = [Bi | Br] = [-(B_re slice 1) | B_re slice 0]; 3 split products
+    // per real product, the smaller ones first, re and im alternating.
+    // (h|h) block r: the real product of the row and column (h|h) operands.
+    auto mfma_dh = [&](const Frag& f, const uint4& nbh, const uint4& nbl, int g, int k) {
       Acc& re = acc[g][0][0][0];
       Acc& im = acc[g][0][0][1];
-      mma<PREC>(re, f.al[0], f.bh[0]); mma<PREC>(im, f.al[0], nbh);
-      mma<PREC>(re, f.ah[0], f.bl[0]); mma<PREC>(im, f.ah[0], nbl);
-      mma<PREC>(re, f.ah[0], f.bh[0]); mma<PREC>(im, f.ah[0], nbh);
-      mma<PREC>(re, f.al[1], f.bh[1]); mma<PREC>(im, f.al[1], f.bh[0]);
-      mma<PREC>(re, f.ah[1], f.bl[1]); mma<PREC>(im, f.ah[1], f.bl[0]);
-      mma<PREC>(re, f.ah[1], f.bh[1]); mma<PREC>(im, f.ah[1], f.bh[0]);
-    };
-    // (h|h) block r: real product of the row and column (h|h) operands
-    auto compute_hh = [&](const Frag& f, auto ri) {
-      constexpr int r = decltype(ri)::value;
-      if constexpr (r < NRT) {
-        Acc& h = acch[r][0][0];
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-          mma<PREC>(h, f.al[sl], f.bh[sl]);
-          mma<PREC>(h, f.ah[sl], f.bl[sl]);
-          mma<PREC>(h, f.ah[sl], f.bh[sl]);
-        }
+      switch (k) {
+        case 0: mma<PREC>(re, f.al[0], f.bh[0]); break;
+        case 1: mma<PREC>(im, f.al[0], nbh); break;
+        case 2: mma<PREC>(re, f.ah[0], f.bl[0]); break;
+        case 3: mma<PREC>(im, f.ah[0], nbl); break;
+        case 4: mma<PREC>(re, f.ah[0], f.bh[0]); break;
+        case 5: mma<PREC>(im, f.ah[0], nbh); break;
+        case 6: mma<PREC>(re, f.al[1], f.bh[1]); break;
+        case 7: mma<PREC>(im, f.al[1], f.bh[0]); break;
+        case 8: mma<PREC>(re, f.ah[1], f.bl[1]); break;
+        case 9: mma<PREC>(im, f.ah[1], f.bl[0]); break;
+        case 10: mma<PREC>(re, f.ah[1], f.bh[1]); break;
+        default: mma<PREC>(im, f.ah[1], f.bh[0]); break;
       }
     };
-    // prologue: chunks 0..NS-1 in flight, wait for 0 and 1
-    static_for<NS>([&](auto q) { issue(decltype(q)::value); });
+    auto mfma_hh = [&](const Frag& f, int r, int k) {
+      Acc& h = acch[r][0][0];
+      const int sl = k / 3;
+      switch (k % 3) {
+        case 0: mma<PREC>(h, f.al[sl], f.bh[sl]); break;
+        case 1: mma<PREC>(h, f.ah[sl], f.bl[sl]); break;
+        default: mma<PREC>(h, f.ah[sl], f.bh[sl]); break;
+      }
+    };
+    // Pipeline: NS buffers; the loads of chunk c are issued at step c + 1 -
+    // NS (the first NS - 1 chunks before step 0), into the buffer of chunk
+    // c - NS, whose fragments were read at step c - NS - 1 (before the last
+    // barrier).  Step j multiplies chunk j and reads the fragments of chunk
+    // j + 1 between its products (one wave per SIMD issues everything, so
+    // LDS reads and loads go where a product is running).  A barrier after
+    // every second step (j odd) makes chunks up to j + 3 visible to all
+    // waves and frees the buffers read so far.
+    auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
+    // FL: 1 read ahead, 2 issue, 4 barrier after; W: loads allowed in flight
+    // at that barrier; NMF: products; O: the wave's load slot offset
+    auto step = [&](int j, auto slot, auto fl, auto w, auto nmf, auto off, auto&& mfma_k) {
+      constexpr int sl = decltype(slot)::value;
+      constexpr int FL = decltype(fl)::value;
+      constexpr int NMF = decltype(nmf)::value;
+      constexpr int O = decltype(off)::value;
+      Frag& cur = frag(slot);
+      Frag& nxt = frag(std::integral_constant<int, sl + 1>{});
+      const int ci = j - 1 + NS;      // chunk issued in this step
+      // slot t (0 .. max(NMF, 8) - 1): product t, then read t, then (every
+      // third slot from O) a load
+      constexpr int NSLOT = NMF > 8 ? NMF : 8;
+      static_for<NSLOT>([&](auto ti) {
+        constexpr int t = decltype(ti)::value;
+        if constexpr (t < NMF) mfma_k(cur, t);
+        if constexpr ((FL & 1) && t < 8) read_k(nxt, j + 1, t);
+        if constexpr ((FL & 2) && t % 3 == O && t / 3 < LPC) {
+          fence();
+          issue_q(ci, t / 3);
+          fence();
+        }
+      });
+      if constexpr (FL & 2) {
+        // loads not placed between products
+        static_for<LPC>([&](auto qi) {
+          constexpr int q = decltype(qi)::value;
+          if constexpr (3 * q + O >= NSLOT) issue_q(ci, q);
+        });
+        advance(ci);
+      }
+      if constexpr (FL & 4) pipeline_barrier<decltype(w)::value>();
+    };
+    // prologue: chunks 0 .. NS-2 in flight; wait for 0, 1, 2; read chunk 0
+    static_for<NS - 1>([&](auto q) { issue(decltype(q)::value); });
     if (tid < TM) {
       rowd[tid * 4] = rv0; rowd[tid * 4 + 1] = rv1; rowd[tid * 4 + 2] = rv2; rowd[tid * 4 + 3] = rv3;
       rowq[tid * 2] = rv1 * rv1 / rv2; rowq[tid * 2 + 1] = rv0;
@@ -1064,57 +1122,47 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     }
     if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
     __syncthreads();                              // rowd, cold, counters
-    pipeline_barrier<LPC * (NS - 2)>();           // chunks 0 and 1 have landed
+    pipeline_barrier<LPC * (NS - 4)>();           // chunks 0, 1, 2 have landed
     read_frag(fr0, 0);
-    pipeline_barrier<LPC * (NS - 2)>();           // step 0 refills buffer 0: chunk 0 read everywhere
-    // step j: read the fragments of chunk j+1, multiply chunk j, refill the
-    // buffer of chunk j (its fragments were read before the last barrier)
-    // with chunk j+NS, wait until chunk j+2 has landed, barrier.  FL: 1 read
-    // the next fragments, 2 issue chunk j+NS; W: loads allowed in flight.
-    // One wave per SIMD issues everything: the LDS reads go between the
-    // matrix products so that they issue while a product runs.
-    auto step = [&](int j, auto slot, auto fl, auto w, auto nmf, auto&& compute_fn) {
-      constexpr int sl = decltype(slot)::value;
-      constexpr int FL = decltype(fl)::value;
-      constexpr int NMF = decltype(nmf)::value;
-      if constexpr (FL & 1) read_frag(frag(std::integral_constant<int, sl + 1>{}), j + 1);
-      compute_fn(frag(slot));
-      if constexpr (FL & 2) issue(j + NS);
-      constexpr int NRD = (FL & 1) ? 8 : 0;
-      static_for<NMF>([&](auto k) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        if constexpr (decltype(k)::value < NRD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      });
-      pipeline_barrier<decltype(w)::value>();
-    };
+    pipeline_barrier<LPC * (NS - 4)>();           // chunk 0 read everywhere (step 1 refills it)
     // every group spans a multiple of 4 chunks (bins padded to 64), so the
-    // fragment set of each step is static; with at least NS (h|h) blocks
-    // after them every (d|h) step reads ahead, issues chunk j+NS and keeps
-    // chunks j+3..j+NS in flight
-    static_assert(NHB >= NS, "pipeline needs NS trailing blocks");
+    // fragment set and the barrier of each step are static; with at least
+    // NS (h|h) blocks after them every (d|h) step reads ahead and issues
+    static_assert(NHB >= NS && NS >= 4, "pipeline needs NS trailing blocks");
     int ch = 0;
     static_for<G>([&](auto gi) {
       constexpr int g = decltype(gi)::value;
       const int gend = a.mt.gk0[g + 1];
-      for (; ch < gend; ch += 4) {
-        static_for<4>([&](auto slot) {
-          step(ch + decltype(slot)::value, slot, std::integral_constant<int, 3>{},
-               std::integral_constant<int, LPC * (NS - 2)>{}, std::integral_constant<int, 12>{},
-               [&](const Frag& f) { compute_dh(f, gi); });
-        });
-      }
+      auto run = [&](auto off) {
+        for (; ch < gend; ch += 4) {
+          // B_im slice 0 is minus B_re slice 1: the sign flips are formed per step
+          static_for<4>([&](auto slot) {
+            constexpr int s4 = decltype(slot)::value;
+            const Frag& f = frag(slot);
+            const uint4 nbh = make_uint4(f.bh[1].x ^ 0x80008000u, f.bh[1].y ^ 0x80008000u,
+                                         f.bh[1].z ^ 0x80008000u, f.bh[1].w ^ 0x80008000u);
+            const uint4 nbl = make_uint4(f.bl[1].x ^ 0x80008000u, f.bl[1].y ^ 0x80008000u,
+                                         f.bl[1].z ^ 0x80008000u, f.bl[1].w ^ 0x80008000u);
+            step(ch + s4, slot, std::integral_constant<int, 3 | (s4 & 1 ? 4 : 0)>{},
+                 std::integral_constant<int, LPC * (NS - 4)>{}, std::integral_constant<int, 12>{},
+                 off, [&](const Frag& fc, int k) { mfma_dh(fc, nbh, nbl, g, k); });
+          });
+        }
+      };
+      run(std::integral_constant<int, 2>{});
     });
 #pragma unroll
     for (int r = 0; r < NRT; ++r) acch[r][0][0] = Acc{};
     static_for<NHB>([&](auto ri) {
       constexpr int r = decltype(ri)::value;
-      constexpr int fl = (r + 1 < NHB ? 1 : 0) | (r + NS < NHB ? 2 : 0);
-      // in flight after this step's issue: blocks r+3 .. min(r+NS, NHB-1)
-      constexpr int last = (r + NS < NHB - 1) ? r + NS : NHB - 1;
-      constexpr int wc = LPC * (last > r + 2 ? last - r - 2 : 0);
+      // reads ahead while a block follows; issues while one is left to load;
+      // barrier after odd steps (ndh is even) with blocks r+4 .. last in flight
+      constexpr int fl = (r + 1 < NHB ? 1 : 0) | (r + NS - 1 < NHB ? 2 : 0) | (r % 2 ? 4 : 0);
+      constexpr int last = (r + NS - 1 < NHB - 1) ? r + NS - 1 : NHB - 1;
+      constexpr int wc = LPC * (last > r + 3 ? last - r - 3 : 0);
       step(ndh + r, std::integral_constant<int, r % 4>{}, std::integral_constant<int, fl>{},
            std::integral_constant<int, wc>{}, std::integral_constant<int, (r < NRT ? 6 : 0)>{},
-           [&](const Frag& f) { compute_hh(f, ri); });
+           std::integral_constant<int, 2>{}, [&](const Frag& fc, int k) { mfma_hh(fc, r, k); });
     });
   } else {
   // per-thread source addresses of its 16-byte pieces for chunk 0 of the
