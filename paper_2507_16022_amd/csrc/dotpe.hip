@@ -303,7 +303,7 @@ void launch_hh(dotpe_event* ev, const double* w) {
 template <int PREC, int G, int MODE, bool FAST>
 int launch_fused_t(const FusedArgs& a, int64_t grid, hipStream_t s) {
   typedef Tile<PREC> TL;
-  size_t sh = TL::MAIN_BYTES + sizeof(double) * kMaxM * a.n_phi * 2;
+  size_t sh = TL::CS_OFF + sizeof(double) * kMaxM * a.n_phi * 2;
   // allow more than 64 KiB of dynamic LDS (once per kernel; not every
   // runtime needs or supports the attribute, so a failure is not an error)
   static std::once_flag attr_once;

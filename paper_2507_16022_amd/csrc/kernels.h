@@ -671,6 +671,9 @@ struct Tile {
   static constexpr int CNT_OFF = RED_OFF + NW * kNPart * 8;        // int counter, u64 max
   static constexpr int ROWQ_OFF = CNT_OFF + 16;                    // double [TM][2]
   static constexpr int MAIN_BYTES = ROWQ_OFF + TM * 2 * 8;
+  // then the distance-rule parameters and the phase table
+  static constexpr int DP_OFF = (MAIN_BYTES + 15) / 16 * 16;
+  static constexpr int CS_OFF = DP_OFF + ((int)sizeof(DistParams) + 15) / 16 * 16;
   static constexpr int PIECE_ELEMS = 16 / (int)sizeof(typename P::T);   // 16-byte pieces
   static constexpr int PIECES_PER_ROW = 32 / PIECE_ELEMS;
   static constexpr int PIECES = (P::NA * TM + P::NB * TN) * PIECES_PER_ROW;
@@ -812,7 +815,8 @@ struct EvAcc {
 // lnL^ML to mlmax; cut phases' upper bounds go to ev.drop.  The caller
 // combines the parts of one pair.
 template <int MODE, int G>
-__device__ void pair_phases(const FusedArgs& a, const double* lds_cs, int64_t ie, int64_t e,
+__device__ void pair_phases(const FusedArgs& a, const double* lds_cs, const DistParams& dp,
+                            int64_t ie, int64_t e,
                             const double2 (&X)[G], double S0, const double (&Sr)[kMaxND],
                             const double (&Si)[kMaxND], double lnw, double thr_ml, int o0, int os,
                             EvAcc& ev, Lse& lse, double& best, int& o_best, double& mlmax) {
@@ -851,7 +855,7 @@ __device__ void pair_phases(const FusedArgs& a, const double* lds_cs, int64_t ie
       ev.drop.add(x + fabsf(x) * 1e-6f + 1e-5f);   // rounding margin keeps it a bound
       continue;
     }
-    double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, a.dist.prm->geom, a.dist.prm->ghx, a.dist.prm->ghw);
+    double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, dp.geom, dp.ghx, dp.ghw);
     if (v > best) { best = v; o_best = o; }
     lse.add(v);
     if (!EVAL) ev.n_marg += 1;
@@ -874,7 +878,8 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   constexpr int TM = TL::TM, TN = TL::TN, PITCH = P::PITCH, NT = TL::NT, NW = TL::NW;
   extern __shared__ __align__(16) unsigned char smem[];
   T* stage = (T*)smem;
-  double* lds_cs = (double*)(smem + TL::MAIN_BYTES);
+  double* lds_cs = (double*)(smem + TL::CS_OFF);
+  DistParams* lds_dp = (DistParams*)(smem + TL::DP_OFF);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / P::WN, wn = wave % P::WN;
@@ -906,8 +911,12 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   }
   const int64_t row0 = tm * TM, col0 = tn * TN;
 
-  // phase table to LDS
+  // phase table and distance-rule parameters to LDS (the rule's segment
+  // search and nodes are read per triple)
   for (int t = tid; t < kMaxM * a.n_phi * 2; t += NT) lds_cs[t] = a.phase_cs[t];
+  static_assert(sizeof(DistParams) % 4 == 0, "DistParams words");
+  for (int t = tid; t < (int)(sizeof(DistParams) / 4); t += NT)
+    ((unsigned*)lds_dp)[t] = ((const unsigned*)a.dist.prm)[t];
 
   // per-row / per-column scalars: issued first, stored after the first
   // chunk's loads are in flight
@@ -1472,8 +1481,8 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       lse.init();
       double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
-      pair_phases<MODE, G>(a, lds_cs, ie, e, X, S0, Sr, Si, lnw, thr_ml, gl, 32, ev, lse, best, ob,
-                           mlmax);
+      pair_phases<MODE, G>(a, lds_cs, *lds_dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, gl, 32, ev, lse,
+                           best, ob, mlmax);
       for (int off = 16; off > 0; off >>= 1) {
         const double lm = __shfl_xor(lse.m, off, 32), ls = __shfl_xor(lse.s, off, 32);
         const double ls2 = __shfl_xor(lse.s2, off, 32);
@@ -1575,7 +1584,6 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   ev.n_bounded = (double)n_bounded_i;
 
   // ---- tile reduction ----
-  const double tile_max_lnp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
   double* red = (double*)(smem + TL::RED_OFF);   // [NW][kNPart]
   {
     // counts and maxima: wave reductions, then one lane per wave
@@ -1629,7 +1637,8 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       mlm = fmax(mlm, r[5]);
       nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); np_ += r[10];
     }
-    const double mxp = tile_max_lnp;
+    // every wave's E2 has finished (barrier above): the tile maximum is final
+    const double mxp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
     double* out = a.partials + wg * kNPart;
     out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
     out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
