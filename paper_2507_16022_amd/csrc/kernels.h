@@ -479,7 +479,7 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
                                 int n_det, const double* __restrict__ w, ModeTables mt,
                                 const int* __restrict__ terms, int KH, void* __restrict__ H0,
                                 void* __restrict__ H1, double* __restrict__ hscale) {
-  extern __shared__ double2 rowbuf[];   // [n_c][n_bp] when it fits
+  extern __shared__ double2 rowbuf[];   // [n_c][n_bp] then w [n_det][n_b], when they fit
   __shared__ double2 Hs[kMaxDet * kMaxNP];
   __shared__ double vals[256];
   __shared__ double red[64];
@@ -487,10 +487,12 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   if (ie >= n_sub) return;
   const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
   const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
-  const bool staged = (size_t)mt.n_c * n_bp * sizeof(double2) <= 65536;
+  const bool staged = (size_t)mt.n_c * n_bp * sizeof(double2) + (size_t)n_det * n_b * sizeof(double) <= 65536;
+  double* wl = (double*)(rowbuf + mt.n_c * n_bp);
   if (staged) {
     for (int t = threadIdx.x; t < mt.n_c * n_bp; t += blockDim.x)
       rowbuf[t] = bank_value<PREC>(A0, A1, i, K2, t / n_bp, t % n_bp, n_bp);
+    for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[t] = w[t];
     __syncthreads();
   }
   double sc = row_scale ? row_scale[i] : 1.0;
@@ -499,13 +501,35 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
     int k = t / mt.NP, p = t % mt.NP;
     int c = mt.pc[p], c2 = mt.pc2[p];
     double2 acc = make_double2(0.0, 0.0);
-    for (int b = 0; b < n_b; ++b) {
-      double2 a = staged ? rowbuf[c * n_bp + b] : bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
-      double2 a2 = staged ? rowbuf[c2 * n_bp + b] : bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
-      double2 v = cmul(cconj(a), a2);      // h_c conj(h_c') = conj(A_c) A_c'
-      double ww = w[k * n_b + b];
-      acc.x += ww * v.x;
-      acc.y += ww * v.y;
+    if (staged) {
+      // two partial sums, so that consecutive bins do not wait on each other
+      double2 acc2 = make_double2(0.0, 0.0);
+      int b = 0;
+      for (; b + 1 < n_b; b += 2) {
+        const double2 v0 = cmul(cconj(rowbuf[c * n_bp + b]), rowbuf[c2 * n_bp + b]);
+        const double2 v1 = cmul(cconj(rowbuf[c * n_bp + b + 1]), rowbuf[c2 * n_bp + b + 1]);
+        const double w0 = wl[k * n_b + b], w1 = wl[k * n_b + b + 1];
+        acc.x += w0 * v0.x;
+        acc.y += w0 * v0.y;
+        acc2.x += w1 * v1.x;
+        acc2.y += w1 * v1.y;
+      }
+      if (b < n_b) {
+        const double2 v0 = cmul(cconj(rowbuf[c * n_bp + b]), rowbuf[c2 * n_bp + b]);
+        acc.x += wl[k * n_b + b] * v0.x;
+        acc.y += wl[k * n_b + b] * v0.y;
+      }
+      acc.x += acc2.x;
+      acc.y += acc2.y;
+    } else {
+      for (int b = 0; b < n_b; ++b) {
+        double2 a = bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
+        double2 a2 = bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
+        double2 v = cmul(cconj(a), a2);      // h_c conj(h_c') = conj(A_c) A_c'
+        double ww = w[k * n_b + b];
+        acc.x += ww * v.x;
+        acc.y += ww * v.y;
+      }
     }
     Hs[k * mt.NP + p] = make_double2(acc.x * sc, acc.y * sc);
   }
@@ -885,7 +909,9 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   const int wm = wave / P::WN, wn = wave % P::WN;
 
   // workgroup -> tile: spread consecutive ids over the XCDs so that each XCD
-  // walks a contiguous band of tiles, then raster in groups of 8 tile rows
+  // walks a contiguous band of tiles, then raster in bands of 4 tile rows
+  // (the ~32 tiles an XCD runs at once then share 4 row blocks and 8 column
+  // blocks of operands in its L2)
   int64_t wg = blockIdx.x;
   if (a.rerun_list) {
     wg = a.rerun_list[blockIdx.x];        // a tile listed by a fast pass
@@ -902,7 +928,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     tn = wg % a.n_tiles_n;
   } else {
     if (wg >= a.n_tiles) return;
-    const int64_t GM = 1;
+    const int64_t GM = 4;
     int64_t band = wg / (GM * a.n_tiles_n);
     int64_t rows_in_band = min(GM, a.n_tiles_m - band * GM);
     int64_t in = wg - band * GM * a.n_tiles_n;

@@ -190,6 +190,9 @@ def test_evidence_cut_is_certified(ctx, prec):
     assert n > 0
     assert np.array_equal(np.stack([r["topk_i"][:n], r["topk_e"][:n]], -1), ref["topk_idx"][:n])
     assert np.allclose(r["topk_lnp"][:n], ref["topk_lnp"][:n], atol=tol)
+    # the reported maximum is the best pair's, whichever wave evaluated it
+    assert r["max_ln_p"] == pytest.approx(float(np.max(ref["lnp"])), abs=tol)
+    assert r["max_ln_p"] == r["topk_lnp"][0]
 
 
 def test_subset_rows_and_norm(ctx):
