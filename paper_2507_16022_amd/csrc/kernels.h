@@ -1420,13 +1420,18 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   // from the accumulators: the certified bound on lnL^ML, bounded pairs into
   // the dropped mass; true for a survivor (no shared-memory writes, so that
   // the elements' loads and arithmetic overlap)
-  auto e1_bound = [&](auto bmi, auto bni, auto ri) -> bool {
+  // rows and columns of the tile inside the subset and the sample set
+  const int rows_in = (int)min((int64_t)TM, a.n_sub - row0);
+  const int cols_in = (int)min((int64_t)TN, a.n_ext - col0);
+  // UB: use_bound, known at compile time where the caller knows it
+  auto e1_bound = [&](auto bmi, auto bni, auto ri, auto ub) -> bool {
     constexpr int bm = decltype(bmi)::value, bn = decltype(bni)::value, r = decltype(ri)::value;
+    constexpr bool UB = decltype(ub)::value;
     const int tc = wn * BS * P::BN + bn * BS + (lane & (BS - 1));
     const int tr = wm * BS * P::BM + bm * BS + rowmap(r);
-    const bool in = col0 + tc < a.n_ext && row0 + tr < a.n_sub;
+    const bool in = tc < cols_in && tr < rows_in;
     n_pairs_i += in ? 1 : 0;
-    if (!use_bound) return in;
+    if constexpr (!UB) return in;
     // bound = (sx^2 / sh) U0^2 / (2 lo0) from the raw accumulators:
     // U0 = sum_g |X_g|, and hh_o >= S0 - 2 sum_d |S_d| for every phase (the
     // margin, relative to the magnitudes involved, covers FP32 accumulation
@@ -1560,7 +1565,8 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       static_for<P::BN>([&](auto bni) {
         static_for<NE>([&](auto ri) {
           constexpr int k = (decltype(bmi)::value * P::BN + decltype(bni)::value) * NE + decltype(ri)::value;
-          if (e1_bound(bmi, bni, ri)) sm |= 1u << k;
+          // the fast pass always cuts (threshold frozen above zero)
+          if (e1_bound(bmi, bni, ri, std::true_type{})) sm |= 1u << k;
         });
       });
     });
@@ -1590,7 +1596,9 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         const auto bmi = std::integral_constant<int, bb / P::BN>{};
         const auto bni = std::integral_constant<int, bb % P::BN>{};
         const auto rr = std::integral_constant<int, 2 * rh + decltype(ri)::value>{};
-        if (e1_bound(bmi, bni, rr)) e1_record(bmi, bni, rr);
+        const bool surv = use_bound ? e1_bound(bmi, bni, rr, std::true_type{})
+                                    : e1_bound(bmi, bni, rr, std::false_type{});
+        if (surv) e1_record(bmi, bni, rr);
       });
       __syncthreads();
       e2_list(*list_n);
