@@ -490,8 +490,34 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   const bool staged = (size_t)mt.n_c * n_bp * sizeof(double2) + (size_t)n_det * n_b * sizeof(double) <= 65536;
   double* wl = (double*)(rowbuf + mt.n_c * n_bp);
   if (staged) {
-    for (int t = threadIdx.x; t < mt.n_c * n_bp; t += blockDim.x)
-      rowbuf[t] = bank_value<PREC>(A0, A1, i, K2, t / n_bp, t % n_bp, n_bp);
+    // the row in pieces of 8 consecutive positions (16 bytes per operand
+    // array in the split layouts): 8 bins of the real or the imaginary part
+    for (int pc = threadIdx.x; pc < (int)(K2 / 8); pc += blockDim.x) {
+      const int64_t o = op_index<PREC>(i, (int64_t)pc * 8, K2);
+      double v[8];
+      if (PREC == kFP64) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = ((const double*)A0)[o + j];
+      } else {
+        const uint4 hq = *(const uint4*)((const uint16_t*)A0 + o);
+        const uint4 lq = *(const uint4*)((const uint16_t*)A1 + o);
+        const unsigned hw[4] = {hq.x, hq.y, hq.z, hq.w}, lw[4] = {lq.x, lq.y, lq.z, lq.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint16_t hb = (uint16_t)(hw[j >> 1] >> (16 * (j & 1)));
+          const uint16_t lb = (uint16_t)(lw[j >> 1] >> (16 * (j & 1)));
+          if (PREC == kFP16X2)
+            v[j] = (double)__builtin_bit_cast(_Float16, hb) + (double)__builtin_bit_cast(_Float16, lb);
+          else
+            v[j] = (double)(float)__builtin_bit_cast(__bf16, hb) + (double)(float)__builtin_bit_cast(__bf16, lb);
+        }
+      }
+      const int kk = pc * 8, chunk = kk >> 5, within = kk & 31;
+      const int c = chunk / (n_bp / kChunk), b0 = (chunk % (n_bp / kChunk)) * kChunk + (within & 15);
+      double* dst = (double*)(rowbuf + c * n_bp + b0) + (within >= 16 ? 1 : 0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) dst[2 * j] = v[j];
+    }
     for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[t] = w[t];
     __syncthreads();
   }
