@@ -718,7 +718,7 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
 std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) {
   std::vector<EvBuf> v;
   const size_t esz = D.prec == kFP64 ? 8 : 2;
-  // FP64: B_re, B_im; split precisions: B_re hi, lo (B_im is formed in registers)
+  // FP64: B_re, B_im; split precisions: B_re hi, lo (B_im is the other slice of B_re)
   for (int q = 0; q < 2; ++q) v.push_back({&ev->B[q], (size_t)D.ne_p * D.K2 * esz, false});
   if (D.prec != kFP64) v.push_back({(void**)&ev->col_scale, (size_t)D.ne * 8, false});
   v.push_back({(void**)&ev->hh_terms, (size_t)D.KH * sizeof(int), false});

@@ -731,12 +731,6 @@ struct Tile {
   static_assert(PIECES % NT == 0, "pieces must split evenly over the threads");
 };
 
-// physical 16-byte piece of logical piece p in row r of a split-precision
-// stage buffer (rows of 64 bytes): p ^ lds_swz(r mod 16).  Within any 16
-// consecutive rows read at one logical piece (a fragment read) the pieces
-// fall on distinct bank groups for 32 and for 64 LDS banks.
-__device__ __forceinline__ int lds_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
-
 // wait until at most N vector-memory operations of this wave are in flight
 // (expcnt and lgkmcnt left unconstrained)
 // s_waitcnt immediate: vmcnt N (6 bits, split over [3:0] and [15:14]),
