@@ -704,11 +704,14 @@ struct Tile {
   static constexpr int STAGE_ELEMS = (P::NA * TM + P::NB * TN) * P::PITCH;
   static constexpr int STAGE_BYTES = STAGE_ELEMS * (int)sizeof(typename P::T);
   static constexpr int ACC_T_BYTES = (PREC == kFP64) ? 8 : 4;
-  // epilogue batches: each lane offers 2 of its pairs at a time, so a batch
-  // holds at most 128 pairs per wave; survivors' records (X_g re/im, the
-  // (h|h) outputs) have an odd stride to spread LDS banks
-  static constexpr int REC = 2 * kMaxG + kMaxNR + 2;   // 17
-  static constexpr int BATCH = 128 * NW;
+  // epilogue batches: each lane offers EPB of its pairs at a time (split
+  // precisions: half of them, so that half of the accumulators are free
+  // while the first half is evaluated), a batch holding at most EPB per
+  // lane; survivors' records (X_g re/im, the (h|h) outputs) have an odd
+  // stride to spread LDS banks
+  static constexpr int REC = 2 * kMaxG + kMaxNR;       // 15
+  static constexpr int EPB = (PREC == kFP64) ? 2 : P::BM * P::BN * P::NE / 2;
+  static constexpr int BATCH = EPB * NT;
   static constexpr int EPI_BYTES = BATCH * REC * ACC_T_BYTES;
   // LDS stage buffers: FP64 stages chunks j..j+2 through registers; the
   // split precisions load chunks straight into LDS, up to NS - 1 ahead
@@ -1609,13 +1612,16 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     }
     e2_list(nsurv);
   } else {
-    // batches of 2 pairs per lane (at most BATCH survivors each)
-    static_for<P::BM * P::BN * (NE / 2)>([&](auto bi) {
-      constexpr int bb = decltype(bi)::value / (NE / 2), rh = decltype(bi)::value % (NE / 2);
-      static_for<2>([&](auto ri) {
-        const auto bmi = std::integral_constant<int, bb / P::BN>{};
-        const auto bni = std::integral_constant<int, bb % P::BN>{};
-        const auto rr = std::integral_constant<int, 2 * rh + decltype(ri)::value>{};
+    // batches of EPB pairs per lane (at most BATCH survivors each)
+    constexpr int EPB = TL::EPB;
+    static_assert(NE % EPB == 0 || EPB % NE == 0, "batch split");
+    static_for<P::BM * P::BN * NE / EPB>([&](auto bi) {
+      static_for<EPB>([&](auto ri) {
+        // element k of this lane in (block, element) order
+        constexpr int k = decltype(bi)::value * EPB + decltype(ri)::value;
+        const auto bmi = std::integral_constant<int, k / NE / P::BN>{};
+        const auto bni = std::integral_constant<int, k / NE % P::BN>{};
+        const auto rr = std::integral_constant<int, k % NE>{};
         const bool surv = use_bound ? e1_bound(bmi, bni, rr, std::true_type{})
                                     : e1_bound(bmi, bni, rr, std::false_type{});
         if (surv) e1_record(bmi, bni, rr);
