@@ -1506,12 +1506,14 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       }
     }
   };
-  // E2: the survivors' full evaluation.  The phases of one survivor are
-  // spread over a group of 32 lanes (phase o on lane o mod 32) and combined
-  // by shuffles within the group; the groups take survivors in turn.
-  auto e2_list = [&](int nsurv) {
-    constexpr int NGRP = NT / 32;
-    const int grp = tid >> 5, gl = lane & 31;
+  // E2: the survivors' full evaluation.  With few survivors the phases of
+  // one survivor are spread over a group of 32 lanes (phase o on lane o mod
+  // 32) and combined by shuffles within the group, the groups taking
+  // survivors in turn; with many, each lane takes whole survivors.
+  auto e2_run = [&](int nsurv, auto lps) {
+    constexpr int LPS = decltype(lps)::value;      // lanes per survivor
+    constexpr int NGRP = NT / LPS;
+    const int grp = tid / LPS, gl = tid % LPS;
     for (int j = grp; j < nsurv; j += NGRP) {
       const int tr = list[j] >> 8, tcs = list[j] & 255;
       const int64_t ie = row0 + tr, e = col0 + tcs;
@@ -1535,16 +1537,17 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       lse.init();
       double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
-      pair_phases<MODE, G>(a, lds_cs, *lds_dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, gl, 32, ev, lse,
+      pair_phases<MODE, G>(a, lds_cs, *lds_dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, gl, LPS, ev, lse,
                            best, ob, mlmax);
-      for (int off = 16; off > 0; off >>= 1) {
-        const double lm = __shfl_xor(lse.m, off, 32), ls = __shfl_xor(lse.s, off, 32);
-        const double ls2 = __shfl_xor(lse.s2, off, 32);
+#pragma unroll
+      for (int off = LPS / 2; off > 0; off >>= 1) {
+        const double lm = __shfl_xor(lse.m, off, LPS), ls = __shfl_xor(lse.s, off, LPS);
+        const double ls2 = __shfl_xor(lse.s2, off, LPS);
         lse.merge(lm, ls, ls2);
-        const double bv = __shfl_xor(best, off, 32);
-        const int bo = __shfl_xor(ob, off, 32);
+        const double bv = __shfl_xor(best, off, LPS);
+        const int bo = __shfl_xor(ob, off, LPS);
         if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }
-        mlmax = fmax(mlmax, __shfl_xor(mlmax, off, 32));
+        mlmax = fmax(mlmax, __shfl_xor(mlmax, off, LPS));
       }
       if (gl != 0) continue;
       const double lnl = (lse.m == -INFINITY) ? -INFINITY : lse.m + log(lse.s) - a.ln_nphi;
@@ -1575,6 +1578,10 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         }
       }
     }
+  };
+  auto e2_list = [&](int nsurv) {
+    if (nsurv >= NT / 2) e2_run(nsurv, std::integral_constant<int, 1>{});
+    else e2_run(nsurv, std::integral_constant<int, 32>{});
   };
 
   if constexpr (FAST) {
