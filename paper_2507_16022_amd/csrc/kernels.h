@@ -467,6 +467,9 @@ __device__ __forceinline__ double term_value(int code, const double2* X, int NP,
   return x;
 }
 
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+
 // per-waveform (h|h) sums H_ikcc' = sum_b w_kb h_icb conj(h_ic'b) for the
 // event's bank subset, from the same operand values the contraction uses,
 // written as the row-side (h|h) operand (n_sub rows of KH, op_index layout)
@@ -479,7 +482,11 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
                                 int n_det, const double* __restrict__ w, ModeTables mt,
                                 const int* __restrict__ terms, int KH, void* __restrict__ H0,
                                 void* __restrict__ H1, double* __restrict__ hscale) {
-  extern __shared__ double2 rowbuf[];   // [n_c][n_bp] then w [n_det][n_b], when they fit
+  // the row [n_c][n_bp] then w [n_det][n_b], when they fit.  A split value
+  // hi + lo spans at most 23 significant bits, so float holds it exactly.
+  typedef typename std::conditional<PREC == kFP64, double2, float2>::type RB;
+  extern __shared__ __align__(16) unsigned char hh_smem[];
+  RB* rowbuf = (RB*)hh_smem;
   __shared__ double2 Hs[kMaxDet * kMaxNP];
   __shared__ double vals[256];
   __shared__ double red[64];
@@ -487,7 +494,7 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   if (ie >= n_sub) return;
   const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
   const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
-  const bool staged = (size_t)mt.n_c * n_bp * sizeof(double2) + (size_t)n_det * n_b * sizeof(double) <= 65536;
+  const bool staged = (size_t)mt.n_c * n_bp * sizeof(RB) + (size_t)n_det * n_b * sizeof(double) <= 65536;
   double* wl = (double*)(rowbuf + mt.n_c * n_bp);
   if (staged) {
     // the row in pieces of 8 consecutive positions (16 bytes per operand
@@ -514,9 +521,10 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
       }
       const int kk = pc * 8, chunk = kk >> 5, within = kk & 31;
       const int c = chunk / (n_bp / kChunk), b0 = (chunk % (n_bp / kChunk)) * kChunk + (within & 15);
-      double* dst = (double*)(rowbuf + c * n_bp + b0) + (within >= 16 ? 1 : 0);
+      typedef typename std::conditional<PREC == kFP64, double, float>::type RV;
+      RV* dst = (RV*)(rowbuf + c * n_bp + b0) + (within >= 16 ? 1 : 0);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) dst[2 * j] = v[j];
+      for (int j = 0; j < 8; ++j) dst[2 * j] = (RV)v[j];
     }
     for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[t] = w[t];
     __syncthreads();
@@ -532,8 +540,8 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
       double2 acc2 = make_double2(0.0, 0.0);
       int b = 0;
       for (; b + 1 < n_b; b += 2) {
-        const double2 v0 = cmul(cconj(rowbuf[c * n_bp + b]), rowbuf[c2 * n_bp + b]);
-        const double2 v1 = cmul(cconj(rowbuf[c * n_bp + b + 1]), rowbuf[c2 * n_bp + b + 1]);
+        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * n_bp + b])), to_d2(rowbuf[c2 * n_bp + b]));
+        const double2 v1 = cmul(cconj(to_d2(rowbuf[c * n_bp + b + 1])), to_d2(rowbuf[c2 * n_bp + b + 1]));
         const double w0 = wl[k * n_b + b], w1 = wl[k * n_b + b + 1];
         acc.x += w0 * v0.x;
         acc.y += w0 * v0.y;
@@ -541,7 +549,7 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
         acc2.y += w1 * v1.y;
       }
       if (b < n_b) {
-        const double2 v0 = cmul(cconj(rowbuf[c * n_bp + b]), rowbuf[c2 * n_bp + b]);
+        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * n_bp + b])), to_d2(rowbuf[c2 * n_bp + b]));
         acc.x += wl[k * n_b + b] * v0.x;
         acc.y += wl[k * n_b + b] * v0.y;
       }
