@@ -1051,8 +1051,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         srch[q] = (gbyte*)(wave == 2 ? a.Bh0 : a.Bh1) + (blk(e, a.KH) + in_chunk) * ES;
       }
     }
-    const int ndh = a.n_chunks;        // (d|h) chunks (a multiple of 4)
-    const int nch = ndh + NHB;         // then the (h|h) blocks
+    const int ndh = a.n_chunks;        // (d|h) chunks (a multiple of 4), then NHB (h|h) blocks
     // next chunk to load: per-thread source of each of its loads, and the
     // wave's LDS destination base (wave-uniform); chunk c goes to buffer
     // c mod NS.  The loads of chunk c follow those of c - 1, so the sources
@@ -1065,11 +1064,18 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lvoid*)(smem + wave * 4096));
     // load q of chunk c (issued as asm so that the compiler does not treat
     // it as a pending LDS store that every later LDS read must wait for; the
-    // pipeline's own vmcnt waits order it: the load has no register result)
+    // pipeline's own vmcnt waits order it: the load has no register result).
+    // M0 carries the LDS destination: the asm saves and restores it, and
+    // waits the one state an M0 write needs before the load reads it.
     auto issue_q = [&](int c, int q) {
       const unsigned m0v = lds_wave + (unsigned)((c & (NS - 1)) * TL::STAGE_BYTES + q * 1024);
-      __asm__ __volatile__("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
-                           :: "s"(__builtin_amdgcn_readfirstlane(m0v)), "v"(gp[q]) : "memory", "m0");
+      unsigned m0_saved;
+      __asm__ __volatile__(
+          "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+          "global_load_lds_dwordx4 %2, off\n\ts_mov_b32 m0, %0"
+          : "=&s"(m0_saved)
+          : "s"(__builtin_amdgcn_readfirstlane(m0v)), "v"(gp[q])
+          : "memory");
     };
     auto advance = [&](int c) {       // after chunk c has been issued
 #pragma unroll
@@ -1426,7 +1432,6 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   if (MODE == kPilot) thr_ml = __longlong_as_double(a.state[0]);
   const bool use_bound = MODE != kEval && thr_ml > 0.0;
   const float thr_f = (float)thr_ml;
-  const int ND = a.mt.ND;
   EvAcc ev;
   ev.init();
   int n_pairs_i = 0, n_bounded_i = 0;
