@@ -1062,28 +1062,36 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     for (int q = 0; q < LPC; ++q) gp[q] = (ndh == 0) ? srch[q] : srcp[q];
     const unsigned lds_wave =
         __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lvoid*)(smem + wave * 4096));
-    // load q of chunk c (issued as asm so that the compiler does not treat
-    // it as a pending LDS store that every later LDS read must wait for; the
-    // pipeline's own vmcnt waits order it: the load has no register result).
-    // M0 carries the LDS destination: the asm saves and restores it, and
-    // waits the one state an M0 write needs before the load reads it.
-    auto issue_q = [&](int c, int q) {
-      const unsigned m0v = lds_wave + (unsigned)((c & (NS - 1)) * TL::STAGE_BYTES + q * 1024);
-      unsigned m0_saved;
-      __asm__ __volatile__(
-          "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
-          "global_load_lds_dwordx4 %2, off\n\ts_mov_b32 m0, %0"
-          : "=&s"(m0_saved)
-          : "s"(__builtin_amdgcn_readfirstlane(m0v)), "v"(gp[q])
-          : "memory");
-    };
     auto advance = [&](int c) {       // after chunk c has been issued
 #pragma unroll
       for (int q = 0; q < LPC; ++q) gp[q] = (c + 1 == ndh) ? srch[q] : gp[q] + 1024 * ES;
     };
+    // the loads of chunk c, issued as asm so that the compiler does not treat
+    // them as pending LDS stores that every later LDS read must wait for; the
+    // pipeline's own vmcnt waits order them (they have no register result).
+    // M0 carries the LDS destination and the immediate offset applies to both
+    // addresses, so one M0 write serves the 4 loads; the asm saves and
+    // restores M0 (the compiler keeps lane indices in it elsewhere) and waits
+    // the one state an M0 write needs before a load reads it.
+    auto issue4 = [&](int c) {
+      const unsigned m0v = lds_wave + (unsigned)((c & (NS - 1)) * TL::STAGE_BYTES);
+      gbyte* p0 = gp[0];
+      gbyte* p1 = gp[1] - 1024;
+      gbyte* p2 = gp[2] - 2048;
+      gbyte* p3 = gp[3] - 3072;
+      unsigned m0_saved;
+      __asm__ __volatile__(
+          "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+          "global_load_lds_dwordx4 %2, off\n\t"
+          "global_load_lds_dwordx4 %3, off offset:1024\n\t"
+          "global_load_lds_dwordx4 %4, off offset:2048\n\t"
+          "global_load_lds_dwordx4 %5, off offset:3072\n\ts_mov_b32 m0, %0"
+          : "=&s"(m0_saved)
+          : "s"(__builtin_amdgcn_readfirstlane(m0v)), "v"(p0), "v"(p1), "v"(p2), "v"(p3)
+          : "memory");
+    };
     auto issue = [&](int c) {
-#pragma unroll
-      for (int q = 0; q < LPC; ++q) issue_q(c, q);
+      issue4(c);
       advance(c);
     };
     // fragments of one chunk: A hi/lo and B_re hi/lo of both slices
@@ -1152,7 +1160,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     // waves and frees the buffers read so far.
     auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
     // FL: 1 read ahead, 2 issue, 4 barrier after; W: loads allowed in flight
-    // at that barrier; NMF: products; O: the wave's load slot offset
+    // at that barrier; NMF: products; O: the slot after which the loads go
     auto step = [&](int j, auto slot, auto fl, auto w, auto nmf, auto off, auto&& mfma_k) {
       constexpr int sl = decltype(slot)::value;
       constexpr int FL = decltype(fl)::value;
@@ -1161,27 +1169,20 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
       Frag& cur = frag(slot);
       Frag& nxt = frag(std::integral_constant<int, sl + 1>{});
       const int ci = j - 1 + NS;      // chunk issued in this step
-      // slot t (0 .. max(NMF, 8) - 1): product t, then read t, then (every
-      // third slot from O) a load
+      // slot t (0 .. max(NMF, 8) - 1): product t, then read t; the chunk's
+      // loads go after slot O
       constexpr int NSLOT = NMF > 8 ? NMF : 8;
       static_for<NSLOT>([&](auto ti) {
         constexpr int t = decltype(ti)::value;
         if constexpr (t < NMF) mfma_k(cur, t);
         if constexpr ((FL & 1) && t < 8) read_k(nxt, j + 1, t);
-        if constexpr ((FL & 2) && t % 3 == O && t / 3 < LPC) {
+        if constexpr ((FL & 2) && t == O) {   // the chunk's loads after product O
           fence();
-          issue_q(ci, t / 3);
+          issue4(ci);
           fence();
         }
       });
-      if constexpr (FL & 2) {
-        // loads not placed between products
-        static_for<LPC>([&](auto qi) {
-          constexpr int q = decltype(qi)::value;
-          if constexpr (3 * q + O >= NSLOT) issue_q(ci, q);
-        });
-        advance(ci);
-      }
+      if constexpr (FL & 2) advance(ci);
       if constexpr (FL & 4) pipeline_barrier<decltype(w)::value>();
     };
     // prologue: chunks 0 .. NS-2 in flight; wait for 0, 1, 2; read chunk 0
