@@ -1,27 +1,61 @@
-"""Build the HIP library libdotpe.so in-tree for gfx950 (hipcc, no JIT)."""
+"""Build the HIP library libdotpe.so in-tree for gfx950 (hipcc, no JIT).
+
+The host runtime (csrc/dotpe.hip) and one instantiation unit of the fused
+kernel per (precision, number of m groups) (csrc/fused_inst.hip) are compiled
+to objects in parallel, then linked into one shared library.
+"""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libdotpe.so")
-SRC = os.path.join(HERE, "csrc", "dotpe.hip")
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(os.path.dirname(HERE), "_build", "dotpe")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
 
+PRECISIONS = (0, 1, 2)     # FP64, FP16x2, BF16x2
+GROUPS = (1, 2, 3, 4)      # distinct m values
 
-def build(verbose=False):
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-o", tmp, SRC]
+
+def units():
+    """(source, object, extra flags) of every translation unit."""
+    out = [(os.path.join(CSRC, "dotpe.hip"), os.path.join(OBJ, "dotpe.o"), [])]
+    for p in PRECISIONS:
+        for g in GROUPS:
+            out.append((os.path.join(CSRC, "fused_inst.hip"), os.path.join(OBJ, f"fused_p{p}_g{g}.o"),
+                        [f"-DDOTPE_INST_PREC={p}", f"-DDOTPE_INST_G={g}"]))
+    return out
+
+
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libdotpe.so")
-    if verbose:
-        sys.stderr.write(r.stderr)
+    return r.returncode, r.stdout + r.stderr
+
+
+def build(verbose=False, jobs=None):
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(16, max(1, len(os.sched_getaffinity(0))))
+    cmds = [[HIPCC] + FLAGS + extra + ["-c", "-o", obj, src] for src, obj, extra in units()]
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    for cmd, (rc, log) in zip(cmds, results):
+        if rc != 0:
+            sys.stderr.write(" ".join(cmd) + "\n" + log)
+            raise RuntimeError("hipcc failed compiling " + cmd[-1])
+        if verbose and log.strip():
+            sys.stderr.write(log)
+    tmp = LIB + ".tmp"
+    rc, log = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp]
+                   + [obj for _, obj, _ in units()])
+    if rc != 0:
+        sys.stderr.write(log)
+        raise RuntimeError("hipcc failed linking libdotpe.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,154 @@
+// Shared definitions of the device code of the likelihood-matrix hot path
+// (gfx950, wave64, MFMA): types, constants, mode tables, small helpers and
+// the split-operand layout.  Included by every translation unit with kernels.
+//
+// Notation: i bank row (subset index ie), e extrinsic sample, k detector,
+// c mode channel (channels reordered so that equal m are contiguous; g the
+// group of channels sharing m), b frequency bin, o phase grid index.
+//
+// (d|h) for a triple (eq. dh_ieo) is rearranged as
+//     dh_ieo = Re sum_g exp(i m_g phi_o) X_ieg,
+//     X_ieg  = sum_{c in g} sum_b conj(h_icb) B_cb(e),
+//     B_cb(e) = sum_k w_kb d_kb conj(R_ekc) exp(+2 pi i f_b t_ek),
+// i.e. a complex GEMM over K = (c, b) with the detector sum folded into the
+// extrinsic operand; (h|h) (eq. hh_ieo) as
+//     hh_ieo = S0 + 2 Re sum_{delta > 0} S_delta exp(-i delta phi_o),
+//     S_delta = sum_k sum_{c,c': m_c - m_c' = delta} H_ikcc' Q_ekcc',
+//     H_ikcc' = sum_b w_kb h_icb conj(h_ic'b),  Q_ekcc' = R_ekc conj(R_ekc').
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "dist_rule.h"
+
+namespace dotpe {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMaxC = 8;        // channels
+constexpr int kMaxG = 4;        // distinct m
+constexpr int kMaxDet = 8;
+constexpr int kMaxPhi = 128;
+constexpr int kMaxNP = kMaxC * (kMaxC + 1) / 2;
+constexpr int kMaxND = 4;       // delta = 0..3
+constexpr int kMaxM = 4;
+constexpr int kChunk = 16;      // bins per K chunk (32 real K)
+constexpr int kNPart = 12;      // doubles per tile partial
+
+enum Prec { kFP64 = 0, kFP16X2 = 1, kBF16X2 = 2 };
+
+struct ModeTables {
+  int n_c, G, ND, NP;
+  int l[kMaxC], m[kMaxC];          // per channel (group order)
+  int orig[kMaxC];                 // input channel index of each
+  int gm[kMaxG];                   // m of each group
+  int gk0[kMaxG + 1];              // chunk index where each group starts
+  // channel pairs (c, c') with c <= c', sorted by |m_c - m_c'|: pairs with
+  // |delta| = d occupy [pstart[d], pstart[d + 1])
+  int pc[kMaxNP], pc2[kMaxNP], pdel[kMaxNP];   // m_c - m_c' (signed)
+  int pstart[kMaxND + 1];
+  float pf[kMaxNP];                // delta = 0: 1 (c = c') or 2 (c != c')
+  float ps[kMaxNP];                // sign of the imaginary part (conjugate when delta < 0)
+  int pdiag[kMaxC];                // pair index of (c, c)
+};
+
+// distance-rule parameters, kept in device memory next to the table (passed
+// by pointer so that no kernel argument has to be copied to private memory)
+struct DistParams {
+  DistTableGeom geom;
+  double ghx[kGH], ghw[kGH];
+};
+struct DistArgs {
+  const double* tab;
+  const DistParams* prm;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for_impl(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for_impl<I + 1, N>(f);
+  }
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<0, N>(f);
+}
+
+
+// online log-sum-exp accumulator (also of 2x)
+struct Lse {
+  double m, s, s2;
+  __device__ void init() { m = -INFINITY; s = 0.0; s2 = 0.0; }
+  __device__ void add(double x) {
+    if (x == -INFINITY) return;
+    if (x > m) {
+      double f = exp(m - x);
+      s = s * f + 1.0;
+      s2 = s2 * f * f + 1.0;
+      m = x;
+    } else {
+      double f = exp(x - m);
+      s += f;
+      s2 += f * f;
+    }
+  }
+  __device__ void merge(double mb, double sb, double s2b) {
+    if (mb == -INFINITY) return;
+    if (m == -INFINITY) { m = mb; s = sb; s2 = s2b; return; }
+    double mm = fmax(m, mb);
+    double fa = exp(m - mm), fb = exp(mb - mm);
+    s = s * fa + sb * fb;
+    s2 = s2 * fa * fa + s2b * fb * fb;
+    m = mm;
+  }
+};
+
+__device__ __forceinline__ uint64_t order_bits(double x) {
+  uint64_t u = __double_as_longlong(x);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_value(uint64_t u) {
+  u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+  return __longlong_as_double(u);
+}
+// value of lane src (wave-uniform) of a double
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, src);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// made of 2 slices (positions 16 s .. 16 s + 15) of 1 KB, and in a slice the
+// 8 positions of piece h (8 h .. 8 h + 7) of row r sit at elements
+// 8 (32 h + r) .. +7.  One 32-row slice is then exactly the 1 KB that a
+// 32x32x16 matrix-core operand read takes (lane 32 h + r holds row r, piece
+// h), so loads and LDS reads are contiguous.
+template <int PREC>
+__host__ __device__ __forceinline__ int64_t op_index(int64_t i, int64_t k, int64_t K) {
+  if (PREC == kFP64) return i * K + k;
+  return ((i >> 5) * (K >> 5) + (k >> 5)) * 1024 + ((k >> 4) & 1) * 512 + ((k >> 3) & 1) * 256 +
+         (i & 31) * 8 + (k & 7);
+}
+
+
+constexpr int kMaxNR = 2 * kMaxND - 1;   // (h|h) phase-coefficient outputs
+
+}  // namespace dotpe

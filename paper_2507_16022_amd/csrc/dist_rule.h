@@ -111,7 +111,7 @@ __host__ __device__ __forceinline__ double dr_panel(double lo, double hi, double
 }
 
 // ln Lbar(z, s), robust and accurate to ~1e-13 relative.
-__host__ __device__ __attribute__((noinline)) double dr_ln_exact(double z, double s) {
+__host__ __device__ inline __attribute__((noinline)) double dr_ln_exact(double z, double s) {
   if (!(s > 0.0)) return 0.0;
   const double a = z * s, b = s * s;
   double gx[16], gw[16];

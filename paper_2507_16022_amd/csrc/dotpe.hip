@@ -17,7 +17,8 @@
 #include <vector>
 
 #include "../../include/dotpe.h"
-#include "kernels.h"
+#include "launch.h"
+#include "prep.h"
 #include "serving.h"
 
 using namespace dotpe;
@@ -303,44 +304,16 @@ void launch_hh(dotpe_event* ev, const double* w) {
                      ev->Bh[0], ev->Bh[1], ev->bh_scale);
 }
 
-template <int PREC, int G, int MODE, bool FAST>
-int launch_fused_t(const FusedArgs& a, int64_t grid, hipStream_t s) {
-  typedef Tile<PREC> TL;
-  size_t sh = TL::CS_OFF + sizeof(double) * kMaxM * a.n_phi * 2;
-  // allow more than 64 KiB of dynamic LDS (once per kernel; not every
-  // runtime needs or supports the attribute, so a failure is not an error)
-  static std::once_flag attr_once;
-  std::call_once(attr_once, [sh] {
-    if (hipFuncSetAttribute((const void*)k_lnl_fused<PREC, G, MODE, FAST>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh + 16384) != hipSuccess)
-      (void)hipGetLastError();
-  });
-  hipLaunchKernelGGL((k_lnl_fused<PREC, G, MODE, FAST>), dim3((unsigned)grid), dim3(TL::NT), sh, s, a);
-  HIP_OK(hipGetLastError());
-  return DOTPE_OK;
-}
-
-template <int PREC, int MODE, bool FAST>
-int launch_fused_g(const FusedArgs& a, int64_t grid, hipStream_t s) {
-  switch (a.mt.G) {
-    case 1: return launch_fused_t<PREC, 1, MODE, FAST>(a, grid, s);
-    case 2: return launch_fused_t<PREC, 2, MODE, FAST>(a, grid, s);
-    case 3: return launch_fused_t<PREC, 3, MODE, FAST>(a, grid, s);
-    case 4: return launch_fused_t<PREC, 4, MODE, FAST>(a, grid, s);
-  }
-  return fail(DOTPE_E_INVALID_ARG, "bad group count %d", a.mt.G);
-}
-
 // FAST (evidence pass only): every pair through the bound first, one full
 // evaluation pass after, tiles with too many survivors listed for a rerun
 template <int MODE, bool FAST = false>
 int launch_fused(int prec, const FusedArgs& a, int64_t grid, hipStream_t s) {
-  switch (prec) {
-    case kFP64: return launch_fused_g<kFP64, MODE, FAST>(a, grid, s);
-    case kFP16X2: return launch_fused_g<kFP16X2, MODE, FAST>(a, grid, s);
-    case kBF16X2: return launch_fused_g<kBF16X2, MODE, FAST>(a, grid, s);
-  }
-  return fail(DOTPE_E_INVALID_ARG, "bad precision %d", prec);
+  FusedLaunchFn fn = fused_launcher(prec, a.mt.G);
+  if (!fn) return fail(DOTPE_E_INVALID_ARG, "bad precision %d or group count %d", prec, a.mt.G);
+  hipError_t e = fn(MODE, FAST, a, grid, s);
+  if (e != hipSuccess)
+    return fail(DOTPE_E_DEVICE, "fused kernel launch: %s", hipGetErrorString(e));
+  return DOTPE_OK;
 }
 
 void tile_shape(int prec, int* tm, int* tn) {
@@ -454,7 +427,7 @@ int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
   ctx->budget = hbm_budget_bytes;
   ctx->own_bytes = ctx->bytes;
   if (rc) {
-    hipStreamDestroy(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return rc;
   }

@@ -1,621 +1,12 @@
-// Device kernels of the likelihood-matrix hot path (gfx950, wave64, MFMA).
-//
-// Notation: i bank row (subset index ie), e extrinsic sample, k detector,
-// c mode channel (channels reordered so that equal m are contiguous; g the
-// group of channels sharing m), b frequency bin, o phase grid index.
-//
-// (d|h) for a triple (eq. dh_ieo) is rearranged as
-//     dh_ieo = Re sum_g exp(i m_g phi_o) X_ieg,
-//     X_ieg  = sum_{c in g} sum_b conj(h_icb) B_cb(e),
-//     B_cb(e) = sum_k w_kb d_kb conj(R_ekc) exp(+2 pi i f_b t_ek),
-// i.e. a complex GEMM over K = (c, b) with the detector sum folded into the
-// extrinsic operand; (h|h) (eq. hh_ieo) as
-//     hh_ieo = S0 + 2 Re sum_{delta > 0} S_delta exp(-i delta phi_o),
-//     S_delta = sum_k sum_{c,c': m_c - m_c' = delta} H_ikcc' Q_ekcc',
-//     H_ikcc' = sum_b w_kb h_icb conj(h_ic'b),  Q_ekcc' = R_ekc conj(R_ekc').
+// The fused likelihood kernel: complex MFMA contraction of (d|h) and the
+// (h|h) phase coefficients, then the per-pair marginalisation epilogue.
+// Included by the host runtime (argument and tile shapes) and by the
+// translation units that instantiate the kernel.
 #pragma once
 
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include <type_traits>
-
-#include "dist_rule.h"
+#include "common.h"
 
 namespace dotpe {
-
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-constexpr int kMaxC = 8;        // channels
-constexpr int kMaxG = 4;        // distinct m
-constexpr int kMaxDet = 8;
-constexpr int kMaxPhi = 128;
-constexpr int kMaxNP = kMaxC * (kMaxC + 1) / 2;
-constexpr int kMaxND = 4;       // delta = 0..3
-constexpr int kMaxM = 4;
-constexpr int kChunk = 16;      // bins per K chunk (32 real K)
-constexpr int kNPart = 12;      // doubles per tile partial
-
-enum Prec { kFP64 = 0, kFP16X2 = 1, kBF16X2 = 2 };
-
-struct ModeTables {
-  int n_c, G, ND, NP;
-  int l[kMaxC], m[kMaxC];          // per channel (group order)
-  int orig[kMaxC];                 // input channel index of each
-  int gm[kMaxG];                   // m of each group
-  int gk0[kMaxG + 1];              // chunk index where each group starts
-  // channel pairs (c, c') with c <= c', sorted by |m_c - m_c'|: pairs with
-  // |delta| = d occupy [pstart[d], pstart[d + 1])
-  int pc[kMaxNP], pc2[kMaxNP], pdel[kMaxNP];   // m_c - m_c' (signed)
-  int pstart[kMaxND + 1];
-  float pf[kMaxNP];                // delta = 0: 1 (c = c') or 2 (c != c')
-  float ps[kMaxNP];                // sign of the imaginary part (conjugate when delta < 0)
-  int pdiag[kMaxC];                // pair index of (c, c)
-};
-
-// distance-rule parameters, kept in device memory next to the table (passed
-// by pointer so that no kernel argument has to be copied to private memory)
-struct DistParams {
-  DistTableGeom geom;
-  double ghx[kGH], ghw[kGH];
-};
-struct DistArgs {
-  const double* tab;
-  const DistParams* prm;
-};
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-
-// compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for_impl(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for_impl<I + 1, N>(f);
-  }
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl<0, N>(f);
-}
-
-
-// online log-sum-exp accumulator (also of 2x)
-struct Lse {
-  double m, s, s2;
-  __device__ void init() { m = -INFINITY; s = 0.0; s2 = 0.0; }
-  __device__ void add(double x) {
-    if (x == -INFINITY) return;
-    if (x > m) {
-      double f = exp(m - x);
-      s = s * f + 1.0;
-      s2 = s2 * f * f + 1.0;
-      m = x;
-    } else {
-      double f = exp(x - m);
-      s += f;
-      s2 += f * f;
-    }
-  }
-  __device__ void merge(double mb, double sb, double s2b) {
-    if (mb == -INFINITY) return;
-    if (m == -INFINITY) { m = mb; s = sb; s2 = s2b; return; }
-    double mm = fmax(m, mb);
-    double fa = exp(m - mm), fb = exp(mb - mm);
-    s = s * fa + sb * fb;
-    s2 = s2 * fa * fa + s2b * fb * fb;
-    m = mm;
-  }
-};
-
-__device__ __forceinline__ uint64_t order_bits(double x) {
-  uint64_t u = __double_as_longlong(x);
-  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double order_value(uint64_t u) {
-  u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
-  return __longlong_as_double(u);
-}
-// value of lane src (wave-uniform) of a double
-__device__ __forceinline__ double read_lane(double v, int src) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, src);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), src);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// ---------------------------------------------------------------------------
-// distance-marginalisation table
-// ---------------------------------------------------------------------------
-__global__ void k_build_dist_table(double* tab, DistTableGeom g) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)g.ncol * g.nt) return;
-  int col = (int)(idx % g.ncol), jt = (int)(idx / g.ncol);
-  double z = dr_col_z(g, col), t = g.t0 + jt * g.ht;
-  tab[idx] = dr_ln_exact(z, dr_s_of_tau(t));
-}
-
-__global__ void k_debug_distmarg(int64_t n, const double* dh, const double* hh, double r0,
-                                 DistArgs da, double* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  out[i] = dr_ln_marg(dh[i], hh[i], r0, da.tab, da.prm->geom, da.prm->ghx, da.prm->ghw);
-}
-
-// Element offset of (row i, position k) in an operand with K positions per
-// row (K a multiple of 32).  FP64: row-major.  Split precisions: fragment
-// order -- 32-row blocks; within a block each chunk of 32 positions is 2 KB
-// made of 2 slices (positions 16 s .. 16 s + 15) of 1 KB, and in a slice the
-// 8 positions of piece h (8 h .. 8 h + 7) of row r sit at elements
-// 8 (32 h + r) .. +7.  One 32-row slice is then exactly the 1 KB that a
-// 32x32x16 matrix-core operand read takes (lane 32 h + r holds row r, piece
-// h), so loads and LDS reads are contiguous.
-template <int PREC>
-__host__ __device__ __forceinline__ int64_t op_index(int64_t i, int64_t k, int64_t K) {
-  if (PREC == kFP64) return i * K + k;
-  return ((i >> 5) * (K >> 5) + (k >> 5)) * 1024 + ((k >> 4) & 1) * 512 + ((k >> 3) & 1) * 256 +
-         (i & 31) * 8 + (k & 7);
-}
-
-// ---------------------------------------------------------------------------
-// bank-summary layout: FP64 amplitudes -> MFMA operand rows
-// row layout (K2 = n_c * n_bp * 2 per row): for channel c (group order) and
-// chunk j of 16 bins, 32 consecutive values: Re A (16 bins) then Im A,
-// A = conj(h) (scaled by 2^-e_i in the split precisions).
-// ---------------------------------------------------------------------------
-template <int PREC>
-__global__ void k_bank_convert(const double* __restrict__ h, int64_t n_wf, int n_c_in, int n_b,
-                               int n_bp, ModeTables mt, void* __restrict__ A0,
-                               void* __restrict__ A1, double* __restrict__ row_scale,
-                               int* __restrict__ err) {
-  const int64_t row = blockIdx.x;
-  if (row >= n_wf) return;
-  const double* hr = h + (size_t)row * n_c_in * n_b * 2;
-  __shared__ double red[256];
-  double mx = 0.0;
-  bool bad = false;
-  for (int t = threadIdx.x; t < n_c_in * n_b; t += blockDim.x) {
-    double re = hr[2 * t], im = hr[2 * t + 1];
-    if (!isfinite(re) || !isfinite(im)) bad = true;
-    mx = fmax(mx, fmax(fabs(re), fabs(im)));
-  }
-  if (bad) atomicOr(err, 1);
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  mx = red[0];
-  int ex = 0;
-  if (PREC != kFP64 && mx > 0.0 && isfinite(mx)) ex = ilogb(mx) - 13;   // max in [2^13, 2^14)
-  if (threadIdx.x == 0 && row_scale) row_scale[row] = ldexp(1.0, ex);
-  const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
-  for (int t = threadIdx.x; t < mt.n_c * n_bp; t += blockDim.x) {
-    int c = t / n_bp, b = t % n_bp;
-    double re = 0.0, im = 0.0;
-    if (b < n_b) {
-      const double* src = hr + ((size_t)mt.orig[c] * n_b + b) * 2;
-      re = ldexp(src[0], -ex);
-      im = -ldexp(src[1], -ex);                 // conj(h)
-    }
-    const int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
-    const int64_t o = op_index<PREC>(row, base, K2), o16 = op_index<PREC>(row, base + 16, K2);
-    if (PREC == kFP64) {
-      double* A = (double*)A0;
-      A[o] = re;
-      A[o16] = im;
-    } else if (PREC == kFP16X2) {
-      _Float16* Ah = (_Float16*)A0;
-      _Float16* Al = (_Float16*)A1;
-      _Float16 hr_ = (_Float16)re, hi_ = (_Float16)im;
-      Ah[o] = hr_; Ah[o16] = hi_;
-      Al[o] = (_Float16)(re - (double)hr_); Al[o16] = (_Float16)(im - (double)hi_);
-    } else {
-      __bf16* Ah = (__bf16*)A0;
-      __bf16* Al = (__bf16*)A1;
-      __bf16 hr_ = (__bf16)(float)re, hi_ = (__bf16)(float)im;
-      Ah[o] = hr_; Ah[o16] = hi_;
-      Al[o] = (__bf16)(float)(re - (double)(float)hr_);
-      Al[o16] = (__bf16)(float)(im - (double)(float)hi_);
-    }
-  }
-}
-
-// reconstructed conj(h) value (A) of row i, channel c (group order), bin b
-template <int PREC>
-__device__ __forceinline__ double2 bank_value(const void* A0, const void* A1, int64_t i, int64_t K2,
-                                              int c, int b, int n_bp) {
-  const int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
-  const int64_t o = op_index<PREC>(i, base, K2), o16 = op_index<PREC>(i, base + 16, K2);
-  if (PREC == kFP64) {
-    const double* A = (const double*)A0;
-    return make_double2(A[o], A[o16]);
-  } else if (PREC == kFP16X2) {
-    const _Float16* Ah = (const _Float16*)A0;
-    const _Float16* Al = (const _Float16*)A1;
-    return make_double2((double)Ah[o] + (double)Al[o], (double)Ah[o16] + (double)Al[o16]);
-  } else {
-    const __bf16* Ah = (const __bf16*)A0;
-    const __bf16* Al = (const __bf16*)A1;
-    return make_double2((double)(float)Ah[o] + (double)(float)Al[o],
-                        (double)(float)Ah[o16] + (double)(float)Al[o16]);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// extrinsic response (Sec. IV A): antenna patterns, arrival times, mode
-// factors, R_ekc, |R_ekc|^2 and Q_ekcc'
-// ---------------------------------------------------------------------------
-__device__ double swsh_m2(int l, int m, double cos_t) {
-  // spin-weight -2 harmonic at azimuth 0: sqrt((2l+1)/4pi) d^l_{m,2}(theta)
-  const double fact[13] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880, 3628800, 39916800,
-                           479001600};
-  double ct = fmin(1.0, fmax(-1.0, cos_t));
-  double cb = sqrt(0.5 * (1.0 + ct)), sb = sqrt(0.5 * (1.0 - ct));   // cos, sin of theta/2
-  const int s = 2;
-  double sum = 0.0;
-  for (int k = 0; k <= 2 * l; ++k) {
-    int a = l + s - k, b = k, c = l - k - m, d = k - s + m;
-    if (a < 0 || c < 0 || d < 0) continue;
-    double coef = sqrt(fact[l + s] * fact[l - s] * fact[l + m] * fact[l - m]) /
-                  (fact[a] * fact[b] * fact[c] * fact[d]);
-    if ((k - s + m) & 1) coef = -coef;
-    int pc = 2 * l - 2 * k + s - m, ps = 2 * k - s + m;
-    double v = coef;
-    for (int q = 0; q < pc; ++q) v *= cb;
-    for (int q = 0; q < ps; ++q) v *= sb;
-    sum += v;
-  }
-  return sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * sum;
-}
-
-__global__ void k_ext_response(int64_t n_ext, int n_det, const double* __restrict__ det_r,
-                               const double* __restrict__ det_D, const double* __restrict__ lat,
-                               const double* __restrict__ lon, const double* __restrict__ psi,
-                               const double* __restrict__ cosi, const double* __restrict__ tgeo,
-                               ModeTables mt, double2* __restrict__ R, double* __restrict__ T,
-                               double2* __restrict__ Q, double* __restrict__ R2) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_ext) return;
-  const double C = 299792458.0;
-  double la = lat[e], lo = lon[e], ps = psi[e];
-  double sla = sin(la), cla = cos(la), slo = sin(lo), clo = cos(lo), sps = sin(ps), cps = cos(ps);
-  double n[3] = {cla * clo, cla * slo, sla};
-  double elon[3] = {-slo, clo, 0.0};
-  double elat[3] = {-sla * clo, -sla * slo, cla};
-  double X[3], Y[3];
-  for (int a = 0; a < 3; ++a) {
-    X[a] = cps * elon[a] + sps * elat[a];
-    Y[a] = -sps * elon[a] + cps * elat[a];
-  }
-  double2 K[kMaxC][2];
-  for (int c = 0; c < mt.n_c; ++c) {
-    int l = mt.l[c], m = mt.m[c];
-    double yn = swsh_m2(l, -m, cosi[e]), yp = swsh_m2(l, m, cosi[e]);
-    double sg = (l & 1) ? -1.0 : 1.0;
-    K[c][0] = make_double2(0.5 * (yn + sg * yp), 0.0);
-    K[c][1] = make_double2(0.0, 0.5 * (yn - sg * yp));
-  }
-  for (int k = 0; k < n_det; ++k) {
-    const double* Dk = det_D + 9 * k;
-    double fp = 0.0, fx = 0.0, rn = 0.0;
-    for (int a = 0; a < 3; ++a) {
-      rn += det_r[3 * k + a] * n[a];
-      for (int b = 0; b < 3; ++b) {
-        fp += Dk[3 * a + b] * (X[a] * X[b] - Y[a] * Y[b]);
-        fx += Dk[3 * a + b] * (X[a] * Y[b] + Y[a] * X[b]);
-      }
-    }
-    T[e * n_det + k] = tgeo[e] - rn / C;
-    double2 Rk[kMaxC];
-    for (int c = 0; c < mt.n_c; ++c) {
-      Rk[c] = make_double2(fp * K[c][0].x + fx * K[c][1].x, fp * K[c][0].y + fx * K[c][1].y);
-      R[(e * n_det + k) * mt.n_c + c] = Rk[c];
-      R2[(e * n_det + k) * mt.n_c + c] = Rk[c].x * Rk[c].x + Rk[c].y * Rk[c].y;
-    }
-    for (int p = 0; p < mt.NP; ++p)
-      Q[(e * n_det + k) * mt.NP + p] = cmul(Rk[mt.pc[p]], cconj(Rk[mt.pc2[p]]));
-  }
-}
-
-// B_cb(e) = sum_k w_kb d_kb conj(R_ekc) exp(+2 pi i f_b t_ek), bins padded
-__global__ void k_build_B(int64_t n_ext, int n_det, int n_c, int n_b, int n_bp,
-                          const double* __restrict__ f, const double2* __restrict__ d,
-                          const double* __restrict__ w, const double2* __restrict__ R,
-                          const double* __restrict__ T, double2* __restrict__ Btmp) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t total = n_ext * n_c * n_bp;
-  if (idx >= total) return;
-  int b = (int)(idx % n_bp);
-  int c = (int)((idx / n_bp) % n_c);
-  int64_t e = idx / ((int64_t)n_bp * n_c);
-  double2 acc = make_double2(0.0, 0.0);
-  if (b < n_b) {
-    for (int k = 0; k < n_det; ++k) {
-      double x = f[b] * T[e * n_det + k];     // cycles
-      double fr = x - rint(x);
-      double sn, cs;
-      sincos(2.0 * M_PI * fr, &sn, &cs);
-      double2 r = cconj(R[(e * n_det + k) * n_c + c]);
-      double2 dk = d[k * n_b + b];
-      double wk = w[k * n_b + b];
-      double2 v = cmul(cmul(make_double2(wk * dk.x, wk * dk.y), r), make_double2(cs, sn));
-      acc.x += v.x;
-      acc.y += v.y;
-    }
-  }
-  Btmp[idx] = acc;
-}
-
-template <int PREC>
-__device__ __forceinline__ void store_split(void* A0, void* A1, int64_t o, double v) {
-  if (PREC == kFP64) {
-    ((double*)A0)[o] = v;
-  } else if (PREC == kFP16X2) {
-    _Float16 h = (_Float16)v;
-    ((_Float16*)A0)[o] = h;
-    ((_Float16*)A1)[o] = (_Float16)(v - (double)h);
-  } else {
-    __bf16 h = (__bf16)(float)v;
-    ((__bf16*)A0)[o] = h;
-    ((__bf16*)A1)[o] = (__bf16)(float)(v - (double)(float)h);
-  }
-}
-
-// extrinsic operand rows: Bre = [Br | -Bi], Bim = [Bi | Br] per chunk,
-// scaled by 2^-g_e in the split precisions; rows e >= n_ext are zero
-template <int PREC>
-__global__ void k_convert_B(int64_t n_ext, int64_t n_ext_p, int n_c, int n_bp,
-                            const double2* __restrict__ Btmp, void* __restrict__ B0,
-                            void* __restrict__ B1, void* __restrict__ B2, void* __restrict__ B3,
-                            double* __restrict__ col_scale, int* __restrict__ err) {
-  const int64_t e = blockIdx.x;
-  if (e >= n_ext_p) return;
-  __shared__ double red[256];
-  const int n = n_c * n_bp;
-  double mx = 0.0;
-  bool bad = false;
-  if (e < n_ext) {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      double2 v = Btmp[e * n + t];
-      if (!isfinite(v.x) || !isfinite(v.y)) bad = true;
-      mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
-    }
-  }
-  if (bad) atomicOr(err, 2);
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  mx = red[0];
-  int ex = 0;
-  if (PREC != kFP64 && mx > 0.0 && isfinite(mx)) ex = ilogb(mx) - 13;
-  if (threadIdx.x == 0 && col_scale && e < n_ext) col_scale[e] = ldexp(1.0, ex);
-  const int64_t K2 = (int64_t)n * 2;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    int c = t / n_bp, b = t % n_bp;
-    double br = 0.0, bi = 0.0;
-    if (e < n_ext) {
-      double2 v = Btmp[e * n + t];
-      br = ldexp(v.x, -ex);
-      bi = ldexp(v.y, -ex);
-    }
-    const int64_t base = ((int64_t)c * (n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
-    const int64_t o = op_index<PREC>(e, base, K2), o16 = op_index<PREC>(e, base + 16, K2);
-    if (PREC == kFP64) {
-      double* Bre = (double*)B0;
-      double* Bim = (double*)B1;
-      Bre[o] = br; Bre[o16] = -bi;     // B_re = [Br | -Bi]
-      Bim[o] = bi; Bim[o16] = br;      // B_im = [Bi | Br]
-    } else {
-      // split precisions: B_re only (B_im is the other slice of B_re)
-      store_split<PREC>(B0, B1, o, br);
-      store_split<PREC>(B0, B1, o16, -bi);
-    }
-  }
-}
-
-// (d|d)
-__global__ void k_data_norm(int n, const double2* __restrict__ d, const double* __restrict__ w,
-                            double* __restrict__ out) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) s += w[t] * (d[t].x * d[t].x + d[t].y * d[t].y);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = red[0];
-}
-
-// ---------------------------------------------------------------------------
-// (h|h) operands.  For one pair, the phase coefficients of (h|h)
-//     S0 (real), Re S_d, Im S_d (d = 1 .. ND-1)      -- NR = 2 ND - 1 outputs
-// are each a dot product of at most 32 terms a * b with a taken from the
-// waveform's H_ikcc' and b from the sample's Q_ekcc'; they are computed by
-// the same matrix cores as (d|h), as extra K blocks of 32.  A term (output r,
-// slot j) is encoded in 16 bits: k (0-3), p (4-9), a from Im H (10), b from
-// Im Q (11), coefficient index (12-14: 0, 1, -1, 2, -2), valid (15).
-// ---------------------------------------------------------------------------
-constexpr int kMaxNR = 2 * kMaxND - 1;
-
-__device__ __forceinline__ double term_value(int code, const double2* X, int NP, bool row_side) {
-  if (!(code & 0x8000)) return 0.0;
-  int k = code & 15, p = (code >> 4) & 63;
-  int part = row_side ? (code >> 10) & 1 : (code >> 11) & 1;
-  double2 v = X[k * NP + p];
-  double x = part ? v.y : v.x;
-  if (row_side) {
-    int ci = (code >> 12) & 7;
-    x *= ci == 1 ? 1.0 : ci == 2 ? -1.0 : ci == 3 ? 2.0 : ci == 4 ? -2.0 : 0.0;
-  }
-  return x;
-}
-
-__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
-
-// per-waveform (h|h) sums H_ikcc' = sum_b w_kb h_icb conj(h_ic'b) for the
-// event's bank subset, from the same operand values the contraction uses,
-// written as the row-side (h|h) operand (n_sub rows of KH, op_index layout)
-// with a power-of-two
-// row scale in the split precisions
-template <int PREC>
-__global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_idx, int64_t sub0,
-                                const void* __restrict__ A0, const void* __restrict__ A1,
-                                const double* __restrict__ row_scale, int n_bp, int n_b,
-                                int n_det, const double* __restrict__ w, ModeTables mt,
-                                const int* __restrict__ terms, int KH, void* __restrict__ H0,
-                                void* __restrict__ H1, double* __restrict__ hscale) {
-  // the row [n_c][n_bp] then w [n_det][n_b], when they fit.  A split value
-  // hi + lo spans at most 23 significant bits, so float holds it exactly.
-  typedef typename std::conditional<PREC == kFP64, double2, float2>::type RB;
-  extern __shared__ __align__(16) unsigned char hh_smem[];
-  RB* rowbuf = (RB*)hh_smem;
-  __shared__ double2 Hs[kMaxDet * kMaxNP];
-  __shared__ double vals[256];
-  __shared__ double red[64];
-  const int64_t ie = blockIdx.x;
-  if (ie >= n_sub) return;
-  const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
-  const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
-  const bool staged = (size_t)mt.n_c * n_bp * sizeof(RB) + (size_t)n_det * n_b * sizeof(double) <= 65536;
-  double* wl = (double*)(rowbuf + mt.n_c * n_bp);
-  if (staged) {
-    // the row in pieces of 8 consecutive positions (16 bytes per operand
-    // array in the split layouts): 8 bins of the real or the imaginary part
-    for (int pc = threadIdx.x; pc < (int)(K2 / 8); pc += blockDim.x) {
-      const int64_t o = op_index<PREC>(i, (int64_t)pc * 8, K2);
-      double v[8];
-      if (PREC == kFP64) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = ((const double*)A0)[o + j];
-      } else {
-        const uint4 hq = *(const uint4*)((const uint16_t*)A0 + o);
-        const uint4 lq = *(const uint4*)((const uint16_t*)A1 + o);
-        const unsigned hw[4] = {hq.x, hq.y, hq.z, hq.w}, lw[4] = {lq.x, lq.y, lq.z, lq.w};
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint16_t hb = (uint16_t)(hw[j >> 1] >> (16 * (j & 1)));
-          const uint16_t lb = (uint16_t)(lw[j >> 1] >> (16 * (j & 1)));
-          if (PREC == kFP16X2)
-            v[j] = (double)__builtin_bit_cast(_Float16, hb) + (double)__builtin_bit_cast(_Float16, lb);
-          else
-            v[j] = (double)(float)__builtin_bit_cast(__bf16, hb) + (double)(float)__builtin_bit_cast(__bf16, lb);
-        }
-      }
-      const int kk = pc * 8, chunk = kk >> 5, within = kk & 31;
-      const int c = chunk / (n_bp / kChunk), b0 = (chunk % (n_bp / kChunk)) * kChunk + (within & 15);
-      typedef typename std::conditional<PREC == kFP64, double, float>::type RV;
-      RV* dst = (RV*)(rowbuf + c * n_bp + b0) + (within >= 16 ? 1 : 0);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) dst[2 * j] = (RV)v[j];
-    }
-    for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[t] = w[t];
-    __syncthreads();
-  }
-  double sc = row_scale ? row_scale[i] : 1.0;
-  sc = sc * sc;
-  for (int t = threadIdx.x; t < n_det * mt.NP; t += blockDim.x) {
-    int k = t / mt.NP, p = t % mt.NP;
-    int c = mt.pc[p], c2 = mt.pc2[p];
-    double2 acc = make_double2(0.0, 0.0);
-    if (staged) {
-      // two partial sums, so that consecutive bins do not wait on each other
-      double2 acc2 = make_double2(0.0, 0.0);
-      int b = 0;
-      for (; b + 1 < n_b; b += 2) {
-        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * n_bp + b])), to_d2(rowbuf[c2 * n_bp + b]));
-        const double2 v1 = cmul(cconj(to_d2(rowbuf[c * n_bp + b + 1])), to_d2(rowbuf[c2 * n_bp + b + 1]));
-        const double w0 = wl[k * n_b + b], w1 = wl[k * n_b + b + 1];
-        acc.x += w0 * v0.x;
-        acc.y += w0 * v0.y;
-        acc2.x += w1 * v1.x;
-        acc2.y += w1 * v1.y;
-      }
-      if (b < n_b) {
-        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * n_bp + b])), to_d2(rowbuf[c2 * n_bp + b]));
-        acc.x += wl[k * n_b + b] * v0.x;
-        acc.y += wl[k * n_b + b] * v0.y;
-      }
-      acc.x += acc2.x;
-      acc.y += acc2.y;
-    } else {
-      for (int b = 0; b < n_b; ++b) {
-        double2 a = bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
-        double2 a2 = bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
-        double2 v = cmul(cconj(a), a2);      // h_c conj(h_c') = conj(A_c) A_c'
-        double ww = w[k * n_b + b];
-        acc.x += ww * v.x;
-        acc.y += ww * v.y;
-      }
-    }
-    Hs[k * mt.NP + p] = make_double2(acc.x * sc, acc.y * sc);
-  }
-  __syncthreads();
-  double mx = 0.0;
-  for (int j = threadIdx.x; j < KH; j += blockDim.x) {
-    double v = term_value(terms[j], Hs, mt.NP, true);
-    vals[j] = v;
-    mx = fmax(mx, fabs(v));
-  }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  int ex = 0;
-  if (PREC != kFP64 && red[0] > 0.0 && isfinite(red[0])) ex = ilogb(red[0]) - 13;
-  if (threadIdx.x == 0 && hscale) hscale[ie] = ldexp(1.0, ex);
-  for (int j = threadIdx.x; j < KH; j += blockDim.x)
-    store_split<PREC>(H0, H1, op_index<PREC>(ie, j, KH), ldexp(vals[j], -ex));
-}
-
-// column-side (h|h) operand (n_ext_p rows of KH, op_index layout) from
-// Q_ekcc' = R_ekc conj(R_ekc')
-template <int PREC>
-__global__ void k_build_Bhh(int64_t n_ext, int64_t n_ext_p, int n_det, const double2* __restrict__ Q,
-                            ModeTables mt, const int* __restrict__ terms, int KH,
-                            void* __restrict__ B0, void* __restrict__ B1,
-                            double* __restrict__ bscale) {
-  __shared__ double vals[256];
-  __shared__ double red[64];
-  const int64_t e = blockIdx.x;
-  if (e >= n_ext_p) return;
-  double mx = 0.0;
-  for (int j = threadIdx.x; j < KH; j += blockDim.x) {
-    double v = e < n_ext ? term_value(terms[j], Q + e * n_det * mt.NP, mt.NP, false) : 0.0;
-    vals[j] = v;
-    mx = fmax(mx, fabs(v));
-  }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  int ex = 0;
-  if (PREC != kFP64 && red[0] > 0.0 && isfinite(red[0])) ex = ilogb(red[0]) - 13;
-  if (threadIdx.x == 0 && bscale && e < n_ext) bscale[e] = ldexp(1.0, ex);
-  for (int j = threadIdx.x; j < KH; j += blockDim.x)
-    store_split<PREC>(B0, B1, op_index<PREC>(e, j, KH), ldexp(vals[j], -ex));
-}
 
 // ---------------------------------------------------------------------------
 // fused kernel: complex MFMA contraction (d|h) + (h|h) phase coefficients,
@@ -1727,79 +1118,6 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     if (mlm > 0.0) atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
     if (mxp > -INFINITY) atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(mxp));
   }
-}
-
-// fixed-order reduction of tile partials: block b combines tiles
-// [b * per, (b + 1) * per) into out[b][kNPart]; a second launch with one
-// block combines the block results
-__global__ void k_finalize(const double* __restrict__ partials, int64_t n_tiles, int64_t per,
-                           double* __restrict__ out) {
-  __shared__ double sh[256 * kNPart];
-  const int64_t t0 = blockIdx.x * per, t1 = min(n_tiles, t0 + per);
-  Lse p, d;
-  p.init(); d.init();
-  double mlm = 0.0, mb = -INFINITY, mxp = -INFINITY, nm = 0, nb = 0, np_ = 0;
-  for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-    const double* r = partials + t * kNPart;
-    p.merge(r[0], r[1], r[2]);
-    d.merge(r[3], r[4], 0.0);
-    mlm = fmax(mlm, r[5]);
-    nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); mxp = fmax(mxp, r[9]); np_ += r[10];
-  }
-  double* m = sh + threadIdx.x * kNPart;
-  m[0] = p.m; m[1] = p.s; m[2] = p.s2; m[3] = d.m; m[4] = d.s; m[5] = mlm;
-  m[6] = nm; m[7] = nb; m[8] = mb; m[9] = mxp; m[10] = np_; m[11] = 0;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      double* x = sh + threadIdx.x * kNPart;
-      double* y = sh + (threadIdx.x + s) * kNPart;
-      Lse pp, dd;
-      pp.m = x[0]; pp.s = x[1]; pp.s2 = x[2];
-      dd.m = x[3]; dd.s = x[4]; dd.s2 = 0.0;
-      pp.merge(y[0], y[1], y[2]);
-      dd.merge(y[3], y[4], 0.0);
-      x[0] = pp.m; x[1] = pp.s; x[2] = pp.s2; x[3] = dd.m; x[4] = dd.s;
-      x[5] = fmax(x[5], y[5]); x[6] += y[6]; x[7] += y[7]; x[8] = fmax(x[8], y[8]);
-      x[9] = fmax(x[9], y[9]); x[10] += y[10];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0)
-    for (int q = 0; q < kNPart; ++q) out[blockIdx.x * kNPart + q] = sh[q];
-}
-
-// one bitonic merge step over candidate records [n][4] (ln p, i, e, o):
-// order = ln p descending, then i, then e ascending
-__device__ __forceinline__ bool cand_before(const double* x, const double* y) {
-  if (x[0] != y[0]) return x[0] > y[0];
-  if (x[1] != y[1]) return x[1] < y[1];
-  return x[2] < y[2];
-}
-__global__ void k_bitonic_step(double* __restrict__ c, int64_t n, int64_t j, int64_t k) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int64_t l = i ^ j;
-  if (l <= i) return;
-  double* x = c + 4 * i;
-  double* y = c + 4 * l;
-  bool up = (i & k) == 0;
-  bool swap = up ? cand_before(y, x) : cand_before(x, y);
-  if (swap) {
-    for (int q = 0; q < 4; ++q) {
-      double t = x[q];
-      x[q] = y[q];
-      y[q] = t;
-    }
-  }
-}
-__global__ void k_fill_cand(double* __restrict__ c, int64_t from, int64_t to) {
-  int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= to) return;
-  c[4 * i] = -INFINITY;
-  c[4 * i + 1] = 1e300;
-  c[4 * i + 2] = 1e300;
-  c[4 * i + 3] = 0;
 }
 
 }  // namespace dotpe

@@ -1,0 +1,60 @@
+// Instantiations of the fused likelihood kernel for one precision and one
+// number of m groups, chosen at compile time by DOTPE_INST_PREC (0 FP64,
+// 1 FP16x2, 2 BF16x2) and DOTPE_INST_G (1..4).
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "launch.h"
+
+#ifndef DOTPE_INST_PREC
+#error "DOTPE_INST_PREC must be defined"
+#endif
+#ifndef DOTPE_INST_G
+#error "DOTPE_INST_G must be defined"
+#endif
+
+namespace dotpe {
+namespace {
+
+template <int PREC, int G, int MODE, bool FAST>
+hipError_t launch_one(const FusedArgs& a, int64_t grid, hipStream_t s) {
+  typedef Tile<PREC> TL;
+  const size_t sh = TL::CS_OFF + sizeof(double) * kMaxM * a.n_phi * 2;
+  // allow more than 64 KiB of dynamic LDS (once per kernel; not every
+  // runtime needs or supports the attribute, so a failure is not an error)
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    const size_t most = TL::CS_OFF + sizeof(double) * kMaxM * kMaxPhi * 2;
+    if (hipFuncSetAttribute((const void*)k_lnl_fused<PREC, G, MODE, FAST>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
+      (void)hipGetLastError();
+  });
+  hipLaunchKernelGGL((k_lnl_fused<PREC, G, MODE, FAST>), dim3((unsigned)grid), dim3(TL::NT), sh, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <int PREC, int G>
+hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hipStream_t s) {
+  switch (mode) {
+    case kEval: return launch_one<PREC, G, kEval, false>(a, grid, s);
+    case kPilot: return launch_one<PREC, G, kPilot, false>(a, grid, s);
+    case kEvidence:
+      return fast ? launch_one<PREC, G, kEvidence, true>(a, grid, s)
+                  : launch_one<PREC, G, kEvidence, false>(a, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+#define DOTPE_CAT4(a, b, c, d) a##b##c##d
+#define DOTPE_NAME(P, G) DOTPE_CAT4(launch_fused_p, P, _g, G)
+
+hipError_t DOTPE_NAME(DOTPE_INST_PREC, DOTPE_INST_G)(int mode, bool fast, const FusedArgs& a,
+                                                     int64_t grid, hipStream_t s) {
+  return launch_any<DOTPE_INST_PREC, DOTPE_INST_G>(mode, fast, a, grid, s);
+}
+
+}  // namespace dotpe

@@ -1,0 +1,46 @@
+// Launchers of the fused likelihood kernel, one per (precision, number of m
+// groups).  Each is compiled in its own translation unit (fused_inst.hip
+// built with DOTPE_INST_PREC and DOTPE_INST_G), so the library's kernels
+// compile in parallel; the host runtime picks one from the table below.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fused.h"
+
+namespace dotpe {
+
+// mode: kEval, kPilot or kEvidence; fast only with kEvidence.  Launches
+// `grid` workgroups on stream s and returns the launch status.
+typedef hipError_t (*FusedLaunchFn)(int mode, bool fast, const FusedArgs& a, int64_t grid,
+                                    hipStream_t s);
+
+#define DOTPE_FUSED_DECL(P, G)                                                              \
+  hipError_t launch_fused_p##P##_g##G(int mode, bool fast, const FusedArgs& a, int64_t grid, \
+                                      hipStream_t s);
+DOTPE_FUSED_DECL(0, 1)
+DOTPE_FUSED_DECL(0, 2)
+DOTPE_FUSED_DECL(0, 3)
+DOTPE_FUSED_DECL(0, 4)
+DOTPE_FUSED_DECL(1, 1)
+DOTPE_FUSED_DECL(1, 2)
+DOTPE_FUSED_DECL(1, 3)
+DOTPE_FUSED_DECL(1, 4)
+DOTPE_FUSED_DECL(2, 1)
+DOTPE_FUSED_DECL(2, 2)
+DOTPE_FUSED_DECL(2, 3)
+DOTPE_FUSED_DECL(2, 4)
+#undef DOTPE_FUSED_DECL
+
+// launcher for precision prec (kFP64, kFP16X2, kBF16X2) and G m groups
+// (1..kMaxG), or nullptr
+inline FusedLaunchFn fused_launcher(int prec, int G) {
+  static const FusedLaunchFn table[3][kMaxG] = {
+      {launch_fused_p0_g1, launch_fused_p0_g2, launch_fused_p0_g3, launch_fused_p0_g4},
+      {launch_fused_p1_g1, launch_fused_p1_g2, launch_fused_p1_g3, launch_fused_p1_g4},
+      {launch_fused_p2_g1, launch_fused_p2_g2, launch_fused_p2_g3, launch_fused_p2_g4}};
+  if (prec < 0 || prec > 2 || G < 1 || G > kMaxG) return nullptr;
+  return table[prec][G - 1];
+}
+
+}  // namespace dotpe
