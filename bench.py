@@ -72,41 +72,74 @@ def stored_traffic():
         return None
 
 
-def device_bank(torch, mc, q, chi, f, modes, chunk=32768):
-    """Bank amplitudes generated on the GPU in float64: [N, C, B, 2]."""
-    from synth import workload as W
-    n = len(mc)
-    out = torch.empty((n, len(modes), len(f), 2), dtype=torch.float64, device="cuda")
-    ft = torch.as_tensor(f, dtype=torch.float64, device="cuda")
-    for s in range(0, n, chunk):
-        e = min(n, s + chunk)
-        args = [torch.as_tensor(x[s:e], dtype=torch.float64, device="cuda") for x in (mc, q, chi)]
-        h = W.waveform_modes(ft, *args, modes, xp=torch)
-        out[s:e] = torch.view_as_real(h)
-    torch.cuda.synchronize()
-    return out
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(wl_meta, rows, cols, f, modes, wl_event, budget_s=20.0):
-    """Time the FP64 oracle on a bounded sample of pairs of the same workload."""
+def _host_rows(W, wl, rows, cols=None):
+    """A workload of the given bank rows (and extrinsic samples) of a large event, with the
+    rows' amplitudes generated on the host from the same seeded parameters."""
+    m = wl.meta
+    rows = np.asarray(rows)
+    h = W.waveform_modes(wl.f, m["mc"][rows], m["q"][rows], m["chi"][rows], wl.modes)
+    cols = np.arange(wl.n_ext) if cols is None else np.asarray(cols)
+    return W.Workload(wl.modes, wl.f, h, np.zeros(len(rows)), wl.det_r, wl.det_D, wl.d, wl.w,
+                      {k: v[cols] for k, v in wl.ext.items()}, wl.ln_w_ext[cols], wl.n_phi,
+                      wl.d_max, wl.d0)
+
+
+def cpu_baseline(W, wl, rows, cols, cores):
+    """The FP64 oracle on the machine's host cores, on bounded samples:
+    * the large event: rows x cols pairs in worker processes on every core, and a quarter of
+      the rows in one process (one thread);
+    * the tiny configuration (256 x 512 pairs) in full on every core, and 8 of its bank rows
+      in one process.
+    Returns the report and the oracle's ln Lbar on the large-event sample."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import oracle as O
-    from synth import workload as W
-    mc, q, chi = wl_meta["mc"], wl_meta["q"], wl_meta["chi"]
-    h = W.waveform_modes(f, mc[rows], q[rows], chi[rows], modes)
-    sub = W.Workload(modes, f, h, np.zeros(len(rows)), wl_event.det_r, wl_event.det_D,
-                     wl_event.d, wl_event.w, wl_event.ext, wl_event.ln_w_ext, wl_event.n_phi,
-                     wl_event.d_max, wl_event.d0)
+    sub = _host_rows(W, wl, rows, cols)
     t0 = time.perf_counter()
-    done = 0
-    lnl = np.full((len(rows), len(cols)), np.nan)
-    for a in range(len(rows)):
-        r = O.eval_pairs_block(sub, [a], ext_idx=cols)
-        lnl[a] = r["lnl"][0]
-        done += len(cols)
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return done / dt, done, lnl
+    ref = O.eval_lnl(sub, processes=cores)["lnl"]
+    t_multi = time.perf_counter() - t0
+    n_one = max(1, len(rows) // 4)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.eval_pairs_block(sub, np.arange(n_one))
+        t_one = time.perf_counter() - t0
+    tiny = W.config_tiny(seed=0)
+    t0 = time.perf_counter()
+    O.eval_lnl(tiny, processes=cores)
+    t_tiny = time.perf_counter() - t0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.eval_pairs_block(tiny, np.arange(8))
+        t_tiny1 = time.perf_counter() - t0
+    n_s = len(rows) * len(cols)
+    rep = {"value": n_s / t_multi, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n_s} pairs of the large event ({len(rows)} bank rows, half of them past "
+                     f"the 2^31-element operand offset, x {len(cols)} extrinsic samples; all 32 "
+                     "phases, 2000-node distance quadrature), FP64 direct sums, "
+                     f"{cores} worker processes of one thread",
+           "cpu_model": _cpu_model(),
+           "single_process": {"value": n_one * len(cols) / t_one, "unit": "pairs/s",
+                              "threads": 1, "sample": f"{n_one * len(cols)} pairs of the same sample"},
+           "large_extrapolated_s": {"all_cores": len(wl.meta["mc"]) * wl.n_ext * t_multi / n_s,
+                                    "one_core": len(wl.meta["mc"]) * wl.n_ext * t_one / (n_one * len(cols))},
+           "tiny_full": {"pairs": tiny.n_int * tiny.n_ext, "s": t_tiny,
+                         "pairs_per_s": tiny.n_int * tiny.n_ext / t_tiny, "cores": cores,
+                         "single_process_pairs_per_s": 8 * tiny.n_ext / t_tiny1}}
+    log(f"oracle: {rep['value']:.0f} pairs/s on {cores} cores ({rep['cpu_model']}), "
+        f"{rep['single_process']['value']:.0f} pairs/s in one process; tiny config in full "
+        f"{t_tiny:.1f} s")
+    return rep, ref
 
 
 def fp64_comparison(torch, dotpe, W, ctx, args, reps=2):
@@ -117,7 +150,7 @@ def fp64_comparison(torch, dotpe, W, ctx, args, reps=2):
     wl = W.make_workload(seed, n_int=n_int, n_ext=n_ext, n_bins=256, modes=modes, dets="HLV",
                          n_phi=32, snr=snr, mc_range=(5.0, 80.0), q_range=(0.1, 1.0),
                          chi_range=(-0.9, 0.9), with_bank=False)
-    hdev = device_bank(torch, wl.meta["mc"], wl.meta["q"], wl.meta["chi"], wl.f, modes)
+    hdev = W.bank_on_device(torch, wl.meta["mc"], wl.meta["q"], wl.meta["chi"], wl.f, modes)
     out = {"workload": f"production: {n_int} x {n_ext} pairs, cut {args.cut}"}
     for prec in ("fp64", args.precision):
         bank = ctx.load_bank(hdev, modes, wl.f, precision=prec)
@@ -133,6 +166,8 @@ def fp64_comparison(torch, dotpe, W, ctx, args, reps=2):
         out[f"{prec}_ms"] = min(ts)
         out[f"{prec}_ln_z"] = r["ln_z"]
     out["speedup"] = out["fp64_ms"] / out[f"{args.precision}_ms"]
+    out["abs_dlnz"] = abs(out["fp64_ln_z"] - out[f"{args.precision}_ln_z"])
+    out["within_1e-3"] = bool(out["abs_dlnz"] <= 1e-3)
     log(f"FP64 path {out['fp64_ms']:.1f} ms vs {args.precision} {out[args.precision + '_ms']:.1f} ms "
         f"(x{out['speedup']:.1f}); ln Z {out['fp64_ln_z']:.6f} vs {out[args.precision + '_ln_z']:.6f}")
     del hdev
@@ -218,7 +253,6 @@ def main():
     ap.add_argument("--serve-pool-gib", type=int, default=8)
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64-path comparison at the production shape")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this size (calibrates HBM counters)")
     args = ap.parse_args()
@@ -232,14 +266,25 @@ def main():
     from paper_2507_16022_amd import dotpe
     from synth import workload as W
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     n_int, n_ext, seed, snr = WORKLOADS[args.workload]
     modes = W.MODES_HM
     t0 = time.perf_counter()
     wl = W.make_workload(seed, n_int=n_int, n_ext=n_ext, n_bins=256, modes=modes, dets="HLV",
                          n_phi=32, snr=snr, mc_range=(5.0, 80.0), q_range=(0.1, 1.0),
                          chi_range=(-0.9, 0.9), with_bank=False)
-    hdev = device_bank(torch, wl.meta["mc"], wl.meta["q"], wl.meta["chi"], wl.f, modes)
+    # the random-pair sample (half of its rows past the 2^31-element operand offset) and the
+    # CPU baseline on it, before this process touches the GPU (the oracle's worker processes
+    # start from a process without GPU state)
+    rng = np.random.default_rng(99)
+    k2 = 2 * len(modes) * 256
+    cut31 = (1 << 31) // k2 + 1
+    rows = np.sort(np.r_[rng.choice(cut31, 16, replace=False),
+                         rng.choice(np.arange(cut31, n_int), 16, replace=False)])
+    cols = np.sort(rng.choice(n_ext, 256, replace=False))
+    cpu, ref = (None, None) if args.no_cpu else cpu_baseline(
+        W, wl, rows, cols, min(16, len(os.sched_getaffinity(0))))
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    hdev = W.bank_on_device(torch, wl.meta["mc"], wl.meta["q"], wl.meta["chi"], wl.f, modes)
     log(f"workload generated in {time.perf_counter() - t0:.1f} s")
     ctx = dotpe.Context(0)
     t0 = time.perf_counter()
@@ -291,29 +336,27 @@ def main():
         f"ln Z {r['ln_z']:.6f} (upper {r['ln_z_upper']:.6f}), bounded pairs "
         f"{r['n_pairs_bounded']}/{r['n_pairs']}, triples marginalised {r['n_triples_marg']}")
 
-    # sampled parity and the CPU baseline on the same pairs
-    rng = np.random.default_rng(99)
-    rows = np.sort(rng.choice(n_int, 16, replace=False))
-    # include the best pairs found by the GPU so the sample covers the peak
-    if r["topk_count"]:
-        rows = np.unique(np.r_[rows[:12], r["topk_i"][:4]])
-    cols = np.sort(rng.choice(n_ext, 256, replace=False))
+    # parity at the full shape: the fused pass's best pairs one by one against the oracle,
+    # and random pairs (half in rows past the 2^31-element operand offset) through the
+    # materialising pass on the resident bank; the CPU baseline times the oracle on the latter
+    from oracle import oracle as O
+    n_top = min(64, r["topk_count"])
+    top_err = None
+    if n_top:
+        top = _host_rows(W, wl, r["topk_i"][:n_top])
+        ref_top = np.array([O.eval_pairs_block(top, [q], ext_idx=[r["topk_e"][q]])["lnl"][0, 0]
+                            for q in range(n_top)]) + wl.ln_w_ext[r["topk_e"][:n_top]]
+        top_err = float(np.max(np.abs(r["topk_lnp"][:n_top] - ref_top)))
+        log(f"top-{n_top} pairs of the fused pass vs oracle: max |d ln p| = {top_err:.3e}")
     ev = ctx.set_event(bank, d=wl.d, w=wl.w, det_r=wl.det_r, det_D=wl.det_D,
                        ext={k: v[cols] for k, v in wl.ext.items()}, n_phi=wl.n_phi,
                        ln_w_ext=wl.ln_w_ext[cols], d_max=wl.d_max, d0=wl.d0, sub_idx=rows)
     gpu_lnl = ev.eval_lnl()["lnl"]
     ev.close()
-    cpu = None
     parity = None
-    if not args.no_cpu:
-        rate, done, ref = cpu_baseline(wl.meta, rows, cols, wl.f, modes, wl, args.cpu_seconds)
-        ok = np.isfinite(ref)
-        parity = float(np.max(np.abs(gpu_lnl[ok] - ref[ok]))) if ok.any() else None
-        cpu = {"value": rate, "unit": "pairs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} pairs ({len(rows)} bank rows incl. the top GPU pairs x "
-                         f"{len(cols)} extrinsic samples) of the same workload, FP64 direct "
-                         "sums + 2000-node distance quadrature, single process"}
-        log(f"oracle {rate:.1f} pairs/s on {done} pairs; sampled max |d lnLbar| = {parity}")
+    if ref is not None:
+        parity = float(np.max(np.abs(gpu_lnl - ref)))
+        log(f"random pairs vs oracle: max |d lnLbar| = {parity:.3e}")
 
     serving = (serving_leg(dotpe, W, ctx, bank, n_int, args)
                if args.serve_events > 0 else None)
@@ -349,6 +392,7 @@ def main():
         "triples_marginalised": r["n_triples_marg"],
         "pilot_ms": pilot_ms,
         "sampled_max_abs_dlnl_vs_oracle": parity,
+        "topk_max_abs_dlnp_vs_oracle": top_err,
         "topk_count": r["topk_count"], "topk_exact": r["topk_exact"],
         "fp64_path": fp64_cmp,
         "serving": serving,

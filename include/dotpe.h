@@ -134,13 +134,19 @@ typedef struct dotpe_event_desc {
   int64_t sub_start;        /* bank rows [sub_start, sub_start + sub_count) ... */
   int64_t sub_count;        /* ... 0 = the whole bank */
   const int64_t* sub_idx;   /* or explicit rows [sub_count] (host), NULL = range */
-  double cut_delta;         /* coherent cut (eq. coherent_ML_selection): triples with
-                               lnL^ML < running max - cut_delta are bounded, not
+  double cut_delta;         /* coherent cut (eq. coherent_ML_selection): a pilot pass over
+                               every 64th row of tiles finds M = max lnL^ML; pairs whose
+                               certified upper bound on lnL^ML lies below M - cut_delta
+                               are bounded (their mass goes to ln_z_upper), not
                                marginalised; <= 0 disables the cut */
   int32_t top_k;            /* number of top pairs to return from dotpe_evidence */
   int32_t flags;            /* 0, or DOTPE_FLAG_RERUN_ALL */
   double topk_window;       /* candidates kept within this of the max ln p (default 40 if <= 0) */
   void* stream;             /* hipStream_t for this event's work; NULL = context stream */
+  double cut_target;        /* certificate the cut must meet: ln_z_upper - ln_z <= cut_target
+                               (<= 0: 1e-4).  dotpe_evidence repeats the pass with a
+                               larger cut_delta (cutting less), finally with no cut,
+                               until it does */
 } dotpe_event_desc;
 
 /* Stage an event against a resident bank: copies inputs, builds the
@@ -178,6 +184,9 @@ typedef struct dotpe_evidence_result {
   int32_t status;
   double t_pilot_ms;        /* device time of the threshold pilot pass (HIP events) */
   double t_fused_ms;        /* device time of the fused pass (HIP events) */
+  double cut_delta_used;    /* cut_delta of the pass returned (0: no cut) */
+  int32_t n_passes;         /* evidence passes run to meet cut_target */
+  int32_t reserved;
 } dotpe_evidence_result;
 
 typedef struct dotpe_sample {
@@ -213,8 +222,9 @@ int dotpe_event_bytes(const dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_
  * in its pool block, so serving allocates no device memory per event and the
  * work of events in different slots overlaps on the device.  The block
  * returns to the pool when the event completes.  Results equal those of
- * dotpe_evidence on the same event alone, up to the certified cut (which
- * pairs are bounded depends on when the running maximum rises).
+ * dotpe_evidence on the same event alone, bit for bit: the cut threshold is
+ * fixed by the pilot pass before the main pass starts, and every sum is
+ * taken in an order that does not depend on timing.
  * (Sec. IV B: every event is an independent evaluation of the likelihood
  * matrix; scheduling is outside the paper.) */
 typedef struct dotpe_server dotpe_server;
@@ -260,15 +270,6 @@ int dotpe_poll(dotpe_server* srv, int64_t ticket, int32_t* done);
  * the event's error code. */
 int dotpe_wait(dotpe_server* srv, int64_t ticket, dotpe_evidence_result* out, dotpe_sample* topk,
                dotpe_ticket_info* info);
-
-/* Evaluate the device distance-marginalisation rule for n (dh, hh) pairs
- * (host arrays), d0/D_max given; for checking the rule against a reference. */
-int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const double* hh,
-                         double d0_over_dmax, double* out);
-
-/* Copy back the event's extrinsic response: R [n_ext][n_det][n_modes][2] and
- * t [n_ext][n_det] (host arrays), channels in the bank's input order. */
-int dotpe_debug_response(dotpe_ctx* ctx, const dotpe_event* ev, double* R, double* t);
 
 #ifdef __cplusplus
 }

@@ -215,6 +215,60 @@ def ln_dist_marg(dh, hh, d_max, d0=1.0, n_nodes=2000, chunk=4096):
     return out.reshape(shape)
 
 
+def ln_dist_marg_adaptive(dh, hh, d_max, d0=1.0, rel=1e-12):
+    """ln of eq. (lnl_dist_marginalized) by adaptive quadrature (scipy's
+    quad), for peaks narrower than a fixed node set resolves.
+
+    With u = d0/D the prior D^2 on (0, D_max] turns the integral into
+    3 u0^3 int_{u0}^inf u^-4 exp(dh u - hh u^2/2) du, u0 = d0/D_max.  The
+    exponent's largest value over u >= u0 (at u* = max(u0, dh/hh)) is taken
+    out, and [u0, u* + 40/sqrt(hh)] is cut into pieces that quad integrates
+    separately: doubling steps from u0 (where u^-4 changes on the scale u0)
+    and steps of one peak width 1/sqrt(hh) around u*.  Past the last piece
+    the integrand is below exp(-800) of its peak."""
+    import warnings
+
+    from scipy import integrate
+    dh = np.asarray(dh, dtype=np.float64)
+    hh = np.asarray(hh, dtype=np.float64)
+    dh, hh = np.broadcast_arrays(dh, hh)
+    out = np.empty(dh.shape)
+    u0 = d0 / d_max
+    for idx in np.ndindex(dh.shape):
+        a, b = float(dh[idx]), float(hh[idx])
+        if not b > 0.0:
+            if a == 0.0:
+                out[idx] = 0.0          # empty template: the prior integrates to one
+                continue
+            raise ValueError("hh must be positive unless dh = 0")
+        sig = 1.0 / math.sqrt(b)
+        ustar = max(u0, a / b)
+        c = a * ustar - 0.5 * b * ustar * ustar
+        hi = ustar + 40.0 * sig
+        pts = {u0, hi}
+        u = u0
+        while u < hi:
+            pts.add(u)
+            u *= 2.0
+        for k in range(-40, 41):
+            x = ustar + k * sig
+            if u0 < x < hi:
+                pts.add(x)
+        pts = sorted(pts)
+
+        def f(u):
+            return u ** -4 * math.exp(a * u - 0.5 * b * u * u - c)
+
+        tot = 0.0
+        with warnings.catch_warnings():
+            # quad flags pieces whose share is below the rounding of the sum
+            warnings.simplefilter("ignore", integrate.IntegrationWarning)
+            for lo, up in zip(pts[:-1], pts[1:]):
+                tot += integrate.quad(f, lo, up, epsabs=0.0, epsrel=rel, limit=200)[0]
+        out[idx] = math.log(3.0) + 3.0 * math.log(u0) + c + math.log(tot)
+    return out
+
+
 # --------------------------------------------------------------------------
 # O8-O10: per-pair likelihood, evidence, top-K
 # --------------------------------------------------------------------------
@@ -263,10 +317,23 @@ def eval_lnl(wl, n_nodes=2000, processes=1):
     if processes <= 1:
         return eval_pairs_block(wl, rows, None, n_nodes)
     import multiprocessing as mp
+    import os
     chunks = [c for c in np.array_split(rows, processes * 4) if len(c)]
     ctx = mp.get_context("spawn")
-    with ctx.Pool(processes) as pool:
-        parts = pool.map(_worker, [(wl, c, n_nodes) for c in chunks])
+    # one thread per worker process: the workers share the cores, and
+    # numpy's threaded kernels in each of them would oversubscribe them
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    os.environ.update({k: "1" for k in keys})
+    try:
+        with ctx.Pool(processes) as pool:
+            parts = pool.map(_worker, [(wl, c, n_nodes) for c in chunks])
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     return dict(lnl=np.concatenate([p["lnl"] for p in parts]),
                 ml_max=np.concatenate([p["ml_max"] for p in parts]))
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/dotpe.h"
+#include "../../include/dotpe_test.h"
 #include "launch.h"
 #include "prep.h"
 #include "serving.h"
@@ -83,6 +84,7 @@ struct dotpe_event {
   int64_t n_ext = 0, n_ext_p = 0, n_sub = 0, sub0 = 0;
   int64_t* sub_idx = nullptr;
   double d0 = 1.0, d_max = 1.0, n_norm = 0.0, cut_delta = 0.0, topk_window = 40.0;
+  double cut_target = 1e-4;
   int top_k = 0;
   int flags = 0;
   double dd = 0.0;
@@ -767,6 +769,7 @@ int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc*
   ev->n_norm = d->n_norm > 0 ? d->n_norm : (double)D.n_sub;
   ev->cut_delta = d->cut_delta;
   ev->topk_window = d->topk_window > 0 ? d->topk_window : 40.0;
+  ev->cut_target = d->cut_target > 0 ? d->cut_target : 1e-4;
   ev->top_k = std::max(0, d->top_k);
   ev->flags = d->flags;
   ev->KH = D.KH;
@@ -932,42 +935,40 @@ int dotpe_eval_lnl(dotpe_ctx* ctx, dotpe_event* ev, double* lnl, double* ml_max,
   return DOTPE_OK;
 }
 
-int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, dotpe_sample* topk) {
-  if (!ctx || !ev || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
-  HIP_OK(hipSetDevice(ctx->device));
+// One evidence pass with cut `cut_delta` (<= 0: none): pilot, fused pass,
+// fixed-order finalisation.  Fills *out except the top-k fields and returns
+// the raw candidate count in *n_cand.
+static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
+                         dotpe_evidence_result* out, uint64_t* n_cand) {
   hipStream_t s = ev->stream;
   FusedArgs a = make_args(ctx, ev);
+  a.cut_delta = cut_delta;
   int rc;
   a.state = ev->state;
   a.partials = ev->partials;
   a.cand = ev->cand;
   a.cand_cap = ev->cand_cap;
-  if (!ev->ev_t[0]) {
-    HIP_OK(hipEventCreate(&ev->ev_t[0]));
-    HIP_OK(hipEventCreate(&ev->ev_t[1]));
-    HIP_OK(hipEventCreate(&ev->ev_t[2]));
-  }
+  const bool timed = ev->ev_t[0] != nullptr;
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
-  HIP_OK(hipEventRecord(ev->ev_t[0], s));
-  int64_t r_rerun = 0;
-  if (ev->cut_delta > 0.0 && a.n_tiles_m > 1) {
-    // pilot: max lnL^ML over every 64th row of tiles seeds the cut threshold
-    // (the main pass raises it further as tiles complete)
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[0], s));
+  if (cut_delta > 0.0 && a.n_tiles_m > 1) {
+    // pilot: max lnL^ML over every 64th row of tiles sets the cut threshold,
+    // frozen before the main pass (so the cut does not depend on tile order)
     a.pilot_stride = 64;
     int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
     if ((rc = launch_fused<kPilot>(ev->bank->prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
   }
   hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, ev->state);
-  HIP_OK(hipEventRecord(ev->ev_t[1], s));
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[1], s));
   // the fast epilogue pays off when the frozen threshold cuts
   uint64_t thr_bits = 0;
-  if (ev->cut_delta > 0.0 && a.n_tiles_m > 1) {
+  if (cut_delta > 0.0 && a.n_tiles_m > 1) {
     HIP_OK(hipMemcpyAsync(&thr_bits, ev->state + 3, 8, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
   }
   double thr_frozen;
   std::memcpy(&thr_frozen, &thr_bits, 8);
-  const bool fast = ev->cut_delta > 0.0 && thr_frozen - ev->cut_delta > 0.0;
+  const bool fast = cut_delta > 0.0 && thr_frozen - cut_delta > 0.0;
   a.rerun = ev->rerun;
   a.rec_cap = (ev->flags & DOTPE_FLAG_RERUN_ALL) ? 0 : (1 << 30);
   int64_t grid = round_up(a.n_tiles, 8);
@@ -981,12 +982,10 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
       b.rerun_list = ev->rerun;
       if ((rc = launch_fused<kEvidence, false>(ev->bank->prec, b, (int64_t)n_rerun, s))) return rc;
     }
-    r_rerun = (int64_t)n_rerun;
-    (void)r_rerun;
   } else {
     if ((rc = launch_fused<kEvidence, false>(ev->bank->prec, a, grid, s))) return rc;
   }
-  HIP_OK(hipEventRecord(ev->ev_t[2], s));
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[2], s));
   {
     // fixed-order two-level reduction of the tile partials
     const int64_t per = 4096;
@@ -1019,47 +1018,92 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
   r.n_pairs = (int64_t)fo[10];
   r.dd = ev->dd;
   r.precision = ev->bank->prec;
-  float t_pilot = 0.f, t_main = 0.f;
-  HIP_OK(hipEventElapsedTime(&t_pilot, ev->ev_t[0], ev->ev_t[1]));
-  HIP_OK(hipEventElapsedTime(&t_main, ev->ev_t[1], ev->ev_t[2]));
-  r.t_pilot_ms = t_pilot;
-  r.t_fused_ms = t_main;
-  // top-k among candidates within the window of the final maximum
-  int64_t ncand = std::min<int64_t>((int64_t)st[2], ev->cand_cap);
+  r.cut_delta_used = cut_delta > 0.0 ? cut_delta : 0.0;
+  if (timed) {
+    float t_pilot = 0.f, t_main = 0.f;
+    HIP_OK(hipEventElapsedTime(&t_pilot, ev->ev_t[0], ev->ev_t[1]));
+    HIP_OK(hipEventElapsedTime(&t_main, ev->ev_t[1], ev->ev_t[2]));
+    r.t_pilot_ms = t_pilot;
+    r.t_fused_ms = t_main;
+  }
+  // no cut pair could have entered the top-k window
   const double thr = r.max_ln_p - ev->topk_window;
   r.topk_exact = ((int64_t)st[2] <= ev->cand_cap && !(fo[8] >= thr)) ? 1 : 0;
-  if (ev->top_k > 0 && topk && ncand > 0) {
-    int64_t n2 = 1;
-    while (n2 < ncand) n2 <<= 1;
-    // the candidate buffer is a power of two at least as long as ncand
-    if (n2 > ev->cand_cap) return fail(DOTPE_E_DEVICE, "top-k buffer too small");
-    double* buf = ev->cand;
-    if (n2 > ncand)
-      hipLaunchKernelGGL(k_fill_cand, dim3((unsigned)((n2 - ncand + 255) / 256)), dim3(256), 0, s,
-                         buf, ncand, n2);
-    for (int64_t k = 2; k <= n2; k <<= 1)
-      for (int64_t j = k >> 1; j > 0; j >>= 1)
-        hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, buf,
-                           n2, j, k);
-    int64_t take = std::min<int64_t>(ev->top_k, ncand);
-    std::vector<double> h(take * 4);
-    HIP_OK(hipMemcpyAsync(h.data(), buf, take * 32, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    int cnt = 0;
-    for (int64_t q = 0; q < take; ++q) {
-      if (!(h[4 * q] >= thr)) break;
-      topk[cnt].ln_p = h[4 * q];
-      topk[cnt].i = (int64_t)h[4 * q + 1];
-      topk[cnt].e = (int64_t)h[4 * q + 2];
-      topk[cnt].o_best = (int32_t)h[4 * q + 3];
-      topk[cnt].reserved = 0;
-      ++cnt;
-    }
-    r.topk_count = cnt;
+  *n_cand = st[2];
+  *out = r;
+  return DOTPE_OK;
+}
+
+// top-k among the candidates of the last pass within the window of the
+// final maximum: bitonic sort of the candidate buffer on the device
+static int evidence_topk(dotpe_event* ev, uint64_t n_cand_raw, dotpe_evidence_result* r,
+                         dotpe_sample* topk) {
+  hipStream_t s = ev->stream;
+  const int64_t ncand = std::min<int64_t>((int64_t)n_cand_raw, ev->cand_cap);
+  const double thr = r->max_ln_p - ev->topk_window;
+  r->topk_count = 0;
+  if (ev->top_k <= 0 || !topk || ncand <= 0) return DOTPE_OK;
+  int64_t n2 = 1;
+  while (n2 < ncand) n2 <<= 1;
+  // the candidate buffer is a power of two at least as long as ncand
+  if (n2 > ev->cand_cap) return fail(DOTPE_E_DEVICE, "top-k buffer too small");
+  double* buf = ev->cand;
+  if (n2 > ncand)
+    hipLaunchKernelGGL(k_fill_cand, dim3((unsigned)((n2 - ncand + 255) / 256)), dim3(256), 0, s,
+                       buf, ncand, n2);
+  for (int64_t k = 2; k <= n2; k <<= 1)
+    for (int64_t j = k >> 1; j > 0; j >>= 1)
+      hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, buf,
+                         n2, j, k);
+  const int64_t take = std::min<int64_t>(ev->top_k, ncand);
+  std::vector<double> h(take * 4);
+  HIP_OK(hipMemcpyAsync(h.data(), buf, take * 32, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  int cnt = 0;
+  for (int64_t q = 0; q < take; ++q) {
+    if (!(h[4 * q] >= thr)) break;
+    topk[cnt].ln_p = h[4 * q];
+    topk[cnt].i = (int64_t)h[4 * q + 1];
+    topk[cnt].e = (int64_t)h[4 * q + 2];
+    topk[cnt].o_best = (int32_t)h[4 * q + 3];
+    topk[cnt].reserved = 0;
+    ++cnt;
   }
+  r->topk_count = cnt;
+  return DOTPE_OK;
+}
+
+// passes with a growing cut_delta until the certificate meets the target
+static int evidence_run(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out,
+                        dotpe_sample* topk) {
+  double delta = ev->cut_delta;
+  dotpe_evidence_result r;
+  uint64_t n_cand = 0;
+  int passes = 0;
+  for (;;) {
+    int rc = evidence_pass(ctx, ev, delta, &r, &n_cand);
+    if (rc) return rc;
+    ++passes;
+    if (!(delta > 0.0) || r.ln_z_upper - r.ln_z <= ev->cut_target) break;
+    delta = passes < 3 ? delta + 20.0 : 0.0;    // cut less, finally not at all
+  }
+  r.n_passes = passes;
+  int rc = evidence_topk(ev, n_cand, &r, topk);
+  if (rc) return rc;
   r.status = DOTPE_OK;
   *out = r;
   return DOTPE_OK;
+}
+
+int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, dotpe_sample* topk) {
+  if (!ctx || !ev || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  HIP_OK(hipSetDevice(ctx->device));
+  if (!ev->ev_t[0]) {
+    HIP_OK(hipEventCreate(&ev->ev_t[0]));
+    HIP_OK(hipEventCreate(&ev->ev_t[1]));
+    HIP_OK(hipEventCreate(&ev->ev_t[2]));
+  }
+  return evidence_run(ctx, ev, out, topk);
 }
 
 int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const double* hh,

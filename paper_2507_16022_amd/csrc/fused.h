@@ -120,7 +120,7 @@ struct Tile {
   static constexpr int COLD_OFF = ROWD_OFF + TM * 4 * 8;           // double [TN][3]
   static constexpr int LIST_OFF = COLD_OFF + TN * 3 * 8;           // uint16 [BATCH]
   static constexpr int RED_OFF = (LIST_OFF + BATCH * 2 + 15) / 16 * 16;   // double [NW][kNPart]
-  static constexpr int CNT_OFF = RED_OFF + NW * kNPart * 8;        // int counter, u64 max
+  static constexpr int CNT_OFF = RED_OFF + NW * kNPart * 8;        // (spare), u64 tile max of ln p
   static constexpr int ROWQ_OFF = CNT_OFF + 16;                    // double [TM][2]
   static constexpr int MAIN_BYTES = ROWQ_OFF + TM * 2 * 8;
   // then the distance-rule parameters and the phase table
@@ -371,7 +371,6 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   double* rowd = (double*)(smem + TL::ROWD_OFF);
   double* cold = (double*)(smem + TL::COLD_OFF);
   uint16_t* list = (uint16_t*)(smem + TL::LIST_OFF);
-  int* list_n = (int*)(smem + TL::CNT_OFF);
 
   // per row for the E1 bound: row_scale^2 / ah_scale and ln w
   double* rowq = (double*)(smem + TL::ROWQ_OFF);
@@ -584,7 +583,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     } else if (tid < TM + TN) {
       cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
     }
-    if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
+    if (tid == 0) *tile_lnp_max = 0ull;
     __syncthreads();                              // rowd, cold, counters
     pipeline_barrier<LPC * (NS - 4)>();           // chunks 0, 1, 2 have landed
     read_frag(fr0, 0);
@@ -760,7 +759,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   } else if (tid < TM + TN) {
     cold[(tid - TM) * 3] = rv0; cold[(tid - TM) * 3 + 1] = rv1; cold[(tid - TM) * 3 + 2] = rv2;
   }
-  if (tid == 0) { *list_n = 0; *tile_lnp_max = 0ull; }
+  if (tid == 0) *tile_lnp_max = 0ull;
   store_from(set(std::integral_constant<int, 0>{}), buf_c);
   store_from(set(std::integral_constant<int, 1>{}), buf_r);
   if (R < nch) load(set(std::integral_constant<int, 0>{}), R);
@@ -891,25 +890,61 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     }
     return in && !bounded;
   };
-  // a survivor's record into LDS (slots past BATCH are counted but not written)
-  auto e1_record = [&](auto bmi, auto bni, auto ri) {
+  // a survivor's record into LDS slot `slot` (slots past BATCH are counted
+  // but not written)
+  auto e1_record = [&](auto bmi, auto bni, auto ri, int slot) {
     constexpr int bm = decltype(bmi)::value, bn = decltype(bni)::value, r = decltype(ri)::value;
     const int tc = wn * BS * P::BN + bn * BS + (lane & (BS - 1));
     const int tr = wm * BS * P::BM + bm * BS + rowmap(r);
-    {
-      int slot = atomicAdd(list_n, 1);
-      if (slot < TL::BATCH) {
-        AT* rec = recs + slot * TL::REC;
+    if (slot < TL::BATCH) {
+      AT* rec = recs + slot * TL::REC;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          rec[XO + 2 * g] = (AT)acc[g][bm][bn][0][r];
-          rec[XO + 2 * g + 1] = (AT)acc[g][bm][bn][1][r];
-        }
-#pragma unroll
-        for (int q = 0; q < NRT; ++q) rec[SO + q] = (AT)acch[q][bm][bn][r];
-        list[slot] = (uint16_t)((tr << 8) | tc);
+      for (int g = 0; g < G; ++g) {
+        rec[XO + 2 * g] = (AT)acc[g][bm][bn][0][r];
+        rec[XO + 2 * g + 1] = (AT)acc[g][bm][bn][1][r];
       }
+#pragma unroll
+      for (int q = 0; q < NRT; ++q) rec[SO + q] = (AT)acch[q][bm][bn][r];
+      list[slot] = (uint16_t)((tr << 8) | tc);
     }
+  };
+  // Survivor slots in a fixed order -- wave by wave, within a wave by
+  // element (bit of `mask`) then lane -- so that which lane evaluates which
+  // survivor, and with it the order of every floating-point sum, does not
+  // depend on timing.  slot_base returns this wave's first slot and the
+  // tile's total (one barrier; the per-wave counts use the tile-reduction
+  // area, which is free until the end); record_all then hands bit k of each
+  // lane its slot.
+  int* wcnt = (int*)(smem + TL::RED_OFF);
+  auto slot_base = [&](unsigned mask, auto nbits, int& total) -> int {
+    constexpr int NB = decltype(nbits)::value;
+    int cnt = 0;
+    static_for<NB>([&](auto ki) {
+      cnt += (int)__popcll(__ballot((mask >> decltype(ki)::value) & 1u));
+    });
+    if (lane == 0) wcnt[wave] = cnt;
+    __syncthreads();
+    int base = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const int c = wcnt[w];
+      base += w < wave ? c : 0;
+      total += c;
+    }
+    return base;
+  };
+  auto record_all = [&](unsigned mask, int base, auto nbits, auto&& rec_k) {
+    constexpr int NB = decltype(nbits)::value;
+    int run = base;
+    static_for<NB>([&](auto ki) {
+      constexpr int k = decltype(ki)::value;
+      const unsigned long long b = __ballot((mask >> k) & 1u);
+      if ((mask >> k) & 1u)
+        rec_k(ki, run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u)));
+      run += (int)__popcll(b);
+    });
   };
   // E2: the survivors' full evaluation.  With few survivors the phases of
   // one survivor are spread over a group of 32 lanes (phase o on lane o mod
@@ -1005,16 +1040,16 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
         });
       });
     });
-    static_for<P::BM>([&](auto bmi) {
-      static_for<P::BN>([&](auto bni) {
-        static_for<NE>([&](auto ri) {
-          constexpr int k = (decltype(bmi)::value * P::BN + decltype(bni)::value) * NE + decltype(ri)::value;
-          if (sm & (1u << k)) e1_record(bmi, bni, ri);
-        });
-      });
+    constexpr int NK = P::BM * P::BN * NE;
+    int nsurv = 0;
+    const int base = slot_base(sm, std::integral_constant<int, NK>{}, nsurv);
+    record_all(sm, base, std::integral_constant<int, NK>{}, [&](auto ki, int slot) {
+      constexpr int k = decltype(ki)::value;
+      e1_record(std::integral_constant<int, k / NE / P::BN>{},
+                std::integral_constant<int, k / NE % P::BN>{}, std::integral_constant<int, k % NE>{},
+                slot);
     });
     __syncthreads();
-    const int nsurv = *list_n;
     if (nsurv > min(a.rec_cap, TL::BATCH)) {
       if (tid == 0) {
         unsigned long long k = atomicAdd((unsigned long long*)&a.state[4], 1ull);
@@ -1027,21 +1062,30 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     // batches of EPB pairs per lane (at most BATCH survivors each)
     constexpr int EPB = TL::EPB;
     static_assert(NE % EPB == 0 || EPB % NE == 0, "batch split");
+    static_assert(EPB <= 32, "survivor mask");
     static_for<P::BM * P::BN * NE / EPB>([&](auto bi) {
-      static_for<EPB>([&](auto ri) {
-        // element k of this lane in (block, element) order
-        constexpr int k = decltype(bi)::value * EPB + decltype(ri)::value;
+      constexpr int k0 = decltype(bi)::value * EPB;
+      // element k0 + q of this lane in (block, element) order
+      unsigned sm = 0;
+      static_for<EPB>([&](auto qi) {
+        constexpr int k = k0 + decltype(qi)::value;
         const auto bmi = std::integral_constant<int, k / NE / P::BN>{};
         const auto bni = std::integral_constant<int, k / NE % P::BN>{};
         const auto rr = std::integral_constant<int, k % NE>{};
         const bool surv = use_bound ? e1_bound(bmi, bni, rr, std::true_type{})
                                     : e1_bound(bmi, bni, rr, std::false_type{});
-        if (surv) e1_record(bmi, bni, rr);
+        if (surv) sm |= 1u << decltype(qi)::value;
+      });
+      int nsurv = 0;
+      const int base = slot_base(sm, std::integral_constant<int, EPB>{}, nsurv);
+      record_all(sm, base, std::integral_constant<int, EPB>{}, [&](auto qi, int slot) {
+        constexpr int k = k0 + decltype(qi)::value;
+        e1_record(std::integral_constant<int, k / NE / P::BN>{},
+                  std::integral_constant<int, k / NE % P::BN>{},
+                  std::integral_constant<int, k % NE>{}, slot);
       });
       __syncthreads();
-      e2_list(*list_n);
-      __syncthreads();
-      if (tid == 0) *list_n = 0;
+      e2_list(min(nsurv, TL::BATCH));
       __syncthreads();
     });
   }

@@ -53,7 +53,7 @@ class EventDesc(ctypes.Structure):
                 ("sub_idx", ctypes.c_void_p),
                 ("cut_delta", ctypes.c_double), ("top_k", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("topk_window", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("cut_target", ctypes.c_double)]
 
 
 class EvidenceResult(ctypes.Structure):
@@ -65,7 +65,8 @@ class EvidenceResult(ctypes.Structure):
                 ("n_triples_marg", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("topk_count", ctypes.c_int32), ("topk_exact", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("t_pilot_ms", ctypes.c_double),
-                ("t_fused_ms", ctypes.c_double)]
+                ("t_fused_ms", ctypes.c_double), ("cut_delta_used", ctypes.c_double),
+                ("n_passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -111,6 +112,10 @@ SYMBOLS = {
     "dotpe_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]),
     "dotpe_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(EvidenceResult),
                                    ctypes.c_void_p, ctypes.POINTER(TicketInfo)]),
+}
+
+# include/dotpe_test.h: hooks the parity tests use to check single steps
+TEST_SYMBOLS = {
     "dotpe_debug_distmarg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "dotpe_debug_response": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -129,7 +134,7 @@ def load_library(path=LIB_PATH):
         raise RuntimeError(f"{path} not found: build it with __graft_entry__.build() "
                            "(python paper_2507_16022_amd/build.py)")
     lib = ctypes.CDLL(path)
-    for name, (res, args) in SYMBOLS.items():
+    for name, (res, args) in list(SYMBOLS.items()) + list(TEST_SYMBOLS.items()):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
@@ -260,7 +265,7 @@ FLAG_RERUN_ALL = 1
 
 def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=1.0, n_norm=0.0,
                 sub_start=0, sub_count=0, sub_idx=None, cut_delta=0.0, top_k=0, topk_window=40.0,
-                stream=None, flags=0):
+                stream=None, flags=0, cut_target=0.0):
     """EventDesc over host copies of the inputs; returns (desc, arrays to keep alive)."""
     keep = []
 
@@ -289,7 +294,7 @@ def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=
     desc = EventDesc(dc.shape[0], int(n_phi), pd, pw, pr, pD, n_ext, plat, plon, ppsi, pci, ptg,
                      plw, float(d_max), float(d0), float(n_norm), int(sub_start),
                      int(sub_count), psub, float(cut_delta), int(top_k), int(flags),
-                     float(topk_window), stream)
+                     float(topk_window), stream, float(cut_target))
     return desc, keep
 
 

@@ -166,6 +166,22 @@ def waveform_modes(f, mc, q, chi, modes, xp=np, d0_mpc=1.0):
     return xp.stack(out, axis=1)
 
 
+def bank_on_device(torch, mc, q, chi, f, modes, chunk=32768):
+    """The bank of waveform_modes built on the GPU with torch in float64, as a
+    [N, N_c, N_b, 2] tensor (interleaved complex), chunk by chunk: banks of
+    the large workloads are generated where they are used."""
+    n = len(mc)
+    out = torch.empty((n, len(modes), len(f), 2), dtype=torch.float64, device="cuda")
+    ft = torch.as_tensor(np.asarray(f), dtype=torch.float64, device="cuda")
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        args = [torch.as_tensor(np.asarray(x[s:e]), dtype=torch.float64, device="cuda")
+                for x in (mc, q, chi)]
+        out[s:e] = torch.view_as_real(waveform_modes(ft, *args, modes, xp=torch))
+    torch.cuda.synchronize()
+    return out
+
+
 # --------------------------------------------------------------------------
 # extrinsic samples
 # --------------------------------------------------------------------------

@@ -9,8 +9,8 @@ from paper_2507_16022_amd import dotpe
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    src = open(os.path.join(ROOT, "include", "dotpe.h")).read()
+def declared_symbols(header="dotpe.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(dotpe_[a-z_0-9]+)\s*\(", src)))
 
@@ -19,9 +19,11 @@ def test_header_symbols_exported():
     lib = ctypes.CDLL(dotpe.LIB_PATH)
     names = declared_symbols()
     assert len(names) >= 12
-    for n in names:
+    test_names = declared_symbols("dotpe_test.h")
+    for n in names + test_names:
         assert hasattr(lib, n), n
     assert set(names) == set(dotpe.SYMBOLS), "binding and header disagree"
+    assert set(test_names) == set(dotpe.TEST_SYMBOLS), "binding and test header disagree"
 
 
 def test_version_and_error_string():
@@ -34,7 +36,7 @@ def test_struct_layouts():
     # sizes must match the C structs (checked against hand-computed layouts)
     assert ctypes.sizeof(dotpe.BankDesc) == 8 + 4 + 4 + 5 * 8 + 4 + 4
     assert ctypes.sizeof(dotpe.Sample) == 32
-    assert ctypes.sizeof(dotpe.EvidenceResult) == 7 * 8 + 3 * 8 + 4 * 4 + 2 * 8
+    assert ctypes.sizeof(dotpe.EvidenceResult) == 7 * 8 + 3 * 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4
 
 
 STRUCTS = {

@@ -39,7 +39,7 @@ def test_distance_rule_vs_oracle(ctx):
     rng = np.random.default_rng(0)
     dmax = 5000.0
     # (z, s) over the range met by the workloads: template SNR at D_max from
-    # 1e-4 to 20, projected data SNR from -10 to 60, peaks resolved by the oracle
+    # 1e-4 to 20, projected data SNR from -10 to 60
     s = np.exp(rng.uniform(np.log(1e-4), np.log(20.0), 4000))
     z = rng.uniform(-10, 60, 4000)
     # the oracle's 2000 Gauss-Legendre nodes resolve a peak at D* = D_max s/z
@@ -47,14 +47,19 @@ def test_distance_rule_vs_oracle(ctx):
     dstar = dmax * s / np.maximum(z, 1e-9)
     spacing = np.pi / 2000 * np.sqrt(np.clip(dstar * (dmax - dstar), 1.0, None))
     keep = (z < 4) | ((dstar / np.maximum(z, 1e-9) >= 2 * spacing) & (dstar < dmax))
-    s, z = s[keep], z[keep]
     hh = (s * dmax) ** 2
     dh = z * np.sqrt(hh)
     got = ctx.distmarg(dh, hh, 1.0 / dmax)
-    ref = O.ln_dist_marg(dh, hh, dmax, 1.0, 2000)
-    err = np.abs(got - ref)
-    print("distance rule: max err", err.max(), "n", len(z), flush=True)
+    ref = O.ln_dist_marg(dh[keep], hh[keep], dmax, 1.0, 2000)
+    err = np.abs(got[keep] - ref)
+    print("distance rule, resolved peaks: max err", err.max(), "n", int(keep.sum()), flush=True)
     assert err.max() < 5e-7
+    # peaks too sharp for the fixed rule: against the adaptive-quadrature oracle
+    sharp = np.flatnonzero(~keep)[:400]
+    ref_s = O.ln_dist_marg_adaptive(dh[sharp], hh[sharp], dmax, 1.0)
+    err_s = np.abs(got[sharp] - ref_s)
+    print("distance rule, sharp peaks: max err", err_s.max(), "n", len(sharp), flush=True)
+    assert len(sharp) >= 100 and err_s.max() < 5e-7
     assert ctx.distmarg([0.0], [0.0], 1e-3)[0] == 0.0
 
 
@@ -123,9 +128,21 @@ def test_evidence_fp64_no_cut(ctx, window):
     assert np.allclose(r["topk_lnp"], ref["topk_lnp"][:n_exp], atol=TOL_FP64)
 
 
-@pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
-@pytest.mark.parametrize("snr", [8.0, 20.0, 50.0])
+# BF16 hi+lo keeps about 16 significant bits per operand, so the coherent
+# worst case of the representation error is ~2^-16 rho^2 in lnL: 1e-3 is met
+# at SNR 8 and missed above it (measured max |d lnLbar| 1.6e-3 at SNR 20 and
+# 1.1e-2 at SNR 50 on this event).  Those cases are expected failures.
+_BF16_MISS = pytest.mark.xfail(strict=True, reason="BF16 hi+lo misses 1e-3 above SNR ~15 "
+                               "(measured 1.6e-3 at SNR 20, 1.1e-2 at SNR 50)")
+
+
+@pytest.mark.parametrize("prec,snr", [("fp16x2", 8.0), ("fp16x2", 20.0), ("fp16x2", 50.0),
+                                      ("bf16x2", 8.0),
+                                      pytest.param("bf16x2", 20.0, marks=_BF16_MISS),
+                                      pytest.param("bf16x2", 50.0, marks=_BF16_MISS)])
 def test_eval_mixed_tiny(ctx, prec, snr):
+    """Split precisions against the oracle on every pair: |d ln Lbar| <= 1e-3
+    and |d ln Z| <= 1e-3 (the stated tolerance of the mixed path)."""
     wl = W.config_tiny(seed=2, n_int=64, n_ext=96, snr=snr)
     bank, ev = make_event(ctx, wl, precision=prec)
     got = ev.eval_lnl()["lnl"]
@@ -135,14 +152,8 @@ def test_eval_mixed_tiny(ctx, prec, snr):
     zr = O.evidence_from_lnl(ref, wl.ln_w_int, wl.ln_w_ext)["ln_z"]
     print(f"{prec} snr {snr}: max |d lnLbar| = {err.max():.3e}, |d lnZ| = {abs(zg - zr):.3e}",
           flush=True)
-    if prec == "fp16x2":
-        assert err.max() <= TOL_MIXED
-        assert abs(zg - zr) <= TOL_MIXED
-    else:
-        # BF16 hi+lo keeps ~16 significant bits per operand: the coherent worst case of the
-        # representation error is ~2^-16 rho^2 in lnL, so 1e-3 is out of reach at high SNR;
-        # hold it to twice that bound
-        assert err.max() <= 2.0 ** -15 * snr ** 2
+    assert err.max() <= TOL_MIXED
+    assert abs(zg - zr) <= TOL_MIXED
 
 
 def test_eval_mixed_higher_modes(ctx):
@@ -244,23 +255,55 @@ def test_invalid_inputs_rejected(ctx):
     assert e.value.code in (dotpe.E_ADMISSION, dotpe.E_OOM)
 
 
-def test_mixed_higher_modes_snr50_vs_fp64(ctx):
+@pytest.mark.parametrize("prec", ["fp16x2", pytest.param("bf16x2", marks=_BF16_MISS)])
+def test_mixed_higher_modes_snr50_vs_fp64(ctx, prec):
     """Split precision at the 5-mode shape and SNR 50: every pair within 1e-3
-    of the FP64 path and of the oracle."""
+    of the FP64 path and of the oracle, and ln Z within 1e-3."""
     wl = W.config_production(seed=9, n_int=96, n_ext=64, snr=50.0)
     b64, e64 = make_event(ctx, wl, precision="fp64")
     l64 = e64.eval_lnl()["lnl"]
     ref = O.eval_pairs_block(wl, np.arange(wl.n_int))["lnl"]
     assert np.max(np.abs(l64 - ref)) < TOL_FP64
-    for prec in ("fp16x2", "bf16x2"):
-        b, e = make_event(ctx, wl, precision=prec)
-        l = e.eval_lnl()["lnl"]
-        err = np.abs(l - l64)
-        top = l64 >= np.max(l64) - 20
-        print(f"{prec} snr50 hm: max |d lnLbar| all {err.max():.3e}, near max {err[top].max():.3e}",
-              flush=True)
-        if prec == "fp16x2":
-            assert err.max() <= TOL_MIXED
+    b, e = make_event(ctx, wl, precision=prec)
+    l = e.eval_lnl()["lnl"]
+    err = np.abs(l - l64)
+    top = l64 >= np.max(l64) - 20
+    zg = O.evidence_from_lnl(l, wl.ln_w_int, wl.ln_w_ext)["ln_z"]
+    zr = O.evidence_from_lnl(ref, wl.ln_w_int, wl.ln_w_ext)["ln_z"]
+    print(f"{prec} snr50 hm: max |d lnLbar| all {err.max():.3e}, near max {err[top].max():.3e}, "
+          f"|d lnZ| {abs(zg - zr):.3e}", flush=True)
+    assert err.max() <= TOL_MIXED
+    assert np.max(np.abs(l - ref)) <= TOL_MIXED
+    assert abs(zg - zr) <= TOL_MIXED
+
+
+def test_device_memory_bank_and_outputs(ctx):
+    """A bank handed over in device memory (DOTPE_MEM_DEVICE) and ln Lbar
+    written straight to device memory give the oracle's values."""
+    import torch
+    wl = W.config_production(seed=12, n_int=70, n_ext=50, snr=20.0, random_weights=True)
+    h = torch.view_as_real(torch.as_tensor(wl.h)).contiguous().cuda()
+    lw = torch.as_tensor(wl.ln_w_int).cuda()
+    ref = O.eval_pairs_block(wl, np.arange(wl.n_int))
+    for prec, tol in (("fp64", TOL_FP64), ("fp16x2", TOL_MIXED)):
+        bank = ctx.load_bank(h, wl.modes, wl.f, lw, precision=prec)
+        ev = ctx.set_event(bank, d=wl.d, w=wl.w, det_r=wl.det_r, det_D=wl.det_D, ext=wl.ext,
+                           n_phi=wl.n_phi, ln_w_ext=wl.ln_w_ext, d_max=wl.d_max, d0=wl.d0, top_k=4)
+        out = torch.full((wl.n_int, wl.n_ext), float("nan"), dtype=torch.float64, device="cuda")
+        ml = torch.full_like(out, float("nan"))
+        ev.eval_lnl_device(out, ml)
+        torch.cuda.synchronize()
+        err = np.max(np.abs(out.cpu().numpy() - ref["lnl"]))
+        print(f"device bank {prec}: max |d lnLbar| = {err:.3e}", flush=True)
+        assert err < tol
+        assert np.allclose(ml.cpu().numpy(), ref["ml_max"], rtol=1e-6 if prec == "fp64" else 1e-3,
+                           atol=1e-6)
+        # the bank weights travelled with the device bank: ln Z as the oracle's
+        r = ev.evidence()
+        z = O.evidence_from_lnl(ref["lnl"], wl.ln_w_int, wl.ln_w_ext)["ln_z"]
+        assert abs(r["ln_z"] - z) < tol
+        ev.close()
+        bank.close()
 
 
 def test_evidence_rerun_route_agrees(ctx):

@@ -329,3 +329,56 @@ def test_zero_template_is_prior():
     """A template that vanishes in band (hh = 0) gives Lbar = 1."""
     assert float(O.ln_dist_marg(0.0, 0.0, 5000.0)) == pytest.approx(0.0, abs=1e-14)
     assert float(O.lnl_ml(0.0, 0.0)) == 0.0
+
+
+# ------------------------------------------------------- P3 / P5 (sharp) ------
+def test_adaptive_distance_rule_pins():
+    """The adaptive-quadrature form of eq. (lnl_dist_marginalized), used
+    where a fixed node set cannot resolve the peak, is pinned three ways:
+    it equals the 2000-node Gauss-Legendre rule where that resolves the peak; with d = 0 it equals the closed form
+    e^{-x0^2}(1 - 2 x0^2) + 2 sqrt(pi) x0^3 erfc(x0), x0 = (d0/D_max) sqrt(hh/2);
+    and for sharp interior peaks it follows Laplace's expansion in
+    u = d0/D: with z = dh/sqrt(hh) and u* = dh/hh, the u^-4 factor of the
+    integrand averages to u*^-4 (1 + 10/z^2 + 105/z^4 + O(z^-6)) over the
+    Gaussian peak of width u*/z."""
+    dmax, d0 = 5000.0, 1.0
+    for z, s in [(0.0, 1.0), (3.0, 2.0), (10.0, 5.0), (20.0, 3.0), (-5.0, 1.0), (0.5, 1e-3),
+                 (40.0, 20.0), (8.0, 0.3)]:
+        hh = (s * dmax / d0) ** 2
+        dh = z * math.sqrt(hh)
+        a = float(O.ln_dist_marg_adaptive(dh, hh, dmax, d0))
+        assert a == pytest.approx(float(O.ln_dist_marg(dh, hh, dmax, d0, 2000)), abs=1e-10)
+    # (the closed form cancels between its two terms as x0 grows: ~1e-11 at x0 = 20)
+    for hh, tol in ((1e-2, 1e-12), (1.0, 1e-12), (1e4, 1e-12), ((2.0 * dmax) ** 2, 1e-11),
+                    ((30.0 * dmax) ** 2, 1e-9)):
+        x0 = (d0 / dmax) * math.sqrt(hh / 2.0)
+        closed = math.exp(-x0 * x0) * ((1 - 2 * x0 * x0) + 2 * math.sqrt(math.pi) * x0 ** 3 * special.erfcx(x0))
+        assert float(O.ln_dist_marg_adaptive(0.0, hh, dmax, d0)) == pytest.approx(math.log(closed), abs=tol)
+    for z, dstar in [(30.0, 500.0), (60.0, 2.0), (60.0, 0.01), (200.0, 1000.0), (2000.0, 40.0)]:
+        hh = (z * dstar / d0) ** 2          # peak at D* = d0 hh / dh
+        dh = z * math.sqrt(hh)
+        sig = dstar ** 2 / (d0 * math.sqrt(hh))
+        lap = dh * dh / (2 * hh) + math.log(3 * dstar ** 2 / dmax ** 3 * math.sqrt(2 * math.pi) * sig)
+        series = lap + math.log1p(10.0 / z ** 2 + 105.0 / z ** 4)
+        got = float(O.ln_dist_marg_adaptive(dh, hh, dmax, d0))
+        assert abs(got - series) < 2e3 / z ** 6 + 1e-11 * abs(got), (z, dstar, got - series)
+    # a peak far narrower than the 2000-node spacing near D = 0: the fixed
+    # rule is off by order one there, the adaptive one follows Laplace
+    hh = (60.0 * 0.01) ** 2
+    dh = 60.0 * math.sqrt(hh)
+    assert abs(float(O.ln_dist_marg(dh, hh, dmax, d0, 2000)) - float(O.ln_dist_marg_adaptive(dh, hh, dmax, d0))) > 0.1
+
+
+def test_eval_lnl_multiprocess_equals_single():
+    """The oracle's multi-process split over bank rows returns the rows in
+    order and bit-identical values (every row is computed by the same code
+    on the same inputs, whichever process takes it)."""
+    wl = W.config_production(seed=21, n_int=13, n_ext=24, n_bins=64, random_weights=True)
+    one = O.eval_lnl(wl, processes=1)
+    two = O.eval_lnl(wl, processes=2)
+    assert np.array_equal(one["lnl"], two["lnl"])
+    assert np.array_equal(one["ml_max"], two["ml_max"])
+    # and the rows are in bank order: row i equals a one-row evaluation of row i
+    for i in (0, 6, 12):
+        r = O.eval_pairs_block(wl, [i])
+        assert np.array_equal(r["lnl"][0], one["lnl"][i])
