@@ -204,6 +204,24 @@ typedef struct dotpe_sample {
 int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out,
                    dotpe_sample* topk);
 
+/* dotpe_set_event + dotpe_evidence + dotpe_free_event in one call that
+ * allocates no device memory (no hipMalloc / hipFree, no allocating library
+ * routine): for callers that cannot allocate -- code that runs under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Every buffer of the event is packed into a fixed device scratch array of
+ * 128 MiB that the library holds on each GPU it runs on until the process
+ * ends; events whose footprint (dotpe_event_bytes) exceeds it are rejected
+ * with TOO_LARGE.  The caller passes the inputs (desc, host arrays) and the
+ * outputs (out, topk [desc.top_k] host array or NULL) as for
+ * dotpe_evidence; t_pilot_ms and t_fused_ms are 0 (no timing events).  All
+ * calls on one GPU share its scratch, which keeps the last call's contents
+ * (everything that must start at zero is cleared by the call itself); the
+ * library serialises such calls within a process, so calls that overlap on
+ * one GPU wait for each other.  Synchronous.  Errors: INVALID_ARG, NUMERIC,
+ * TOO_LARGE, UNIMPLEMENTED (device without scratch), DEVICE. */
+int dotpe_evidence_static(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_event_desc* desc,
+                          dotpe_evidence_result* out, dotpe_sample* topk);
+
 /* Device bytes one event needs: every buffer dotpe_set_event and
  * dotpe_evidence use for it, packed in one block (the admission footprint of
  * the serving calls).  Validates the description like dotpe_set_event.

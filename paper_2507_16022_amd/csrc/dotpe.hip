@@ -50,6 +50,42 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 }  // namespace
 
+// Device scratch of dotpe_evidence_static: every buffer of one event packed
+// into one file-scope array, so that the call allocates no device memory.
+// Each GPU holds its own copy until the process ends.  In host code the
+// array's name is only a handle: the device address of each GPU's copy is
+// taken once per device (scratch_setup, from dotpe_create) and used instead.
+constexpr uint64_t kScratchBytes = uint64_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+struct ScratchSlot {
+  std::mutex mu;            // held for a whole dotpe_evidence_static call
+  void* ptr = nullptr;      // device address of this GPU's copy of `scratch`
+};
+ScratchSlot g_scratch[kScratchDevices];
+std::mutex g_scratch_setup;
+
+// with `device` current: record the device address of its copy of scratch
+int scratch_setup(int device) {
+  if (device >= kScratchDevices) return DOTPE_OK;   // static entry point unavailable there
+  std::lock_guard<std::mutex> lk(g_scratch_setup);
+  if (g_scratch[device].ptr) return DOTPE_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(DOTPE_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                hipGetErrorString(e));
+  }
+  g_scratch[device].ptr = p;
+  return DOTPE_OK;
+}
+
+}  // namespace
+
 struct dotpe_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -411,6 +447,10 @@ int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
   HIP_OK(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(DOTPE_E_INVALID_ARG, "device %d of %d", device, n);
   HIP_OK(hipSetDevice(device));
+  {
+    int rc0 = scratch_setup(device);
+    if (rc0) return rc0;
+  }
   dotpe_ctx* ctx = new dotpe_ctx();
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
@@ -1104,6 +1144,40 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
     HIP_OK(hipEventCreate(&ev->ev_t[2]));
   }
   return evidence_run(ctx, ev, out, topk);
+}
+
+int dotpe_evidence_static(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d,
+                          dotpe_evidence_result* out, dotpe_sample* topk) {
+  if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (ctx->device >= kScratchDevices || !g_scratch[ctx->device].ptr)
+    return fail(DOTPE_E_UNIMPLEMENTED, "no device scratch on device %d", ctx->device);
+  EvDims D;
+  std::vector<int> terms;
+  int rc = event_dims(bk, d, &D, &terms);
+  if (rc) return rc;
+  uint64_t need;
+  {
+    dotpe_event probe;
+    EvStage st;
+    need = block_bytes(event_buffers(D, &probe, &st));
+  }
+  if (need > kScratchBytes)
+    return fail(DOTPE_E_TOO_LARGE,
+                "event needs %llu bytes of device scratch; dotpe_evidence_static holds %llu",
+                (unsigned long long)need, (unsigned long long)kScratchBytes);
+  HIP_OK(hipSetDevice(ctx->device));
+  ScratchSlot& slot = g_scratch[ctx->device];
+  std::lock_guard<std::mutex> lk(slot.mu);
+  dotpe_event* ev = nullptr;
+  rc = set_event_impl(ctx, bk, d, (char*)slot.ptr, kScratchBytes,
+                      d->stream ? (hipStream_t)d->stream : ctx->stream, &ev);
+  if (rc) return rc;
+  dotpe_evidence_result r;
+  rc = evidence_run(ctx, ev, &r, topk);     // untimed: the event has no HIP events
+  dotpe_free_event(ctx, ev);                // frees nothing: every buffer is in the scratch
+  if (rc) return rc;
+  *out = r;
+  return DOTPE_OK;
 }
 
 int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const double* hh,

@@ -101,6 +101,9 @@ SYMBOLS = {
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "dotpe_evidence": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.POINTER(EvidenceResult), ctypes.c_void_p]),
+    "dotpe_evidence_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(EventDesc),
+                                              ctypes.POINTER(EvidenceResult), ctypes.c_void_p]),
     "dotpe_event_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(EventDesc),
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "dotpe_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
@@ -195,6 +198,18 @@ class Context:
 
     def set_event(self, bank, **kw):
         return Event(self, bank, **kw)
+
+    def evidence_static(self, bank, **kw):
+        """dotpe_evidence_static: stage and evaluate one event in the library's fixed device
+        scratch, allocating no device memory (same keywords as set_event)."""
+        desc, keep = _event_desc(**kw)
+        r = EvidenceResult()
+        k = desc.top_k
+        arr = (Sample * max(k, 1))()
+        _check(load_library().dotpe_evidence_static(
+            self._h, bank.handle, ctypes.byref(desc), ctypes.byref(r),
+            ctypes.cast(arr, ctypes.c_void_p) if k else None))
+        return _result(r, arr)
 
     def distmarg(self, dh, hh, r0):
         dh, pdh = _host(dh)
