@@ -322,6 +322,7 @@ def main():
     r = res[-1]
     n_pairs = n_int * n_ext
     fused_ms = float(np.mean([x["t_fused_ms"] for x in res]))
+    main_ms = float(np.mean([x["t_main_ms"] for x in res]))
     pilot_ms = float(np.mean([x["t_pilot_ms"] for x in res]))
     alg_flops = 8.0 * len(modes) * 256 * n_pairs          # (d|h) contraction, detector-folded
     achieved = alg_flops / (fused_ms * 1e-3) / 1e12
@@ -334,7 +335,9 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     log(f"step {dt * 1e3:.1f} ms, fused {fused_ms:.1f} ms, pilot {pilot_ms:.1f} ms, "
         f"ln Z {r['ln_z']:.6f} (upper {r['ln_z_upper']:.6f}), bounded pairs "
-        f"{r['n_pairs_bounded']}/{r['n_pairs']}, triples marginalised {r['n_triples_marg']}")
+        f"{r['n_pairs_bounded']}/{r['n_pairs']}, triples marginalised {r['n_triples_marg']}, "
+        f"main kernel {main_ms:.1f} ms, tiles to the second pass {r['n_tiles_rerun']}, "
+        f"tiles with listed survivors {r['n_tiles_listed']}")
 
     # parity at the full shape: the fused pass's best pairs one by one against the oracle,
     # and random pairs (half in rows past the 2^31-element operand offset) through the

@@ -62,6 +62,13 @@ extern "C" {
  * batched pass.  DOTPE_FLAG_RERUN_ALL sends every tile with a survivor
  * through that second pass (a check that both routes agree; slower). */
 #define DOTPE_FLAG_RERUN_ALL 1
+/* With a cut, split-precision events of at least 2048 tiles of 128 x 128
+ * pairs first run a bound pass: it only bounds every pair (the contraction
+ * without the per-pair marginalisation, at half the operand traffic per pair)
+ * and lists each 64 x 64 tile with a surviving pair for the second, batched
+ * pass.  DOTPE_FLAG_NO_BOUND_PASS uses the fused kernel's bound-then-evaluate
+ * epilogue instead (results agree to rounding). */
+#define DOTPE_FLAG_NO_BOUND_PASS 2
 
 /* where a caller pointer lives */
 #define DOTPE_MEM_HOST 0
@@ -140,7 +147,7 @@ typedef struct dotpe_event_desc {
                                are bounded (their mass goes to ln_z_upper), not
                                marginalised; <= 0 disables the cut */
   int32_t top_k;            /* number of top pairs to return from dotpe_evidence */
-  int32_t flags;            /* 0, or DOTPE_FLAG_RERUN_ALL */
+  int32_t flags;            /* 0, or DOTPE_FLAG_* bits */
   double topk_window;       /* candidates kept within this of the max ln p (default 40 if <= 0) */
   void* stream;             /* hipStream_t for this event's work; NULL = context stream */
   double cut_target;        /* certificate the cut must meet: ln_z_upper - ln_z <= cut_target
@@ -183,9 +190,14 @@ typedef struct dotpe_evidence_result {
   int32_t topk_exact;       /* 1 if no cut pair could have entered the top-k window */
   int32_t status;
   double t_pilot_ms;        /* device time of the threshold pilot pass (HIP events) */
-  double t_fused_ms;        /* device time of the fused pass (HIP events) */
+  double t_fused_ms;        /* device time from the end of the pilot to the end of the
+                               main pass, second pass included (HIP events) */
   double cut_delta_used;    /* cut_delta of the pass returned (0: no cut) */
   int32_t n_passes;         /* evidence passes run to meet cut_target */
+  int32_t n_tiles_rerun;    /* 64 x 64 tiles evaluated by the second, batched pass */
+  double t_main_ms;         /* device time of the main pass's first kernel alone: the
+                               bound pass, or the fused kernel (HIP events) */
+  int32_t n_tiles_listed;   /* 64 x 64 tiles whose few survivors the bound pass listed */
   int32_t reserved;
 } dotpe_evidence_result;
 

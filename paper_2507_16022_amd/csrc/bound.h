@@ -1,0 +1,633 @@
+// Bound pass of the evidence with the coherent cut (split precisions).
+//
+// Every pair's certified upper bound on lnL^ML (eq. bestfit_lnl) is
+//     bound = (sx^2 / sh) U0^2 / (2 lo0),  U0 = sum_g |X_g|,
+//     lo0 = S0 - 2 sum_{delta > 0} |S_delta|  (<= hh_o for every phase o),
+// the same quantity the fused kernel's first epilogue step uses.  This
+// kernel computes only that: the (h|h) phase coefficients first, folded
+// into lo0 as each output completes, then the (d|h) contraction one m group
+// at a time, each group's |X_g| added into U0 as the group completes.  So
+// a wave keeps lo0, U0 and one group's accumulators -- 64 x 64 pairs per
+// wave instead of the fused kernel's 32 x 32 -- and a 128 x 128 tile reads
+// half the operand bytes per pair from L2 and LDS.
+//
+// Each wave's 64 x 64 quadrant is one tile of the fused kernel's grid.  A
+// quadrant all of whose pairs are bounded writes that tile's partial (the
+// bounded mass and counts); a quadrant with any surviving pair is listed,
+// and the fused kernel's batched epilogue evaluates the whole tile again.
+#pragma once
+
+#include "fused.h"
+
+namespace dotpe {
+
+struct BoundTile {
+  static constexpr int NT = 256;           // 4 waves, one per SIMD
+  static constexpr int TS = 128;           // rows and columns per tile
+  static constexpr int NS = 4;             // LDS stages
+  static constexpr int ARR = 8192;         // bytes of one operand array per stage
+  static constexpr int STAGE = 4 * ARR;    // A hi, A lo, B hi, B lo
+  static constexpr int ROWQ_OFF = NS * STAGE;            // double2 [128]: q factor, ln w
+  static constexpr int COLQ_OFF = ROWQ_OFF + TS * 16;    // double2 [128]
+  static constexpr int LDS_BYTES = COLQ_OFF + TS * 16;
+};
+
+// Keep a value computed here: without it the compiler may defer the
+// arithmetic that folds accumulators into lo0 and U0 to the end of the
+// kernel, keeping every accumulator alive (and spilled) until then.
+template <typename T>
+__device__ __forceinline__ void pin(T& x) {
+  __asm__ __volatile__("" : "+v"(x));
+}
+
+template <int PREC, int G>
+__global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
+  static_assert(PREC != kFP64, "split precisions only");
+  typedef BoundTile BT;
+  typedef typename Pol<PREC>::Acc Acc;
+  typedef __attribute__((address_space(1))) const unsigned char gbyte;
+  typedef __attribute__((address_space(3))) void lvoid;
+  constexpr int ES = 2;                         // bytes per operand element
+  constexpr int NRT = (G == 1) ? 1 : kMaxNR;    // (h|h) outputs: S0, Re/Im S_1..3
+  constexpr int NS = BT::NS;
+  extern __shared__ __align__(16) unsigned char smem[];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // workgroup -> 128 x 128 tile: consecutive ids spread over the XCDs, each
+  // XCD walking a contiguous band of tiles in bands of 4 tile rows
+  const int64_t nst_m = (a.n_tiles_m + 1) / 2, nst_n = (a.n_tiles_n + 1) / 2;
+  int64_t wg = blockIdx.x;
+  {
+    const int64_t nwg = gridDim.x;   // multiple of 8
+    wg = (wg % 8) * (nwg / 8) + wg / 8;
+  }
+  if (wg >= nst_m * nst_n) return;
+  int64_t sm_, sn_;
+  {
+    const int64_t GM = 4;
+    const int64_t band = wg / (GM * nst_n);
+    const int64_t rows_in_band = min(GM, nst_m - band * GM);
+    const int64_t in = wg - band * GM * nst_n;
+    sm_ = band * GM + in % rows_in_band;
+    sn_ = in / rows_in_band;
+  }
+  const int64_t row0 = sm_ * BT::TS, col0 = sn_ * BT::TS;
+
+  // per-row and per-column factors of the bound: q = row_scale^2 / ah_scale
+  // (x the column's; powers of two, each possibly outside float range, so
+  // multiplied in double) and ln w
+  double2* rowq = (double2*)(smem + BT::ROWQ_OFF);
+  double2* colq = (double2*)(smem + BT::COLQ_OFF);
+  if (tid < BT::TS) {
+    double2 v = make_double2(1.0, 0.0);
+    const int64_t ie = row0 + tid;
+    if (ie < a.n_sub) {
+      const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+      const double rs = a.row_scale[i];
+      v = make_double2(rs * rs / a.ah_scale[ie], a.ln_w_bank ? a.ln_w_bank[i] : 0.0);
+    }
+    rowq[tid] = v;
+  } else {
+    double2 v = make_double2(1.0, 0.0);
+    const int64_t e = col0 + (tid - BT::TS);
+    if (e < a.n_ext) {
+      const double cs = a.col_scale[e];
+      v = make_double2(cs * cs / a.bh_scale[e], a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
+    }
+    colq[tid - BT::TS] = v;
+  }
+
+  // ---- operand streams: wave w loads array w (A hi, A lo, B hi, B lo) of
+  // every chunk: 32-row blocks 0..3, slices 0 and 1, 1 KB each copied as it
+  // sits in HBM (fragment order).  A lane's address of block rb, slice 0;
+  // slice 1 is 1 KB further.  Rows past the subset re-read the last row;
+  // columns run to the padded sample count (a multiple of 128, zero rows
+  // past n_ext). ----
+  gbyte* src_dh[4];
+  gbyte* src_hh[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int r = 32 * rb + (lane & 31);
+    const int64_t in_chunk = (lane >> 5) * 256;
+    auto blk = [](int64_t i, int64_t K) { return (i >> 5) * (K >> 5) * 1024 + (i & 31) * 8; };
+    if (wave < 2) {
+      const int64_t ie = min(row0 + r, a.n_sub - 1);
+      const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+      src_dh[rb] = (gbyte*)(wave == 0 ? a.A0 : a.A1) + (blk(i, a.K2) + in_chunk) * ES;
+      src_hh[rb] = (gbyte*)(wave == 0 ? a.Ah0 : a.Ah1) + (blk(ie, a.KH) + in_chunk) * ES;
+    } else {
+      const int64_t e = col0 + r;
+      src_dh[rb] = (gbyte*)(wave == 2 ? a.B0 : a.B1) + (blk(e, a.K2) + in_chunk) * ES;
+      src_hh[rb] = (gbyte*)(wave == 2 ? a.Bh0 : a.Bh1) + (blk(e, a.KH) + in_chunk) * ES;
+    }
+  }
+  // chunks: NRT (h|h) blocks first, then the (d|h) chunks; chunk c sits in
+  // stage c mod NS
+  const int ndh = a.n_chunks;
+  const int nk = NRT + ndh;
+  const unsigned lds_wave =
+      __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lvoid*)(smem + wave * BT::ARR));
+  // the 8 loads of chunk c (block rb, slice s to stage offset (2 rb + s) KB),
+  // two blocks of 4 sharing one M0 value each: the immediate offset applies
+  // to the global and the LDS address alike.  The asm saves and restores M0
+  // and waits the state an M0 write needs.
+  auto issue = [&](int c) {
+    gbyte* p[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+      p[rb] = c < NRT ? src_hh[rb] + (int64_t)c * 1024 * ES
+                      : src_dh[rb] + (int64_t)(c - NRT) * 1024 * ES;
+    const unsigned base = lds_wave + (unsigned)((c % NS) * BT::STAGE);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      unsigned m0_saved;
+      __asm__ __volatile__(
+          "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+          "global_load_lds_dwordx4 %2, off\n\t"
+          "global_load_lds_dwordx4 %2, off offset:1024\n\t"
+          "global_load_lds_dwordx4 %3, off offset:2048\n\t"
+          "global_load_lds_dwordx4 %3, off offset:3072\n\ts_mov_b32 m0, %0"
+          : "=&s"(m0_saved)
+          : "s"(__builtin_amdgcn_readfirstlane(base + 4096u * h)), "v"(p[2 * h]),
+            "v"(p[2 * h + 1] - 2048)
+          : "memory");
+    }
+  };
+
+  // Fragments of one chunk for this wave: A rows 64 wm + 32 bm (FA: [bm]
+  // [slice][hi, lo]) and B rows 64 wn + 32 bn (FB: [slice][hi, lo], one per
+  // bn).  The products of a chunk run in two halves, bn = 0 then bn = 1.
+  // During the first half the bn = 1 fragments of the same chunk are read;
+  // during the second, the A and bn = 0 fragments of the next chunk.  So at
+  // most 24 fragments are live, not the 32 of two whole chunks.
+  struct FA {
+    uint4 v[2][2][2];
+  };
+  struct FB {
+    uint4 v[2][2];
+  };
+  FA fa0, fa1;
+  FB fb0_0, fb0_1, fb1;
+  auto fa = [&](auto pi) -> FA& {
+    if constexpr (decltype(pi)::value % 2 == 0) return fa0;
+    else return fa1;
+  };
+  auto fb0 = [&](auto pi) -> FB& {
+    if constexpr (decltype(pi)::value % 2 == 0) return fb0_0;
+    else return fb0_1;
+  };
+  auto stage_lane = [&](int c) { return smem + (c % NS) * BT::STAGE + lane * 16; };
+  auto read_a = [&](FA& f, int c, int k) {    // k: block (k >> 2), slice, hi / lo
+    const int bm = (k >> 2) & 1, sl = (k >> 1) & 1, lo = k & 1;
+    f.v[bm][sl][lo] = *(const uint4*)(stage_lane(c) + lo * BT::ARR + (2 * (2 * wm + bm) + sl) * 1024);
+  };
+  auto read_b = [&](FB& f, int c, int bn, int k) {   // k: slice, hi / lo
+    const int sl = (k >> 1) & 1, lo = k & 1;
+    f.v[sl][lo] = *(const uint4*)(stage_lane(c) + (2 + lo) * BT::ARR + (2 * (2 * wn + bn) + sl) * 1024);
+  };
+  auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
+
+  // Step j (fragment parity P = j mod 2): wait until this wave's loads of
+  // chunk j + 1 have landed and every wave is done with chunk j - 1, issue
+  // chunk j + 3 into the stage chunk j - 1 used, then the products of chunk
+  // j (NH per half; mf(fa, fb, bm, k) issues product k of block (bm, bn))
+  // with the fragment reads between them.  After the last chunk the reads
+  // fetch a stale stage, unused, so no branch sits between the products.
+  auto step = [&](int j, auto pi, auto nh, auto&& mf) {
+    constexpr int P = decltype(pi)::value % 2;
+    constexpr int NH = decltype(nh)::value;
+    FA& acur = fa(std::integral_constant<int, P>{});
+    FA& anxt = fa(std::integral_constant<int, P + 1>{});
+    FB& bcur = fb0(std::integral_constant<int, P>{});
+    FB& bnxt = fb0(std::integral_constant<int, P + 1>{});
+    if (j + 2 < nk) pipeline_barrier<8>();
+    else pipeline_barrier<0>();
+    if (j + 3 < nk) {
+      fence();
+      issue(j + 3);
+      fence();
+    }
+    // half 0: blocks (0, 0), (1, 0); the 4 reads of this chunk's bn = 1
+    static_for<2 * NH>([&](auto ti) {
+      constexpr int t = decltype(ti)::value;
+      mf(acur, bcur, t & 1, 0, t >> 1);
+      constexpr int EV = (2 * NH) / 4;
+      if constexpr (t % EV == EV - 1 && t / EV < 4) read_b(fb1, j, 1, t / EV);
+    });
+    // half 1: blocks (0, 1), (1, 1); the 12 reads of the next chunk
+    static_for<2 * NH>([&](auto ti) {
+      constexpr int t = decltype(ti)::value;
+      mf(acur, fb1, t & 1, 1, t >> 1);
+      constexpr int EV = (2 * NH) >= 24 ? 2 : 1;
+      if constexpr (t % EV == EV - 1 && t / EV < 12) {
+        constexpr int k = t / EV;
+        if constexpr (k < 8) read_a(anxt, j + 1, k);
+        else read_b(bnxt, j + 1, 0, k - 8);
+      }
+    });
+    static_for<12>([&](auto ki) {     // reads not placed between products
+      constexpr int k = decltype(ki)::value;
+      constexpr int EV = (2 * NH) >= 24 ? 2 : 1;
+      if constexpr (k >= (2 * NH) / EV) {
+        if constexpr (k < 8) read_a(anxt, j + 1, k);
+        else read_b(bnxt, j + 1, 0, k - 8);
+      }
+    });
+  };
+
+  // prologue: chunks 0, 1, 2 in flight, chunk 0's A and bn = 0 fragments read
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (c < nk) issue(c);
+  pipeline_barrier<0>();     // (also makes rowq / colq visible)
+  static_for<8>([&](auto ki) { read_a(fa0, 0, decltype(ki)::value); });
+  static_for<4>([&](auto ki) { read_b(fb0_0, 0, 0, decltype(ki)::value); });
+
+  // ---- (h|h): lo0 = S0 - 2 sum |S_delta| per pair, output by output ----
+  Acc s0[2][2], sabs[2][2], sre[2][2], hacc[2][2];
+  auto mf_hh = [&](const FA& A, const FB& B, int bm, int bn, int k) {   // k: 0..5
+    const int sl = k / 3;
+    switch (k % 3) {
+      case 0: mma<PREC>(hacc[bm][bn], A.v[bm][sl][1], B.v[sl][0]); break;
+      case 1: mma<PREC>(hacc[bm][bn], A.v[bm][sl][0], B.v[sl][1]); break;
+      default: mma<PREC>(hacc[bm][bn], A.v[bm][sl][0], B.v[sl][0]); break;
+    }
+  };
+  static_for<NRT>([&](auto ri) {
+    constexpr int r = decltype(ri)::value;
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) hacc[bm][bn] = Acc{};
+    step(r, std::integral_constant<int, r>{}, std::integral_constant<int, 6>{}, mf_hh);
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        if constexpr (r == 0) {
+          s0[bm][bn] = hacc[bm][bn];
+          sabs[bm][bn] = Acc{};
+        } else if constexpr (r % 2 == 1) {
+          sre[bm][bn] = hacc[bm][bn];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const float x = sre[bm][bn][e], y = hacc[bm][bn][e];
+            sabs[bm][bn][e] += 2.f * __builtin_amdgcn_sqrtf(x * x + y * y);
+          }
+          pin(sabs[bm][bn]);
+        }
+      }
+  });
+  // lo0 with the rounding margin of the fused kernel's bound
+  Acc lo0[2][2];
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const float x = s0[bm][bn][e], sa = sabs[bm][bn][e];
+        lo0[bm][bn][e] = (x - sa) - 2e-5f * (fabsf(x) + sa);
+      }
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) pin(lo0[bm][bn]);
+
+  // ---- (d|h): one m group at a time, |X_g| into U0 ----
+  Acc u0[2][2], acc[2][2][2];
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) u0[bm][bn] = Acc{};
+  // product k (0..11) of block (bm, bn): with A = [hr | hi] and B_re =
+  // [Br | -Bi] by slice, B_im = [Bi | Br] = [-(B_re slice 1) | B_re slice 0];
+  // 3 split products per real product, re and im alternating
+  auto neg = [](const uint4& x) {
+    return make_uint4(x.x ^ 0x80008000u, x.y ^ 0x80008000u, x.z ^ 0x80008000u, x.w ^ 0x80008000u);
+  };
+  auto mf_dh = [&](const FA& A, const FB& B, int bm, int bn, int k) {
+    Acc& re = acc[bm][bn][0];
+    Acc& im = acc[bm][bn][1];
+    switch (k) {
+      case 0: mma<PREC>(re, A.v[bm][0][1], B.v[0][0]); break;
+      case 1: mma<PREC>(im, A.v[bm][0][1], neg(B.v[1][0])); break;
+      case 2: mma<PREC>(re, A.v[bm][0][0], B.v[0][1]); break;
+      case 3: mma<PREC>(im, A.v[bm][0][0], neg(B.v[1][1])); break;
+      case 4: mma<PREC>(re, A.v[bm][0][0], B.v[0][0]); break;
+      case 5: mma<PREC>(im, A.v[bm][0][0], neg(B.v[1][0])); break;
+      case 6: mma<PREC>(re, A.v[bm][1][1], B.v[1][0]); break;
+      case 7: mma<PREC>(im, A.v[bm][1][1], B.v[0][0]); break;
+      case 8: mma<PREC>(re, A.v[bm][1][0], B.v[1][1]); break;
+      case 9: mma<PREC>(im, A.v[bm][1][0], B.v[0][1]); break;
+      case 10: mma<PREC>(re, A.v[bm][1][0], B.v[1][0]); break;
+      default: mma<PREC>(im, A.v[bm][1][0], B.v[0][0]); break;
+    }
+  };
+  int ch = 0;
+  static_for<G>([&](auto gi) {
+    constexpr int g = decltype(gi)::value;
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        acc[bm][bn][0] = Acc{};
+        acc[bm][bn][1] = Acc{};
+      }
+    // each group spans a multiple of 4 chunks, so the fragment parity of
+    // every step is static
+    const int gend = a.mt.gk0[g + 1];
+    for (; ch < gend; ch += 2) {
+      step(NRT + ch, std::integral_constant<int, NRT>{}, std::integral_constant<int, 12>{}, mf_dh);
+      step(NRT + ch + 1, std::integral_constant<int, NRT + 1>{}, std::integral_constant<int, 12>{},
+           mf_dh);
+    }
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float xr = acc[bm][bn][0][e], xi = acc[bm][bn][1][e];
+          u0[bm][bn][e] += __builtin_amdgcn_sqrtf(xr * xr + xi * xi);
+        }
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) pin(u0[bm][bn]);
+  });
+
+  // ---- bound every pair of this wave's tile ----
+  const int64_t tm = 2 * sm_ + wm, tn = 2 * sn_ + wn;
+  if (tm >= a.n_tiles_m || tn >= a.n_tiles_n) return;
+  const int64_t tile_id = tm * a.n_tiles_n + tn;
+  const int rows_in = (int)min((int64_t)64, a.n_sub - tm * 64);
+  const int cols_in = (int)min((int64_t)64, a.n_ext - tn * 64);
+  const float thr_f = (float)(__longlong_as_double(a.state[3]) - a.cut_delta);
+  LseF drop;
+  drop.init();
+  float max_bound = -INFINITY;
+  int n_in = 0, n_bounded = 0;
+  unsigned smask[2] = {0u, 0u};   // survivors of this lane, per bn: bit 16 bm + e
+#pragma unroll
+  for (int bn = 0; bn < 2; ++bn) {
+    const int tc = 32 * bn + (lane & 31);
+    const double2 cq = colq[64 * wn + tc];
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int tr = 32 * bm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const double2 rq = rowq[64 * wm + tr];
+        const bool in = tr < rows_in && tc < cols_in;
+        const float U0 = u0[bm][bn][e], lo = lo0[bm][bn][e];
+        // rcp is within an ulp; the 1.001 factor covers it
+        const float bound = (float)(rq.x * cq.x) * (U0 * U0) * __builtin_amdgcn_rcpf(2.f * lo) * 1.001f + 1e-3f;
+        const bool bounded = in && lo > 0.f && bound < thr_f;
+        const float lw = (float)(rq.y + cq.y);
+        drop.add(bounded ? lw + bound : -INFINITY);
+        max_bound = bounded ? fmaxf(max_bound, lw + bound) : max_bound;
+        n_in += in ? 1 : 0;
+        n_bounded += bounded ? 1 : 0;
+        smask[bn] |= (in && !bounded) ? 1u << (16 * bm + e) : 0u;
+      }
+  }
+  // survivors in a fixed order (bn, bm, element, lane)
+  int n_surv = 0;
+#pragma unroll
+  for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+    for (int q = 0; q < 32; ++q) n_surv += (int)__popcll(__ballot((smask[bn] >> q) & 1u));
+  if (n_surv > kSurvCap) {
+    // the whole tile goes to the fused kernel's batched epilogue
+    if (lane == 0) {
+      const unsigned long long k = atomicAdd((unsigned long long*)&a.state[4], 1ull);
+      a.rerun[k] = (int)tile_id;
+    }
+    return;
+  }
+  if (n_surv > 0) {
+    // listed one by one for the survivor pass, which adds their evaluation
+    // to the partial written below
+    uint16_t* rec = a.surv + tile_id * kSurvCap;
+    int run = 0;
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int q = 0; q < 32; ++q) {
+        const unsigned long long bal = __ballot((smask[bn] >> q) & 1u);
+        if ((smask[bn] >> q) & 1u) {
+          const int slot = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+          const int bm = q >> 4, e = q & 15;
+          const int tr = 32 * bm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+          const int tc = 32 * bn + (lane & 31);
+          rec[slot] = (uint16_t)((tr << 8) | tc);
+        }
+        run += (int)__popcll(bal);
+      }
+    if (lane == 0) {
+      const unsigned long long k = atomicAdd((unsigned long long*)&a.state[5], 1ull);
+      a.surv_list[2 * k] = (int)tile_id;
+      a.surv_list[2 * k + 1] = n_surv;
+    }
+  }
+  // the tile's partial: bounded mass (m, s), counts, largest bound
+  auto add_i = [](int x, int y) { return x + y; };
+  const int w_np = wave_reduce(n_in, 0, add_i);
+  const int w_nb = wave_reduce(n_bounded, 0, add_i);
+  const float w_mb = wave_reduce(max_bound, (float)-INFINITY, [](float x, float y) { return fmaxf(x, y); });
+  float dm = drop.m, ds = drop.s;
+  auto dmerge = [&](auto ctrl, auto rowmask) {
+    constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
+    LseF t{dm, ds};
+    t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
+    dm = t.m;
+    ds = t.s;
+  };
+  dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+  dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+  if (lane == 63) {
+    double* out = a.partials + tile_id * kNPart;
+    out[0] = -INFINITY; out[1] = 0.0; out[2] = 0.0;          // no pair evaluated (yet)
+    out[3] = dm == -INFINITY ? -INFINITY : (double)dm;
+    out[4] = ds; out[5] = 0.0; out[6] = 0.0; out[7] = (double)w_nb;
+    out[8] = (double)w_mb; out[9] = -INFINITY; out[10] = (double)w_np; out[11] = 0.0;
+  }
+}
+
+// Survivor pass after the bound pass: one wave per listed tile evaluates its
+// survivors one at a time.  For a survivor (i, e) the wave forms X_g and the
+// (h|h) phase coefficients as FP64 sums of the products of the split
+// operands (each value hi + lo is exact in double; lanes take chunks of the
+// contraction, then a wave reduction), and then the per-phase
+// marginalisation of the fused kernel (pair_phases), one phase per lane.
+// The results are merged into the tile's partial, which the bound pass wrote
+// with the tile's bounded mass.
+template <int PREC, int G>
+__global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
+  static_assert(PREC != kFP64, "split precisions only");
+  constexpr int NRT = (G == 1) ? 1 : kMaxNR;
+  typedef typename std::conditional<PREC == kFP16X2, _Float16, __bf16>::type H;
+  __shared__ __align__(16) unsigned char sm[sizeof(DistParams) + 16 + kMaxM * kMaxPhi * 2 * 8];
+  DistParams* dp = (DistParams*)sm;
+  double* lds_cs = (double*)(sm + (sizeof(DistParams) + 15) / 16 * 16);
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int t = tid; t < kMaxM * a.n_phi * 2; t += 256) lds_cs[t] = a.phase_cs[t];
+  for (int t = tid; t < (int)(sizeof(DistParams) / 4); t += 256)
+    ((unsigned*)dp)[t] = ((const unsigned*)a.dist.prm)[t];
+  __syncthreads();
+  const int64_t n_list = (int64_t)a.state[5];
+  const int64_t item = (int64_t)blockIdx.x * 4 + (tid >> 6);
+  if (item >= n_list) return;
+  const int64_t tile_id = a.surv_list[2 * item];
+  const int n_surv = a.surv_list[2 * item + 1];
+  const int64_t tm = tile_id / a.n_tiles_n, tn = tile_id % a.n_tiles_n;
+  const double thr_ml = __longlong_as_double(a.state[3]) - a.cut_delta;
+  const double thr_topk_glob = order_value(a.state[1]) - a.topk_window;
+  const int nch = (int)(a.K2 >> 5);
+  auto val = [](const H* p, const H* q, int j) { return (double)(float)p[j] + (double)(float)q[j]; };
+  EvAcc ev;
+  ev.init();
+  double tile_max = -INFINITY;
+  for (int sidx = 0; sidx < n_surv; ++sidx) {
+    const unsigned rc = a.surv[tile_id * kSurvCap + sidx];
+    const int64_t ie = tm * 64 + (rc >> 8), e = tn * 64 + (rc & 255);
+    const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+    // X_g: lane l takes half l % 2 (8 positions of each slice) of chunks
+    // l / 2, l / 2 + 32, ...
+    double xr[G], xi[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) { xr[g] = 0.0; xi[g] = 0.0; }
+    const int h = lane & 1;
+    const int64_t arow = ((i >> 5) * (a.K2 >> 5)) * 1024 + (i & 31) * 8 + h * 256;
+    const int64_t brow = ((e >> 5) * (a.K2 >> 5)) * 1024 + (e & 31) * 8 + h * 256;
+    for (int c = lane >> 1; c < nch; c += 32) {
+      const H* a0h = (const H*)a.A0 + arow + (int64_t)c * 1024;
+      const H* a0l = (const H*)a.A1 + arow + (int64_t)c * 1024;
+      const H* b0h = (const H*)a.B0 + brow + (int64_t)c * 1024;
+      const H* b0l = (const H*)a.B1 + brow + (int64_t)c * 1024;
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double x0 = val(a0h, a0l, j), x1 = val(a0h + 512, a0l + 512, j);
+        const double y0 = val(b0h, b0l, j), y1 = val(b0h + 512, b0l + 512, j);
+        re += x0 * y0 + x1 * y1;      // A [hr | hi'] . B_re [Br | -Bi]
+        im += x1 * y0 - x0 * y1;      // A . B_im, B_im = [-(B_re slice 1) | B_re slice 0]
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const bool in_g = c >= a.mt.gk0[g] && c < a.mt.gk0[g + 1];
+        xr[g] += in_g ? re : 0.0;
+        xi[g] += in_g ? im : 0.0;
+      }
+    }
+    // (h|h) outputs: lanes 4 r .. 4 r + 3 take block r (slice, half)
+    double sv = 0.0;
+    if (lane < 4 * NRT) {
+      const int r = lane >> 2, s2 = (lane >> 1) & 1, h2 = lane & 1;
+      const int64_t ho = ((ie >> 5) * (a.KH >> 5) + r) * 1024 + s2 * 512 + h2 * 256 + (ie & 31) * 8;
+      const int64_t bo = ((e >> 5) * (a.KH >> 5) + r) * 1024 + s2 * 512 + h2 * 256 + (e & 31) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        sv += val((const H*)a.Ah0 + ho, (const H*)a.Ah1 + ho, j) *
+              val((const H*)a.Bh0 + bo, (const H*)a.Bh1 + bo, j);
+    }
+    // quad sums, then every lane reads the totals
+    sv += dpp_mov<0xB1, 0xF>(0.0, sv);
+    sv += dpp_mov<0x4E, 0xF>(0.0, sv);
+    auto add_d = [](double x, double y) { return x + y; };
+    const double sx = a.row_scale[i] * a.col_scale[e];
+    const double shh = a.ah_scale[ie] * a.bh_scale[e];
+    double2 X[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      X[g].x = sx * read_lane(wave_reduce(xr[g], 0.0, add_d), 63);
+      X[g].y = sx * read_lane(wave_reduce(xi[g], 0.0, add_d), 63);
+    }
+    double S0 = shh * read_lane(sv, 0), Sr[kMaxND], Si[kMaxND];
+#pragma unroll
+    for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0.0; Si[d] = 0.0; }
+#pragma unroll
+    for (int d = 1; d < (NRT + 1) / 2; ++d) {
+      Sr[d] = shh * read_lane(sv, 4 * (2 * d - 1));
+      Si[d] = shh * read_lane(sv, 4 * (2 * d));
+    }
+    const double lnw = (a.ln_w_bank ? a.ln_w_bank[i] : 0.0) + (a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
+    Lse lse;
+    lse.init();
+    double best = -INFINITY, mlmax = 0.0;
+    int ob = 0;
+    pair_phases<kEvidence, G>(a, lds_cs, *dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, lane, 64, ev, lse,
+                              best, ob, mlmax);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double lm = __shfl_xor(lse.m, off, 64), ls = __shfl_xor(lse.s, off, 64);
+      const double ls2 = __shfl_xor(lse.s2, off, 64);
+      lse.merge(lm, ls, ls2);
+      const double bv = __shfl_xor(best, off, 64);
+      const int bo = __shfl_xor(ob, off, 64);
+      if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }
+      mlmax = fmax(mlmax, __shfl_xor(mlmax, off, 64));
+    }
+    ev.ml_max = fmax(ev.ml_max, mlmax);
+    if (lane != 0 || lse.m == -INFINITY) continue;
+    const double lnp = lnw + lse.m + log(lse.s) - a.ln_nphi;
+    ev.p.add(lnp);
+    tile_max = fmax(tile_max, lnp);
+    if (lnp >= fmax(thr_topk_glob, tile_max - a.topk_window)) {
+      const unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
+      if ((int64_t)slot < a.cand_cap) {
+        double* cd = a.cand + 4 * slot;
+        cd[0] = lnp;
+        cd[1] = (double)i;
+        cd[2] = (double)e;
+        cd[3] = (double)ob;
+      }
+    }
+  }
+  // merge into the tile's partial: the cut phases' bounds (every lane), the
+  // evaluated pairs (lane 0), the phases marginalised
+  float dm = ev.drop.m, ds = ev.drop.s;
+  auto dmerge = [&](auto ctrl, auto rowmask) {
+    constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
+    LseF t{dm, ds};
+    t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
+    dm = t.m;
+    ds = t.s;
+  };
+  dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
+  dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+  dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+  const int n_marg = wave_reduce(ev.n_marg, 0, [](int x, int y) { return x + y; });
+  const double dmd = read_lane(dm == -INFINITY ? -INFINITY : (double)dm, 63);
+  const double dsd = read_lane((double)ds, 63);
+  const int n_marg_all = __builtin_amdgcn_readlane(n_marg, 63);
+  if (lane == 0) {
+    double* out = a.partials + tile_id * kNPart;
+    Lse d;
+    d.m = out[3];
+    d.s = out[4];
+    d.s2 = 0.0;
+    d.merge(dmd, dsd, 0.0);
+    out[0] = ev.p.m; out[1] = ev.p.s; out[2] = ev.p.s2;
+    out[3] = d.m; out[4] = d.s;
+    out[5] = ev.ml_max; out[6] = (double)n_marg_all; out[9] = tile_max;
+    if (ev.ml_max > 0.0)
+      atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(ev.ml_max));
+    if (tile_max > -INFINITY)
+      atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(tile_max));
+  }
+}
+
+}  // namespace dotpe

@@ -41,6 +41,7 @@ constexpr int kMaxND = 4;       // delta = 0..3
 constexpr int kMaxM = 4;
 constexpr int kChunk = 16;      // bins per K chunk (32 real K)
 constexpr int kNPart = 12;      // doubles per tile partial
+constexpr int kSurvCap = 16;    // survivors of a 64 x 64 tile the bound pass lists one by one
 
 enum Prec { kFP64 = 0, kFP16X2 = 1, kBF16X2 = 2 };
 

@@ -48,6 +48,10 @@ int fail(int code, const char* fmt, ...) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// 128 x 128 tiles an event needs before the bound pass replaces the fused
+// kernel's fast epilogue (fewer would leave the device partly idle)
+constexpr int64_t kBoundMinTiles = 2048;
+
 }  // namespace
 
 // Device scratch of dotpe_evidence_static: every buffer of one event packed
@@ -147,7 +151,9 @@ struct dotpe_event {
   double* final_out = nullptr;
   double* final_blk = nullptr;
   int* rerun = nullptr;          // tiles a fast evidence pass leaves to the batched epilogue
-  hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};
+  uint16_t* surv = nullptr;      // bound pass: listed survivors [n_tiles][kSurvCap]
+  int* surv_list = nullptr;      // bound pass: (tile, count) of tiles with listed survivors
+  hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<void*> allocs;
   uint64_t bytes = 0;
 };
@@ -426,6 +432,7 @@ __global__ void k_reset_state(uint64_t* st) {
     st[2] = 0ull;
     st[3] = 0ull;
     st[4] = 0ull;                       // tiles listed for a rerun
+    st[5] = 0ull;                       // tiles whose survivors are listed
   }
 }
 
@@ -675,7 +682,8 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
     return fail(DOTPE_E_INVALID_ARG, "event arrays must not be NULL");
   if (!(d->d_max > 0.0) || !(d->d0 > 0.0) || !std::isfinite(d->d_max) || !std::isfinite(d->d0))
     return fail(DOTPE_E_INVALID_ARG, "distances must be positive and finite");
-  if (d->flags & ~DOTPE_FLAG_RERUN_ALL) return fail(DOTPE_E_INVALID_ARG, "unknown flags 0x%x", d->flags);
+  if (d->flags & ~(DOTPE_FLAG_RERUN_ALL | DOTPE_FLAG_NO_BOUND_PASS))
+    return fail(DOTPE_E_INVALID_ARG, "unknown flags 0x%x", d->flags);
   int KH = 0;
   {
     int rc0 = build_hh_terms(bk->mt, d->n_det, terms, &KH);
@@ -711,7 +719,7 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
   D->NP = bk->mt.NP;
   D->prec = bk->prec;
   D->ne = ne;
-  D->ne_p = round_up(ne, 64);
+  D->ne_p = round_up(ne, 128);   // whole 128-sample tiles of the bound pass
   D->n_sub = n_sub;
   D->K2 = bk->K2;
   int tm, tn;
@@ -761,6 +769,10 @@ std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) 
   v.push_back({(void**)&ev->final_blk, (size_t)((D.n_tiles + 4095) / 4096) * kNPart * 8, false});
   v.push_back({(void**)&ev->cand, (size_t)D.cand_cap * 32, false});
   v.push_back({(void**)&ev->rerun, (size_t)D.n_tiles * sizeof(int), false});
+  if (D.prec != kFP64) {
+    v.push_back({(void**)&ev->surv, (size_t)D.n_tiles * kSurvCap * sizeof(uint16_t), false});
+    v.push_back({(void**)&ev->surv_list, (size_t)D.n_tiles * 2 * sizeof(int), false});
+  }
   v.push_back({(void**)&st->d, (size_t)D.nk * D.nb * 16, true});
   v.push_back({(void**)&st->w, (size_t)D.nk * D.nb * 8, true});
   v.push_back({(void**)&st->r, (size_t)D.nk * 24, true});
@@ -1010,13 +1022,31 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   std::memcpy(&thr_frozen, &thr_bits, 8);
   const bool fast = cut_delta > 0.0 && thr_frozen - cut_delta > 0.0;
   a.rerun = ev->rerun;
+  a.surv = ev->surv;
+  a.surv_list = ev->surv_list;
   a.rec_cap = (ev->flags & DOTPE_FLAG_RERUN_ALL) ? 0 : (1 << 30);
   int64_t grid = round_up(a.n_tiles, 8);
+  // the bound pass (128 x 128 tiles, split precisions) when the event has
+  // enough of them to fill the device; else the fused kernel's fast epilogue
+  const int64_t n_big = ((a.n_tiles_m + 1) / 2) * ((a.n_tiles_n + 1) / 2);
+  const bool bound_pass = fast && ev->bank->prec != kFP64 && n_big >= kBoundMinTiles &&
+                          !(ev->flags & (DOTPE_FLAG_NO_BOUND_PASS | DOTPE_FLAG_RERUN_ALL));
+  uint64_t n_rerun = 0, n_listed = 0;
   if (fast) {
-    if ((rc = launch_fused<kEvidence, true>(ev->bank->prec, a, grid, s))) return rc;
-    uint64_t n_rerun = 0;
-    HIP_OK(hipMemcpyAsync(&n_rerun, ev->state + 4, 8, hipMemcpyDeviceToHost, s));
+    if (bound_pass) {
+      if ((rc = launch_fused<kBound>(ev->bank->prec, a, round_up(n_big, 8), s))) return rc;
+    } else {
+      if ((rc = launch_fused<kEvidence, true>(ev->bank->prec, a, grid, s))) return rc;
+    }
+    if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
+    uint64_t cnt[2] = {0, 0};     // tiles to rerun, tiles with listed survivors
+    HIP_OK(hipMemcpyAsync(cnt, ev->state + 4, 16, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    n_rerun = cnt[0];
+    n_listed = cnt[1];
+    if (cnt[1] > 0) {
+      if ((rc = launch_fused<kSurvivors>(ev->bank->prec, a, (int64_t)((cnt[1] + 3) / 4), s))) return rc;
+    }
     if (n_rerun > 0) {
       FusedArgs b = a;
       b.rerun_list = ev->rerun;
@@ -1024,6 +1054,7 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
     }
   } else {
     if ((rc = launch_fused<kEvidence, false>(ev->bank->prec, a, grid, s))) return rc;
+    if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
   }
   if (timed) HIP_OK(hipEventRecord(ev->ev_t[2], s));
   {
@@ -1059,12 +1090,16 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   r.dd = ev->dd;
   r.precision = ev->bank->prec;
   r.cut_delta_used = cut_delta > 0.0 ? cut_delta : 0.0;
+  r.n_tiles_rerun = (int32_t)n_rerun;
+  r.n_tiles_listed = (int32_t)n_listed;
   if (timed) {
-    float t_pilot = 0.f, t_main = 0.f;
+    float t_pilot = 0.f, t_all = 0.f, t_first = 0.f;
     HIP_OK(hipEventElapsedTime(&t_pilot, ev->ev_t[0], ev->ev_t[1]));
-    HIP_OK(hipEventElapsedTime(&t_main, ev->ev_t[1], ev->ev_t[2]));
+    HIP_OK(hipEventElapsedTime(&t_all, ev->ev_t[1], ev->ev_t[2]));
+    HIP_OK(hipEventElapsedTime(&t_first, ev->ev_t[1], ev->ev_t[3]));
     r.t_pilot_ms = t_pilot;
-    r.t_fused_ms = t_main;
+    r.t_fused_ms = t_all;
+    r.t_main_ms = t_first;
   }
   // no cut pair could have entered the top-k window
   const double thr = r.max_ln_p - ev->topk_window;
@@ -1142,6 +1177,7 @@ int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out, 
     HIP_OK(hipEventCreate(&ev->ev_t[0]));
     HIP_OK(hipEventCreate(&ev->ev_t[1]));
     HIP_OK(hipEventCreate(&ev->ev_t[2]));
+    HIP_OK(hipEventCreate(&ev->ev_t[3]));
   }
   return evidence_run(ctx, ev, out, topk);
 }

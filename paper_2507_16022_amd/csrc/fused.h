@@ -65,6 +65,11 @@ struct FusedArgs {
   int* rerun;                // fast evidence pass: tiles left to the batched epilogue
   const int* rerun_list;     // batched pass over listed tiles only (NULL: all tiles)
   int rec_cap;               // fast pass: survivors a tile may have (<= the record area)
+  // bound pass: survivors of tiles with at most kSurvCap of them, as
+  // (row << 8 | column) within the tile, [n_tiles][kSurvCap]; and the list
+  // of such tiles, (tile id, count) pairs, its length in state[5]
+  uint16_t* surv;
+  int* surv_list;
 };
 
 template <int PREC>
@@ -176,7 +181,7 @@ __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a
   }
 }
 
-enum Mode { kEval = 0, kEvidence = 1, kPilot = 2 };
+enum Mode { kEval = 0, kEvidence = 1, kPilot = 2, kBound = 3, kSurvivors = 4 };
 
 // Wave-wide reductions through DPP lane moves (no LDS round trips): pairs
 // of lanes, quads, half rows and rows of 16 are combined within rows, then
@@ -335,28 +340,33 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   // (the ~32 tiles an XCD runs at once then share 4 row blocks and 8 column
   // blocks of operands in its L2)
   int64_t wg = blockIdx.x;
+  int64_t tm, tn;
   if (a.rerun_list) {
-    wg = a.rerun_list[blockIdx.x];        // a tile listed by a fast pass
+    // a tile listed by a fast or bound pass (row-major tile id)
+    const int64_t t = a.rerun_list[blockIdx.x];
+    tm = t / a.n_tiles_n;
+    tn = t % a.n_tiles_n;
   } else {
     int64_t nwg = gridDim.x;              // multiple of 8
     wg = (wg % 8) * (nwg / 8) + wg / 8;
+    if (MODE == kPilot) {
+      // every pilot_stride-th row of tiles, all columns
+      int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
+      if (wg >= npr * a.n_tiles_n) return;
+      tm = (wg / a.n_tiles_n) * a.pilot_stride;
+      tn = wg % a.n_tiles_n;
+    } else {
+      if (wg >= a.n_tiles) return;
+      const int64_t GM = 4;
+      int64_t band = wg / (GM * a.n_tiles_n);
+      int64_t rows_in_band = min(GM, a.n_tiles_m - band * GM);
+      int64_t in = wg - band * GM * a.n_tiles_n;
+      tm = band * GM + in % rows_in_band;
+      tn = in / rows_in_band;
+    }
   }
-  int64_t tm, tn;
-  if (MODE == kPilot) {
-    // every pilot_stride-th row of tiles, all columns
-    int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
-    if (wg >= npr * a.n_tiles_n) return;
-    tm = (wg / a.n_tiles_n) * a.pilot_stride;
-    tn = wg % a.n_tiles_n;
-  } else {
-    if (wg >= a.n_tiles) return;
-    const int64_t GM = 4;
-    int64_t band = wg / (GM * a.n_tiles_n);
-    int64_t rows_in_band = min(GM, a.n_tiles_m - band * GM);
-    int64_t in = wg - band * GM * a.n_tiles_n;
-    tm = band * GM + in % rows_in_band;
-    tn = in / rows_in_band;
-  }
+  // partials and rerun lists are indexed by the row-major tile id
+  const int64_t tile_id = tm * a.n_tiles_n + tn;
   const int64_t row0 = tm * TM, col0 = tn * TN;
 
   // phase table and distance-rule parameters to LDS (the rule's segment
@@ -1053,7 +1063,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     if (nsurv > min(a.rec_cap, TL::BATCH)) {
       if (tid == 0) {
         unsigned long long k = atomicAdd((unsigned long long*)&a.state[4], 1ull);
-        a.rerun[k] = (int)wg;
+        a.rerun[k] = (int)tile_id;
       }
       return;
     }
@@ -1155,7 +1165,7 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     }
     // every wave's E2 has finished (barrier above): the tile maximum is final
     const double mxp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
-    double* out = a.partials + wg * kNPart;
+    double* out = a.partials + tile_id * kNPart;
     out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
     out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
     // running maxima (the results are not waited for)

@@ -36,6 +36,34 @@ hipError_t launch_one(const FusedArgs& a, int64_t grid, hipStream_t s) {
 }
 
 template <int PREC, int G>
+hipError_t launch_bound(const FusedArgs& a, int64_t grid, hipStream_t s) {
+  if constexpr (PREC == kFP64) {
+    return hipErrorInvalidValue;
+  } else {
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+      if (hipFuncSetAttribute((const void*)k_lnl_bound<PREC, G>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              BoundTile::LDS_BYTES) != hipSuccess)
+        (void)hipGetLastError();
+    });
+    hipLaunchKernelGGL((k_lnl_bound<PREC, G>), dim3((unsigned)grid), dim3(BoundTile::NT),
+                       BoundTile::LDS_BYTES, s, a);
+    return hipGetLastError();
+  }
+}
+
+template <int PREC, int G>
+hipError_t launch_survivors(const FusedArgs& a, int64_t grid, hipStream_t s) {
+  if constexpr (PREC == kFP64) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((k_survivors<PREC, G>), dim3((unsigned)grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+}
+
+template <int PREC, int G>
 hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hipStream_t s) {
   switch (mode) {
     case kEval: return launch_one<PREC, G, kEval, false>(a, grid, s);
@@ -43,6 +71,8 @@ hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hip
     case kEvidence:
       return fast ? launch_one<PREC, G, kEvidence, true>(a, grid, s)
                   : launch_one<PREC, G, kEvidence, false>(a, grid, s);
+    case kBound: return launch_bound<PREC, G>(a, grid, s);
+    case kSurvivors: return launch_survivors<PREC, G>(a, grid, s);
   }
   return hipErrorInvalidValue;
 }

@@ -6,12 +6,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include "bound.h"
 #include "fused.h"
 
 namespace dotpe {
 
-// mode: kEval, kPilot or kEvidence; fast only with kEvidence.  Launches
-// `grid` workgroups on stream s and returns the launch status.
+// mode: kEval, kPilot, kEvidence (fast only with kEvidence), kBound
+// (split precisions; `grid` counts 128 x 128 tiles) or kSurvivors (split
+// precisions; `grid` workgroups of 4 listed tiles).  Launches `grid`
+// workgroups on stream s and returns the launch status.
 typedef hipError_t (*FusedLaunchFn)(int mode, bool fast, const FusedArgs& a, int64_t grid,
                                     hipStream_t s);
 

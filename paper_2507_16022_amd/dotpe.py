@@ -66,7 +66,9 @@ class EvidenceResult(ctypes.Structure):
                 ("topk_count", ctypes.c_int32), ("topk_exact", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("t_pilot_ms", ctypes.c_double),
                 ("t_fused_ms", ctypes.c_double), ("cut_delta_used", ctypes.c_double),
-                ("n_passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_passes", ctypes.c_int32), ("n_tiles_rerun", ctypes.c_int32),
+                ("t_main_ms", ctypes.c_double), ("n_tiles_listed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -276,6 +278,7 @@ class Bank:
 
 
 FLAG_RERUN_ALL = 1
+FLAG_NO_BOUND_PASS = 2
 
 
 def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=1.0, n_norm=0.0,
