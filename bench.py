@@ -277,7 +277,7 @@ def main():
     # start from a process without GPU state)
     rng = np.random.default_rng(99)
     k2 = 2 * len(modes) * 256
-    cut31 = (1 << 31) // k2 + 1
+    cut31 = min((1 << 31) // k2 + 1, n_int // 2)     # (smaller workloads: the upper half)
     rows = np.sort(np.r_[rng.choice(cut31, 16, replace=False),
                          rng.choice(np.arange(cut31, n_int), 16, replace=False)])
     cols = np.sort(rng.choice(n_ext, 256, replace=False))

@@ -209,31 +209,30 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
       issue(j + 3);
       fence();
     }
-    // half 0: blocks (0, 0), (1, 0); the 4 reads of this chunk's bn = 1
+    // half 0: blocks (0, 0), (1, 0), with all 16 reads after its first 16
+    // products: this chunk's bn = 1 fragments, then the next chunk's A and
+    // bn = 0 (their registers are free since the previous step), so that
+    // they are complete long before they are used and before the next
+    // barrier waits for them
     static_for<2 * NH>([&](auto ti) {
       constexpr int t = decltype(ti)::value;
       mf(acur, bcur, t & 1, 0, t >> 1);
-      constexpr int EV = (2 * NH) / 4;
-      if constexpr (t % EV == EV - 1 && t / EV < 4) read_b(fb1, j, 1, t / EV);
+      if constexpr (t < 4) read_b(fb1, j, 1, t);
+      else if constexpr (t < 12) read_a(anxt, j + 1, t - 4);
+      else if constexpr (t < 16) read_b(bnxt, j + 1, 0, t - 12);
     });
-    // half 1: blocks (0, 1), (1, 1); the 12 reads of the next chunk
+    static_for<16>([&](auto ki) {     // reads not placed between products
+      constexpr int k = decltype(ki)::value;
+      if constexpr (k >= 2 * NH) {
+        if constexpr (k < 4) read_b(fb1, j, 1, k);
+        else if constexpr (k < 12) read_a(anxt, j + 1, k - 4);
+        else read_b(bnxt, j + 1, 0, k - 12);
+      }
+    });
+    // half 1: blocks (0, 1), (1, 1)
     static_for<2 * NH>([&](auto ti) {
       constexpr int t = decltype(ti)::value;
       mf(acur, fb1, t & 1, 1, t >> 1);
-      constexpr int EV = (2 * NH) >= 24 ? 2 : 1;
-      if constexpr (t % EV == EV - 1 && t / EV < 12) {
-        constexpr int k = t / EV;
-        if constexpr (k < 8) read_a(anxt, j + 1, k);
-        else read_b(bnxt, j + 1, 0, k - 8);
-      }
-    });
-    static_for<12>([&](auto ki) {     // reads not placed between products
-      constexpr int k = decltype(ki)::value;
-      constexpr int EV = (2 * NH) >= 24 ? 2 : 1;
-      if constexpr (k >= (2 * NH) / EV) {
-        if constexpr (k < 8) read_a(anxt, j + 1, k);
-        else read_b(bnxt, j + 1, 0, k - 8);
-      }
     });
   };
 
@@ -367,40 +366,45 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   const int rows_in = (int)min((int64_t)64, a.n_sub - tm * 64);
   const int cols_in = (int)min((int64_t)64, a.n_ext - tn * 64);
   const float thr_f = (float)(__longlong_as_double(a.state[3]) - a.cut_delta);
-  LseF drop;
-  drop.init();
-  float max_bound = -INFINITY;
-  int n_in = 0, n_bounded = 0;
+  // The bounded mass is summed against a fixed reference: every bounded
+  // pair has bound < thr_f and ln w no larger than the tile's largest row
+  // weight plus its largest column weight, so each term exp(lw + bound -
+  // m_ref) is at most 1 and a plain float sum holds them (its rounding, at
+  // most ~1e-5 relative here, is far inside the bound's e^0.001 margin).
+  const float lw_max = wave_max((double)rowq[64 * wm + lane].y) + wave_max((double)colq[64 * wn + lane].y);
+  const float m_ref = thr_f + lw_max;
+  float dsum = 0.f, max_bound = -INFINITY;
   unsigned smask[2] = {0u, 0u};   // survivors of this lane, per bn: bit 16 bm + e
 #pragma unroll
   for (int bn = 0; bn < 2; ++bn) {
     const int tc = 32 * bn + (lane & 31);
     const double2 cq = colq[64 * wn + tc];
+    const bool col_in = tc < cols_in;
 #pragma unroll
     for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int tr = 32 * bm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         const double2 rq = rowq[64 * wm + tr];
-        const bool in = tr < rows_in && tc < cols_in;
+        const bool in = col_in && tr < rows_in;
         const float U0 = u0[bm][bn][e], lo = lo0[bm][bn][e];
         // rcp is within an ulp; the 1.001 factor covers it
         const float bound = (float)(rq.x * cq.x) * (U0 * U0) * __builtin_amdgcn_rcpf(2.f * lo) * 1.001f + 1e-3f;
         const bool bounded = in && lo > 0.f && bound < thr_f;
-        const float lw = (float)(rq.y + cq.y);
-        drop.add(bounded ? lw + bound : -INFINITY);
-        max_bound = bounded ? fmaxf(max_bound, lw + bound) : max_bound;
-        n_in += in ? 1 : 0;
-        n_bounded += bounded ? 1 : 0;
+        const float x = (float)(rq.y + cq.y) + bound;
+        dsum += bounded ? __expf(x - m_ref) : 0.f;
+        max_bound = bounded ? fmaxf(max_bound, x) : max_bound;
         smask[bn] |= (in && !bounded) ? 1u << (16 * bm + e) : 0u;
       }
   }
   // survivors in a fixed order (bn, bm, element, lane)
   int n_surv = 0;
+  if (__ballot((smask[0] | smask[1]) != 0u)) {
 #pragma unroll
-  for (int bn = 0; bn < 2; ++bn)
+    for (int bn = 0; bn < 2; ++bn)
 #pragma unroll
-    for (int q = 0; q < 32; ++q) n_surv += (int)__popcll(__ballot((smask[bn] >> q) & 1u));
+      for (int q = 0; q < 32; ++q) n_surv += (int)__popcll(__ballot((smask[bn] >> q) & 1u));
+  }
   if (n_surv > kSurvCap) {
     // the whole tile goes to the fused kernel's batched epilogue
     if (lane == 0) {
@@ -435,31 +439,17 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
       a.surv_list[2 * k + 1] = n_surv;
     }
   }
-  // the tile's partial: bounded mass (m, s), counts, largest bound
-  auto add_i = [](int x, int y) { return x + y; };
-  const int w_np = wave_reduce(n_in, 0, add_i);
-  const int w_nb = wave_reduce(n_bounded, 0, add_i);
+  // the tile's partial: bounded mass (m_ref, sum), counts, largest bound
   const float w_mb = wave_reduce(max_bound, (float)-INFINITY, [](float x, float y) { return fmaxf(x, y); });
-  float dm = drop.m, ds = drop.s;
-  auto dmerge = [&](auto ctrl, auto rowmask) {
-    constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
-    LseF t{dm, ds};
-    t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
-    dm = t.m;
-    ds = t.s;
-  };
-  dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
-  dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+  const float w_ds = wave_reduce(dsum, 0.f, [](float x, float y) { return x + y; });
   if (lane == 63) {
+    const int n_in = rows_in * cols_in;
     double* out = a.partials + tile_id * kNPart;
     out[0] = -INFINITY; out[1] = 0.0; out[2] = 0.0;          // no pair evaluated (yet)
-    out[3] = dm == -INFINITY ? -INFINITY : (double)dm;
-    out[4] = ds; out[5] = 0.0; out[6] = 0.0; out[7] = (double)w_nb;
-    out[8] = (double)w_mb; out[9] = -INFINITY; out[10] = (double)w_np; out[11] = 0.0;
+    out[3] = w_ds > 0.f ? (double)m_ref : -INFINITY;
+    out[4] = w_ds > 0.f ? (double)w_ds : 0.0;
+    out[5] = 0.0; out[6] = 0.0; out[7] = (double)(n_in - n_surv);
+    out[8] = (double)w_mb; out[9] = -INFINITY; out[10] = (double)n_in; out[11] = 0.0;
   }
 }
 
