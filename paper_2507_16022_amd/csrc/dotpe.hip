@@ -1006,7 +1006,10 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   if (cut_delta > 0.0 && a.n_tiles_m > 1) {
     // pilot: max lnL^ML over every 64th row of tiles sets the cut threshold,
     // frozen before the main pass (so the cut does not depend on tile order)
-    a.pilot_stride = 64;
+    // every pilot_stride-th row of tiles: 1 in 64 on large events, and at
+    // least 16 rows of tiles on small ones (a sparse pilot there may miss the
+    // rows that set the maximum, and then nothing is cut)
+    a.pilot_stride = std::max<int64_t>(1, std::min<int64_t>(64, a.n_tiles_m / 16));
     int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
     if ((rc = launch_fused<kPilot>(ev->bank->prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
   }
