@@ -13,8 +13,10 @@
 //
 // Each wave's 64 x 64 quadrant is one tile of the fused kernel's grid.  A
 // quadrant all of whose pairs are bounded writes that tile's partial (the
-// bounded mass and counts); a quadrant with any surviving pair is listed,
-// and the fused kernel's batched epilogue evaluates the whole tile again.
+// bounded mass and counts); one with a few survivors lists them for the
+// survivor pass, which adds their evaluation to the partial; one with more
+// is listed whole for the coefficient route, which bounds and evaluates the
+// tile again.
 #pragma once
 
 #include "fused.h"
@@ -51,6 +53,8 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;    // (h|h) outputs: S0, Re/Im S_1..3
   constexpr int NS = BT::NS;
   extern __shared__ __align__(16) unsigned char smem[];
+  // with the cut off the coefficient route takes every tile
+  if (!cut_on(a)) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
       for (int q = 0; q < 32; ++q) n_surv += (int)__popcll(__ballot((smask[bn] >> q) & 1u));
   }
   if (n_surv > kSurvCap) {
-    // the whole tile goes to the fused kernel's batched epilogue
+    // the whole tile goes to the coefficient route
     if (lane == 0) {
       const unsigned long long k = atomicAdd((unsigned long long*)&a.state[4], 1ull);
       a.rerun[k] = (int)tile_id;
@@ -453,7 +457,7 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   }
 }
 
-// Survivor pass after the bound pass: one wave per listed tile evaluates its
+// Survivor pass after the bound pass: a wave per listed tile evaluates its
 // survivors one at a time.  For a survivor (i, e) the wave forms X_g and the
 // (h|h) phase coefficients as FP64 sums of the products of the split
 // operands (each value hi + lo is exact in double; lanes take chunks of the
@@ -474,149 +478,152 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
   for (int t = tid; t < (int)(sizeof(DistParams) / 4); t += 256)
     ((unsigned*)dp)[t] = ((const unsigned*)a.dist.prm)[t];
   __syncthreads();
+  // the workgroups' waves take the listed tiles in turn (the list's length
+  // is known on the device only)
   const int64_t n_list = (int64_t)a.state[5];
-  const int64_t item = (int64_t)blockIdx.x * 4 + (tid >> 6);
-  if (item >= n_list) return;
-  const int64_t tile_id = a.surv_list[2 * item];
-  const int n_surv = a.surv_list[2 * item + 1];
-  const int64_t tm = tile_id / a.n_tiles_n, tn = tile_id % a.n_tiles_n;
-  const double thr_ml = __longlong_as_double(a.state[3]) - a.cut_delta;
-  const double thr_topk_glob = order_value(a.state[1]) - a.topk_window;
-  const int nch = (int)(a.K2 >> 5);
-  auto val = [](const H* p, const H* q, int j) { return (double)(float)p[j] + (double)(float)q[j]; };
-  EvAcc ev;
-  ev.init();
-  double tile_max = -INFINITY;
-  for (int sidx = 0; sidx < n_surv; ++sidx) {
-    const unsigned rc = a.surv[tile_id * kSurvCap + sidx];
-    const int64_t ie = tm * 64 + (rc >> 8), e = tn * 64 + (rc & 255);
-    const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-    // X_g: lane l takes half l % 2 (8 positions of each slice) of chunks
-    // l / 2, l / 2 + 32, ...
-    double xr[G], xi[G];
+  for (int64_t item = (int64_t)blockIdx.x * 4 + (tid >> 6); item < n_list;
+       item += (int64_t)gridDim.x * 4) {
+    const int64_t tile_id = a.surv_list[2 * item];
+    const int n_surv = a.surv_list[2 * item + 1];
+    const int64_t tm = tile_id / a.n_tiles_n, tn = tile_id % a.n_tiles_n;
+    const double thr_ml = __longlong_as_double(a.state[3]) - a.cut_delta;
+    const double thr_topk_glob = order_value(a.state[1]) - a.topk_window;
+    const int nch = (int)(a.K2 >> 5);
+    auto val = [](const H* p, const H* q, int j) { return (double)(float)p[j] + (double)(float)q[j]; };
+    EvAcc ev;
+    ev.init();
+    double tile_max = -INFINITY;
+    for (int sidx = 0; sidx < n_surv; ++sidx) {
+      const unsigned rc = a.surv[tile_id * kSurvCap + sidx];
+      const int64_t ie = tm * 64 + (rc >> 8), e = tn * 64 + (rc & 255);
+      const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+      // X_g: lane l takes half l % 2 (8 positions of each slice) of chunks
+      // l / 2, l / 2 + 32, ...
+      double xr[G], xi[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) { xr[g] = 0.0; xi[g] = 0.0; }
-    const int h = lane & 1;
-    const int64_t arow = ((i >> 5) * (a.K2 >> 5)) * 1024 + (i & 31) * 8 + h * 256;
-    const int64_t brow = ((e >> 5) * (a.K2 >> 5)) * 1024 + (e & 31) * 8 + h * 256;
-    for (int c = lane >> 1; c < nch; c += 32) {
-      const H* a0h = (const H*)a.A0 + arow + (int64_t)c * 1024;
-      const H* a0l = (const H*)a.A1 + arow + (int64_t)c * 1024;
-      const H* b0h = (const H*)a.B0 + brow + (int64_t)c * 1024;
-      const H* b0l = (const H*)a.B1 + brow + (int64_t)c * 1024;
-      double re = 0.0, im = 0.0;
+      for (int g = 0; g < G; ++g) { xr[g] = 0.0; xi[g] = 0.0; }
+      const int h = lane & 1;
+      const int64_t arow = ((i >> 5) * (a.K2 >> 5)) * 1024 + (i & 31) * 8 + h * 256;
+      const int64_t brow = ((e >> 5) * (a.K2 >> 5)) * 1024 + (e & 31) * 8 + h * 256;
+      for (int c = lane >> 1; c < nch; c += 32) {
+        const H* a0h = (const H*)a.A0 + arow + (int64_t)c * 1024;
+        const H* a0l = (const H*)a.A1 + arow + (int64_t)c * 1024;
+        const H* b0h = (const H*)a.B0 + brow + (int64_t)c * 1024;
+        const H* b0l = (const H*)a.B1 + brow + (int64_t)c * 1024;
+        double re = 0.0, im = 0.0;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const double x0 = val(a0h, a0l, j), x1 = val(a0h + 512, a0l + 512, j);
-        const double y0 = val(b0h, b0l, j), y1 = val(b0h + 512, b0l + 512, j);
-        re += x0 * y0 + x1 * y1;      // A [hr | hi'] . B_re [Br | -Bi]
-        im += x1 * y0 - x0 * y1;      // A . B_im, B_im = [-(B_re slice 1) | B_re slice 0]
+        for (int j = 0; j < 8; ++j) {
+          const double x0 = val(a0h, a0l, j), x1 = val(a0h + 512, a0l + 512, j);
+          const double y0 = val(b0h, b0l, j), y1 = val(b0h + 512, b0l + 512, j);
+          re += x0 * y0 + x1 * y1;      // A [hr | hi'] . B_re [Br | -Bi]
+          im += x1 * y0 - x0 * y1;      // A . B_im, B_im = [-(B_re slice 1) | B_re slice 0]
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const bool in_g = c >= a.mt.gk0[g] && c < a.mt.gk0[g + 1];
+          xr[g] += in_g ? re : 0.0;
+          xi[g] += in_g ? im : 0.0;
+        }
       }
+      // (h|h) outputs: lanes 4 r .. 4 r + 3 take block r (slice, half)
+      double sv = 0.0;
+      if (lane < 4 * NRT) {
+        const int r = lane >> 2, s2 = (lane >> 1) & 1, h2 = lane & 1;
+        const int64_t ho = ((ie >> 5) * (a.KH >> 5) + r) * 1024 + s2 * 512 + h2 * 256 + (ie & 31) * 8;
+        const int64_t bo = ((e >> 5) * (a.KH >> 5) + r) * 1024 + s2 * 512 + h2 * 256 + (e & 31) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          sv += val((const H*)a.Ah0 + ho, (const H*)a.Ah1 + ho, j) *
+                val((const H*)a.Bh0 + bo, (const H*)a.Bh1 + bo, j);
+      }
+      // quad sums, then every lane reads the totals
+      sv += dpp_mov<0xB1, 0xF>(0.0, sv);
+      sv += dpp_mov<0x4E, 0xF>(0.0, sv);
+      auto add_d = [](double x, double y) { return x + y; };
+      const double sx = a.row_scale[i] * a.col_scale[e];
+      const double shh = a.ah_scale[ie] * a.bh_scale[e];
+      double2 X[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const bool in_g = c >= a.mt.gk0[g] && c < a.mt.gk0[g + 1];
-        xr[g] += in_g ? re : 0.0;
-        xi[g] += in_g ? im : 0.0;
+        X[g].x = sx * read_lane(wave_reduce(xr[g], 0.0, add_d), 63);
+        X[g].y = sx * read_lane(wave_reduce(xi[g], 0.0, add_d), 63);
+      }
+      double S0 = shh * read_lane(sv, 0), Sr[kMaxND], Si[kMaxND];
+#pragma unroll
+      for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0.0; Si[d] = 0.0; }
+#pragma unroll
+      for (int d = 1; d < (NRT + 1) / 2; ++d) {
+        Sr[d] = shh * read_lane(sv, 4 * (2 * d - 1));
+        Si[d] = shh * read_lane(sv, 4 * (2 * d));
+      }
+      const double lnw = (a.ln_w_bank ? a.ln_w_bank[i] : 0.0) + (a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
+      Lse lse;
+      lse.init();
+      double best = -INFINITY, mlmax = 0.0;
+      int ob = 0;
+      pair_phases<kEvidence, G>(a, lds_cs, *dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, lane, 64, ev, lse,
+                                best, ob, mlmax);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double lm = __shfl_xor(lse.m, off, 64), ls = __shfl_xor(lse.s, off, 64);
+        const double ls2 = __shfl_xor(lse.s2, off, 64);
+        lse.merge(lm, ls, ls2);
+        const double bv = __shfl_xor(best, off, 64);
+        const int bo = __shfl_xor(ob, off, 64);
+        if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }
+        mlmax = fmax(mlmax, __shfl_xor(mlmax, off, 64));
+      }
+      ev.ml_max = fmax(ev.ml_max, mlmax);
+      if (lane != 0 || lse.m == -INFINITY) continue;
+      const double lnp = lnw + lse.m + log(lse.s) - a.ln_nphi;
+      ev.p.add(lnp);
+      tile_max = fmax(tile_max, lnp);
+      if (lnp >= fmax(thr_topk_glob, tile_max - a.topk_window)) {
+        const unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
+        if ((int64_t)slot < a.cand_cap) {
+          double* cd = a.cand + 4 * slot;
+          cd[0] = lnp;
+          cd[1] = (double)i;
+          cd[2] = (double)e;
+          cd[3] = (double)ob;
+        }
       }
     }
-    // (h|h) outputs: lanes 4 r .. 4 r + 3 take block r (slice, half)
-    double sv = 0.0;
-    if (lane < 4 * NRT) {
-      const int r = lane >> 2, s2 = (lane >> 1) & 1, h2 = lane & 1;
-      const int64_t ho = ((ie >> 5) * (a.KH >> 5) + r) * 1024 + s2 * 512 + h2 * 256 + (ie & 31) * 8;
-      const int64_t bo = ((e >> 5) * (a.KH >> 5) + r) * 1024 + s2 * 512 + h2 * 256 + (e & 31) * 8;
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        sv += val((const H*)a.Ah0 + ho, (const H*)a.Ah1 + ho, j) *
-              val((const H*)a.Bh0 + bo, (const H*)a.Bh1 + bo, j);
+    // merge into the tile's partial: the cut phases' bounds (every lane), the
+    // evaluated pairs (lane 0), the phases marginalised
+    float dm = ev.drop.m, ds = ev.drop.s;
+    auto dmerge = [&](auto ctrl, auto rowmask) {
+      constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
+      LseF t{dm, ds};
+      t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
+      dm = t.m;
+      ds = t.s;
+    };
+    dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+    dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+    const int n_marg = wave_reduce(ev.n_marg, 0, [](int x, int y) { return x + y; });
+    const double dmd = read_lane(dm == -INFINITY ? -INFINITY : (double)dm, 63);
+    const double dsd = read_lane((double)ds, 63);
+    const int n_marg_all = __builtin_amdgcn_readlane(n_marg, 63);
+    if (lane == 0) {
+      double* out = a.partials + tile_id * kNPart;
+      Lse d;
+      d.m = out[3];
+      d.s = out[4];
+      d.s2 = 0.0;
+      d.merge(dmd, dsd, 0.0);
+      out[0] = ev.p.m; out[1] = ev.p.s; out[2] = ev.p.s2;
+      out[3] = d.m; out[4] = d.s;
+      out[5] = ev.ml_max; out[6] = (double)n_marg_all; out[9] = tile_max;
+      if (ev.ml_max > 0.0)
+        atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(ev.ml_max));
+      if (tile_max > -INFINITY)
+        atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(tile_max));
     }
-    // quad sums, then every lane reads the totals
-    sv += dpp_mov<0xB1, 0xF>(0.0, sv);
-    sv += dpp_mov<0x4E, 0xF>(0.0, sv);
-    auto add_d = [](double x, double y) { return x + y; };
-    const double sx = a.row_scale[i] * a.col_scale[e];
-    const double shh = a.ah_scale[ie] * a.bh_scale[e];
-    double2 X[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      X[g].x = sx * read_lane(wave_reduce(xr[g], 0.0, add_d), 63);
-      X[g].y = sx * read_lane(wave_reduce(xi[g], 0.0, add_d), 63);
-    }
-    double S0 = shh * read_lane(sv, 0), Sr[kMaxND], Si[kMaxND];
-#pragma unroll
-    for (int d = 0; d < kMaxND; ++d) { Sr[d] = 0.0; Si[d] = 0.0; }
-#pragma unroll
-    for (int d = 1; d < (NRT + 1) / 2; ++d) {
-      Sr[d] = shh * read_lane(sv, 4 * (2 * d - 1));
-      Si[d] = shh * read_lane(sv, 4 * (2 * d));
-    }
-    const double lnw = (a.ln_w_bank ? a.ln_w_bank[i] : 0.0) + (a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
-    Lse lse;
-    lse.init();
-    double best = -INFINITY, mlmax = 0.0;
-    int ob = 0;
-    pair_phases<kEvidence, G>(a, lds_cs, *dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, lane, 64, ev, lse,
-                              best, ob, mlmax);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double lm = __shfl_xor(lse.m, off, 64), ls = __shfl_xor(lse.s, off, 64);
-      const double ls2 = __shfl_xor(lse.s2, off, 64);
-      lse.merge(lm, ls, ls2);
-      const double bv = __shfl_xor(best, off, 64);
-      const int bo = __shfl_xor(ob, off, 64);
-      if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }
-      mlmax = fmax(mlmax, __shfl_xor(mlmax, off, 64));
-    }
-    ev.ml_max = fmax(ev.ml_max, mlmax);
-    if (lane != 0 || lse.m == -INFINITY) continue;
-    const double lnp = lnw + lse.m + log(lse.s) - a.ln_nphi;
-    ev.p.add(lnp);
-    tile_max = fmax(tile_max, lnp);
-    if (lnp >= fmax(thr_topk_glob, tile_max - a.topk_window)) {
-      const unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
-      if ((int64_t)slot < a.cand_cap) {
-        double* cd = a.cand + 4 * slot;
-        cd[0] = lnp;
-        cd[1] = (double)i;
-        cd[2] = (double)e;
-        cd[3] = (double)ob;
-      }
-    }
-  }
-  // merge into the tile's partial: the cut phases' bounds (every lane), the
-  // evaluated pairs (lane 0), the phases marginalised
-  float dm = ev.drop.m, ds = ev.drop.s;
-  auto dmerge = [&](auto ctrl, auto rowmask) {
-    constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
-    LseF t{dm, ds};
-    t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
-    dm = t.m;
-    ds = t.s;
-  };
-  dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
-  dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
-  dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
-  const int n_marg = wave_reduce(ev.n_marg, 0, [](int x, int y) { return x + y; });
-  const double dmd = read_lane(dm == -INFINITY ? -INFINITY : (double)dm, 63);
-  const double dsd = read_lane((double)ds, 63);
-  const int n_marg_all = __builtin_amdgcn_readlane(n_marg, 63);
-  if (lane == 0) {
-    double* out = a.partials + tile_id * kNPart;
-    Lse d;
-    d.m = out[3];
-    d.s = out[4];
-    d.s2 = 0.0;
-    d.merge(dmd, dsd, 0.0);
-    out[0] = ev.p.m; out[1] = ev.p.s; out[2] = ev.p.s2;
-    out[3] = d.m; out[4] = d.s;
-    out[5] = ev.ml_max; out[6] = (double)n_marg_all; out[9] = tile_max;
-    if (ev.ml_max > 0.0)
-      atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(ev.ml_max));
-    if (tile_max > -INFINITY)
-      atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(tile_max));
   }
 }
 

@@ -150,9 +150,11 @@ struct dotpe_event {
   int64_t cand_cap = 0;
   double* final_out = nullptr;
   double* final_blk = nullptr;
-  int* rerun = nullptr;          // tiles a fast evidence pass leaves to the batched epilogue
+  int* rerun = nullptr;          // tiles the fast or bound pass leaves to the coefficient route
   uint16_t* surv = nullptr;      // bound pass: listed survivors [n_tiles][kSurvCap]
   int* surv_list = nullptr;      // bound pass: (tile, count) of tiles with listed survivors
+  void* coef = nullptr;          // coefficient route: raw accumulators of coef_tiles tiles
+  int64_t coef_tiles = 0;
   hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<void*> allocs;
   uint64_t bytes = 0;
@@ -413,6 +415,8 @@ FusedArgs make_args(dotpe_ctx* ctx, dotpe_event* ev) {
   a.n_tiles_m = (ev->n_sub + tm - 1) / tm;
   a.n_tiles_n = (ev->n_ext + tn - 1) / tn;
   a.n_tiles = a.n_tiles_m * a.n_tiles_n;
+  a.coef = ev->coef;
+  a.coef_tiles = ev->coef_tiles;
   return a;
 }
 
@@ -424,15 +428,16 @@ bool finite_all(const double* p, size_t n) {
 
 // state words: [0] running max of lnL^ML (bits of a non-negative double),
 // [1] running max of ln p (ordered encoding), [2] candidate count,
-// [3] cut reference frozen after the pilot pass, [4] tiles to rerun
+// [3] cut reference frozen after the pilot pass, [4] tiles listed for the
+// coefficient route, [5] tiles whose survivors are listed
 __global__ void k_reset_state(uint64_t* st) {
   if (threadIdx.x == 0) {
     st[0] = 0ull;                       // bits of +0.0
     st[1] = 0x000fffffffffffffull;      // ordered encoding below every finite value
     st[2] = 0ull;
     st[3] = 0ull;
-    st[4] = 0ull;                       // tiles listed for a rerun
-    st[5] = 0ull;                       // tiles whose survivors are listed
+    st[4] = 0ull;
+    st[5] = 0ull;
   }
 }
 
@@ -656,6 +661,8 @@ namespace {
 struct EvDims {
   int nk = 0, nb = 0, nc = 0, n_bp = 0, n_phi = 0, KH = 0, NP = 0, prec = 0;
   int64_t ne = 0, ne_p = 0, n_sub = 0, K2 = 0, n_tiles = 0, cand_cap = 0;
+  int64_t coef_tiles = 0;          // tiles per chunk of the coefficient route
+  uint64_t coef_tile_bytes = 0;    // their raw accumulators, bytes per tile
   bool ln_w_ext = false, sub_idx = false;
 };
 
@@ -673,7 +680,9 @@ struct EvBuf {
   bool stage;
 };
 
-int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::vector<int>* terms) {
+// coef_cap: most bytes of the coefficient route's buffer (0: 8 GiB)
+int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::vector<int>* terms,
+               uint64_t coef_cap = 0) {
   if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
   if (d->n_phi < 1 || d->n_phi > kMaxPhi) return fail(DOTPE_E_INVALID_ARG, "n_phi=%d", d->n_phi);
   if (d->n_ext < 1) return fail(DOTPE_E_INVALID_ARG, "n_ext=%lld", (long long)d->n_ext);
@@ -732,6 +741,16 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
   int64_t cap = 1;
   while (cap < want) cap <<= 1;
   D->cand_cap = cap;
+  // coefficient route: chunks of whole tiles, enough to fill the device and
+  // few enough that a pass makes at most ~64 pairs of launches
+  {
+    const int G = bk->mt.G, nrt = G == 1 ? 1 : kMaxNR;
+    D->coef_tile_bytes = (uint64_t)(2 * G + nrt) * tm * tn * (bk->prec == kFP64 ? 8 : 4);
+    const uint64_t most = coef_cap ? coef_cap : (uint64_t(8) << 30);
+    int64_t c = std::max<int64_t>(2048, (D->n_tiles + 63) / 64);
+    c = std::min<int64_t>(c, (int64_t)(most / D->coef_tile_bytes));
+    D->coef_tiles = std::max<int64_t>(1, std::min(c, D->n_tiles));
+  }
   D->ln_w_ext = d->ln_w_ext != nullptr;
   D->sub_idx = d->sub_idx != nullptr;
   return DOTPE_OK;
@@ -769,6 +788,7 @@ std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) 
   v.push_back({(void**)&ev->final_blk, (size_t)((D.n_tiles + 4095) / 4096) * kNPart * 8, false});
   v.push_back({(void**)&ev->cand, (size_t)D.cand_cap * 32, false});
   v.push_back({(void**)&ev->rerun, (size_t)D.n_tiles * sizeof(int), false});
+  v.push_back({&ev->coef, (size_t)D.coef_tiles * D.coef_tile_bytes, false});
   if (D.prec != kFP64) {
     v.push_back({(void**)&ev->surv, (size_t)D.n_tiles * kSurvCap * sizeof(uint16_t), false});
     v.push_back({(void**)&ev->surv_list, (size_t)D.n_tiles * 2 * sizeof(int), false});
@@ -801,10 +821,10 @@ uint64_t block_bytes(const std::vector<EvBuf>& v) {
 // them are packed into the caller's device block of block_len bytes and
 // nothing is allocated.
 int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d, char* block,
-                   uint64_t block_len, hipStream_t s, dotpe_event** out) {
+                   uint64_t block_len, hipStream_t s, dotpe_event** out, uint64_t coef_cap = 0) {
   EvDims D;
   std::vector<int> terms;
-  int rc = event_dims(bk, d, &D, &terms);
+  int rc = event_dims(bk, d, &D, &terms, coef_cap);
   if (rc) return rc;
   HIP_OK(hipSetDevice(ctx->device));
   dotpe_event* ev = new dotpe_event();
@@ -826,6 +846,7 @@ int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc*
   ev->flags = d->flags;
   ev->KH = D.KH;
   ev->cand_cap = D.cand_cap;
+  ev->coef_tiles = D.coef_tiles;
   const ModeTables& mt = bk->mt;
   const int nb = D.nb, nk = D.nk, nc = D.nc;
   const int64_t ne = D.ne, n_sub = D.n_sub;
@@ -987,12 +1008,22 @@ int dotpe_eval_lnl(dotpe_ctx* ctx, dotpe_event* ev, double* lnl, double* ml_max,
   return DOTPE_OK;
 }
 
-// One evidence pass with cut `cut_delta` (<= 0: none): pilot, fused pass,
-// fixed-order finalisation.  Fills *out except the top-k fields and returns
-// the raw candidate count in *n_cand.
+// Persistent grids of the passes whose work is known on the device only
+constexpr int64_t kSurvGrid = 1024;   // workgroups of 4 waves, a listed tile per wave
+constexpr int64_t kCoefGrid = 1024;   // fused kernel, a tile per workgroup at a time
+constexpr int64_t kE2Grid = 4096;
+
+// One evidence pass with cut `cut_delta` (<= 0: none), every decision taken
+// on the device: pilot, then, if the threshold it freezes cuts, the bound
+// pass (or the fused kernel's fast pass on small events) with the survivor
+// pass; then the coefficient route over the tiles those leave (every tile
+// when the cut is off), chunk by chunk; then the fixed-order finalisation.
+// The host waits once, for the results.  Fills *out except the top-k
+// fields and returns the raw candidate count in *n_cand.
 static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
                          dotpe_evidence_result* out, uint64_t* n_cand) {
   hipStream_t s = ev->stream;
+  const int prec = ev->bank->prec;
   FusedArgs a = make_args(ctx, ev);
   a.cut_delta = cut_delta;
   int rc;
@@ -1000,64 +1031,58 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   a.partials = ev->partials;
   a.cand = ev->cand;
   a.cand_cap = ev->cand_cap;
-  const bool timed = ev->ev_t[0] != nullptr;
-  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
-  if (timed) HIP_OK(hipEventRecord(ev->ev_t[0], s));
-  if (cut_delta > 0.0 && a.n_tiles_m > 1) {
-    // pilot: max lnL^ML over every 64th row of tiles sets the cut threshold,
-    // frozen before the main pass (so the cut does not depend on tile order)
-    // every pilot_stride-th row of tiles: 1 in 64 on large events, and at
-    // least 16 rows of tiles on small ones (a sparse pilot there may miss the
-    // rows that set the maximum, and then nothing is cut)
-    a.pilot_stride = std::max<int64_t>(1, std::min<int64_t>(64, a.n_tiles_m / 16));
-    int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
-    if ((rc = launch_fused<kPilot>(ev->bank->prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
-  }
-  hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, ev->state);
-  if (timed) HIP_OK(hipEventRecord(ev->ev_t[1], s));
-  // the fast epilogue pays off when the frozen threshold cuts
-  uint64_t thr_bits = 0;
-  if (cut_delta > 0.0 && a.n_tiles_m > 1) {
-    HIP_OK(hipMemcpyAsync(&thr_bits, ev->state + 3, 8, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-  }
-  double thr_frozen;
-  std::memcpy(&thr_frozen, &thr_bits, 8);
-  const bool fast = cut_delta > 0.0 && thr_frozen - cut_delta > 0.0;
   a.rerun = ev->rerun;
   a.surv = ev->surv;
   a.surv_list = ev->surv_list;
   a.rec_cap = (ev->flags & DOTPE_FLAG_RERUN_ALL) ? 0 : (1 << 30);
-  int64_t grid = round_up(a.n_tiles, 8);
-  // the bound pass (128 x 128 tiles, split precisions) when the event has
-  // enough of them to fill the device; else the fused kernel's fast epilogue
-  const int64_t n_big = ((a.n_tiles_m + 1) / 2) * ((a.n_tiles_n + 1) / 2);
-  const bool bound_pass = fast && ev->bank->prec != kFP64 && n_big >= kBoundMinTiles &&
-                          !(ev->flags & (DOTPE_FLAG_NO_BOUND_PASS | DOTPE_FLAG_RERUN_ALL));
-  uint64_t n_rerun = 0, n_listed = 0;
-  if (fast) {
+  const bool timed = ev->ev_t[0] != nullptr;
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[0], s));
+  // the cut needs a pilot over other rows of tiles than the ones it cuts;
+  // without one the frozen threshold stays at zero and the cut is off
+  const bool may_cut = cut_delta > 0.0 && a.n_tiles_m > 1;
+  if (may_cut) {
+    // pilot: max lnL^ML over every pilot_stride-th row of tiles sets the
+    // cut threshold, frozen before the main pass (so the cut does not
+    // depend on tile order): 1 in 64 rows on large events, and at least 16
+    // rows of tiles on small ones (a sparse pilot there may miss the rows
+    // that set the maximum, and then nothing is cut)
+    a.pilot_stride = std::max<int64_t>(1, std::min<int64_t>(64, a.n_tiles_m / 16));
+    int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
+    if ((rc = launch_fused<kPilot>(prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
+  }
+  hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, ev->state);
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[1], s));
+  if (may_cut) {
+    // the bound pass (128 x 128 tiles, split precisions) when the event has
+    // enough of them to fill the device; else the fused kernel's fast pass.
+    // Both return at once when the frozen threshold does not cut.
+    const int64_t n_big = ((a.n_tiles_m + 1) / 2) * ((a.n_tiles_n + 1) / 2);
+    const bool bound_pass = prec != kFP64 && n_big >= kBoundMinTiles &&
+                            !(ev->flags & (DOTPE_FLAG_NO_BOUND_PASS | DOTPE_FLAG_RERUN_ALL));
     if (bound_pass) {
-      if ((rc = launch_fused<kBound>(ev->bank->prec, a, round_up(n_big, 8), s))) return rc;
+      if ((rc = launch_fused<kBound>(prec, a, round_up(n_big, 8), s))) return rc;
+      if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
+      const int64_t sg = std::min<int64_t>(kSurvGrid, (a.n_tiles + 3) / 4);
+      if ((rc = launch_fused<kSurvivors>(prec, a, sg, s))) return rc;
     } else {
-      if ((rc = launch_fused<kEvidence, true>(ev->bank->prec, a, grid, s))) return rc;
+      if ((rc = launch_fused<kEvidence, true>(prec, a, round_up(a.n_tiles, 8), s))) return rc;
+      if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
     }
-    if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
-    uint64_t cnt[2] = {0, 0};     // tiles to rerun, tiles with listed survivors
-    HIP_OK(hipMemcpyAsync(cnt, ev->state + 4, 16, hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    n_rerun = cnt[0];
-    n_listed = cnt[1];
-    if (cnt[1] > 0) {
-      if ((rc = launch_fused<kSurvivors>(ev->bank->prec, a, (int64_t)((cnt[1] + 3) / 4), s))) return rc;
+  } else if (timed) {
+    HIP_OK(hipEventRecord(ev->ev_t[3], s));
+  }
+  {
+    // coefficient route: chunks of coef_tiles work items, as many chunks as
+    // every tile would need; the kernels of a chunk past the device's count
+    // return at once
+    const int64_t C = ev->coef_tiles;
+    const int64_t n_chunks = (a.n_tiles + C - 1) / C;
+    for (int64_t c = 0; c < n_chunks; ++c) {
+      a.work0 = c * C;
+      if ((rc = launch_fused<kCoef>(prec, a, std::min(C, kCoefGrid), s))) return rc;
+      if ((rc = launch_fused<kE2>(prec, a, std::min(C, kE2Grid), s))) return rc;
     }
-    if (n_rerun > 0) {
-      FusedArgs b = a;
-      b.rerun_list = ev->rerun;
-      if ((rc = launch_fused<kEvidence, false>(ev->bank->prec, b, (int64_t)n_rerun, s))) return rc;
-    }
-  } else {
-    if ((rc = launch_fused<kEvidence, false>(ev->bank->prec, a, grid, s))) return rc;
-    if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
   }
   if (timed) HIP_OK(hipEventRecord(ev->ev_t[2], s));
   {
@@ -1071,10 +1096,13 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   }
   HIP_OK(hipGetLastError());
   double fo[kNPart];
-  uint64_t st[3];
+  uint64_t st[6];
   HIP_OK(hipMemcpyAsync(fo, ev->final_out, sizeof(fo), hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(st, ev->state, sizeof(st), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  double thr_frozen;
+  std::memcpy(&thr_frozen, &st[3], 8);
+  const bool cut = cut_delta > 0.0 && thr_frozen - cut_delta > 0.0;
   const double ln_norm = std::log(ev->n_norm) + std::log((double)ev->n_ext);
   dotpe_evidence_result r;
   std::memset(&r, 0, sizeof(r));
@@ -1091,10 +1119,12 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   r.max_ln_p = fo[9];
   r.n_pairs = (int64_t)fo[10];
   r.dd = ev->dd;
-  r.precision = ev->bank->prec;
-  r.cut_delta_used = cut_delta > 0.0 ? cut_delta : 0.0;
-  r.n_tiles_rerun = (int32_t)n_rerun;
-  r.n_tiles_listed = (int32_t)n_listed;
+  r.precision = prec;
+  r.cut_delta_used = cut ? cut_delta : 0.0;
+  // tiles of the coefficient route (all of them with the cut off), tiles
+  // whose survivors the survivor pass evaluated
+  r.n_tiles_rerun = (int32_t)(cut ? (int64_t)st[4] : a.n_tiles);
+  r.n_tiles_listed = (int32_t)st[5];
   if (timed) {
     float t_pilot = 0.f, t_all = 0.f, t_first = 0.f;
     HIP_OK(hipEventElapsedTime(&t_pilot, ev->ev_t[0], ev->ev_t[1]));
@@ -1194,22 +1224,28 @@ int dotpe_evidence_static(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_even
   std::vector<int> terms;
   int rc = event_dims(bk, d, &D, &terms);
   if (rc) return rc;
+  // the coefficient route's buffer takes what the rest leaves (at least
+  // one tile; its size per tile is a multiple of the block alignment)
   uint64_t need;
   {
     dotpe_event probe;
     EvStage st;
-    need = block_bytes(event_buffers(D, &probe, &st));
+    EvDims E = D;
+    E.coef_tiles = 1;
+    need = block_bytes(event_buffers(E, &probe, &st));
   }
   if (need > kScratchBytes)
     return fail(DOTPE_E_TOO_LARGE,
                 "event needs %llu bytes of device scratch; dotpe_evidence_static holds %llu",
                 (unsigned long long)need, (unsigned long long)kScratchBytes);
+  const uint64_t coef_cap = (kScratchBytes - need) / D.coef_tile_bytes * D.coef_tile_bytes +
+                            D.coef_tile_bytes;
   HIP_OK(hipSetDevice(ctx->device));
   ScratchSlot& slot = g_scratch[ctx->device];
   std::lock_guard<std::mutex> lk(slot.mu);
   dotpe_event* ev = nullptr;
   rc = set_event_impl(ctx, bk, d, (char*)slot.ptr, kScratchBytes,
-                      d->stream ? (hipStream_t)d->stream : ctx->stream, &ev);
+                      d->stream ? (hipStream_t)d->stream : ctx->stream, &ev, coef_cap);
   if (rc) return rc;
   dotpe_evidence_result r;
   rc = evidence_run(ctx, ev, &r, topk);     // untimed: the event has no HIP events

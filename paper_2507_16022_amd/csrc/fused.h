@@ -62,14 +62,19 @@ struct FusedArgs {
   int64_t cand_cap;
   int64_t n_tiles_m, n_tiles_n, n_tiles;
   int64_t pilot_stride;      // pilot pass: every pilot_stride-th row of tiles
-  int* rerun;                // fast evidence pass: tiles left to the batched epilogue
-  const int* rerun_list;     // batched pass over listed tiles only (NULL: all tiles)
+  int* rerun;                // fast or bound pass: tiles left to the coefficient route
   int rec_cap;               // fast pass: survivors a tile may have (<= the record area)
   // bound pass: survivors of tiles with at most kSurvCap of them, as
   // (row << 8 | column) within the tile, [n_tiles][kSurvCap]; and the list
   // of such tiles, (tile id, count) pairs, its length in state[5]
   uint16_t* surv;
   int* surv_list;
+  // coefficient route: work items work0 .. work0 + coef_tiles - 1 (tiles: all
+  // of them when the cut is off, else the rerun list), the raw accumulators
+  // of each stored at coef + (item - work0) * NCO * TM * TN, component-major
+  // (X_g re, im per group, then the (h|h) outputs), pairs row-major
+  void* coef;
+  int64_t work0, coef_tiles;
 };
 
 template <int PREC>
@@ -181,7 +186,22 @@ __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a
   }
 }
 
-enum Mode { kEval = 0, kEvidence = 1, kPilot = 2, kBound = 3, kSurvivors = 4 };
+enum Mode { kEval = 0, kEvidence = 1, kPilot = 2, kBound = 3, kSurvivors = 4, kCoef = 5, kE2 = 6 };
+
+// The cut of an evidence pass is on when the threshold frozen after the
+// pilot (state[3], the pilot's largest lnL^ML) less cut_delta is above
+// zero.  Then the fast or bound pass bounds every pair and lists the tiles
+// it leaves to the coefficient route; otherwise that route takes every
+// tile.  Every kernel of the pass takes this decision from device memory.
+__device__ __forceinline__ bool cut_on(const FusedArgs& a) {
+  return a.cut_delta > 0.0 && __longlong_as_double(a.state[3]) - a.cut_delta > 0.0;
+}
+__device__ __forceinline__ int64_t coef_work_count(const FusedArgs& a) {
+  return cut_on(a) ? (int64_t)a.state[4] : a.n_tiles;
+}
+__device__ __forceinline__ int64_t coef_tile(const FusedArgs& a, int64_t q) {
+  return cut_on(a) ? (int64_t)a.rerun[q] : q;
+}
 
 // Wave-wide reductions through DPP lane moves (no LDS round trips): pairs
 // of lanes, quads, half rows and rows of 16 are combined within rows, then
@@ -313,8 +333,84 @@ __device__ void pair_phases(const FusedArgs& a, const double* lds_cs, const Dist
   }
 }
 
+// The tile's partial from the per-thread accumulators: counts and maxima
+// by wave reductions, evaluated and dropped mass merged lane by lane, then
+// the waves' parts merged in wave order by thread 0 (a fixed order); red is
+// LDS [NW][kNPart], tile_lnp_max the tile's largest ln p (ordered bits).
+template <int NW>
+__device__ __forceinline__ void tile_partial(const FusedArgs& a, const EvAcc& ev, int n_pairs_i,
+                                             int n_bounded_i, double* red,
+                                             const unsigned long long* tile_lnp_max,
+                                             int64_t tile_id) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    // counts and maxima: wave reductions, then one lane per wave
+    auto add_i = [](int x, int y) { return x + y; };
+    const int w_np = wave_reduce(n_pairs_i, 0, add_i);
+    const int w_nb = wave_reduce(n_bounded_i, 0, add_i);
+    const int w_nm = wave_reduce(ev.n_marg, 0, add_i);
+    const double w_ml = wave_reduce(ev.ml_max, 0.0, [](double x, double y) { return fmax(x, y); });
+    const float w_mb = wave_reduce(ev.max_bound, (float)-INFINITY, [](float x, float y) { return fmaxf(x, y); });
+    // dropped mass: (m, s) pairs merged the same way
+    float dm = ev.drop.m, ds = ev.drop.s;
+    auto dmerge = [&](auto ctrl, auto rowmask) {
+      constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
+      LseF t{dm, ds};
+      t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
+      dm = t.m;
+      ds = t.s;
+    };
+    dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
+    dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+    dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
+    // evaluated pairs: a few lanes of the wave at most, merged in lane order
+    Lse p;
+    p.init();
+    unsigned long long pl = __ballot(ev.p.m != -INFINITY);
+    while (pl) {
+      const int src = __ffsll((long long)pl) - 1;
+      p.merge(read_lane(ev.p.m, src), read_lane(ev.p.s, src), read_lane(ev.p.s2, src));
+      pl &= pl - 1;
+    }
+    if (lane == 63) {
+      double* r = red + wave * kNPart;
+      r[0] = p.m; r[1] = p.s; r[2] = p.s2;
+      r[3] = dm == -INFINITY ? -INFINITY : (double)dm;
+      r[4] = ds; r[5] = w_ml; r[6] = (double)w_nm; r[7] = (double)w_nb; r[8] = (double)w_mb;
+      r[10] = (double)w_np;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Lse p, d;
+    p.init(); d.init();
+    double mlm = 0.0, mb = -INFINITY, nm = 0, nb = 0, np_ = 0;
+    for (int w = 0; w < NW; ++w) {
+      const double* r = red + w * kNPart;
+      p.merge(r[0], r[1], r[2]);
+      d.merge(r[3], r[4], 0.0);
+      mlm = fmax(mlm, r[5]);
+      nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); np_ += r[10];
+    }
+    // every wave's E2 has finished (barrier above): the tile maximum is final
+    const double mxp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
+    double* out = a.partials + tile_id * kNPart;
+    out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
+    out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
+    // running maxima (the results are not waited for)
+    if (mlm > 0.0) atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
+    if (mxp > -INFINITY) atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(mxp));
+  }
+}
+
+// One tile (tm, tn) of the fused kernel; `slot` is the work item's place
+// in the coefficient buffer (kCoef only).
 template <int PREC, int G, int MODE, bool FAST>
-__global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
+__device__ __forceinline__ void fused_tile(const FusedArgs& a, unsigned char* smem, int64_t tm,
+                                           int64_t tn, int64_t slot) {
   constexpr bool EVAL = MODE == kEval;
   // (h|h) outputs: a single m group has S0 only; otherwise up to 7, padded
   // to an even number of K blocks
@@ -327,7 +423,6 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   typedef typename P::T T;
   typedef typename P::Acc Acc;
   constexpr int TM = TL::TM, TN = TL::TN, PITCH = P::PITCH, NT = TL::NT, NW = TL::NW;
-  extern __shared__ __align__(16) unsigned char smem[];
   T* stage = (T*)smem;
   double* lds_cs = (double*)(smem + TL::CS_OFF);
   DistParams* lds_dp = (DistParams*)(smem + TL::DP_OFF);
@@ -335,36 +430,6 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / P::WN, wn = wave % P::WN;
 
-  // workgroup -> tile: spread consecutive ids over the XCDs so that each XCD
-  // walks a contiguous band of tiles, then raster in bands of 4 tile rows
-  // (the ~32 tiles an XCD runs at once then share 4 row blocks and 8 column
-  // blocks of operands in its L2)
-  int64_t wg = blockIdx.x;
-  int64_t tm, tn;
-  if (a.rerun_list) {
-    // a tile listed by a fast or bound pass (row-major tile id)
-    const int64_t t = a.rerun_list[blockIdx.x];
-    tm = t / a.n_tiles_n;
-    tn = t % a.n_tiles_n;
-  } else {
-    int64_t nwg = gridDim.x;              // multiple of 8
-    wg = (wg % 8) * (nwg / 8) + wg / 8;
-    if (MODE == kPilot) {
-      // every pilot_stride-th row of tiles, all columns
-      int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
-      if (wg >= npr * a.n_tiles_n) return;
-      tm = (wg / a.n_tiles_n) * a.pilot_stride;
-      tn = wg % a.n_tiles_n;
-    } else {
-      if (wg >= a.n_tiles) return;
-      const int64_t GM = 4;
-      int64_t band = wg / (GM * a.n_tiles_n);
-      int64_t rows_in_band = min(GM, a.n_tiles_m - band * GM);
-      int64_t in = wg - band * GM * a.n_tiles_n;
-      tm = band * GM + in % rows_in_band;
-      tn = in / rows_in_band;
-    }
-  }
   // partials and rerun lists are indexed by the row-major tile id
   const int64_t tile_id = tm * a.n_tiles_n + tn;
   const int64_t row0 = tm * TM, col0 = tn * TN;
@@ -822,6 +887,38 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
 
   // ---- epilogue ----
   typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
+  // output element r of a lane's accumulator block sits in row rowmap(r),
+  // column lane mod BS (16x16x4 FP64 and 32x32x16 split-precision layouts)
+  auto rowmap = [&](int r) {
+    return (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
+  };
+  constexpr int BS = P::BS, NE = P::NE;
+  if constexpr (MODE == kCoef) {
+    // the raw accumulators to the coefficient buffer, as the accumulator
+    // type: component-major, pairs row-major (a row of a block is BS
+    // consecutive elements)
+    constexpr int NCO = 2 * G + NRT, NPT = TM * TN;
+    AT* cf = (AT*)a.coef + slot * (int64_t)(NCO * NPT);
+#pragma unroll
+    for (int bm = 0; bm < P::BM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < P::BN; ++bn) {
+        const int tc = wn * BS * P::BN + bn * BS + (lane & (BS - 1));
+#pragma unroll
+        for (int r = 0; r < NE; ++r) {
+          const int tr = wm * BS * P::BM + bm * BS + rowmap(r);
+          AT* o = cf + tr * TN + tc;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            o[(2 * g) * NPT] = (AT)acc[g][bm][bn][0][r];
+            o[(2 * g + 1) * NPT] = (AT)acc[g][bm][bn][1][r];
+          }
+#pragma unroll
+          for (int q = 0; q < NRT; ++q) o[(2 * G + q) * NPT] = (AT)acch[q][bm][bn][r];
+        }
+      }
+    return;
+  }
   double thr_ml = -INFINITY, thr_topk_glob = -INFINITY;
   if (MODE == kEvidence) {
     // the cut threshold is the one frozen after the pilot pass, so which
@@ -838,12 +935,6 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   int n_pairs_i = 0, n_bounded_i = 0;
   AT* recs = (AT*)smem;                  // [BATCH][REC] survivors' records
   constexpr int XO = 0, SO = 2 * G;      // offsets of X and S in a record
-  // output element r of a lane's accumulator block sits in row rowmap(r),
-  // column lane mod BS (16x16x4 FP64 and 32x32x16 split-precision layouts)
-  auto rowmap = [&](int r) {
-    return (PREC == kFP64) ? ((lane >> 4) + 4 * r) : (8 * (r >> 2) + 4 * (lane >> 5) + (r & 3));
-  };
-  constexpr int BS = P::BS, NE = P::NE;
   // per column of this lane for the E1 bound: col_scale^2 / bh_scale and ln w
   double colq[P::BN], colw[P::BN];
 #pragma unroll
@@ -1037,8 +1128,8 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   if constexpr (FAST) {
     // every pair of the tile through E1 first, then one E2 once the
     // accumulators are dead.  A tile with more survivors than the record
-    // area holds is left to a second launch of the batched epilogue: it is
-    // listed and contributes nothing here.
+    // area holds is left to the coefficient route: it is listed and
+    // contributes nothing here.
     static_assert(P::BM * P::BN * NE <= 32, "survivor mask");
     unsigned sm = 0;
     static_for<P::BM>([&](auto bmi) {
@@ -1110,67 +1201,48 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
   ev.n_bounded = (double)n_bounded_i;
 
   // ---- tile reduction ----
-  double* red = (double*)(smem + TL::RED_OFF);   // [NW][kNPart]
-  {
-    // counts and maxima: wave reductions, then one lane per wave
-    auto add_i = [](int x, int y) { return x + y; };
-    const int w_np = wave_reduce(n_pairs_i, 0, add_i);
-    const int w_nb = wave_reduce(n_bounded_i, 0, add_i);
-    const int w_nm = wave_reduce(ev.n_marg, 0, add_i);
-    const double w_ml = wave_reduce(ev.ml_max, 0.0, [](double x, double y) { return fmax(x, y); });
-    const float w_mb = wave_reduce(ev.max_bound, (float)-INFINITY, [](float x, float y) { return fmaxf(x, y); });
-    // dropped mass: (m, s) pairs merged the same way
-    float dm = ev.drop.m, ds = ev.drop.s;
-    auto dmerge = [&](auto ctrl, auto rowmask) {
-      constexpr int C = decltype(ctrl)::value, RM = decltype(rowmask)::value;
-      LseF t{dm, ds};
-      t.merge(dpp_mov<C, RM>(-INFINITY, dm), dpp_mov<C, RM>(0.f, ds));
-      dm = t.m;
-      ds = t.s;
-    };
-    dmerge(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
-    dmerge(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
-    dmerge(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
-    dmerge(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
-    dmerge(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
-    dmerge(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});
-    // evaluated pairs: a few lanes of the wave at most, merged in lane order
-    Lse p;
-    p.init();
-    unsigned long long pl = __ballot(ev.p.m != -INFINITY);
-    while (pl) {
-      const int src = __ffsll((long long)pl) - 1;
-      p.merge(read_lane(ev.p.m, src), read_lane(ev.p.s, src), read_lane(ev.p.s2, src));
-      pl &= pl - 1;
+  tile_partial<NW>(a, ev, n_pairs_i, n_bounded_i, (double*)(smem + TL::RED_OFF), tile_lnp_max,
+                   tile_id);
+}
+
+template <int PREC, int G, int MODE, bool FAST>
+__global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if constexpr (MODE == kCoef) {
+    // coefficient route: the workgroups take the chunk's work items in turn
+    const int64_t end = min(a.work0 + a.coef_tiles, coef_work_count(a));
+    for (int64_t q = a.work0 + blockIdx.x; q < end; q += gridDim.x) {
+      const int64_t t = coef_tile(a, q);
+      fused_tile<PREC, G, MODE, FAST>(a, smem, t / a.n_tiles_n, t % a.n_tiles_n, q - a.work0);
+      __syncthreads();
     }
-    if (lane == 63) {
-      double* r = red + wave * kNPart;
-      r[0] = p.m; r[1] = p.s; r[2] = p.s2;
-      r[3] = dm == -INFINITY ? -INFINITY : (double)dm;
-      r[4] = ds; r[5] = w_ml; r[6] = (double)w_nm; r[7] = (double)w_nb; r[8] = (double)w_mb;
-      r[10] = (double)w_np;
+  } else {
+    // the fast pass only runs when the cut is on
+    if (MODE == kEvidence && FAST && !cut_on(a)) return;
+    // workgroup -> tile: spread consecutive ids over the XCDs so that each
+    // XCD walks a contiguous band of tiles, then raster in bands of 4 tile
+    // rows (the ~32 tiles an XCD runs at once then share 4 row blocks and 8
+    // column blocks of operands in its L2)
+    int64_t wg = blockIdx.x;
+    int64_t tm, tn;
+    const int64_t nwg = gridDim.x;              // multiple of 8
+    wg = (wg % 8) * (nwg / 8) + wg / 8;
+    if (MODE == kPilot) {
+      // every pilot_stride-th row of tiles, all columns
+      const int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
+      if (wg >= npr * a.n_tiles_n) return;
+      tm = (wg / a.n_tiles_n) * a.pilot_stride;
+      tn = wg % a.n_tiles_n;
+    } else {
+      if (wg >= a.n_tiles) return;
+      const int64_t GM = 4;
+      const int64_t band = wg / (GM * a.n_tiles_n);
+      const int64_t rows_in_band = min(GM, a.n_tiles_m - band * GM);
+      const int64_t in = wg - band * GM * a.n_tiles_n;
+      tm = band * GM + in % rows_in_band;
+      tn = in / rows_in_band;
     }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    Lse p, d;
-    p.init(); d.init();
-    double mlm = 0.0, mb = -INFINITY, nm = 0, nb = 0, np_ = 0;
-    for (int w = 0; w < NW; ++w) {
-      const double* r = red + w * kNPart;
-      p.merge(r[0], r[1], r[2]);
-      d.merge(r[3], r[4], 0.0);
-      mlm = fmax(mlm, r[5]);
-      nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); np_ += r[10];
-    }
-    // every wave's E2 has finished (barrier above): the tile maximum is final
-    const double mxp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
-    double* out = a.partials + tile_id * kNPart;
-    out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
-    out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
-    // running maxima (the results are not waited for)
-    if (mlm > 0.0) atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
-    if (mxp > -INFINITY) atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(mxp));
+    fused_tile<PREC, G, MODE, FAST>(a, smem, tm, tn, 0);
   }
 }
 

@@ -64,15 +64,24 @@ hipError_t launch_survivors(const FusedArgs& a, int64_t grid, hipStream_t s) {
 }
 
 template <int PREC, int G>
+hipError_t launch_e2(const FusedArgs& a, int64_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_e2_tiles<PREC, G>), dim3((unsigned)grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int PREC, int G>
 hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hipStream_t s) {
   switch (mode) {
     case kEval: return launch_one<PREC, G, kEval, false>(a, grid, s);
     case kPilot: return launch_one<PREC, G, kPilot, false>(a, grid, s);
     case kEvidence:
-      return fast ? launch_one<PREC, G, kEvidence, true>(a, grid, s)
-                  : launch_one<PREC, G, kEvidence, false>(a, grid, s);
+      // only the fast pass: without the cut every tile takes the
+      // coefficient route
+      return fast ? launch_one<PREC, G, kEvidence, true>(a, grid, s) : hipErrorInvalidValue;
     case kBound: return launch_bound<PREC, G>(a, grid, s);
     case kSurvivors: return launch_survivors<PREC, G>(a, grid, s);
+    case kCoef: return launch_one<PREC, G, kCoef, false>(a, grid, s);
+    case kE2: return launch_e2<PREC, G>(a, grid, s);
   }
   return hipErrorInvalidValue;
 }

@@ -7,14 +7,17 @@
 #include <hip/hip_runtime.h>
 
 #include "bound.h"
+#include "e2.h"
 #include "fused.h"
 
 namespace dotpe {
 
-// mode: kEval, kPilot, kEvidence (fast only with kEvidence), kBound
-// (split precisions; `grid` counts 128 x 128 tiles) or kSurvivors (split
-// precisions; `grid` workgroups of 4 listed tiles).  Launches `grid`
-// workgroups on stream s and returns the launch status.
+// mode: kEval, kPilot, kEvidence (the fast pass: fast must be true),
+// kBound (split precisions; `grid` counts 128 x 128 tiles), kSurvivors
+// (split precisions; workgroups of 4 waves that take the listed tiles in
+// turn), kCoef or kE2 (the coefficient route: workgroups that take the
+// chunk's work items in turn).  Launches `grid` workgroups on stream s and
+// returns the launch status.
 typedef hipError_t (*FusedLaunchFn)(int mode, bool fast, const FusedArgs& a, int64_t grid,
                                     hipStream_t s);
 

@@ -37,7 +37,7 @@ def _run(ctx, bank, wl, **kw):
 
 
 @pytest.mark.parametrize("prec", ["fp16x2", "bf16x2"])
-@pytest.mark.parametrize("cut", [40.0, 12.0])
+@pytest.mark.parametrize("cut", [40.0, 12.0, 0.0])
 @pytest.mark.parametrize("rows", ["range", "scattered"])
 def test_bound_pass_agrees(env, prec, cut, rows):
     dotpe, wl, ctx, banks = env
