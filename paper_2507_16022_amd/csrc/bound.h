@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
         Si[d] = shh * read_lane(sv, 4 * (2 * d));
       }
       const double lnw = (a.ln_w_bank ? a.ln_w_bank[i] : 0.0) + (a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
-      Lse lse;
+      LsePh lse;
       lse.init();
       double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
@@ -566,8 +566,7 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const double lm = __shfl_xor(lse.m, off, 64), ls = __shfl_xor(lse.s, off, 64);
-        const double ls2 = __shfl_xor(lse.s2, off, 64);
-        lse.merge(lm, ls, ls2);
+        lse.merge(lm, ls);
         const double bv = __shfl_xor(best, off, 64);
         const int bo = __shfl_xor(ob, off, 64);
         if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }

@@ -121,6 +121,32 @@ struct Lse {
   }
 };
 
+// online log-sum-exp over the phases of one pair: FP64 running maximum and
+// sum, each term's exponential taken in FP32 (a relative error ~1e-7, far
+// inside the tolerance on ln Lbar; a term more than ~87 below the running
+// maximum, under 1e-37 of the sum, counts as zero); one exponential and no
+// branch per term
+struct LsePh {
+  double m, s;
+  __device__ void init() { m = -INFINITY; s = 0.0; }
+  __device__ void add(double x) {
+    const double d = x - m;                       // +inf while empty
+    const double t = (double)__expf(-fabsf((float)d));
+    const bool up = d > 0.0;
+    const double ns = up ? fma(s, t, 1.0) : s + t;
+    const bool skip = !(x > -INFINITY);
+    s = skip ? s : ns;
+    m = (up && !skip) ? x : m;
+  }
+  __device__ void merge(double mb, double sb) {
+    if (mb == -INFINITY) return;
+    if (m == -INFINITY) { m = mb; s = sb; return; }
+    const double mm = fmax(m, mb);
+    s = s * exp(m - mm) + sb * exp(mb - mm);
+    m = mm;
+  }
+};
+
 __device__ __forceinline__ uint64_t order_bits(double x) {
   uint64_t u = __double_as_longlong(x);
   return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);

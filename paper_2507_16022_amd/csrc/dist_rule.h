@@ -35,18 +35,20 @@ namespace dotpe {
 // uniform segments (finer where the prior-dominated and peak-dominated
 // regimes of the integrand cross), each stored with its own columns; rows
 // are uniform in tau
-constexpr int kDrSeg = 3;
+constexpr int kDrSeg = 4;
 struct DistTableGeom {
   double zs0[kDrSeg], hz[kDrSeg];   // first stored column and step per segment
+  double ihz[kDrSeg], iht;          // reciprocal steps (the reader multiplies)
   double zlo[kDrSeg], zhi[kDrSeg];  // z range served by each segment
   int nz[kDrSeg], off[kDrSeg];      // columns per segment, column offset of its block
   double t0, ht;                    // tau_k = t0 + k ht, k < nt
   int nt, ncol;                     // rows, total columns
 };
 
-constexpr double kDrZ0 = -12.0, kDrZ1 = 32.0;
-constexpr double kDrSegEdge[kDrSeg + 1] = {-12.0, 2.0, 14.0, 32.0};
-constexpr double kDrSegStep[kDrSeg] = {0.05, 0.0125, 0.05};
+// (strongly negative z, the anti-aligned phases of loud pairs, is smooth and
+// takes a coarser step)
+constexpr double kDrSegEdge[kDrSeg + 1] = {-64.0, -12.0, 2.0, 14.0, 32.0};
+constexpr double kDrSegStep[kDrSeg] = {0.1, 0.05, 0.0125, 0.05};
 constexpr double kDrT0 = -20.5, kDrT1 = 20.0, kDrHt = 0.025;
 constexpr double kDrSMin = 1e-9;     // below: small-s expansion
 constexpr int kGH = 12;              // Gauss-Hermite nodes for the tail
@@ -57,6 +59,7 @@ __host__ __device__ inline DistTableGeom dr_make_geom() {
   for (int k = 0; k < kDrSeg; ++k) {
     double h = kDrSegStep[k];
     g.hz[k] = h;
+    g.ihz[k] = 1.0 / h;
     g.zlo[k] = kDrSegEdge[k];
     g.zhi[k] = kDrSegEdge[k + 1];
     g.zs0[k] = kDrSegEdge[k] - 2.0 * h;       // two guard columns each side
@@ -67,6 +70,7 @@ __host__ __device__ inline DistTableGeom dr_make_geom() {
   g.ncol = off;
   g.t0 = kDrT0;
   g.ht = kDrHt;
+  g.iht = 1.0 / kDrHt;
   g.nt = (int)((kDrT1 - kDrT0) / kDrHt + 0.5) + 1;
   return g;
 }
@@ -248,10 +252,11 @@ __host__ __device__ __forceinline__ void dr_lagrange4(double t, double* c) {
 
 __host__ __device__ __forceinline__ bool dr_table_lookup(const double* tab, const DistTableGeom& g,
                                                          double z, double tau, double* out) {
+  // segments are contiguous: count the upper edges at or below z
+  if (!(z >= g.zlo[0] && z < g.zhi[kDrSeg - 1])) return false;
   int k = 0;
-  while (k < kDrSeg && !(z >= g.zlo[k] && z < g.zhi[k])) ++k;
-  if (k == kDrSeg) return false;
-  double fz = (z - g.zs0[k]) / g.hz[k], ft = (tau - g.t0) / g.ht;
+  for (int q = 0; q + 1 < kDrSeg; ++q) k += z >= g.zhi[q] ? 1 : 0;
+  double fz = (z - g.zs0[k]) * g.ihz[k], ft = (tau - g.t0) * g.iht;
   int jz = (int)floor(fz), jt = (int)floor(ft);
   if (jz < 1 || jz > g.nz[k] - 3 || jt < 1 || jt > g.nt - 3) return false;
   double cz[4], ct[4];
@@ -287,6 +292,24 @@ __host__ __device__ inline double dr_ln_marg(double dh, double hh, double d0_ove
   double v;
   if (dr_table_lookup(tab, g, z, dr_tau_of_s(s), &v)) return v;
   return dr_ln_exact(z, s);
+}
+
+// The same rule with its most frequent case inlined: a triple that the
+// full rule would read from the table is read here (the same arithmetic, so
+// the same value); any other calls the full rule.  For callers that
+// evaluate many triples in a loop.
+__host__ __device__ __attribute__((always_inline)) inline double dr_ln_marg_inl(
+    double dh, double hh, double d0_over_dmax, const double* tab, const DistTableGeom& g,
+    const double* ghx, const double* ghw) {
+  if (hh > 0.0) {
+    const double sq = sqrt(hh);
+    const double z = dh / sq, s = sq * d0_over_dmax;
+    if (s >= kDrSMin && !dr_tail_ok(z, s)) {
+      double v;
+      if (dr_table_lookup(tab, g, z, dr_tau_of_s(s), &v)) return v;
+    }
+  }
+  return dr_ln_marg(dh, hh, d0_over_dmax, tab, g, ghx, ghw);
 }
 
 }  // namespace dotpe

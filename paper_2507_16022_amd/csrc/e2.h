@@ -130,12 +130,12 @@ __global__ __launch_bounds__(256) void k_e2_tiles(FusedArgs a) {
       }
       const double lnw = rowd[tr * 4] + cold[tc * 3];
       const int64_t e = col0 + tc;
-      Lse lse;
+      LsePh lse;
       lse.init();
       double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
-      pair_phases<kEvidence, G>(a, lds_cs, dp, row0 + tr, e, X, S0, Sr, Si, lnw, thr_ml, 0, 1, ev,
-                                lse, best, ob, mlmax);
+      pair_phases<kEvidence, G, false>(a, lds_cs, dp, row0 + tr, e, X, S0, Sr, Si, lnw, thr_ml, 0, 1,
+                                      ev, lse, best, ob, mlmax);
       ev.ml_max = fmax(ev.ml_max, mlmax);
       if (lse.m == -INFINITY) continue;
       const double lnp = lnw + (lse.m + log(lse.s) - a.ln_nphi);

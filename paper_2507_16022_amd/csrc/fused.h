@@ -284,17 +284,21 @@ struct EvAcc {
 // coefficients: cut, distance marginalisation.  The kept phases' ln L go to
 // lse, the best one to best / o_best (first of equal values), the largest
 // lnL^ML to mlmax; cut phases' upper bounds go to ev.drop.  The caller
-// combines the parts of one pair.
-template <int MODE, int G>
+// combines the parts of one pair.  INL: the distance rule inlined (for a
+// kernel whose lanes each evaluate many pairs).
+template <int MODE, int G, bool INL = false>
 __device__ void pair_phases(const FusedArgs& a, const double* lds_cs, const DistParams& dp,
                             int64_t ie, int64_t e,
                             const double2 (&X)[G], double S0, const double (&Sr)[kMaxND],
                             const double (&Si)[kMaxND], double lnw, double thr_ml, int o0, int os,
-                            EvAcc& ev, Lse& lse, double& best, int& o_best, double& mlmax) {
+                            EvAcc& ev, LsePh& lse, double& best, int& o_best, double& mlmax) {
   constexpr bool EVAL = MODE == kEval;
   const ModeTables& mt = a.mt;
   const int ND = mt.ND;
   const double thr2 = 2.0 * thr_ml;
+  // the largest lnL^ML = dh^2 / (2 hh), kept as a fraction (mn / md) and
+  // divided once at the end
+  double mn = 0.0, md = 1.0;
   for (int o = o0; o < a.n_phi; o += os) {
     double dh = 0.0;
 #pragma unroll
@@ -316,21 +320,26 @@ __device__ void pair_phases(const FusedArgs& a, const double* lds_cs, const Dist
       a.trip_out[t] = dh;
       a.trip_out[t + 1] = hh;
     }
-    // lnL^ML >= thr  <=>  dh > 0 and dh^2 >= 2 thr hh (no division)
-    const bool keep = EVAL || thr_ml <= 0.0 || (dh > 0.0 && dh * dh >= thr2 * hh);
-    double ml = (dh > 0.0 && hh > 0.0) ? dh * dh / (2.0 * hh) : 0.0;
-    mlmax = fmax(mlmax, ml);
+    const bool pos = dh > 0.0 && hh > 0.0;
+    const double dh2 = dh * dh;
+    if (pos && dh2 * md > mn * hh) { mn = dh2; md = hh; }
     if (MODE == kPilot) continue;
+    // lnL^ML >= thr  <=>  dh > 0 and dh^2 >= 2 thr hh (no division)
+    const bool keep = EVAL || thr_ml <= 0.0 || (dh > 0.0 && dh2 >= thr2 * hh);
     if (!keep) {
+      const double ml = pos ? dh2 / (2.0 * hh) : 0.0;
       float x = (float)(lnw + ml - a.ln_nphi);
       ev.drop.add(x + fabsf(x) * 1e-6f + 1e-5f);   // rounding margin keeps it a bound
       continue;
     }
-    double v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, dp.geom, dp.ghx, dp.ghw);
+    double v;
+    if constexpr (INL) v = dr_ln_marg_inl(dh, hh, a.r0, a.dist.tab, dp.geom, dp.ghx, dp.ghw);
+    else v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, dp.geom, dp.ghx, dp.ghw);
     if (v > best) { best = v; o_best = o; }
     lse.add(v);
     if (!EVAL) ev.n_marg += 1;
   }
+  mlmax = fmax(mlmax, mn / (2.0 * md));
 }
 
 // The tile's partial from the per-thread accumulators: counts and maxima
@@ -1074,7 +1083,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, unsigned char* sm
         Si[d] = sh * (double)xq[SO + 2 * d];
       }
       double lnw = rowd[tr * 4] + cold[tcs * 3];
-      Lse lse;
+      LsePh lse;
       lse.init();
       double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
@@ -1083,8 +1092,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, unsigned char* sm
 #pragma unroll
       for (int off = LPS / 2; off > 0; off >>= 1) {
         const double lm = __shfl_xor(lse.m, off, LPS), ls = __shfl_xor(lse.s, off, LPS);
-        const double ls2 = __shfl_xor(lse.s2, off, LPS);
-        lse.merge(lm, ls, ls2);
+        lse.merge(lm, ls);
         const double bv = __shfl_xor(best, off, LPS);
         const int bo = __shfl_xor(ob, off, LPS);
         if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }

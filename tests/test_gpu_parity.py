@@ -60,6 +60,18 @@ def test_distance_rule_vs_oracle(ctx):
     err_s = np.abs(got[sharp] - ref_s)
     print("distance rule, sharp peaks: max err", err_s.max(), "n", len(sharp), flush=True)
     assert len(sharp) >= 100 and err_s.max() < 5e-7
+    # the anti-aligned phases of loud pairs (z down to -60): the table's
+    # coarse segment, against the adaptive-quadrature oracle
+    sn = np.exp(rng.uniform(np.log(1e-3), np.log(20.0), 300))
+    zn = rng.uniform(-60.0, -10.0, 300)
+    hn = (sn * dmax) ** 2
+    dn = zn * np.sqrt(hn)
+    got_n = ctx.distmarg(dn, hn, 1.0 / dmax)
+    ref_n = O.ln_dist_marg_adaptive(dn, hn, dmax, 1.0)
+    err_n = np.abs(got_n - ref_n)
+    print("distance rule, negative z: max err", err_n.max(), "max rel", np.max(err_n / np.abs(ref_n)),
+          flush=True)
+    assert np.all(err_n < 5e-7 + 1e-9 * np.abs(ref_n))
     assert ctx.distmarg([0.0], [0.0], 1e-3)[0] == 0.0
 
 
