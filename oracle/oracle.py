@@ -370,3 +370,71 @@ def evidence(wl, n_nodes=2000, processes=1, k=0):
         idx, vals = top_k(ev["lnp"], k)
         out.update(topk_idx=idx, topk_lnp=vals)
     return out
+
+
+# --------------------------------------------------------------------------
+# P1: intrinsic pre-selection by the incoherent single-detector maximum
+# likelihood (Sec. IV D; App. B eqs. dh_itop, x_ML, single_det_ML)
+# --------------------------------------------------------------------------
+def polarisations(h_i, modes, cos_iota, phis):
+    """h_p(f) of one bank row at each grid phase: [N_phi, 2, N_b] complex,
+    h_p = sum_c K_{c,p}(iota) h_c(f) exp(-i m_c phi) (p = +, x).  For the
+    pre-selection the inclination is a property of the bank row."""
+    K = mode_factors(modes, np.array([cos_iota], dtype=np.float64))[0]     # [C, 2]
+    m = np.array([mm for _, mm in modes], dtype=np.float64)
+    Phi = np.exp(-1j * np.outer(phis, m))                                  # [O, C]
+    return np.einsum("cp,oc,cb->opb", K, Phi, np.asarray(h_i))
+
+
+def _pinv_sym2(H, rel=1e-10):
+    """Moore-Penrose pseudo-inverse of a real symmetric 2x2 matrix: its
+    eigen-directions with eigenvalue below rel x the largest are dropped."""
+    lam, V = np.linalg.eigh(H)
+    top = np.max(np.abs(lam))
+    out = np.zeros((2, 2))
+    for q in range(2):
+        if top > 0.0 and lam[q] > rel * top:
+            out += np.outer(V[:, q], V[:, q]) / lam[q]
+    return out
+
+
+def single_detector_ml(h_i, modes, cos_iota, f, d_k, w_k, times, n_phi):
+    """ln L^ML_{i k o t} of eq. (single_det_ML) for one bank row and one
+    detector on the grid phase_grid(n_phi) x times: [N_phi, N_t].
+
+    The detector's response and the distance become one free real
+    amplitude per polarisation, x_p (eq. x_ML).  With
+    b_p(o, t) = (d | h_p e^{-2 pi i f t}) (eq. dh_itop) and
+    H_pp'(o) = (h_p | h_p') the largest ln L over x is b^T H^+ b / 2, H^+
+    the pseudo-inverse (a polarisation that vanishes, as h_x does for an
+    edge-on source, adds nothing)."""
+    hp = polarisations(h_i, modes, cos_iota, phase_grid(n_phi))          # [O, 2, B]
+    f = np.asarray(f, dtype=np.float64)
+    shift = np.exp(2j * np.pi * np.outer(np.asarray(times, dtype=np.float64), f))   # [T, B]
+    b = np.real(np.einsum("b,opb,tb->otp", np.asarray(w_k) * np.asarray(d_k), np.conj(hp), shift))
+    H = np.real(np.einsum("b,opb,oqb->opq", np.asarray(w_k), hp, np.conj(hp)))
+    out = np.empty((n_phi, len(times)))
+    for o in range(n_phi):
+        out[o] = 0.5 * np.einsum("tp,pq,tq->t", b[o], _pinv_sym2(H[o]), b[o])
+    return out
+
+
+def incoherent_ml(h, modes, cos_iota, f, d, w, t0, dt, n_t, n_phi):
+    """ln L^{inco ML}_i = sum_k max_{o,t} ln L^ML_{ikot} (Sec. IV D) for the
+    rows of h [N_rows, N_c, N_b]; detector k's time grid is
+    t0[k] + j dt, j < n_t.  Returns (per row [N_rows], per row and detector
+    [N_rows, K])."""
+    n_rows, n_det = len(h), len(d)
+    per = np.empty((n_rows, n_det))
+    for i in range(n_rows):
+        for k in range(n_det):
+            times = t0[k] + dt * np.arange(n_t)
+            per[i, k] = np.max(single_detector_ml(h[i], modes, cos_iota[i], f, d[k], w[k], times, n_phi))
+    return per.sum(axis=1), per
+
+
+def preselect(lnl_inco, delta=20.0):
+    """Sec. IV D: the rows whose incoherent maximum likelihood is within
+    delta of the largest (ascending row order)."""
+    lnl_inco = np.asarray(lnl_inco)
+    return np.flatnonzero(lnl_inco >= np.max(lnl_inco) - delta)
