@@ -111,3 +111,35 @@ def test_poll_and_rejections(setup):
     small2 = dotpe.Server(ctx, bank, n_slots=1, pool_bytes=need + (1 << 20))
     small2.submit(**kw)
     small2.close()
+
+
+def test_served_event_vs_oracle(setup):
+    """One event through the server, next to another it overlaps with,
+    against the oracle (eq. Z_sum over eq. lnl_dist_marginalized): ln Z, the
+    largest lnL^ML, and the returned top pairs' ln p, each checked at its
+    (i, e) and as the set of the largest values."""
+    from oracle import oracle as O
+    dotpe, ctx, bank, bank_wl = setup
+    start, count, n_ext, k = 1200, 40, 64, 8
+    kw = event_kwargs(bank_wl, 321, n_ext, "HLV", 15.0, start, count, cut=0.0, top_k=k)
+    other = event_kwargs(bank_wl, 322, 512, "HL", 20.0, 0, 3072)
+    srv = dotpe.Server(ctx, bank, n_slots=2, pool_bytes=1 << 30)
+    t_other = srv.submit(**other)
+    t = srv.submit(**kw)
+    r, _ = srv.wait(t)
+    srv.wait(t_other)
+    srv.close()
+    wl = W.Workload(bank_wl.modes, bank_wl.f, bank_wl.h[start:start + count], np.zeros(count),
+                    kw["det_r"], kw["det_D"], kw["d"], kw["w"], kw["ext"], kw["ln_w_ext"],
+                    kw["n_phi"], kw["d_max"], kw["d0"])
+    ref = O.evidence(wl, k=k)
+    print(f"served event: ln Z {r['ln_z']:.8f} vs oracle {ref['ln_z']:.8f}", flush=True)
+    assert abs(r["ln_z"] - ref["ln_z"]) <= 1e-3
+    assert abs(r["max_lnl_ml"] - ref["max_lnl_ml"]) <= 1e-3
+    n = r["topk_count"]
+    assert n == k
+    i = r["topk_i"][:n] - start
+    e = r["topk_e"][:n]
+    assert np.all((i >= 0) & (i < count))
+    assert np.max(np.abs(r["topk_lnp"][:n] - ref["lnp"][i, e])) <= 1e-3
+    assert np.max(np.abs(r["topk_lnp"][:n] - ref["topk_lnp"])) <= 1e-3
