@@ -58,16 +58,18 @@ extern "C" {
 
 /* event flags.  With a cut, dotpe_evidence bounds every pair of a tile
  * first and evaluates the tile's survivors afterwards; a tile with more
- * survivors than its record area holds is evaluated again by a second,
- * batched pass.  DOTPE_FLAG_RERUN_ALL sends every tile with a survivor
- * through that second pass (a check that both routes agree; slower). */
+ * survivors than its record area holds is left to the coefficient route
+ * (its raw contraction results stored, then every pair bounded and
+ * evaluated by a separate kernel), which also takes every tile when the
+ * cut is off.  DOTPE_FLAG_RERUN_ALL sends every tile with a survivor
+ * through that route (a check that both routes agree; slower). */
 #define DOTPE_FLAG_RERUN_ALL 1
 /* With a cut, split-precision events of at least 2048 tiles of 128 x 128
  * pairs first run a bound pass: it only bounds every pair (the contraction
  * without the per-pair marginalisation, at half the operand traffic per pair)
- * and lists each 64 x 64 tile with a surviving pair for the second, batched
- * pass.  DOTPE_FLAG_NO_BOUND_PASS uses the fused kernel's bound-then-evaluate
- * epilogue instead (results agree to rounding). */
+ * and lists each 64 x 64 tile's few survivors for a survivor pass, or the
+ * tile for the coefficient route.  DOTPE_FLAG_NO_BOUND_PASS uses the fused
+ * kernel's bound-then-evaluate epilogue instead (results agree to rounding). */
 #define DOTPE_FLAG_NO_BOUND_PASS 2
 
 /* where a caller pointer lives */
@@ -142,7 +144,8 @@ typedef struct dotpe_event_desc {
   int64_t sub_count;        /* ... 0 = the whole bank */
   const int64_t* sub_idx;   /* or explicit rows [sub_count] (host), NULL = range */
   double cut_delta;         /* coherent cut (eq. coherent_ML_selection): a pilot pass over
-                               every 64th row of tiles finds M = max lnL^ML; pairs whose
+                               every 64th row of tiles (at least 16 rows of tiles on
+                               small events) finds M = max lnL^ML; pairs whose
                                certified upper bound on lnL^ML lies below M - cut_delta
                                are bounded (their mass goes to ln_z_upper), not
                                marginalised; <= 0 disables the cut */
@@ -194,7 +197,8 @@ typedef struct dotpe_evidence_result {
                                main pass, second pass included (HIP events) */
   double cut_delta_used;    /* cut_delta of the pass returned (0: no cut) */
   int32_t n_passes;         /* evidence passes run to meet cut_target */
-  int32_t n_tiles_rerun;    /* 64 x 64 tiles evaluated by the second, batched pass */
+  int32_t n_tiles_rerun;    /* 64 x 64 tiles evaluated by the coefficient route (all of
+                               them when the cut is off) */
   double t_main_ms;         /* device time of the main pass's first kernel alone: the
                                bound pass, or the fused kernel (HIP events) */
   int32_t n_tiles_listed;   /* 64 x 64 tiles whose few survivors the bound pass listed */
@@ -209,10 +213,11 @@ typedef struct dotpe_sample {
   int32_t reserved;
 } dotpe_sample;
 
-/* Fused, non-materialising evaluation: one persistent pass of the
- * (d|h) contraction with the marginalisation and evidence epilogue.
- * topk: [desc.top_k] host array or NULL.  Synchronous.  Errors:
- * INVALID_ARG, DEVICE. */
+/* Fused, non-materialising evaluation of the evidence: the pilot, the bound
+ * or fast pass with the survivor pass, the coefficient route and the
+ * fixed-order reduction, every decision between them taken on the device
+ * (the host waits once per pass, for the results).  topk: [desc.top_k]
+ * host array or NULL.  Synchronous.  Errors: INVALID_ARG, DEVICE. */
 int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out,
                    dotpe_sample* topk);
 
@@ -240,6 +245,56 @@ int dotpe_evidence_static(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_ev
  * Errors: INVALID_ARG, NUMERIC. */
 int dotpe_event_bytes(const dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_event_desc* desc,
                       uint64_t* bytes);
+
+/* ---- Intrinsic pre-selection (Sec. IV D; App. B eqs. dh_itop, x_ML,
+ * single_det_ML) ----
+ *
+ * For bank rows [sub_start, sub_start + sub_count), each detector k on its
+ * own: the largest likelihood over a grid of reference phases phi_o
+ * (n_phi) and arrival times t_kj = t0[k] + j dt (n_t), with the detector
+ * response and the distance replaced by one free real amplitude per
+ * polarisation (eq. x_ML): lnL^ML = b^T H^+ b / 2, b_p = (d_k | h_p
+ * exp(-2 pi i f t)) (eq. dh_itop), H_pp' = (h_p | h_p'), H^+ the
+ * pseudo-inverse (an eigen-direction with eigenvalue below 1e-10 of the
+ * largest dropped).  The polarisations h_p = sum_c K_cp(iota_i) h_c
+ * exp(-i m_c phi_o) take each row's inclination from cos_iota.  The
+ * incoherent maximum is lnL^inco_i = sum_k max_{o,j} lnL^ML_ikoj; rows with
+ * lnL^inco_i >= max_j lnL^inco_j - delta_lnl are selected, in ascending
+ * order -- the subset to pass as sub_idx to dotpe_set_event.  Split-precision
+ * banks only: the products run on the matrix cores over the bank's operand. */
+typedef struct dotpe_preselect_desc {
+  int32_t n_det;            /* 1..8 */
+  int32_t n_t;              /* time-grid points per detector: 32, 64, 96 or 128 */
+  int32_t n_phi;            /* 1..128 */
+  int32_t reserved;         /* 0 */
+  const double* d;          /* [n_det][n_bins][2] data at f_bins, host */
+  const double* w;          /* [n_det][n_bins] noise weights, host */
+  const double* t0;         /* [n_det] first grid time of each detector, s, host */
+  double dt;                /* grid step, s */
+  const double* cos_iota;   /* [sub_count] cosine of each row's inclination, host */
+  int64_t sub_start;        /* rows [sub_start, sub_start + sub_count) ... */
+  int64_t sub_count;        /* ... 0 = the whole bank */
+  double delta_lnl;         /* selection width (<= 0: 20) */
+  void* stream;             /* hipStream_t; NULL = context stream */
+} dotpe_preselect_desc;
+
+typedef struct dotpe_preselect_result {
+  double lnl_max;           /* largest lnL^inco over the rows */
+  double threshold;         /* lnl_max - delta_lnl */
+  int64_t n_rows;           /* rows considered */
+  int64_t n_selected;       /* rows written to `selected` */
+  double t_ms;              /* device time of the pass (HIP events) */
+} dotpe_preselect_result;
+
+/* Outputs, host arrays, each may be NULL: lnl_inco [sub_count] lnL^inco per
+ * row; lnl_det [sub_count][n_det] each detector's maximum; selected
+ * [sub_count] the absolute bank rows kept, ascending (the first n_selected
+ * entries).  Synchronous; the pass's device buffers are allocated and freed
+ * within the call, charged to the budget.  Errors: INVALID_ARG, NUMERIC
+ * (non-finite input), UNIMPLEMENTED (FP64 bank), OOM / ADMISSION, DEVICE. */
+int dotpe_preselect(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_preselect_desc* desc,
+                    double* lnl_inco, double* lnl_det, int64_t* selected,
+                    dotpe_preselect_result* out);
 
 /* ---- Serving: continuous admission of events against a resident bank ----
  *

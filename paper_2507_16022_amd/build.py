@@ -1,8 +1,9 @@
 """Build the HIP library libdotpe.so in-tree for gfx950 (hipcc, no JIT).
 
-The host runtime (csrc/dotpe.hip) and one instantiation unit of the fused
-kernel per (precision, number of m groups) (csrc/fused_inst.hip) are compiled
-to objects in parallel, then linked into one shared library.
+The host runtime (csrc/dotpe.hip), the pre-selection kernels
+(csrc/preselect.hip) and one instantiation unit of the fused kernel per
+(precision, number of m groups) (csrc/fused_inst.hip) are compiled to
+objects in parallel, then linked into one shared library.
 """
 import os
 import subprocess
@@ -25,7 +26,8 @@ GROUPS = (1, 2, 3, 4)      # distinct m values
 
 def units():
     """(source, object, extra flags) of every translation unit."""
-    out = [(os.path.join(CSRC, "dotpe.hip"), os.path.join(OBJ, "dotpe.o"), [])]
+    out = [(os.path.join(CSRC, "dotpe.hip"), os.path.join(OBJ, "dotpe.o"), []),
+           (os.path.join(CSRC, "preselect.hip"), os.path.join(OBJ, "preselect.o"), [])]
     for p in PRECISIONS:
         for g in GROUPS:
             out.append((os.path.join(CSRC, "fused_inst.hip"), os.path.join(OBJ, f"fused_p{p}_g{g}.o"),

@@ -479,7 +479,8 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
     ((unsigned*)dp)[t] = ((const unsigned*)a.dist.prm)[t];
   __syncthreads();
   // the workgroups' waves take the listed tiles in turn (the list's length
-  // is known on the device only)
+  // is known on the device only; the grid is large enough that a wave
+  // takes a few at most)
   const int64_t n_list = (int64_t)a.state[5];
   for (int64_t item = (int64_t)blockIdx.x * 4 + (tid >> 6); item < n_list;
        item += (int64_t)gridDim.x * 4) {

@@ -178,4 +178,27 @@ __host__ __device__ __forceinline__ int64_t op_index(int64_t i, int64_t k, int64
 
 constexpr int kMaxNR = 2 * kMaxND - 1;   // (h|h) phase-coefficient outputs
 
+__device__ inline double swsh_m2(int l, int m, double cos_t) {
+  // spin-weight -2 harmonic at azimuth 0: sqrt((2l+1)/4pi) d^l_{m,2}(theta)
+  const double fact[13] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880, 3628800, 39916800,
+                           479001600};
+  double ct = fmin(1.0, fmax(-1.0, cos_t));
+  double cb = sqrt(0.5 * (1.0 + ct)), sb = sqrt(0.5 * (1.0 - ct));   // cos, sin of theta/2
+  const int s = 2;
+  double sum = 0.0;
+  for (int k = 0; k <= 2 * l; ++k) {
+    int a = l + s - k, b = k, c = l - k - m, d = k - s + m;
+    if (a < 0 || c < 0 || d < 0) continue;
+    double coef = sqrt(fact[l + s] * fact[l - s] * fact[l + m] * fact[l - m]) /
+                  (fact[a] * fact[b] * fact[c] * fact[d]);
+    if ((k - s + m) & 1) coef = -coef;
+    int pc = 2 * l - 2 * k + s - m, ps = 2 * k - s + m;
+    double v = coef;
+    for (int q = 0; q < pc; ++q) v *= cb;
+    for (int q = 0; q < ps; ++q) v *= sb;
+    sum += v;
+  }
+  return sqrt((2.0 * l + 1.0) / (4.0 * M_PI)) * sum;
+}
+
 }  // namespace dotpe

@@ -20,6 +20,7 @@
 #include "../../include/dotpe_test.h"
 #include "launch.h"
 #include "prep.h"
+#include "preselect.h"
 #include "serving.h"
 
 using namespace dotpe;
@@ -1009,7 +1010,7 @@ int dotpe_eval_lnl(dotpe_ctx* ctx, dotpe_event* ev, double* lnl, double* ml_max,
 }
 
 // Persistent grids of the passes whose work is known on the device only
-constexpr int64_t kSurvGrid = 1024;   // workgroups of 4 waves, a listed tile per wave
+constexpr int64_t kSurvGrid = 65536;  // workgroups of 4 waves, a listed tile per wave
 constexpr int64_t kCoefGrid = 1024;   // fused kernel, a tile per workgroup at a time
 constexpr int64_t kE2Grid = 4096;
 
@@ -1251,6 +1252,141 @@ int dotpe_evidence_static(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_even
   rc = evidence_run(ctx, ev, &r, topk);     // untimed: the event has no HIP events
   dotpe_free_event(ctx, ev);                // frees nothing: every buffer is in the scratch
   if (rc) return rc;
+  *out = r;
+  return DOTPE_OK;
+}
+
+int dotpe_preselect(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_preselect_desc* d,
+                    double* lnl_inco, double* lnl_det, int64_t* selected,
+                    dotpe_preselect_result* out) {
+  if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (bk->prec == kFP64)
+    return fail(DOTPE_E_UNIMPLEMENTED, "pre-selection runs on split-precision banks only");
+  if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
+  if (d->n_t < 32 || d->n_t > kPreMaxT || d->n_t % 32)
+    return fail(DOTPE_E_INVALID_ARG, "n_t=%d (32, 64, 96 or 128)", d->n_t);
+  if (d->n_phi < 1 || d->n_phi > kMaxPhi) return fail(DOTPE_E_INVALID_ARG, "n_phi=%d", d->n_phi);
+  if (!d->d || !d->w || !d->t0 || !d->cos_iota)
+    return fail(DOTPE_E_INVALID_ARG, "pre-selection arrays must not be NULL");
+  const int64_t n_rows = d->sub_count > 0 ? d->sub_count : bk->n_wf;
+  if (d->sub_start < 0 || d->sub_start + n_rows > bk->n_wf)
+    return fail(DOTPE_E_INVALID_ARG, "bank range out of bounds");
+  const int nk = d->n_det, nb = bk->n_b;
+  if (!finite_all(d->d, (size_t)nk * nb * 2) || !finite_all(d->w, (size_t)nk * nb) ||
+      !finite_all(d->t0, nk) || !std::isfinite(d->dt) || !finite_all(d->cos_iota, n_rows))
+    return fail(DOTPE_E_NUMERIC, "non-finite pre-selection input");
+  for (int64_t r = 0; r < n_rows; ++r)
+    if (std::fabs(d->cos_iota[r]) > 1.0) return fail(DOTPE_E_INVALID_ARG, "|cos_iota| > 1");
+  for (size_t t = 0; t < (size_t)nk * nb; ++t)
+    if (d->w[t] < 0.0) return fail(DOTPE_E_INVALID_ARG, "negative noise weight");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = d->stream ? (hipStream_t)d->stream : ctx->stream;
+  const ModeTables& mt = bk->mt;
+  PreArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.A0 = bk->A0;
+  a.A1 = bk->A1;
+  a.row_scale = bk->row_scale;
+  a.K2 = bk->K2;
+  a.n_c = mt.n_c;
+  a.n_b = nb;
+  a.n_bp = bk->n_bp;
+  for (int c = 0; c < mt.n_c; ++c) {
+    a.l[c] = mt.l[c];
+    a.m[c] = mt.m[c];
+    for (int g = 0; g < mt.G; ++g)
+      if (mt.gm[g] == mt.m[c]) a.cg[c] = g;
+  }
+  for (int g = 0; g < mt.G; ++g) a.gm[g] = mt.gm[g];
+  a.G = mt.G;
+  a.row0 = d->sub_start;
+  a.n_rows = n_rows;
+  a.n_det = nk;
+  a.n_t = d->n_t;
+  a.n_phi = d->n_phi;
+  a.f = bk->f;
+  a.dt = d->dt;
+  a.K2p = 2 * (int64_t)bk->n_bp;
+  a.delta = d->delta_lnl > 0.0 ? d->delta_lnl : 20.0;
+  const int64_t n_grid = (int64_t)nk * d->n_t;
+  const int64_t nblk = (n_rows + 1023) / 1024;
+  const int64_t n_chunk = std::min<int64_t>(n_rows, kPreChunk);
+  // the pass's buffers, freed on every return below
+  std::vector<void*> bufs;
+  uint64_t held = 0;
+  struct Release {
+    dotpe_ctx* ctx;
+    std::vector<void*>* bufs;
+    uint64_t* held;
+    hipStream_t s;
+    ~Release() {
+      (void)hipStreamSynchronize(s);
+      for (void* p : *bufs) (void)hipFree(p);
+      ctx->bytes -= *held;
+    }
+  } release{ctx, &bufs, &held, s};
+  int rc;
+  auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &bufs, &held); };
+  void *dd = nullptr, *ww = nullptr, *tt = nullptr, *ci = nullptr, *st = nullptr;
+  if ((rc = alloc(&dd, (size_t)nk * nb * 16)) || (rc = alloc(&ww, (size_t)nk * nb * 8)) ||
+      (rc = alloc(&tt, (size_t)nk * 8)) || (rc = alloc(&ci, (size_t)n_rows * 8)) ||
+      (rc = alloc((void**)&a.B0, (size_t)n_grid * a.K2p * 2)) ||
+      (rc = alloc((void**)&a.B1, (size_t)n_grid * a.K2p * 2)) ||
+      (rc = alloc((void**)&a.col_scale, (size_t)n_grid * 8)) ||
+      (rc = alloc((void**)&a.gram, (size_t)n_chunk * nk * pre_pairs(mt.n_c) * 16)) ||
+      (rc = alloc((void**)&a.ml_det, (size_t)n_rows * nk * 8)) ||
+      (rc = alloc((void**)&a.lnl, (size_t)n_rows * 8)) || (rc = alloc(&st, 64)) ||
+      (rc = alloc((void**)&a.counts, (size_t)nblk * 4)) ||
+      (rc = alloc((void**)&a.offsets, (size_t)nblk * 8)) ||
+      (rc = alloc((void**)&a.selected, (size_t)n_rows * 8)))
+    return rc;
+  a.d = (const double2*)dd;
+  a.w = (const double*)ww;
+  a.t0 = (const double*)tt;
+  a.cos_iota = (const double*)ci;
+  a.state = (uint64_t*)st;
+  const uint64_t st0[2] = {0x000fffffffffffffull, 0ull};   // below every ordered value; count
+  HIP_OK(hipMemcpyAsync(dd, d->d, (size_t)nk * nb * 16, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(ww, d->w, (size_t)nk * nb * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(tt, d->t0, (size_t)nk * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(ci, d->cos_iota, (size_t)n_rows * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(st, st0, sizeof(st0), hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  struct Events {
+    hipEvent_t a, b;
+    ~Events() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evs{e0, e1};
+  HIP_OK(hipEventRecord(e0, s));
+  hipError_t e = preselect_launch(bk->prec, a, s);
+  if (e != hipSuccess) return fail(DOTPE_E_DEVICE, "pre-selection launch: %s", hipGetErrorString(e));
+  HIP_OK(hipEventRecord(e1, s));
+  uint64_t sth[2];
+  HIP_OK(hipMemcpyAsync(sth, st, sizeof(sth), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int64_t n_sel = (int64_t)sth[1];
+  if (lnl_inco) HIP_OK(hipMemcpyAsync(lnl_inco, a.lnl, (size_t)n_rows * 8, hipMemcpyDeviceToHost, s));
+  if (lnl_det) HIP_OK(hipMemcpyAsync(lnl_det, a.ml_det, (size_t)n_rows * nk * 8, hipMemcpyDeviceToHost, s));
+  if (selected && n_sel > 0)
+    HIP_OK(hipMemcpyAsync(selected, a.selected, (size_t)n_sel * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  uint64_t u = sth[0];
+  u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+  double mx;
+  std::memcpy(&mx, &u, 8);
+  dotpe_preselect_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.lnl_max = mx;
+  r.threshold = mx - a.delta;
+  r.n_rows = n_rows;
+  r.n_selected = n_sel;
+  r.t_ms = ms;
   *out = r;
   return DOTPE_OK;
 }

@@ -82,6 +82,19 @@ class TicketInfo(ctypes.Structure):
                 ("slot", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
+class PreselectDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("n_t", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("d", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("t0", ctypes.c_void_p), ("dt", ctypes.c_double), ("cos_iota", ctypes.c_void_p),
+                ("sub_start", ctypes.c_int64), ("sub_count", ctypes.c_int64),
+                ("delta_lnl", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class PreselectResult(ctypes.Structure):
+    _fields_ = [("lnl_max", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("n_rows", ctypes.c_int64), ("n_selected", ctypes.c_int64), ("t_ms", ctypes.c_double)]
+
+
 class Sample(ctypes.Structure):
     _fields_ = [("i", ctypes.c_int64), ("e", ctypes.c_int64), ("ln_p", ctypes.c_double),
                 ("o_best", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -108,6 +121,9 @@ SYMBOLS = {
                                               ctypes.POINTER(EvidenceResult), ctypes.c_void_p]),
     "dotpe_event_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(EventDesc),
                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "dotpe_preselect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PreselectDesc),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(PreselectResult)]),
     "dotpe_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(ServerDesc),
                                             ctypes.POINTER(ctypes.c_void_p)]),
@@ -212,6 +228,35 @@ class Context:
             self._h, bank.handle, ctypes.byref(desc), ctypes.byref(r),
             ctypes.cast(arr, ctypes.c_void_p) if k else None))
         return _result(r, arr)
+
+    def preselect(self, bank, d, w, t0, dt, n_t, cos_iota, n_phi, sub_start=0, sub_count=0,
+                  delta_lnl=20.0, stream=None):
+        """dotpe_preselect: each row's incoherent maximum likelihood over the (phase, time)
+        grid and the rows within delta_lnl of the best.  Returns a dict with lnl_inco
+        [rows], lnl_det [rows, n_det], selected (absolute bank rows, ascending) and the
+        result fields."""
+        d = np.ascontiguousarray(d, dtype=np.complex128)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        t0 = np.ascontiguousarray(t0, dtype=np.float64)
+        ci = np.ascontiguousarray(cos_iota, dtype=np.float64)
+        n_rows = len(ci)
+        if sub_count == 0:
+            sub_count = n_rows
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        desc = PreselectDesc(d.shape[0], int(n_t), int(n_phi), 0, d.ctypes.data, w.ctypes.data,
+                             t0.ctypes.data, float(dt), ci.ctypes.data, int(sub_start),
+                             int(sub_count), float(delta_lnl), stream)
+        lnl = np.empty(n_rows)
+        per = np.empty((n_rows, d.shape[0]))
+        sel = np.empty(n_rows, dtype=np.int64)
+        r = PreselectResult()
+        _check(load_library().dotpe_preselect(self._h, bank.handle, ctypes.byref(desc),
+                                              lnl.ctypes.data, per.ctypes.data, sel.ctypes.data,
+                                              ctypes.byref(r)))
+        out = {name: getattr(r, name) for name, _ in PreselectResult._fields_}
+        out.update(lnl_inco=lnl, lnl_det=per, selected=sel[:r.n_selected].copy())
+        return out
 
     def distmarg(self, dh, hh, r0):
         dh, pdh = _host(dh)

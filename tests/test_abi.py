@@ -46,6 +46,8 @@ STRUCTS = {
     "dotpe_sample": dotpe.Sample,
     "dotpe_server_desc": dotpe.ServerDesc,
     "dotpe_ticket_info": dotpe.TicketInfo,
+    "dotpe_preselect_desc": dotpe.PreselectDesc,
+    "dotpe_preselect_result": dotpe.PreselectResult,
 }
 
 
