@@ -84,37 +84,46 @@ __global__ __launch_bounds__(256) void k_pre_build_B(PreArgs a) {
   }
 }
 
-// G_ikcc' = sum_b w_kb h_icb conj(h_ic'b) (c <= c') of one row per
-// workgroup, from the split bank values (h = conj(A) 2^e_i), in FP64.
-template <int PREC>
-__global__ __launch_bounds__(64) void k_pre_gram(PreArgs a) {
-  extern __shared__ double2 hv[];     // [n_c][n_b]: h 2^-e_i
-  const int64_t q = blockIdx.x;
+// G_ikcc' = sum_b w_kb h_icb conj(h_ic'b) (c <= c') from the split bank
+// values (h = conj(A) 2^e_i), in FP64: a wave per row, its lanes over the
+// bins, one wave sum per output.
+template <int PREC, int NC>
+__global__ __launch_bounds__(256) void k_pre_gram(PreArgs a) {
+  constexpr int NP = NC * (NC + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= a.n_chunk) return;
   const int64_t i = a.row0 + a.chunk0 + q;
-  for (int t = threadIdx.x; t < a.n_c * a.n_b; t += blockDim.x) {
-    const int c = t / a.n_b, b = t % a.n_b;
-    const int64_t base = ((int64_t)c * (a.n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
-    const double re = load_split<PREC>(a.A0, a.A1, op_index<PREC>(i, base, a.K2));
-    const double im = load_split<PREC>(a.A0, a.A1, op_index<PREC>(i, base + 16, a.K2));
-    hv[t] = make_double2(re, -im);
-  }
-  __syncthreads();
   const double s2 = a.row_scale[i] * a.row_scale[i];
-  const int NP = pre_pairs(a.n_c);
-  for (int item = threadIdx.x; item < a.n_det * NP; item += blockDim.x) {
-    const int k = item / NP;
-    int p = item % NP, c = 0;
-    while (p >= a.n_c - c) { p -= a.n_c - c; ++c; }
-    const int c2 = c + p;
-    const double* w = a.w + (int64_t)k * a.n_b;
-    const double2* x = hv + (int64_t)c * a.n_b;
-    const double2* y = hv + (int64_t)c2 * a.n_b;
-    double sr = 0.0, si = 0.0;
-    for (int b = 0; b < a.n_b; ++b) {
-      sr += w[b] * (x[b].x * y[b].x + x[b].y * y[b].y);
-      si += w[b] * (x[b].y * y[b].x - x[b].x * y[b].y);
+  auto add = [](double x, double y) { return x + y; };
+  for (int k = 0; k < a.n_det; ++k) {
+    double gr[NP], gi[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) { gr[p] = 0.0; gi[p] = 0.0; }
+    for (int b = lane; b < a.n_b; b += 64) {
+      double hr[NC], hi[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int64_t base = ((int64_t)c * (a.n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
+        hr[c] = load_split<PREC>(a.A0, a.A1, op_index<PREC>(i, base, a.K2));
+        hi[c] = -load_split<PREC>(a.A0, a.A1, op_index<PREC>(i, base + 16, a.K2));
+      }
+      const double w = a.w[(int64_t)k * a.n_b + b];
+      int p = 0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int c2 = c; c2 < NC; ++c2, ++p) {
+          gr[p] += w * (hr[c] * hr[c2] + hi[c] * hi[c2]);
+          gi[p] += w * (hi[c] * hr[c2] - hr[c] * hi[c2]);
+        }
     }
-    a.gram[(q * a.n_det + k) * NP + (item % NP)] = make_double2(s2 * sr, s2 * si);
+    double2* out = a.gram + (q * a.n_det + k) * NP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const double r = wave_reduce(gr[p], 0.0, add), m = wave_reduce(gi[p], 0.0, add);
+      if (lane == 63) out[p] = make_double2(s2 * r, s2 * m);
+    }
   }
 }
 
@@ -133,8 +142,9 @@ __global__ __launch_bounds__(64 * kPreMaxT / 32) void k_preselect(PreArgs a) {
   double* cs = pls;                          // [kMaxM][n_phi][2] cos, sin of m phi_o
   double* kp = cs + kMaxM * n_phi * 2;       // [32][NC] K_c+
   double* kx = kp + 32 * NC;                 // [32][NC] K_cx / i
-  double* qf = kx + 32 * NC;                 // [32][n_phi][3] H^+ / 2
-  double* red = qf + 32 * n_phi * 3;         // [NW][32]
+  float* qf = (float*)(kx + 32 * NC);        // [32][n_phi][4] H^+ / 2 as (cos, sin, a1, a2)
+  double* red = (double*)(qf + 32 * n_phi * 4);   // [NW][32]
+  float* csf = (float*)(red + 32 * (kPreMaxT / 32));   // [kMaxM][n_phi][2] in FP32
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nt = blockDim.x;
   const int k = blockIdx.y;
   const int64_t rb0 = a.chunk0 + (int64_t)blockIdx.x * 32;   // first row of the block
@@ -146,6 +156,8 @@ __global__ __launch_bounds__(64 * kPreMaxT / 32) void k_preselect(PreArgs a) {
     sincospi(2.0 * (double)((mm * o) % n_phi) / n_phi, &sn, &cn);
     cs[2 * t] = cn;
     cs[2 * t + 1] = sn;
+    csf[2 * t] = (float)cn;
+    csf[2 * t + 1] = (float)sn;
   }
   for (int t = tid; t < 32 * NC; t += nt) {
     const int rr = t / NC, c = t % NC;
@@ -157,7 +169,9 @@ __global__ __launch_bounds__(64 * kPreMaxT / 32) void k_preselect(PreArgs a) {
   }
   __syncthreads();
   // H_pp'(row, o) from the Gram matrix, then its pseudo-inverse / 2 (an
-  // eigen-direction with eigenvalue below 1e-10 of the largest dropped)
+  // eigen-direction with eigenvalue below 1e-10 of the largest dropped) in
+  // eigen-form: b^T H^+ b / 2 = a1 (c b+ + s bx)^2 + a2 (-s b+ + c bx)^2, a
+  // sum of non-negative terms, so the epilogue may evaluate it in FP32
   constexpr int NP = NC * (NC + 1) / 2;
   for (int t = tid; t < 32 * n_phi; t += nt) {
     const int rr = t / n_phi, o = t % n_phi;
@@ -187,29 +201,25 @@ __global__ __launch_bounds__(64 * kPreMaxT / 32) void k_preselect(PreArgs a) {
           h01 += (c == c2) ? pa * xb * im : (pa * xb - pb * xa) * im;
         }
     }
-    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    double ec = 1.0, es = 0.0, a1 = 0.0, a2 = 0.0;
     const double df = 0.5 * (h00 - h11);
     const double lp = 0.5 * (h00 + h11) + sqrt(df * df + h01 * h01);
     if (lp > 0.0) {
-      const double det = h00 * h11 - h01 * h01;
-      if (det / lp > 1e-10 * lp) {
-        q0 = 0.5 * h11 / det;
-        q1 = -0.5 * h01 / det;
-        q2 = 0.5 * h00 / det;
-      } else {
-        double vx = df >= 0.0 ? lp - h11 : h01, vy = df >= 0.0 ? h01 : lp - h00;
-        const double nn = vx * vx + vy * vy;
-        if (nn > 0.0) {
-          const double sc = 0.5 / (lp * nn);
-          q0 = sc * vx * vx;
-          q1 = sc * vx * vy;
-          q2 = sc * vy * vy;
-        }
+      // eigenvector of the larger eigenvalue, then the smaller one as det / lp
+      const double vx = df >= 0.0 ? lp - h11 : h01, vy = df >= 0.0 ? h01 : lp - h00;
+      const double nn = sqrt(vx * vx + vy * vy);
+      if (nn > 0.0) {
+        ec = vx / nn;
+        es = vy / nn;
       }
+      a1 = 0.5 / lp;
+      const double lm = (h00 * h11 - h01 * h01) / lp;
+      a2 = lm > 1e-10 * lp ? 0.5 / lm : 0.0;
     }
-    qf[3 * t] = q0;
-    qf[3 * t + 1] = q1;
-    qf[3 * t + 2] = q2;
+    qf[4 * t] = (float)ec;
+    qf[4 * t + 1] = (float)es;
+    qf[4 * t + 2] = (float)a1;
+    qf[4 * t + 3] = (float)a2;
   }
 
   // ---- Y_ikc for this wave's 32 grid times, every channel ----
@@ -224,17 +234,36 @@ __global__ __launch_bounds__(64 * kPreMaxT / 32) void k_preselect(PreArgs a) {
     acc[c][0] = Acc{};
     acc[c][1] = Acc{};
   }
-  const int nj = a.n_bp / kChunk;
-  for (int j = 0; j < nj; ++j) {
+  // fragments of one bin chunk: B hi/lo of both slices, A hi/lo of both
+  // slices for every channel; the next chunk's are loaded while this one's
+  // products run (one wave per SIMD: the loads' latency is hidden by the
+  // wave's own work)
+  struct Frag {
+    uint4 b[4];          // bh0, bh1, bl0, bl1
+    uint4 a[NC][4];      // ah0, ah1, al0, al1
+  };
+  const int nj = a.n_bp / kChunk;    // a multiple of 4 (bins padded to 64)
+  auto load = [&](Frag& f, int j) {
     const int64_t bo = bbase + (int64_t)j * 1024;
-    const uint4 bh0 = ld16(a.B0, bo), bh1 = ld16(a.B0, bo + 512);
-    const uint4 bl0 = ld16(a.B1, bo), bl1 = ld16(a.B1, bo + 512);
-    const uint4 nbh1 = neg16(bh1), nbl1 = neg16(bl1);
+    f.b[0] = ld16(a.B0, bo);
+    f.b[1] = ld16(a.B0, bo + 512);
+    f.b[2] = ld16(a.B1, bo);
+    f.b[3] = ld16(a.B1, bo + 512);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int64_t ao = abase + (int64_t)(c * nj + j) * 1024;
-      const uint4 ah0 = ld16(a.A0, ao), ah1 = ld16(a.A0, ao + 512);
-      const uint4 al0 = ld16(a.A1, ao), al1 = ld16(a.A1, ao + 512);
+      f.a[c][0] = ld16(a.A0, ao);
+      f.a[c][1] = ld16(a.A0, ao + 512);
+      f.a[c][2] = ld16(a.A1, ao);
+      f.a[c][3] = ld16(a.A1, ao + 512);
+    }
+  };
+  auto compute = [&](const Frag& f) {
+    const uint4 &bh0 = f.b[0], &bh1 = f.b[1], &bl0 = f.b[2], &bl1 = f.b[3];
+    const uint4 nbh1 = neg16(bh1), nbl1 = neg16(bl1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint4 &ah0 = f.a[c][0], &ah1 = f.a[c][1], &al0 = f.a[c][2], &al1 = f.a[c][3];
       // A = [Re conj h | Im conj h], B_re = [Br | -Bi], B_im = [Bi | Br]:
       // 3 split products per real product
       Acc& re = acc[c][0];
@@ -246,37 +275,48 @@ __global__ __launch_bounds__(64 * kPreMaxT / 32) void k_preselect(PreArgs a) {
       mma<PREC>(re, ah1, bl1);  mma<PREC>(im, ah1, bl0);
       mma<PREC>(re, ah1, bh1);  mma<PREC>(im, ah1, bh0);
     }
+  };
+  Frag f0, f1;
+  load(f0, 0);
+  for (int j = 0; j < nj; j += 2) {
+    load(f1, j + 1);
+    compute(f0);
+    if (j + 2 < nj) load(f0, j + 2);
+    compute(f1);
   }
   __syncthreads();   // (the forms in qf are complete)
 
   // ---- epilogue: polarisation projections, 2x2 form, maximum ----
+  // (in FP32: the accumulators are FP32 and the form is a sum of squares)
   const double csc = a.col_scale[rbB];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int rr = 8 * (r >> 2) + 4 * h + (r & 3);
-    const double sc = (rr < rows_in ? a.row_scale[a.row0 + rb0 + rr] : 0.0) * csc;
-    double wpr[NC], wpi[NC], wxr[NC], wxi[NC];
+    const float sc = (float)((rr < rows_in ? a.row_scale[a.row0 + rb0 + rr] : 0.0) * csc);
+    float wpr[NC], wpi[NC], wxr[NC], wxi[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double yr = sc * (double)acc[c][0][r], yi = sc * (double)acc[c][1][r];
-      const double pk = kp[rr * NC + c], xk = kx[rr * NC + c];
+      const float yr = sc * acc[c][0][r], yi = sc * acc[c][1][r];
+      const float pk = (float)kp[rr * NC + c], xk = (float)kx[rr * NC + c];
       wpr[c] = pk * yr;     // conj(K_c+) Y
       wpi[c] = pk * yi;
       wxr[c] = xk * yi;     // conj(K_cx) Y = -i (K_cx / i) Y
       wxi[c] = -xk * yr;
     }
-    double best = 0.0;
+    float bestf = 0.f;
     for (int o = 0; o < n_phi; ++o) {
-      double bp = 0.0, bx = 0.0;
+      float bp = 0.f, bx = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const double cn = cs[((a.m[c] - 1) * n_phi + o) * 2], sn = cs[((a.m[c] - 1) * n_phi + o) * 2 + 1];
+        const float cn = csf[((a.m[c] - 1) * n_phi + o) * 2], sn = csf[((a.m[c] - 1) * n_phi + o) * 2 + 1];
         bp += cn * wpr[c] - sn * wpi[c];
         bx += cn * wxr[c] - sn * wxi[c];
       }
-      const double* q = qf + 3 * (rr * n_phi + o);
-      best = fmax(best, q[0] * bp * bp + 2.0 * q[1] * bp * bx + q[2] * bx * bx);
+      const float4 q = *(const float4*)(qf + 4 * (rr * n_phi + o));
+      const float u = q.x * bp + q.y * bx, v = q.x * bx - q.y * bp;
+      bestf = fmaxf(bestf, q.z * u * u + q.w * v * v);
     }
+    double best = (double)bestf;
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, 32));
     if ((lane & 31) == 0) red[wave * 32 + rr] = best;
@@ -357,17 +397,20 @@ __global__ __launch_bounds__(256) void k_pre_write(PreArgs a) {
 
 template <int PREC, int NC>
 hipError_t launch_pre_main(const PreArgs& a, hipStream_t s) {
-  const size_t lds = sizeof(double) * ((size_t)kMaxM * a.n_phi * 2 + 64 * NC + 32 * (size_t)a.n_phi * 3 +
-                                       (kPreMaxT / 32) * 32);
+  const size_t lds = sizeof(double) * ((size_t)kMaxM * a.n_phi * 2 + 64 * NC + 32 * (size_t)a.n_phi * 2 +
+                                       (kPreMaxT / 32) * 32 + (size_t)kMaxM * a.n_phi);
   static bool attr_done = false;
   if (!attr_done) {
-    const size_t most = sizeof(double) * ((size_t)kMaxM * kMaxPhi * 2 + 64 * NC + 32 * (size_t)kMaxPhi * 3 +
-                                          (kPreMaxT / 32) * 32);
+    const size_t most = sizeof(double) * ((size_t)kMaxM * kMaxPhi * 2 + 64 * NC + 32 * (size_t)kMaxPhi * 2 +
+                                          (kPreMaxT / 32) * 32 + (size_t)kMaxM * kMaxPhi);
     if (hipFuncSetAttribute((const void*)k_preselect<PREC, NC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)most) != hipSuccess)
       (void)hipGetLastError();
     attr_done = true;
   }
+  hipLaunchKernelGGL((k_pre_gram<PREC, NC>), dim3((unsigned)((a.n_chunk + 3) / 4)), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   dim3 grid((unsigned)((a.n_chunk + 31) / 32), (unsigned)a.n_det);
   hipLaunchKernelGGL((k_preselect<PREC, NC>), grid, dim3(64 * (a.n_t / 32)), lds, s, a);
   return hipGetLastError();
@@ -393,12 +436,9 @@ hipError_t run_all(PreArgs a, hipStream_t s) {
   hipLaunchKernelGGL(k_pre_build_B<PREC>, dim3((unsigned)(a.n_det * a.n_t)), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t gram_lds = sizeof(double2) * (size_t)a.n_c * a.n_b;
   for (int64_t c0 = 0; c0 < a.n_rows; c0 += kPreChunk) {
     a.chunk0 = c0;
     a.n_chunk = std::min<int64_t>(kPreChunk, a.n_rows - c0);
-    hipLaunchKernelGGL(k_pre_gram<PREC>, dim3((unsigned)a.n_chunk), dim3(64), gram_lds, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_pre_nc<PREC>(a, s)) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_pre_final, dim3((unsigned)((a.n_rows + 255) / 256)), dim3(256), 0, s, a);
