@@ -203,6 +203,14 @@ typedef struct dotpe_evidence_result {
                                bound pass, or the fused kernel (HIP events) */
   int32_t n_tiles_listed;   /* 64 x 64 tiles whose few survivors the bound pass listed */
   int32_t reserved;
+  /* effective-sample-size ingredients over the marginalised pairs, with
+   * p_ieo = w_i w_e Lbar_ieo / N_phi (so that sum_o p_ieo = p_ie):
+   *   N_eff      = exp(2 ln_sum_p - ln_sum_p2_triples)   (eq. posterior_element)
+   *   N_eff,int  = exp(2 ln_sum_p - ln_sum_row2)         (eq. int_ess)
+   *   N_eff,ext  = exp(2 ln_sum_p - ln_sum_col2)         (eq. ext_ess) */
+  double ln_sum_p2_triples; /* ln sum_ieo p_ieo^2 */
+  double ln_sum_row2;       /* ln sum_i (sum_e p_ie)^2 */
+  double ln_sum_col2;       /* ln sum_e (sum_i p_ie)^2 */
 } dotpe_evidence_result;
 
 typedef struct dotpe_sample {

@@ -272,11 +272,14 @@ def ln_dist_marg_adaptive(dh, hh, d_max, d0=1.0, rel=1e-12):
 # --------------------------------------------------------------------------
 # O8-O10: per-pair likelihood, evidence, top-K
 # --------------------------------------------------------------------------
-def eval_pairs_block(wl, rows, ext_idx=None, n_nodes=2000, return_triples=False):
+def eval_pairs_block(wl, rows, ext_idx=None, n_nodes=2000, return_triples=False,
+                     return_phase=False):
     """ln Lbar_ie for bank rows `rows` x extrinsic samples `ext_idx`.
 
     Returns dict with lnl [len(rows), E] and max lnL^ML [len(rows), E];
-    with return_triples also dh, hh [len(rows), E, N_phi].
+    with return_triples also dh, hh [len(rows), E, N_phi]; with
+    return_phase also lnl_phase [len(rows), E, N_phi], the distance-
+    marginalised ln Lbar_ieo of each triple.
     """
     ext_idx = np.arange(wl.n_ext) if ext_idx is None else np.asarray(ext_idx)
     ext = {k: np.asarray(v)[ext_idx] for k, v in wl.ext.items()}
@@ -289,6 +292,7 @@ def eval_pairs_block(wl, rows, ext_idx=None, n_nodes=2000, return_triples=False)
     mlmax = np.empty((len(rows), E))
     dhs = np.empty((len(rows), E, wl.n_phi)) if return_triples else None
     hhs = np.empty((len(rows), E, wl.n_phi)) if return_triples else None
+    lph = np.empty((len(rows), E, wl.n_phi)) if return_phase else None
     eb = max(1, min(E, 262144 // max(1, wl.n_phi * wl.d.shape[0] * len(wl.f))))
     for a, i in enumerate(rows):
         for s in range(0, E, eb):
@@ -296,6 +300,8 @@ def eval_pairs_block(wl, rows, ext_idx=None, n_nodes=2000, return_triples=False)
             dh, hh = triple_inner_products(wl.h[i], R[sl], t[sl], wl.f, mode_m, phis, wl.d, wl.w)
             lnl_o = ln_dist_marg(dh, hh, wl.d_max, wl.d0, n_nodes)
             lnl[a, sl] = _lse(lnl_o, axis=1) - math.log(wl.n_phi)
+            if return_phase:
+                lph[a, sl] = lnl_o
             mlmax[a, sl] = np.max(lnl_ml(dh, hh), axis=1)
             if return_triples:
                 dhs[a, sl] = dh
@@ -303,6 +309,8 @@ def eval_pairs_block(wl, rows, ext_idx=None, n_nodes=2000, return_triples=False)
     out = dict(lnl=lnl, ml_max=mlmax)
     if return_triples:
         out.update(dh=dhs, hh=hhs)
+    if return_phase:
+        out.update(lnl_phase=lph)
     return out
 
 
@@ -370,6 +378,42 @@ def evidence(wl, n_nodes=2000, processes=1, k=0):
         idx, vals = top_k(ev["lnp"], k)
         out.update(topk_idx=idx, topk_lnp=vals)
     return out
+
+
+# --------------------------------------------------------------------------
+# O11: effective sample sizes (Sec. III B eq. n_effective; Sec. V A eqs.
+# posterior_element, int_ess, ext_ess)
+# --------------------------------------------------------------------------
+def posterior_weights(wl, n_nodes=2000):
+    """ln p_ieo = ln w_i + ln w_e + ln w_o + ln Lbar_ieo with w_o = 1/N_phi
+    (eq. posterior_element): [N_i, N_e, N_phi]."""
+    r = eval_pairs_block(wl, np.arange(wl.n_int), n_nodes=n_nodes, return_phase=True)
+    return (np.asarray(wl.ln_w_int)[:, None, None] + np.asarray(wl.ln_w_ext)[None, :, None]
+            + r["lnl_phase"] - math.log(wl.n_phi))
+
+
+def effective_sizes(lnp3):
+    """From ln p_ieo [N_i, N_e, N_phi]: N_eff over triples (eq.
+    posterior_element), over intrinsic samples (eq. int_ess: squares of the
+    row sums over e and o), over extrinsic samples (eq. ext_ess: squares of
+    the column sums over i and o), and over pairs (eq. n_effective with
+    p_ie = sum_o p_ieo)."""
+    lnp3 = np.asarray(lnp3, dtype=np.float64)
+    with np.errstate(divide="ignore"):      # rows or columns with no weight at all
+        return _effective_sizes(lnp3)
+
+
+def _effective_sizes(lnp3):
+    tot = float(_lse(lnp3.ravel()))
+
+    def ratio(ln_parts):
+        return math.exp(2.0 * tot - float(_lse(2.0 * np.ravel(ln_parts))))
+
+    rows = _lse(lnp3.reshape(lnp3.shape[0], -1), axis=1)
+    cols = _lse(np.moveaxis(lnp3, 1, 0).reshape(lnp3.shape[1], -1), axis=1)
+    pairs = _lse(lnp3, axis=2)
+    return dict(n_eff=ratio(lnp3), n_eff_int=ratio(rows), n_eff_ext=ratio(cols),
+                n_eff_pairs=ratio(pairs))
 
 
 # --------------------------------------------------------------------------

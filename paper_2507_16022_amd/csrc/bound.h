@@ -494,6 +494,7 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
     EvAcc ev;
     ev.init();
     double tile_max = -INFINITY;
+    double my_lnp = -INFINITY;     // lane s: ln p of survivor s (-inf if not evaluated)
     for (int sidx = 0; sidx < n_surv; ++sidx) {
       const unsigned rc = a.surv[tile_id * kSurvCap + sidx];
       const int64_t ie = tm * 64 + (rc >> 8), e = tn * 64 + (rc & 255);
@@ -567,16 +568,19 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const double lm = __shfl_xor(lse.m, off, 64), ls = __shfl_xor(lse.s, off, 64);
-        lse.merge(lm, ls);
+        const double ls2 = __shfl_xor(lse.s2, off, 64);
+        lse.merge(lm, ls, ls2);
         const double bv = __shfl_xor(best, off, 64);
         const int bo = __shfl_xor(ob, off, 64);
         if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }
         mlmax = fmax(mlmax, __shfl_xor(mlmax, off, 64));
       }
       ev.ml_max = fmax(ev.ml_max, mlmax);
-      if (lane != 0 || lse.m == -INFINITY) continue;
+      if (lse.m == -INFINITY) continue;
       const double lnp = lnw + lse.m + log(lse.s) - a.ln_nphi;
-      ev.p.add(lnp);
+      if (lane == sidx) my_lnp = lnp;
+      if (lane != 0) continue;
+      ev.p.add(lnp, lse.sq_ratio());
       tile_max = fmax(tile_max, lnp);
       if (lnp >= fmax(thr_topk_glob, tile_max - a.topk_window)) {
         const unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
@@ -609,14 +613,28 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
     const double dmd = read_lane(dm == -INFINITY ? -INFINITY : (double)dm, 63);
     const double dsd = read_lane((double)ds, 63);
     const int n_marg_all = __builtin_amdgcn_readlane(n_marg, 63);
+    // the survivors' p in the tile's row and column sums, relative to the
+    // tile maximum, in survivor order (the bound pass left the sums zero)
+    const double tmax = read_lane(tile_max, 0);
+    for (int sidx = 0; sidx < n_surv; ++sidx) {
+      const double v = read_lane(my_lnp, sidx);
+      if (lane == 0 && v > -INFINITY) {
+        const unsigned rc = a.surv[tile_id * kSurvCap + sidx];
+        double* rs = a.rowcol + tile_id * 128;
+        const double x = exp(v - tmax);
+        rs[rc >> 8] += x;
+        rs[64 + (rc & 255)] += x;
+      }
+    }
     if (lane == 0) {
       double* out = a.partials + tile_id * kNPart;
       Lse d;
       d.m = out[3];
       d.s = out[4];
       d.s2 = 0.0;
+      d.s3 = 0.0;
       d.merge(dmd, dsd, 0.0);
-      out[0] = ev.p.m; out[1] = ev.p.s; out[2] = ev.p.s2;
+      out[0] = ev.p.m; out[1] = ev.p.s; out[2] = ev.p.s2; out[11] = ev.p.s3;
       out[3] = d.m; out[4] = d.s;
       out[5] = ev.ml_max; out[6] = (double)n_marg_all; out[9] = tile_max;
       if (ev.ml_max > 0.0)

@@ -93,30 +93,36 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 
-// online log-sum-exp accumulator (also of 2x)
+// online log-sum-exp accumulator of terms e^x: s = sum e^(x - m), s2 = sum
+// e^(2 (x - m)), and s3 = sum r e^(2 (x - m)) with a weight r per term (for
+// a pair, r = sum_o p_ieo^2 / p_ie^2: the triples' squares of eq.
+// posterior_element)
 struct Lse {
-  double m, s, s2;
-  __device__ void init() { m = -INFINITY; s = 0.0; s2 = 0.0; }
-  __device__ void add(double x) {
+  double m, s, s2, s3;
+  __device__ void init() { m = -INFINITY; s = 0.0; s2 = 0.0; s3 = 0.0; }
+  __device__ void add(double x, double r = 1.0) {
     if (x == -INFINITY) return;
     if (x > m) {
       double f = exp(m - x);
       s = s * f + 1.0;
       s2 = s2 * f * f + 1.0;
+      s3 = s3 * f * f + r;
       m = x;
     } else {
       double f = exp(x - m);
       s += f;
       s2 += f * f;
+      s3 += f * f * r;
     }
   }
-  __device__ void merge(double mb, double sb, double s2b) {
+  __device__ void merge(double mb, double sb, double s2b, double s3b = 0.0) {
     if (mb == -INFINITY) return;
-    if (m == -INFINITY) { m = mb; s = sb; s2 = s2b; return; }
+    if (m == -INFINITY) { m = mb; s = sb; s2 = s2b; s3 = s3b; return; }
     double mm = fmax(m, mb);
     double fa = exp(m - mm), fb = exp(mb - mm);
     s = s * fa + sb * fb;
     s2 = s2 * fa * fa + s2b * fb * fb;
+    s3 = s3 * fa * fa + s3b * fb * fb;
     m = mm;
   }
 };
@@ -127,24 +133,30 @@ struct Lse {
 // maximum, under 1e-37 of the sum, counts as zero); one exponential and no
 // branch per term
 struct LsePh {
-  double m, s;
-  __device__ void init() { m = -INFINITY; s = 0.0; }
+  double m, s, s2;     // s2: sum of the squared terms (the triples' squares)
+  __device__ void init() { m = -INFINITY; s = 0.0; s2 = 0.0; }
   __device__ void add(double x) {
     const double d = x - m;                       // +inf while empty
     const double t = (double)__expf(-fabsf((float)d));
     const bool up = d > 0.0;
     const double ns = up ? fma(s, t, 1.0) : s + t;
+    const double ns2 = up ? fma(s2, t * t, 1.0) : fma(t, t, s2);
     const bool skip = !(x > -INFINITY);
     s = skip ? s : ns;
+    s2 = skip ? s2 : ns2;
     m = (up && !skip) ? x : m;
   }
-  __device__ void merge(double mb, double sb) {
+  __device__ void merge(double mb, double sb, double s2b) {
     if (mb == -INFINITY) return;
-    if (m == -INFINITY) { m = mb; s = sb; return; }
+    if (m == -INFINITY) { m = mb; s = sb; s2 = s2b; return; }
     const double mm = fmax(m, mb);
-    s = s * exp(m - mm) + sb * exp(mb - mm);
+    const double fa = exp(m - mm), fb = exp(mb - mm);
+    s = s * fa + sb * fb;
+    s2 = s2 * fa * fa + s2b * fb * fb;
     m = mm;
   }
+  // sum_o p_o^2 / (sum_o p_o)^2 of the terms added
+  __device__ double sq_ratio() const { return s > 0.0 ? s2 / (s * s) : 1.0; }
 };
 
 __device__ __forceinline__ uint64_t order_bits(double x) {

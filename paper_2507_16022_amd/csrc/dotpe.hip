@@ -52,6 +52,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // 128 x 128 tiles an event needs before the bound pass replaces the fused
 // kernel's fast epilogue (fewer would leave the device partly idle)
 constexpr int64_t kBoundMinTiles = 2048;
+constexpr int64_t kMargPer = 256;     // tiles summed by one thread of the marginal pass
 
 }  // namespace
 
@@ -156,6 +157,9 @@ struct dotpe_event {
   int* surv_list = nullptr;      // bound pass: (tile, count) of tiles with listed survivors
   void* coef = nullptr;          // coefficient route: raw accumulators of coef_tiles tiles
   int64_t coef_tiles = 0;
+  double* rowcol = nullptr;      // per tile: row and column sums of the evaluated p [n_tiles][128]
+  double* marg_part = nullptr;   // marginals in parts along rows / columns of tiles
+  double* marg_blk = nullptr;    // block sums of the squared marginals
   hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<void*> allocs;
   uint64_t bytes = 0;
@@ -418,6 +422,7 @@ FusedArgs make_args(dotpe_ctx* ctx, dotpe_event* ev) {
   a.n_tiles = a.n_tiles_m * a.n_tiles_n;
   a.coef = ev->coef;
   a.coef_tiles = ev->coef_tiles;
+  a.rowcol = ev->rowcol;
   return a;
 }
 
@@ -790,6 +795,16 @@ std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) 
   v.push_back({(void**)&ev->cand, (size_t)D.cand_cap * 32, false});
   v.push_back({(void**)&ev->rerun, (size_t)D.n_tiles * sizeof(int), false});
   v.push_back({&ev->coef, (size_t)D.coef_tiles * D.coef_tile_bytes, false});
+  v.push_back({(void**)&ev->rowcol, (size_t)D.n_tiles * 128 * 8, false});
+  {
+    int tm, tn;
+    tile_shape(D.prec, &tm, &tn);
+    const int64_t ntm = (D.n_sub + tm - 1) / tm, ntn = (D.ne + tn - 1) / tn;
+    const int64_t parts = std::max(D.n_sub * ((ntn + kMargPer - 1) / kMargPer),
+                                   D.ne * ((ntm + kMargPer - 1) / kMargPer));
+    v.push_back({(void**)&ev->marg_part, (size_t)parts * 8, false});
+  }
+  v.push_back({(void**)&ev->marg_blk, (size_t)((std::max(D.n_sub, D.ne) + 255) / 256) * 8, false});
   if (D.prec != kFP64) {
     v.push_back({(void**)&ev->surv, (size_t)D.n_tiles * kSurvCap * sizeof(uint16_t), false});
     v.push_back({(void**)&ev->surv_list, (size_t)D.n_tiles * 2 * sizeof(int), false});
@@ -1035,9 +1050,14 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   a.rerun = ev->rerun;
   a.surv = ev->surv;
   a.surv_list = ev->surv_list;
-  a.rec_cap = (ev->flags & DOTPE_FLAG_RERUN_ALL) ? 0 : (1 << 30);
+  // the fast pass only bounds: a tile with any survivor takes the
+  // coefficient route (where every evaluated pair also enters its tile's
+  // row and column sums)
+  a.rec_cap = 0;
   const bool timed = ev->ev_t[0] != nullptr;
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, (a.n_tiles * 128 + 255) / 256)),
+                     dim3(256), 0, s, ev->rowcol, a.n_tiles * 128);
   if (timed) HIP_OK(hipEventRecord(ev->ev_t[0], s));
   // the cut needs a pilot over other rows of tiles than the ones it cuts;
   // without one the frozen threshold stays at zero and the cut is off
@@ -1094,9 +1114,25 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
                        per, ev->final_blk);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ev->final_blk, nblk, nblk,
                        ev->final_out);
+    // sums of the squared intrinsic and extrinsic marginals (final_out[13], [14])
+    int tm, tn;
+    tile_shape(prec, &tm, &tn);
+    for (int rows = 1; rows >= 0; --rows) {
+      const int64_t n_idx = rows ? ev->n_sub : ev->n_ext;
+      const int64_t nb = (n_idx + 255) / 256;
+      const int64_t n_other = rows ? a.n_tiles_n : a.n_tiles_m;
+      const int64_t n_parts = (n_other + kMargPer - 1) / kMargPer;
+      hipLaunchKernelGGL(k_marginal_part, dim3((unsigned)nb, (unsigned)n_parts), dim3(256), 0, s,
+                         ev->partials, ev->rowcol, ev->final_out, a.n_tiles_m, a.n_tiles_n, tm, tn,
+                         n_idx, rows, kMargPer, ev->marg_part);
+      hipLaunchKernelGGL(k_marginal_sq, dim3((unsigned)nb), dim3(256), 0, s, ev->marg_part, n_parts,
+                         n_idx, ev->marg_blk);
+      hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(256), 0, s, ev->marg_blk, nb,
+                         ev->final_out + kNPart + (rows ? 1 : 2));
+    }
   }
   HIP_OK(hipGetLastError());
-  double fo[kNPart];
+  double fo[kNPart + 3];
   uint64_t st[6];
   HIP_OK(hipMemcpyAsync(fo, ev->final_out, sizeof(fo), hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(st, ev->state, sizeof(st), hipMemcpyDeviceToHost, s));
@@ -1109,6 +1145,9 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   std::memset(&r, 0, sizeof(r));
   r.ln_sum_p = fo[0] + std::log(fo[1]);
   r.ln_sum_p2 = 2.0 * fo[0] + std::log(fo[2]);
+  r.ln_sum_p2_triples = 2.0 * fo[0] + std::log(fo[11]);
+  r.ln_sum_row2 = 2.0 * fo[9] + std::log(fo[kNPart + 1]);
+  r.ln_sum_col2 = 2.0 * fo[9] + std::log(fo[kNPart + 2]);
   r.ln_z = r.ln_sum_p - ln_norm;
   double ln_drop = (fo[3] == -INFINITY) ? -INFINITY : fo[3] + std::log(fo[4]);
   double mx = std::max(r.ln_sum_p, ln_drop);

@@ -24,6 +24,7 @@ __global__ __launch_bounds__(256) void k_e2_tiles(FusedArgs a) {
   __shared__ DistParams dp;
   __shared__ double lds_cs[kMaxM * kMaxPhi * 2];
   __shared__ double rowd[TM * 4], cold[TN * 3], rowq[TM * 2], red[NW * kNPart];
+  __shared__ double lnp_pair[NPT];       // ln p of each evaluated pair, -inf otherwise
   __shared__ unsigned long long tile_lnp_max;
 
   const int tid = threadIdx.x;
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(256) void k_e2_tiles(FusedArgs a) {
     for (int k = 0; k < NPT / NT; ++k) {
       // a wave takes consecutive pairs of a row: coalesced component reads
       const int p = k * NT + tid, tr = p / TN, tc = p % TN;
+      lnp_pair[p] = -INFINITY;
       if (!(tr < rows_in && tc < cols_in)) continue;
       ++n_pairs_i;
       AT x[2 * G], sv[NRT];
@@ -139,7 +141,8 @@ __global__ __launch_bounds__(256) void k_e2_tiles(FusedArgs a) {
       ev.ml_max = fmax(ev.ml_max, mlmax);
       if (lse.m == -INFINITY) continue;
       const double lnp = lnw + (lse.m + log(lse.s) - a.ln_nphi);
-      ev.p.add(lnp);
+      ev.p.add(lnp, lse.sq_ratio());
+      lnp_pair[p] = lnp;
       // top-k candidates within the window of the running maxima
       const unsigned long long ob_bits = order_bits(lnp);
       const unsigned long long prev = atomicMax(&tile_lnp_max, ob_bits);
@@ -156,6 +159,30 @@ __global__ __launch_bounds__(256) void k_e2_tiles(FusedArgs a) {
       }
     }
     tile_partial<NW>(a, ev, n_pairs_i, n_bounded_i, red, &tile_lnp_max, t);
+    // (every pair's ln p and the tile maximum are final: tile_partial has a
+    // barrier) the row and column sums relative to the tile maximum, each
+    // summed in index order
+    {
+      const unsigned long long mb = tile_lnp_max;
+      const double mxp = mb == 0ull ? -INFINITY : order_value(mb);
+      double* rc = a.rowcol + t * 128;
+      if (tid < TM) {
+        double sum = 0.0;
+        for (int c = 0; c < TN; ++c) {
+          const double v = lnp_pair[tid * TN + c];
+          sum += v == -INFINITY ? 0.0 : exp(v - mxp);
+        }
+        rc[tid] = sum;
+      } else if (tid < TM + TN) {
+        const int c = tid - TM;
+        double sum = 0.0;
+        for (int r = 0; r < TM; ++r) {
+          const double v = lnp_pair[r * TN + c];
+          sum += v == -INFINITY ? 0.0 : exp(v - mxp);
+        }
+        rc[64 + c] = sum;
+      }
+    }
     __syncthreads();   // the tile's scalars and reduction area are reused
   }
 }

@@ -75,6 +75,11 @@ struct FusedArgs {
   // (X_g re, im per group, then the (h|h) outputs), pairs row-major
   void* coef;
   int64_t work0, coef_tiles;
+  // per tile, the evaluated pairs' p_ie summed over each of its rows (64
+  // slots) and columns (64 slots, from slot 64), relative to the tile's
+  // largest ln p (partial [9]): the intrinsic and extrinsic marginals of
+  // eqs. int_ess and ext_ess are their sums over tiles
+  double* rowcol;
 };
 
 template <int PREC>
@@ -381,7 +386,8 @@ __device__ __forceinline__ void tile_partial(const FusedArgs& a, const EvAcc& ev
     unsigned long long pl = __ballot(ev.p.m != -INFINITY);
     while (pl) {
       const int src = __ffsll((long long)pl) - 1;
-      p.merge(read_lane(ev.p.m, src), read_lane(ev.p.s, src), read_lane(ev.p.s2, src));
+      p.merge(read_lane(ev.p.m, src), read_lane(ev.p.s, src), read_lane(ev.p.s2, src),
+              read_lane(ev.p.s3, src));
       pl &= pl - 1;
     }
     if (lane == 63) {
@@ -389,7 +395,7 @@ __device__ __forceinline__ void tile_partial(const FusedArgs& a, const EvAcc& ev
       r[0] = p.m; r[1] = p.s; r[2] = p.s2;
       r[3] = dm == -INFINITY ? -INFINITY : (double)dm;
       r[4] = ds; r[5] = w_ml; r[6] = (double)w_nm; r[7] = (double)w_nb; r[8] = (double)w_mb;
-      r[10] = (double)w_np;
+      r[10] = (double)w_np; r[11] = p.s3;
     }
   }
   __syncthreads();
@@ -399,7 +405,7 @@ __device__ __forceinline__ void tile_partial(const FusedArgs& a, const EvAcc& ev
     double mlm = 0.0, mb = -INFINITY, nm = 0, nb = 0, np_ = 0;
     for (int w = 0; w < NW; ++w) {
       const double* r = red + w * kNPart;
-      p.merge(r[0], r[1], r[2]);
+      p.merge(r[0], r[1], r[2], r[11]);
       d.merge(r[3], r[4], 0.0);
       mlm = fmax(mlm, r[5]);
       nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); np_ += r[10];
@@ -408,7 +414,7 @@ __device__ __forceinline__ void tile_partial(const FusedArgs& a, const EvAcc& ev
     const double mxp = order_value(*tile_lnp_max == 0ull ? 0x000fffffffffffffull : *tile_lnp_max);
     double* out = a.partials + tile_id * kNPart;
     out[0] = p.m; out[1] = p.s; out[2] = p.s2; out[3] = d.m; out[4] = d.s; out[5] = mlm;
-    out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = 0.0;
+    out[6] = nm; out[7] = nb; out[8] = mb; out[9] = mxp; out[10] = np_; out[11] = p.s3;
     // running maxima (the results are not waited for)
     if (mlm > 0.0) atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(mlm));
     if (mxp > -INFINITY) atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(mxp));
@@ -1092,7 +1098,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, unsigned char* sm
 #pragma unroll
       for (int off = LPS / 2; off > 0; off >>= 1) {
         const double lm = __shfl_xor(lse.m, off, LPS), ls = __shfl_xor(lse.s, off, LPS);
-        lse.merge(lm, ls);
+        const double ls2 = __shfl_xor(lse.s2, off, LPS);
+        lse.merge(lm, ls, ls2);
         const double bv = __shfl_xor(best, off, LPS);
         const int bo = __shfl_xor(ob, off, LPS);
         if (bv > best || (bv == best && bo < ob)) { best = bv; ob = bo; }
@@ -1109,7 +1116,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, unsigned char* sm
       ev.ml_max = fmax(ev.ml_max, mlmax);
       if (MODE == kPilot || lnl == -INFINITY) continue;
       const double lnp = lnw + lnl;
-      ev.p.add(lnp);
+      ev.p.add(lnp, lse.sq_ratio());
       if (MODE == kEvidence) {
         unsigned long long ob_bits = order_bits(lnp);
         unsigned long long prev = atomicMax(tile_lnp_max, ob_bits);

@@ -466,25 +466,25 @@ __global__ void k_finalize(const double* __restrict__ partials, int64_t n_tiles,
   double mlm = 0.0, mb = -INFINITY, mxp = -INFINITY, nm = 0, nb = 0, np_ = 0;
   for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
     const double* r = partials + t * kNPart;
-    p.merge(r[0], r[1], r[2]);
+    p.merge(r[0], r[1], r[2], r[11]);
     d.merge(r[3], r[4], 0.0);
     mlm = fmax(mlm, r[5]);
     nm += r[6]; nb += r[7]; mb = fmax(mb, r[8]); mxp = fmax(mxp, r[9]); np_ += r[10];
   }
   double* m = sh + threadIdx.x * kNPart;
   m[0] = p.m; m[1] = p.s; m[2] = p.s2; m[3] = d.m; m[4] = d.s; m[5] = mlm;
-  m[6] = nm; m[7] = nb; m[8] = mb; m[9] = mxp; m[10] = np_; m[11] = 0;
+  m[6] = nm; m[7] = nb; m[8] = mb; m[9] = mxp; m[10] = np_; m[11] = p.s3;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
       double* x = sh + threadIdx.x * kNPart;
       double* y = sh + (threadIdx.x + s) * kNPart;
       Lse pp, dd;
-      pp.m = x[0]; pp.s = x[1]; pp.s2 = x[2];
-      dd.m = x[3]; dd.s = x[4]; dd.s2 = 0.0;
-      pp.merge(y[0], y[1], y[2]);
+      pp.m = x[0]; pp.s = x[1]; pp.s2 = x[2]; pp.s3 = x[11];
+      dd.m = x[3]; dd.s = x[4]; dd.s2 = 0.0; dd.s3 = 0.0;
+      pp.merge(y[0], y[1], y[2], y[11]);
       dd.merge(y[3], y[4], 0.0);
-      x[0] = pp.m; x[1] = pp.s; x[2] = pp.s2; x[3] = dd.m; x[4] = dd.s;
+      x[0] = pp.m; x[1] = pp.s; x[2] = pp.s2; x[3] = dd.m; x[4] = dd.s; x[11] = pp.s3;
       x[5] = fmax(x[5], y[5]); x[6] += y[6]; x[7] += y[7]; x[8] = fmax(x[8], y[8]);
       x[9] = fmax(x[9], y[9]); x[10] += y[10];
     }
@@ -518,6 +518,73 @@ __global__ void k_bitonic_step(double* __restrict__ c, int64_t n, int64_t j, int
     }
   }
 }
+__global__ void k_zero(double* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
+// Marginals for eqs. int_ess and ext_ess: the sum of p_ie over one row i
+// (rows = 1) or one column e (rows = 0) of the pair matrix, from the tiles'
+// row and column sums scaled from each tile's maximum to the global maximum
+// M = final_out[9].  Block (x, c) sums the tiles c * q_per .. (c + 1) *
+// q_per - 1 along the row or column: part[c][x].
+__global__ void k_marginal_part(const double* __restrict__ partials, const double* __restrict__ rowcol,
+                                const double* __restrict__ final_out, int64_t n_tiles_m,
+                                int64_t n_tiles_n, int tm_rows, int tn_cols, int64_t n_idx, int rows,
+                                int64_t q_per, double* __restrict__ part) {
+  const double M = final_out[9];
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n_idx) return;
+  const int64_t outer = rows ? x / tm_rows : x / tn_cols;
+  const int slot = rows ? (int)(x % tm_rows) : 64 + (int)(x % tn_cols);
+  const int64_t n_other = rows ? n_tiles_n : n_tiles_m;
+  const int64_t q0 = (int64_t)blockIdx.y * q_per, q1 = min(n_other, q0 + q_per);
+  double P = 0.0;
+  if (M > -INFINITY)
+    for (int64_t q = q0; q < q1; ++q) {
+      const int64_t t = rows ? outer * n_tiles_n + q : q * n_tiles_n + outer;
+      const double mx = partials[t * kNPart + 9];
+      if (mx > -INFINITY) P += rowcol[t * 128 + slot] * exp(mx - M);
+    }
+  part[blockIdx.y * n_idx + x] = P;
+}
+
+// each index's marginal (the sum of its parts, in part order), squared;
+// block sums of the squares (tree order) to blk
+__global__ void k_marginal_sq(const double* __restrict__ part, int64_t n_parts, int64_t n_idx,
+                              double* __restrict__ blk) {
+  __shared__ double sh[256];
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (x < n_idx) {
+    double P = 0.0;
+    for (int64_t c = 0; c < n_parts; ++c) P += part[c * n_idx + x];
+    v = P * P;
+  }
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blk[blockIdx.x] = sh[0];
+}
+
+// out[0] = sum of blk[0 .. n) in a fixed order
+__global__ void k_sum_blocks(const double* __restrict__ blk, int64_t n, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += blk[i];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 __global__ void k_fill_cand(double* __restrict__ c, int64_t from, int64_t to) {
   int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= to) return;

@@ -68,7 +68,8 @@ class EvidenceResult(ctypes.Structure):
                 ("t_fused_ms", ctypes.c_double), ("cut_delta_used", ctypes.c_double),
                 ("n_passes", ctypes.c_int32), ("n_tiles_rerun", ctypes.c_int32),
                 ("t_main_ms", ctypes.c_double), ("n_tiles_listed", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("ln_sum_p2_triples", ctypes.c_double),
+                ("ln_sum_row2", ctypes.c_double), ("ln_sum_col2", ctypes.c_double)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -368,6 +369,12 @@ def _result(r, arr):
     out["topk_e"] = np.array([arr[q].e for q in range(n)], dtype=np.int64)
     out["topk_lnp"] = np.array([arr[q].ln_p for q in range(n)])
     out["topk_o"] = np.array([arr[q].o_best for q in range(n)], dtype=np.int32)
+    # effective sample sizes (eqs. n_effective over pairs, posterior_element, int_ess, ext_ess)
+    two = 2.0 * r.ln_sum_p
+    out["n_eff_pairs"] = float(np.exp(two - r.ln_sum_p2))
+    out["n_eff"] = float(np.exp(two - r.ln_sum_p2_triples))
+    out["n_eff_int"] = float(np.exp(two - r.ln_sum_row2))
+    out["n_eff_ext"] = float(np.exp(two - r.ln_sum_col2))
     return out
 
 

@@ -36,7 +36,7 @@ def test_struct_layouts():
     # sizes must match the C structs (checked against hand-computed layouts)
     assert ctypes.sizeof(dotpe.BankDesc) == 8 + 4 + 4 + 5 * 8 + 4 + 4
     assert ctypes.sizeof(dotpe.Sample) == 32
-    assert ctypes.sizeof(dotpe.EvidenceResult) == 7 * 8 + 3 * 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4 + 8 + 2 * 4
+    assert ctypes.sizeof(dotpe.EvidenceResult) == 7 * 8 + 3 * 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4 + 8 + 2 * 4 + 3 * 8
 
 
 STRUCTS = {

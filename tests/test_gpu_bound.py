@@ -59,7 +59,8 @@ def test_bound_pass_agrees(env, prec, cut, rows):
     # FP32 on the matrix cores on the other, so the rest agrees to rounding
     assert a["n_pairs_bounded"] == b["n_pairs_bounded"]
     assert abs(a["n_triples_marg"] - b["n_triples_marg"]) <= 1e-3 * b["n_triples_marg"] + 2
-    for k in ("ln_z", "ln_z_upper", "ln_sum_p2", "max_lnl_ml", "max_ln_p"):
+    for k in ("ln_z", "ln_z_upper", "ln_sum_p2", "max_lnl_ml", "max_ln_p", "ln_sum_p2_triples",
+              "ln_sum_row2", "ln_sum_col2"):
         assert abs(a[k] - b[k]) <= 1e-3, k
     assert a["topk_count"] == b["topk_count"] and a["topk_count"] > 0
     assert np.max(np.abs(a["topk_lnp"] - b["topk_lnp"])) <= 1e-3

@@ -48,6 +48,8 @@ def alone(ctx, bank, kw):
 
 def same(a, b):
     assert abs(a["ln_z"] - b["ln_z"]) <= TOL
+    for k in ("ln_sum_p2_triples", "ln_sum_row2", "ln_sum_col2"):
+        assert abs(a[k] - b[k]) <= TOL, k
     assert a["max_lnl_ml"] == pytest.approx(b["max_lnl_ml"], abs=TOL)
     assert a["n_pairs"] == b["n_pairs"]
     assert a["topk_count"] == b["topk_count"]
