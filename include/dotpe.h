@@ -229,6 +229,36 @@ typedef struct dotpe_sample {
 int dotpe_evidence(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* out,
                    dotpe_sample* topk);
 
+/* Posterior samples (Sec. III B: resampling by the probabilistic weights;
+ * Sec. V B: N_s = N_eff / 2).  After dotpe_evidence on the event, draws
+ * n_samples triples (i, e, o) and a distance each: pairs by systematic
+ * resampling over the weights p_ie of the pairs the last pass evaluated --
+ * draw s at cumulative mass (s + u0) / n_samples of the total, the pairs
+ * taken 64 x 64 tile by tile (tiles in row-major order of the tile grid,
+ * pairs row-major within a tile; an FP64 tile is 64 x 32) -- then, per pair,
+ * the phase o with probability Lbar_ieo over the phases the cut kept, and
+ * the distance D from its posterior given (dh_ieo, hh_ieo) with the D^2
+ * prior on (0, D_max], each by inverting its distribution at the uniform
+ * number 2 s (phase) and 2 s + 1 (distance) of a SplitMix64 generator seeded
+ * with `seed` (the distance's in v = d0/D, ascending: P(D' >= D) = u).
+ * n_samples <= 0 draws floor(N_eff / 2) with N_eff over triples (eq.
+ * posterior_element); at most `capacity`.  out: [capacity]
+ * host array; *n_out: samples written.  Synchronous.  Errors: INVALID_ARG
+ * (no evidence pass yet, u0 outside [0, 1)), OOM / ADMISSION, DEVICE. */
+typedef struct dotpe_posterior_sample {
+  int64_t i;                /* bank row (absolute index) */
+  int64_t e;                /* extrinsic sample */
+  int32_t o;                /* phase index, phi_o = 2 pi o / N_phi */
+  int32_t reserved;
+  double distance;          /* Mpc */
+  double ln_p_pair;         /* ln p_ie = ln w_i + ln w_e + ln Lbar_ie */
+  double ln_p_triple;       /* ln p_ieo = ln w_i + ln w_e + ln Lbar_ieo - ln N_phi */
+} dotpe_posterior_sample;
+
+int dotpe_sample_posterior(dotpe_ctx* ctx, dotpe_event* ev, int64_t n_samples, double u0,
+                           uint64_t seed, dotpe_posterior_sample* out, int64_t capacity,
+                           int64_t* n_out);
+
 /* dotpe_set_event + dotpe_evidence + dotpe_free_event in one call that
  * allocates no device memory (no hipMalloc / hipFree, no allocating library
  * routine): for callers that cannot allocate -- code that runs under HIP

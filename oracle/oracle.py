@@ -417,6 +417,82 @@ def _effective_sizes(lnp3):
 
 
 # --------------------------------------------------------------------------
+# O12: posterior samples (Sec. III B: resampling by the probabilistic
+# weights; Sec. V B: N_s = N_eff / 2)
+# --------------------------------------------------------------------------
+def splitmix64_uniform(seed, n):
+    """Output n (from 0) of a SplitMix64 generator (Steele, Lea and Flood,
+    2014) seeded with `seed`, as a uniform number in [0, 1) from its top 53
+    bits."""
+    mask = (1 << 64) - 1
+    z = (int(seed) + (int(n) + 1) * 0x9E3779B97F4A7C15) & mask
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+    z ^= z >> 31
+    return (z >> 11) * 2.0 ** -53
+
+
+def systematic_draws(weights, n_s, u0):
+    """Systematic resampling: draw s lands at cumulative mass (s + u0) W / n_s
+    of the weights in the order given (W their total); returns the index of
+    the first weight whose running sum exceeds it."""
+    cum = np.cumsum(np.asarray(weights, dtype=np.float64))
+    t = (np.arange(n_s) + u0) * cum[-1] / n_s
+    return np.minimum(np.searchsorted(cum, t, side="right"), len(cum) - 1)
+
+
+def inverse_cdf_index(weights, u):
+    """The first index whose running sum of the weights exceeds u x total."""
+    cum = np.cumsum(np.asarray(weights, dtype=np.float64))
+    return int(min(np.searchsorted(cum, u * cum[-1], side="right"), len(cum) - 1))
+
+
+def distance_posterior_draw(dh, hh, d_max, d0, u):
+    """The distance drawn at the uniform number u from the posterior of eq.
+    (lnl_dist_marginalized)'s integrand, pi(D) proportional to D^2 on
+    (0, D_max]: in v = d0/D its density is proportional to
+    v^-4 exp(dh v - hh v^2 / 2) on [d0/D_max, inf), and D = d0/v with
+    P(v' <= v) = u (so P(D' >= D) = u).  The distribution function by
+    adaptive quadrature, inverted by bisection to a relative 1e-12 in v."""
+    from scipy import integrate, optimize
+    v0 = d0 / d_max
+    vs = max(v0, dh / hh) if hh > 0 else v0
+    sg = 1.0 / math.sqrt(hh) if hh > 0 else v0
+    c = max(-4.0 * math.log(v) + dh * v - 0.5 * hh * v * v for v in (v0, vs))
+
+    def f(v):
+        return math.exp(-4.0 * math.log(v) + dh * v - 0.5 * hh * v * v - c)
+
+    # pieces: doubling steps from v0, and widths around the peak
+    hi = max(vs + 40.0 * sg, 1e4 * v0)
+    pts = {v0, hi}
+    v = v0
+    while v < hi:
+        pts.add(v)
+        v *= 2.0
+    for k in range(-40, 41):
+        x = vs + k * sg
+        if v0 < x < hi:
+            pts.add(x)
+    pts = sorted(pts)
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", integrate.IntegrationWarning)
+        seg = [integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-12, limit=200)[0]
+               for a, b in zip(pts[:-1], pts[1:])]
+        total = sum(seg)
+        target = u * total
+        run = 0.0
+        for (a, b), m in zip(zip(pts[:-1], pts[1:]), seg):
+            if run + m >= target:
+                g = lambda x: run + integrate.quad(f, a, x, epsabs=0.0, epsrel=1e-12, limit=200)[0] - target
+                vv = optimize.brentq(g, a, b, xtol=1e-15, rtol=1e-12)
+                return d0 / vv
+            run += m
+    return d0 / pts[-1]
+
+
+# --------------------------------------------------------------------------
 # P1: intrinsic pre-selection by the incoherent single-detector maximum
 # likelihood (Sec. IV D; App. B eqs. dh_itop, x_ML, single_det_ML)
 # --------------------------------------------------------------------------

@@ -190,6 +190,18 @@ __host__ __device__ __forceinline__ int64_t op_index(int64_t i, int64_t k, int64
 
 constexpr int kMaxNR = 2 * kMaxND - 1;   // (h|h) phase-coefficient outputs
 
+// SplitMix64 (Steele, Lea and Flood, 2014): output n (from 0) of the
+// generator seeded with `seed`, as a uniform double in [0, 1) from its top
+// 53 bits.  A counter-based source of the draws that the posterior sampling
+// needs: any draw is computed from (seed, n) alone.
+__host__ __device__ inline double sm64_uniform(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + (n + 1) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * 0x1.0p-53;
+}
+
 __device__ inline double swsh_m2(int l, int m, double cos_t) {
   // spin-weight -2 harmonic at azimuth 0: sqrt((2l+1)/4pi) d^l_{m,2}(theta)
   const double fact[13] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880, 3628800, 39916800,

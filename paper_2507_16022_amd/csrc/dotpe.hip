@@ -158,6 +158,9 @@ struct dotpe_event {
   void* coef = nullptr;          // coefficient route: raw accumulators of coef_tiles tiles
   int64_t coef_tiles = 0;
   double* rowcol = nullptr;      // per tile: row and column sums of the evaluated p [n_tiles][128]
+  bool evaluated = false;        // the last evidence pass's partials, state and results are
+  double last_cut = 0.0;         //   on the device: its cut_delta and N_eff over triples
+  double last_n_eff = 0.0;
   double* marg_part = nullptr;   // marginals in parts along rows / columns of tiles
   double* marg_blk = nullptr;    // block sums of the squared marginals
   hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1238,6 +1241,9 @@ static int evidence_run(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* 
   r.n_passes = passes;
   int rc = evidence_topk(ev, n_cand, &r, topk);
   if (rc) return rc;
+  ev->evaluated = true;
+  ev->last_cut = r.cut_delta_used;
+  ev->last_n_eff = std::exp(2.0 * r.ln_sum_p - r.ln_sum_p2_triples);
   r.status = DOTPE_OK;
   *out = r;
   return DOTPE_OK;
@@ -1427,6 +1433,89 @@ int dotpe_preselect(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_preselect_
   r.n_selected = n_sel;
   r.t_ms = ms;
   *out = r;
+  return DOTPE_OK;
+}
+
+int dotpe_sample_posterior(dotpe_ctx* ctx, dotpe_event* ev, int64_t n_samples, double u0,
+                           uint64_t seed, dotpe_posterior_sample* out, int64_t capacity,
+                           int64_t* n_out) {
+  if (!ctx || !ev || !out || !n_out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (!ev->evaluated) return fail(DOTPE_E_INVALID_ARG, "call dotpe_evidence on the event first");
+  if (!(u0 >= 0.0 && u0 < 1.0)) return fail(DOTPE_E_INVALID_ARG, "u0 must lie in [0, 1)");
+  if (capacity < 1) return fail(DOTPE_E_INVALID_ARG, "capacity must be positive");
+  int64_t ns = n_samples > 0 ? n_samples : (int64_t)std::floor(0.5 * ev->last_n_eff);
+  ns = std::max<int64_t>(1, std::min(ns, capacity));
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ev->stream;
+  const int prec = ev->bank->prec;
+  FusedArgs a = make_args(ctx, ev);
+  a.cut_delta = ev->last_cut;
+  a.state = ev->state;
+  a.partials = ev->partials;
+  a.final_out = ev->final_out;
+  a.d0 = ev->d0;
+  a.seed = seed;
+  std::vector<void*> bufs;
+  uint64_t held = 0;
+  struct Release {
+    dotpe_ctx* ctx;
+    std::vector<void*>* bufs;
+    uint64_t* held;
+    hipStream_t s;
+    ~Release() {
+      (void)hipStreamSynchronize(s);
+      for (void* p : *bufs) (void)hipFree(p);
+      ctx->bytes -= *held;
+    }
+  } release{ctx, &bufs, &held, s};
+  auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &bufs, &held); };
+  const int64_t nt = a.n_tiles, nb = (nt + 1023) / 1024;
+  double *cum = nullptr, *blk = nullptr, *res = nullptr, *smp = nullptr;
+  int *tile = nullptr, *list = nullptr;
+  int64_t *first = nullptr, *n_u_dev = nullptr;
+  int rc;
+  if ((rc = alloc((void**)&cum, (size_t)nt * 8)) || (rc = alloc((void**)&blk, (size_t)nb * 8)) ||
+      (rc = alloc((void**)&tile, (size_t)ns * 4)) || (rc = alloc((void**)&res, (size_t)ns * 8)) ||
+      (rc = alloc((void**)&list, (size_t)ns * 4)) || (rc = alloc((void**)&first, (size_t)(ns + 1) * 8)) ||
+      (rc = alloc((void**)&n_u_dev, 8)) || (rc = alloc((void**)&smp, (size_t)ns * 6 * 8)))
+    return rc;
+  hipLaunchKernelGGL(k_tile_mass, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, ev->partials,
+                     ev->final_out, nt, cum);
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(1024), 0, s, cum, nt, blk);
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(64), 0, s, blk, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(1024), 0, s, cum, nt, blk);
+  hipLaunchKernelGGL(k_place_draws, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, cum, nt, ns,
+                     u0, tile, res);
+  hipLaunchKernelGGL(k_group_draws, dim3(1), dim3(64), 0, s, tile, ns, list, first, n_u_dev);
+  HIP_OK(hipGetLastError());
+  int64_t n_u = 0;
+  HIP_OK(hipMemcpyAsync(&n_u, n_u_dev, 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  a.work_list = list;
+  a.n_work_list = n_u;
+  a.sample_first = first;
+  a.sample_res = res;
+  a.samples = smp;
+  const int64_t C = ev->coef_tiles;
+  for (int64_t c = 0; c * C < n_u; ++c) {
+    a.work0 = c * C;
+    if ((rc = launch_fused<kCoef>(prec, a, std::min(C, kCoefGrid), s))) return rc;
+    if ((rc = launch_fused<kSample>(prec, a, std::min(C, kE2Grid), s))) return rc;
+  }
+  std::vector<double> h((size_t)ns * 6);
+  HIP_OK(hipMemcpyAsync(h.data(), smp, (size_t)ns * 6 * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  for (int64_t q = 0; q < ns; ++q) {
+    dotpe_posterior_sample& o = out[q];
+    o.i = (int64_t)h[6 * q];
+    o.e = (int64_t)h[6 * q + 1];
+    o.o = (int32_t)h[6 * q + 2];
+    o.reserved = 0;
+    o.distance = h[6 * q + 3];
+    o.ln_p_pair = h[6 * q + 4];
+    o.ln_p_triple = h[6 * q + 5];
+  }
+  *n_out = ns;
   return DOTPE_OK;
 }
 

@@ -80,6 +80,16 @@ struct FusedArgs {
   // largest ln p (partial [9]): the intrinsic and extrinsic marginals of
   // eqs. int_ess and ext_ess are their sums over tiles
   double* rowcol;
+  // posterior sampling: the tiles to evaluate again (ascending), and per
+  // tile the range of samples that fall in it
+  const int* work_list;
+  int64_t n_work_list;
+  const int64_t* sample_first;   // [n_work_list + 1]
+  const double* sample_res;      // [n_samples] residual mass within the tile (relative to e^M)
+  double* samples;               // [n_samples][6]: i, e, o, D, ln p_ie, ln p_ieo
+  uint64_t seed;                 // counter-based uniforms for the phase and distance draws
+  const double* final_out;       // the reduced results (the global max of ln p at [9])
+  double d0;                     // distance the bank is stored at
 };
 
 template <int PREC>
@@ -191,7 +201,8 @@ __device__ __forceinline__ void mma(typename Pol<PREC>::Acc& acc, const uint4& a
   }
 }
 
-enum Mode { kEval = 0, kEvidence = 1, kPilot = 2, kBound = 3, kSurvivors = 4, kCoef = 5, kE2 = 6 };
+enum Mode { kEval = 0, kEvidence = 1, kPilot = 2, kBound = 3, kSurvivors = 4, kCoef = 5, kE2 = 6,
+            kSample = 7 };
 
 // The cut of an evidence pass is on when the threshold frozen after the
 // pilot (state[3], the pilot's largest lnL^ML) less cut_delta is above
@@ -201,10 +212,13 @@ enum Mode { kEval = 0, kEvidence = 1, kPilot = 2, kBound = 3, kSurvivors = 4, kC
 __device__ __forceinline__ bool cut_on(const FusedArgs& a) {
   return a.cut_delta > 0.0 && __longlong_as_double(a.state[3]) - a.cut_delta > 0.0;
 }
+// (a sampling pass names its tiles in work_list instead)
 __device__ __forceinline__ int64_t coef_work_count(const FusedArgs& a) {
+  if (a.work_list) return a.n_work_list;
   return cut_on(a) ? (int64_t)a.state[4] : a.n_tiles;
 }
 __device__ __forceinline__ int64_t coef_tile(const FusedArgs& a, int64_t q) {
+  if (a.work_list) return a.work_list[q];
   return cut_on(a) ? (int64_t)a.rerun[q] : q;
 }
 
@@ -291,6 +305,32 @@ struct EvAcc {
 // lnL^ML to mlmax; cut phases' upper bounds go to ev.drop.  The caller
 // combines the parts of one pair.  INL: the distance rule inlined (for a
 // kernel whose lanes each evaluate many pairs).
+// dh and hh of phase o of one pair from X_g and the (h|h) phase
+// coefficients (hh clamped at zero)
+template <int G>
+__device__ __forceinline__ void phase_dh_hh(const FusedArgs& a, const double* lds_cs,
+                                            const double2 (&X)[G], double S0,
+                                            const double (&Sr)[kMaxND], const double (&Si)[kMaxND],
+                                            int o, double& dh_out, double& hh_out) {
+  const ModeTables& mt = a.mt;
+  double dh = 0.0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const double* cs = lds_cs + ((mt.gm[g] - 1) * a.n_phi + o) * 2;
+    dh += X[g].x * cs[0] - X[g].y * cs[1];
+  }
+  double hh = S0;
+#pragma unroll
+  for (int d = 1; d < kMaxND; ++d) {
+    if (d < mt.ND) {
+      const double* cs = lds_cs + ((d - 1) * a.n_phi + o) * 2;
+      hh += 2.0 * (Sr[d] * cs[0] + Si[d] * cs[1]);
+    }
+  }
+  dh_out = dh;
+  hh_out = fmax(hh, 0.0);
+}
+
 template <int MODE, int G, bool INL = false>
 __device__ void pair_phases(const FusedArgs& a, const double* lds_cs, const DistParams& dp,
                             int64_t ie, int64_t e,
@@ -298,28 +338,13 @@ __device__ void pair_phases(const FusedArgs& a, const double* lds_cs, const Dist
                             const double (&Si)[kMaxND], double lnw, double thr_ml, int o0, int os,
                             EvAcc& ev, LsePh& lse, double& best, int& o_best, double& mlmax) {
   constexpr bool EVAL = MODE == kEval;
-  const ModeTables& mt = a.mt;
-  const int ND = mt.ND;
   const double thr2 = 2.0 * thr_ml;
   // the largest lnL^ML = dh^2 / (2 hh), kept as a fraction (mn / md) and
   // divided once at the end
   double mn = 0.0, md = 1.0;
   for (int o = o0; o < a.n_phi; o += os) {
-    double dh = 0.0;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const double* cs = lds_cs + ((mt.gm[g] - 1) * a.n_phi + o) * 2;
-      dh += X[g].x * cs[0] - X[g].y * cs[1];
-    }
-    double hh = S0;
-#pragma unroll
-    for (int d = 1; d < kMaxND; ++d) {
-      if (d < ND) {
-        const double* cs = lds_cs + ((d - 1) * a.n_phi + o) * 2;
-        hh += 2.0 * (Sr[d] * cs[0] + Si[d] * cs[1]);
-      }
-    }
-    hh = fmax(hh, 0.0);
+    double dh, hh;
+    phase_dh_hh<G>(a, lds_cs, X, S0, Sr, Si, o, dh, hh);
     if (EVAL && a.trip_out) {
       size_t t = (((size_t)ie * a.n_ext + e) * a.n_phi + o) * 2;
       a.trip_out[t] = dh;

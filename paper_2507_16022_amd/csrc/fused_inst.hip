@@ -70,6 +70,12 @@ hipError_t launch_e2(const FusedArgs& a, int64_t grid, hipStream_t s) {
 }
 
 template <int PREC, int G>
+hipError_t launch_sample(const FusedArgs& a, int64_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_sample_tiles<PREC, G>), dim3((unsigned)grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int PREC, int G>
 hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hipStream_t s) {
   switch (mode) {
     case kEval: return launch_one<PREC, G, kEval, false>(a, grid, s);
@@ -82,6 +88,7 @@ hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hip
     case kSurvivors: return launch_survivors<PREC, G>(a, grid, s);
     case kCoef: return launch_one<PREC, G, kCoef, false>(a, grid, s);
     case kE2: return launch_e2<PREC, G>(a, grid, s);
+    case kSample: return launch_sample<PREC, G>(a, grid, s);
   }
   return hipErrorInvalidValue;
 }

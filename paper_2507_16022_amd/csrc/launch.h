@@ -16,7 +16,8 @@ namespace dotpe {
 // kBound (split precisions; `grid` counts 128 x 128 tiles), kSurvivors
 // (split precisions; workgroups of 4 waves that take the listed tiles in
 // turn), kCoef or kE2 (the coefficient route: workgroups that take the
-// chunk's work items in turn).  Launches `grid` workgroups on stream s and
+// chunk's work items in turn), kSample (posterior draws in the listed
+// tiles, after kCoef over the same list).  Launches `grid` workgroups on stream s and
 // returns the launch status.
 typedef hipError_t (*FusedLaunchFn)(int mode, bool fast, const FusedArgs& a, int64_t grid,
                                     hipStream_t s);

@@ -585,6 +585,85 @@ __global__ void k_sum_blocks(const double* __restrict__ blk, int64_t n, double* 
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// ---------------------------------------------------------------------------
+// posterior sampling: the tiles' masses, their running sum, the systematic
+// draws placed in tiles
+// ---------------------------------------------------------------------------
+// mass of tile t relative to e^M (M = final_out[9]): e^(p.m - M) p.s
+__global__ void k_tile_mass(const double* __restrict__ partials, const double* __restrict__ final_out,
+                            int64_t n_tiles, double* __restrict__ mass) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const double M = final_out[9], m = partials[t * kNPart], s = partials[t * kNPart + 1];
+  mass[t] = (m > -INFINITY && M > -INFINITY) ? exp(m - M) * s : 0.0;
+}
+
+// inclusive running sum in place, in three steps over blocks of 1024: each
+// block's own running sum (its total to blk), the blocks' offsets (one
+// thread, in order), the offsets added
+__global__ void k_scan_block(double* __restrict__ x, int64_t n, double* __restrict__ blk) {
+  __shared__ double sh[1024];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  sh[threadIdx.x] = i < n ? x[i] : 0.0;
+  __syncthreads();
+  for (int s = 1; s < 1024; s <<= 1) {
+    const double v = threadIdx.x >= (unsigned)s ? sh[threadIdx.x - s] : 0.0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (i < n) x[i] = sh[threadIdx.x];
+  if (threadIdx.x == 1023) blk[blockIdx.x] = sh[1023];
+}
+__global__ void k_scan_offsets(double* __restrict__ blk, int64_t nb) {
+  if (threadIdx.x != 0) return;
+  double run = 0.0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const double v = blk[b];
+    blk[b] = run;
+    run += v;
+  }
+}
+__global__ void k_scan_add(double* __restrict__ x, int64_t n, const double* __restrict__ blk) {
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  if (i < n) x[i] += blk[blockIdx.x];
+}
+
+// systematic draws t_s = (s + u0) W / n_s (W = the total mass, cum[n - 1])
+// placed in tiles: the first tile whose running sum exceeds t_s, and the
+// residual t_s minus the mass before that tile
+__global__ void k_place_draws(const double* __restrict__ cum, int64_t n_tiles, int64_t n_s, double u0,
+                              int* __restrict__ tile, double* __restrict__ res) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_s) return;
+  const double W = cum[n_tiles - 1];
+  const double ts = ((double)s + u0) * W / (double)n_s;
+  int64_t lo = 0, hi = n_tiles - 1;     // first index with cum > ts (the last if none)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (cum[mid] > ts) hi = mid;
+    else lo = mid + 1;
+  }
+  tile[s] = (int)lo;
+  res[s] = ts - (lo > 0 ? cum[lo - 1] : 0.0);
+}
+
+// the distinct tiles of the (ascending) draws and, per distinct tile, its
+// first draw; n_out[0] = number of distinct tiles (one thread, in order)
+__global__ void k_group_draws(const int* __restrict__ tile, int64_t n_s, int* __restrict__ list,
+                              int64_t* __restrict__ first, int64_t* __restrict__ n_out) {
+  if (threadIdx.x != 0) return;
+  int64_t u = 0;
+  for (int64_t s = 0; s < n_s; ++s)
+    if (s == 0 || tile[s] != tile[s - 1]) {
+      list[u] = tile[s];
+      first[u] = s;
+      ++u;
+    }
+  first[u] = n_s;
+  n_out[0] = u;
+}
+
 __global__ void k_fill_cand(double* __restrict__ c, int64_t from, int64_t to) {
   int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= to) return;

@@ -96,6 +96,12 @@ class PreselectResult(ctypes.Structure):
                 ("n_rows", ctypes.c_int64), ("n_selected", ctypes.c_int64), ("t_ms", ctypes.c_double)]
 
 
+class PosteriorSample(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int64), ("e", ctypes.c_int64), ("o", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("distance", ctypes.c_double),
+                ("ln_p_pair", ctypes.c_double), ("ln_p_triple", ctypes.c_double)]
+
+
 class Sample(ctypes.Structure):
     _fields_ = [("i", ctypes.c_int64), ("e", ctypes.c_int64), ("ln_p", ctypes.c_double),
                 ("o_best", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -122,6 +128,9 @@ SYMBOLS = {
                                               ctypes.POINTER(EvidenceResult), ctypes.c_void_p]),
     "dotpe_event_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(EventDesc),
                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "dotpe_sample_posterior": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                               ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p,
+                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "dotpe_preselect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PreselectDesc),
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(PreselectResult)]),
@@ -436,6 +445,21 @@ class Event:
         _check(load_library().dotpe_evidence(self.ctx.handle, self._h, ctypes.byref(r),
                                              ctypes.cast(arr, ctypes.c_void_p) if k else None))
         return _result(r, arr)
+
+    def sample_posterior(self, n_samples=0, u0=0.5, seed=0, capacity=1 << 20):
+        """dotpe_sample_posterior after evidence(): arrays i, e, o, distance, ln_p_pair,
+        ln_p_triple of the draws (n_samples <= 0: floor(N_eff / 2))."""
+        cap = int(n_samples) if n_samples > 0 else int(capacity)
+        arr = (PosteriorSample * cap)()
+        n = ctypes.c_int64()
+        _check(load_library().dotpe_sample_posterior(self.ctx.handle, self._h, int(n_samples),
+                                                     float(u0), ctypes.c_uint64(int(seed)),
+                                                     ctypes.cast(arr, ctypes.c_void_p), cap,
+                                                     ctypes.byref(n)))
+        m = n.value
+        out = {name: np.array([getattr(arr[q], name) for q in range(m)])
+               for name, _ in PosteriorSample._fields_ if name != "reserved"}
+        return out
 
     def response(self):
         """(R [n_ext, n_det, n_modes] complex, t [n_ext, n_det]) from the device."""

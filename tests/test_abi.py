@@ -47,6 +47,7 @@ STRUCTS = {
     "dotpe_server_desc": dotpe.ServerDesc,
     "dotpe_ticket_info": dotpe.TicketInfo,
     "dotpe_preselect_desc": dotpe.PreselectDesc,
+    "dotpe_posterior_sample": dotpe.PosteriorSample,
     "dotpe_preselect_result": dotpe.PreselectResult,
 }
 
