@@ -374,11 +374,11 @@ def main():
     # events on the event's stream around its launch
     alg_flops = 8.0 * len(modes) * 256 * n_pairs          # (d|h) contraction, detector-folded
     achieved = alg_flops / (main_ms * 1e-3) / 1e12
-    # matrix-core work actually issued: 3 split products of re and im over K2 = 2 x modes x
-    # 256 positions, plus the 7 (h|h) blocks of 32 (FP64: one product each)
+    # matrix-core work actually issued: one product (of the hi parts in the split
+    # precisions, FP64 otherwise) each for re and im over K2 = 2 x modes x 256 positions,
+    # plus the 7 (h|h) blocks of 32
     k2 = 2 * len(modes) * 256
-    n_split = 1 if args.precision == "fp64" else 3
-    exec_flops = n_split * (2 * 2 * k2 + 2 * 32 * 7) * float(n_pairs)
+    exec_flops = (2 * 2 * k2 + 2 * 32 * 7) * float(n_pairs)
     executed = exec_flops / (main_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     log(f"step {dt * 1e3:.1f} ms, fused {fused_ms:.1f} ms, pilot {pilot_ms:.1f} ms, "

@@ -25,6 +25,16 @@ int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const doub
  * Synchronous.  Errors: INVALID_ARG, DEVICE. */
 int dotpe_debug_response(dotpe_ctx* ctx, const dotpe_event* ev, double* R, double* t);
 
+/* The bound pass's certified upper bounds on each pair's largest lnL^ML over
+ * the phases (eq. bestfit_lnl), from the hi parts of the split operands and
+ * the Cauchy-Schwarz margin for the rest: out [2][n_sub][n_ext] host floats,
+ * plane 0 with the margin from the norms of whole rows, plane 1 with the
+ * margin per m group and (h|h) output; +inf where the (h|h) lower bound is
+ * not positive.  Nothing is cut and the event's evidence state is
+ * untouched.  Synchronous.  Errors: INVALID_ARG (FP64 bank), OOM /
+ * ADMISSION, DEVICE. */
+int dotpe_debug_bound(dotpe_ctx* ctx, dotpe_event* ev, float* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,15 +1,31 @@
 // Bound pass of the evidence with the coherent cut (split precisions).
 //
 // Every pair's certified upper bound on lnL^ML (eq. bestfit_lnl) is
-//     bound = (sx^2 / sh) U0^2 / (2 lo0),  U0 = sum_g |X_g|,
-//     lo0 = S0 - 2 sum_{delta > 0} |S_delta|  (<= hh_o for every phase o),
-// the same quantity the fused kernel's first epilogue step uses.  This
-// kernel computes only that: the (h|h) phase coefficients first, folded
-// into lo0 as each output completes, then the (d|h) contraction one m group
-// at a time, each group's |X_g| added into U0 as the group completes.  So
-// a wave keeps lo0, U0 and one group's accumulators -- 64 x 64 pairs per
-// wave instead of the fused kernel's 32 x 32 -- and a 128 x 128 tile reads
-// half the operand bytes per pair from L2 and LDS.
+//     bound = (sx^2 / sh) U^2 / (2 lo),   U >= sum_g |X_g|,
+//     lo <= S0 - 2 sum_{delta > 0} |S_delta|   (<= hh_o for every phase o).
+// This kernel forms it from products of the hi parts of the split operands
+// alone -- one matrix-core product per real product, where the value itself
+// takes three -- and bounds what that leaves out by Cauchy-Schwarz: with
+// a = ah + al and b = bh + bl (complex vectors over a row's positions),
+//     |sum a b - fl(sum ah bh)| <= |ah| |bl| + |al| |bh| + |al| |bl|
+//                                  + sqrt2 gamma_K |ah| |bh|,
+// |.| the 2-norm and gamma_K = K 2^-23 for the FP32 accumulation of K real
+// products.  k_operand_norms gives these norms per operand row and per m
+// group ((d|h)) or output ((h|h)), so with c_0 = 1, c_r = 2 for the outputs
+// r > 0 (Re, Im of S_delta):
+//     U  = sum_g |X~_g| + sum_g [ah_g (bl_g + sqrt2 gamma_g bh_g) + al_g (bh_g + bl_g)],
+//     lo = S~0 - 2 sum |S~_delta|
+//          - sum_r c_r [nh_r (ql_r + gamma_32 qh_r) + nl_r (qh_r + ql_r)]
+// (a, b: bank and extrinsic operand rows; n, q: the (h|h) operand rows).
+// Each sum is a dot product of a row vector with a column vector, which
+// Cauchy-Schwarz bounds by the product of their norms; that looser margin
+// (four multiply-adds per pair) decides almost every pair, and only pairs
+// it leaves near the threshold take the per-group one.  The (h|h) phase
+// coefficients come first,
+// folded into lo as each output completes, then the (d|h) contraction one m
+// group at a time, each group's |X_g| added into U as the group completes.
+// So a wave keeps lo, U and one group's accumulators: 64 x 64 pairs per
+// wave, a 128 x 128 tile per workgroup.
 //
 // Each wave's 64 x 64 quadrant is one tile of the fused kernel's grid.  A
 // quadrant all of whose pairs are bounded writes that tile's partial (the
@@ -26,12 +42,18 @@ namespace dotpe {
 struct BoundTile {
   static constexpr int NT = 256;           // 4 waves, one per SIMD
   static constexpr int TS = 128;           // rows and columns per tile
-  static constexpr int NS = 4;             // LDS stages
-  static constexpr int ARR = 8192;         // bytes of one operand array per stage
-  static constexpr int STAGE = 4 * ARR;    // A hi, A lo, B hi, B lo
+  static constexpr int NS = 7;             // LDS stages
+  static constexpr int LPC = 4;            // 1 KB loads per wave per chunk
+  static constexpr int ARR = 8192;         // bytes of one operand's hi part per stage
+  static constexpr int STAGE = 2 * ARR;    // A hi, B hi
+  static constexpr int NV = 24;            // margin factors per row or column
   static constexpr int ROWQ_OFF = NS * STAGE;            // double2 [128]: q factor, ln w
   static constexpr int COLQ_OFF = ROWQ_OFF + TS * 16;    // double2 [128]
-  static constexpr int LDS_BYTES = COLQ_OFF + TS * 16;
+  static constexpr int ROWN_OFF = COLQ_OFF + TS * 16;    // float4 [128]: the norms of whole rows
+  static constexpr int COLN_OFF = ROWN_OFF + TS * 16;    // float4 [128]
+  static constexpr int ROWT_OFF = COLN_OFF + TS * 16;    // float [128][NV]: per group and output
+  static constexpr int COLT_OFF = ROWT_OFF + TS * NV * 4;
+  static constexpr int LDS_BYTES = COLT_OFF + TS * NV * 4;
 };
 
 // Keep a value computed here: without it the compiler may defer the
@@ -40,6 +62,16 @@ struct BoundTile {
 template <typename T>
 __device__ __forceinline__ void pin(T& x) {
   __asm__ __volatile__("" : "+v"(x));
+}
+
+// pipeline_barrier with at most n (0..M, uniform over the workgroup) chunks
+// of LPC loads each still in flight
+template <int M, int LPC>
+__device__ __forceinline__ void barrier_in_flight(int n) {
+  static_for<M + 1>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    if (n == q) pipeline_barrier<q * LPC>();
+  });
 }
 
 template <int PREC, int G>
@@ -51,10 +83,10 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   typedef __attribute__((address_space(3))) void lvoid;
   constexpr int ES = 2;                         // bytes per operand element
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;    // (h|h) outputs: S0, Re/Im S_1..3
-  constexpr int NS = BT::NS;
+  constexpr int NS = BT::NS, LPC = BT::LPC;
   extern __shared__ __align__(16) unsigned char smem[];
   // with the cut off the coefficient route takes every tile
-  if (!cut_on(a)) return;
+  if (!a.bound_out && !cut_on(a)) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -79,98 +111,143 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   }
   const int64_t row0 = sm_ * BT::TS, col0 = sn_ * BT::TS;
 
-  // per-row and per-column factors of the bound: q = row_scale^2 / ah_scale
-  // (x the column's; powers of two, each possibly outside float range, so
-  // multiplied in double) and ln w
+  // per row and column: the factors of the bound (q = row_scale^2 /
+  // ah_scale x the column's: powers of two, each possibly outside float
+  // range, so multiplied in double; ln w) and of its margin, per group and
+  // output (row: ah_g, al_g, nh_r, nl_r at 0, 4, 8, 16; column: bl_g +
+  // sqrt2 gamma_g bh_g, bh_g + bl_g, c_r (ql_r + gamma_32 qh_r), c_r (qh_r +
+  // ql_r) at the same places) and the norms of those four vectors (rounded
+  // up) for the margin of whole rows
   double2* rowq = (double2*)(smem + BT::ROWQ_OFF);
   double2* colq = (double2*)(smem + BT::COLQ_OFF);
-  if (tid < BT::TS) {
+  float4* rown = (float4*)(smem + BT::ROWN_OFF);
+  float4* coln = (float4*)(smem + BT::COLN_OFF);
+  float* rowt = (float*)(smem + BT::ROWT_OFF);
+  float* colt = (float*)(smem + BT::COLT_OFF);
+  {
+    const bool is_row = tid < BT::TS;
+    const int t = is_row ? tid : tid - BT::TS;
     double2 v = make_double2(1.0, 0.0);
-    const int64_t ie = row0 + tid;
-    if (ie < a.n_sub) {
-      const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-      const double rs = a.row_scale[i];
-      v = make_double2(rs * rs / a.ah_scale[ie], a.ln_w_bank ? a.ln_w_bank[i] : 0.0);
+    float f[BT::NV];
+#pragma unroll
+    for (int k = 0; k < BT::NV; ++k) f[k] = 0.f;
+    if (is_row) {
+      const int64_t ie = row0 + t;
+      if (ie < a.n_sub) {
+        const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
+        const double rs = a.row_scale[i];
+        v = make_double2(rs * rs / a.ah_scale[ie], a.ln_w_bank ? a.ln_w_bank[i] : 0.0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const float2 x = a.a_nrm[i * G + g];
+          f[g] = x.x;
+          f[4 + g] = x.y;
+        }
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          const float2 x = a.ah_nrm[ie * NRT + r];
+          f[8 + r] = x.x;
+          f[16 + r] = x.y;
+        }
+      }
+    } else {
+      const int64_t e = col0 + t;
+      if (e < a.n_ext) {
+        const double cs = a.col_scale[e];
+        v = make_double2(cs * cs / a.bh_scale[e], a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const float2 x = a.b_nrm[e * G + g];
+          f[g] = x.y + a.gam_dh[g] * x.x;
+          f[4 + g] = x.x + x.y;
+        }
+#pragma unroll
+        for (int r = 0; r < NRT; ++r) {
+          const float2 x = a.bh_nrm[e * NRT + r];
+          const float c = r == 0 ? 1.f : 2.f;
+          f[8 + r] = c * (x.y + a.gam_hh * x.x);
+          f[16 + r] = c * (x.x + x.y);
+        }
+      }
     }
-    rowq[tid] = v;
-  } else {
-    double2 v = make_double2(1.0, 0.0);
-    const int64_t e = col0 + (tid - BT::TS);
-    if (e < a.n_ext) {
-      const double cs = a.col_scale[e];
-      v = make_double2(cs * cs / a.bh_scale[e], a.ln_w_ext ? a.ln_w_ext[e] : 0.0);
+    float nv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k0 = q < 2 ? 4 * q : 8 * q - 8, nk = q < 2 ? 4 : 8;
+      float s = 0.f;
+      for (int k = 0; k < nk; ++k) s += f[k0 + k] * f[k0 + k];
+      nv[q] = __builtin_sqrtf(s) * (1.f + 0x1p-18f);
     }
-    colq[tid - BT::TS] = v;
+    float* dst = (is_row ? rowt : colt) + t * BT::NV;
+#pragma unroll
+    for (int k = 0; k < BT::NV; k += 4) *(float4*)(dst + k) = make_float4(f[k], f[k + 1], f[k + 2], f[k + 3]);
+    (is_row ? rowq : colq)[t] = v;
+    (is_row ? rown : coln)[t] = make_float4(nv[0], nv[1], nv[2], nv[3]);
   }
 
-  // ---- operand streams: wave w loads array w (A hi, A lo, B hi, B lo) of
-  // every chunk: 32-row blocks 0..3, slices 0 and 1, 1 KB each copied as it
-  // sits in HBM (fragment order).  A lane's address of block rb, slice 0;
+  // ---- operand streams: waves 0, 1 load the A hi rows of 32-row blocks
+  // 2 w, 2 w + 1, waves 2, 3 the B hi rows of blocks 2 (w - 2), 2 (w - 2) + 1:
+  // of every chunk, slices 0 and 1 of both blocks, 1 KB each copied as it
+  // sits in HBM (fragment order).  A lane's address of block q, slice 0;
   // slice 1 is 1 KB further.  Rows past the subset re-read the last row;
   // columns run to the padded sample count (a multiple of 128, zero rows
   // past n_ext). ----
-  gbyte* src_dh[4];
-  gbyte* src_hh[4];
+  gbyte* src_dh[2];
+  gbyte* src_hh[2];
+  auto blk = [](int64_t i, int64_t K) { return (i >> 5) * (K >> 5) * 1024 + (i & 31) * 8; };
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    const int r = 32 * rb + (lane & 31);
+  for (int q = 0; q < 2; ++q) {
+    const int r = 32 * (2 * (wave & 1) + q) + (lane & 31);
     const int64_t in_chunk = (lane >> 5) * 256;
-    auto blk = [](int64_t i, int64_t K) { return (i >> 5) * (K >> 5) * 1024 + (i & 31) * 8; };
     if (wave < 2) {
       const int64_t ie = min(row0 + r, a.n_sub - 1);
       const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
-      src_dh[rb] = (gbyte*)(wave == 0 ? a.A0 : a.A1) + (blk(i, a.K2) + in_chunk) * ES;
-      src_hh[rb] = (gbyte*)(wave == 0 ? a.Ah0 : a.Ah1) + (blk(ie, a.KH) + in_chunk) * ES;
+      src_dh[q] = (gbyte*)a.A0 + (blk(i, a.K2) + in_chunk) * ES;
+      src_hh[q] = (gbyte*)a.Ah0 + (blk(ie, a.KH) + in_chunk) * ES;
     } else {
       const int64_t e = col0 + r;
-      src_dh[rb] = (gbyte*)(wave == 2 ? a.B0 : a.B1) + (blk(e, a.K2) + in_chunk) * ES;
-      src_hh[rb] = (gbyte*)(wave == 2 ? a.Bh0 : a.Bh1) + (blk(e, a.KH) + in_chunk) * ES;
+      src_dh[q] = (gbyte*)a.B0 + (blk(e, a.K2) + in_chunk) * ES;
+      src_hh[q] = (gbyte*)a.Bh0 + (blk(e, a.KH) + in_chunk) * ES;
     }
   }
   // chunks: NRT (h|h) blocks first, then the (d|h) chunks; chunk c sits in
-  // stage c mod NS
+  // stage c mod NS, where this wave's part starts 4 KB x wave in
   const int ndh = a.n_chunks;
   const int nk = NRT + ndh;
   const unsigned lds_wave =
-      __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lvoid*)(smem + wave * BT::ARR));
-  // the 8 loads of chunk c (block rb, slice s to stage offset (2 rb + s) KB),
-  // two blocks of 4 sharing one M0 value each: the immediate offset applies
-  // to the global and the LDS address alike.  The asm saves and restores M0
-  // and waits the state an M0 write needs.
+      __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lvoid*)(smem + wave * 4096));
+  // the 4 loads of chunk c (block q, slice s to stage offset (2 q + s) KB)
+  // sharing one M0 value: the immediate offset applies to the global and
+  // the LDS address alike.  The asm saves and restores M0 and waits the
+  // state an M0 write needs.
   auto issue = [&](int c) {
-    gbyte* p[4];
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-      p[rb] = c < NRT ? src_hh[rb] + (int64_t)c * 1024 * ES
-                      : src_dh[rb] + (int64_t)(c - NRT) * 1024 * ES;
+    gbyte* p0 = c < NRT ? src_hh[0] + (int64_t)c * 1024 * ES
+                        : src_dh[0] + (int64_t)(c - NRT) * 1024 * ES;
+    gbyte* p1 = c < NRT ? src_hh[1] + (int64_t)c * 1024 * ES
+                        : src_dh[1] + (int64_t)(c - NRT) * 1024 * ES;
     const unsigned base = lds_wave + (unsigned)((c % NS) * BT::STAGE);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      unsigned m0_saved;
-      __asm__ __volatile__(
-          "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
-          "global_load_lds_dwordx4 %2, off\n\t"
-          "global_load_lds_dwordx4 %2, off offset:1024\n\t"
-          "global_load_lds_dwordx4 %3, off offset:2048\n\t"
-          "global_load_lds_dwordx4 %3, off offset:3072\n\ts_mov_b32 m0, %0"
-          : "=&s"(m0_saved)
-          : "s"(__builtin_amdgcn_readfirstlane(base + 4096u * h)), "v"(p[2 * h]),
-            "v"(p[2 * h + 1] - 2048)
-          : "memory");
-    }
+    unsigned m0_saved;
+    __asm__ __volatile__(
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+        "global_load_lds_dwordx4 %2, off\n\t"
+        "global_load_lds_dwordx4 %2, off offset:1024\n\t"
+        "global_load_lds_dwordx4 %3, off offset:2048\n\t"
+        "global_load_lds_dwordx4 %3, off offset:3072\n\ts_mov_b32 m0, %0"
+        : "=&s"(m0_saved)
+        : "s"(__builtin_amdgcn_readfirstlane(base)), "v"(p0), "v"(p1 - 2048)
+        : "memory");
   };
 
   // Fragments of one chunk for this wave: A rows 64 wm + 32 bm (FA: [bm]
-  // [slice][hi, lo]) and B rows 64 wn + 32 bn (FB: [slice][hi, lo], one per
-  // bn).  The products of a chunk run in two halves, bn = 0 then bn = 1.
-  // During the first half the bn = 1 fragments of the same chunk are read;
-  // during the second, the A and bn = 0 fragments of the next chunk.  So at
-  // most 24 fragments are live, not the 32 of two whole chunks.
+  // [slice]) and B rows 64 wn + 32 bn (FB: [slice], one per bn).  The
+  // products of a chunk run in two halves, bn = 0 then bn = 1.  During the
+  // first half the bn = 1 fragments of the same chunk are read, and the A
+  // and bn = 0 fragments of the next chunk.
   struct FA {
-    uint4 v[2][2][2];
+    uint4 v[2][2];
   };
   struct FB {
-    uint4 v[2][2];
+    uint4 v[2];
   };
   FA fa0, fa1;
   FB fb0_0, fb0_1, fb1;
@@ -183,22 +260,22 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     else return fb0_1;
   };
   auto stage_lane = [&](int c) { return smem + (c % NS) * BT::STAGE + lane * 16; };
-  auto read_a = [&](FA& f, int c, int k) {    // k: block (k >> 2), slice, hi / lo
-    const int bm = (k >> 2) & 1, sl = (k >> 1) & 1, lo = k & 1;
-    f.v[bm][sl][lo] = *(const uint4*)(stage_lane(c) + lo * BT::ARR + (2 * (2 * wm + bm) + sl) * 1024);
+  auto read_a = [&](FA& f, int c, int k) {    // k: block (k >> 1), slice
+    const int bm = k >> 1, sl = k & 1;
+    f.v[bm][sl] = *(const uint4*)(stage_lane(c) + (2 * (2 * wm + bm) + sl) * 1024);
   };
-  auto read_b = [&](FB& f, int c, int bn, int k) {   // k: slice, hi / lo
-    const int sl = (k >> 1) & 1, lo = k & 1;
-    f.v[sl][lo] = *(const uint4*)(stage_lane(c) + (2 + lo) * BT::ARR + (2 * (2 * wn + bn) + sl) * 1024);
+  auto read_b = [&](FB& f, int c, int bn, int sl) {
+    f.v[sl] = *(const uint4*)(stage_lane(c) + BT::ARR + (2 * (2 * wn + bn) + sl) * 1024);
   };
   auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
 
-  // Step j (fragment parity P = j mod 2): wait until this wave's loads of
-  // chunk j + 1 have landed and every wave is done with chunk j - 1, issue
-  // chunk j + 3 into the stage chunk j - 1 used, then the products of chunk
-  // j (NH per half; mf(fa, fb, bm, k) issues product k of block (bm, bn))
-  // with the fragment reads between them.  After the last chunk the reads
-  // fetch a stale stage, unused, so no branch sits between the products.
+  // Step j (fragment parity P = j mod 2): wait until chunk j + 1 has landed
+  // (every wave's loads) and every wave is done with chunk j - 1, issue
+  // chunk j + NS - 1 into the stage chunk j - 1 used, then the products of
+  // chunk j (NH per half; mf(fa, fb, bm, bn, k) issues product k of block
+  // (bm, bn)) with the fragment reads between them.  After the last chunk
+  // the reads fetch a stale stage, unused, so no branch sits between the
+  // products.
   auto step = [&](int j, auto pi, auto nh, auto&& mf) {
     constexpr int P = decltype(pi)::value % 2;
     constexpr int NH = decltype(nh)::value;
@@ -206,31 +283,27 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     FA& anxt = fa(std::integral_constant<int, P + 1>{});
     FB& bcur = fb0(std::integral_constant<int, P>{});
     FB& bnxt = fb0(std::integral_constant<int, P + 1>{});
-    if (j + 2 < nk) pipeline_barrier<8>();
-    else pipeline_barrier<0>();
-    if (j + 3 < nk) {
+    // chunks j + 2 .. min(j + NS - 2, nk - 1) may stay in flight
+    barrier_in_flight<NS - 2, LPC>(max(0, min(NS - 3, nk - 2 - j)));
+    if (j + NS - 1 < nk) {
       fence();
-      issue(j + 3);
+      issue(j + NS - 1);
       fence();
     }
-    // half 0: blocks (0, 0), (1, 0), with all 16 reads after its first 16
-    // products: this chunk's bn = 1 fragments, then the next chunk's A and
-    // bn = 0 (their registers are free since the previous step), so that
-    // they are complete long before they are used and before the next
-    // barrier waits for them
+    // half 0: blocks (0, 0), (1, 0), a read after each of its products
     static_for<2 * NH>([&](auto ti) {
       constexpr int t = decltype(ti)::value;
       mf(acur, bcur, t & 1, 0, t >> 1);
-      if constexpr (t < 4) read_b(fb1, j, 1, t);
-      else if constexpr (t < 12) read_a(anxt, j + 1, t - 4);
-      else if constexpr (t < 16) read_b(bnxt, j + 1, 0, t - 12);
+      if constexpr (t < 2) read_b(fb1, j, 1, t);
+      else if constexpr (t < 6) read_a(anxt, j + 1, t - 2);
+      else if constexpr (t < 8) read_b(bnxt, j + 1, 0, t - 6);
     });
-    static_for<16>([&](auto ki) {     // reads not placed between products
+    static_for<8>([&](auto ki) {     // reads not placed between products
       constexpr int k = decltype(ki)::value;
       if constexpr (k >= 2 * NH) {
-        if constexpr (k < 4) read_b(fb1, j, 1, k);
-        else if constexpr (k < 12) read_a(anxt, j + 1, k - 4);
-        else read_b(bnxt, j + 1, 0, k - 12);
+        if constexpr (k < 2) read_b(fb1, j, 1, k);
+        else if constexpr (k < 6) read_a(anxt, j + 1, k - 2);
+        else read_b(bnxt, j + 1, 0, k - 6);
       }
     });
     // half 1: blocks (0, 1), (1, 1)
@@ -240,23 +313,19 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     });
   };
 
-  // prologue: chunks 0, 1, 2 in flight, chunk 0's A and bn = 0 fragments read
+  // prologue: chunks 0 .. NS - 2 in flight; once chunk 0 has landed, its A
+  // and bn = 0 fragments are read
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < NS - 1; ++c)
     if (c < nk) issue(c);
-  pipeline_barrier<0>();     // (also makes rowq / colq visible)
-  static_for<8>([&](auto ki) { read_a(fa0, 0, decltype(ki)::value); });
-  static_for<4>([&](auto ki) { read_b(fb0_0, 0, 0, decltype(ki)::value); });
+  barrier_in_flight<NS - 2, LPC>(min(NS - 2, nk - 1));   // (also makes rowq .. coln visible)
+  static_for<4>([&](auto ki) { read_a(fa0, 0, decltype(ki)::value); });
+  static_for<2>([&](auto ki) { read_b(fb0_0, 0, 0, decltype(ki)::value); });
 
   // ---- (h|h): lo0 = S0 - 2 sum |S_delta| per pair, output by output ----
   Acc s0[2][2], sabs[2][2], sre[2][2], hacc[2][2];
-  auto mf_hh = [&](const FA& A, const FB& B, int bm, int bn, int k) {   // k: 0..5
-    const int sl = k / 3;
-    switch (k % 3) {
-      case 0: mma<PREC>(hacc[bm][bn], A.v[bm][sl][1], B.v[sl][0]); break;
-      case 1: mma<PREC>(hacc[bm][bn], A.v[bm][sl][0], B.v[sl][1]); break;
-      default: mma<PREC>(hacc[bm][bn], A.v[bm][sl][0], B.v[sl][0]); break;
-    }
+  auto mf_hh = [&](const FA& A, const FB& B, int bm, int bn, int k) {   // k: slice
+    mma<PREC>(hacc[bm][bn], A.v[bm][k], B.v[k]);
   };
   static_for<NRT>([&](auto ri) {
     constexpr int r = decltype(ri)::value;
@@ -264,7 +333,7 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
       for (int bn = 0; bn < 2; ++bn) hacc[bm][bn] = Acc{};
-    step(r, std::integral_constant<int, r>{}, std::integral_constant<int, 6>{}, mf_hh);
+    step(r, std::integral_constant<int, r>{}, std::integral_constant<int, 2>{}, mf_hh);
 #pragma unroll
     for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -284,7 +353,7 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
         }
       }
   });
-  // lo0 with the rounding margin of the fused kernel's bound
+  // lo0 with a margin for the rounding of the fold itself
   Acc lo0[2][2];
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm)
@@ -306,9 +375,8 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn) u0[bm][bn] = Acc{};
-  // product k (0..11) of block (bm, bn): with A = [hr | hi] and B_re =
-  // [Br | -Bi] by slice, B_im = [Bi | Br] = [-(B_re slice 1) | B_re slice 0];
-  // 3 split products per real product, re and im alternating
+  // product k (0..3) of block (bm, bn): with A = [hr | hi] and B_re =
+  // [Br | -Bi] by slice, B_im = [Bi | Br] = [-(B_re slice 1) | B_re slice 0]
   auto neg = [](const uint4& x) {
     return make_uint4(x.x ^ 0x80008000u, x.y ^ 0x80008000u, x.z ^ 0x80008000u, x.w ^ 0x80008000u);
   };
@@ -316,18 +384,10 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     Acc& re = acc[bm][bn][0];
     Acc& im = acc[bm][bn][1];
     switch (k) {
-      case 0: mma<PREC>(re, A.v[bm][0][1], B.v[0][0]); break;
-      case 1: mma<PREC>(im, A.v[bm][0][1], neg(B.v[1][0])); break;
-      case 2: mma<PREC>(re, A.v[bm][0][0], B.v[0][1]); break;
-      case 3: mma<PREC>(im, A.v[bm][0][0], neg(B.v[1][1])); break;
-      case 4: mma<PREC>(re, A.v[bm][0][0], B.v[0][0]); break;
-      case 5: mma<PREC>(im, A.v[bm][0][0], neg(B.v[1][0])); break;
-      case 6: mma<PREC>(re, A.v[bm][1][1], B.v[1][0]); break;
-      case 7: mma<PREC>(im, A.v[bm][1][1], B.v[0][0]); break;
-      case 8: mma<PREC>(re, A.v[bm][1][0], B.v[1][1]); break;
-      case 9: mma<PREC>(im, A.v[bm][1][0], B.v[0][1]); break;
-      case 10: mma<PREC>(re, A.v[bm][1][0], B.v[1][0]); break;
-      default: mma<PREC>(im, A.v[bm][1][0], B.v[0][0]); break;
+      case 0: mma<PREC>(re, A.v[bm][0], B.v[0]); break;
+      case 1: mma<PREC>(im, A.v[bm][0], neg(B.v[1])); break;
+      case 2: mma<PREC>(re, A.v[bm][1], B.v[1]); break;
+      default: mma<PREC>(im, A.v[bm][1], B.v[0]); break;
     }
   };
   int ch = 0;
@@ -344,8 +404,8 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     // every step is static
     const int gend = a.mt.gk0[g + 1];
     for (; ch < gend; ch += 2) {
-      step(NRT + ch, std::integral_constant<int, NRT>{}, std::integral_constant<int, 12>{}, mf_dh);
-      step(NRT + ch + 1, std::integral_constant<int, NRT + 1>{}, std::integral_constant<int, 12>{},
+      step(NRT + ch, std::integral_constant<int, NRT>{}, std::integral_constant<int, 4>{}, mf_dh);
+      step(NRT + ch + 1, std::integral_constant<int, NRT + 1>{}, std::integral_constant<int, 4>{},
            mf_dh);
     }
 #pragma unroll
@@ -369,6 +429,59 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   const int64_t tile_id = tm * a.n_tiles_n + tn;
   const int rows_in = (int)min((int64_t)64, a.n_sub - tm * 64);
   const int cols_in = (int)min((int64_t)64, a.n_ext - tn * 64);
+  // bound from the accumulators and a margin (q, ln w of the pair's row and
+  // column in rq, cq)
+  auto bound_of = [](double2 rq, double2 cq, float U0, float lo) {
+    // rcp is within an ulp; the 1.001 factor covers it
+    return (float)(rq.x * cq.x) * (U0 * U0) * __builtin_amdgcn_rcpf(2.f * lo) * 1.001f + 1e-3f;
+  };
+  // margin per group and output: row factors r, column factors c
+  auto tight = [](const float* r, const float* c, float& du, float& dl) {
+    du = 0.f;
+    dl = 0.f;
+#pragma unroll
+    for (int g = 0; g < G; ++g) du += r[g] * c[g] + r[4 + g] * c[4 + g];
+#pragma unroll
+    for (int q = 0; q < NRT; ++q) dl += r[8 + q] * c[8 + q] + r[16 + q] * c[16 + q];
+  };
+  auto load_nv = [](const float* p, float* f) {
+#pragma unroll
+    for (int k = 0; k < BoundTile::NV; k += 4) {
+      const float4 v = *(const float4*)(p + k);
+      f[k] = v.x; f[k + 1] = v.y; f[k + 2] = v.z; f[k + 3] = v.w;
+    }
+  };
+  if (a.bound_out) {
+    const int64_t plane = a.n_sub * a.n_ext;
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int tr = 32 * bm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const double2 rq = rowq[64 * wm + tr];
+        const float4 rn = rown[64 * wm + tr];
+        float rt[BT::NV];
+        load_nv(rowt + (64 * wm + tr) * BT::NV, rt);
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+          const int tc = 32 * bn + (lane & 31);
+          if (tr >= rows_in || tc >= cols_in) continue;
+          const double2 cq = colq[64 * wn + tc];
+          const float4 cn = coln[64 * wn + tc];
+          float ct[BT::NV];
+          load_nv(colt + (64 * wn + tc) * BT::NV, ct);
+          float du, dl;
+          tight(rt, ct, du, dl);
+          const float U0 = u0[bm][bn][e], lo = lo0[bm][bn][e];
+          const float Ul = U0 + (rn.x * cn.x + rn.y * cn.y), ll = lo - (rn.z * cn.z + rn.w * cn.w);
+          const float Ut = U0 + du, lt = lo - dl;
+          const int64_t o = (tm * 64 + tr) * a.n_ext + tn * 64 + tc;
+          a.bound_out[o] = ll > 0.f ? bound_of(rq, cq, Ul, ll) : INFINITY;
+          a.bound_out[plane + o] = lt > 0.f ? bound_of(rq, cq, Ut, lt) : INFINITY;
+        }
+      }
+    return;
+  }
   const float thr_f = (float)(__longlong_as_double(a.state[3]) - a.cut_delta);
   // The bounded mass is summed against a fixed reference: every bounded
   // pair has bound < thr_f and ln w no larger than the tile's largest row
@@ -378,27 +491,69 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   const float lw_max = wave_max((double)rowq[64 * wm + lane].y) + wave_max((double)colq[64 * wn + lane].y);
   const float m_ref = thr_f + lw_max;
   float dsum = 0.f, max_bound = -INFINITY;
-  unsigned smask[2] = {0u, 0u};   // survivors of this lane, per bn: bit 16 bm + e
+  // first with the margin of whole rows; pairs it leaves (bit 16 bm + e of
+  // tmask[bn]) with the margin per group and output; survivors of both in
+  // smask
+  unsigned tmask[2] = {0u, 0u}, smask[2] = {0u, 0u};
+  double2 cq[2];
+  float4 cn[2];
+  bool col_in[2];
 #pragma unroll
   for (int bn = 0; bn < 2; ++bn) {
     const int tc = 32 * bn + (lane & 31);
-    const double2 cq = colq[64 * wn + tc];
-    const bool col_in = tc < cols_in;
+    cq[bn] = colq[64 * wn + tc];
+    cn[bn] = coln[64 * wn + tc];
+    col_in[bn] = tc < cols_in;
+  }
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int tr = 32 * bm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      const double2 rq = rowq[64 * wm + tr];
+      const float4 rn = rown[64 * wm + tr];
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        const bool in = col_in[bn] && tr < rows_in;
+        const float U0 = u0[bm][bn][e] + (rn.x * cn[bn].x + rn.y * cn[bn].y);
+        const float lo = lo0[bm][bn][e] - (rn.z * cn[bn].z + rn.w * cn[bn].w);
+        const float bound = bound_of(rq, cq[bn], U0, lo);
+        const bool bounded = in && lo > 0.f && bound < thr_f;
+        const float x = (float)(rq.y + cq[bn].y) + bound;
+        dsum += bounded ? __expf(x - m_ref) : 0.f;
+        max_bound = bounded ? fmaxf(max_bound, x) : max_bound;
+        tmask[bn] |= (in && !bounded) ? 1u << (16 * bm + e) : 0u;
+      }
+    }
+  if (__ballot((tmask[0] | tmask[1]) != 0u)) {
+    float ct[2][BT::NV];
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) load_nv(colt + (64 * wn + 32 * bn + (lane & 31)) * BT::NV, ct[bn]);
 #pragma unroll
     for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
+        const unsigned bit = 1u << (16 * bm + e);
+        if (!__ballot(((tmask[0] | tmask[1]) & bit) != 0u)) continue;
         const int tr = 32 * bm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         const double2 rq = rowq[64 * wm + tr];
-        const bool in = col_in && tr < rows_in;
-        const float U0 = u0[bm][bn][e], lo = lo0[bm][bn][e];
-        // rcp is within an ulp; the 1.001 factor covers it
-        const float bound = (float)(rq.x * cq.x) * (U0 * U0) * __builtin_amdgcn_rcpf(2.f * lo) * 1.001f + 1e-3f;
-        const bool bounded = in && lo > 0.f && bound < thr_f;
-        const float x = (float)(rq.y + cq.y) + bound;
-        dsum += bounded ? __expf(x - m_ref) : 0.f;
-        max_bound = bounded ? fmaxf(max_bound, x) : max_bound;
-        smask[bn] |= (in && !bounded) ? 1u << (16 * bm + e) : 0u;
+        float rt[BT::NV];
+        load_nv(rowt + (64 * wm + tr) * BT::NV, rt);
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) {
+          if (!(tmask[bn] & bit)) continue;
+          float du, dl;
+          tight(rt, ct[bn], du, dl);
+          const float lo = lo0[bm][bn][e] - dl;
+          const float bound = bound_of(rq, cq[bn], u0[bm][bn][e] + du, lo);
+          if (lo > 0.f && bound < thr_f) {
+            const float x = (float)(rq.y + cq[bn].y) + bound;
+            dsum += __expf(x - m_ref);
+            max_bound = fmaxf(max_bound, x);
+          } else {
+            smask[bn] |= bit;
+          }
+        }
       }
   }
   // survivors in a fixed order (bn, bm, element, lane)

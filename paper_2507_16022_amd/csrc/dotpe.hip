@@ -115,6 +115,7 @@ struct dotpe_bank {
   void* A0 = nullptr;
   void* A1 = nullptr;
   double* row_scale = nullptr;
+  float2* nrm = nullptr;        // split precisions: per row, norms of the hi and left-out parts
   double* ln_w = nullptr;
   uint64_t bytes = 0;
 };
@@ -140,6 +141,9 @@ struct dotpe_event {
   double* ah_scale = nullptr;
   void* Bh[2] = {nullptr, nullptr};   // column-side (h|h) operand [n_ext_p][KH]
   double* bh_scale = nullptr;
+  float2* b_nrm = nullptr;     // split precisions: per row of B, Ah, Bh, norms of the hi
+  float2* ah_nrm = nullptr;    //   and left-out parts (the bound pass's margin)
+  float2* bh_nrm = nullptr;
   double2* Q = nullptr;
   double* R2 = nullptr;
   double2* R = nullptr;
@@ -358,6 +362,37 @@ void launch_hh(dotpe_event* ev, const double* w) {
                      ev->Bh[0], ev->Bh[1], ev->bh_scale);
 }
 
+// chunk ranges of the m groups of a (d|h) operand row
+NormRanges group_ranges(const ModeTables& mt) {
+  NormRanges r{};
+  r.n = mt.G;
+  for (int g = 0; g <= mt.G; ++g) r.c0[g] = mt.gk0[g];
+  return r;
+}
+
+// (h|h) phase-coefficient outputs the kernels use: S0, and Re, Im of
+// S_1..3 with more than one m group
+int hh_outputs(int G) { return G == 1 ? 1 : kMaxNR; }
+
+// chunk ranges of those outputs in a (h|h) operand row (one chunk each)
+NormRanges output_ranges(int G) {
+  NormRanges r{};
+  r.n = hh_outputs(G);
+  for (int q = 0; q <= r.n; ++q) r.c0[q] = q;
+  return r;
+}
+
+// per-row, per-range norms of a split operand (no-op for FP64)
+void launch_norms(int prec, const void* P0, const void* P1, int64_t n_rows, int64_t K,
+                  const NormRanges& rg, float2* out, hipStream_t s) {
+  if (prec == kFP64 || n_rows <= 0) return;
+  const dim3 g((unsigned)((n_rows + 255) / 256));
+  if (prec == kFP16X2)
+    hipLaunchKernelGGL(k_operand_norms<kFP16X2>, g, dim3(256), 0, s, P0, P1, n_rows, K, rg, out);
+  else
+    hipLaunchKernelGGL(k_operand_norms<kBF16X2>, g, dim3(256), 0, s, P0, P1, n_rows, K, rg, out);
+}
+
 // FAST (evidence pass only): every pair through the bound first, one full
 // evaluation pass after, tiles with too many survivors listed for a rerun
 template <int MODE, bool FAST = false>
@@ -408,6 +443,13 @@ FusedArgs make_args(dotpe_ctx* ctx, dotpe_event* ev) {
   a.Bh1 = ev->Bh[1];
   a.bh_scale = ev->bh_scale;
   a.KH = ev->KH;
+  a.a_nrm = bk->nrm;
+  a.b_nrm = ev->b_nrm;
+  a.ah_nrm = ev->ah_nrm;
+  a.bh_nrm = ev->bh_nrm;
+  for (int g = 0; g < bk->mt.G; ++g)
+    a.gam_dh[g] = (float)(1.4143 * 32.0 * (bk->mt.gk0[g + 1] - bk->mt.gk0[g]) * 0x1p-23);
+  a.gam_hh = (float)(32.0 * 0x1p-23);
   a.n_det = ev->n_det;
   a.mt = bk->mt;
   a.n_phi = ev->n_phi;
@@ -564,6 +606,9 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
     if ((rc = dev_alloc(ctx, &bk->A1, nA * esz, &owned, &bk->bytes))) return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&bk->row_scale, bk->n_wf * 8, &owned, &bk->bytes)))
       return cleanup(rc);
+    if ((rc = dev_alloc(ctx, (void**)&bk->nrm, bk->n_wf * bk->mt.G * sizeof(float2), &owned,
+                        &bk->bytes)))
+      return cleanup(rc);
   }
   if ((rc = dev_alloc(ctx, (void**)&bk->f, bk->n_b * 8, &owned, &bk->bytes))) return cleanup(rc);
   if ((rc = dev_alloc(ctx, (void**)&bk->ln_w, bk->n_wf * 8, &owned, &bk->bytes)))
@@ -627,6 +672,8 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
     (void)hipFree(stagebuf);
     if (e) return hip_fail(e, "bank staging");
   }
+  launch_norms(bk->prec, bk->A0, bk->A1, bk->n_wf, bk->K2, group_ranges(bk->mt), bk->nrm, s);
+  if ((e = hipGetLastError())) return hip_fail(e, "bank norms");
   int herr = 0;
   if ((e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s)))
     return hip_fail(e, "copy err");
@@ -643,7 +690,8 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
 int dotpe_free_bank(dotpe_ctx* ctx, dotpe_bank* bk) {
   if (!ctx || !bk) return DOTPE_OK;
   (void)hipSetDevice(ctx->device);
-  for (void* p : {bk->A0, bk->A1, (void*)bk->row_scale, (void*)bk->f, (void*)bk->ln_w})
+  for (void* p : {bk->A0, bk->A1, (void*)bk->row_scale, (void*)bk->nrm, (void*)bk->f,
+                  (void*)bk->ln_w})
     if (p) (void)hipFree(p);
   ctx->bytes -= bk->bytes;
   delete bk;
@@ -668,7 +716,7 @@ namespace {
 
 // validated description of one event and the shapes derived from it
 struct EvDims {
-  int nk = 0, nb = 0, nc = 0, n_bp = 0, n_phi = 0, KH = 0, NP = 0, prec = 0;
+  int nk = 0, nb = 0, nc = 0, n_bp = 0, n_phi = 0, KH = 0, NP = 0, prec = 0, G = 0;
   int64_t ne = 0, ne_p = 0, n_sub = 0, K2 = 0, n_tiles = 0, cand_cap = 0;
   int64_t coef_tiles = 0;          // tiles per chunk of the coefficient route
   uint64_t coef_tile_bytes = 0;    // their raw accumulators, bytes per tile
@@ -735,6 +783,7 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
   D->n_phi = d->n_phi;
   D->KH = KH;
   D->NP = bk->mt.NP;
+  D->G = bk->mt.G;
   D->prec = bk->prec;
   D->ne = ne;
   D->ne_p = round_up(ne, 128);   // whole 128-sample tiles of the bound pass
@@ -783,6 +832,9 @@ std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) 
   if (D.prec != kFP64) {
     v.push_back({(void**)&ev->ah_scale, (size_t)D.n_sub * 8, false});
     v.push_back({(void**)&ev->bh_scale, (size_t)D.ne * 8, false});
+    v.push_back({(void**)&ev->b_nrm, (size_t)D.ne_p * D.G * sizeof(float2), false});
+    v.push_back({(void**)&ev->ah_nrm, (size_t)D.n_sub * hh_outputs(D.G) * sizeof(float2), false});
+    v.push_back({(void**)&ev->bh_nrm, (size_t)D.ne_p * hh_outputs(D.G) * sizeof(float2), false});
   }
   v.push_back({(void**)&ev->Q, (size_t)D.ne * D.nk * D.NP * 16, false});
   v.push_back({(void**)&ev->R2, (size_t)D.ne * D.nk * D.nc * 8, false});
@@ -947,6 +999,10 @@ int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc*
     case kFP16X2: launch_hh<kFP16X2>(ev, st.w); break;
     default: launch_hh<kBF16X2>(ev, st.w); break;
   }
+  launch_norms(bk->prec, ev->B[0], ev->B[1], ev->n_ext_p, bk->K2, group_ranges(mt), ev->b_nrm, s);
+  launch_norms(bk->prec, ev->Ah[0], ev->Ah[1], ev->n_sub, ev->KH, output_ranges(mt.G), ev->ah_nrm, s);
+  launch_norms(bk->prec, ev->Bh[0], ev->Bh[1], ev->n_ext_p, ev->KH, output_ranges(mt.G), ev->bh_nrm,
+               s);
   hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(256), 0, s, nk * nb, (const double2*)st.d, st.w,
                      ev->final_out + kNPart);
   e = hipGetLastError();
@@ -1545,6 +1601,30 @@ int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const doub
   (void)hipFree(buf);
   ctx->bytes -= tb;
   if (e) return fail(DOTPE_E_DEVICE, "debug_distmarg: %s", hipGetErrorString(e));
+  return DOTPE_OK;
+}
+
+int dotpe_debug_bound(dotpe_ctx* ctx, dotpe_event* ev, float* out) {
+  if (!ctx || !ev || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  const int prec = ev->bank->prec;
+  if (prec == kFP64) return fail(DOTPE_E_INVALID_ARG, "the bound pass runs on split precisions only");
+  HIP_OK(hipSetDevice(ctx->device));
+  FusedArgs a = make_args(ctx, ev);
+  const size_t n = 2 * (size_t)ev->n_sub * ev->n_ext * sizeof(float);
+  float* buf = nullptr;
+  std::vector<void*> owned;
+  uint64_t acct = 0;
+  int rc = dev_alloc(ctx, (void**)&buf, n, &owned, &acct);
+  if (rc) return rc;
+  a.bound_out = buf;
+  const int64_t n_big = ((a.n_tiles_m + 1) / 2) * ((a.n_tiles_n + 1) / 2);
+  rc = launch_fused<kBound>(prec, a, round_up(n_big, 8), ev->stream);
+  hipError_t e = rc ? hipSuccess : hipMemcpyAsync(out, buf, n, hipMemcpyDeviceToHost, ev->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ev->stream);
+  (void)hipFree(buf);
+  ctx->bytes -= acct;
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(DOTPE_E_DEVICE, "bound hook: %s", hipGetErrorString(e));
   return DOTPE_OK;
 }
 

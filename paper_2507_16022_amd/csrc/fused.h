@@ -69,6 +69,22 @@ struct FusedArgs {
   // of such tiles, (tile id, count) pairs, its length in state[5]
   uint16_t* surv;
   int* surv_list;
+  // bound pass margin: per row of each split operand the 2-norms of its hi
+  // part and of what a product of hi parts leaves out, per m group (bank
+  // rows [n_wf][G], extrinsic rows [n_ext_p][G]) and per output ((h|h) row
+  // and column operands, [n_sub][NRT] and [n_ext_p][NRT]); the accumulation
+  // factors sqrt2 K_g 2^-23 (K_g: positions of group g) and 32 2^-23
+  const float2* a_nrm;
+  const float2* b_nrm;
+  const float2* ah_nrm;
+  const float2* bh_nrm;
+  float gam_dh[kMaxG];
+  float gam_hh;
+  // test hook: when set, the bound pass writes every pair's bounds on
+  // lnL^ML here instead of cutting: [0][n_sub][n_ext] from the margin of
+  // whole rows, [1][n_sub][n_ext] from the margin per group and output
+  // (+inf where the (h|h) lower bound is not positive)
+  float* bound_out;
   // coefficient route: work items work0 .. work0 + coef_tiles - 1 (tiles: all
   // of them when the cut is off, else the rerun list), the raw accumulators
   // of each stored at coef + (item - work0) * NCO * TM * TN, component-major

@@ -266,6 +266,52 @@ __global__ void k_convert_B(int64_t n_ext, int64_t n_ext_p, int n_c, int n_bp,
   }
 }
 
+// Chunk ranges [c0[r], c0[r + 1]), r < n, of an operand row (chunks of 32
+// positions): the m groups of a (d|h) operand, the outputs of a (h|h) one.
+struct NormRanges {
+  int n;
+  int c0[kMaxNR + 2];
+};
+
+// Per row of a split operand (op_index layout, K positions per row) and
+// per chunk range: the 2-norm of its hi parts and the 2-norm of what a
+// product of the hi parts alone leaves out -- the lo parts, plus any hi part
+// below the format's normal range in case the matrix cores flush it -- each
+// rounded up to float: out[row * n + r] = (hi, left out).  The bound pass
+// builds its margin from them.  A thread per row: the lanes of a wave read
+// 16 contiguous bytes each, 512 contiguous bytes per 32-row block.
+template <int PREC>
+__global__ void k_operand_norms(const void* __restrict__ P0, const void* __restrict__ P1,
+                                int64_t n_rows, int64_t K, NormRanges rg, float2* __restrict__ out) {
+  typedef typename std::conditional<PREC == kFP16X2, _Float16, __bf16>::type H;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n_rows) return;
+  const int64_t base = (row >> 5) * (K >> 5) * 1024 + (row & 31) * 8;
+  const double tiny = PREC == kFP16X2 ? 0x1p-14 : 0x1p-126;
+  for (int r = 0; r < rg.n; ++r) {
+    double sh = 0.0, sl = 0.0;
+    for (int64_t c = rg.c0[r]; c < rg.c0[r + 1]; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {     // (slice, piece) of the chunk
+        const int64_t o = base + c * 1024 + q * 256;
+        const uint4 vh = *(const uint4*)((const H*)P0 + o);
+        const uint4 vl = *(const uint4*)((const H*)P1 + o);
+        H xh[8], xl[8];
+        __builtin_memcpy(xh, &vh, 16);
+        __builtin_memcpy(xl, &vl, 16);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const double h = (double)(float)xh[j], l = (double)(float)xl[j];
+          const double t = fabs(h) < tiny ? l + h : l;
+          sh += h * h;
+          sl += t * t;
+        }
+      }
+    out[row * rg.n + r] = make_float2((float)(sqrt(sh) * (1.0 + 0x1p-20)),
+                                      (float)(sqrt(sl) * (1.0 + 0x1p-20)));
+  }
+}
+
 // (d|d)
 __global__ void k_data_norm(int n, const double2* __restrict__ d, const double* __restrict__ w,
                             double* __restrict__ out) {

@@ -151,6 +151,7 @@ TEST_SYMBOLS = {
                                              ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
     "dotpe_debug_response": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]),
+    "dotpe_debug_bound": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -468,6 +469,13 @@ class Event:
         _check(load_library().dotpe_debug_response(self.ctx.handle, self._h, R.ctypes.data,
                                                     t.ctypes.data))
         return R[..., 0] + 1j * R[..., 1], t
+
+    def bound(self):
+        """The bound pass's per-pair bounds on max_o lnL^ML, [2, n_sub, n_ext] float32:
+        [0] with the margin of whole rows, [1] with the margin per group and output."""
+        out = np.empty((2, self.n_sub, self.n_ext), dtype=np.float32)
+        _check(load_library().dotpe_debug_bound(self.ctx.handle, self._h, out.ctypes.data))
+        return out
 
 
 class Server:
