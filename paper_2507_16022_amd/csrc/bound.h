@@ -84,6 +84,7 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   constexpr int ES = 2;                         // bytes per operand element
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;    // (h|h) outputs: S0, Re/Im S_1..3
   constexpr int NS = BT::NS, LPC = BT::LPC;
+  static_assert(NS >= 5, "two chunks issued per barrier, two more in flight");
   extern __shared__ __align__(16) unsigned char smem[];
   // with the cut off the coefficient route takes every tile
   if (!a.bound_out && !cut_on(a)) return;
@@ -269,10 +270,11 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   };
   auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
 
-  // Step j (fragment parity P = j mod 2): wait until chunk j + 1 has landed
-  // (every wave's loads) and every wave is done with chunk j - 1, issue
-  // chunk j + NS - 1 into the stage chunk j - 1 used, then the products of
-  // chunk j (NH per half; mf(fa, fb, bm, bn, k) issues product k of block
+  // Step j (fragment parity P = j mod 2): on even steps, wait until chunks
+  // j + 1 and j + 2 have landed (every wave's loads) and every wave is done
+  // with chunks j - 2 and j - 1, and issue chunks j + NS - 2, j + NS - 1 into
+  // the stages those used (a barrier every second chunk); then the products
+  // of chunk j (NH per half; mf(fa, fb, bm, bn, k) issues product k of block
   // (bm, bn)) with the fragment reads between them.  After the last chunk
   // the reads fetch a stale stage, unused, so no branch sits between the
   // products.
@@ -283,11 +285,12 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     FA& anxt = fa(std::integral_constant<int, P + 1>{});
     FB& bcur = fb0(std::integral_constant<int, P>{});
     FB& bnxt = fb0(std::integral_constant<int, P + 1>{});
-    // chunks j + 2 .. min(j + NS - 2, nk - 1) may stay in flight
-    barrier_in_flight<NS - 2, LPC>(max(0, min(NS - 3, nk - 2 - j)));
-    if (j + NS - 1 < nk) {
+    if constexpr (P == 0) {
+      // chunks j + 3 .. min(j + NS - 3, nk - 1) may stay in flight
+      barrier_in_flight<NS - 3, LPC>(max(0, min(NS - 5, nk - 3 - j)));
       fence();
-      issue(j + NS - 1);
+      if (j + NS - 2 < nk) issue(j + NS - 2);
+      if (j + NS - 1 < nk) issue(j + NS - 1);
       fence();
     }
     // half 0: blocks (0, 0), (1, 0), a read after each of its products
@@ -313,12 +316,12 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
     });
   };
 
-  // prologue: chunks 0 .. NS - 2 in flight; once chunk 0 has landed, its A
+  // prologue: chunks 0 .. NS - 3 in flight; once chunk 0 has landed, its A
   // and bn = 0 fragments are read
 #pragma unroll
-  for (int c = 0; c < NS - 1; ++c)
+  for (int c = 0; c < NS - 2; ++c)
     if (c < nk) issue(c);
-  barrier_in_flight<NS - 2, LPC>(min(NS - 2, nk - 1));   // (also makes rowq .. coln visible)
+  barrier_in_flight<NS - 3, LPC>(min(NS - 3, nk - 1));   // (also makes rowq .. colt visible)
   static_for<4>([&](auto ki) { read_a(fa0, 0, decltype(ki)::value); });
   static_for<2>([&](auto ki) { read_b(fb0_0, 0, 0, decltype(ki)::value); });
 
