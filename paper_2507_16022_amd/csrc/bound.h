@@ -653,6 +653,7 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
     ev.init();
     double tile_max = -INFINITY;
     double my_lnp = -INFINITY;     // lane s: ln p of survivor s (-inf if not evaluated)
+    int my_ob = 0;                 //   and its best phase
     for (int sidx = 0; sidx < n_surv; ++sidx) {
       const unsigned rc = a.surv[tile_id * kSurvCap + sidx];
       const int64_t ie = tm * 64 + (rc >> 8), e = tn * 64 + (rc & 255);
@@ -736,18 +737,37 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
       ev.ml_max = fmax(ev.ml_max, mlmax);
       if (lse.m == -INFINITY) continue;
       const double lnp = lnw + lse.m + log(lse.s) - a.ln_nphi;
-      if (lane == sidx) my_lnp = lnp;
+      if (lane == sidx) {
+        my_lnp = lnp;
+        my_ob = ob;
+      }
       if (lane != 0) continue;
       ev.p.add(lnp, lse.sq_ratio());
       tile_max = fmax(tile_max, lnp);
-      if (lnp >= fmax(thr_topk_glob, tile_max - a.topk_window)) {
-        const unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
-        if ((int64_t)slot < a.cand_cap) {
-          double* cd = a.cand + 4 * slot;
-          cd[0] = lnp;
-          cd[1] = (double)i;
-          cd[2] = (double)e;
-          cd[3] = (double)ob;
+    }
+    // top-k candidates among the survivors (within the window of the tile's
+    // and the running global maximum), appended with one atomic per tile in
+    // survivor order: lane s holds survivor s
+    {
+      const double thr_c = fmax(thr_topk_glob, read_lane(tile_max, 0) - a.topk_window);
+      const bool cand = lane < n_surv && my_lnp > -INFINITY && my_lnp >= thr_c;
+      const unsigned long long bal = __ballot(cand);
+      if (bal) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long*)&a.state[2], (unsigned long long)__popcll(bal));
+        base = (unsigned long long)__shfl((long long)base, 0, 64);
+        if (cand) {
+          const unsigned long long slot =
+              base + __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+          if ((int64_t)slot < a.cand_cap) {
+            const unsigned rc = a.surv[tile_id * kSurvCap + lane];
+            const int64_t ie = tm * 64 + (rc >> 8), e = tn * 64 + (rc & 255);
+            double* cd = a.cand + 4 * slot;
+            cd[0] = my_lnp;
+            cd[1] = (double)(a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie);
+            cd[2] = (double)e;
+            cd[3] = (double)my_ob;
+          }
         }
       }
     }
@@ -795,9 +815,11 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
       out[0] = ev.p.m; out[1] = ev.p.s; out[2] = ev.p.s2; out[11] = ev.p.s3;
       out[3] = d.m; out[4] = d.s;
       out[5] = ev.ml_max; out[6] = (double)n_marg_all; out[9] = tile_max;
-      if (ev.ml_max > 0.0)
+      // running maxima: most tiles cannot raise them, so they read before
+      // they update (a stale read costs only an unneeded atomic)
+      if (ev.ml_max > 0.0 && __double_as_longlong(ev.ml_max) > (long long)a.state[0])
         atomicMax((unsigned long long*)&a.state[0], (unsigned long long)__double_as_longlong(ev.ml_max));
-      if (tile_max > -INFINITY)
+      if (tile_max > -INFINITY && order_bits(tile_max) > a.state[1])
         atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(tile_max));
     }
   }
