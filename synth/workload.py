@@ -383,3 +383,95 @@ def config_production(seed=1, snr=20.0, n_int=65536, n_ext=4096, **kw):
 def config_large(seed=3, snr=20.0, n_int=1 << 20, n_ext=16384, **kw):
     """Large-bank streaming shape: 2^20 x 16384, 3 det, 5 modes, 256 bins."""
     return config_production(seed=seed, snr=snr, n_int=n_int, n_ext=n_ext, **kw)
+
+
+# --------------------------------------------------------------------------
+# the paper's own layout, (m, p) channels with the inclination in the bank
+# (Sec. IV A), and full-resolution events for relative binning (App. A)
+# --------------------------------------------------------------------------
+def mp_channels(modes):
+    """The (m, p) channels of the distinct m of `modes`: m ascending, + (0) then x (1)."""
+    ms = sorted({m for _, m in modes})
+    return tuple((m, p) for m in ms for p in (0, 1))
+
+
+def waveform_mp(f, mc, q, chi, cos_iota, modes):
+    """h_{mp}(f) [N, 2 N_m, N_b] at d0, phi = 0, psi = 0 for rows with
+    inclination cos_iota [N]: the + and x polarisations of each azimuthal
+    harmonic m, i.e. the (l, m) modes of waveform_modes summed over l with
+    the polarisation factors simulate_strain uses."""
+    hlm = waveform_modes(f, mc, q, chi, modes)
+    chans = mp_channels(modes)
+    ci = np.asarray(cos_iota, dtype=np.float64)
+    out = np.zeros((hlm.shape[0], len(chans), hlm.shape[2]), dtype=np.complex128)
+    for c, (l, m) in enumerate(modes):
+        yn = _swsh_m2(l, -m, ci)
+        yp = _swsh_m2(l, m, ci)
+        j = chans.index((m, 0))
+        out[:, j] += (0.5 * (yn + (-1) ** l * yp))[:, None] * hlm[:, c]
+        out[:, j + 1] += (0.5j * (yn - (-1) ** l * yp))[:, None] * hlm[:, c]
+    return out, chans
+
+
+@dataclass
+class RBEvent:
+    """A full-resolution event for relative binning, and a bank on its nodes."""
+    f_full: np.ndarray             # [F] Hz, uniform grid
+    d_full: np.ndarray             # [K, F] complex
+    w_full: np.ndarray             # [K, F] 4 df / S_k(f)
+    node_idx: np.ndarray           # [B] indices of the spline nodes in f_full
+    h0: np.ndarray                 # [C, F] reference channels (the bank's layout)
+    t0: np.ndarray                 # [K] reference arrival time per detector, s
+    layout: str                    # "lm": (l, m) channels; "mp": (m, p) channels
+    chans: tuple                   # (l, m) or (m, p) per channel
+    wl: Workload                   # bank on the nodes, detectors, extrinsic set
+
+
+def make_rb_event(seed, n_int, n_ext, n_bins, n_full, modes=MODES_HM, dets="HLV", n_phi=32,
+                  snr=20.0, layout="lm", mc0=4.0, q0=0.6, spread=0.01, f_lo=20.0, f_hi=200.0,
+                  t_spread=5e-4, noise_on=True):
+    """An injection at (mc0, q0, chi 0) observed on a uniform full-resolution
+    grid with noise; the reference waveform is the injection's own channels
+    with its detector arrival times; the bank (rows within `spread` of mc0
+    in chirp mass, q0 +- 0.05) is evaluated on n_bins log-spaced nodes of the
+    grid; the extrinsic samples put the source within t_spread of the
+    injection's arrival time (sky and inclination drawn as usual)."""
+    rng = np.random.default_rng(seed)
+    net = network(dets)
+    f_full = np.linspace(f_lo, f_hi, n_full)
+    w_full = psd_weights(f_full, net)
+    want = f_lo * (f_hi / f_lo) ** (np.arange(n_bins) / (n_bins - 1.0))
+    node_idx = np.unique(np.clip(np.round((want - f_lo) / (f_full[1] - f_full[0])), 0, n_full - 1)
+                         .astype(np.int64))
+    f_nodes = f_full[node_idx]
+    mc = mc0 * np.exp(rng.uniform(-spread, spread, n_int))
+    q = np.clip(q0 + rng.uniform(-0.05, 0.05, n_int), 0.1, 1.0)
+    chi = np.zeros(n_int)
+    ext1 = {k: v[0] for k, v in draw_extrinsic(rng, 1).items()}
+    phi = rng.uniform(0, 2 * np.pi)
+    h_inj = waveform_modes(f_full, np.array([mc0]), np.array([q0]), np.array([0.0]), modes)[0]
+    s0 = simulate_strain(h_inj, modes, f_full, net, ext1, phi, 1.0, 1.0)
+    dist = math.sqrt(optimal_snr2(s0, w_full)) / snr
+    d_full = s0 / dist
+    if noise_on:
+        d_full = d_full + noise(rng, w_full)
+    n = np.array([np.cos(ext1["lat"]) * np.cos(ext1["lon"]), np.cos(ext1["lat"]) * np.sin(ext1["lon"]),
+                  np.sin(ext1["lat"])])
+    t0 = ext1["t_geo"] - net.r @ n / C_SI
+    if layout == "lm":
+        h = waveform_modes(f_nodes, mc, q, chi, modes)
+        h0 = h_inj
+        chans = tuple(modes)
+    else:
+        h, chans = waveform_mp(f_nodes, mc, q, chi, rng.uniform(-0.9, 0.9, n_int), modes)
+        h0 = waveform_mp(f_full, np.array([mc0]), np.array([q0]), np.array([0.0]),
+                         np.array([ext1["cos_iota"]]), modes)[0][0]
+    ext = draw_extrinsic(rng, n_ext)
+    ext["lat"] = ext1["lat"] + rng.normal(0.0, 0.02, n_ext)
+    ext["lon"] = ext1["lon"] + rng.normal(0.0, 0.02, n_ext)
+    ext["t_geo"] = ext1["t_geo"] + rng.uniform(-t_spread, t_spread, n_ext)
+    wl = Workload(tuple(chans), f_nodes, h, np.zeros(n_int), net.r.copy(), net.D.copy(),
+                  d_full[:, node_idx], w_full[:, node_idx], ext, np.zeros(n_ext), n_phi,
+                  meta=dict(seed=seed, mc=mc, q=q, chi=chi, snr=snr, dets=dets, inj_ext=ext1,
+                            inj_phi=phi, inj_dist=dist, layout=layout))
+    return RBEvent(f_full, d_full, w_full, node_idx, h0, t0, layout, tuple(chans), wl)
