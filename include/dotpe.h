@@ -102,17 +102,31 @@ uint64_t dotpe_device_bytes(const dotpe_ctx* ctx);
 /* Intrinsic waveform bank (Sec. IV C): n_wf waveforms, each n_modes (l, m)
  * channel amplitudes on n_bins frequencies, at distance d0, reference phase
  * 0 and polarisation angle 0. */
+/* Channel layouts of a bank.  DOTPE_LAYOUT_LM: one channel per (l, m) mode
+ * of a non-precessing waveform; the inclination is an extrinsic parameter
+ * and each channel's response is sum_p F_kp K_cp(iota) (eq. response_plus,
+ * response_cross with the -2Y_lm factors).  DOTPE_LAYOUT_MP: the paper's own
+ * layout (Sec. IV A, eq. h_k): one channel per azimuthal harmonic m and
+ * polarisation p of h_mp(f; theta_int), the inclination inside theta_int
+ * (eq. thetaint), the response the real antenna pattern F_kp. */
+#define DOTPE_LAYOUT_LM 0
+#define DOTPE_LAYOUT_MP 1
+
 typedef struct dotpe_bank_desc {
   int64_t n_wf;
   int32_t n_modes;        /* 1..8 channels; m in 1..4; at most 4 distinct m */
   int32_t n_bins;         /* 1..4096 */
-  const int32_t* mode_l;  /* [n_modes] host */
+  const int32_t* mode_l;  /* [n_modes] host (layout LM; unused for MP) */
   const int32_t* mode_m;  /* [n_modes] host */
   const double* f_bins;   /* [n_bins] Hz, host */
   const double* h;        /* [n_wf][n_modes][n_bins][2], host or device (mem) */
   const double* ln_w;     /* [n_wf] ln w_i (eq. int_weights), host or device, NULL = 0 */
   int32_t precision;      /* DOTPE_PREC_* */
   int32_t mem;            /* DOTPE_MEM_* for h and ln_w */
+  int32_t layout;         /* DOTPE_LAYOUT_* (0 = LM) */
+  int32_t reserved;       /* 0 */
+  const int32_t* mode_p;  /* layout MP: [n_modes] host, polarisation of each channel, 0 (+) or
+                             1 (x); each (m, p) at most once */
 } dotpe_bank_desc;
 
 /* Copy and convert a bank into device memory (the bank-summary layout).
@@ -157,6 +171,17 @@ typedef struct dotpe_event_desc {
                                (<= 0: 1e-4).  dotpe_evidence repeats the pass with a
                                larger cut_delta (cutting less), finally with no cut,
                                until it does */
+  /* Relative binning (App. A): with w_dh set the inner products are
+   * (d|h) = Re sum_kcb W^dh_kcb conj(h_kc(f_b)) (eq. d_h) and (h|h) =
+   * sum_kcc'b W^hh_kcc'b h_kc(f_b) conj(h_kc'(f_b)) (eq. h_h), h_kc the
+   * detector waveform's channel c at the bank's f_bins, instead of the plain
+   * bin sums with w and d (which are then ignored; they may be NULL).
+   * dotpe_rb_weights builds the weights from full-resolution data. */
+  const double* w_dh;       /* [n_det][n_modes][n_bins][2] W^dh_kcb, bank channel order, host;
+                               NULL = plain bins (W^dh = w d, W^hh = w) */
+  const double* w_hh;       /* [n_det][n_modes][n_modes][n_bins][2] W^hh_kcc'b, host; required
+                               with w_dh; Hermitian in (c, c') (only c <= c' is read) */
+  double dd;                /* (d|d) with w_dh (the full-resolution value); ignored without */
 } dotpe_event_desc;
 
 /* Stage an event against a resident bank: copies inputs, builds the
@@ -329,10 +354,46 @@ typedef struct dotpe_preselect_result {
  * [sub_count] the absolute bank rows kept, ascending (the first n_selected
  * entries).  Synchronous; the pass's device buffers are allocated and freed
  * within the call, charged to the budget.  Errors: INVALID_ARG, NUMERIC
- * (non-finite input), UNIMPLEMENTED (FP64 bank), OOM / ADMISSION, DEVICE. */
+ * (non-finite input), UNIMPLEMENTED (FP64 bank, or a bank of the MP layout: the
+ * polarisations are formed from (l, m) channels), OOM / ADMISSION, DEVICE. */
 int dotpe_preselect(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_preselect_desc* desc,
                     double* lnl_inco, double* lnl_det, int64_t* selected,
                     dotpe_preselect_result* out);
+
+/* ---- Relative-binning weights (App. A, eqs. dh_weights, hh_weights) ----
+ *
+ * From data on a full-resolution frequency grid and a reference waveform,
+ * the weights that dotpe_event_desc.w_dh / w_hh take:
+ *   W^dh_kcb   = <d_k | h0_kc s_b> / conj(h0_kc(f_b)),
+ *   W^hh_kcc'b = <h0_kc | h0_kc' s_b> / (h0_kc(f_b) conj(h0_kc'(f_b))),
+ * with <a|b>_k = sum_f w_kf a(f) conj(b(f)) over the grid, s_b the
+ * piecewise-linear functions on the nodes f_b (s_b(f_b') = delta_bb', zero
+ * outside [f_0, f_{B-1}]), and h0_kc(f) = h0_c(f) exp(-2 pi i f t0_k): the
+ * reference's channels shifted to its arrival time at detector k, the one
+ * part of its extrinsic parameters that does not cancel.  The nodes are grid
+ * points and must be the bank's f_bins.  Also (d|d) = sum_kf w_kf |d_kf|^2. */
+typedef struct dotpe_rb_desc {
+  int32_t n_det;            /* 1..8 */
+  int32_t n_modes;          /* channels of the reference, in the bank's channel order */
+  int64_t n_full;           /* full-resolution grid points, >= 2 */
+  const double* f;          /* [n_full] Hz, ascending, host */
+  const double* d;          /* [n_det][n_full][2] data, host */
+  const double* w;          /* [n_det][n_full] 4 df / S_k(f), host */
+  const double* h0;         /* [n_modes][n_full][2] reference channels, host; non-zero at the
+                               nodes */
+  const double* t0;         /* [n_det] reference arrival times, s, host; NULL = 0 */
+  int32_t n_nodes;          /* 2..4096 */
+  int32_t reserved;         /* 0 */
+  const int64_t* node_idx;  /* [n_nodes] strictly ascending indices into f, host */
+} dotpe_rb_desc;
+
+/* Outputs, host arrays: w_dh [n_det][n_modes][n_nodes][2], w_hh
+ * [n_det][n_modes][n_modes][n_nodes][2], dd (each may be NULL).  Synchronous;
+ * device buffers are allocated and freed within the call.  Errors:
+ * INVALID_ARG, NUMERIC (non-finite input, reference zero at a node), OOM /
+ * ADMISSION, DEVICE. */
+int dotpe_rb_weights(dotpe_ctx* ctx, const dotpe_rb_desc* desc, double* w_dh, double* w_hh,
+                     double* dd);
 
 /* ---- Serving: continuous admission of events against a resident bank ----
  *

@@ -624,7 +624,7 @@ def triple_inner_products_rb(h_i, R, t, f, mode_m, phis, W_dh, W_hh):
     Phi = np.exp(-1j * np.outer(phis, mode_m))                                  # [O,C]
     hk = np.einsum("cb,ekc,oc->eokcb", h_i, R, Phi) * T[:, None, :, None, :]   # [E,O,K,C,B]
     dh = np.real(np.einsum("kcb,eokcb->eo", W_dh, np.conj(hk)))
-    hh = np.real(np.einsum("kcdb,eokcb,eokdb->eo", W_hh, hk, np.conj(hk)))
+    hh = np.real(np.einsum("kcdb,eokcb,eokdb->eo", W_hh, hk, np.conj(hk), optimize=True))
     return dh, hh
 
 
@@ -642,11 +642,15 @@ def eval_pairs_general(h, mode_m, R, t, f, n_phi, W_dh, W_hh, ln_w_int, ln_w_ext
     ml = np.empty((n_i, E))
     dhs = np.empty((n_i, E, n_phi))
     hhs = np.empty((n_i, E, n_phi))
+    K, C, B = R.shape[1], R.shape[2], len(f)
+    eb = max(1, (1 << 21) // (n_phi * K * C * B))      # extrinsic samples per block
     for i in range(n_i):
-        dh, hh = triple_inner_products_rb(h[i], R, t, f, mode_m, phis, W_dh, W_hh)
-        lnl[i] = _lse(ln_dist_marg(dh, hh, d_max, d0, n_nodes), axis=1) - math.log(n_phi)
-        ml[i] = np.max(lnl_ml(dh, hh), axis=1)
-        dhs[i], hhs[i] = dh, hh
+        for s in range(0, E, eb):
+            sl = slice(s, s + eb)
+            dh, hh = triple_inner_products_rb(h[i], R[sl], t[sl], f, mode_m, phis, W_dh, W_hh)
+            lnl[i, sl] = _lse(ln_dist_marg(dh, hh, d_max, d0, n_nodes), axis=1) - math.log(n_phi)
+            ml[i, sl] = np.max(lnl_ml(dh, hh), axis=1)
+            dhs[i, sl], hhs[i, sl] = dh, hh
     lnp = np.asarray(ln_w_int)[:, None] + np.asarray(ln_w_ext)[None, :] + lnl
     return dict(lnl=lnl, ml_max=ml, dh=dhs, hh=hhs, lnp=lnp)
 

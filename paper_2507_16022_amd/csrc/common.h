@@ -42,6 +42,7 @@ constexpr int kMaxM = 4;
 constexpr int kChunk = 16;      // bins per K chunk (32 real K)
 constexpr int kNPart = 12;      // doubles per tile partial
 constexpr int kSurvCap = 16;    // survivors of a 64 x 64 tile the bound pass lists one by one
+constexpr int kMaxNF = 16;      // (m, p) layout: (h|h) sums folded over m
 
 enum Prec { kFP64 = 0, kFP16X2 = 1, kBF16X2 = 2 };
 
@@ -58,6 +59,15 @@ struct ModeTables {
   float pf[kMaxNP];                // delta = 0: 1 (c = c') or 2 (c != c')
   float ps[kMaxNP];                // sign of the imaginary part (conjugate when delta < 0)
   int pdiag[kMaxC];                // pair index of (c, c)
+  // channel layout: 0 (l, m) modes; 1 (m, p): pol[c] is the channel's
+  // polarisation and its response the real antenna pattern F_{k,pol[c]}
+  int layout;
+  int pol[kMaxC];
+  // (m, p) layout: (h|h) sums folded over m.  Entry f sums the channel
+  // pairs fpair[f][0 .. fcnt[f]) -- conjugated where fconj -- which share
+  // (delta, p, p') and so the column factor F_kp F_kp'
+  int nf;
+  int fcnt[kMaxNF], fpair[kMaxNF][kMaxG], fconj[kMaxNF][kMaxG];
 };
 
 // distance-rule parameters, kept in device memory next to the table (passed

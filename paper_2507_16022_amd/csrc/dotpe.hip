@@ -236,12 +236,24 @@ void gauss_hermite(int n, double* x, double* w) {
 
 int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
   const int nc = d->n_modes;
+  const bool mp = d->layout == DOTPE_LAYOUT_MP;
   std::vector<int> ms;
   for (int c = 0; c < nc; ++c) {
-    int l = d->mode_l[c], m = d->mode_m[c];
-    if (m < 1 || m > kMaxM || l < 2 || l > 8 || m > l)
-      return fail(DOTPE_E_INVALID_ARG, "mode (%d,%d) unsupported (need 2<=l<=8, 1<=m<=min(l,4))",
-                  l, m);
+    int m = d->mode_m[c];
+    if (mp) {
+      const int p = d->mode_p[c];
+      if (m < 1 || m > kMaxM || (p != 0 && p != 1))
+        return fail(DOTPE_E_INVALID_ARG, "channel (m=%d, p=%d) unsupported (need 1<=m<=4, p 0 or 1)",
+                    m, p);
+      for (int c2 = 0; c2 < c; ++c2)
+        if (d->mode_m[c2] == m && d->mode_p[c2] == p)
+          return fail(DOTPE_E_INVALID_ARG, "channel (m=%d, p=%d) given twice", m, p);
+    } else {
+      int l = d->mode_l[c];
+      if (m < 1 || m > kMaxM || l < 2 || l > 8 || m > l)
+        return fail(DOTPE_E_INVALID_ARG, "mode (%d,%d) unsupported (need 2<=l<=8, 1<=m<=min(l,4))",
+                    l, m);
+    }
     if (std::find(ms.begin(), ms.end(), m) == ms.end()) ms.push_back(m);
   }
   std::sort(ms.begin(), ms.end());
@@ -249,18 +261,22 @@ int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
   std::memset(mt, 0, sizeof(*mt));
   mt->n_c = nc;
   mt->G = (int)ms.size();
+  mt->layout = mp ? 1 : 0;
   int c2 = 0;
   const int cpc = n_bp / kChunk;
   for (int g = 0; g < mt->G; ++g) {
     mt->gm[g] = ms[g];
     mt->gk0[g] = c2 * cpc;
-    for (int c = 0; c < nc; ++c)
-      if (d->mode_m[c] == ms[g]) {
-        mt->l[c2] = d->mode_l[c];
-        mt->m[c2] = d->mode_m[c];
-        mt->orig[c2] = c;
-        ++c2;
-      }
+    // (m, p) layout: + before x within a group
+    for (int pp = 0; pp < (mp ? 2 : 1); ++pp)
+      for (int c = 0; c < nc; ++c)
+        if (d->mode_m[c] == ms[g] && (!mp || d->mode_p[c] == pp)) {
+          mt->l[c2] = mp ? 0 : d->mode_l[c];
+          mt->m[c2] = d->mode_m[c];
+          mt->pol[c2] = mp ? pp : 0;
+          mt->orig[c2] = c;
+          ++c2;
+        }
   }
   mt->gk0[mt->G] = c2 * cpc;
   mt->ND = ms.back() - ms.front() + 1;
@@ -283,6 +299,37 @@ int build_modes(const dotpe_bank_desc* d, ModeTables* mt, int n_bp) {
   }
   for (int d = std::min(mt->ND, kMaxND); d <= kMaxND; ++d) mt->pstart[d] = p;
   mt->NP = p;
+  if (mp) {
+    // folded (h|h) sums: per delta and polarisation pair, the channel pairs
+    // (c, c') with m_c - m_c' = delta, pol p_c, p_c' -- conjugated where the
+    // stored pair runs the other way.  delta = 0: (+,+), (x,x), (+,x).
+    auto chan = [&](int m, int pol) {
+      for (int c = 0; c < nc; ++c)
+        if (mt->m[c] == m && mt->pol[c] == pol) return c;
+      return -1;
+    };
+    auto pair_of = [&](int a, int b) {
+      for (int q = 0; q < mt->NP; ++q)
+        if (mt->pc[q] == std::min(a, b) && mt->pc2[q] == std::max(a, b)) return q;
+      return -1;
+    };
+    for (int dd = 0; dd < std::min(mt->ND, kMaxND); ++dd) {
+      const int np_ = dd == 0 ? 3 : 4;
+      for (int q = 0; q < np_; ++q) {
+        const int pa = dd == 0 ? (q == 1 ? 1 : 0) : q >> 1, pb = dd == 0 ? (q == 0 ? 0 : 1) : q & 1;
+        const int f = mt->nf;
+        if (f >= kMaxNF) return fail(DOTPE_E_INVALID_ARG, "too many folded (h|h) sums");
+        for (int g = 0; g < mt->G; ++g) {
+          const int a = chan(mt->gm[g], pa), b = chan(mt->gm[g] - dd, pb);
+          if (a < 0 || b < 0) continue;
+          mt->fpair[f][mt->fcnt[f]] = pair_of(a, b);
+          mt->fconj[f][mt->fcnt[f]] = a > b ? 1 : 0;
+          ++mt->fcnt[f];
+        }
+        if (mt->fcnt[f] > 0) ++mt->nf;
+      }
+    }
+  }
   return DOTPE_OK;
 }
 
@@ -297,7 +344,22 @@ int build_hh_terms(const ModeTables& mt, int n_det, std::vector<int>* terms, int
   };
   for (int r = 0; r < NR; ++r) {
     std::vector<int> t;
-    for (int k = 0; k < n_det; ++k) {
+    for (int k = 0; k < n_det && mt.layout == 1; ++k) {
+      // (m, p) layout: one term per folded sum (its column factor F_kp F_kp'
+      // is real): S0 from the delta = 0 sums (x2 for (+, x)), Re / Im S_d
+      // from the real / imaginary parts of the delta = d sums
+      for (int f = 0; f < mt.nf; ++f) {
+        const int q0 = mt.fpair[f][0];
+        const int del = std::abs(mt.pdel[q0]);
+        if (r == 0) {
+          if (del == 0)
+            t.push_back(code(k, f, 0, 0, mt.pc[q0] == mt.pc2[q0] ? 1 : 3) | 0x10000);
+        } else if (del == (r + 1) / 2) {
+          t.push_back(code(k, f, (r % 2) == 0 ? 1 : 0, 0, 1) | 0x10000);
+        }
+      }
+    }
+    for (int k = 0; k < n_det && mt.layout == 0; ++k) {
       if (r == 0) {
         for (int p = mt.pstart[0]; p < mt.pstart[1]; ++p) {
           if (mt.pc[p] == mt.pc2[p]) {
@@ -346,7 +408,7 @@ void launch_convert_B(dotpe_event* ev, const double2* Btmp, int* err) {
 }
 
 template <int PREC>
-void launch_hh(dotpe_event* ev, const double* w) {
+void launch_hh(dotpe_event* ev, const double* w, const double2* whh) {
   const dotpe_bank* bk = ev->bank;
   // the row's amplitudes and the noise weights in LDS when they fit (the
   // kernel applies the same test)
@@ -355,8 +417,8 @@ void launch_hh(dotpe_event* ev, const double* w) {
   if (sh > 65536) sh = 0;
   hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(64), sh, ev->stream,
                      ev->n_sub, ev->sub_idx, ev->sub0, bk->A0, bk->A1, bk->row_scale, bk->n_bp,
-                     bk->n_b, ev->n_det, w, bk->mt, ev->hh_terms, ev->KH, ev->Ah[0], ev->Ah[1],
-                     ev->ah_scale);
+                     bk->n_b, ev->n_det, w, whh, bk->mt, ev->hh_terms, ev->KH, ev->Ah[0],
+                     ev->Ah[1], ev->ah_scale);
   hipLaunchKernelGGL(k_build_Bhh<PREC>, dim3((unsigned)ev->n_ext_p), dim3(64), 0, ev->stream,
                      ev->n_ext, ev->n_ext_p, ev->n_det, ev->Q, bk->mt, ev->hh_terms, ev->KH,
                      ev->Bh[0], ev->Bh[1], ev->bh_scale);
@@ -571,7 +633,10 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
   if (d->n_wf < 1 || d->n_modes < 1 || d->n_modes > kMaxC || d->n_bins < 1 || d->n_bins > 4096)
     return fail(DOTPE_E_INVALID_ARG, "bank shape n_wf=%lld n_modes=%d n_bins=%d out of range",
                 (long long)d->n_wf, d->n_modes, d->n_bins);
-  if (!d->mode_l || !d->mode_m || !d->f_bins || !d->h)
+  if (d->layout != DOTPE_LAYOUT_LM && d->layout != DOTPE_LAYOUT_MP)
+    return fail(DOTPE_E_INVALID_ARG, "bad layout %d", d->layout);
+  if ((d->layout == DOTPE_LAYOUT_LM && !d->mode_l) || (d->layout == DOTPE_LAYOUT_MP && !d->mode_p) ||
+      !d->mode_m || !d->f_bins || !d->h)
     return fail(DOTPE_E_INVALID_ARG, "bank arrays must not be NULL");
   if (d->precision < 0 || d->precision > 2) return fail(DOTPE_E_INVALID_ARG, "bad precision");
   if (d->mem != DOTPE_MEM_HOST && d->mem != DOTPE_MEM_DEVICE)
@@ -721,6 +786,7 @@ struct EvDims {
   int64_t coef_tiles = 0;          // tiles per chunk of the coefficient route
   uint64_t coef_tile_bytes = 0;    // their raw accumulators, bytes per tile
   bool ln_w_ext = false, sub_idx = false;
+  bool rb = false;                 // relative-binning weights given
 };
 
 // input staging buffers of set_event (used only while the event is staged)
@@ -728,6 +794,8 @@ struct EvStage {
   double *d = nullptr, *w = nullptr, *r = nullptr, *D = nullptr, *lat = nullptr, *lon = nullptr,
          *psi = nullptr, *ci = nullptr, *tg = nullptr;
   double2* Btmp = nullptr;
+  double2* wdh = nullptr;   // relative binning: [nk][nc][nb] (group order), [nk][NP][nb]
+  double2* whh = nullptr;
   int* err = nullptr;
 };
 
@@ -743,9 +811,12 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
   if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
   if (d->n_phi < 1 || d->n_phi > kMaxPhi) return fail(DOTPE_E_INVALID_ARG, "n_phi=%d", d->n_phi);
   if (d->n_ext < 1) return fail(DOTPE_E_INVALID_ARG, "n_ext=%lld", (long long)d->n_ext);
-  if (!d->d || !d->w || !d->det_r || !d->det_D || !d->lat || !d->lon || !d->psi || !d->cos_iota ||
-      !d->t_geo)
+  const bool rb = d->w_dh != nullptr;
+  if ((!rb && (!d->d || !d->w)) || !d->det_r || !d->det_D || !d->lat || !d->lon || !d->psi ||
+      !d->cos_iota || !d->t_geo)
     return fail(DOTPE_E_INVALID_ARG, "event arrays must not be NULL");
+  if (rb && !d->w_hh)
+    return fail(DOTPE_E_INVALID_ARG, "relative binning needs both w_dh and w_hh");
   if (!(d->d_max > 0.0) || !(d->d0 > 0.0) || !std::isfinite(d->d_max) || !std::isfinite(d->d0))
     return fail(DOTPE_E_INVALID_ARG, "distances must be positive and finite");
   if (d->flags & ~(DOTPE_FLAG_RERUN_ALL | DOTPE_FLAG_NO_BOUND_PASS))
@@ -757,14 +828,17 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
   }
   const int nb = bk->n_b, nk = d->n_det;
   const int64_t ne = d->n_ext;
-  if (!finite_all(d->d, (size_t)nk * nb * 2) || !finite_all(d->w, (size_t)nk * nb) ||
+  const size_t nc_ = (size_t)bk->n_c;
+  if ((!rb && (!finite_all(d->d, (size_t)nk * nb * 2) || !finite_all(d->w, (size_t)nk * nb))) ||
+      (rb && (!finite_all(d->w_dh, (size_t)nk * nc_ * nb * 2) ||
+              !finite_all(d->w_hh, (size_t)nk * nc_ * nc_ * nb * 2) || !std::isfinite(d->dd))) ||
       !finite_all(d->det_r, nk * 3) || !finite_all(d->det_D, nk * 9) || !finite_all(d->lat, ne) ||
       !finite_all(d->lon, ne) || !finite_all(d->psi, ne) || !finite_all(d->cos_iota, ne) ||
       !finite_all(d->t_geo, ne) || (d->ln_w_ext && !finite_all(d->ln_w_ext, ne)))
     return fail(DOTPE_E_NUMERIC, "non-finite event input");
   for (int64_t e = 0; e < ne; ++e)
     if (std::fabs(d->cos_iota[e]) > 1.0) return fail(DOTPE_E_INVALID_ARG, "|cos_iota| > 1");
-  for (size_t t = 0; t < (size_t)nk * nb; ++t)
+  for (size_t t = 0; t < (size_t)nk * nb && !rb; ++t)
     if (d->w[t] < 0.0) return fail(DOTPE_E_INVALID_ARG, "negative noise weight");
   int64_t n_sub = d->sub_count > 0 ? d->sub_count : bk->n_wf;
   if (d->sub_idx) {
@@ -810,6 +884,7 @@ int event_dims(const dotpe_bank* bk, const dotpe_event_desc* d, EvDims* D, std::
     D->coef_tiles = std::max<int64_t>(1, std::min(c, D->n_tiles));
   }
   D->ln_w_ext = d->ln_w_ext != nullptr;
+  D->rb = d->w_dh != nullptr;
   D->sub_idx = d->sub_idx != nullptr;
   return DOTPE_OK;
 }
@@ -874,6 +949,10 @@ std::vector<EvBuf> event_buffers(const EvDims& D, dotpe_event* ev, EvStage* st) 
   v.push_back({(void**)&st->ci, (size_t)D.ne * 8, true});
   v.push_back({(void**)&st->tg, (size_t)D.ne * 8, true});
   v.push_back({(void**)&st->Btmp, (size_t)D.ne * D.nc * D.n_bp * 16, true});
+  if (D.rb) {
+    v.push_back({(void**)&st->wdh, (size_t)D.nk * D.nc * D.nb * 16, true});
+    v.push_back({(void**)&st->whh, (size_t)D.nk * D.NP * D.nb * 16, true});
+  }
   v.push_back({(void**)&st->err, 64, true});
   return v;
 }
@@ -958,8 +1037,34 @@ int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc*
   auto H2D = [&](void* dst, const void* src, size_t n) {
     if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
   };
-  H2D(st.d, d->d, (size_t)nk * nb * 16);
-  H2D(st.w, d->w, (size_t)nk * nb * 8);
+  if (D.rb) {
+    // relative-binning weights: W^dh to group order, W^hh to the stored
+    // channel pairs (c <= c' in group order), read from c <= c' in the
+    // caller's order and conjugated where the two orders differ
+    std::vector<double2> wdh((size_t)nk * nc * nb), whh((size_t)nk * D.NP * nb);
+    const double2* Wd = (const double2*)d->w_dh;
+    const double2* Wh = (const double2*)d->w_hh;
+    for (int k = 0; k < nk; ++k) {
+      for (int c = 0; c < nc; ++c)
+        for (int b = 0; b < nb; ++b)
+          wdh[((size_t)k * nc + c) * nb + b] = Wd[((size_t)k * nc + mt.orig[c]) * nb + b];
+      for (int p = 0; p < D.NP; ++p) {
+        const int a = mt.orig[mt.pc[p]], a2 = mt.orig[mt.pc2[p]];
+        const int lo = std::min(a, a2), hi = std::max(a, a2);
+        for (int b = 0; b < nb; ++b) {
+          double2 v = Wh[(((size_t)k * nc + lo) * nc + hi) * nb + b];
+          if (a > a2) v.y = -v.y;
+          whh[((size_t)k * D.NP + p) * nb + b] = v;
+        }
+      }
+    }
+    H2D(st.wdh, wdh.data(), wdh.size() * 16);
+    H2D(st.whh, whh.data(), whh.size() * 16);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host vectors end with this scope
+  } else {
+    H2D(st.d, d->d, (size_t)nk * nb * 16);
+    H2D(st.w, d->w, (size_t)nk * nb * 8);
+  }
   H2D(st.r, d->det_r, (size_t)nk * 24);
   H2D(st.D, d->det_D, (size_t)nk * 72);
   H2D(st.lat, d->lat, ne * 8);
@@ -988,24 +1093,32 @@ int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc*
                      ev->R2);
   int64_t nbt = ne * nc * bk->n_bp;
   hipLaunchKernelGGL(k_build_B, dim3((unsigned)((nbt + 255) / 256)), dim3(256), 0, s, ne, nk, nc,
-                     nb, bk->n_bp, bk->f, (const double2*)st.d, st.w, ev->R, ev->T, st.Btmp);
+                     nb, bk->n_bp, bk->f, (const double2*)st.d, st.w, (const double2*)st.wdh, ev->R,
+                     ev->T, st.Btmp);
   switch (bk->prec) {
     case kFP64: launch_convert_B<kFP64>(ev, st.Btmp, st.err); break;
     case kFP16X2: launch_convert_B<kFP16X2>(ev, st.Btmp, st.err); break;
     default: launch_convert_B<kBF16X2>(ev, st.Btmp, st.err); break;
   }
   switch (bk->prec) {
-    case kFP64: launch_hh<kFP64>(ev, st.w); break;
-    case kFP16X2: launch_hh<kFP16X2>(ev, st.w); break;
-    default: launch_hh<kBF16X2>(ev, st.w); break;
+    case kFP64: launch_hh<kFP64>(ev, st.w, st.whh); break;
+    case kFP16X2: launch_hh<kFP16X2>(ev, st.w, st.whh); break;
+    default: launch_hh<kBF16X2>(ev, st.w, st.whh); break;
   }
   launch_norms(bk->prec, ev->B[0], ev->B[1], ev->n_ext_p, bk->K2, group_ranges(mt), ev->b_nrm, s);
   launch_norms(bk->prec, ev->Ah[0], ev->Ah[1], ev->n_sub, ev->KH, output_ranges(mt.G), ev->ah_nrm, s);
   launch_norms(bk->prec, ev->Bh[0], ev->Bh[1], ev->n_ext_p, ev->KH, output_ranges(mt.G), ev->bh_nrm,
                s);
-  hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(256), 0, s, nk * nb, (const double2*)st.d, st.w,
-                     ev->final_out + kNPart);
+  hipError_t e_dd = hipSuccess;
+  if (D.rb) {
+    // (d|d) as given (full resolution)
+    e_dd = hipMemcpyAsync(ev->final_out + kNPart, &d->dd, 8, hipMemcpyHostToDevice, s);
+  } else {
+    hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(256), 0, s, nk * nb, (const double2*)st.d, st.w,
+                       ev->final_out + kNPart);
+  }
   e = hipGetLastError();
+  if (e == hipSuccess) e = e_dd;
   int herr = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&herr, st.err, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
@@ -1363,6 +1476,8 @@ int dotpe_preselect(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_preselect_
   if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
   if (bk->prec == kFP64)
     return fail(DOTPE_E_UNIMPLEMENTED, "pre-selection runs on split-precision banks only");
+  if (bk->mt.layout != 0)
+    return fail(DOTPE_E_UNIMPLEMENTED, "pre-selection forms polarisations from (l, m) channels");
   if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
   if (d->n_t < 32 || d->n_t > kPreMaxT || d->n_t % 32)
     return fail(DOTPE_E_INVALID_ARG, "n_t=%d (32, 64, 96 or 128)", d->n_t);
@@ -1602,6 +1717,87 @@ int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const doub
   ctx->bytes -= tb;
   if (e) return fail(DOTPE_E_DEVICE, "debug_distmarg: %s", hipGetErrorString(e));
   return DOTPE_OK;
+}
+
+int dotpe_rb_weights(dotpe_ctx* ctx, const dotpe_rb_desc* d, double* w_dh, double* w_hh,
+                     double* dd) {
+  if (!ctx || !d) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
+  if (d->n_modes < 1 || d->n_modes > kMaxC) return fail(DOTPE_E_INVALID_ARG, "n_modes=%d", d->n_modes);
+  if (d->n_full < 2 || d->n_full > (int64_t(1) << 26) || d->n_nodes < 2 || d->n_nodes > 4096 ||
+      d->reserved)
+    return fail(DOTPE_E_INVALID_ARG, "n_full=%lld n_nodes=%d", (long long)d->n_full, d->n_nodes);
+  if (!d->f || !d->d || !d->w || !d->h0 || !d->node_idx)
+    return fail(DOTPE_E_INVALID_ARG, "relative-binning arrays must not be NULL");
+  const int nk = d->n_det, nc = d->n_modes, nn = d->n_nodes;
+  const int64_t nf = d->n_full;
+  for (int b = 0; b < nn; ++b)
+    if (d->node_idx[b] < 0 || d->node_idx[b] >= nf || (b > 0 && d->node_idx[b] <= d->node_idx[b - 1]))
+      return fail(DOTPE_E_INVALID_ARG, "node_idx must rise strictly within the grid");
+  for (int64_t q = 1; q < nf; ++q)
+    if (!(d->f[q] > d->f[q - 1])) return fail(DOTPE_E_INVALID_ARG, "f must rise strictly");
+  if (!finite_all(d->f, nf) || !finite_all(d->d, (size_t)nk * nf * 2) ||
+      !finite_all(d->w, (size_t)nk * nf) || !finite_all(d->h0, (size_t)nc * nf * 2) ||
+      (d->t0 && !finite_all(d->t0, nk)))
+    return fail(DOTPE_E_NUMERIC, "non-finite relative-binning input");
+  for (int c = 0; c < nc; ++c)
+    for (int b = 0; b < nn; ++b) {
+      const double* v = d->h0 + ((size_t)c * nf + d->node_idx[b]) * 2;
+      if (v[0] == 0.0 && v[1] == 0.0)
+        return fail(DOTPE_E_NUMERIC, "reference channel %d is zero at node %d", c, b);
+    }
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  std::vector<void*> owned;
+  uint64_t acct = 0;
+  double *f = nullptr, *w = nullptr, *t0 = nullptr;
+  double2 *dv = nullptr, *h0 = nullptr, *wdh = nullptr, *whh = nullptr;
+  int64_t* idx = nullptr;
+  double* ddv = nullptr;
+  const size_t n_dh = (size_t)nk * nc * nn, n_hh = (size_t)nk * nc * nc * nn;
+  auto release = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    for (void* p : owned) (void)hipFree(p);
+    ctx->bytes -= acct;
+    return code;
+  };
+  int rc;
+  if ((rc = dev_alloc(ctx, (void**)&f, nf * 8, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&w, (size_t)nk * nf * 8, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&t0, (size_t)nk * 8, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&dv, (size_t)nk * nf * 16, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&h0, (size_t)nc * nf * 16, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&idx, (size_t)nn * 8, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&wdh, n_dh * 16, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&whh, n_hh * 16, &owned, &acct)) ||
+      (rc = dev_alloc(ctx, (void**)&ddv, 8, &owned, &acct)))
+    return release(rc);
+  std::vector<double> t0h(nk, 0.0);
+  if (d->t0) t0h.assign(d->t0, d->t0 + nk);
+  hipError_t e = hipSuccess;
+  auto H2D = [&](void* dst, const void* src, size_t n) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+  };
+  H2D(f, d->f, nf * 8);
+  H2D(w, d->w, (size_t)nk * nf * 8);
+  H2D(t0, t0h.data(), (size_t)nk * 8);
+  H2D(dv, d->d, (size_t)nk * nf * 16);
+  H2D(h0, d->h0, (size_t)nc * nf * 16);
+  H2D(idx, d->node_idx, (size_t)nn * 8);
+  if (e == hipSuccess) {
+    const int64_t n = (int64_t)(n_dh + n_hh);
+    hipLaunchKernelGGL(k_rb_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nk, nc, nf,
+                       nn, f, dv, w, h0, t0, idx, wdh, whh);
+    hipLaunchKernelGGL(k_data_norm, dim3(1), dim3(256), 0, s, (int)(nk * nf), dv, w, ddv);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && w_dh) e = hipMemcpyAsync(w_dh, wdh, n_dh * 16, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && w_hh) e = hipMemcpyAsync(w_hh, whh, n_hh * 16, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && dd) e = hipMemcpyAsync(dd, ddv, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return release(fail(DOTPE_E_DEVICE, "relative-binning weights: %s",
+                                           hipGetErrorString(e)));
+  return release(DOTPE_OK);
 }
 
 int dotpe_debug_bound(dotpe_ctx* ctx, dotpe_event* ev, float* out) {

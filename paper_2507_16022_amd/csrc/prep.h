@@ -137,8 +137,16 @@ __global__ void k_ext_response(int64_t n_ext, int n_det, const double* __restric
     X[a] = cps * elon[a] + sps * elat[a];
     Y[a] = -sps * elon[a] + cps * elat[a];
   }
+  // per channel and polarisation the factor of F_kp in R_ekc: the -2Y_lm
+  // combinations (layout (l, m)), or 1 for the channel's own polarisation
+  // (layout (m, p), the inclination inside the bank)
   double2 K[kMaxC][2];
   for (int c = 0; c < mt.n_c; ++c) {
+    if (mt.layout == 1) {
+      K[c][0] = make_double2(mt.pol[c] == 0 ? 1.0 : 0.0, 0.0);
+      K[c][1] = make_double2(mt.pol[c] == 1 ? 1.0 : 0.0, 0.0);
+      continue;
+    }
     int l = mt.l[c], m = mt.m[c];
     double yn = swsh_m2(l, -m, cosi[e]), yp = swsh_m2(l, m, cosi[e]);
     double sg = (l & 1) ? -1.0 : 1.0;
@@ -168,10 +176,14 @@ __global__ void k_ext_response(int64_t n_ext, int n_det, const double* __restric
 }
 
 // B_cb(e) = sum_k w_kb d_kb conj(R_ekc) exp(+2 pi i f_b t_ek), bins padded
+// B_ecb = sum_k W_kcb conj(R_ekc) exp(2 pi i f_b t_ek) with W_kcb = w_kb d_kb
+// (plain bins) or the relative-binning weights wdh [n_det][n_c][n_b] (group
+// order) when given
 __global__ void k_build_B(int64_t n_ext, int n_det, int n_c, int n_b, int n_bp,
                           const double* __restrict__ f, const double2* __restrict__ d,
-                          const double* __restrict__ w, const double2* __restrict__ R,
-                          const double* __restrict__ T, double2* __restrict__ Btmp) {
+                          const double* __restrict__ w, const double2* __restrict__ wdh,
+                          const double2* __restrict__ R, const double* __restrict__ T,
+                          double2* __restrict__ Btmp) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = n_ext * n_c * n_bp;
   if (idx >= total) return;
@@ -186,9 +198,15 @@ __global__ void k_build_B(int64_t n_ext, int n_det, int n_c, int n_b, int n_bp,
       double sn, cs;
       sincos(2.0 * M_PI * fr, &sn, &cs);
       double2 r = cconj(R[(e * n_det + k) * n_c + c]);
-      double2 dk = d[k * n_b + b];
-      double wk = w[k * n_b + b];
-      double2 v = cmul(cmul(make_double2(wk * dk.x, wk * dk.y), r), make_double2(cs, sn));
+      double2 wd;
+      if (wdh) {
+        wd = wdh[((int64_t)k * n_c + c) * n_b + b];
+      } else {
+        const double2 dk = d[k * n_b + b];
+        const double wk = w[k * n_b + b];
+        wd = make_double2(wk * dk.x, wk * dk.y);
+      }
+      double2 v = cmul(cmul(wd, r), make_double2(cs, sn));
       acc.x += v.x;
       acc.y += v.y;
     }
@@ -312,6 +330,64 @@ __global__ void k_operand_norms(const void* __restrict__ P0, const void* __restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// relative-binning weights (App. A, eqs. dh_weights, hh_weights): a thread
+// per (k, c, b) of W^dh and per (k, c, c', b) of W^hh, each a sum over the
+// full-resolution points of the hat function s_b's support (from the node
+// before to the node after).  Reference of detector k: h0_c(f) exp(-2 pi i
+// f t0_k), so W^dh carries exp(2 pi i (f - f_b) t0_k), reduced in cycles,
+// and W^hh none.
+// ---------------------------------------------------------------------------
+__global__ void k_rb_weights(int n_det, int n_c, int64_t n_full, int n_nodes,
+                             const double* __restrict__ f, const double2* __restrict__ d,
+                             const double* __restrict__ w, const double2* __restrict__ h0,
+                             const double* __restrict__ t0, const int64_t* __restrict__ node_idx,
+                             double2* __restrict__ wdh, double2* __restrict__ whh) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_dh = (int64_t)n_det * n_c * n_nodes;
+  const int64_t n_hh = (int64_t)n_det * n_c * n_c * n_nodes;
+  if (idx >= n_dh + n_hh) return;
+  const bool is_dh = idx < n_dh;
+  const int64_t j = is_dh ? idx : idx - n_dh;
+  const int b = (int)(j % n_nodes);
+  int c, c2 = 0, k;
+  if (is_dh) {
+    c = (int)((j / n_nodes) % n_c);
+    k = (int)(j / ((int64_t)n_nodes * n_c));
+  } else {
+    c2 = (int)((j / n_nodes) % n_c);
+    c = (int)((j / ((int64_t)n_nodes * n_c)) % n_c);
+    k = (int)(j / ((int64_t)n_nodes * n_c * n_c));
+  }
+  const int64_t qb = node_idx[b];
+  const int64_t lo = b > 0 ? node_idx[b - 1] : qb, hi = b + 1 < n_nodes ? node_idx[b + 1] : qb;
+  const double fb = f[qb], flo = f[lo], fhi = f[hi];
+  const double tk = t0 ? t0[k] : 0.0;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t q = lo; q <= hi; ++q) {
+    const double fq = f[q];
+    const double s = q < qb ? (fq - flo) / (fb - flo) : q > qb ? (fhi - fq) / (fhi - fb) : 1.0;
+    const double ws = w[(int64_t)k * n_full + q] * s;
+    double2 v;
+    if (is_dh) {
+      const double x = (fq - fb) * tk;
+      double sn, cs;
+      sincospi(2.0 * (x - rint(x)), &sn, &cs);
+      v = cmul(cmul(d[(int64_t)k * n_full + q], cconj(h0[(int64_t)c * n_full + q])), make_double2(cs, sn));
+    } else {
+      v = cmul(h0[(int64_t)c * n_full + q], cconj(h0[(int64_t)c2 * n_full + q]));
+    }
+    acc.x += ws * v.x;
+    acc.y += ws * v.y;
+  }
+  // divide by conj(h0_c(f_b)), or by h0_c(f_b) conj(h0_c'(f_b))
+  double2 den = cconj(h0[(int64_t)c * n_full + qb]);
+  if (!is_dh) den = cmul(h0[(int64_t)c * n_full + qb], cconj(h0[(int64_t)c2 * n_full + qb]));
+  const double dn = den.x * den.x + den.y * den.y;
+  const double2 r = cmul(acc, cconj(den));
+  (is_dh ? wdh : whh)[j] = make_double2(r.x / dn, r.y / dn);
+}
+
 // (d|d)
 __global__ void k_data_norm(int n, const double2* __restrict__ d, const double* __restrict__ w,
                             double* __restrict__ out) {
@@ -333,15 +409,32 @@ __global__ void k_data_norm(int n, const double2* __restrict__ d, const double* 
 // are each a dot product of at most 32 terms a * b with a taken from the
 // waveform's H_ikcc' and b from the sample's Q_ekcc'; they are computed by
 // the same matrix cores as (d|h), as extra K blocks of 32.  A term (output r,
-// slot j) is encoded in 16 bits: k (0-3), p (4-9), a from Im H (10), b from
-// Im Q (11), coefficient index (12-14: 0, 1, -1, 2, -2), valid (15).
+// slot j) is encoded in 17 bits: k (0-3), p (4-9), a from Im H (10), b from
+// Im Q (11), coefficient index (12-14: 0, 1, -1, 2, -2), valid (15), and
+// folded (16): p is then an entry of the (m, p) layout's folded sums, whose
+// row value sums its member pairs and whose column value is its first
+// member's (every member has the same F_kp F_kp').
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double term_value(int code, const double2* X, int NP, bool row_side) {
+__device__ __forceinline__ double term_value(int code, const double2* X, const ModeTables& mt,
+                                             bool row_side) {
   if (!(code & 0x8000)) return 0.0;
+  const int NP = mt.NP;
   int k = code & 15, p = (code >> 4) & 63;
   int part = row_side ? (code >> 10) & 1 : (code >> 11) & 1;
-  double2 v = X[k * NP + p];
+  double2 v;
+  if (code & 0x10000) {
+    v = make_double2(0.0, 0.0);
+    const int n = row_side ? mt.fcnt[p] : 1;
+    for (int j = 0; j < n; ++j) {
+      double2 u = X[k * NP + mt.fpair[p][j]];
+      if (mt.fconj[p][j]) u.y = -u.y;
+      v.x += u.x;
+      v.y += u.y;
+    }
+  } else {
+    v = X[k * NP + p];
+  }
   double x = part ? v.y : v.x;
   if (row_side) {
     int ci = (code >> 12) & 7;
@@ -353,7 +446,8 @@ __device__ __forceinline__ double term_value(int code, const double2* X, int NP,
 __device__ __forceinline__ double2 to_d2(double2 v) { return v; }
 __device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
 
-// per-waveform (h|h) sums H_ikcc' = sum_b w_kb h_icb conj(h_ic'b) for the
+// per-waveform (h|h) sums H_ikcc' = sum_b w_kb h_icb conj(h_ic'b) (relative
+// binning: sum_b W_kcc'b h_icb conj(h_ic'b), whh [n_det][NP][n_b]) for the
 // event's bank subset, from the same operand values the contraction uses,
 // written as the row-side (h|h) operand (n_sub rows of KH, op_index layout)
 // with a power-of-two
@@ -362,7 +456,8 @@ template <int PREC>
 __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_idx, int64_t sub0,
                                 const void* __restrict__ A0, const void* __restrict__ A1,
                                 const double* __restrict__ row_scale, int n_bp, int n_b,
-                                int n_det, const double* __restrict__ w, ModeTables mt,
+                                int n_det, const double* __restrict__ w,
+                                const double2* __restrict__ whh, ModeTables mt,
                                 const int* __restrict__ terms, int KH, void* __restrict__ H0,
                                 void* __restrict__ H1, double* __restrict__ hscale) {
   // the row [n_c][n_bp] then w [n_det][n_b], when they fit.  A split value
@@ -409,7 +504,8 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
 #pragma unroll
       for (int j = 0; j < 8; ++j) dst[2 * j] = (RV)v[j];
     }
-    for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[t] = w[t];
+    if (!whh)
+      for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[t] = w[t];
     __syncthreads();
   }
   double sc = row_scale ? row_scale[i] : 1.0;
@@ -418,7 +514,17 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
     int k = t / mt.NP, p = t % mt.NP;
     int c = mt.pc[p], c2 = mt.pc2[p];
     double2 acc = make_double2(0.0, 0.0);
-    if (staged) {
+    if (whh) {
+      // relative binning: a complex weight per channel pair and bin
+      const double2* Wp = whh + ((int64_t)k * mt.NP + p) * n_b;
+      for (int b = 0; b < n_b; ++b) {
+        const double2 a = staged ? to_d2(rowbuf[c * n_bp + b]) : bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
+        const double2 a2 = staged ? to_d2(rowbuf[c2 * n_bp + b]) : bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
+        const double2 u = cmul(Wp[b], cmul(cconj(a), a2));
+        acc.x += u.x;
+        acc.y += u.y;
+      }
+    } else if (staged) {
       // two partial sums, so that consecutive bins do not wait on each other
       double2 acc2 = make_double2(0.0, 0.0);
       int b = 0;
@@ -453,7 +559,7 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   __syncthreads();
   double mx = 0.0;
   for (int j = threadIdx.x; j < KH; j += blockDim.x) {
-    double v = term_value(terms[j], Hs, mt.NP, true);
+    double v = term_value(terms[j], Hs, mt, true);
     vals[j] = v;
     mx = fmax(mx, fabs(v));
   }
@@ -483,7 +589,7 @@ __global__ void k_build_Bhh(int64_t n_ext, int64_t n_ext_p, int n_det, const dou
   if (e >= n_ext_p) return;
   double mx = 0.0;
   for (int j = threadIdx.x; j < KH; j += blockDim.x) {
-    double v = e < n_ext ? term_value(terms[j], Q + e * n_det * mt.NP, mt.NP, false) : 0.0;
+    double v = e < n_ext ? term_value(terms[j], Q + e * n_det * mt.NP, mt, false) : 0.0;
     vals[j] = v;
     mx = fmax(mx, fabs(v));
   }

@@ -37,7 +37,12 @@ class BankDesc(ctypes.Structure):
     _fields_ = [("n_wf", ctypes.c_int64), ("n_modes", ctypes.c_int32), ("n_bins", ctypes.c_int32),
                 ("mode_l", ctypes.c_void_p), ("mode_m", ctypes.c_void_p),
                 ("f_bins", ctypes.c_void_p), ("h", ctypes.c_void_p), ("ln_w", ctypes.c_void_p),
-                ("precision", ctypes.c_int32), ("mem", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("mem", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mode_p", ctypes.c_void_p)]
+
+
+LAYOUT = {"lm": 0, "mp": 1}
 
 
 class EventDesc(ctypes.Structure):
@@ -53,7 +58,15 @@ class EventDesc(ctypes.Structure):
                 ("sub_idx", ctypes.c_void_p),
                 ("cut_delta", ctypes.c_double), ("top_k", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("topk_window", ctypes.c_double),
-                ("stream", ctypes.c_void_p), ("cut_target", ctypes.c_double)]
+                ("stream", ctypes.c_void_p), ("cut_target", ctypes.c_double),
+                ("w_dh", ctypes.c_void_p), ("w_hh", ctypes.c_void_p), ("dd", ctypes.c_double)]
+
+
+class RBDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("n_full", ctypes.c_int64),
+                ("f", ctypes.c_void_p), ("d", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("h0", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("n_nodes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("node_idx", ctypes.c_void_p)]
 
 
 class EvidenceResult(ctypes.Structure):
@@ -134,6 +147,8 @@ SYMBOLS = {
     "dotpe_preselect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(PreselectDesc),
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(PreselectResult)]),
+    "dotpe_rb_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RBDesc), ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "dotpe_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(ServerDesc),
                                             ctypes.POINTER(ctypes.c_void_p)]),
@@ -220,10 +235,32 @@ class Context:
         except Exception:
             pass
 
-    def load_bank(self, h, modes, f, ln_w=None, precision="fp16x2"):
+    def load_bank(self, h, modes, f, ln_w=None, precision="fp16x2", layout="lm"):
         """h: complex numpy [N, C, B] (host) or a float64 torch tensor
-        [N, C, B, 2] on the GPU (device pointer, no host copy)."""
-        return Bank(self, h, modes, f, ln_w, precision)
+        [N, C, B, 2] on the GPU (device pointer, no host copy).  modes: (l, m) per
+        channel (layout "lm") or (m, p) per channel (layout "mp", p 0 for +, 1 for x)."""
+        return Bank(self, h, modes, f, ln_w, precision, layout)
+
+    def rb_weights(self, f, d, w, h0, node_idx, t0=None):
+        """dotpe_rb_weights: relative-binning weights from full-resolution data f [F],
+        d [K, F] complex, w [K, F], reference channels h0 [C, F] complex, spline nodes
+        node_idx [B] and reference arrival times t0 [K].  Returns (w_dh [K, C, B],
+        w_hh [K, C, C, B], dd)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        d = np.ascontiguousarray(d, dtype=np.complex128)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        h0 = np.ascontiguousarray(h0, dtype=np.complex128)
+        idx = np.ascontiguousarray(node_idx, dtype=np.int64)
+        t0a = None if t0 is None else np.ascontiguousarray(t0, dtype=np.float64)
+        K, C, B = d.shape[0], h0.shape[0], len(idx)
+        desc = RBDesc(K, C, len(f), f.ctypes.data, d.ctypes.data, w.ctypes.data, h0.ctypes.data,
+                      None if t0a is None else t0a.ctypes.data, B, 0, idx.ctypes.data)
+        wdh = np.empty((K, C, B), dtype=np.complex128)
+        whh = np.empty((K, C, C, B), dtype=np.complex128)
+        dd = ctypes.c_double()
+        _check(load_library().dotpe_rb_weights(self._h, ctypes.byref(desc), wdh.ctypes.data,
+                                                whh.ctypes.data, ctypes.byref(dd)))
+        return wdh, whh, dd.value
 
     def set_event(self, bank, **kw):
         return Event(self, bank, **kw)
@@ -279,14 +316,20 @@ class Context:
 
 
 class Bank:
-    def __init__(self, ctx, h, modes, f, ln_w=None, precision="fp16x2"):
+    def __init__(self, ctx, h, modes, f, ln_w=None, precision="fp16x2", layout="lm"):
         lib = load_library()
         self.ctx = ctx
         self._keep = []
-        ml, pml = _host([l for l, _ in modes], np.int32)
-        mm, pmm = _host([m for _, m in modes], np.int32)
+        if layout == "mp":          # channels (m, p)
+            ml, pml = _host([0 for _ in modes], np.int32)
+            mm, pmm = _host([m for m, _ in modes], np.int32)
+            mp_, pmp = _host([p for _, p in modes], np.int32)
+        else:                       # channels (l, m)
+            ml, pml = _host([l for l, _ in modes], np.int32)
+            mm, pmm = _host([m for _, m in modes], np.int32)
+            mp_, pmp = None, None
         fb, pf = _host(f)
-        self._keep += [ml, mm, fb]
+        self._keep += [ml, mm, fb, mp_]
         if _is_torch(h):
             assert h.is_cuda and str(h.dtype) == "torch.float64" and h.is_contiguous()
             n_wf, n_c, n_b = h.shape[0], h.shape[1], h.shape[2]
@@ -308,7 +351,8 @@ class Bank:
                 self._keep.append(lw)
             else:
                 pw = None
-        desc = BankDesc(n_wf, n_c, n_b, pml, pmm, pf, ph, pw, PREC[precision], mem)
+        desc = BankDesc(n_wf, n_c, n_b, pml, pmm, pf, ph, pw, PREC[precision], mem, LAYOUT[layout], 0,
+                        pmp)
         out = ctypes.c_void_p()
         _check(lib.dotpe_load_bank(ctx.handle, ctypes.byref(desc), ctypes.byref(out)))
         self._h = out
@@ -316,6 +360,7 @@ class Bank:
         self.n_wf, self.n_modes, self.n_bins = n_wf, n_c, n_b
         self.precision = precision
         self.modes = tuple(modes)
+        self.layout = layout
 
     @property
     def handle(self):
@@ -339,8 +384,9 @@ FLAG_NO_BOUND_PASS = 2
 
 def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=1.0, n_norm=0.0,
                 sub_start=0, sub_count=0, sub_idx=None, cut_delta=0.0, top_k=0, topk_window=40.0,
-                stream=None, flags=0, cut_target=0.0):
-    """EventDesc over host copies of the inputs; returns (desc, arrays to keep alive)."""
+                stream=None, flags=0, cut_target=0.0, w_dh=None, w_hh=None, dd=0.0):
+    """EventDesc over host copies of the inputs; returns (desc, arrays to keep alive).
+    With w_dh [K, C, B] and w_hh [K, C, C, B] (relative binning) d and w may be None."""
     keep = []
 
     def hp(a, dt=np.float64):
@@ -348,8 +394,15 @@ def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=
         keep.append(arr)
         return arr, p
 
-    dc, pd = hp(np.asarray(d, dtype=np.complex128), np.complex128)
-    _, pw = hp(w)
+    if w_dh is not None:
+        _, pwdh = hp(np.asarray(w_dh, dtype=np.complex128), np.complex128)
+        _, pwhh = hp(np.asarray(w_hh, dtype=np.complex128), np.complex128)
+        n_det = np.asarray(w_dh).shape[0]
+    else:
+        pwdh = pwhh = None
+        n_det = np.asarray(d).shape[0]
+    pd = hp(np.asarray(d, dtype=np.complex128), np.complex128)[1] if d is not None else None
+    pw = hp(w)[1] if w is not None else None
     _, pr = hp(det_r)
     _, pD = hp(det_D)
     n_ext = len(ext["lat"])
@@ -365,10 +418,10 @@ def _event_desc(d, w, det_r, det_D, ext, n_phi, ln_w_ext=None, d_max=5000.0, d0=
         sub_count = len(si)
     if stream is not None and not isinstance(stream, int):
         stream = stream.cuda_stream
-    desc = EventDesc(dc.shape[0], int(n_phi), pd, pw, pr, pD, n_ext, plat, plon, ppsi, pci, ptg,
+    desc = EventDesc(n_det, int(n_phi), pd, pw, pr, pD, n_ext, plat, plon, ppsi, pci, ptg,
                      plw, float(d_max), float(d0), float(n_norm), int(sub_start),
                      int(sub_count), psub, float(cut_delta), int(top_k), int(flags),
-                     float(topk_window), stream, float(cut_target))
+                     float(topk_window), stream, float(cut_target), pwdh, pwhh, float(dd))
     return desc, keep
 
 

@@ -34,7 +34,7 @@ def test_version_and_error_string():
 
 def test_struct_layouts():
     # sizes must match the C structs (checked against hand-computed layouts)
-    assert ctypes.sizeof(dotpe.BankDesc) == 8 + 4 + 4 + 5 * 8 + 4 + 4
+    assert ctypes.sizeof(dotpe.BankDesc) == 8 + 4 + 4 + 5 * 8 + 4 + 4 + 4 + 4 + 8
     assert ctypes.sizeof(dotpe.Sample) == 32
     assert ctypes.sizeof(dotpe.EvidenceResult) == 7 * 8 + 3 * 8 + 4 * 4 + 2 * 8 + 8 + 2 * 4 + 8 + 2 * 4 + 3 * 8
 
@@ -49,6 +49,7 @@ STRUCTS = {
     "dotpe_preselect_desc": dotpe.PreselectDesc,
     "dotpe_posterior_sample": dotpe.PosteriorSample,
     "dotpe_preselect_result": dotpe.PreselectResult,
+    "dotpe_rb_desc": dotpe.RBDesc,
 }
 
 
