@@ -659,3 +659,83 @@ def evidence_general(res, n_norm, n_ext):
     """ln Z = LSE_ie ln p_ie - ln N_norm - ln N_ext (eq. Z_sum) from
     eval_pairs_general's output."""
     return float(_lse(res["lnp"].ravel())) - math.log(n_norm) - math.log(n_ext)
+
+
+# --------------------------------------------------------------------------
+# O14: extrinsic samples by importance sampling from arrival-time
+# probabilities (Sec. IV E; App. C)
+# --------------------------------------------------------------------------
+def fibonacci_sky(n):
+    """n sky points of equal area 4 pi / n (a Fibonacci lattice: z_s = 1 -
+    (2 s + 1)/n, longitude s times the golden angle): lat, lon [n]."""
+    s = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * s + 1.0) / n
+    ga = math.pi * (3.0 - math.sqrt(5.0))
+    lon = np.mod(s * ga, 2.0 * math.pi)
+    return np.arcsin(z), lon
+
+
+def arrival_time_series(h, modes, cos_iota, f, d, w, t0, dt, n_t, n_phi):
+    """rho^2_{ck}(t_j) = 2 max_o lnL^ML_{ckoj} (eq. single_det_ML maximised
+    over the phase: the distance-optimised SNR^2 of one detector with free
+    polarisation amplitudes) on detector k's grid t0[k] + j dt, for the
+    rows c of h: [C, K, n_t]."""
+    out = np.empty((len(h), len(d), n_t))
+    for c in range(len(h)):
+        for k in range(len(d)):
+            times = t0[k] + dt * np.arange(n_t)
+            out[c, k] = 2.0 * np.max(single_detector_ml(h[c], modes, cos_iota[c], f, d[k], w[k],
+                                                        times, n_phi), axis=0)
+    return out
+
+
+def proposal_table(rho2, t0, dt, det_r, sky_lat, sky_lon, tg_lo, tg_hi, n_tg, beta=0.5):
+    """The proposal over cells (sky point s, geocentre-time cell j) of one
+    intrinsic sample c: ln W_c(s, j) = sum_k ln p_ck(t_j - r_k . n_s / c)
+    with t_j = tg_lo + (j + 1/2)(tg_hi - tg_lo)/n_tg, and the per-detector
+    arrival-time probability p_ck(t) = exp(beta (rho^2_ck(t_i) - max_i
+    rho^2_ck)) taken at the grid point t_i nearest to t (zero off the grid's
+    cells).  Returns ln W [C, S, J] and ln Z_c = ln sum_sj W_c."""
+    C, K, n_t = rho2.shape
+    n = sky_direction(sky_lat, sky_lon)                                     # [S, 3]
+    tau = -(n @ np.asarray(det_r).T) / C_SI                                 # [S, K]
+    dtg = (tg_hi - tg_lo) / n_tg
+    tj = tg_lo + (np.arange(n_tg) + 0.5) * dtg                              # [J]
+    lnW = np.zeros((C, len(n), n_tg))
+    for k in range(K):
+        tk = tj[None, :] + tau[:, k:k + 1]                                  # [S, J]
+        i = np.rint((tk - t0[k]) / dt).astype(np.int64)
+        inside = (i >= 0) & (i < n_t)
+        lp = beta * (rho2[:, k, :] - np.max(rho2[:, k, :], axis=1, keepdims=True))   # [C, n_t]
+        term = np.where(inside[None], lp[:, np.clip(i, 0, n_t - 1)], -np.inf)
+        lnW = lnW + term
+    lnZ = np.array([_lse(lnW[c].ravel()) for c in range(C)])
+    return lnW, lnZ
+
+
+def extrinsic_proposal(lnW, lnZ, sky_lat, sky_lon, tg_lo, tg_hi, n_samples, seed):
+    """Draws from the mixture of the C proposals (stratified: draw q from
+    component q mod C): its cell by inverting the component's distribution
+    over the cells (s-major) at u = SplitMix64(seed, 4 q), t_geo uniform in
+    the cell's time at SplitMix64(seed, 4 q + 1), psi = pi u at 4 q + 2 and
+    cos iota = 2 u - 1 at 4 q + 3 (prior); the importance weight of eq.
+    (w_e): ln w = ln pi_cell - ln pi'_cell with the prior's cell probability
+    1 / (S J) and the mixture's (1/C) sum_c W_c / Z_c.  Returns a dict of
+    lat, lon, psi, cos_iota, t_geo, ln_w, cell [n_samples]."""
+    C, S, J = lnW.shape
+    P = np.exp(lnW - lnZ[:, None, None]).reshape(C, S * J)
+    mix = np.log(np.mean(P, axis=0))                                        # ln pi'_cell
+    dtg = (tg_hi - tg_lo) / J
+    out = {k: np.empty(n_samples) for k in ("lat", "lon", "psi", "cos_iota", "t_geo", "ln_w")}
+    out["cell"] = np.empty(n_samples, dtype=np.int64)
+    for q in range(n_samples):
+        c = q % C
+        cell = inverse_cdf_index(P[c], splitmix64_uniform(seed, 4 * q))
+        s, j = divmod(cell, J)
+        out["cell"][q] = cell
+        out["lat"][q], out["lon"][q] = sky_lat[s], sky_lon[s]
+        out["t_geo"][q] = tg_lo + (j + splitmix64_uniform(seed, 4 * q + 1)) * dtg
+        out["psi"][q] = math.pi * splitmix64_uniform(seed, 4 * q + 2)
+        out["cos_iota"][q] = 2.0 * splitmix64_uniform(seed, 4 * q + 3) - 1.0
+        out["ln_w"][q] = -math.log(S * J) - mix[cell]
+    return out
