@@ -395,6 +395,64 @@ typedef struct dotpe_rb_desc {
 int dotpe_rb_weights(dotpe_ctx* ctx, const dotpe_rb_desc* desc, double* w_dh, double* w_hh,
                      double* dd);
 
+/* ---- Extrinsic samples (Sec. IV E; App. C) ----
+ *
+ * Importance sampling of the extrinsic parameters from the data.  For each
+ * of the n_rows intrinsic samples c (bank rows, each with its inclination),
+ * each detector's arrival-time series rho^2_ck(t_j) = 2 max_o lnL^ML_ckoj
+ * on its grid t0[k] + j dt (eq. single_det_ML, maximised over the phase
+ * grid) gives the arrival-time probability p_ck(t) = exp(beta (rho^2_ck(t)
+ * - max_t rho^2_ck)), taken at the grid point nearest to t and zero off the
+ * grid.  The sky is n_sky points of equal area (a Fibonacci lattice: z_s =
+ * 1 - (2 s + 1)/n_sky, longitude s times the golden angle) and the
+ * geocentre time [tg_lo, tg_hi] n_tg equal cells; sample c's proposal over
+ * the cells is W_c(s, j) = prod_k p_ck(t_j - r_k . n_s / c) at the cell's
+ * centre time t_j, normalised.  Draw q comes from proposal q mod n_rows:
+ * its cell by inverting that proposal at the uniform number 4 q of a
+ * SplitMix64 generator seeded with `seed` (cells s-major), t_geo uniform in
+ * the cell's time (number 4 q + 1), psi = pi u (4 q + 2), cos_iota = 2 u - 1
+ * (4 q + 3); its importance weight (eq. w_e) is the prior's cell
+ * probability 1 / (n_sky n_tg) over the mixture's (1 / n_rows) sum_c
+ * W_c / Z_c.  Split-precision banks of the (l, m) layout (the series come
+ * from the pre-selection's products). */
+typedef struct dotpe_extrinsic_desc {
+  int32_t n_det;            /* 1..8 */
+  int32_t n_t;              /* detector time-grid points: 32, 64, 96 or 128 */
+  int32_t n_phi;            /* phase grid of the single-detector maximum, 1..128 */
+  int32_t n_rows;           /* intrinsic samples, 1..64 */
+  const double* d;          /* [n_det][n_bins][2] data at the bank's f_bins, host */
+  const double* w;          /* [n_det][n_bins] noise weights, host */
+  const double* det_r;      /* [n_det][3] detector positions, metres, host */
+  const double* t0;         /* [n_det] first grid time of each detector, s, host */
+  double dt;                /* grid step, s */
+  const int64_t* rows;      /* [n_rows] bank rows, host */
+  const double* cos_iota;   /* [n_rows] their inclinations, host */
+  double beta;              /* inverse temperature (<= 0: 0.5) */
+  int32_t n_sky;            /* sky lattice points, 1..65536 */
+  int32_t n_tg;             /* geocentre-time cells, 1..4096 */
+  double tg_lo, tg_hi;      /* the prior's geocentre-time window, s */
+  int64_t n_samples;        /* draws, >= 1 */
+  uint64_t seed;
+  void* stream;             /* hipStream_t; NULL = context stream */
+} dotpe_extrinsic_desc;
+
+typedef struct dotpe_extrinsic_result {
+  double n_eff_prior;       /* (sum w)^2 / sum w^2 over the draws */
+  double support;           /* prior mass of the cells the mixture reaches */
+  double t_ms;              /* device time (HIP events) */
+  int64_t n_samples;
+} dotpe_extrinsic_result;
+
+/* Outputs, host arrays of n_samples each (any may be NULL): lat, lon, psi,
+ * cos_iota, t_geo -- the extrinsic set dotpe_event_desc takes -- and ln_w,
+ * the log importance weights (its ln_w_ext).  n_rows * n_sky * n_tg is at
+ * most 2^26.  Synchronous; device buffers are allocated and freed within
+ * the call.  Errors: INVALID_ARG, NUMERIC, UNIMPLEMENTED (FP64 bank or MP
+ * layout), OOM / ADMISSION, DEVICE. */
+int dotpe_extrinsic_samples(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_extrinsic_desc* desc,
+                            double* lat, double* lon, double* psi, double* cos_iota, double* t_geo,
+                            double* ln_w, dotpe_extrinsic_result* out);
+
 /* ---- Serving: continuous admission of events against a resident bank ----
  *
  * A server owns one device pool and n_slots streams.  dotpe_submit copies an

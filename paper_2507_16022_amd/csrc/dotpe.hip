@@ -1719,6 +1719,185 @@ int dotpe_debug_distmarg(dotpe_ctx* ctx, int64_t n, const double* dh, const doub
   return DOTPE_OK;
 }
 
+int dotpe_extrinsic_samples(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_extrinsic_desc* d,
+                            double* lat, double* lon, double* psi, double* cos_iota, double* t_geo,
+                            double* ln_w, dotpe_extrinsic_result* out) {
+  if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
+  if (bk->prec == kFP64 || bk->mt.layout != 0)
+    return fail(DOTPE_E_UNIMPLEMENTED,
+                "arrival-time series come from the pre-selection: split-precision (l, m) banks only");
+  if (d->n_det < 1 || d->n_det > kMaxDet) return fail(DOTPE_E_INVALID_ARG, "n_det=%d", d->n_det);
+  if (d->n_t < 32 || d->n_t > kPreMaxT || d->n_t % 32)
+    return fail(DOTPE_E_INVALID_ARG, "n_t=%d (32, 64, 96 or 128)", d->n_t);
+  if (d->n_phi < 1 || d->n_phi > kMaxPhi) return fail(DOTPE_E_INVALID_ARG, "n_phi=%d", d->n_phi);
+  if (d->n_rows < 1 || d->n_rows > 64) return fail(DOTPE_E_INVALID_ARG, "n_rows=%d", d->n_rows);
+  if (d->n_sky < 1 || d->n_sky > 65536 || d->n_tg < 1 || d->n_tg > 4096 || d->n_samples < 1)
+    return fail(DOTPE_E_INVALID_ARG, "n_sky=%d n_tg=%d n_samples=%lld", d->n_sky, d->n_tg,
+                (long long)d->n_samples);
+  const int64_t SJ = (int64_t)d->n_sky * d->n_tg, CSJ = SJ * d->n_rows;
+  if (CSJ > (int64_t(1) << 26)) return fail(DOTPE_E_INVALID_ARG, "n_rows x n_sky x n_tg > 2^26");
+  if (!d->d || !d->w || !d->det_r || !d->t0 || !d->rows || !d->cos_iota)
+    return fail(DOTPE_E_INVALID_ARG, "extrinsic-sample arrays must not be NULL");
+  const int nk = d->n_det, nb = bk->n_b, C = d->n_rows;
+  if (!finite_all(d->d, (size_t)nk * nb * 2) || !finite_all(d->w, (size_t)nk * nb) ||
+      !finite_all(d->det_r, (size_t)nk * 3) || !finite_all(d->t0, nk) || !std::isfinite(d->dt) ||
+      !finite_all(d->cos_iota, C) || !std::isfinite(d->tg_lo) || !std::isfinite(d->tg_hi) ||
+      !std::isfinite(d->beta))
+    return fail(DOTPE_E_NUMERIC, "non-finite extrinsic-sample input");
+  if (!(d->dt > 0.0) || !(d->tg_hi > d->tg_lo))
+    return fail(DOTPE_E_INVALID_ARG, "dt and the geocentre-time window must be positive");
+  for (int c = 0; c < C; ++c) {
+    if (d->rows[c] < 0 || d->rows[c] >= bk->n_wf) return fail(DOTPE_E_INVALID_ARG, "row out of range");
+    if (std::fabs(d->cos_iota[c]) > 1.0) return fail(DOTPE_E_INVALID_ARG, "|cos_iota| > 1");
+  }
+  for (size_t t = 0; t < (size_t)nk * nb; ++t)
+    if (d->w[t] < 0.0) return fail(DOTPE_E_INVALID_ARG, "negative noise weight");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t s = d->stream ? (hipStream_t)d->stream : ctx->stream;
+  const ModeTables& mt = bk->mt;
+  // the pre-selection's products, one intrinsic sample at a time, keeping
+  // each detector's per-time maxima
+  PreArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.A0 = bk->A0;
+  a.A1 = bk->A1;
+  a.row_scale = bk->row_scale;
+  a.K2 = bk->K2;
+  a.n_c = mt.n_c;
+  a.n_b = nb;
+  a.n_bp = bk->n_bp;
+  for (int c = 0; c < mt.n_c; ++c) {
+    a.l[c] = mt.l[c];
+    a.m[c] = mt.m[c];
+    for (int g = 0; g < mt.G; ++g)
+      if (mt.gm[g] == mt.m[c]) a.cg[c] = g;
+  }
+  for (int g = 0; g < mt.G; ++g) a.gm[g] = mt.gm[g];
+  a.G = mt.G;
+  a.n_rows = 1;
+  a.n_det = nk;
+  a.n_t = d->n_t;
+  a.n_phi = d->n_phi;
+  a.f = bk->f;
+  a.dt = d->dt;
+  a.K2p = 2 * (int64_t)bk->n_bp;
+  a.delta = 20.0;
+  const int64_t n_grid = (int64_t)nk * d->n_t;
+  std::vector<void*> bufs;
+  uint64_t held = 0;
+  struct Release {
+    dotpe_ctx* ctx;
+    std::vector<void*>* bufs;
+    uint64_t* held;
+    hipStream_t s;
+    ~Release() {
+      (void)hipStreamSynchronize(s);
+      for (void* p : *bufs) (void)hipFree(p);
+      ctx->bytes -= *held;
+    }
+  } release{ctx, &bufs, &held, s};
+  int rc;
+  auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &bufs, &held); };
+  void *dd = nullptr, *ww = nullptr, *tt = nullptr, *ci = nullptr, *st = nullptr;
+  double *ml = nullptr, *rmax = nullptr, *tab = nullptr, *lnZ = nullptr, *mix = nullptr,
+         *blk = nullptr, *draws = nullptr, *stats = nullptr;
+  const int64_t nblk = (CSJ + 1023) / 1024;
+  if ((rc = alloc(&dd, (size_t)nk * nb * 16)) || (rc = alloc(&ww, (size_t)nk * nb * 8)) ||
+      (rc = alloc(&tt, (size_t)nk * 8)) || (rc = alloc(&ci, (size_t)C * 8)) ||
+      (rc = alloc((void**)&a.B0, (size_t)n_grid * a.K2p * 2)) ||
+      (rc = alloc((void**)&a.B1, (size_t)n_grid * a.K2p * 2)) ||
+      (rc = alloc((void**)&a.col_scale, (size_t)n_grid * 8)) ||
+      (rc = alloc((void**)&a.gram, (size_t)nk * pre_pairs(mt.n_c) * 16)) ||
+      (rc = alloc((void**)&a.ml_det, (size_t)nk * 8)) || (rc = alloc((void**)&a.lnl, 8)) ||
+      (rc = alloc(&st, 64)) || (rc = alloc((void**)&a.counts, 4)) ||
+      (rc = alloc((void**)&a.offsets, 8)) || (rc = alloc((void**)&a.selected, 8)) ||
+      (rc = alloc((void**)&ml, (size_t)C * n_grid * 8)) ||
+      (rc = alloc((void**)&rmax, (size_t)C * nk * 8)) ||
+      (rc = alloc((void**)&tab, (size_t)CSJ * 8)) || (rc = alloc((void**)&lnZ, (size_t)C * 8)) ||
+      (rc = alloc((void**)&mix, (size_t)SJ * 8)) || (rc = alloc((void**)&blk, (size_t)nblk * 8)) ||
+      (rc = alloc((void**)&draws, (size_t)d->n_samples * 7 * 8)) ||
+      (rc = alloc((void**)&stats, 16)))
+    return rc;
+  a.d = (const double2*)dd;
+  a.w = (const double*)ww;
+  a.t0 = (const double*)tt;
+  a.state = (uint64_t*)st;
+  HIP_OK(hipMemcpyAsync(dd, d->d, (size_t)nk * nb * 16, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(ww, d->w, (size_t)nk * nb * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(tt, d->t0, (size_t)nk * 8, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(ci, d->cos_iota, (size_t)C * 8, hipMemcpyHostToDevice, s));
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  struct Events {
+    hipEvent_t a, b;
+    ~Events() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evs{e0, e1};
+  HIP_OK(hipEventRecord(e0, s));
+  const uint64_t st0[2] = {0x000fffffffffffffull, 0ull};
+  for (int c = 0; c < C; ++c) {
+    HIP_OK(hipMemcpyAsync(st, st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    a.row0 = d->rows[c];
+    a.cos_iota = (const double*)ci + c;
+    a.ml_t = ml + (size_t)c * n_grid;
+    hipError_t e = preselect_launch(bk->prec, a, s);
+    if (e != hipSuccess) return fail(DOTPE_E_DEVICE, "arrival-time series: %s", hipGetErrorString(e));
+  }
+  // the proposals over (sky, geocentre-time) cells, their mixture, the draws
+  PropGeom g;
+  std::memset(&g, 0, sizeof(g));
+  g.C = C;
+  g.S = d->n_sky;
+  g.J = d->n_tg;
+  g.K = nk;
+  g.n_t = d->n_t;
+  for (int k = 0; k < nk; ++k) {
+    g.t0[k] = d->t0[k];
+    for (int q = 0; q < 3; ++q) g.r[k][q] = d->det_r[3 * k + q];
+  }
+  g.dt = d->dt;
+  g.tg_lo = d->tg_lo;
+  g.dtg = (d->tg_hi - d->tg_lo) / d->n_tg;
+  g.beta = d->beta > 0.0 ? d->beta : 0.5;
+  hipLaunchKernelGGL(k_prop_max, dim3((unsigned)((C * nk + 63) / 64)), dim3(64), 0, s, ml, g, rmax);
+  hipLaunchKernelGGL(k_prop_table, dim3((unsigned)((CSJ + 255) / 256)), dim3(256), 0, s, ml, rmax, g,
+                     tab);
+  hipLaunchKernelGGL(k_prop_lse, dim3((unsigned)C), dim3(256), 0, s, tab, g, lnZ);
+  hipLaunchKernelGGL(k_prop_prob, dim3((unsigned)((SJ + 255) / 256)), dim3(256), 0, s, tab, lnZ, g,
+                     mix);
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nblk), dim3(1024), 0, s, tab, CSJ, blk);
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(64), 0, s, blk, nblk);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(1024), 0, s, tab, CSJ, (const double*)blk);
+  hipLaunchKernelGGL(k_prop_draw, dim3((unsigned)((d->n_samples + 255) / 256)), dim3(256), 0, s,
+                     (const double*)tab, (const double*)mix, g, d->n_samples, d->seed, draws);
+  hipLaunchKernelGGL(k_prop_stats, dim3(1), dim3(256), 0, s, (const double*)draws, d->n_samples,
+                     (const double*)mix, SJ, stats);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipEventRecord(e1, s));
+  std::vector<double> h((size_t)d->n_samples * 7);
+  double sth[2];
+  HIP_OK(hipMemcpyAsync(h.data(), draws, h.size() * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(sth, stats, 16, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  double* outs[6] = {lat, lon, psi, cos_iota, t_geo, ln_w};
+  for (int f = 0; f < 6; ++f)
+    if (outs[f])
+      for (int64_t q = 0; q < d->n_samples; ++q) outs[f][q] = h[(size_t)q * 7 + f];
+  float ms = 0.f;
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  dotpe_extrinsic_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_eff_prior = sth[0];
+  r.support = sth[1];
+  r.t_ms = ms;
+  r.n_samples = d->n_samples;
+  *out = r;
+  return DOTPE_OK;
+}
+
 int dotpe_rb_weights(dotpe_ctx* ctx, const dotpe_rb_desc* d, double* w_dh, double* w_hh,
                      double* dd) {
   if (!ctx || !d) return fail(DOTPE_E_INVALID_ARG, "NULL argument");

@@ -388,6 +388,183 @@ __global__ void k_rb_weights(int n_det, int n_c, int64_t n_full, int n_nodes,
   (is_dh ? wdh : whh)[j] = make_double2(r.x / dn, r.y / dn);
 }
 
+// ---------------------------------------------------------------------------
+// extrinsic-sample proposals (Sec. IV E; App. C): per intrinsic sample c a
+// distribution over the cells (sky lattice point s, geocentre-time cell j)
+// from the detectors' arrival-time probabilities, their mixture, draws and
+// importance weights
+// ---------------------------------------------------------------------------
+struct PropGeom {
+  int C, S, J, K, n_t;
+  double t0[kMaxDet], dt, r[kMaxDet][3];
+  double tg_lo, dtg, beta;
+};
+
+__device__ __forceinline__ void fib_sky(int s, int S, double* lat, double* lon) {
+  const double z = 1.0 - (2.0 * s + 1.0) / S;
+  const double ga = M_PI * (3.0 - sqrt(5.0));
+  *lat = asin(z);
+  *lon = fmod((double)s * ga, 2.0 * M_PI);
+}
+
+// rmax[c][k] = max_j of the per-time maxima ml[c][k][j]
+__global__ void k_prop_max(const double* __restrict__ ml, PropGeom g, double* __restrict__ rmax) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.C * g.K) return;
+  double m = -INFINITY;
+  for (int j = 0; j < g.n_t; ++j) m = fmax(m, ml[(int64_t)t * g.n_t + j]);
+  rmax[t] = m;
+}
+
+// ln W_c(s, j) = sum_k beta (rho^2_ck(t_i) - max rho^2_ck), i the grid point
+// nearest to t_j - r_k . n_s / c (-inf off the grid); rho^2 = 2 ml
+__global__ void k_prop_table(const double* __restrict__ ml, const double* __restrict__ rmax,
+                             PropGeom g, double* __restrict__ lnW) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t SJ = (int64_t)g.S * g.J;
+  if (idx >= (int64_t)g.C * SJ) return;
+  const int c = (int)(idx / SJ);
+  const int s = (int)((idx % SJ) / g.J), j = (int)(idx % g.J);
+  double lat, lon;
+  fib_sky(s, g.S, &lat, &lon);
+  const double n0 = cos(lat) * cos(lon), n1 = cos(lat) * sin(lon), n2 = sin(lat);
+  const double tj = g.tg_lo + (j + 0.5) * g.dtg;
+  double acc = 0.0;
+  for (int k = 0; k < g.K; ++k) {
+    const double tk = tj - (g.r[k][0] * n0 + g.r[k][1] * n1 + g.r[k][2] * n2) / 299792458.0;
+    const double x = rint((tk - g.t0[k]) / g.dt);
+    if (!(x >= 0.0 && x < g.n_t)) {
+      acc = -INFINITY;
+      break;
+    }
+    const int64_t ck = (int64_t)c * g.K + k;
+    acc += g.beta * 2.0 * (ml[ck * g.n_t + (int)x] - rmax[ck]);
+  }
+  lnW[idx] = acc;
+}
+
+// ln Z_c = LSE over the cells of ln W_c: a block per c
+__global__ void k_prop_lse(const double* __restrict__ lnW, PropGeom g, double* __restrict__ lnZ) {
+  __shared__ double sm[256], ss[256];
+  const int c = blockIdx.x;
+  const int64_t SJ = (int64_t)g.S * g.J;
+  const double* x = lnW + (int64_t)c * SJ;
+  double m = -INFINITY, s = 0.0;
+  for (int64_t t = threadIdx.x; t < SJ; t += 256) {
+    const double v = x[t];
+    if (v == -INFINITY) continue;
+    if (v > m) {
+      s = s * exp(m - v) + 1.0;
+      m = v;
+    } else {
+      s += exp(v - m);
+    }
+  }
+  sm[threadIdx.x] = m;
+  ss[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double M = -INFINITY, Ssum = 0.0;
+    for (int t = 0; t < 256; ++t) {
+      if (sm[t] == -INFINITY) continue;
+      if (sm[t] > M) {
+        Ssum = Ssum * exp(M - sm[t]) + ss[t];
+        M = sm[t];
+      } else {
+        Ssum += ss[t] * exp(sm[t] - M);
+      }
+    }
+    lnZ[c] = M == -INFINITY ? -INFINITY : M + log(Ssum);
+  }
+}
+
+// P_c(cell) = W_c / Z_c (in place over ln W), and the mixture (1/C) sum_c P_c
+__global__ void k_prop_prob(double* __restrict__ x, const double* __restrict__ lnZ, PropGeom g,
+                            double* __restrict__ mix) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t SJ = (int64_t)g.S * g.J;
+  if (cell >= SJ) return;
+  double m = 0.0;
+  for (int c = 0; c < g.C; ++c) {
+    const double v = x[(int64_t)c * SJ + cell];
+    const double p = (v == -INFINITY || lnZ[c] == -INFINITY) ? 0.0 : exp(v - lnZ[c]);
+    x[(int64_t)c * SJ + cell] = p;
+    m += p;
+  }
+  mix[cell] = m / g.C;
+}
+
+// draws: q from component q mod C, its cell the first whose running sum
+// (cum: inclusive running sums over the components back to back) exceeds
+// u times the component's total
+__global__ void k_prop_draw(const double* __restrict__ cum, const double* __restrict__ mix,
+                            PropGeom g, int64_t n_s, uint64_t seed, double* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_s) return;
+  const int64_t SJ = (int64_t)g.S * g.J;
+  const int c = (int)(q % g.C);
+  const int64_t lo0 = (int64_t)c * SJ;
+  const double base = c > 0 ? cum[lo0 - 1] : 0.0;
+  const double tot = cum[lo0 + SJ - 1] - base;
+  const double target = sm64_uniform(seed, 4 * (uint64_t)q) * tot;
+  int64_t lo = 0, hi = SJ - 1;          // first x with cum[lo0 + x] - base > target (the last if none)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (cum[lo0 + mid] - base > target) hi = mid;
+    else lo = mid + 1;
+  }
+  const int s = (int)(lo / g.J), j = (int)(lo % g.J);
+  double lat, lon;
+  fib_sky(s, g.S, &lat, &lon);
+  double* o = out + 7 * q;
+  o[0] = lat;
+  o[1] = lon;
+  o[2] = M_PI * sm64_uniform(seed, 4 * (uint64_t)q + 2);
+  o[3] = 2.0 * sm64_uniform(seed, 4 * (uint64_t)q + 3) - 1.0;
+  o[4] = g.tg_lo + (j + sm64_uniform(seed, 4 * (uint64_t)q + 1)) * g.dtg;
+  o[5] = -log((double)SJ) - log(mix[lo]);
+  o[6] = (double)lo;
+}
+
+// N_eff over the draws' weights and the prior mass of the mixture's support:
+// one block; st[0] = (sum w)^2 / sum w^2, st[1] = support
+__global__ void k_prop_stats(const double* __restrict__ out, int64_t n_s, const double* __restrict__ mix,
+                             int64_t SJ, double* __restrict__ st) {
+  __shared__ double a[256], b[256], m[256], cnt[256];
+  double mx = -INFINITY;
+  for (int64_t q = threadIdx.x; q < n_s; q += 256) mx = fmax(mx, out[7 * q + 5]);
+  m[threadIdx.x] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double M = -INFINITY;
+    for (int t = 0; t < 256; ++t) M = fmax(M, m[t]);
+    m[0] = M;
+  }
+  __syncthreads();
+  const double M = m[0];
+  double s1 = 0.0, s2 = 0.0, ns = 0.0;
+  for (int64_t q = threadIdx.x; q < n_s; q += 256) {
+    const double v = exp(out[7 * q + 5] - M);
+    s1 += v;
+    s2 += v * v;
+  }
+  for (int64_t t = threadIdx.x; t < SJ; t += 256) ns += mix[t] > 0.0 ? 1.0 : 0.0;
+  a[threadIdx.x] = s1;
+  b[threadIdx.x] = s2;
+  cnt[threadIdx.x] = ns;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double A = 0.0, B = 0.0, N = 0.0;
+    for (int t = 0; t < 256; ++t) {
+      A += a[t];
+      B += b[t];
+      N += cnt[t];
+    }
+    st[0] = A * A / B;
+    st[1] = N / (double)SJ;
+  }
+}
+
 // (d|d)
 __global__ void k_data_norm(int n, const double2* __restrict__ d, const double* __restrict__ w,
                             double* __restrict__ out) {

@@ -61,6 +61,7 @@ struct PreArgs {
   int* counts;               // [n_blocks] rows selected per block of 1024
   int64_t* offsets;          // [n_blocks]
   int64_t* selected;         // [n_rows] bank rows kept, ascending
+  double* ml_t;              // optional [n_rows][n_det][n_t]: max over phases per grid time
 };
 
 __host__ __device__ inline int pre_pairs(int n_c) { return n_c * (n_c + 1) / 2; }

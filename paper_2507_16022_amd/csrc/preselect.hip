@@ -316,6 +316,8 @@ __global__ __launch_bounds__(64 * kPreMaxT / 32) void k_preselect(PreArgs a) {
       const float u = q.x * bp + q.y * bx, v = q.x * bx - q.y * bp;
       bestf = fmaxf(bestf, q.z * u * u + q.w * v * v);
     }
+    if (a.ml_t && rr < rows_in)
+      a.ml_t[((rb0 + rr) * a.n_det + k) * a.n_t + 32 * wave + (lane & 31)] = (double)bestf;
     double best = (double)bestf;
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, 32));

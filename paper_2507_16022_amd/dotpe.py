@@ -62,6 +62,21 @@ class EventDesc(ctypes.Structure):
                 ("w_dh", ctypes.c_void_p), ("w_hh", ctypes.c_void_p), ("dd", ctypes.c_double)]
 
 
+class ExtrinsicDesc(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int32), ("n_t", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+                ("n_rows", ctypes.c_int32), ("d", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("det_r", ctypes.c_void_p), ("t0", ctypes.c_void_p), ("dt", ctypes.c_double),
+                ("rows", ctypes.c_void_p), ("cos_iota", ctypes.c_void_p), ("beta", ctypes.c_double),
+                ("n_sky", ctypes.c_int32), ("n_tg", ctypes.c_int32), ("tg_lo", ctypes.c_double),
+                ("tg_hi", ctypes.c_double), ("n_samples", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p)]
+
+
+class ExtrinsicResult(ctypes.Structure):
+    _fields_ = [("n_eff_prior", ctypes.c_double), ("support", ctypes.c_double),
+                ("t_ms", ctypes.c_double), ("n_samples", ctypes.c_int64)]
+
+
 class RBDesc(ctypes.Structure):
     _fields_ = [("n_det", ctypes.c_int32), ("n_modes", ctypes.c_int32), ("n_full", ctypes.c_int64),
                 ("f", ctypes.c_void_p), ("d", ctypes.c_void_p), ("w", ctypes.c_void_p),
@@ -149,6 +164,9 @@ SYMBOLS = {
                                         ctypes.POINTER(PreselectResult)]),
     "dotpe_rb_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(RBDesc), ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "dotpe_extrinsic_samples": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.POINTER(ExtrinsicDesc)] + [ctypes.c_void_p] * 6
+                                + [ctypes.POINTER(ExtrinsicResult)]),
     "dotpe_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.POINTER(ServerDesc),
                                             ctypes.POINTER(ctypes.c_void_p)]),
@@ -240,6 +258,32 @@ class Context:
         [N, C, B, 2] on the GPU (device pointer, no host copy).  modes: (l, m) per
         channel (layout "lm") or (m, p) per channel (layout "mp", p 0 for +, 1 for x)."""
         return Bank(self, h, modes, f, ln_w, precision, layout)
+
+    def extrinsic_samples(self, bank, d, w, det_r, t0, dt, n_t, rows, cos_iota, n_phi, n_sky, n_tg,
+                          tg_lo, tg_hi, n_samples, seed=0, beta=0.5, stream=None):
+        """dotpe_extrinsic_samples: importance-sampled extrinsic parameters from the
+        arrival-time probabilities of the intrinsic samples `rows`.  Returns a dict with
+        lat, lon, psi, cos_iota, t_geo, ln_w [n_samples] and the result fields."""
+        d = np.ascontiguousarray(d, dtype=np.complex128)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        r = np.ascontiguousarray(det_r, dtype=np.float64)
+        t0 = np.ascontiguousarray(t0, dtype=np.float64)
+        rw = np.ascontiguousarray(rows, dtype=np.int64)
+        ci = np.ascontiguousarray(cos_iota, dtype=np.float64)
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        desc = ExtrinsicDesc(d.shape[0], int(n_t), int(n_phi), len(rw), d.ctypes.data, w.ctypes.data,
+                             r.ctypes.data, t0.ctypes.data, float(dt), rw.ctypes.data, ci.ctypes.data,
+                             float(beta), int(n_sky), int(n_tg), float(tg_lo), float(tg_hi),
+                             int(n_samples), ctypes.c_uint64(int(seed)), stream)
+        out = {k: np.empty(int(n_samples)) for k in ("lat", "lon", "psi", "cos_iota", "t_geo", "ln_w")}
+        res = ExtrinsicResult()
+        _check(load_library().dotpe_extrinsic_samples(
+            self._h, bank.handle, ctypes.byref(desc), out["lat"].ctypes.data, out["lon"].ctypes.data,
+            out["psi"].ctypes.data, out["cos_iota"].ctypes.data, out["t_geo"].ctypes.data,
+            out["ln_w"].ctypes.data, ctypes.byref(res)))
+        out.update({name: getattr(res, name) for name, _ in ExtrinsicResult._fields_})
+        return out
 
     def rb_weights(self, f, d, w, h0, node_idx, t0=None):
         """dotpe_rb_weights: relative-binning weights from full-resolution data f [F],

@@ -50,6 +50,8 @@ STRUCTS = {
     "dotpe_posterior_sample": dotpe.PosteriorSample,
     "dotpe_preselect_result": dotpe.PreselectResult,
     "dotpe_rb_desc": dotpe.RBDesc,
+    "dotpe_extrinsic_desc": dotpe.ExtrinsicDesc,
+    "dotpe_extrinsic_result": dotpe.ExtrinsicResult,
 }
 
 
