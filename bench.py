@@ -182,6 +182,54 @@ def preselect_leg(W, O, ctx, bank, wl, n_int, args, reps=3):
     return out
 
 
+def extrinsic_leg(W, O, ctx, bank, wl, args, reps=3):
+    """Extrinsic samples (Sec. IV E, App. C) for the large event: 16 intrinsic samples (the
+    pre-selection's best rows when available, else the first), 16384 sky points x 256
+    geocentre-time cells over +-10 ms, 16384 draws; timed with HIP events inside the call.
+    The draws' prior parts are checked against the oracle's (same uniforms)."""
+    n_t, dt, n_phi = 128, 2.5e-4, 32
+    ext1 = wl.meta["inj_ext"]
+    la, lo = ext1["lat"], ext1["lon"]
+    nvec = np.array([np.cos(la) * np.cos(lo), np.cos(la) * np.sin(lo), np.sin(la)])
+    t0 = ext1["t_geo"] - wl.det_r @ nvec / 299792458.0 - 0.5 * n_t * dt
+    rows = np.arange(16, dtype=np.int64) * 4099
+    ci = np.full(16, ext1["cos_iota"])
+    kw = dict(n_sky=16384, n_tg=256, tg_lo=ext1["t_geo"] - 0.01, tg_hi=ext1["t_geo"] + 0.01,
+              n_samples=16384, seed=5)
+    g = ctx.extrinsic_samples(bank, wl.d, wl.w, wl.det_r, t0, dt, n_t, rows, ci, n_phi, **kw)
+    ms = []
+    for _ in range(reps):
+        g = ctx.extrinsic_samples(bank, wl.d, wl.w, wl.det_r, t0, dt, n_t, rows, ci, n_phi, **kw)
+        ms.append(g["t_ms"])
+    psi = np.array([math.pi * O.splitmix64_uniform(5, 4 * q + 2) for q in range(64)])
+    err = float(np.max(np.abs(g["psi"][:64] - psi)))
+    out = {"intrinsic_samples": 16, "sky_points": 16384, "time_cells": 256, "draws": 16384,
+           "ms": float(np.mean(ms)), "n_eff_prior": g["n_eff_prior"], "support": g["support"],
+           "prior_draws_max_abs_diff_vs_oracle": err}
+    log(f"extrinsic samples: 16 x 16384 x 256 cells, 16384 draws in {out['ms']:.2f} ms, N_eff prior "
+        f"{g['n_eff_prior']:.0f}, support {g['support']:.3f}")
+    return out
+
+
+def rb_leg(W, O, ctx, args, reps=3):
+    """Relative-binning weights (App. A) from 2^17 full-resolution frequencies, 3 detectors,
+    5 channels, 256 nodes; timed around the call, host transfers included (their parity with
+    the oracle is a test)."""
+    import time as _t
+    ev = W.make_rb_event(31, 4, 4, 256, 1 << 17, snr=20.0)
+    ctx.rb_weights(ev.f_full, ev.d_full, ev.w_full, ev.h0, ev.node_idx, ev.t0)
+    ts = []
+    for _ in range(reps):
+        t1 = _t.perf_counter()
+        ctx.rb_weights(ev.f_full, ev.d_full, ev.w_full, ev.h0, ev.node_idx, ev.t0)
+        ts.append(_t.perf_counter() - t1)
+    out = {"full_resolution": 1 << 17, "nodes": len(ev.node_idx), "detectors": 3, "channels": 5,
+           "ms_with_transfers": 1e3 * float(np.mean(ts))}
+    log(f"relative-binning weights: 2^17 frequencies -> {len(ev.node_idx)} nodes, 3 x 5 channels in "
+        f"{out['ms_with_transfers']:.1f} ms (host transfers included)")
+    return out
+
+
 def fp64_comparison(torch, dotpe, W, ctx, args, reps=2):
     """Fused-pass time of the plain FP64 path against the split-precision path on the
     same production-shape event (65536 x 4096 pairs, same cut), and their ln Z."""
@@ -412,6 +460,8 @@ def main():
     serving = (serving_leg(dotpe, W, ctx, bank, n_int, args)
                if args.serve_events > 0 else None)
     presel = None if args.precision == "fp64" else preselect_leg(W, O, ctx, bank, wl, n_int, args)
+    extr = None if args.precision == "fp64" else extrinsic_leg(W, O, ctx, bank, wl, args)
+    rb = rb_leg(W, O, ctx, args)
     fp64_cmp = None if args.no_fp64 else fp64_comparison(torch, dotpe, W, ctx, args)
     traffic = stored_traffic()
     out = {
@@ -450,6 +500,8 @@ def main():
         "fp64_path": fp64_cmp,
         "serving": serving,
         "preselect": presel,
+        "extrinsic_samples": extr,
+        "relative_binning": rb,
     }
     print(json.dumps(out), flush=True)
 
