@@ -413,7 +413,7 @@ void launch_hh(dotpe_event* ev, const double* w, const double2* whh) {
   // the row's amplitudes and the noise weights in LDS when they fit (the
   // kernel applies the same test)
   const size_t rb = PREC == kFP64 ? sizeof(double2) : sizeof(float2);   // staged row value
-  size_t sh = (size_t)bk->n_c * bk->n_bp * rb + (size_t)ev->n_det * bk->n_b * sizeof(double);
+  size_t sh = (size_t)bk->n_c * (bk->n_bp + 1) * rb + (size_t)ev->n_det * (bk->n_b + 1) * sizeof(double);
   if (sh > 65536) sh = 0;
   hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(64), sh, ev->stream,
                      ev->n_sub, ev->sub_idx, ev->sub0, bk->A0, bk->A1, bk->row_scale, bk->n_bp,

@@ -649,8 +649,12 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   if (ie >= n_sub) return;
   const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
   const int64_t K2 = (int64_t)mt.n_c * n_bp * 2;
-  const bool staged = (size_t)mt.n_c * n_bp * sizeof(RB) + (size_t)n_det * n_b * sizeof(double) <= 65536;
-  double* wl = (double*)(rowbuf + mt.n_c * n_bp);
+  // channel rows and detector rows one entry longer than the data, so that
+  // the lanes reading one bin of different channels or detectors fall on
+  // different LDS banks
+  const int rs = n_bp + 1, ws = n_b + 1;
+  const bool staged = (size_t)mt.n_c * rs * sizeof(RB) + (size_t)n_det * ws * sizeof(double) <= 65536;
+  double* wl = (double*)(rowbuf + mt.n_c * rs);
   if (staged) {
     // the row in pieces of 8 consecutive positions (16 bytes per operand
     // array in the split layouts): 8 bins of the real or the imaginary part
@@ -677,12 +681,12 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
       const int kk = pc * 8, chunk = kk >> 5, within = kk & 31;
       const int c = chunk / (n_bp / kChunk), b0 = (chunk % (n_bp / kChunk)) * kChunk + (within & 15);
       typedef typename std::conditional<PREC == kFP64, double, float>::type RV;
-      RV* dst = (RV*)(rowbuf + c * n_bp + b0) + (within >= 16 ? 1 : 0);
+      RV* dst = (RV*)(rowbuf + c * rs + b0) + (within >= 16 ? 1 : 0);
 #pragma unroll
       for (int j = 0; j < 8; ++j) dst[2 * j] = (RV)v[j];
     }
     if (!whh)
-      for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[t] = w[t];
+      for (int t = threadIdx.x; t < n_det * n_b; t += blockDim.x) wl[(t / n_b) * ws + t % n_b] = w[t];
     __syncthreads();
   }
   double sc = row_scale ? row_scale[i] : 1.0;
@@ -695,8 +699,8 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
       // relative binning: a complex weight per channel pair and bin
       const double2* Wp = whh + ((int64_t)k * mt.NP + p) * n_b;
       for (int b = 0; b < n_b; ++b) {
-        const double2 a = staged ? to_d2(rowbuf[c * n_bp + b]) : bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
-        const double2 a2 = staged ? to_d2(rowbuf[c2 * n_bp + b]) : bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
+        const double2 a = staged ? to_d2(rowbuf[c * rs + b]) : bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
+        const double2 a2 = staged ? to_d2(rowbuf[c2 * rs + b]) : bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
         const double2 u = cmul(Wp[b], cmul(cconj(a), a2));
         acc.x += u.x;
         acc.y += u.y;
@@ -706,18 +710,18 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
       double2 acc2 = make_double2(0.0, 0.0);
       int b = 0;
       for (; b + 1 < n_b; b += 2) {
-        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * n_bp + b])), to_d2(rowbuf[c2 * n_bp + b]));
-        const double2 v1 = cmul(cconj(to_d2(rowbuf[c * n_bp + b + 1])), to_d2(rowbuf[c2 * n_bp + b + 1]));
-        const double w0 = wl[k * n_b + b], w1 = wl[k * n_b + b + 1];
+        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * rs + b])), to_d2(rowbuf[c2 * rs + b]));
+        const double2 v1 = cmul(cconj(to_d2(rowbuf[c * rs + b + 1])), to_d2(rowbuf[c2 * rs + b + 1]));
+        const double w0 = wl[k * ws + b], w1 = wl[k * ws + b + 1];
         acc.x += w0 * v0.x;
         acc.y += w0 * v0.y;
         acc2.x += w1 * v1.x;
         acc2.y += w1 * v1.y;
       }
       if (b < n_b) {
-        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * n_bp + b])), to_d2(rowbuf[c2 * n_bp + b]));
-        acc.x += wl[k * n_b + b] * v0.x;
-        acc.y += wl[k * n_b + b] * v0.y;
+        const double2 v0 = cmul(cconj(to_d2(rowbuf[c * rs + b])), to_d2(rowbuf[c2 * rs + b]));
+        acc.x += wl[k * ws + b] * v0.x;
+        acc.y += wl[k * ws + b] * v0.y;
       }
       acc.x += acc2.x;
       acc.y += acc2.y;
