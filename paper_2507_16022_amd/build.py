@@ -1,9 +1,10 @@
 """Build the HIP library libdotpe.so in-tree for gfx950 (hipcc, no JIT).
 
 The host runtime (csrc/dotpe.hip), the pre-selection kernels
-(csrc/preselect.hip) and one instantiation unit of the fused kernel per
-(precision, number of m groups) (csrc/fused_inst.hip) are compiled to
-objects in parallel, then linked into one shared library.
+(csrc/preselect.hip) and two instantiation units per (precision, number of
+m groups) -- the fused kernel and bound pass (csrc/fused_inst.hip), the
+marginalisation kernels (csrc/marg_inst.hip) -- are compiled to objects in
+parallel, then linked into one shared library.
 """
 import os
 import subprocess
@@ -30,8 +31,12 @@ def units():
            (os.path.join(CSRC, "preselect.hip"), os.path.join(OBJ, "preselect.o"), [])]
     for p in PRECISIONS:
         for g in GROUPS:
+            inst = [f"-DDOTPE_INST_PREC={p}", f"-DDOTPE_INST_G={g}"]
             out.append((os.path.join(CSRC, "fused_inst.hip"), os.path.join(OBJ, f"fused_p{p}_g{g}.o"),
-                        [f"-DDOTPE_INST_PREC={p}", f"-DDOTPE_INST_G={g}"]))
+                        inst))
+            # the marginalisation kernels: no machine-level hoisting of constants
+            out.append((os.path.join(CSRC, "marg_inst.hip"), os.path.join(OBJ, f"marg_p{p}_g{g}.o"),
+                        inst + ["-mllvm", "-disable-machine-licm"]))
     return out
 
 

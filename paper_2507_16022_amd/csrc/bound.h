@@ -624,7 +624,7 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
 // The results are merged into the tile's partial, which the bound pass wrote
 // with the tile's bounded mass.
 template <int PREC, int G>
-__global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
+__global__ __launch_bounds__(256, 2) void k_survivors(FusedArgs a) {
   static_assert(PREC != kFP64, "split precisions only");
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;
   typedef typename std::conditional<PREC == kFP16X2, _Float16, __bf16>::type H;
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(256) void k_survivors(FusedArgs a) {
       lse.init();
       double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
-      pair_phases<kEvidence, G>(a, lds_cs, *dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, lane, 64, ev, lse,
+      pair_phases<kEvidence, G, true>(a, lds_cs, *dp, ie, e, X, S0, Sr, Si, lnw, thr_ml, lane, 64, ev, lse,
                                 best, ob, mlmax);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {

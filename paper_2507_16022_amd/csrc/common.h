@@ -70,10 +70,10 @@ struct ModeTables {
   int fcnt[kMaxNF], fpair[kMaxNF][kMaxG], fconj[kMaxNF][kMaxG];
 };
 
-// distance-rule parameters, kept in device memory next to the table (passed
-// by pointer so that no kernel argument has to be copied to private memory)
+// distance-rule parameters (the tail formula's Gauss-Hermite nodes), kept in
+// device memory next to the table (the table's geometry is a compile-time
+// constant)
 struct DistParams {
-  DistTableGeom geom;
   double ghx[kGH], ghw[kGH];
 };
 struct DistArgs {

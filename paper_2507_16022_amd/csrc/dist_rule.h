@@ -12,9 +12,11 @@
 //   * dr_ln_exact: composite adaptive Gauss-Legendre over r with
 //     breakpoints at the stationary points of the log-integrand; used to
 //     build the table and for arguments outside it;
-//   * a table of ln Lbar on a uniform grid in (z, tau), tau = ln(e^s - 1)
-//     (softplus inverse: tau ~ ln s for small s, tau ~ s for large s),
-//     read with 4x4 tensor-product cubic Lagrange interpolation;
+//   * a table of ln Lbar on a grid in (z, w), w = ln s for s < 1 and
+//     w = s - 1 above (logarithmic resolution where Lbar depends on ln s,
+//     linear where it depends on s; w is cheap to form from s), both axes
+//     in uniform segments, read with 4x4 tensor-product cubic Lagrange
+//     interpolation;
 //   * the high-SNR tail (peak far inside the domain and dominant):
 //     Gaussian-Hermite quadrature of E[(z + eps)^-4], eps ~ N(0, 1).
 #pragma once
@@ -31,55 +33,115 @@
 
 namespace dotpe {
 
-// table geometry (shared by builder and reader): the z axis is split into
-// uniform segments (finer where the prior-dominated and peak-dominated
-// regimes of the integrand cross), each stored with its own columns; rows
-// are uniform in tau
-constexpr int kDrSeg = 4;
+// table geometry (shared by builder and reader): both axes are split into
+// uniform segments, each stored with two guard lines on either side so that
+// a stencil never crosses a segment edge.  z (columns): finer where the
+// prior-dominated and peak-dominated regimes of the integrand cross; w
+// (rows): w = ln s below w = 0 (s < 1) and w = s - 1 above, finer where the
+// two maps meet.
+constexpr int kDrSeg = 4;       // z segments
+constexpr int kDrRowSeg = 4;    // w segments
 struct DistTableGeom {
-  double zs0[kDrSeg], hz[kDrSeg];   // first stored column and step per segment
-  double ihz[kDrSeg], iht;          // reciprocal steps (the reader multiplies)
+  double ihz[kDrSeg];               // reciprocal steps (whole numbers)
   double zlo[kDrSeg], zhi[kDrSeg];  // z range served by each segment
-  int nz[kDrSeg], off[kDrSeg];      // columns per segment, column offset of its block
-  double t0, ht;                    // tau_k = t0 + k ht, k < nt
-  int nt, ncol;                     // rows, total columns
+  int nz[kDrSeg], off[kDrSeg];      // columns per segment (guards included), column offset
+  double ihw[kDrRowSeg];            // the same for the rows
+  double wlo[kDrRowSeg], whi[kDrRowSeg];
+  int nw[kDrRowSeg], roff[kDrRowSeg];
+  bool wlog[kDrRowSeg];             // the segment's rows have s = e^w (else s = 1 + w)
+  int nrow, ncol;                   // total rows and columns
 };
 
 // (strongly negative z, the anti-aligned phases of loud pairs, is smooth and
 // takes a coarser step)
 constexpr double kDrSegEdge[kDrSeg + 1] = {-64.0, -12.0, 2.0, 14.0, 32.0};
 constexpr double kDrSegStep[kDrSeg] = {0.1, 0.05, 0.0125, 0.05};
-constexpr double kDrT0 = -20.5, kDrT1 = 20.0, kDrHt = 0.025;
+// w from ln(1e-9) to 19 (s = 20); half steps for 0.135 < s < 3
+constexpr double kDrRowEdge[kDrRowSeg + 1] = {-20.75, -2.0, 0.0, 2.0, 19.0};
+constexpr double kDrRowStep[kDrRowSeg] = {0.025, 0.0125, 0.0125, 0.025};
 constexpr double kDrSMin = 1e-9;     // below: small-s expansion
 constexpr int kGH = 12;              // Gauss-Hermite nodes for the tail
 
-__host__ __device__ inline DistTableGeom dr_make_geom() {
-  DistTableGeom g;
+__host__ __device__ constexpr DistTableGeom dr_make_geom() {
+  DistTableGeom g{};
   int off = 0;
   for (int k = 0; k < kDrSeg; ++k) {
-    double h = kDrSegStep[k];
-    g.hz[k] = h;
+    const double h = kDrSegStep[k];
     g.ihz[k] = 1.0 / h;
     g.zlo[k] = kDrSegEdge[k];
     g.zhi[k] = kDrSegEdge[k + 1];
-    g.zs0[k] = kDrSegEdge[k] - 2.0 * h;       // two guard columns each side
     g.nz[k] = (int)((kDrSegEdge[k + 1] - kDrSegEdge[k]) / h + 0.5) + 5;
     g.off[k] = off;
     off += g.nz[k];
   }
   g.ncol = off;
-  g.t0 = kDrT0;
-  g.ht = kDrHt;
-  g.iht = 1.0 / kDrHt;
-  g.nt = (int)((kDrT1 - kDrT0) / kDrHt + 0.5) + 1;
+  int roff = 0;
+  for (int k = 0; k < kDrRowSeg; ++k) {
+    const double h = kDrRowStep[k];
+    g.ihw[k] = 1.0 / h;
+    g.wlo[k] = kDrRowEdge[k];
+    g.whi[k] = kDrRowEdge[k + 1];
+    g.nw[k] = (int)((kDrRowEdge[k + 1] - kDrRowEdge[k]) / h + 0.5) + 5;
+    g.roff[k] = roff;
+    g.wlog[k] = kDrRowEdge[k + 1] <= 0.0;
+    roff += g.nw[k];
+  }
+  g.nrow = roff;
   return g;
 }
 
+// The geometry as compile-time constants: the reader below folds every
+// segment parameter into its instructions (no loads, no registers held).
+constexpr DistTableGeom kDrGeom = dr_make_geom();
+static_assert(kDrRowEdge[2] == 0.0, "the two row maps meet at w = 0, a segment edge");
+// the reader forms positions as (x - edge) / step + 2 with the reciprocal
+// step: both must be exact in binary for the builder's nodes to sit at whole
+// positions (to rounding)
+constexpr bool dr_exact_recip(double h) { return (1.0 / h) * h == 1.0 && (double)(int)(1.0 / h) == 1.0 / h; }
+static_assert(dr_exact_recip(kDrSegStep[0]) && dr_exact_recip(kDrSegStep[1]) &&
+                  dr_exact_recip(kDrSegStep[2]) && dr_exact_recip(kDrSegStep[3]) &&
+                  dr_exact_recip(kDrRowStep[0]) && dr_exact_recip(kDrRowStep[1]) &&
+                  dr_exact_recip(kDrRowStep[2]) && dr_exact_recip(kDrRowStep[3]),
+              "table steps with whole reciprocals");
+
+// Natural logarithm of a positive normal x: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), ln m = 2 atanh(t) with t = (m - 1) / (m + 1),
+// |t| < 0.172, by the atanh series through t^17 (the rest is below 3e-16).
+// About a quarter of the instructions of the math library's version, and
+// accurate to a few units in the last place of ln x's absolute value.
+__device__ __forceinline__ double dr_log(double x) {
+  int e;
+  double m = frexp(x, &e);             // m in [1/2, 1)
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    --e;
+  }
+  const double t = (m - 1.0) / (m + 1.0), t2 = t * t;
+  double p = 1.0 / 17.0;
+  p = fma(p, t2, 1.0 / 15.0);
+  p = fma(p, t2, 1.0 / 13.0);
+  p = fma(p, t2, 1.0 / 11.0);
+  p = fma(p, t2, 1.0 / 9.0);
+  p = fma(p, t2, 1.0 / 7.0);
+  p = fma(p, t2, 1.0 / 5.0);
+  p = fma(p, t2, 1.0 / 3.0);
+  p = fma(p, t2, 1.0);
+  return fma((double)e, 0.69314718055994531, 2.0 * t * p);
+}
+
+// 1 / d for d > 0 of moderate range: the FP32 reciprocal refined by two
+// Newton steps in FP64 (relative error squared per step: below 1e-15)
+__device__ __forceinline__ double dr_rcp(double d) {
+  double y = (double)__builtin_amdgcn_rcpf((float)d);
+  y = y * fma(-d, y, 2.0);
+  return y * fma(-d, y, 2.0);
+}
+
 // z of stored column `col` (any segment)
-__host__ __device__ inline double dr_col_z(const DistTableGeom& g, int col) {
+__device__ inline double dr_col_z(const DistTableGeom& g, int col) {
   int k = 0;
   while (k + 1 < kDrSeg && col >= g.off[k + 1]) ++k;
-  return g.zs0[k] + (col - g.off[k]) * g.hz[k];
+  return g.zlo[k] + (col - g.off[k] - 2) / g.ihz[k];     // two guard columns below the edge
 }
 
 __host__ __device__ __forceinline__ double dr_psi(double r, double a, double b) {
@@ -204,81 +266,108 @@ __host__ __device__ inline __attribute__((noinline)) double dr_ln_exact(double z
   return log(3.0) + pmax + log(total);
 }
 
-__host__ __device__ __forceinline__ double dr_tau_of_s(double s) {
-  // inverse softplus: ln(e^s - 1)
-  return s > 30.0 ? s : log(expm1(s));
-}
-
-__host__ __device__ __forceinline__ double dr_s_of_tau(double t) {
-  return t > 30.0 ? t : log1p(exp(t));
-}
-
 // ln E[(z + eps)^-4], eps ~ N(0,1), by probabilists' Gauss-Hermite nodes
-__host__ __device__ __forceinline__ double dr_gh_ln_moment(double z, const double* ghx,
-                                                            const double* ghw) {
+// (the tail formula is used for z >= 8 only, so z + x_k > 2 for every node)
+__device__ __forceinline__ double dr_gh_ln_moment(double z, const double* ghx, const double* ghw) {
   double acc = 0.0;
   for (int k = 0; k < kGH; ++k) {
-    double y = 1.0 / (z + ghx[k]);
-    double y2 = y * y;
-    acc += ghw[k] * y2 * y2;
+    const double y = dr_rcp(z + ghx[k]);
+    const double y2 = y * y;
+    acc = fma(ghw[k], y2 * y2, acc);
   }
-  return log(acc);
+  return dr_log(acc);
 }
 
 // value from the tail formula (peak well inside, Gaussian in y)
-__host__ __device__ __forceinline__ double dr_ln_tail(double z, double s, const double* ghx,
-                                                       const double* ghw) {
+__device__ __forceinline__ double dr_ln_tail(double z, double s, const double* ghx,
+                                             const double* ghw) {
   const double kLn3Sqrt2Pi = 2.0175508218727823;   // ln(3 sqrt(2 pi))
-  return kLn3Sqrt2Pi + 3.0 * log(s) + 0.5 * z * z + dr_gh_ln_moment(z, ghx, ghw);
+  return kLn3Sqrt2Pi + 3.0 * dr_log(s) + 0.5 * z * z + dr_gh_ln_moment(z, ghx, ghw);
 }
 
 // tail formula valid: Gaussian peak at y ~ z at least 8 sigma above the
 // boundary y = s and the boundary region negligible next to it
-__host__ __device__ __forceinline__ bool dr_tail_ok(double z, double s) {
+__device__ __forceinline__ bool dr_tail_ok(double z, double s) {
   if (z < 8.0 || z - s < 8.0) return false;
-  double gap = 0.5 * (z - s) * (z - s) - 4.0 * log(z / s);
+  const double gap = 0.5 * (z - s) * (z - s) - 4.0 * dr_log(z / s);
   return gap >= 40.0;
 }
 
 // 4x4 cubic Lagrange interpolation in the table
-__host__ __device__ __forceinline__ void dr_lagrange4(double t, double* c) {
+__device__ __forceinline__ void dr_lagrange4(double t, double* c) {
   // nodes at -1, 0, 1, 2; t in [0, 1)
-  double tm1 = t - 1.0, tm2 = t - 2.0, tp1 = t + 1.0;
-  c[0] = -t * tm1 * tm2 / 6.0;
-  c[1] = tp1 * tm1 * tm2 / 2.0;
-  c[2] = -tp1 * t * tm2 / 2.0;
-  c[3] = tp1 * t * tm1 / 6.0;
+  const double tm1 = t - 1.0, tm2 = t - 2.0, tp1 = t + 1.0;
+  c[0] = -t * tm1 * tm2 * (1.0 / 6.0);
+  c[1] = tp1 * tm1 * tm2 * 0.5;
+  c[2] = -tp1 * t * tm2 * 0.5;
+  c[3] = tp1 * t * tm1 * (1.0 / 6.0);
 }
 
-__host__ __device__ __forceinline__ bool dr_table_lookup(const double* tab, const DistTableGeom& g,
-                                                         double z, double tau, double* out) {
-  // segments are contiguous: count the upper edges at or below z
-  if (!(z >= g.zlo[0] && z < g.zhi[kDrSeg - 1])) return false;
-  int k = 0;
-  for (int q = 0; q + 1 < kDrSeg; ++q) k += z >= g.zhi[q] ? 1 : 0;
-  double fz = (z - g.zs0[k]) * g.ihz[k], ft = (tau - g.t0) * g.iht;
-  int jz = (int)floor(fz), jt = (int)floor(ft);
-  if (jz < 1 || jz > g.nz[k] - 3 || jt < 1 || jt > g.nt - 3) return false;
-  double cz[4], ct[4];
-  dr_lagrange4(fz - jz, cz);
-  dr_lagrange4(ft - jt, ct);
+// ln Lbar at (z, s) from the table; false when (z, s) lies outside it
+__device__ __forceinline__ bool dr_table_lookup(const double* tab, double z, double s,
+                                                double* out) {
+  constexpr DistTableGeom g = kDrGeom;
+  const double w = s < 1.0 ? dr_log(s) : s - 1.0;
+  if (!(z >= g.zlo[0] && z < g.zhi[kDrSeg - 1] && w >= g.wlo[0] && w < g.whi[kDrRowSeg - 1]))
+    return false;
+  // each axis' segment: segments are contiguous, so the last one whose lower
+  // edge is at or below the coordinate.  The position is formed from the
+  // edge and the reciprocal step, which are exact in binary (the guard lines
+  // add 2), so the selected constants are immediate operands.
+  double zlo = g.zlo[0], ihz = g.ihz[0], wlo = g.wlo[0], ihw = g.ihw[0];
+  int nz = g.nz[0], off = g.off[0], nw = g.nw[0], roff = g.roff[0];
+#pragma unroll
+  for (int q = 1; q < kDrSeg; ++q) {
+    if (z >= g.zlo[q]) {
+      zlo = g.zlo[q];
+      ihz = g.ihz[q];
+      nz = g.nz[q];
+      off = g.off[q];
+    }
+  }
+#pragma unroll
+  for (int q = 1; q < kDrRowSeg; ++q) {
+    if (w >= g.wlo[q]) {
+      wlo = g.wlo[q];
+      ihw = g.ihw[q];
+      nw = g.nw[q];
+      roff = g.roff[q];
+    }
+  }
+  const double fz = fma(z - zlo, ihz, 2.0), fw = fma(w - wlo, ihw, 2.0);
+  const double flz = floor(fz), flw = floor(fw);
+  const int jz = (int)flz, jw = (int)flw;
+  if (jz < 1 || jz > nz - 3 || jw < 1 || jw > nw - 3) return false;
+  double cz[4], cw[4];
+  dr_lagrange4(fz - flz, cz);
+  dr_lagrange4(fw - flw, cw);
+  const double* base = tab + ((roff + jw - 1) * g.ncol + off + (jz - 1));
   double v = 0.0;
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const double* row = tab + (size_t)(jt - 1 + a) * g.ncol + g.off[k] + (jz - 1);
-    double rv = cz[0] * row[0] + cz[1] * row[1] + cz[2] * row[2] + cz[3] * row[3];
-    v += ct[a] * rv;
+    const double* row = base + a * g.ncol;
+    const double rv = cz[0] * row[0] + cz[1] * row[1] + cz[2] * row[2] + cz[3] * row[3];
+    v = fma(cw[a], rv, v);
   }
   *out = v;
   return true;
 }
 
+// z and s of a triple: z = dh / sqrt(hh), s = sqrt(hh) d0 / D_max (hh > 0)
+__device__ __forceinline__ void dr_zs(double dh, double hh, double d0_over_dmax, double& z,
+                                      double& s) {
+  const double sq = sqrt(hh);
+  z = dh / sq;
+  s = sq * d0_over_dmax;
+}
+
 // full rule: ln Lbar for one triple given dh, hh at distance d0
-__host__ __device__ inline double dr_ln_marg(double dh, double hh, double d0_over_dmax,
-                                             const double* tab, const DistTableGeom& g,
-                                             const double* ghx, const double* ghw) {
+__device__ __attribute__((always_inline)) inline double dr_ln_marg_body(
+    double dh, double hh, double d0_over_dmax, const double* tab, const double* ghx,
+    const double* ghw) {
   if (!(hh > 0.0)) return 0.0;
-  double sq = sqrt(hh);
-  double z = dh / sq, s = sq * d0_over_dmax;
+  double z, s;
+  dr_zs(dh, hh, d0_over_dmax, z, s);
   if (s < kDrSMin) {
     // Lbar = 1 + 1.5 z s + O(s^2) plus the peak contribution if any
     double v = 1.5 * z * s;
@@ -290,26 +379,28 @@ __host__ __device__ inline double dr_ln_marg(double dh, double hh, double d0_ove
   }
   if (dr_tail_ok(z, s)) return dr_ln_tail(z, s, ghx, ghw);
   double v;
-  if (dr_table_lookup(tab, g, z, dr_tau_of_s(s), &v)) return v;
+  if (dr_table_lookup(tab, z, s, &v)) return v;
   return dr_ln_exact(z, s);
 }
 
-// The same rule with its most frequent case inlined: a triple that the
-// full rule would read from the table is read here (the same arithmetic, so
-// the same value); any other calls the full rule.  For callers that
-// evaluate many triples in a loop.
-__host__ __device__ __attribute__((always_inline)) inline double dr_ln_marg_inl(
-    double dh, double hh, double d0_over_dmax, const double* tab, const DistTableGeom& g,
-    const double* ghx, const double* ghw) {
-  if (hh > 0.0) {
-    const double sq = sqrt(hh);
-    const double z = dh / sq, s = sq * d0_over_dmax;
-    if (s >= kDrSMin && !dr_tail_ok(z, s)) {
-      double v;
-      if (dr_table_lookup(tab, g, z, dr_tau_of_s(s), &v)) return v;
-    }
-  }
-  return dr_ln_marg(dh, hh, d0_over_dmax, tab, g, ghx, ghw);
+// The rule as a function (not inlined): for callers with few triples per
+// lane, where its registers would otherwise add to their own.
+__device__ __attribute__((noinline)) inline double dr_ln_marg(double dh, double hh,
+                                                              double d0_over_dmax,
+                                                              const double* tab,
+                                                              const double* ghx,
+                                                              const double* ghw) {
+  return dr_ln_marg_body(dh, hh, d0_over_dmax, tab, ghx, ghw);
+}
+
+// The rule inlined (the same arithmetic, so the same values), only the
+// adaptive quadrature called: for kernels whose lanes evaluate many triples
+// in a loop (a call there makes every value live across it occupy a saved
+// register).
+__device__ __attribute__((always_inline)) inline double dr_ln_marg_inl(
+    double dh, double hh, double d0_over_dmax, const double* tab, const double* ghx,
+    const double* ghw) {
+  return dr_ln_marg_body(dh, hh, d0_over_dmax, tab, ghx, ghw);
 }
 
 }  // namespace dotpe

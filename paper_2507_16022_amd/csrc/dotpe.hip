@@ -99,8 +99,7 @@ struct dotpe_ctx {
   std::atomic<uint64_t> bytes{0};   // serving slot threads also release through it
   uint64_t own_bytes = 0;    // the context's own tables (not charged to the budget)
   double* dist_tab = nullptr;
-  DistParams* dist_prm = nullptr;   // device copy of geom, ghx, ghw
-  DistTableGeom geom{};
+  DistParams* dist_prm = nullptr;   // device copy of the Gauss-Hermite nodes
   double ghx[kGH], ghw[kGH];
 };
 
@@ -584,9 +583,8 @@ int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
     delete ctx;
     return fail(DOTPE_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
   }
-  ctx->geom = dr_make_geom();
-  DistTableGeom& g = ctx->geom;
-  size_t ntab = (size_t)g.ncol * g.nt;
+  constexpr DistTableGeom g = kDrGeom;
+  size_t ntab = (size_t)g.ncol * g.nrow;
   ctx->budget = 0;
   int rc = dev_alloc(ctx, (void**)&ctx->dist_tab, ntab * sizeof(double) + sizeof(DistParams),
                      nullptr, nullptr);
@@ -602,7 +600,6 @@ int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
                      ctx->stream, ctx->dist_tab, g);
   gauss_hermite(kGH, ctx->ghx, ctx->ghw);
   DistParams prm;
-  prm.geom = g;
   for (int k = 0; k < kGH; ++k) {
     prm.ghx[k] = ctx->ghx[k];
     prm.ghw[k] = ctx->ghw[k];
@@ -1607,6 +1604,26 @@ int dotpe_preselect(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_preselect_
   return DOTPE_OK;
 }
 
+// Doubles of workspace scan_inclusive needs for n values: the block totals
+// of every level.
+static int64_t scan_tmp_size(int64_t n) {
+  int64_t t = 0;
+  for (int64_t nb = (n + 1023) / 1024; nb > 1; nb = (nb + 1023) / 1024) t += nb;
+  return t + 1;
+}
+
+// Inclusive running sum of x[0, n) in place on stream s (tmp: scan_tmp_size(n)
+// doubles): blocks of 1024 scanned, their totals scanned the same way one
+// level up, the totals before each block added.
+static void scan_inclusive(double* x, int64_t n, double* tmp, hipStream_t s) {
+  const int64_t nb = (n + 1023) / 1024;
+  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(1024), 0, s, x, n, tmp);
+  if (nb > 1) {
+    scan_inclusive(tmp, nb, tmp + nb, s);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(1024), 0, s, x, n, (const double*)tmp);
+  }
+}
+
 int dotpe_sample_posterior(dotpe_ctx* ctx, dotpe_event* ev, int64_t n_samples, double u0,
                            uint64_t seed, dotpe_posterior_sample* out, int64_t capacity,
                            int64_t* n_out) {
@@ -1640,7 +1657,7 @@ int dotpe_sample_posterior(dotpe_ctx* ctx, dotpe_event* ev, int64_t n_samples, d
     }
   } release{ctx, &bufs, &held, s};
   auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &bufs, &held); };
-  const int64_t nt = a.n_tiles, nb = (nt + 1023) / 1024;
+  const int64_t nt = a.n_tiles, nb = scan_tmp_size(nt);
   double *cum = nullptr, *blk = nullptr, *res = nullptr, *smp = nullptr;
   int *tile = nullptr, *list = nullptr;
   int64_t *first = nullptr, *n_u_dev = nullptr;
@@ -1652,9 +1669,7 @@ int dotpe_sample_posterior(dotpe_ctx* ctx, dotpe_event* ev, int64_t n_samples, d
     return rc;
   hipLaunchKernelGGL(k_tile_mass, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, ev->partials,
                      ev->final_out, nt, cum);
-  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(1024), 0, s, cum, nt, blk);
-  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(64), 0, s, blk, nb);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(1024), 0, s, cum, nt, blk);
+  scan_inclusive(cum, nt, blk, s);
   hipLaunchKernelGGL(k_place_draws, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, cum, nt, ns,
                      u0, tile, res);
   hipLaunchKernelGGL(k_group_draws, dim3(1), dim3(64), 0, s, tile, ns, list, first, n_u_dev);
@@ -1800,8 +1815,9 @@ int dotpe_extrinsic_samples(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_ex
   auto alloc = [&](void** p, size_t n) { return dev_alloc(ctx, p, n, &bufs, &held); };
   void *dd = nullptr, *ww = nullptr, *tt = nullptr, *ci = nullptr, *st = nullptr;
   double *ml = nullptr, *rmax = nullptr, *tab = nullptr, *lnZ = nullptr, *mix = nullptr,
-         *blk = nullptr, *draws = nullptr, *stats = nullptr;
-  const int64_t nblk = (CSJ + 1023) / 1024;
+         *blk = nullptr, *draws = nullptr, *stats = nullptr, *lse_part = nullptr;
+  unsigned long long* n_supp = nullptr;
+  const int64_t nblk = scan_tmp_size(CSJ);
   if ((rc = alloc(&dd, (size_t)nk * nb * 16)) || (rc = alloc(&ww, (size_t)nk * nb * 8)) ||
       (rc = alloc(&tt, (size_t)nk * 8)) || (rc = alloc(&ci, (size_t)C * 8)) ||
       (rc = alloc((void**)&a.B0, (size_t)n_grid * a.K2p * 2)) ||
@@ -1816,7 +1832,9 @@ int dotpe_extrinsic_samples(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_ex
       (rc = alloc((void**)&tab, (size_t)CSJ * 8)) || (rc = alloc((void**)&lnZ, (size_t)C * 8)) ||
       (rc = alloc((void**)&mix, (size_t)SJ * 8)) || (rc = alloc((void**)&blk, (size_t)nblk * 8)) ||
       (rc = alloc((void**)&draws, (size_t)d->n_samples * 7 * 8)) ||
-      (rc = alloc((void**)&stats, 16)))
+      (rc = alloc((void**)&stats, 16)) ||
+      (rc = alloc((void**)&lse_part, (size_t)C * kPropParts * 16)) ||
+      (rc = alloc((void**)&n_supp, 8)))
     return rc;
   a.d = (const double2*)dd;
   a.w = (const double*)ww;
@@ -1865,16 +1883,19 @@ int dotpe_extrinsic_samples(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_ex
   hipLaunchKernelGGL(k_prop_max, dim3((unsigned)((C * nk + 63) / 64)), dim3(64), 0, s, ml, g, rmax);
   hipLaunchKernelGGL(k_prop_table, dim3((unsigned)((CSJ + 255) / 256)), dim3(256), 0, s, ml, rmax, g,
                      tab);
-  hipLaunchKernelGGL(k_prop_lse, dim3((unsigned)C), dim3(256), 0, s, tab, g, lnZ);
+  hipLaunchKernelGGL(k_prop_lse_part, dim3((unsigned)kPropParts, (unsigned)C), dim3(256), 0, s, tab,
+                     g, lse_part);
+  hipLaunchKernelGGL(k_prop_lse, dim3((unsigned)C), dim3(256), 0, s, (const double*)lse_part, lnZ);
   hipLaunchKernelGGL(k_prop_prob, dim3((unsigned)((SJ + 255) / 256)), dim3(256), 0, s, tab, lnZ, g,
                      mix);
-  hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nblk), dim3(1024), 0, s, tab, CSJ, blk);
-  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(64), 0, s, blk, nblk);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nblk), dim3(1024), 0, s, tab, CSJ, (const double*)blk);
+  scan_inclusive(tab, CSJ, blk, s);
   hipLaunchKernelGGL(k_prop_draw, dim3((unsigned)((d->n_samples + 255) / 256)), dim3(256), 0, s,
                      (const double*)tab, (const double*)mix, g, d->n_samples, d->seed, draws);
+  HIP_OK(hipMemsetAsync(n_supp, 0, 8, s));
+  hipLaunchKernelGGL(k_count_support, dim3((unsigned)((SJ + 255) / 256)), dim3(256), 0, s,
+                     (const double*)mix, SJ, n_supp);
   hipLaunchKernelGGL(k_prop_stats, dim3(1), dim3(256), 0, s, (const double*)draws, d->n_samples,
-                     (const double*)mix, SJ, stats);
+                     (const unsigned long long*)n_supp, SJ, stats);
   HIP_OK(hipGetLastError());
   HIP_OK(hipEventRecord(e1, s));
   std::vector<double> h((size_t)d->n_samples * 7);

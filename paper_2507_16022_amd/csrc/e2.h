@@ -104,7 +104,7 @@ struct PairCoef {
 };
 
 template <int PREC, int G>
-__global__ __launch_bounds__(256) void k_e2_tiles(FusedArgs a) {
+__global__ __launch_bounds__(256, 3) void k_e2_tiles(FusedArgs a) {
   typedef Tile<PREC> TL;
   typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_e2_tiles(FusedArgs a) {
       lse.init();
       double best = -INFINITY, mlmax = 0.0;
       int ob = 0;
-      pair_phases<kEvidence, G, false>(a, lds_cs, dp, row0 + tr, e, X, S0, Sr, Si, lnw, thr_ml, 0, 1,
+      pair_phases<kEvidence, G, true>(a, lds_cs, dp, row0 + tr, e, X, S0, Sr, Si, lnw, thr_ml, 0, 1,
                                       ev, lse, best, ob, mlmax);
       ev.ml_max = fmax(ev.ml_max, mlmax);
       if (lse.m == -INFINITY) continue;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void k_sample_tiles(FusedArgs a) {
         if (o < a.n_phi) {
           phase_dh_hh<G>(a, lds_cs, X, S0, Sr, Si, o, dh_o[h], hh_o[h]);
           const bool keep = thr_ml <= 0.0 || (dh_o[h] > 0.0 && dh_o[h] * dh_o[h] >= 2.0 * thr_ml * hh_o[h]);
-          if (keep) v_o[h] = dr_ln_marg(dh_o[h], hh_o[h], a.r0, a.dist.tab, dp.geom, dp.ghx, dp.ghw);
+          if (keep) v_o[h] = dr_ln_marg(dh_o[h], hh_o[h], a.r0, a.dist.tab, dp.ghx, dp.ghw);
         }
       }
       const double vmax = wave_max(fmax(v_o[0], v_o[1]));

@@ -379,8 +379,8 @@ __device__ void pair_phases(const FusedArgs& a, const double* lds_cs, const Dist
       continue;
     }
     double v;
-    if constexpr (INL) v = dr_ln_marg_inl(dh, hh, a.r0, a.dist.tab, dp.geom, dp.ghx, dp.ghw);
-    else v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, dp.geom, dp.ghx, dp.ghw);
+    if constexpr (INL) v = dr_ln_marg_inl(dh, hh, a.r0, a.dist.tab, dp.ghx, dp.ghw);
+    else v = dr_ln_marg(dh, hh, a.r0, a.dist.tab, dp.ghx, dp.ghw);
     if (v > best) { best = v; o_best = o; }
     lse.add(v);
     if (!EVAL) ev.n_marg += 1;

@@ -1,6 +1,7 @@
-// Instantiations of the fused likelihood kernel for one precision and one
-// number of m groups, chosen at compile time by DOTPE_INST_PREC (0 FP64,
-// 1 FP16x2, 2 BF16x2) and DOTPE_INST_G (1..4).
+// Instantiations of the fused likelihood kernel and the bound pass for one
+// precision and one number of m groups, chosen at compile time by
+// DOTPE_INST_PREC (0 FP64, 1 FP16x2, 2 BF16x2) and DOTPE_INST_G (1..4).  The
+// marginalisation kernels of the same pair are in marg_inst.hip.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -15,6 +16,10 @@
 #endif
 
 namespace dotpe {
+
+#define DOTPE_MARG_CAT4(a, b, c, d) a##b##c##d
+#define DOTPE_MARG_NAME(P, G) DOTPE_MARG_CAT4(launch_marg_p, P, _g, G)
+
 namespace {
 
 template <int PREC, int G, int MODE, bool FAST>
@@ -54,28 +59,6 @@ hipError_t launch_bound(const FusedArgs& a, int64_t grid, hipStream_t s) {
 }
 
 template <int PREC, int G>
-hipError_t launch_survivors(const FusedArgs& a, int64_t grid, hipStream_t s) {
-  if constexpr (PREC == kFP64) {
-    return hipErrorInvalidValue;
-  } else {
-    hipLaunchKernelGGL((k_survivors<PREC, G>), dim3((unsigned)grid), dim3(256), 0, s, a);
-    return hipGetLastError();
-  }
-}
-
-template <int PREC, int G>
-hipError_t launch_e2(const FusedArgs& a, int64_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_e2_tiles<PREC, G>), dim3((unsigned)grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int PREC, int G>
-hipError_t launch_sample(const FusedArgs& a, int64_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_sample_tiles<PREC, G>), dim3((unsigned)grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int PREC, int G>
 hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hipStream_t s) {
   switch (mode) {
     case kEval: return launch_one<PREC, G, kEval, false>(a, grid, s);
@@ -85,10 +68,10 @@ hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hip
       // coefficient route
       return fast ? launch_one<PREC, G, kEvidence, true>(a, grid, s) : hipErrorInvalidValue;
     case kBound: return launch_bound<PREC, G>(a, grid, s);
-    case kSurvivors: return launch_survivors<PREC, G>(a, grid, s);
     case kCoef: return launch_one<PREC, G, kCoef, false>(a, grid, s);
-    case kE2: return launch_e2<PREC, G>(a, grid, s);
-    case kSample: return launch_sample<PREC, G>(a, grid, s);
+    case kSurvivors:
+    case kE2:
+    case kSample: return DOTPE_MARG_NAME(DOTPE_INST_PREC, DOTPE_INST_G)(mode, a, grid, s);
   }
   return hipErrorInvalidValue;
 }

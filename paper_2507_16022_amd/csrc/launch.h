@@ -1,7 +1,8 @@
 // Launchers of the fused likelihood kernel, one per (precision, number of m
-// groups).  Each is compiled in its own translation unit (fused_inst.hip
-// built with DOTPE_INST_PREC and DOTPE_INST_G), so the library's kernels
-// compile in parallel; the host runtime picks one from the table below.
+// groups).  Each is compiled in its own translation units (fused_inst.hip and
+// marg_inst.hip built with DOTPE_INST_PREC and DOTPE_INST_G), so the
+// library's kernels compile in parallel; the host runtime picks one from the
+// table below.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +39,24 @@ DOTPE_FUSED_DECL(2, 2)
 DOTPE_FUSED_DECL(2, 3)
 DOTPE_FUSED_DECL(2, 4)
 #undef DOTPE_FUSED_DECL
+
+// the survivor pass, kE2 and kSample (marg_inst.hip), called by the
+// launchers above
+#define DOTPE_MARG_DECL(P, G)                                                               \
+  hipError_t launch_marg_p##P##_g##G(int mode, const FusedArgs& a, int64_t grid, hipStream_t s);
+DOTPE_MARG_DECL(0, 1)
+DOTPE_MARG_DECL(0, 2)
+DOTPE_MARG_DECL(0, 3)
+DOTPE_MARG_DECL(0, 4)
+DOTPE_MARG_DECL(1, 1)
+DOTPE_MARG_DECL(1, 2)
+DOTPE_MARG_DECL(1, 3)
+DOTPE_MARG_DECL(1, 4)
+DOTPE_MARG_DECL(2, 1)
+DOTPE_MARG_DECL(2, 2)
+DOTPE_MARG_DECL(2, 3)
+DOTPE_MARG_DECL(2, 4)
+#undef DOTPE_MARG_DECL
 
 // launcher for precision prec (kFP64, kFP16X2, kBF16X2) and G m groups
 // (1..kMaxG), or nullptr

@@ -12,17 +12,19 @@ namespace dotpe {
 // ---------------------------------------------------------------------------
 __global__ void k_build_dist_table(double* tab, DistTableGeom g) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)g.ncol * g.nt) return;
-  int col = (int)(idx % g.ncol), jt = (int)(idx / g.ncol);
-  double z = dr_col_z(g, col), t = g.t0 + jt * g.ht;
-  tab[idx] = dr_ln_exact(z, dr_s_of_tau(t));
+  if (idx >= (int64_t)g.ncol * g.nrow) return;
+  const int col = (int)(idx % g.ncol), row = (int)(idx / g.ncol);
+  int k = 0;
+  while (k + 1 < kDrRowSeg && row >= g.roff[k + 1]) ++k;
+  const double w = g.wlo[k] + (row - g.roff[k] - 2) / g.ihw[k];   // two guard rows below the edge
+  tab[idx] = dr_ln_exact(dr_col_z(g, col), g.wlog[k] ? exp(w) : 1.0 + w);
 }
 
 __global__ void k_debug_distmarg(int64_t n, const double* dh, const double* hh, double r0,
                                  DistArgs da, double* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = dr_ln_marg(dh[i], hh[i], r0, da.tab, da.prm->geom, da.prm->ghx, da.prm->ghw);
+  out[i] = dr_ln_marg(dh[i], hh[i], r0, da.tab, da.prm->ghx, da.prm->ghw);
 }
 
 // Element offset of (row i, position k) in an operand with K positions per
@@ -443,39 +445,65 @@ __global__ void k_prop_table(const double* __restrict__ ml, const double* __rest
   lnW[idx] = acc;
 }
 
-// ln Z_c = LSE over the cells of ln W_c: a block per c
-__global__ void k_prop_lse(const double* __restrict__ lnW, PropGeom g, double* __restrict__ lnZ) {
-  __shared__ double sm[256], ss[256];
-  const int c = blockIdx.x;
-  const int64_t SJ = (int64_t)g.S * g.J;
-  const double* x = lnW + (int64_t)c * SJ;
-  double m = -INFINITY, s = 0.0;
-  for (int64_t t = threadIdx.x; t < SJ; t += 256) {
-    const double v = x[t];
-    if (v == -INFINITY) continue;
-    if (v > m) {
-      s = s * exp(m - v) + 1.0;
-      m = v;
-    } else {
-      s += exp(v - m);
-    }
+// ln Z_c = LSE over the cells of ln W_c, in two steps: blocks (part, c) each
+// reduce one of kPropParts contiguous ranges of component c's cells to (max,
+// sum of exp(x - max)), lanes then threads in a fixed tree order; then a
+// block per c merges its parts the same way.
+constexpr int kPropParts = 256;
+
+__device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
+  if (m2 == -INFINITY) return;
+  if (m2 > m) {
+    s = s * exp(m - m2) + s2;
+    m = m2;
+  } else {
+    s += s2 * exp(m2 - m);
   }
+}
+
+// (m, s) of the 256 threads' (m, s) in LDS, tree order; thread 0 gets them
+__device__ __forceinline__ void lse_block_256(double* sm, double* ss, double& m, double& s) {
   sm[threadIdx.x] = m;
   ss[threadIdx.x] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double M = -INFINITY, Ssum = 0.0;
-    for (int t = 0; t < 256; ++t) {
-      if (sm[t] == -INFINITY) continue;
-      if (sm[t] > M) {
-        Ssum = Ssum * exp(M - sm[t]) + ss[t];
-        M = sm[t];
-      } else {
-        Ssum += ss[t] * exp(sm[t] - M);
-      }
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      double a = sm[threadIdx.x], b = ss[threadIdx.x];
+      lse_merge(a, b, sm[threadIdx.x + k], ss[threadIdx.x + k]);
+      sm[threadIdx.x] = a;
+      ss[threadIdx.x] = b;
     }
-    lnZ[c] = M == -INFINITY ? -INFINITY : M + log(Ssum);
+    __syncthreads();
   }
+  m = sm[0];
+  s = ss[0];
+}
+
+__global__ __launch_bounds__(256) void k_prop_lse_part(const double* __restrict__ lnW, PropGeom g,
+                                                        double* __restrict__ part) {
+  __shared__ double sm[256], ss[256];
+  const int c = blockIdx.y, p = blockIdx.x;
+  const int64_t SJ = (int64_t)g.S * g.J, per = (SJ + kPropParts - 1) / kPropParts;
+  const int64_t lo = p * per, hi = min(SJ, lo + per);
+  const double* x = lnW + (int64_t)c * SJ;
+  double m = -INFINITY, s = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += 256) lse_merge(m, s, x[t], 1.0);
+  lse_block_256(sm, ss, m, s);
+  if (threadIdx.x == 0) {
+    part[2 * ((int64_t)c * kPropParts + p)] = m;
+    part[2 * ((int64_t)c * kPropParts + p) + 1] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_prop_lse(const double* __restrict__ part,
+                                                   double* __restrict__ lnZ) {
+  static_assert(kPropParts == 256, "one part per thread");
+  __shared__ double sm[256], ss[256];
+  const int c = blockIdx.x;
+  double m = part[2 * ((int64_t)c * kPropParts + threadIdx.x)];
+  double s = part[2 * ((int64_t)c * kPropParts + threadIdx.x) + 1];
+  lse_block_256(sm, ss, m, s);
+  if (threadIdx.x == 0) lnZ[c] = m == -INFINITY ? -INFINITY : m + log(s);
 }
 
 // P_c(cell) = W_c / Z_c (in place over ln W), and the mixture (1/C) sum_c P_c
@@ -526,11 +554,20 @@ __global__ void k_prop_draw(const double* __restrict__ cum, const double* __rest
   o[6] = (double)lo;
 }
 
+// cells of the mixture's support (mix > 0), counted into *n (zeroed before)
+__global__ __launch_bounds__(256) void k_count_support(const double* __restrict__ mix, int64_t SJ,
+                                                       unsigned long long* __restrict__ n) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const unsigned long long v = __ballot(t < SJ && mix[t] > 0.0);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(n, (unsigned long long)__popcll(v));
+}
+
 // N_eff over the draws' weights and the prior mass of the mixture's support:
-// one block; st[0] = (sum w)^2 / sum w^2, st[1] = support
-__global__ void k_prop_stats(const double* __restrict__ out, int64_t n_s, const double* __restrict__ mix,
-                             int64_t SJ, double* __restrict__ st) {
-  __shared__ double a[256], b[256], m[256], cnt[256];
+// one block; st[0] = (sum w)^2 / sum w^2, st[1] = support (from the count)
+__global__ void k_prop_stats(const double* __restrict__ out, int64_t n_s,
+                             const unsigned long long* __restrict__ n_support, int64_t SJ,
+                             double* __restrict__ st) {
+  __shared__ double a[256], b[256], m[256];
   double mx = -INFINITY;
   for (int64_t q = threadIdx.x; q < n_s; q += 256) mx = fmax(mx, out[7 * q + 5]);
   m[threadIdx.x] = mx;
@@ -542,26 +579,23 @@ __global__ void k_prop_stats(const double* __restrict__ out, int64_t n_s, const 
   }
   __syncthreads();
   const double M = m[0];
-  double s1 = 0.0, s2 = 0.0, ns = 0.0;
+  double s1 = 0.0, s2 = 0.0;
   for (int64_t q = threadIdx.x; q < n_s; q += 256) {
     const double v = exp(out[7 * q + 5] - M);
     s1 += v;
     s2 += v * v;
   }
-  for (int64_t t = threadIdx.x; t < SJ; t += 256) ns += mix[t] > 0.0 ? 1.0 : 0.0;
   a[threadIdx.x] = s1;
   b[threadIdx.x] = s2;
-  cnt[threadIdx.x] = ns;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double A = 0.0, B = 0.0, N = 0.0;
+    double A = 0.0, B = 0.0;
     for (int t = 0; t < 256; ++t) {
       A += a[t];
       B += b[t];
-      N += cnt[t];
     }
     st[0] = A * A / B;
-    st[1] = N / (double)SJ;
+    st[1] = (double)*n_support / (double)SJ;
   }
 }
 
@@ -931,9 +965,10 @@ __global__ void k_tile_mass(const double* __restrict__ partials, const double* _
   mass[t] = (m > -INFINITY && M > -INFINITY) ? exp(m - M) * s : 0.0;
 }
 
-// inclusive running sum in place, in three steps over blocks of 1024: each
-// block's own running sum (its total to blk), the blocks' offsets (one
-// thread, in order), the offsets added
+// Inclusive running sum in place over blocks of 1024 (scan_inclusive on the
+// host drives it): each block's own running sum, in LDS, its total to blk;
+// the blocks' totals are summed the same way, one level up, and each block
+// then adds the running total before it.
 __global__ void k_scan_block(double* __restrict__ x, int64_t n, double* __restrict__ blk) {
   __shared__ double sh[1024];
   const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
@@ -948,18 +983,10 @@ __global__ void k_scan_block(double* __restrict__ x, int64_t n, double* __restri
   if (i < n) x[i] = sh[threadIdx.x];
   if (threadIdx.x == 1023) blk[blockIdx.x] = sh[1023];
 }
-__global__ void k_scan_offsets(double* __restrict__ blk, int64_t nb) {
-  if (threadIdx.x != 0) return;
-  double run = 0.0;
-  for (int64_t b = 0; b < nb; ++b) {
-    const double v = blk[b];
-    blk[b] = run;
-    run += v;
-  }
-}
+// blk: the blocks' inclusive running totals
 __global__ void k_scan_add(double* __restrict__ x, int64_t n, const double* __restrict__ blk) {
   const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
-  if (i < n) x[i] += blk[blockIdx.x];
+  if (blockIdx.x > 0 && i < n) x[i] += blk[blockIdx.x - 1];
 }
 
 // systematic draws t_s = (s + u0) W / n_s (W = the total mass, cum[n - 1])
