@@ -318,18 +318,29 @@ def serving_leg(dotpe, W, ctx, bank, n_bank, args):
                           sub_start=start, sub_count=n_sub, cut_delta=args.cut, top_k=256,
                           topk_window=args.topk_window))
         pairs.append(n_sub * n_ext)
-    srv = dotpe.Server(ctx, bank, n_slots=args.serve_slots, pool_bytes=args.serve_pool_gib << 30)
     n_cal = min(64, n)
-    t0 = time.perf_counter()
-    cal = [srv.submit(**specs[q]) for q in range(n_cal)]
-    for t in cal:
-        srv.wait(t)
-    sat_s = time.perf_counter() - t0
-    sat_rate = n_cal / sat_s                                        # events per second
-    sat_pairs = float(np.sum(pairs[:n_cal])) / sat_s
-    log(f"serving: saturated {sat_rate:.1f} events/s ({sat_pairs:.3g} pairs/s) over {n_cal} events")
-    out = {"events": n, "slots": args.serve_slots, "saturated_events_per_s": sat_rate,
-           "saturated_pairs_per_s": sat_pairs, "pairs_total": int(np.sum(pairs)), "loads": []}
+
+    def saturated(max_batch):
+        srv = dotpe.Server(ctx, bank, n_slots=args.serve_slots,
+                           pool_bytes=args.serve_pool_gib << 30, max_batch=max_batch)
+        t0 = time.perf_counter()
+        cal = [srv.submit(**specs[q]) for q in range(n_cal)]
+        batch = [srv.wait(t)[1]["batch"] for t in cal]
+        sat_s = time.perf_counter() - t0
+        return srv, n_cal / sat_s, float(np.sum(pairs[:n_cal])) / sat_s, float(np.mean(batch))
+
+    # one event per launch (no packing) for comparison, then the packed server
+    srv, sat1, sat1_pairs, _ = saturated(1)
+    srv.close()
+    log(f"serving, one event per launch: saturated {sat1:.1f} events/s ({sat1_pairs:.3g} pairs/s)")
+    srv, sat_rate, sat_pairs, mean_batch = saturated(args.serve_batch)
+    log(f"serving: saturated {sat_rate:.1f} events/s ({sat_pairs:.3g} pairs/s) over {n_cal} events, "
+        f"{mean_batch:.2f} events per batch on average")
+    out = {"events": n, "slots": args.serve_slots, "max_batch": args.serve_batch,
+           "saturated_events_per_s": sat_rate, "saturated_pairs_per_s": sat_pairs,
+           "saturated_mean_batch": mean_batch,
+           "saturated_events_per_s_unpacked": sat1, "saturated_pairs_per_s_unpacked": sat1_pairs,
+           "pairs_total": int(np.sum(pairs)), "loads": []}
     for load in args.serve_loads:
         lam = load * sat_rate
         arrivals = np.cumsum(rng.exponential(1.0 / lam, n))
@@ -349,11 +360,12 @@ def serving_leg(dotpe, W, ctx, bank, n_bank, args):
         span_s = (max(i["t_done_ms"] for i in infos) - min(i["t_submit_ms"] for i in infos)) / 1e3
         row = {"offered_load": load, "arrival_rate_per_s": lam,
                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-               "mean_queue_ms": float(queue.mean()), "pairs_per_s": float(np.sum(pairs)) / span_s}
+               "mean_queue_ms": float(queue.mean()), "pairs_per_s": float(np.sum(pairs)) / span_s,
+               "mean_batch": float(np.mean([i["batch"] for i in infos]))}
         out["loads"].append(row)
         log(f"serving at {load:.1f} x saturation ({lam:.1f} events/s): p50 {row['p50_ms']:.1f} ms, "
             f"p99 {row['p99_ms']:.1f} ms, mean queue {row['mean_queue_ms']:.1f} ms, "
-            f"{row['pairs_per_s']:.3g} pairs/s")
+            f"{row['pairs_per_s']:.3g} pairs/s, {row['mean_batch']:.2f} events per batch")
     srv.close()
     return out
 
@@ -374,6 +386,11 @@ def main():
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.3, 0.7, 1.0],
                     help="offered loads, as fractions of the saturated event rate")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=8,
+                    help="events per serving batch (their passes share launches)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time the large workload only (no CPU, FP64, serving or other legs), "
+                         "so that a profile of the run holds that workload's kernels alone")
     ap.add_argument("--serve-pool-gib", type=int, default=8)
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64-path comparison at the production shape")
@@ -405,7 +422,7 @@ def main():
     rows = np.sort(np.r_[rng.choice(cut31, 16, replace=False),
                          rng.choice(np.arange(cut31, n_int), 16, replace=False)])
     cols = np.sort(rng.choice(n_ext, 256, replace=False))
-    cpu, ref = (None, None) if args.no_cpu else cpu_baseline(
+    cpu, ref = (None, None) if (args.no_cpu or args.main_only) else cpu_baseline(
         W, wl, rows, cols, min(16, len(os.sched_getaffinity(0))))
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     hdev = W.bank_on_device(torch, wl.meta["mc"], wl.meta["q"], wl.meta["chi"], wl.f, modes)
@@ -487,13 +504,16 @@ def main():
         parity = float(np.max(np.abs(gpu_lnl - ref)))
         log(f"random pairs vs oracle: max |d lnLbar| = {parity:.3e}")
 
+    legs = not args.main_only
+    split = args.precision != "fp64"
     serving = (serving_leg(dotpe, W, ctx, bank, n_int, args)
-               if args.serve_events > 0 else None)
-    presel = None if args.precision == "fp64" else preselect_leg(W, O, ctx, bank, wl, n_int, args)
-    extr = None if args.precision == "fp64" else extrinsic_leg(W, O, ctx, bank, wl, args)
-    rb = rb_leg(W, O, ctx, args)
-    quiet = None if args.precision == "fp64" else quiet_leg(W, ctx, bank, args)
-    fp64_cmp = None if args.no_fp64 else fp64_comparison(torch, dotpe, W, ctx, args)
+               if legs and args.serve_events > 0 else None)
+    presel = preselect_leg(W, O, ctx, bank, wl, n_int, args) if legs and split else None
+    extr = extrinsic_leg(W, O, ctx, bank, wl, args) if legs and split else None
+    rb = rb_leg(W, O, ctx, args) if legs else None
+    quiet = quiet_leg(W, ctx, bank, args) if legs and split else None
+    fp64_cmp = (fp64_comparison(torch, dotpe, W, ctx, args)
+                if legs and not args.no_fp64 else None)
     traffic = stored_traffic()
     out = {
         "metric": "lnL pairs/s at |dlnL|<=1e-3 (mixed vs FP64)",

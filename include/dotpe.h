@@ -458,23 +458,31 @@ int dotpe_extrinsic_samples(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_
  * A server owns one device pool and n_slots streams.  dotpe_submit copies an
  * event description and returns at once.  Events are admitted first in, first
  * out: the head of the queue starts when a slot is idle and the pool has a
- * free block of its footprint (dotpe_event_bytes).  Each admitted event is
- * staged and evaluated (dotpe_set_event + dotpe_evidence semantics, the
- * description's stream ignored) on its slot's stream, with every buffer packed
- * in its pool block, so serving allocates no device memory per event and the
- * work of events in different slots overlaps on the device.  The block
- * returns to the pool when the event completes.  Results equal those of
+ * free block of its footprint (dotpe_event_bytes).  An idle slot takes the
+ * head and, while they fit, the events queued behind it, up to max_batch of
+ * them and batch_pairs pairs in all (events that fill the device alone run
+ * alone: a batch completes when its largest event does).  The slot stages each (dotpe_set_event semantics, the description's
+ * stream ignored) and evaluates them together (dotpe_evidence semantics):
+ * every stage of the evidence pass -- pilot, bound or fast pass, survivor
+ * pass, each chunk of the coefficient route -- is one launch over the tiles
+ * of all the batch's events that take it, each event keeping the grid and
+ * the decisions it has alone.  Every buffer is packed in the event's pool
+ * block, so serving allocates no device memory per event, and the work of
+ * events in different slots overlaps on the device as well.  The blocks
+ * return to the pool when the batch completes.  Results equal those of
  * dotpe_evidence on the same event alone, bit for bit: the cut threshold is
  * fixed by the pilot pass before the main pass starts, and every sum is
- * taken in an order that does not depend on timing.
+ * taken in an order that does not depend on timing or on the batch.
  * (Sec. IV B: every event is an independent evaluation of the likelihood
  * matrix; scheduling is outside the paper.) */
 typedef struct dotpe_server dotpe_server;
 
 typedef struct dotpe_server_desc {
-  int32_t n_slots;        /* events in flight at once, 1..16; 0 = 4 */
-  int32_t reserved;       /* 0 */
+  int32_t n_slots;        /* batches in flight at once, 1..16; 0 = 4 */
+  int32_t max_batch;      /* events per batch, 1..16 (1: one event per launch); 0 = 8 */
   uint64_t pool_bytes;    /* device pool shared by admitted events; 0 = 8 GiB */
+  uint64_t batch_pairs;   /* pairs (bank rows x extrinsic samples) a batch of several
+                             events holds at most; a larger event runs alone; 0 = 2^25 */
 } dotpe_server_desc;
 
 typedef struct dotpe_ticket_info {
@@ -484,6 +492,8 @@ typedef struct dotpe_ticket_info {
   uint64_t bytes;         /* pool footprint of the event */
   int32_t slot;           /* slot (stream) that ran it */
   int32_t status;         /* DOTPE_OK or the event's error code */
+  int32_t batch;          /* events of the batch it ran in (its passes shared launches) */
+  int32_t reserved;
 } dotpe_ticket_info;
 
 /* Create a server for `bank` (which must outlive it).  The pool is charged to

@@ -75,7 +75,7 @@ __device__ __forceinline__ void barrier_in_flight(int n) {
 }
 
 template <int PREC, int G>
-__global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
+__device__ __forceinline__ void bound_pass_tile(const FusedArgs& a, int64_t wg_id, int64_t wg_count) {
   static_assert(PREC != kFP64, "split precisions only");
   typedef BoundTile BT;
   typedef typename Pol<PREC>::Acc Acc;
@@ -95,9 +95,9 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   // workgroup -> 128 x 128 tile: consecutive ids spread over the XCDs, each
   // XCD walking a contiguous band of tiles in bands of 4 tile rows
   const int64_t nst_m = (a.n_tiles_m + 1) / 2, nst_n = (a.n_tiles_n + 1) / 2;
-  int64_t wg = blockIdx.x;
+  int64_t wg = wg_id;
   {
-    const int64_t nwg = gridDim.x;   // multiple of 8
+    const int64_t nwg = wg_count;   // multiple of 8
     wg = (wg % 8) * (nwg / 8) + wg / 8;
   }
   if (wg >= nst_m * nst_n) return;
@@ -615,6 +615,21 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
   }
 }
 
+template <int PREC, int G>
+__global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
+  bound_pass_tile<PREC, G>(a, blockIdx.x, gridDim.x);
+}
+
+// the bound pass of several events in one launch
+template <int PREC, int G>
+__global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound_packed(PackLaunch p) {
+  int64_t blk, nblk;
+  int q;
+  const int e = pack_locate(p, blockIdx.x, &blk, &nblk, &q);
+  FusedArgs a = pack_args(p, e, q);
+  bound_pass_tile<PREC, G>(a, blk, nblk);
+}
+
 // Survivor pass after the bound pass: a wave per listed tile evaluates its
 // survivors one at a time.  For a survivor (i, e) the wave forms X_g and the
 // (h|h) phase coefficients as FP64 sums of the products of the split
@@ -624,7 +639,7 @@ __global__ __launch_bounds__(BoundTile::NT) void k_lnl_bound(FusedArgs a) {
 // The results are merged into the tile's partial, which the bound pass wrote
 // with the tile's bounded mass.
 template <int PREC, int G>
-__global__ __launch_bounds__(256, 2) void k_survivors(FusedArgs a) {
+__device__ __forceinline__ void survivor_pass(const FusedArgs& a, int64_t wg_id, int64_t wg_count) {
   static_assert(PREC != kFP64, "split precisions only");
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;
   typedef typename std::conditional<PREC == kFP16X2, _Float16, __bf16>::type H;
@@ -640,8 +655,7 @@ __global__ __launch_bounds__(256, 2) void k_survivors(FusedArgs a) {
   // is known on the device only; the grid is large enough that a wave
   // takes a few at most)
   const int64_t n_list = (int64_t)a.state[5];
-  for (int64_t item = (int64_t)blockIdx.x * 4 + (tid >> 6); item < n_list;
-       item += (int64_t)gridDim.x * 4) {
+  for (int64_t item = wg_id * 4 + (tid >> 6); item < n_list; item += wg_count * 4) {
     const int64_t tile_id = a.surv_list[2 * item];
     const int n_surv = a.surv_list[2 * item + 1];
     const int64_t tm = tile_id / a.n_tiles_n, tn = tile_id % a.n_tiles_n;
@@ -823,6 +837,21 @@ __global__ __launch_bounds__(256, 2) void k_survivors(FusedArgs a) {
         atomicMax((unsigned long long*)&a.state[1], (unsigned long long)order_bits(tile_max));
     }
   }
+}
+
+template <int PREC, int G>
+__global__ __launch_bounds__(256, 2) void k_survivors(FusedArgs a) {
+  survivor_pass<PREC, G>(a, blockIdx.x, gridDim.x);
+}
+
+// the survivor pass of several events in one launch
+template <int PREC, int G>
+__global__ __launch_bounds__(256, 2) void k_survivors_packed(PackLaunch p) {
+  int64_t blk, nblk;
+  int q;
+  const int e = pack_locate(p, blockIdx.x, &blk, &nblk, &q);
+  FusedArgs a = pack_args(p, e, q);
+  survivor_pass<PREC, G>(a, blk, nblk);
 }
 
 }  // namespace dotpe

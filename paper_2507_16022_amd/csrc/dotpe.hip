@@ -1198,20 +1198,16 @@ constexpr int64_t kSurvGrid = 65536;  // workgroups of 4 waves, a listed tile pe
 constexpr int64_t kCoefGrid = 1024;   // fused kernel, a tile per workgroup at a time
 constexpr int64_t kE2Grid = 4096;
 
-// One evidence pass with cut `cut_delta` (<= 0: none), every decision taken
-// on the device: pilot, then, if the threshold it freezes cuts, the bound
-// pass (or the fused kernel's fast pass on small events) with the survivor
-// pass; then the coefficient route over the tiles those leave (every tile
-// when the cut is off), chunk by chunk; then the fixed-order finalisation.
-// The host waits once, for the results.  Fills *out except the top-k
-// fields and returns the raw candidate count in *n_cand.
-static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
-                         dotpe_evidence_result* out, uint64_t* n_cand) {
-  hipStream_t s = ev->stream;
-  const int prec = ev->bank->prec;
+// Arguments of one evidence pass of ev with cut `cut_delta` (<= 0: none).
+// The fast pass only bounds: a tile with any survivor takes the coefficient
+// route (where every evaluated pair also enters its tile's row and column
+// sums).  The pilot takes every pilot_stride-th row of tiles: 1 in 64 rows
+// on large events, and at least 16 rows of tiles on small ones (a sparse
+// pilot there may miss the rows that set the maximum, and then nothing is
+// cut).
+static FusedArgs pass_args(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta) {
   FusedArgs a = make_args(ctx, ev);
   a.cut_delta = cut_delta;
-  int rc;
   a.state = ev->state;
   a.partials = ev->partials;
   a.cand = ev->cand;
@@ -1219,93 +1215,94 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   a.rerun = ev->rerun;
   a.surv = ev->surv;
   a.surv_list = ev->surv_list;
-  // the fast pass only bounds: a tile with any survivor takes the
-  // coefficient route (where every evaluated pair also enters its tile's
-  // row and column sums)
   a.rec_cap = 0;
-  const bool timed = ev->ev_t[0] != nullptr;
+  a.pilot_stride = std::max<int64_t>(1, std::min<int64_t>(64, a.n_tiles_m / 16));
+  return a;
+}
+
+// The pass's decisions that the host takes from sizes alone.  The cut needs
+// a pilot over other rows of tiles than the ones it cuts; without one the
+// frozen threshold stays at zero and the cut is off.  The bound pass (128 x
+// 128 tiles, split precisions) runs when the event has enough of them to
+// fill the device, else the fused kernel's fast pass; both return at once
+// when the frozen threshold does not cut.
+struct PassPlan {
+  bool may_cut = false, bound_pass = false;
+  int64_t pilot_grid = 0, cut_grid = 0, surv_grid = 0, n_chunks = 0, coef_grid = 0, e2_grid = 0;
+};
+
+static PassPlan pass_plan(const dotpe_event* ev, const FusedArgs& a) {
+  PassPlan p;
+  const int prec = ev->bank->prec;
+  p.may_cut = a.cut_delta > 0.0 && a.n_tiles_m > 1;
+  if (p.may_cut) {
+    const int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
+    p.pilot_grid = round_up(npr * a.n_tiles_n, 8);
+    const int64_t n_big = ((a.n_tiles_m + 1) / 2) * ((a.n_tiles_n + 1) / 2);
+    p.bound_pass = prec != kFP64 && n_big >= kBoundMinTiles &&
+                   !(ev->flags & (DOTPE_FLAG_NO_BOUND_PASS | DOTPE_FLAG_RERUN_ALL));
+    p.cut_grid = round_up(p.bound_pass ? n_big : a.n_tiles, 8);
+    if (p.bound_pass) p.surv_grid = std::min<int64_t>(kSurvGrid, (a.n_tiles + 3) / 4);
+  }
+  // coefficient route: chunks of coef_tiles work items, as many chunks as
+  // every tile would need; the kernels of a chunk past the device's count
+  // return at once
+  const int64_t C = ev->coef_tiles;
+  p.n_chunks = (a.n_tiles + C - 1) / C;
+  p.coef_grid = std::min(C, kCoefGrid);
+  p.e2_grid = std::min(C, kE2Grid);
+  return p;
+}
+
+// the pass's first kernels: its state and the tiles' row and column sums
+static int pass_head(dotpe_event* ev, const FusedArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, ev->state);
   hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>(4096, (a.n_tiles * 128 + 255) / 256)),
                      dim3(256), 0, s, ev->rowcol, a.n_tiles * 128);
-  if (timed) HIP_OK(hipEventRecord(ev->ev_t[0], s));
-  // the cut needs a pilot over other rows of tiles than the ones it cuts;
-  // without one the frozen threshold stays at zero and the cut is off
-  const bool may_cut = cut_delta > 0.0 && a.n_tiles_m > 1;
-  if (may_cut) {
-    // pilot: max lnL^ML over every pilot_stride-th row of tiles sets the
-    // cut threshold, frozen before the main pass (so the cut does not
-    // depend on tile order): 1 in 64 rows on large events, and at least 16
-    // rows of tiles on small ones (a sparse pilot there may miss the rows
-    // that set the maximum, and then nothing is cut)
-    a.pilot_stride = std::max<int64_t>(1, std::min<int64_t>(64, a.n_tiles_m / 16));
-    int64_t npr = (a.n_tiles_m + a.pilot_stride - 1) / a.pilot_stride;
-    if ((rc = launch_fused<kPilot>(prec, a, round_up(npr * a.n_tiles_n, 8), s))) return rc;
-  }
-  hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, ev->state);
-  if (timed) HIP_OK(hipEventRecord(ev->ev_t[1], s));
-  if (may_cut) {
-    // the bound pass (128 x 128 tiles, split precisions) when the event has
-    // enough of them to fill the device; else the fused kernel's fast pass.
-    // Both return at once when the frozen threshold does not cut.
-    const int64_t n_big = ((a.n_tiles_m + 1) / 2) * ((a.n_tiles_n + 1) / 2);
-    const bool bound_pass = prec != kFP64 && n_big >= kBoundMinTiles &&
-                            !(ev->flags & (DOTPE_FLAG_NO_BOUND_PASS | DOTPE_FLAG_RERUN_ALL));
-    if (bound_pass) {
-      if ((rc = launch_fused<kBound>(prec, a, round_up(n_big, 8), s))) return rc;
-      if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
-      const int64_t sg = std::min<int64_t>(kSurvGrid, (a.n_tiles + 3) / 4);
-      if ((rc = launch_fused<kSurvivors>(prec, a, sg, s))) return rc;
-    } else {
-      if ((rc = launch_fused<kEvidence, true>(prec, a, round_up(a.n_tiles, 8), s))) return rc;
-      if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
-    }
-  } else if (timed) {
-    HIP_OK(hipEventRecord(ev->ev_t[3], s));
-  }
-  {
-    // coefficient route: chunks of coef_tiles work items, as many chunks as
-    // every tile would need; the kernels of a chunk past the device's count
-    // return at once
-    const int64_t C = ev->coef_tiles;
-    const int64_t n_chunks = (a.n_tiles + C - 1) / C;
-    for (int64_t c = 0; c < n_chunks; ++c) {
-      a.work0 = c * C;
-      if ((rc = launch_fused<kCoef>(prec, a, std::min(C, kCoefGrid), s))) return rc;
-      if ((rc = launch_fused<kE2>(prec, a, std::min(C, kE2Grid), s))) return rc;
-    }
-  }
-  if (timed) HIP_OK(hipEventRecord(ev->ev_t[2], s));
-  {
-    // fixed-order two-level reduction of the tile partials
-    const int64_t per = 4096;
-    const int64_t nblk = (a.n_tiles + per - 1) / per;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)nblk), dim3(256), 0, s, ev->partials, a.n_tiles,
-                       per, ev->final_blk);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ev->final_blk, nblk, nblk,
-                       ev->final_out);
-    // sums of the squared intrinsic and extrinsic marginals (final_out[13], [14])
-    int tm, tn;
-    tile_shape(prec, &tm, &tn);
-    for (int rows = 1; rows >= 0; --rows) {
-      const int64_t n_idx = rows ? ev->n_sub : ev->n_ext;
-      const int64_t nb = (n_idx + 255) / 256;
-      const int64_t n_other = rows ? a.n_tiles_n : a.n_tiles_m;
-      const int64_t n_parts = (n_other + kMargPer - 1) / kMargPer;
-      hipLaunchKernelGGL(k_marginal_part, dim3((unsigned)nb, (unsigned)n_parts), dim3(256), 0, s,
-                         ev->partials, ev->rowcol, ev->final_out, a.n_tiles_m, a.n_tiles_n, tm, tn,
-                         n_idx, rows, kMargPer, ev->marg_part);
-      hipLaunchKernelGGL(k_marginal_sq, dim3((unsigned)nb), dim3(256), 0, s, ev->marg_part, n_parts,
-                         n_idx, ev->marg_blk);
-      hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(256), 0, s, ev->marg_blk, nb,
-                         ev->final_out + kNPart + (rows ? 1 : 2));
-    }
+  HIP_OK(hipGetLastError());
+  return DOTPE_OK;
+}
+
+// fixed-order two-level reduction of the tile partials, then the sums of
+// the squared intrinsic and extrinsic marginals (final_out[kNPart + 1, + 2]);
+// the results and the state are copied to fo and st (host memory, read
+// after the stream has been synchronised)
+static int pass_tail(dotpe_event* ev, const FusedArgs& a, hipStream_t s, double* fo,
+                     uint64_t* st) {
+  const int prec = ev->bank->prec;
+  const int64_t per = 4096;
+  const int64_t nblk = (a.n_tiles + per - 1) / per;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)nblk), dim3(256), 0, s, ev->partials, a.n_tiles,
+                     per, ev->final_blk);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ev->final_blk, nblk, nblk,
+                     ev->final_out);
+  int tm, tn;
+  tile_shape(prec, &tm, &tn);
+  for (int rows = 1; rows >= 0; --rows) {
+    const int64_t n_idx = rows ? ev->n_sub : ev->n_ext;
+    const int64_t nb = (n_idx + 255) / 256;
+    const int64_t n_other = rows ? a.n_tiles_n : a.n_tiles_m;
+    const int64_t n_parts = (n_other + kMargPer - 1) / kMargPer;
+    hipLaunchKernelGGL(k_marginal_part, dim3((unsigned)nb, (unsigned)n_parts), dim3(256), 0, s,
+                       ev->partials, ev->rowcol, ev->final_out, a.n_tiles_m, a.n_tiles_n, tm, tn,
+                       n_idx, rows, kMargPer, ev->marg_part);
+    hipLaunchKernelGGL(k_marginal_sq, dim3((unsigned)nb), dim3(256), 0, s, ev->marg_part, n_parts,
+                       n_idx, ev->marg_blk);
+    hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(256), 0, s, ev->marg_blk, nb,
+                       ev->final_out + kNPart + (rows ? 1 : 2));
   }
   HIP_OK(hipGetLastError());
-  double fo[kNPart + 3];
-  uint64_t st[6];
-  HIP_OK(hipMemcpyAsync(fo, ev->final_out, sizeof(fo), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(st, ev->state, sizeof(st), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
+  HIP_OK(hipMemcpyAsync(fo, ev->final_out, sizeof(double) * (kNPart + 3), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(st, ev->state, sizeof(uint64_t) * 6, hipMemcpyDeviceToHost, s));
+  return DOTPE_OK;
+}
+
+// the pass's results from the reduced partials fo and the state st: fills
+// *out except the top-k fields and the timings, and returns the raw
+// candidate count in *n_cand
+static void pass_results(const dotpe_event* ev, const FusedArgs& a, const double* fo,
+                         const uint64_t* st, dotpe_evidence_result* out, uint64_t* n_cand) {
+  const double cut_delta = a.cut_delta;
   double thr_frozen;
   std::memcpy(&thr_frozen, &st[3], 8);
   const bool cut = cut_delta > 0.0 && thr_frozen - cut_delta > 0.0;
@@ -1328,26 +1325,208 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   r.max_ln_p = fo[9];
   r.n_pairs = (int64_t)fo[10];
   r.dd = ev->dd;
-  r.precision = prec;
+  r.precision = ev->bank->prec;
   r.cut_delta_used = cut ? cut_delta : 0.0;
   // tiles of the coefficient route (all of them with the cut off), tiles
   // whose survivors the survivor pass evaluated
   r.n_tiles_rerun = (int32_t)(cut ? (int64_t)st[4] : a.n_tiles);
   r.n_tiles_listed = (int32_t)st[5];
-  if (timed) {
-    float t_pilot = 0.f, t_all = 0.f, t_first = 0.f;
-    HIP_OK(hipEventElapsedTime(&t_pilot, ev->ev_t[0], ev->ev_t[1]));
-    HIP_OK(hipEventElapsedTime(&t_all, ev->ev_t[1], ev->ev_t[2]));
-    HIP_OK(hipEventElapsedTime(&t_first, ev->ev_t[1], ev->ev_t[3]));
-    r.t_pilot_ms = t_pilot;
-    r.t_fused_ms = t_all;
-    r.t_main_ms = t_first;
-  }
   // no cut pair could have entered the top-k window
   const double thr = r.max_ln_p - ev->topk_window;
   r.topk_exact = ((int64_t)st[2] <= ev->cand_cap && !(fo[8] >= thr)) ? 1 : 0;
   *n_cand = st[2];
   *out = r;
+}
+
+// One evidence pass with cut `cut_delta` (<= 0: none), every decision taken
+// on the device: pilot, then, if the threshold it freezes cuts, the bound
+// pass (or the fused kernel's fast pass on small events) with the survivor
+// pass; then the coefficient route over the tiles those leave (every tile
+// when the cut is off), chunk by chunk; then the fixed-order finalisation.
+// The host waits once, for the results.  Fills *out except the top-k
+// fields and returns the raw candidate count in *n_cand.
+static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
+                         dotpe_evidence_result* out, uint64_t* n_cand) {
+  hipStream_t s = ev->stream;
+  const int prec = ev->bank->prec;
+  FusedArgs a = pass_args(ctx, ev, cut_delta);
+  const PassPlan pl = pass_plan(ev, a);
+  const bool timed = ev->ev_t[0] != nullptr;
+  int rc;
+  if ((rc = pass_head(ev, a, s))) return rc;
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[0], s));
+  // pilot: max lnL^ML over the pilot rows sets the cut threshold, frozen
+  // before the main pass (so the cut does not depend on tile order)
+  if (pl.may_cut && (rc = launch_fused<kPilot>(prec, a, pl.pilot_grid, s))) return rc;
+  hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, ev->state);
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[1], s));
+  if (pl.may_cut) {
+    if (pl.bound_pass) {
+      if ((rc = launch_fused<kBound>(prec, a, pl.cut_grid, s))) return rc;
+      if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
+      if ((rc = launch_fused<kSurvivors>(prec, a, pl.surv_grid, s))) return rc;
+    } else {
+      if ((rc = launch_fused<kEvidence, true>(prec, a, pl.cut_grid, s))) return rc;
+      if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
+    }
+  } else if (timed) {
+    HIP_OK(hipEventRecord(ev->ev_t[3], s));
+  }
+  for (int64_t c = 0; c < pl.n_chunks; ++c) {
+    a.work0 = c * ev->coef_tiles;
+    if ((rc = launch_fused<kCoef>(prec, a, pl.coef_grid, s))) return rc;
+    if ((rc = launch_fused<kE2>(prec, a, pl.e2_grid, s))) return rc;
+  }
+  if (timed) HIP_OK(hipEventRecord(ev->ev_t[2], s));
+  double fo[kNPart + 3];
+  uint64_t st[6];
+  if ((rc = pass_tail(ev, a, s, fo, st))) return rc;
+  HIP_OK(hipStreamSynchronize(s));
+  pass_results(ev, a, fo, st, out, n_cand);
+  if (timed) {
+    float t_pilot = 0.f, t_all = 0.f, t_first = 0.f;
+    HIP_OK(hipEventElapsedTime(&t_pilot, ev->ev_t[0], ev->ev_t[1]));
+    HIP_OK(hipEventElapsedTime(&t_all, ev->ev_t[1], ev->ev_t[2]));
+    HIP_OK(hipEventElapsedTime(&t_first, ev->ev_t[1], ev->ev_t[3]));
+    out->t_pilot_ms = t_pilot;
+    out->t_fused_ms = t_all;
+    out->t_main_ms = t_first;
+  }
+  return DOTPE_OK;
+}
+
+// Host and device buffers of packed passes (one set per serving slot): the
+// events' arguments and, per event, its reduced results and state.
+struct PackBufs {
+  FusedArgs* h_args = nullptr;   // pinned host
+  FusedArgs* d_args = nullptr;   // device
+  double* h_fo = nullptr;        // pinned host [kMaxPack][kNPart + 3]
+  uint64_t* h_st = nullptr;      // pinned host [kMaxPack][6]
+};
+
+// Packed launches of one pass for the events whose per-event grid (grids[k])
+// is positive, kMaxPack events per launch at most: each event keeps its own
+// grid, laid end to end at multiples of 8.  h_args: the events' arguments
+// on the host (their pointers go into the launch's kernel arguments), d_args
+// their device copy.
+static int launch_packed_pass(int prec, int G, int mode, int n, const int64_t* grids, int64_t chunk,
+                              const FusedArgs* h_args, const FusedArgs* d_args, int n_phi,
+                              hipStream_t s) {
+  PackedLaunchFn fn = packed_launcher(prec, G);
+  if (!fn) return fail(DOTPE_E_INVALID_ARG, "bad precision %d or group count %d", prec, G);
+  PackLaunch p;
+  std::memset(&p, 0, sizeof(p));
+  p.args = d_args;
+  p.chunk = chunk;
+  p.A0 = h_args[0].A0;
+  p.A1 = h_args[0].A1;
+  p.row_scale = h_args[0].row_scale;
+  p.ln_w_bank = h_args[0].ln_w_bank;
+  p.a_nrm = h_args[0].a_nrm;
+  p.dist_tab = h_args[0].dist.tab;
+  p.dist_prm = h_args[0].dist.prm;
+  auto flush = [&]() -> int {
+    if (p.n == 0) return DOTPE_OK;
+    hipError_t e = fn(mode, p, n_phi, s);
+    if (e != hipSuccess) return fail(DOTPE_E_DEVICE, "packed launch: %s", hipGetErrorString(e));
+    p.n = 0;
+    p.off[0] = 0;
+    return DOTPE_OK;
+  };
+  for (int k = 0; k < n; ++k) {
+    if (grids[k] <= 0) continue;
+    if (p.off[p.n] + round_up(grids[k], 8) > (int64_t)INT32_MAX) {
+      int rc = flush();
+      if (rc) return rc;
+    }
+    const FusedArgs& a = h_args[k];
+    PackPtrs& r = p.ptr[p.n];
+    r.sub_idx = a.sub_idx;
+    r.B0 = a.B0;
+    r.B1 = a.B1;
+    r.B2 = a.B2;
+    r.B3 = a.B3;
+    r.col_scale = a.col_scale;
+    r.ln_w_ext = a.ln_w_ext;
+    r.Ah0 = a.Ah0;
+    r.Ah1 = a.Ah1;
+    r.ah_scale = a.ah_scale;
+    r.Bh0 = a.Bh0;
+    r.Bh1 = a.Bh1;
+    r.bh_scale = a.bh_scale;
+    r.phase_cs = a.phase_cs;
+    r.state = a.state;
+    r.partials = a.partials;
+    r.cand = a.cand;
+    r.rerun = a.rerun;
+    r.surv = a.surv;
+    r.surv_list = a.surv_list;
+    r.b_nrm = a.b_nrm;
+    r.ah_nrm = a.ah_nrm;
+    r.bh_nrm = a.bh_nrm;
+    r.coef = a.coef;
+    r.rowcol = a.rowcol;
+    p.ev[p.n] = k;
+    p.off[p.n + 1] = p.off[p.n] + round_up(grids[k], 8);
+    if (++p.n == kMaxPack) {
+      int rc = flush();
+      if (rc) return rc;
+    }
+  }
+  return flush();
+}
+
+// One evidence pass for n events at once (all on stream s, the same bank):
+// the same kernels and per-event decisions as evidence_pass, each stage one
+// packed launch over the events that take it, so the tiles of several events
+// share the device; the host waits once for all of them.
+static int evidence_pass_packed(dotpe_ctx* ctx, dotpe_event* const* evs, int n,
+                                const double* deltas, PackBufs* pb, hipStream_t s,
+                                dotpe_evidence_result* outs, uint64_t* n_cands) {
+  if (n < 1 || n > kMaxPack) return fail(DOTPE_E_INVALID_ARG, "packed pass of %d events", n);
+  const dotpe_bank* bk = evs[0]->bank;
+  const int prec = bk->prec, G = bk->mt.G;
+  std::vector<PassPlan> pl(n);
+  int n_phi = 1;
+  int64_t max_chunks = 0;
+  for (int k = 0; k < n; ++k) {
+    if (evs[k]->bank != bk) return fail(DOTPE_E_INVALID_ARG, "packed events of different banks");
+    pb->h_args[k] = pass_args(ctx, evs[k], deltas[k]);
+    pl[k] = pass_plan(evs[k], pb->h_args[k]);
+    n_phi = std::max(n_phi, evs[k]->n_phi);
+    max_chunks = std::max(max_chunks, pl[k].n_chunks);
+  }
+  HIP_OK(hipMemcpyAsync(pb->d_args, pb->h_args, sizeof(FusedArgs) * n, hipMemcpyHostToDevice, s));
+  int rc;
+  for (int k = 0; k < n; ++k)
+    if ((rc = pass_head(evs[k], pb->h_args[k], s))) return rc;
+  std::vector<int64_t> g(n);
+  auto stage = [&](int mode, int64_t chunk, auto grid_of) -> int {
+    for (int k = 0; k < n; ++k) g[k] = grid_of(k);
+    return launch_packed_pass(prec, G, mode, n, g.data(), chunk, pb->h_args, pb->d_args, n_phi, s);
+  };
+  if ((rc = stage(kPilot, 0, [&](int k) { return pl[k].pilot_grid; }))) return rc;
+  for (int k = 0; k < n; ++k)
+    hipLaunchKernelGGL(k_freeze_threshold, dim3(1), dim3(64), 0, s, evs[k]->state);
+  if ((rc = stage(kBound, 0, [&](int k) { return pl[k].bound_pass ? pl[k].cut_grid : 0; })))
+    return rc;
+  if ((rc = stage(kSurvivors, 0, [&](int k) { return pl[k].surv_grid; }))) return rc;
+  if ((rc = stage(kEvidence, 0,
+                  [&](int k) { return pl[k].may_cut && !pl[k].bound_pass ? pl[k].cut_grid : 0; })))
+    return rc;
+  for (int64_t c = 0; c < max_chunks; ++c) {
+    if ((rc = stage(kCoef, c, [&](int k) { return c < pl[k].n_chunks ? pl[k].coef_grid : 0; })))
+      return rc;
+    if ((rc = stage(kE2, c, [&](int k) { return c < pl[k].n_chunks ? pl[k].e2_grid : 0; })))
+      return rc;
+  }
+  for (int k = 0; k < n; ++k)
+    if ((rc = pass_tail(evs[k], pb->h_args[k], s, pb->h_fo + k * (kNPart + 3), pb->h_st + k * 6)))
+      return rc;
+  HIP_OK(hipStreamSynchronize(s));
+  for (int k = 0; k < n; ++k)
+    pass_results(evs[k], pb->h_args[k], pb->h_fo + k * (kNPart + 3), pb->h_st + k * 6, &outs[k],
+                 &n_cands[k]);
   return DOTPE_OK;
 }
 
@@ -1412,6 +1591,73 @@ static int evidence_run(dotpe_ctx* ctx, dotpe_event* ev, dotpe_evidence_result* 
   ev->last_n_eff = std::exp(2.0 * r.ln_sum_p - r.ln_sum_p2_triples);
   r.status = DOTPE_OK;
   *out = r;
+  return DOTPE_OK;
+}
+
+// evidence_run for n events of one bank on stream s, their passes packed:
+// every event takes the passes it would take alone (a growing cut_delta
+// until its certificate meets its target), the events still short of their
+// target sharing each further pass; then each event's top-k.  rcs[k] is
+// event k's status; the return value is nonzero only when the batch as a
+// whole failed (then every event has that status).
+static int evidence_run_packed(dotpe_ctx* ctx, dotpe_event* const* evs, int n, PackBufs* pb,
+                               hipStream_t s, dotpe_evidence_result* outs,
+                               dotpe_sample* const* topks, int* rcs) {
+  std::vector<double> delta(n);
+  std::vector<int> passes(n, 0);
+  std::vector<uint64_t> n_cand(n, 0);
+  std::vector<int> active(n);
+  for (int k = 0; k < n; ++k) {
+    delta[k] = evs[k]->cut_delta;
+    active[k] = k;
+    rcs[k] = DOTPE_OK;
+  }
+  std::vector<dotpe_event*> sub;
+  std::vector<double> sub_delta;
+  std::vector<dotpe_evidence_result> sub_out;
+  std::vector<uint64_t> sub_cand;
+  while (!active.empty()) {
+    const int m = (int)active.size();
+    sub.resize(m);
+    sub_delta.resize(m);
+    sub_out.resize(m);
+    sub_cand.resize(m);
+    for (int q = 0; q < m; ++q) {
+      sub[q] = evs[active[q]];
+      sub_delta[q] = delta[active[q]];
+    }
+    int rc = evidence_pass_packed(ctx, sub.data(), m, sub_delta.data(), pb, s, sub_out.data(),
+                                  sub_cand.data());
+    if (rc) {
+      for (int k = 0; k < n; ++k) rcs[k] = rc;
+      return rc;
+    }
+    std::vector<int> next;
+    for (int q = 0; q < m; ++q) {
+      const int k = active[q];
+      outs[k] = sub_out[q];
+      n_cand[k] = sub_cand[q];
+      ++passes[k];
+      const dotpe_evidence_result& r = sub_out[q];
+      if (!(delta[k] > 0.0) || r.ln_z_upper - r.ln_z <= evs[k]->cut_target) continue;
+      delta[k] = passes[k] < 3 ? delta[k] + 20.0 : 0.0;    // cut less, finally not at all
+      next.push_back(k);
+    }
+    active.swap(next);
+  }
+  for (int k = 0; k < n; ++k) {
+    dotpe_evidence_result& r = outs[k];
+    r.n_passes = passes[k];
+    int rc = evidence_topk(evs[k], n_cand[k], &r, topks[k]);
+    if (rc) {
+      rcs[k] = rc;
+      continue;
+    }
+    evs[k]->evaluated = true;
+    evs[k]->last_cut = r.cut_delta_used;
+    evs[k]->last_n_eff = std::exp(2.0 * r.ln_sum_p - r.ln_sum_p2_triples);
+    r.status = DOTPE_OK;
+  }
   return DOTPE_OK;
 }
 
@@ -2050,8 +2296,9 @@ int dotpe_debug_response(dotpe_ctx* ctx, const dotpe_event* ev, double* R, doubl
 
 // ---------------------------------------------------------------------------
 // Serving: events submitted while others run are admitted FIFO as a slot and
-// a block of the device pool free up; each slot runs its event's staging and
-// evidence on its own stream, so the device work of concurrent events overlaps.
+// blocks of the device pool free up; each slot takes a batch of queued events,
+// stages them and runs their evidence passes packed into shared launches on
+// its own stream, so the device work of concurrent batches overlaps too.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -2074,16 +2321,90 @@ const T* copy_in(std::vector<T>* v, const T* src, size_t n) {
 
 }  // namespace
 
+struct dotpe_server;
+static void serve_batch(dotpe_server* s, int slot, std::vector<Scheduler::BatchItem>& items);
+static void free_server_buffers(dotpe_server* s);
+
 struct dotpe_server {
   dotpe_ctx* ctx = nullptr;
   const dotpe_bank* bank = nullptr;
   char* pool = nullptr;
   uint64_t pool_len = 0;
   std::vector<hipStream_t> streams;
+  std::vector<PackBufs> packs;   // per slot
   std::unique_ptr<Scheduler> sched;
   std::mutex mu;
   std::map<int64_t, std::shared_ptr<ServeJob>> jobs;
 };
+
+// Stage the batch's events in their pool blocks, run their evidence passes
+// packed (evidence_run_packed) and release the events; each item's status is
+// its event's.
+static void serve_batch(dotpe_server* s, int slot, std::vector<Scheduler::BatchItem>& items) {
+  const int n = (int)items.size();
+  hipStream_t st = s->streams[slot];
+  std::vector<dotpe_event*> evs(n, nullptr);
+  std::vector<ServeJob*> jobs(n);
+  std::vector<dotpe_event*> run;
+  std::vector<int> run_idx;
+  for (int k = 0; k < n; ++k) {
+    jobs[k] = (ServeJob*)items[k].payload;
+    items[k].rc = set_event_impl(s->ctx, s->bank, &jobs[k]->desc, s->pool + items[k].off,
+                                 jobs[k]->bytes, st, &evs[k]);
+    if (items[k].rc != DOTPE_OK) {
+      jobs[k]->err = g_err;
+      continue;
+    }
+    run.push_back(evs[k]);
+    run_idx.push_back(k);
+  }
+  if (!run.empty()) {
+    const int m = (int)run.size();
+    std::vector<dotpe_evidence_result> res(m);
+    std::vector<dotpe_sample*> topk(m);
+    std::vector<int> rcs(m, DOTPE_OK);
+    for (int q = 0; q < m; ++q) {
+      ServeJob* j = jobs[run_idx[q]];
+      topk[q] = j->topk.empty() ? nullptr : j->topk.data();
+    }
+    if (m == 1)   // alone: the event's own launches
+      rcs[0] = dotpe_evidence(s->ctx, run[0], &res[0], topk[0]);
+    else
+      (void)evidence_run_packed(s->ctx, run.data(), m, &s->packs[slot], st, res.data(),
+                                topk.data(), rcs.data());
+    // after a failure, work may still be queued: the blocks return to the
+    // pool only once the stream has drained
+    if (std::any_of(rcs.begin(), rcs.end(), [](int r) { return r != DOTPE_OK; }))
+      (void)hipStreamSynchronize(st);
+    for (int q = 0; q < m; ++q) {
+      const int k = run_idx[q];
+      items[k].rc = rcs[q];
+      if (rcs[q] == DOTPE_OK)
+        jobs[k]->res = res[q];
+      else
+        jobs[k]->err = g_err;
+    }
+  }
+  for (int k = 0; k < n; ++k)
+    if (evs[k]) dotpe_free_event(s->ctx, evs[k]);
+}
+
+static void free_server_buffers(dotpe_server* s) {
+  for (PackBufs& pb : s->packs) {
+    if (pb.h_args) (void)hipHostFree(pb.h_args);
+    if (pb.h_fo) (void)hipHostFree(pb.h_fo);
+    if (pb.h_st) (void)hipHostFree(pb.h_st);
+    if (pb.d_args) (void)hipFree(pb.d_args);
+  }
+  s->packs.clear();
+  for (hipStream_t t : s->streams) (void)hipStreamDestroy(t);
+  s->streams.clear();
+  if (s->pool) {
+    (void)hipFree(s->pool);
+    s->ctx->bytes -= s->pool_len;
+    s->pool = nullptr;
+  }
+}
 
 extern "C" {
 
@@ -2091,8 +2412,13 @@ int dotpe_server_create(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_serv
                         dotpe_server** out) {
   if (!ctx || !bank || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
   int n_slots = (desc && desc->n_slots > 0) ? desc->n_slots : 4;
+  int max_batch = (desc && desc->max_batch > 0) ? desc->max_batch : 8;
+  const double batch_pairs =
+      (desc && desc->batch_pairs) ? (double)desc->batch_pairs : (double)(uint64_t(1) << 25);
   uint64_t pool = (desc && desc->pool_bytes) ? desc->pool_bytes : (uint64_t(8) << 30);
   if (n_slots > 16) return fail(DOTPE_E_INVALID_ARG, "n_slots=%d (at most 16)", n_slots);
+  if (max_batch > kMaxPack)
+    return fail(DOTPE_E_INVALID_ARG, "max_batch=%d (at most %d)", max_batch, kMaxPack);
   pool = pool / kBlockAlign * kBlockAlign;
   if (pool < kBlockAlign) return fail(DOTPE_E_INVALID_ARG, "pool_bytes too small");
   HIP_OK(hipSetDevice(ctx->device));
@@ -2107,18 +2433,32 @@ int dotpe_server_create(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_serv
   srv->pool_len = pool;
   for (int q = 0; q < n_slots; ++q) {
     hipStream_t st = nullptr;
+    PackBufs pb;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      for (hipStream_t t : srv->streams) (void)hipStreamDestroy(t);
-      (void)hipFree(srv->pool);
-      ctx->bytes -= pool;
-      delete srv;
-      return fail(DOTPE_E_DEVICE, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+    if (e == hipSuccess) {
+      srv->streams.push_back(st);
+      e = hipHostMalloc((void**)&pb.h_args, sizeof(FusedArgs) * kMaxPack, hipHostMallocDefault);
+      if (e == hipSuccess)
+        e = hipHostMalloc((void**)&pb.h_fo, sizeof(double) * kMaxPack * (kNPart + 3),
+                          hipHostMallocDefault);
+      if (e == hipSuccess)
+        e = hipHostMalloc((void**)&pb.h_st, sizeof(uint64_t) * kMaxPack * 6, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipMalloc((void**)&pb.d_args, sizeof(FusedArgs) * kMaxPack);
+      srv->packs.push_back(pb);
     }
-    srv->streams.push_back(st);
+    if (e != hipSuccess) {
+      free_server_buffers(srv);
+      delete srv;
+      return fail(DOTPE_E_DEVICE, "server set-up: %s", hipGetErrorString(e));
+    }
   }
   const int dev = ctx->device;
-  srv->sched.reset(new Scheduler(n_slots, pool, [dev](int) { (void)hipSetDevice(dev); }));
+  dotpe_server* sv = srv;
+  Scheduler::BatchFn batch = [sv](int slot, std::vector<Scheduler::BatchItem>& items) {
+    serve_batch(sv, slot, items);
+  };
+  srv->sched.reset(new Scheduler(n_slots, pool, [dev](int) { (void)hipSetDevice(dev); }, max_batch,
+                                 batch, batch_pairs));
   *out = srv;
   return DOTPE_OK;
 }
@@ -2126,11 +2466,7 @@ int dotpe_server_create(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_serv
 int dotpe_server_destroy(dotpe_server* srv) {
   if (!srv) return DOTPE_OK;
   srv->sched.reset();   // runs every submitted event to completion
-  for (hipStream_t t : srv->streams) (void)hipStreamDestroy(t);
-  if (srv->pool) {
-    (void)hipFree(srv->pool);
-    srv->ctx->bytes -= srv->pool_len;
-  }
+  free_server_buffers(srv);
   delete srv;
   return DOTPE_OK;
 }
@@ -2166,16 +2502,14 @@ int dotpe_submit(dotpe_server* srv, const dotpe_event_desc* d, int64_t* ticket) 
   job->desc.stream = nullptr;
   job->topk.resize((size_t)std::max(0, d->top_k));
   dotpe_server* s = srv;
-  int64_t t = srv->sched->submit(job->bytes, [s, job](int slot, uint64_t off) -> int {
-    dotpe_event* ev = nullptr;
-    int r = set_event_impl(s->ctx, s->bank, &job->desc, s->pool + off, job->bytes,
-                           s->streams[slot], &ev);
-    if (r == DOTPE_OK)
-      r = dotpe_evidence(s->ctx, ev, &job->res, job->topk.empty() ? nullptr : job->topk.data());
-    if (ev) dotpe_free_event(s->ctx, ev);
-    if (r != DOTPE_OK) job->err = g_err;
-    return r;
-  });
+  int64_t t = srv->sched->submit(
+      job->bytes,
+      [s, job](int slot, uint64_t off) -> int {
+        std::vector<Scheduler::BatchItem> one{Scheduler::BatchItem{job.get(), off, 0}};
+        serve_batch(s, slot, one);
+        return one[0].rc;
+      },
+      job, (double)D.n_sub * (double)D.ne);
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->jobs[t] = job;
@@ -2218,6 +2552,8 @@ int dotpe_wait(dotpe_server* srv, int64_t ticket, dotpe_evidence_result* out, do
     info->bytes = tm.bytes;
     info->slot = tm.slot;
     info->status = rc;
+    info->batch = tm.batch;
+    info->reserved = 0;
   }
   if (rc != DOTPE_OK) return fail(rc, "%s", job->err.c_str());
   if (out) *out = job->res;

@@ -104,7 +104,7 @@ struct PairCoef {
 };
 
 template <int PREC, int G>
-__global__ __launch_bounds__(256, 3) void k_e2_tiles(FusedArgs a) {
+__device__ __forceinline__ void e2_pass(const FusedArgs& a, int64_t wg_id, int64_t wg_count) {
   typedef Tile<PREC> TL;
   typedef typename std::conditional<PREC == kFP64, double, float>::type AT;
   constexpr int NRT = (G == 1) ? 1 : kMaxNR;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256, 3) void k_e2_tiles(FusedArgs a) {
   const float thr_f = (float)thr_ml;
   const int64_t end = min(a.work0 + a.coef_tiles, coef_work_count(a));
 
-  for (int64_t q = a.work0 + blockIdx.x; q < end; q += gridDim.x) {
+  for (int64_t q = a.work0 + wg_id; q < end; q += wg_count) {
     const int64_t t = coef_tile(a, q);
     const int64_t tm = t / a.n_tiles_n, tn = t % a.n_tiles_n;
     const int64_t row0 = tm * TM, col0 = tn * TN;
@@ -218,6 +218,22 @@ __global__ __launch_bounds__(256, 3) void k_e2_tiles(FusedArgs a) {
     }
     __syncthreads();   // the tile's scalars and reduction area are reused
   }
+}
+
+template <int PREC, int G>
+__global__ __launch_bounds__(256, 3) void k_e2_tiles(FusedArgs a) {
+  e2_pass<PREC, G>(a, blockIdx.x, gridDim.x);
+}
+
+// one chunk of the coefficient route's second half for several events
+template <int PREC, int G>
+__global__ __launch_bounds__(256, 3) void k_e2_tiles_packed(PackLaunch p) {
+  int64_t blk, nblk;
+  int q;
+  const int e = pack_locate(p, blockIdx.x, &blk, &nblk, &q);
+  FusedArgs a = pack_args(p, e, q);
+  a.work0 = p.chunk * a.coef_tiles;
+  e2_pass<PREC, G>(a, blk, nblk);
 }
 
 // ---------------------------------------------------------------------------

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "common.h"
+#include "pack.h"
 
 namespace dotpe {
 
@@ -107,6 +108,56 @@ struct FusedArgs {
   const double* final_out;       // the reduced results (the global max of ln p at [9])
   double d0;                     // distance the bank is stored at
 };
+
+// the arguments of the event in slot q of packed launch p: its sizes and
+// tables from device memory, every pointer from the kernel arguments
+__device__ __forceinline__ FusedArgs pack_args(const PackLaunch& p, int e, int q) {
+  FusedArgs a = p.args[e];
+  const PackPtrs& r = p.ptr[q];
+  a.A0 = p.A0;
+  a.A1 = p.A1;
+  a.row_scale = p.row_scale;
+  a.ln_w_bank = p.ln_w_bank;
+  a.a_nrm = p.a_nrm;
+  a.dist.tab = p.dist_tab;
+  a.dist.prm = p.dist_prm;
+  a.sub_idx = r.sub_idx;
+  a.B0 = r.B0;
+  a.B1 = r.B1;
+  a.B2 = r.B2;
+  a.B3 = r.B3;
+  a.col_scale = r.col_scale;
+  a.ln_w_ext = r.ln_w_ext;
+  a.Ah0 = r.Ah0;
+  a.Ah1 = r.Ah1;
+  a.ah_scale = r.ah_scale;
+  a.Bh0 = r.Bh0;
+  a.Bh1 = r.Bh1;
+  a.bh_scale = r.bh_scale;
+  a.phase_cs = r.phase_cs;
+  a.state = r.state;
+  a.partials = r.partials;
+  a.cand = r.cand;
+  a.rerun = r.rerun;
+  a.surv = r.surv;
+  a.surv_list = r.surv_list;
+  a.b_nrm = r.b_nrm;
+  a.ah_nrm = r.ah_nrm;
+  a.bh_nrm = r.bh_nrm;
+  a.coef = r.coef;
+  a.rowcol = r.rowcol;
+  // outputs of other entry points: none in a packed pass
+  a.lnl_out = nullptr;
+  a.ml_out = nullptr;
+  a.trip_out = nullptr;
+  a.bound_out = nullptr;
+  a.work_list = nullptr;
+  a.sample_first = nullptr;
+  a.sample_res = nullptr;
+  a.samples = nullptr;
+  a.final_out = nullptr;
+  return a;
+}
 
 template <int PREC>
 struct Pol;
@@ -1261,13 +1312,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, unsigned char* sm
                    tile_id);
 }
 
+// workgroup blk of a grid of nblk (a multiple of 8 outside the coefficient
+// route) -> its tile or tiles
 template <int PREC, int G, int MODE, bool FAST>
-__global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void fused_grid_tile(const FusedArgs& a, unsigned char* smem,
+                                                int64_t wg_id, int64_t wg_count) {
   if constexpr (MODE == kCoef) {
     // coefficient route: the workgroups take the chunk's work items in turn
     const int64_t end = min(a.work0 + a.coef_tiles, coef_work_count(a));
-    for (int64_t q = a.work0 + blockIdx.x; q < end; q += gridDim.x) {
+    for (int64_t q = a.work0 + wg_id; q < end; q += wg_count) {
       const int64_t t = coef_tile(a, q);
       fused_tile<PREC, G, MODE, FAST>(a, smem, t / a.n_tiles_n, t % a.n_tiles_n, q - a.work0);
       __syncthreads();
@@ -1279,9 +1332,9 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     // XCD walks a contiguous band of tiles, then raster in bands of 4 tile
     // rows (the ~32 tiles an XCD runs at once then share 4 row blocks and 8
     // column blocks of operands in its L2)
-    int64_t wg = blockIdx.x;
+    int64_t wg = wg_id;
     int64_t tm, tn;
-    const int64_t nwg = gridDim.x;              // multiple of 8
+    const int64_t nwg = wg_count;                   // multiple of 8
     wg = (wg % 8) * (nwg / 8) + wg / 8;
     if (MODE == kPilot) {
       // every pilot_stride-th row of tiles, all columns
@@ -1300,6 +1353,25 @@ __global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
     }
     fused_tile<PREC, G, MODE, FAST>(a, smem, tm, tn, 0);
   }
+}
+
+template <int PREC, int G, int MODE, bool FAST>
+__global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused(FusedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  fused_grid_tile<PREC, G, MODE, FAST>(a, smem, blockIdx.x, gridDim.x);
+}
+
+// the pilot, the fast pass or one chunk of the coefficient route of several
+// events in one launch
+template <int PREC, int G, int MODE, bool FAST>
+__global__ __launch_bounds__(Tile<PREC>::NT) void k_lnl_fused_packed(PackLaunch p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int64_t blk, nblk;
+  int q;
+  const int e = pack_locate(p, blockIdx.x, &blk, &nblk, &q);
+  FusedArgs a = pack_args(p, e, q);
+  if (MODE == kCoef) a.work0 = p.chunk * a.coef_tiles;
+  fused_grid_tile<PREC, G, MODE, FAST>(a, smem, blk, nblk);
 }
 
 }  // namespace dotpe

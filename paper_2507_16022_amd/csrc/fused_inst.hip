@@ -19,6 +19,7 @@ namespace dotpe {
 
 #define DOTPE_MARG_CAT4(a, b, c, d) a##b##c##d
 #define DOTPE_MARG_NAME(P, G) DOTPE_MARG_CAT4(launch_marg_p, P, _g, G)
+#define DOTPE_MARGP_NAME(P, G) DOTPE_MARG_CAT4(launch_marg_packed_p, P, _g, G)
 
 namespace {
 
@@ -58,6 +59,54 @@ hipError_t launch_bound(const FusedArgs& a, int64_t grid, hipStream_t s) {
   }
 }
 
+template <int PREC, int G, int MODE, bool FAST>
+hipError_t launch_one_packed(const PackLaunch& p, int n_phi, hipStream_t s) {
+  typedef Tile<PREC> TL;
+  const size_t sh = TL::CS_OFF + sizeof(double) * kMaxM * n_phi * 2;
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    const size_t most = TL::CS_OFF + sizeof(double) * kMaxM * kMaxPhi * 2;
+    if (hipFuncSetAttribute((const void*)k_lnl_fused_packed<PREC, G, MODE, FAST>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
+      (void)hipGetLastError();
+  });
+  hipLaunchKernelGGL((k_lnl_fused_packed<PREC, G, MODE, FAST>), dim3((unsigned)p.off[p.n]),
+                     dim3(TL::NT), sh, s, p);
+  return hipGetLastError();
+}
+
+template <int PREC, int G>
+hipError_t launch_bound_packed(const PackLaunch& p, hipStream_t s) {
+  if constexpr (PREC == kFP64) {
+    return hipErrorInvalidValue;
+  } else {
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+      if (hipFuncSetAttribute((const void*)k_lnl_bound_packed<PREC, G>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              BoundTile::LDS_BYTES) != hipSuccess)
+        (void)hipGetLastError();
+    });
+    hipLaunchKernelGGL((k_lnl_bound_packed<PREC, G>), dim3((unsigned)p.off[p.n]),
+                       dim3(BoundTile::NT), BoundTile::LDS_BYTES, s, p);
+    return hipGetLastError();
+  }
+}
+
+template <int PREC, int G>
+hipError_t launch_any_packed(int mode, const PackLaunch& p, int n_phi, hipStream_t s) {
+  if (p.n < 1 || p.n > kMaxPack || p.off[p.n] <= 0) return hipErrorInvalidValue;
+  switch (mode) {
+    case kPilot: return launch_one_packed<PREC, G, kPilot, false>(p, n_phi, s);
+    case kEvidence: return launch_one_packed<PREC, G, kEvidence, true>(p, n_phi, s);
+    case kBound: return launch_bound_packed<PREC, G>(p, s);
+    case kCoef: return launch_one_packed<PREC, G, kCoef, false>(p, n_phi, s);
+    case kSurvivors:
+    case kE2: return DOTPE_MARGP_NAME(DOTPE_INST_PREC, DOTPE_INST_G)(mode, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int PREC, int G>
 hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hipStream_t s) {
   switch (mode) {
@@ -84,6 +133,13 @@ hipError_t launch_any(int mode, bool fast, const FusedArgs& a, int64_t grid, hip
 hipError_t DOTPE_NAME(DOTPE_INST_PREC, DOTPE_INST_G)(int mode, bool fast, const FusedArgs& a,
                                                      int64_t grid, hipStream_t s) {
   return launch_any<DOTPE_INST_PREC, DOTPE_INST_G>(mode, fast, a, grid, s);
+}
+
+#define DOTPE_PNAME(P, G) DOTPE_CAT4(launch_packed_p, P, _g, G)
+
+hipError_t DOTPE_PNAME(DOTPE_INST_PREC, DOTPE_INST_G)(int mode, const PackLaunch& p, int n_phi,
+                                                      hipStream_t s) {
+  return launch_any_packed<DOTPE_INST_PREC, DOTPE_INST_G>(mode, p, n_phi, s);
 }
 
 }  // namespace dotpe

@@ -40,6 +40,24 @@ hipError_t launch_marg(int mode, const FusedArgs& a, int64_t grid, hipStream_t s
   return hipErrorInvalidValue;
 }
 
+template <int PREC, int G>
+hipError_t launch_marg_packed(int mode, const PackLaunch& p, hipStream_t s) {
+  const dim3 grid((unsigned)p.off[p.n]);
+  switch (mode) {
+    case kSurvivors:
+      if constexpr (PREC == kFP64) {
+        return hipErrorInvalidValue;
+      } else {
+        hipLaunchKernelGGL((k_survivors_packed<PREC, G>), grid, dim3(256), 0, s, p);
+        return hipGetLastError();
+      }
+    case kE2:
+      hipLaunchKernelGGL((k_e2_tiles_packed<PREC, G>), grid, dim3(256), 0, s, p);
+      return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 #define DOTPE_CAT4(a, b, c, d) a##b##c##d
@@ -48,6 +66,13 @@ hipError_t launch_marg(int mode, const FusedArgs& a, int64_t grid, hipStream_t s
 hipError_t DOTPE_NAME(DOTPE_INST_PREC, DOTPE_INST_G)(int mode, const FusedArgs& a, int64_t grid,
                                                      hipStream_t s) {
   return launch_marg<DOTPE_INST_PREC, DOTPE_INST_G>(mode, a, grid, s);
+}
+
+#define DOTPE_PNAME(P, G) DOTPE_CAT4(launch_marg_packed_p, P, _g, G)
+
+hipError_t DOTPE_PNAME(DOTPE_INST_PREC, DOTPE_INST_G)(int mode, const PackLaunch& p,
+                                                      hipStream_t s) {
+  return launch_marg_packed<DOTPE_INST_PREC, DOTPE_INST_G>(mode, p, s);
 }
 
 }  // namespace dotpe

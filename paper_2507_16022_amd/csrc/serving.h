@@ -1,11 +1,14 @@
 // serving.h -- host-side admission and scheduling for the serving calls.
 //
 // Plain C++ (no HIP): a first-fit map over one fixed device pool, and a FIFO
-// scheduler whose slot threads each run one admitted event at a time.  An
-// event is admitted when it is at the head of the queue, a slot is idle and
-// the pool holds a free block of the event's size; its block returns to the
-// pool when the event completes.  Events that arrive while others run are
-// admitted as slots and memory free up, so their device work overlaps.
+// scheduler whose slot threads each run a batch of admitted events at a
+// time.  An event is admitted when it is at the head of the queue, a slot is
+// idle and the pool holds a free block of the event's size; an idle slot
+// takes the head and then, while they fit, the events queued behind it, up
+// to the batch limit, and runs them together (their passes packed into
+// shared launches).  Each block returns to the pool when its batch
+// completes.  Events that arrive while others run are admitted as slots and
+// memory free up, so their device work overlaps.
 #pragma once
 
 #include <chrono>
@@ -88,16 +91,35 @@ struct JobTimes {
   double t_submit_ms = 0, t_start_ms = 0, t_done_ms = 0;   // since scheduler creation
   uint64_t bytes = 0;
   int slot = -1;
+  int batch = 0;    // jobs in the batch that ran it
 };
 
 // FIFO scheduler over n_slots threads and one pool.  run(slot, offset) does
 // the job's work with the pool block at `offset` and returns a status code.
+// With a batch function and max_batch > 1, a slot takes up to max_batch
+// queued jobs at once and batch(slot, items) runs them all, setting each
+// item's status; a job's run function is then not called.  A batch of more
+// than one job also holds at most batch_work units of work (as given to
+// submit), so that a job large enough to fill the device runs alone and the
+// jobs packed together are small ones: a batch completes when its largest
+// job does, and a small job packed with a large one would wait for it.
 class Scheduler {
  public:
   typedef std::function<int(int slot, uint64_t off)> RunFn;
+  struct BatchItem {
+    void* payload;    // as given to submit
+    uint64_t off;     // pool block
+    int rc;           // set by the batch function
+  };
+  typedef std::function<void(int slot, std::vector<BatchItem>& items)> BatchFn;
 
-  Scheduler(int n_slots, uint64_t pool_bytes, std::function<void(int)> slot_init)
-      : pool_(pool_bytes), t0_(std::chrono::steady_clock::now()) {
+  Scheduler(int n_slots, uint64_t pool_bytes, std::function<void(int)> slot_init,
+            int max_batch = 1, BatchFn batch = nullptr, double batch_work = 0.0)
+      : pool_(pool_bytes),
+        t0_(std::chrono::steady_clock::now()),
+        max_batch_(batch && max_batch > 1 ? max_batch : 1),
+        batch_(std::move(batch)),
+        batch_work_(batch_work) {
     for (int s = 0; s < n_slots; ++s)
       threads_.emplace_back([this, s, slot_init] {
         if (slot_init) slot_init(s);
@@ -116,10 +138,13 @@ class Scheduler {
   uint64_t pool_bytes() const { return pool_.size(); }
   // false if the job can never be admitted (larger than the pool)
   bool admissible(uint64_t bytes) const { return PoolMap::round(bytes) <= pool_.size(); }
-  int64_t submit(uint64_t bytes, RunFn run) {
+  int64_t submit(uint64_t bytes, RunFn run, std::shared_ptr<void> payload = nullptr,
+                 double work = 0.0) {
     auto j = std::make_shared<Job>();
     j->bytes = bytes;
+    j->work = work;
     j->run = std::move(run);
+    j->payload = std::move(payload);
     j->times.t_submit_ms = now_ms();
     j->times.bytes = bytes;
     int64_t t;
@@ -166,6 +191,8 @@ class Scheduler {
     int64_t ticket = 0;
     uint64_t bytes = 0;
     RunFn run;
+    std::shared_ptr<void> payload;
+    double work = 0.0;
     int rc = 0;
     bool done = false;
     JobTimes times;
@@ -180,23 +207,43 @@ class Scheduler {
         return (!queue_.empty() && pool_.fits(queue_.front()->bytes)) || (stop_ && queue_.empty());
       });
       if (queue_.empty()) return;   // stop_ and drained
-      auto j = queue_.front();
-      queue_.pop_front();
-      uint64_t off = 0;
-      pool_.alloc(j->bytes, &off);   // fits() held under the same lock
-      ++running_;
-      j->times.t_start_ms = now_ms();
-      j->times.slot = slot;
+      // the head (fits() held under the same lock), then while they fit
+      // the jobs behind it, in order, up to the batch limit
+      std::vector<std::shared_ptr<Job>> batch;
+      std::vector<BatchItem> items;
+      double work = 0.0;
+      while (!queue_.empty() && (int)batch.size() < max_batch_) {
+        if (!batch.empty() && work + queue_.front()->work > batch_work_) break;
+        uint64_t off = 0;
+        if (!pool_.alloc(queue_.front()->bytes, &off)) break;
+        work += queue_.front()->work;
+        auto j = queue_.front();
+        queue_.pop_front();
+        j->times.t_start_ms = now_ms();
+        j->times.slot = slot;
+        batch.push_back(j);
+        items.push_back(BatchItem{j->payload.get(), off, 0});
+      }
+      running_ += (int)batch.size();
       lk.unlock();
       cv_.notify_all();   // the next head may fit in what is left
-      int rc = j->run(slot, off);
+      if (batch_) {
+        batch_(slot, items);
+      } else {
+        for (size_t q = 0; q < batch.size(); ++q) items[q].rc = batch[q]->run(slot, items[q].off);
+      }
       lk.lock();
-      pool_.release(off);
-      --running_;
-      j->rc = rc;
-      j->times.t_done_ms = now_ms();
-      j->done = true;
-      j->run = nullptr;
+      const double t_done = now_ms();
+      for (size_t q = 0; q < batch.size(); ++q) {
+        pool_.release(items[q].off);
+        batch[q]->rc = items[q].rc;
+        batch[q]->times.t_done_ms = t_done;
+        batch[q]->times.batch = (int)batch.size();
+        batch[q]->done = true;
+        batch[q]->run = nullptr;
+        batch[q]->payload.reset();
+      }
+      running_ -= (int)batch.size();
       done_cv_.notify_all();
       cv_.notify_all();
     }
@@ -209,6 +256,9 @@ class Scheduler {
   std::deque<std::shared_ptr<Job>> queue_;
   std::map<int64_t, std::shared_ptr<Job>> jobs_;
   std::vector<std::thread> threads_;
+  int max_batch_ = 1;
+  BatchFn batch_;
+  double batch_work_ = 0.0;
   int64_t next_ticket_ = 1;
   int running_ = 0;
   bool stop_ = false;

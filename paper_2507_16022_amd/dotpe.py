@@ -101,14 +101,15 @@ class EvidenceResult(ctypes.Structure):
 
 
 class ServerDesc(ctypes.Structure):
-    _fields_ = [("n_slots", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("pool_bytes", ctypes.c_uint64)]
+    _fields_ = [("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_uint64), ("batch_pairs", ctypes.c_uint64)]
 
 
 class TicketInfo(ctypes.Structure):
     _fields_ = [("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
                 ("t_done_ms", ctypes.c_double), ("bytes", ctypes.c_uint64),
-                ("slot", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("slot", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PreselectDesc(ctypes.Structure):
@@ -579,10 +580,10 @@ class Server:
     """Continuous admission of events against a resident bank (dotpe_submit /
     dotpe_poll / dotpe_wait); see include/dotpe.h."""
 
-    def __init__(self, ctx, bank, n_slots=4, pool_bytes=0):
+    def __init__(self, ctx, bank, n_slots=4, pool_bytes=0, max_batch=0, batch_pairs=0):
         self.ctx, self.bank = ctx, bank
         h = ctypes.c_void_p()
-        desc = ServerDesc(int(n_slots), 0, int(pool_bytes))
+        desc = ServerDesc(int(n_slots), int(max_batch), int(pool_bytes), int(batch_pairs))
         _check(load_library().dotpe_server_create(ctx.handle, bank.handle, ctypes.byref(desc),
                                                   ctypes.byref(h)))
         self._h = h

@@ -102,9 +102,103 @@ static void sched_checks() {
   CHECK(max_bytes.load() <= pool);
 }
 
+// batches: an idle slot takes the head and the jobs queued behind it while
+// they fit, up to the batch limit, in order; a job too large for what is
+// left waits for the next batch (and nothing behind it overtakes it)
+static void batch_checks() {
+  const uint64_t pool = 1 << 20;
+  std::mutex m;
+  std::vector<std::vector<int64_t>> batches;
+  {
+    Scheduler::BatchFn fn = [&](int slot, std::vector<Scheduler::BatchItem>& items) {
+      CHECK(slot == 0);
+      std::vector<int64_t> b;
+      for (auto& it : items) {
+        const int64_t id = *(const int64_t*)it.payload;
+        b.push_back(id);
+        it.rc = (int)id;
+        CHECK(it.off % PoolMap::kPoolAlign == 0);
+      }
+      {
+        std::lock_guard<std::mutex> lk(m);
+        batches.push_back(b);
+      }
+      std::this_thread::sleep_for(std::chrono::milliseconds(30));
+    };
+    Scheduler s(1, pool, nullptr, 3, fn);
+    // job 0 runs alone (the slot is idle when it arrives); 1..3 then queue
+    // and run as one batch of 3; 4 (most of the pool) and 5 come next: 4
+    // alone would leave no room for 5, so they run as two batches
+    std::vector<uint64_t> sizes = {1000, 1000, 1000, 1000, 1000000, 100000, 1000};
+    std::vector<int64_t> tickets;
+    auto submit = [&](size_t q) {
+      auto id = std::make_shared<int64_t>((int64_t)q);
+      tickets.push_back(s.submit(sizes[q], [](int, uint64_t) { return -1; }, id));
+    };
+    submit(0);
+    std::this_thread::sleep_for(std::chrono::milliseconds(10));
+    for (size_t q = 1; q < sizes.size(); ++q) submit(q);
+    for (size_t q = 0; q < tickets.size(); ++q) {
+      dotpe::JobTimes t;
+      CHECK(s.wait(tickets[q], &t) == (int)q);
+      CHECK(t.batch >= 1 && t.batch <= 3);
+    }
+  }
+  std::vector<int64_t> flat;
+  for (auto& b : batches) {
+    CHECK(!b.empty() && b.size() <= 3);
+    for (int64_t id : b) flat.push_back(id);
+  }
+  CHECK(flat.size() == 7);
+  for (size_t q = 0; q < flat.size(); ++q) CHECK(flat[q] == (int64_t)q);   // first in, first out
+  CHECK(batches[0].size() == 1 && batches[0][0] == 0);
+  CHECK(batches[1].size() == 3);
+  // job 4 fills the pool: its batch holds no other job
+  for (auto& b : batches)
+    if (std::find(b.begin(), b.end(), 4) != b.end()) CHECK(b.size() == 1);
+}
+
+// the work budget: a batch of several jobs holds at most batch_work units;
+// a job above the budget runs alone
+static void budget_checks() {
+  std::mutex m;
+  std::vector<std::vector<int64_t>> batches;
+  {
+    Scheduler::BatchFn fn = [&](int, std::vector<Scheduler::BatchItem>& items) {
+      std::vector<int64_t> b;
+      for (auto& it : items) {
+        b.push_back(*(const int64_t*)it.payload);
+        it.rc = 0;
+      }
+      {
+        std::lock_guard<std::mutex> lk(m);
+        batches.push_back(b);
+      }
+      std::this_thread::sleep_for(std::chrono::milliseconds(30));
+    };
+    Scheduler s(1, 1 << 20, nullptr, 8, fn, 10.0);
+    // 0 alone (idle slot); then [1, 2, 3] (4 + 3 + 3 = 10); [4] (50, over
+    // the budget, alone); [5, 6] (6 + 4); [7]
+    std::vector<double> work = {1, 4, 3, 3, 50, 6, 4, 9};
+    std::vector<int64_t> tickets;
+    auto submit = [&](size_t q) {
+      auto id = std::make_shared<int64_t>((int64_t)q);
+      tickets.push_back(s.submit(100, [](int, uint64_t) { return -1; }, id, work[q]));
+    };
+    submit(0);
+    std::this_thread::sleep_for(std::chrono::milliseconds(10));
+    for (size_t q = 1; q < work.size(); ++q) submit(q);
+    for (int64_t t : tickets) CHECK(s.wait(t, nullptr) == 0);
+  }
+  const std::vector<std::vector<int64_t>> want = {{0}, {1, 2, 3}, {4}, {5, 6}, {7}};
+  CHECK(batches == want);
+}
+
 int main() {
   pool_checks();
   sched_checks();
+  batch_checks();
+  budget_checks();
   std::printf("serving_check OK\n");
   return 0;
 }
