@@ -143,6 +143,7 @@ struct dotpe_event {
   float2* b_nrm = nullptr;     // split precisions: per row of B, Ah, Bh, norms of the hi
   float2* ah_nrm = nullptr;    //   and left-out parts (the bound pass's margin)
   float2* bh_nrm = nullptr;
+  bool norms_done = false;     // b_nrm, ah_nrm, bh_nrm computed (before the first bound pass)
   double2* Q = nullptr;
   double* R2 = nullptr;
   double2* R = nullptr;
@@ -452,6 +453,19 @@ void launch_norms(int prec, const void* P0, const void* P1, int64_t n_rows, int6
     hipLaunchKernelGGL(k_operand_norms<kFP16X2>, g, dim3(256), 0, s, P0, P1, n_rows, K, rg, out);
   else
     hipLaunchKernelGGL(k_operand_norms<kBF16X2>, g, dim3(256), 0, s, P0, P1, n_rows, K, rg, out);
+}
+
+// the per-row norms of the event's split operands that the bound pass's
+// margin takes, computed once, before the event's first bound pass
+void event_norms(dotpe_event* ev, hipStream_t s) {
+  if (ev->norms_done) return;
+  const dotpe_bank* bk = ev->bank;
+  const ModeTables& mt = bk->mt;
+  launch_norms(bk->prec, ev->B[0], ev->B[1], ev->n_ext_p, bk->K2, group_ranges(mt), ev->b_nrm, s);
+  launch_norms(bk->prec, ev->Ah[0], ev->Ah[1], ev->n_sub, ev->KH, output_ranges(mt.G), ev->ah_nrm, s);
+  launch_norms(bk->prec, ev->Bh[0], ev->Bh[1], ev->n_ext_p, ev->KH, output_ranges(mt.G), ev->bh_nrm,
+               s);
+  ev->norms_done = true;
 }
 
 // FAST (evidence pass only): every pair through the bound first, one full
@@ -1102,10 +1116,6 @@ int set_event_impl(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc*
     case kFP16X2: launch_hh<kFP16X2>(ev, st.w, st.whh); break;
     default: launch_hh<kBF16X2>(ev, st.w, st.whh); break;
   }
-  launch_norms(bk->prec, ev->B[0], ev->B[1], ev->n_ext_p, bk->K2, group_ranges(mt), ev->b_nrm, s);
-  launch_norms(bk->prec, ev->Ah[0], ev->Ah[1], ev->n_sub, ev->KH, output_ranges(mt.G), ev->ah_nrm, s);
-  launch_norms(bk->prec, ev->Bh[0], ev->Bh[1], ev->n_ext_p, ev->KH, output_ranges(mt.G), ev->bh_nrm,
-               s);
   hipError_t e_dd = hipSuccess;
   if (D.rb) {
     // (d|d) as given (full resolution)
@@ -1362,6 +1372,7 @@ static int evidence_pass(dotpe_ctx* ctx, dotpe_event* ev, double cut_delta,
   if (timed) HIP_OK(hipEventRecord(ev->ev_t[1], s));
   if (pl.may_cut) {
     if (pl.bound_pass) {
+      event_norms(ev, s);
       if ((rc = launch_fused<kBound>(prec, a, pl.cut_grid, s))) return rc;
       if (timed) HIP_OK(hipEventRecord(ev->ev_t[3], s));
       if ((rc = launch_fused<kSurvivors>(prec, a, pl.surv_grid, s))) return rc;
@@ -1498,8 +1509,10 @@ static int evidence_pass_packed(dotpe_ctx* ctx, dotpe_event* const* evs, int n,
   }
   HIP_OK(hipMemcpyAsync(pb->d_args, pb->h_args, sizeof(FusedArgs) * n, hipMemcpyHostToDevice, s));
   int rc;
-  for (int k = 0; k < n; ++k)
+  for (int k = 0; k < n; ++k) {
     if ((rc = pass_head(evs[k], pb->h_args[k], s))) return rc;
+    if (pl[k].bound_pass) event_norms(evs[k], s);
+  }
   std::vector<int64_t> g(n);
   auto stage = [&](int mode, int64_t chunk, auto grid_of) -> int {
     for (int k = 0; k < n; ++k) g[k] = grid_of(k);
@@ -1547,11 +1560,33 @@ static int evidence_topk(dotpe_event* ev, uint64_t n_cand_raw, dotpe_evidence_re
   if (n2 > ncand)
     hipLaunchKernelGGL(k_fill_cand, dim3((unsigned)((n2 - ncand + 255) / 256)), dim3(256), 0, s,
                        buf, ncand, n2);
-  for (int64_t k = 2; k <= n2; k <<= 1)
-    for (int64_t j = k >> 1; j > 0; j >>= 1)
-      hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, buf,
-                         n2, j, k);
   const int64_t take = std::min<int64_t>(ev->top_k, ncand);
+  if (take <= kTopkChunk) {
+    // sorted chunks, then pairwise merges keeping the best chunk of each pair
+    const int C = (int)std::min<int64_t>(kTopkChunk, n2);
+    const size_t lds = (size_t)C * 4 * sizeof(double);
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+      const int most = kTopkChunk * 4 * (int)sizeof(double);
+      if (hipFuncSetAttribute((const void*)k_topk_chunks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              most) != hipSuccess ||
+          hipFuncSetAttribute((const void*)k_topk_merge, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              most) != hipSuccess)
+        (void)hipGetLastError();
+    });
+    const int64_t n_chunks = n2 / C;
+    hipLaunchKernelGGL(k_topk_chunks, dim3((unsigned)n_chunks), dim3(256), lds, s, buf, C);
+    for (int64_t st = 1; st < n_chunks; st <<= 1)
+      hipLaunchKernelGGL(k_topk_merge, dim3((unsigned)(n_chunks / (2 * st))), dim3(256), lds, s, buf,
+                         C, st);
+  } else {
+    // a longer top-k: the whole buffer through the bitonic network
+    for (int64_t k = 2; k <= n2; k <<= 1)
+      for (int64_t j = k >> 1; j > 0; j >>= 1)
+        hipLaunchKernelGGL(k_bitonic_step, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s,
+                           buf, n2, j, k);
+  }
+  HIP_OK(hipGetLastError());
   std::vector<double> h(take * 4);
   HIP_OK(hipMemcpyAsync(h.data(), buf, take * 32, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -2259,6 +2294,7 @@ int dotpe_debug_bound(dotpe_ctx* ctx, dotpe_event* ev, float* out) {
   int rc = dev_alloc(ctx, (void**)&buf, n, &owned, &acct);
   if (rc) return rc;
   a.bound_out = buf;
+  event_norms(ev, ev->stream);
   const int64_t n_big = ((a.n_tiles_m + 1) / 2) * ((a.n_tiles_n + 1) / 2);
   rc = launch_fused<kBound>(prec, a, round_up(n_big, 8), ev->stream);
   hipError_t e = rc ? hipSuccess : hipMemcpyAsync(out, buf, n, hipMemcpyDeviceToHost, ev->stream);

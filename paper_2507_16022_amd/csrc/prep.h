@@ -885,6 +885,70 @@ __global__ void k_bitonic_step(double* __restrict__ c, int64_t n, int64_t j, int
     }
   }
 }
+// Top-k by sorted chunks and pairwise merges: k_topk_chunks sorts each chunk
+// of C records (a power of two, <= kTopkChunk) in LDS; k_topk_merge then
+// replaces chunk a = 2 p s by the best C records of chunks a and a + s (both
+// sorted), which are max(A[t], B[C - 1 - t]) over t -- the upper half of the
+// half-cleaner applied to the bitonic sequence A, reversed B -- and sorts
+// that bitonic half with the merge network.  After log2(n / C) merge rounds
+// (s = 1, 2, 4, ...) the first chunk holds the best C records of all n in
+// order: the first C records of a full sort.
+constexpr int kTopkChunk = 4096;
+
+__device__ __forceinline__ bool cand_before_lds(const double* x, const double* y) {
+  if (x[0] != y[0]) return x[0] > y[0];
+  if (x[1] != y[1]) return x[1] < y[1];
+  return x[2] < y[2];
+}
+
+// compare-exchange steps (j) of the bitonic network of stage k over C records
+// in LDS, by all threads of the block (k = C: one sorted run)
+__device__ __forceinline__ void lds_bitonic_steps(double* r, int C, int k, int j_first) {
+  for (int j = j_first; j > 0; j >>= 1) {
+    for (int t = threadIdx.x; t < C / 2; t += blockDim.x) {
+      const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+      const int l = i | j;
+      double* x = r + 4 * i;
+      double* y = r + 4 * l;
+      const bool up = (i & k) == 0;
+      if (up ? cand_before_lds(y, x) : cand_before_lds(x, y)) {
+        const double4 tx = make_double4(x[0], x[1], x[2], x[3]);
+        x[0] = y[0]; x[1] = y[1]; x[2] = y[2]; x[3] = y[3];
+        y[0] = tx.x; y[1] = tx.y; y[2] = tx.z; y[3] = tx.w;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_topk_chunks(double* __restrict__ c, int C) {
+  extern __shared__ __align__(16) double rec[];
+  double* g = c + (int64_t)blockIdx.x * C * 4;
+  for (int t = threadIdx.x; t < C * 4; t += blockDim.x) rec[t] = g[t];
+  __syncthreads();
+  for (int k = 2; k <= C; k <<= 1) lds_bitonic_steps(rec, C, k, k >> 1);
+  for (int t = threadIdx.x; t < C * 4; t += blockDim.x) g[t] = rec[t];
+}
+
+__global__ __launch_bounds__(256) void k_topk_merge(double* __restrict__ c, int C, int64_t s) {
+  extern __shared__ __align__(16) double rec[];
+  const int64_t a = 2 * (int64_t)blockIdx.x * s;
+  double* A = c + a * C * 4;
+  const double* B = c + (a + s) * C * 4;
+  for (int t = threadIdx.x; t < C; t += blockDim.x) {
+    const double* x = A + 4 * t;
+    const double* y = B + 4 * (C - 1 - t);
+    const double* w = cand_before_lds(y, x) ? y : x;
+    rec[4 * t] = w[0];
+    rec[4 * t + 1] = w[1];
+    rec[4 * t + 2] = w[2];
+    rec[4 * t + 3] = w[3];
+  }
+  __syncthreads();
+  lds_bitonic_steps(rec, C, C, C >> 1);
+  for (int t = threadIdx.x; t < C * 4; t += blockDim.x) A[t] = rec[t];
+}
+
 __global__ void k_zero(double* __restrict__ x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
