@@ -673,22 +673,25 @@ __device__ __forceinline__ void survivor_pass(const FusedArgs& a, int64_t wg_id,
       const int64_t ie = tm * 64 + (rc >> 8), e = tn * 64 + (rc & 255);
       const int64_t i = a.sub_idx ? a.sub_idx[ie] : a.sub0 + ie;
       // X_g: lane l takes half l % 2 (8 positions of each slice) of chunks
-      // l / 2, l / 2 + 32, ...
+      // l / 2, l / 2 + 32, ...  The bank row comes from the row-major copy
+      // (64 contiguous bytes per chunk and array: a wave reads whole lines),
+      // the extrinsic row from the fragment layout (16 bytes per chunk,
+      // slice and half; its 2^14 rows stay in the caches)
       double xr[G], xi[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) { xr[g] = 0.0; xi[g] = 0.0; }
       const int h = lane & 1;
-      const int64_t arow = ((i >> 5) * (a.K2 >> 5)) * 1024 + (i & 31) * 8 + h * 256;
+      const int64_t arow = i * a.K2 + h * 8;
       const int64_t brow = ((e >> 5) * (a.K2 >> 5)) * 1024 + (e & 31) * 8 + h * 256;
       for (int c = lane >> 1; c < nch; c += 32) {
-        const H* a0h = (const H*)a.A0 + arow + (int64_t)c * 1024;
-        const H* a0l = (const H*)a.A1 + arow + (int64_t)c * 1024;
+        const H* a0h = (const H*)a.R0 + arow + (int64_t)c * 32;
+        const H* a0l = (const H*)a.R1 + arow + (int64_t)c * 32;
         const H* b0h = (const H*)a.B0 + brow + (int64_t)c * 1024;
         const H* b0l = (const H*)a.B1 + brow + (int64_t)c * 1024;
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const double x0 = val(a0h, a0l, j), x1 = val(a0h + 512, a0l + 512, j);
+          const double x0 = val(a0h, a0l, j), x1 = val(a0h + 16, a0l + 16, j);
           const double y0 = val(b0h, b0l, j), y1 = val(b0h + 512, b0l + 512, j);
           re += x0 * y0 + x1 * y1;      // A [hr | hi'] . B_re [Br | -Bi]
           im += x1 * y0 - x0 * y1;      // A . B_im, B_im = [-(B_re slice 1) | B_re slice 0]

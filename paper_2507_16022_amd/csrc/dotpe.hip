@@ -113,6 +113,8 @@ struct dotpe_bank {
   std::vector<double> f_host;
   void* A0 = nullptr;
   void* A1 = nullptr;
+  void* R0 = nullptr;           // split precisions: the same hi and lo parts row by row
+  void* R1 = nullptr;           //   ([n_wf][K2]), read by the survivor pass one row at a time
   double* row_scale = nullptr;
   float2* nrm = nullptr;        // split precisions: per row, norms of the hi and left-out parts
   double* ln_w = nullptr;
@@ -396,7 +398,8 @@ int build_hh_terms(const ModeTables& mt, int n_det, std::vector<int>* terms, int
 template <int PREC>
 void launch_bank_convert(const double* h, dotpe_bank* bk, int* err, hipStream_t s) {
   hipLaunchKernelGGL(k_bank_convert<PREC>, dim3((unsigned)bk->n_wf), dim3(256), 0, s, h, bk->n_wf,
-                     bk->n_c, bk->n_b, bk->n_bp, bk->mt, bk->A0, bk->A1, bk->row_scale, err);
+                     bk->n_c, bk->n_b, bk->n_bp, bk->mt, bk->A0, bk->A1, bk->row_scale, err, bk->R0,
+                     bk->R1);
 }
 
 template <int PREC>
@@ -415,10 +418,11 @@ void launch_hh(dotpe_event* ev, const double* w, const double2* whh) {
   const size_t rb = PREC == kFP64 ? sizeof(double2) : sizeof(float2);   // staged row value
   size_t sh = (size_t)bk->n_c * (bk->n_bp + 1) * rb + (size_t)ev->n_det * (bk->n_b + 1) * sizeof(double);
   if (sh > 65536) sh = 0;
-  hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(64), sh, ev->stream,
+  // four waves per row, each summing a quarter of the bins
+  hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(256), sh, ev->stream,
                      ev->n_sub, ev->sub_idx, ev->sub0, bk->A0, bk->A1, bk->row_scale, bk->n_bp,
                      bk->n_b, ev->n_det, w, whh, bk->mt, ev->hh_terms, ev->KH, ev->Ah[0],
-                     ev->Ah[1], ev->ah_scale);
+                     ev->Ah[1], ev->ah_scale, bk->R0, bk->R1);
   hipLaunchKernelGGL(k_build_Bhh<PREC>, dim3((unsigned)ev->n_ext_p), dim3(64), 0, ev->stream,
                      ev->n_ext, ev->n_ext_p, ev->n_det, ev->Q, bk->mt, ev->hh_terms, ev->KH,
                      ev->Bh[0], ev->Bh[1], ev->bh_scale);
@@ -496,6 +500,8 @@ FusedArgs make_args(dotpe_ctx* ctx, dotpe_event* ev) {
   std::memset(&a, 0, sizeof(a));
   a.A0 = bk->A0;
   a.A1 = bk->A1;
+  a.R0 = bk->R0;
+  a.R1 = bk->R1;
   a.row_scale = bk->row_scale;
   a.ln_w_bank = bk->ln_w;
   a.sub_idx = ev->sub_idx;
@@ -680,6 +686,9 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
   if ((rc = dev_alloc(ctx, &bk->A0, nA * esz, &owned, &bk->bytes))) return cleanup(rc);
   if (bk->prec != kFP64) {
     if ((rc = dev_alloc(ctx, &bk->A1, nA * esz, &owned, &bk->bytes))) return cleanup(rc);
+    const size_t nR = (size_t)bk->n_wf * bk->K2;
+    if ((rc = dev_alloc(ctx, &bk->R0, nR * esz, &owned, &bk->bytes))) return cleanup(rc);
+    if ((rc = dev_alloc(ctx, &bk->R1, nR * esz, &owned, &bk->bytes))) return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&bk->row_scale, bk->n_wf * 8, &owned, &bk->bytes)))
       return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&bk->nrm, bk->n_wf * bk->mt.G * sizeof(float2), &owned,
@@ -735,6 +744,8 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
       view.n_wf = nr;
       view.A0 = (char*)bk->A0 + (size_t)r0 * bk->K2 * esz;
       view.A1 = bk->A1 ? (char*)bk->A1 + (size_t)r0 * bk->K2 * esz : nullptr;
+      view.R0 = bk->R0 ? (char*)bk->R0 + (size_t)r0 * bk->K2 * esz : nullptr;
+      view.R1 = bk->R1 ? (char*)bk->R1 + (size_t)r0 * bk->K2 * esz : nullptr;
       view.row_scale = bk->row_scale ? bk->row_scale + r0 : nullptr;
       switch (bk->prec) {
         case kFP64: launch_bank_convert<kFP64>(stagebuf, &view, err, s); break;
@@ -766,7 +777,7 @@ int dotpe_load_bank(dotpe_ctx* ctx, const dotpe_bank_desc* d, dotpe_bank** out) 
 int dotpe_free_bank(dotpe_ctx* ctx, dotpe_bank* bk) {
   if (!ctx || !bk) return DOTPE_OK;
   (void)hipSetDevice(ctx->device);
-  for (void* p : {bk->A0, bk->A1, (void*)bk->row_scale, (void*)bk->nrm, (void*)bk->f,
+  for (void* p : {bk->A0, bk->A1, bk->R0, bk->R1, (void*)bk->row_scale, (void*)bk->nrm, (void*)bk->f,
                   (void*)bk->ln_w})
     if (p) (void)hipFree(p);
   ctx->bytes -= bk->bytes;
@@ -1431,6 +1442,8 @@ static int launch_packed_pass(int prec, int G, int mode, int n, const int64_t* g
   p.chunk = chunk;
   p.A0 = h_args[0].A0;
   p.A1 = h_args[0].A1;
+  p.R0 = h_args[0].R0;
+  p.R1 = h_args[0].R1;
   p.row_scale = h_args[0].row_scale;
   p.ln_w_bank = h_args[0].ln_w_bank;
   p.a_nrm = h_args[0].a_nrm;

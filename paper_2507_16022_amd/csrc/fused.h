@@ -18,6 +18,9 @@ struct FusedArgs {
   // bank operand (n_wf rows of K2)
   const void* A0;
   const void* A1;
+  // split precisions: the bank's hi and lo parts row by row ([n_wf][K2])
+  const void* R0;
+  const void* R1;
   const double* row_scale;
   const double* ln_w_bank;
   // subset
@@ -116,6 +119,8 @@ __device__ __forceinline__ FusedArgs pack_args(const PackLaunch& p, int e, int q
   const PackPtrs& r = p.ptr[q];
   a.A0 = p.A0;
   a.A1 = p.A1;
+  a.R0 = p.R0;
+  a.R1 = p.R1;
   a.row_scale = p.row_scale;
   a.ln_w_bank = p.ln_w_bank;
   a.a_nrm = p.a_nrm;

@@ -59,6 +59,8 @@ struct PackLaunch {
   // pointers of the bank and the context (the same for every event)
   const void* A0;
   const void* A1;
+  const void* R0;
+  const void* R1;
   const double* row_scale;
   const double* ln_w_bank;
   const float2* a_nrm;

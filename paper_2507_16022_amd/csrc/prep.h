@@ -40,7 +40,8 @@ template <int PREC>
 __global__ void k_bank_convert(const double* __restrict__ h, int64_t n_wf, int n_c_in, int n_b,
                                int n_bp, ModeTables mt, void* __restrict__ A0,
                                void* __restrict__ A1, double* __restrict__ row_scale,
-                               int* __restrict__ err) {
+                               int* __restrict__ err, void* __restrict__ R0,
+                               void* __restrict__ R1) {
   const int64_t row = blockIdx.x;
   if (row >= n_wf) return;
   const double* hr = h + (size_t)row * n_c_in * n_b * 2;
@@ -82,15 +83,29 @@ __global__ void k_bank_convert(const double* __restrict__ h, int64_t n_wf, int n
       _Float16* Ah = (_Float16*)A0;
       _Float16* Al = (_Float16*)A1;
       _Float16 hr_ = (_Float16)re, hi_ = (_Float16)im;
+      const _Float16 lr_ = (_Float16)(re - (double)hr_), li_ = (_Float16)(im - (double)hi_);
       Ah[o] = hr_; Ah[o16] = hi_;
-      Al[o] = (_Float16)(re - (double)hr_); Al[o16] = (_Float16)(im - (double)hi_);
+      Al[o] = lr_; Al[o16] = li_;
+      if (R0) {
+        _Float16* Rh = (_Float16*)R0 + row * K2;
+        _Float16* Rl = (_Float16*)R1 + row * K2;
+        Rh[base] = hr_; Rh[base + 16] = hi_;
+        Rl[base] = lr_; Rl[base + 16] = li_;
+      }
     } else {
       __bf16* Ah = (__bf16*)A0;
       __bf16* Al = (__bf16*)A1;
       __bf16 hr_ = (__bf16)(float)re, hi_ = (__bf16)(float)im;
+      const __bf16 lr_ = (__bf16)(float)(re - (double)(float)hr_);
+      const __bf16 li_ = (__bf16)(float)(im - (double)(float)hi_);
       Ah[o] = hr_; Ah[o16] = hi_;
-      Al[o] = (__bf16)(float)(re - (double)(float)hr_);
-      Al[o16] = (__bf16)(float)(im - (double)(float)hi_);
+      Al[o] = lr_; Al[o16] = li_;
+      if (R0) {
+        __bf16* Rh = (__bf16*)R0 + row * K2;
+        __bf16* Rl = (__bf16*)R1 + row * K2;
+        Rh[base] = hr_; Rh[base + 16] = hi_;
+        Rl[base] = lr_; Rl[base + 16] = li_;
+      }
     }
   }
 }
@@ -670,15 +685,19 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
                                 int n_det, const double* __restrict__ w,
                                 const double2* __restrict__ whh, ModeTables mt,
                                 const int* __restrict__ terms, int KH, void* __restrict__ H0,
-                                void* __restrict__ H1, double* __restrict__ hscale) {
+                                void* __restrict__ H1, double* __restrict__ hscale,
+                                const void* __restrict__ R0, const void* __restrict__ R1) {
   // the row [n_c][n_bp] then w [n_det][n_b], when they fit.  A split value
   // hi + lo spans at most 23 significant bits, so float holds it exactly.
   typedef typename std::conditional<PREC == kFP64, double2, float2>::type RB;
   extern __shared__ __align__(16) unsigned char hh_smem[];
   RB* rowbuf = (RB*)hh_smem;
-  __shared__ double2 Hs[kMaxDet * kMaxNP];
+  // the block's waves split the bins: wave q sums bins [q n_b / nq, (q + 1) n_b / nq)
+  // of every (detector, channel pair), and the nq partial sums are added in order
+  __shared__ double2 Hq[4][kMaxDet * kMaxNP];
   __shared__ double vals[256];
-  __shared__ double red[64];
+  __shared__ double red[256];
+  const int nq = (int)blockDim.x / 64, wq = (int)threadIdx.x / 64, u = (int)threadIdx.x % 64;
   const int64_t ie = blockIdx.x;
   if (ie >= n_sub) return;
   const int64_t i = sub_idx ? sub_idx[ie] : sub0 + ie;
@@ -691,16 +710,21 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   double* wl = (double*)(rowbuf + mt.n_c * rs);
   if (staged) {
     // the row in pieces of 8 consecutive positions (16 bytes per operand
-    // array in the split layouts): 8 bins of the real or the imaginary part
+    // array in the split layouts): 8 bins of the real or the imaginary part;
+    // from the row-major copy of the split bank when there is one (whole
+    // lines), else from the fragment layout (16 bytes of each line)
+    const bool rm = PREC != kFP64 && R0 != nullptr;
+    const void* S0 = rm ? R0 : A0;
+    const void* S1 = rm ? R1 : A1;
     for (int pc = threadIdx.x; pc < (int)(K2 / 8); pc += blockDim.x) {
-      const int64_t o = op_index<PREC>(i, (int64_t)pc * 8, K2);
+      const int64_t o = rm ? i * K2 + (int64_t)pc * 8 : op_index<PREC>(i, (int64_t)pc * 8, K2);
       double v[8];
       if (PREC == kFP64) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = ((const double*)A0)[o + j];
       } else {
-        const uint4 hq = *(const uint4*)((const uint16_t*)A0 + o);
-        const uint4 lq = *(const uint4*)((const uint16_t*)A1 + o);
+        const uint4 hq = *(const uint4*)((const uint16_t*)S0 + o);
+        const uint4 lq = *(const uint4*)((const uint16_t*)S1 + o);
         const unsigned hw[4] = {hq.x, hq.y, hq.z, hq.w}, lw[4] = {lq.x, lq.y, lq.z, lq.w};
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -725,14 +749,15 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   }
   double sc = row_scale ? row_scale[i] : 1.0;
   sc = sc * sc;
-  for (int t = threadIdx.x; t < n_det * mt.NP; t += blockDim.x) {
+  const int b_lo = wq * n_b / nq, b_hi = (wq + 1) * n_b / nq;
+  for (int t = u; t < n_det * mt.NP; t += 64) {
     int k = t / mt.NP, p = t % mt.NP;
     int c = mt.pc[p], c2 = mt.pc2[p];
     double2 acc = make_double2(0.0, 0.0);
     if (whh) {
       // relative binning: a complex weight per channel pair and bin
       const double2* Wp = whh + ((int64_t)k * mt.NP + p) * n_b;
-      for (int b = 0; b < n_b; ++b) {
+      for (int b = b_lo; b < b_hi; ++b) {
         const double2 a = staged ? to_d2(rowbuf[c * rs + b]) : bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
         const double2 a2 = staged ? to_d2(rowbuf[c2 * rs + b]) : bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
         const double2 u = cmul(Wp[b], cmul(cconj(a), a2));
@@ -742,8 +767,8 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
     } else if (staged) {
       // two partial sums, so that consecutive bins do not wait on each other
       double2 acc2 = make_double2(0.0, 0.0);
-      int b = 0;
-      for (; b + 1 < n_b; b += 2) {
+      int b = b_lo;
+      for (; b + 1 < b_hi; b += 2) {
         const double2 v0 = cmul(cconj(to_d2(rowbuf[c * rs + b])), to_d2(rowbuf[c2 * rs + b]));
         const double2 v1 = cmul(cconj(to_d2(rowbuf[c * rs + b + 1])), to_d2(rowbuf[c2 * rs + b + 1]));
         const double w0 = wl[k * ws + b], w1 = wl[k * ws + b + 1];
@@ -752,7 +777,7 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
         acc2.x += w1 * v1.x;
         acc2.y += w1 * v1.y;
       }
-      if (b < n_b) {
+      if (b < b_hi) {
         const double2 v0 = cmul(cconj(to_d2(rowbuf[c * rs + b])), to_d2(rowbuf[c2 * rs + b]));
         acc.x += wl[k * ws + b] * v0.x;
         acc.y += wl[k * ws + b] * v0.y;
@@ -760,7 +785,7 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
       acc.x += acc2.x;
       acc.y += acc2.y;
     } else {
-      for (int b = 0; b < n_b; ++b) {
+      for (int b = b_lo; b < b_hi; ++b) {
         double2 a = bank_value<PREC>(A0, A1, i, K2, c, b, n_bp);
         double2 a2 = bank_value<PREC>(A0, A1, i, K2, c2, b, n_bp);
         double2 v = cmul(cconj(a), a2);      // h_c conj(h_c') = conj(A_c) A_c'
@@ -769,9 +794,19 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
         acc.y += ww * v.y;
       }
     }
-    Hs[k * mt.NP + p] = make_double2(acc.x * sc, acc.y * sc);
+    Hq[wq][t] = acc;
   }
   __syncthreads();
+  for (int t = threadIdx.x; t < n_det * mt.NP; t += blockDim.x) {
+    double2 h = Hq[0][t];
+    for (int q = 1; q < nq; ++q) {
+      h.x += Hq[q][t].x;
+      h.y += Hq[q][t].y;
+    }
+    Hq[0][t] = make_double2(h.x * sc, h.y * sc);
+  }
+  __syncthreads();
+  const double2* Hs = Hq[0];
   double mx = 0.0;
   for (int j = threadIdx.x; j < KH; j += blockDim.x) {
     double v = term_value(terms[j], Hs, mt, true);
