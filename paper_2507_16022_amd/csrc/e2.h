@@ -180,16 +180,8 @@ __device__ __forceinline__ void e2_pass(const FusedArgs& a, int64_t wg_id, int64
       const unsigned long long ob_bits = order_bits(lnp);
       const unsigned long long prev = atomicMax(&tile_lnp_max, ob_bits);
       const double tmax = order_value(prev > ob_bits ? prev : ob_bits);
-      if (lnp >= fmax(thr_topk_glob, tmax - a.topk_window)) {
-        const unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
-        if ((int64_t)slot < a.cand_cap) {
-          double* cd = a.cand + 4 * slot;
-          cd[0] = lnp;
-          cd[1] = rowd[tr * 4 + 3];
-          cd[2] = (double)e;
-          cd[3] = (double)ob;
-        }
-      }
+      append_candidate(a, lnp >= fmax(thr_topk_glob, tmax - a.topk_window), lnp, rowd[tr * 4 + 3],
+                       (double)e, ob);
     }
     tile_partial<NW>(a, ev, n_pairs_i, n_bounded_i, red, &tile_lnp_max, t);
     // (every pair's ln p and the tile maximum are final: tile_partial has a

@@ -281,6 +281,31 @@ enum Mode { kEval = 0, kEvidence = 1, kPilot = 2, kBound = 3, kSurvivors = 4, kC
 // zero.  Then the fast or bound pass bounds every pair and lists the tiles
 // it leaves to the coefficient route; otherwise that route takes every
 // tile.  Every kernel of the pass takes this decision from device memory.
+// Append (ln p, i, e, best phase) to the top-k candidate buffer for the
+// lanes with `want` set: one atomic per wave for all of them (the order of
+// the buffer is irrelevant; it is sorted).  Called by the active lanes of
+// a wave; those without a candidate pass want = false.
+__device__ __forceinline__ void append_candidate(const FusedArgs& a, bool want, double lnp,
+                                                 double i, double e, int ob) {
+  const unsigned long long m = __ballot(want);
+  if (!want) return;
+  const unsigned lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const int leader = __builtin_ctzll(m);
+  unsigned long long base = 0;
+  if ((int)lane == leader)
+    base = atomicAdd((unsigned long long*)&a.state[2], (unsigned long long)__popcll(m));
+  base = __shfl(base, leader, 64);
+  const unsigned long long slot =
+      base + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  if ((int64_t)slot < a.cand_cap) {
+    double* cd = a.cand + 4 * slot;
+    cd[0] = lnp;
+    cd[1] = i;
+    cd[2] = e;
+    cd[3] = (double)ob;
+  }
+}
+
 __device__ __forceinline__ bool cut_on(const FusedArgs& a) {
   return a.cut_delta > 0.0 && __longlong_as_double(a.state[3]) - a.cut_delta > 0.0;
 }
@@ -1219,16 +1244,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& a, unsigned char* sm
         unsigned long long prev = atomicMax(tile_lnp_max, ob_bits);
         double tmax = order_value(prev > ob_bits ? prev : ob_bits);
         double thr_k = fmax(thr_topk_glob, tmax - a.topk_window);
-        if (lnp >= thr_k) {
-          unsigned long long slot = atomicAdd((unsigned long long*)&a.state[2], 1ull);
-          if ((int64_t)slot < a.cand_cap) {
-            double* cd = a.cand + 4 * slot;
-            cd[0] = lnp;
-            cd[1] = rowd[tr * 4 + 3];
-            cd[2] = (double)e;
-            cd[3] = (double)ob;
-          }
-        }
+        append_candidate(a, lnp >= thr_k, lnp, rowd[tr * 4 + 3], (double)e, ob);
       }
     }
   };
