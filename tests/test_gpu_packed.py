@@ -113,3 +113,70 @@ def alone_kind(r):
     if r["cut_delta_used"] <= 0.0:
         return "nocut"
     return "bound" if r["n_tiles_listed"] > 0 else "fast"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x2"])
+def test_packed_batch_other_precisions(precision):
+    """The packed launches of the FP64 and BF16x2 kernels (pilot, fast pass,
+    coefficient route): small events served in one batch equal each event
+    alone."""
+    from paper_2507_16022_amd import dotpe
+    ctx = dotpe.Context(0)
+    bank_wl = W.make_workload(21, n_int=2048, n_ext=8, n_bins=256, modes=W.MODES_HM, dets="HLV",
+                              n_phi=32, snr=20.0, mc_range=(5.0, 80.0), q_range=(0.1, 1.0),
+                              chi_range=(-0.9, 0.9))
+    bank = ctx.load_bank(bank_wl.h, bank_wl.modes, bank_wl.f, precision=precision)
+    specs = [
+        event(bank_wl, 600, 512, "HLV", 18.0, sub_start=0, sub_count=2048),
+        event(bank_wl, 601, 256, "HL", 12.0, sub_start=100, sub_count=700),
+        event(bank_wl, 602, 384, "HLV", 5.0, sub_start=1024, sub_count=1024),
+        event(bank_wl, 603, 200, "HLV", 25.0, cut=0.0, sub_start=7, sub_count=300),
+        event(bank_wl, 604, 96, "HL", 22.0, sub_start=1500, sub_count=548),
+    ]
+    srv = dotpe.Server(ctx, bank, n_slots=1, pool_bytes=4 << 30, max_batch=8, batch_pairs=1 << 40)
+    tickets = [srv.submit(**kw) for kw in specs]
+    got = [srv.wait(t) for t in tickets]
+    srv.close()
+    batches = [info["batch"] for _, info in got]
+    print(f"{precision}: batch sizes {batches}", flush=True)
+    assert max(batches) >= 2, batches
+    for (r, info), kw in zip(got, specs):
+        ref = alone(ctx, bank, kw)
+        assert info["status"] == 0
+        assert abs(r["ln_z"] - ref["ln_z"]) <= TOL and abs(r["ln_z_upper"] - ref["ln_z_upper"]) <= TOL
+        for k in ("n_pairs", "n_pairs_bounded", "n_triples_marg", "n_passes", "topk_count"):
+            assert r[k] == ref[k], k
+        if r["topk_exact"]:
+            n = r["topk_count"]
+            assert np.array_equal(r["topk_i"][:n], ref["topk_i"][:n])
+            assert np.array_equal(r["topk_e"][:n], ref["topk_e"][:n])
+    bank.close()
+    ctx.close()
+
+
+def test_packed_batch_with_a_failing_event(setup):
+    """An event whose staging fails on the device (strain so large that the
+    extrinsic operand overflows, which the conversion kernel flags) reports
+    its error; the events batched with it complete as they would alone."""
+    dotpe, ctx, bank, bank_wl = setup
+    good = [event(bank_wl, 700 + q, 256, "HLV", 15.0, sub_start=512 * q, sub_count=512)
+            for q in range(3)]
+    bad = event(bank_wl, 710, 256, "HLV", 15.0, sub_start=0, sub_count=512)
+    bad["d"] = bad["d"].copy()
+    bad["d"][0, 5] = 1e308
+    srv = dotpe.Server(ctx, bank, n_slots=1, pool_bytes=4 << 30, max_batch=8, batch_pairs=1 << 40)
+    specs = [good[0], bad, good[1], good[2]]
+    tickets = [srv.submit(**kw) for kw in specs]
+    outcomes = []
+    for t in tickets:
+        try:
+            outcomes.append(srv.wait(t))
+        except dotpe.DotpeError as e:
+            outcomes.append(e)
+    srv.close()
+    assert isinstance(outcomes[1], dotpe.DotpeError) and outcomes[1].code == dotpe.E_NUMERIC
+    for q, kw in ((0, good[0]), (2, good[1]), (3, good[2])):
+        r, info = outcomes[q]
+        ref = alone(ctx, bank, kw)
+        assert info["status"] == 0
+        assert abs(r["ln_z"] - ref["ln_z"]) <= TOL
