@@ -559,13 +559,18 @@ __device__ __forceinline__ void bound_pass_tile(const FusedArgs& a, int64_t wg_i
         }
       }
   }
-  // survivors in a fixed order (bn, bm, element, lane)
+  // survivors in a fixed order (bn, bm, element, lane): only the (bn, bit)
+  // columns in which some lane has one are visited
   int n_surv = 0;
+  unsigned cols[2] = {0u, 0u};
   if (__ballot((smask[0] | smask[1]) != 0u)) {
+    auto or_i = [](int x, int y) { return x | y; };
 #pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-      for (int q = 0; q < 32; ++q) n_surv += (int)__popcll(__ballot((smask[bn] >> q) & 1u));
+    for (int bn = 0; bn < 2; ++bn) {
+      cols[bn] = (unsigned)__builtin_amdgcn_readlane(wave_reduce((int)smask[bn], 0, or_i), 63);
+      for (unsigned m = cols[bn]; m; m &= m - 1u)
+        n_surv += (int)__popcll(__ballot((smask[bn] >> __builtin_ctz(m)) & 1u));
+    }
   }
   if (n_surv > kSurvCap) {
     // the whole tile goes to the coefficient route
@@ -582,8 +587,8 @@ __device__ __forceinline__ void bound_pass_tile(const FusedArgs& a, int64_t wg_i
     int run = 0;
 #pragma unroll
     for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-      for (int q = 0; q < 32; ++q) {
+      for (unsigned m = cols[bn]; m; m &= m - 1u) {
+        const int q = __builtin_ctz(m);
         const unsigned long long bal = __ballot((smask[bn] >> q) & 1u);
         if ((smask[bn] >> q) & 1u) {
           const int slot = run + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
