@@ -187,8 +187,13 @@ typedef struct dotpe_event_desc {
 /* Stage an event against a resident bank: copies inputs, builds the
  * extrinsic operand (antenna patterns x time-shift phasors folded over
  * detectors with the data), the per-pair (h|h) coefficient tables and the
- * per-waveform (h|h) sums.  Errors: INVALID_ARG, NUMERIC, OOM, ADMISSION,
- * DEVICE. */
+ * per-waveform (h|h) sums.  The event's device buffers are packed into one
+ * block that the context keeps after dotpe_free_event and hands to the next
+ * event that fits (grown when one needs more), so a stream of events does not
+ * allocate device memory each time; the block counts against the context's
+ * budget until dotpe_destroy.  An event staged while another holds the block
+ * gets buffers of its own, freed by dotpe_free_event.  Errors: INVALID_ARG,
+ * NUMERIC, OOM, ADMISSION, DEVICE. */
 int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bank, const dotpe_event_desc* desc,
                     dotpe_event** out);
 int dotpe_free_event(dotpe_ctx* ctx, dotpe_event* ev);

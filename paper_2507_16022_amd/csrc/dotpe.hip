@@ -97,6 +97,13 @@ struct dotpe_ctx {
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
   std::atomic<uint64_t> bytes{0};   // serving slot threads also release through it
+  // one device block that dotpe_set_event packs an event's buffers into and
+  // keeps after dotpe_free_event for the next event that fits, so that a
+  // stream of events does not allocate and free device memory each time
+  std::mutex ev_mu;
+  char* ev_block = nullptr;
+  uint64_t ev_block_len = 0;
+  bool ev_block_busy = false;
   uint64_t own_bytes = 0;    // the context's own tables (not charged to the budget)
   double* dist_tab = nullptr;
   DistParams* dist_prm = nullptr;   // device copy of the Gauss-Hermite nodes
@@ -146,6 +153,7 @@ struct dotpe_event {
   float2* ah_nrm = nullptr;    //   and left-out parts (the bound pass's margin)
   float2* bh_nrm = nullptr;
   bool norms_done = false;     // b_nrm, ah_nrm, bh_nrm computed (before the first bound pass)
+  bool ctx_block = false;      // its buffers sit in the context's event block
   double2* Q = nullptr;
   double* R2 = nullptr;
   double2* R = nullptr;
@@ -637,6 +645,7 @@ int dotpe_create(int device, uint64_t hbm_budget_bytes, dotpe_ctx** out) {
 int dotpe_destroy(dotpe_ctx* ctx) {
   if (!ctx) return DOTPE_OK;
   (void)hipSetDevice(ctx->device);
+  if (ctx->ev_block) (void)hipFree(ctx->ev_block);
   if (ctx->dist_tab) (void)hipFree(ctx->dist_tab);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -792,6 +801,10 @@ int dotpe_free_event(dotpe_ctx* ctx, dotpe_event* ev) {
   for (void* p : ev->allocs) (void)hipFree(p);
   for (hipEvent_t t : ev->ev_t)
     if (t) (void)hipEventDestroy(t);
+  if (ev->ctx_block) {
+    std::lock_guard<std::mutex> lk(ctx->ev_mu);
+    ctx->ev_block_busy = false;    // kept for the next event
+  }
   ctx->bytes -= ev->bytes;
   delete ev;
   return DOTPE_OK;
@@ -1156,8 +1169,52 @@ extern "C" {
 int dotpe_set_event(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d,
                     dotpe_event** out) {
   if (!ctx || !bk || !d || !out) return fail(DOTPE_E_INVALID_ARG, "NULL argument");
-  return set_event_impl(ctx, bk, d, nullptr, 0,
-                        d->stream ? (hipStream_t)d->stream : ctx->stream, out);
+  hipStream_t s = d->stream ? (hipStream_t)d->stream : ctx->stream;
+  uint64_t need = 0;
+  {
+    EvDims D;
+    std::vector<int> terms;
+    int rc = event_dims(bk, d, &D, &terms);
+    if (rc) return rc;
+    dotpe_event probe;
+    EvStage st;
+    need = block_bytes(event_buffers(D, &probe, &st));
+  }
+  // the context's event block when it is free: grown (freed and allocated
+  // again) when the event needs more; an event set while another holds the
+  // block gets buffers of its own
+  char* block = nullptr;
+  uint64_t len = 0;
+  {
+    std::lock_guard<std::mutex> lk(ctx->ev_mu);
+    if (!ctx->ev_block_busy) {
+      HIP_OK(hipSetDevice(ctx->device));
+      if (ctx->ev_block_len < need) {
+        if (ctx->ev_block) {
+          (void)hipFree(ctx->ev_block);
+          ctx->bytes -= ctx->ev_block_len;
+          ctx->ev_block = nullptr;
+          ctx->ev_block_len = 0;
+        }
+        if (dev_alloc(ctx, (void**)&ctx->ev_block, need, nullptr, nullptr) == DOTPE_OK)
+          ctx->ev_block_len = need;
+      }
+      if (ctx->ev_block) {
+        ctx->ev_block_busy = true;
+        block = ctx->ev_block;
+        len = ctx->ev_block_len;
+      }
+    }
+  }
+  if (!block) return set_event_impl(ctx, bk, d, nullptr, 0, s, out);
+  int rc = set_event_impl(ctx, bk, d, block, len, s, out);
+  if (rc) {
+    std::lock_guard<std::mutex> lk(ctx->ev_mu);
+    ctx->ev_block_busy = false;
+    return rc;
+  }
+  (*out)->ctx_block = true;
+  return DOTPE_OK;
 }
 
 int dotpe_event_bytes(const dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_event_desc* d,
