@@ -425,8 +425,10 @@ void launch_hh(dotpe_event* ev, const double* w, const double2* whh) {
   // kernel applies the same test)
   const size_t rb = PREC == kFP64 ? sizeof(double2) : sizeof(float2);   // staged row value
   size_t sh = (size_t)bk->n_c * (bk->n_bp + 1) * rb + (size_t)ev->n_det * (bk->n_b + 1) * sizeof(double);
-  if (sh > 65536) sh = 0;
-  // four waves per row, each summing a quarter of the bins
+  sh = sh > 65536 ? 0 : (sh + 15) / 16 * 16;
+  // four waves per row, each summing a quarter of the bins (their partial
+  // sums after the staged row)
+  sh += (size_t)4 * ev->n_det * bk->mt.NP * sizeof(double2);
   hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(256), sh, ev->stream,
                      ev->n_sub, ev->sub_idx, ev->sub0, bk->A0, bk->A1, bk->row_scale, bk->n_bp,
                      bk->n_b, ev->n_det, w, whh, bk->mt, ev->hh_terms, ev->KH, ev->Ah[0],

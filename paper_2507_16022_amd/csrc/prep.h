@@ -693,8 +693,8 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   extern __shared__ __align__(16) unsigned char hh_smem[];
   RB* rowbuf = (RB*)hh_smem;
   // the block's waves split the bins: wave q sums bins [q n_b / nq, (q + 1) n_b / nq)
-  // of every (detector, channel pair), and the nq partial sums are added in order
-  __shared__ double2 Hq[4][kMaxDet * kMaxNP];
+  // of every (detector, channel pair), and the nq partial sums are added in order;
+  // their area follows the staged row in the dynamic LDS
   __shared__ double vals[256];
   __shared__ double red[256];
   const int nq = (int)blockDim.x / 64, wq = (int)threadIdx.x / 64, u = (int)threadIdx.x % 64;
@@ -706,8 +706,12 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
   // the lanes reading one bin of different channels or detectors fall on
   // different LDS banks
   const int rs = n_bp + 1, ws = n_b + 1;
-  const bool staged = (size_t)mt.n_c * rs * sizeof(RB) + (size_t)n_det * ws * sizeof(double) <= 65536;
+  const size_t stage_bytes = (size_t)mt.n_c * rs * sizeof(RB) + (size_t)n_det * ws * sizeof(double);
+  const bool staged = stage_bytes <= 65536;
   double* wl = (double*)(rowbuf + mt.n_c * rs);
+  const int nhp = n_det * mt.NP;   // (detector, channel pair) sums
+  double2* Hq_base = (double2*)(hh_smem + (staged ? (stage_bytes + 15) / 16 * 16 : 0));
+  auto Hq = [&](int q, int t) -> double2& { return Hq_base[q * nhp + t]; };
   if (staged) {
     // the row in pieces of 8 consecutive positions (16 bytes per operand
     // array in the split layouts): 8 bins of the real or the imaginary part;
@@ -794,19 +798,19 @@ __global__ void k_hh_precompute(int64_t n_sub, const int64_t* __restrict__ sub_i
         acc.y += ww * v.y;
       }
     }
-    Hq[wq][t] = acc;
+    Hq(wq, t) = acc;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n_det * mt.NP; t += blockDim.x) {
-    double2 h = Hq[0][t];
+  for (int t = threadIdx.x; t < nhp; t += blockDim.x) {
+    double2 h = Hq(0, t);
     for (int q = 1; q < nq; ++q) {
-      h.x += Hq[q][t].x;
-      h.y += Hq[q][t].y;
+      h.x += Hq(q, t).x;
+      h.y += Hq(q, t).y;
     }
-    Hq[0][t] = make_double2(h.x * sc, h.y * sc);
+    Hq(0, t) = make_double2(h.x * sc, h.y * sc);
   }
   __syncthreads();
-  const double2* Hs = Hq[0];
+  const double2* Hs = Hq_base;
   double mx = 0.0;
   for (int j = threadIdx.x; j < KH; j += blockDim.x) {
     double v = term_value(terms[j], Hs, mt, true);
