@@ -429,6 +429,15 @@ void launch_hh(dotpe_event* ev, const double* w, const double2* whh) {
   // four waves per row, each summing a quarter of the bins (their partial
   // sums after the staged row)
   sh += (size_t)4 * ev->n_det * bk->mt.NP * sizeof(double2);
+  // more than 64 KB of dynamic LDS needs the attribute (FP64 banks with many
+  // channels and detectors); set once, up to what a CU holds
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    if (hipFuncSetAttribute((const void*)k_hh_precompute<PREC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 8192) !=
+        hipSuccess)
+      (void)hipGetLastError();
+  });
   hipLaunchKernelGGL(k_hh_precompute<PREC>, dim3((unsigned)ev->n_sub), dim3(256), sh, ev->stream,
                      ev->n_sub, ev->sub_idx, ev->sub0, bk->A0, bk->A1, bk->row_scale, bk->n_bp,
                      bk->n_b, ev->n_det, w, whh, bk->mt, ev->hh_terms, ev->KH, ev->Ah[0],
