@@ -1861,6 +1861,8 @@ int dotpe_preselect(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_preselect_
   std::memset(&a, 0, sizeof(a));
   a.A0 = bk->A0;
   a.A1 = bk->A1;
+  a.R0 = bk->R0;
+  a.R1 = bk->R1;
   a.row_scale = bk->row_scale;
   a.K2 = bk->K2;
   a.n_c = mt.n_c;
@@ -2138,6 +2140,8 @@ int dotpe_extrinsic_samples(dotpe_ctx* ctx, const dotpe_bank* bk, const dotpe_ex
   std::memset(&a, 0, sizeof(a));
   a.A0 = bk->A0;
   a.A1 = bk->A1;
+  a.R0 = bk->R0;
+  a.R1 = bk->R1;
   a.row_scale = bk->row_scale;
   a.K2 = bk->K2;
   a.n_c = mt.n_c;

@@ -31,6 +31,8 @@ struct PreArgs {
   // bank operand (split precisions): conj(h) 2^-e_i in op_index layout
   const void* A0;
   const void* A1;
+  const void* R0;            // the same hi and lo parts row by row ([n_wf][K2])
+  const void* R1;
   const double* row_scale;
   int64_t K2;
   int n_c, n_b, n_bp;

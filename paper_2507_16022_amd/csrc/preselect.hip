@@ -86,7 +86,9 @@ __global__ __launch_bounds__(256) void k_pre_build_B(PreArgs a) {
 
 // G_ikcc' = sum_b w_kb h_icb conj(h_ic'b) (c <= c') from the split bank
 // values (h = conj(A) 2^e_i), in FP64: a wave per row, its lanes over the
-// bins, one wave sum per output.
+// bins, one wave sum per output.  The row is read from the row-major copy
+// of the split parts: in the fragment layout a single row's 16-byte pieces
+// lie 512 bytes apart, one per cache line.
 template <int PREC, int NC>
 __global__ __launch_bounds__(256) void k_pre_gram(PreArgs a) {
   constexpr int NP = NC * (NC + 1) / 2;
@@ -105,8 +107,8 @@ __global__ __launch_bounds__(256) void k_pre_gram(PreArgs a) {
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int64_t base = ((int64_t)c * (a.n_bp / kChunk) + b / kChunk) * 32 + (b % kChunk);
-        hr[c] = load_split<PREC>(a.A0, a.A1, op_index<PREC>(i, base, a.K2));
-        hi[c] = -load_split<PREC>(a.A0, a.A1, op_index<PREC>(i, base + 16, a.K2));
+        hr[c] = load_split<PREC>(a.R0, a.R1, i * a.K2 + base);
+        hi[c] = -load_split<PREC>(a.R0, a.R1, i * a.K2 + base + 16);
       }
       const double w = a.w[(int64_t)k * a.n_b + b];
       int p = 0;
